@@ -1,0 +1,192 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (shell_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The product path (the HIP library and its
+Python binding) never imports it, and it imports nothing from the product.
+
+Each function cites the passage of the paper it follows in shell_oracle.c.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "shell_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MODELS = ("EP", "ES", "FP", "FS", "SP", "SS")
+ERRORS = {-1: "invalid argument", -2: "non-manifold mesh", -3: "inconsistent orientation",
+          -4: "degenerate stencil", -5: "iteration budget exhausted"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {ERRORS.get(code, code)}")
+        self.code = code
+
+
+def build() -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        d = ctypes.c_double
+        i = ctypes.c_int
+        L.orc_topology.argtypes = [i, i64, i64, P, P, P]
+        L.orc_build.argtypes = [i, i64, P, i64, P, d, d, d, P, P, P]
+        L.orc_forces.argtypes = [i, i64, P, i64, P, P, P, P, P, P]
+        L.orc_hessian.argtypes = [i, i64, i64, P, P, P, P, P, P, P]
+        L.orc_mass.argtypes = [i64, P, i64, P, d, d, P]
+        L.orc_apply.argtypes = [i64, P, P, P, P, d, P, P]
+        L.orc_step.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, P, P, P, d, P, i, d, d, i, P, P, P]
+        L.orc_edge_normal_literal.argtypes = [P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise OracleError(rc, what)
+
+
+def model_id(model) -> int:
+    return MODELS.index(model) if isinstance(model, str) else int(model)
+
+
+def stencil_size(model) -> int:
+    return 4 if model_id(model) < 2 else 6
+
+
+def curv_size(model) -> int:
+    return 1 if model_id(model) < 2 else 3
+
+
+class Stencils:
+    """Rest-precomputed stencils of one mesh for one model."""
+
+    def __init__(self, model, X, tris, young, poisson, thickness):
+        self.model = model_id(model)
+        self.X = np.ascontiguousarray(X, dtype=np.float64)
+        self.tris = np.ascontiguousarray(tris, dtype=np.int32)
+        self.nv = self.X.shape[0]
+        self.nt = self.tris.shape[0]
+        self.k = stencil_size(self.model)
+        self.r = curv_size(self.model)
+        ns = ctypes.c_int64(0)
+        _check(lib().orc_topology(self.model, self.nv, self.nt, _p(self.tris), ctypes.byref(ns), None), "topology")
+        self.ns = ns.value
+        self.idx = np.zeros((self.ns, self.k), dtype=np.int32)
+        _check(lib().orc_topology(self.model, self.nv, self.nt, _p(self.tris), ctypes.byref(ns), _p(self.idx)),
+               "topology")
+        self.B = np.zeros((self.ns, self.r, self.k))
+        self.kappa0 = np.zeros((self.ns, self.r))
+        self.D = np.zeros((self.ns, self.r, self.r))
+        _check(lib().orc_build(self.model, self.nv, _p(self.X), self.ns, _p(self.idx), young, poisson, thickness,
+                               _p(self.B), _p(self.kappa0), _p(self.D)), "build")
+
+    def forces(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        f = np.zeros((self.nv, 3))
+        e = ctypes.c_double(0.0)
+        _check(lib().orc_forces(self.model, self.nv, _p(x), self.ns, _p(self.idx), _p(self.B), _p(self.kappa0),
+                                _p(self.D), _p(f), ctypes.byref(e)), "forces")
+        return f, e.value
+
+    def energy(self, x):
+        return self.forces(x)[1]
+
+    def hessian(self):
+        """Scalar CSR (rowptr int64, col int32, val float64) of K_s."""
+        nnz = ctypes.c_int64(0)
+        rowptr = np.zeros(self.nv + 1, dtype=np.int64)
+        _check(lib().orc_hessian(self.model, self.nv, self.ns, _p(self.idx), _p(self.B), _p(self.D),
+                                 ctypes.byref(nnz), _p(rowptr), None, None), "hessian")
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value)
+        _check(lib().orc_hessian(self.model, self.nv, self.ns, _p(self.idx), _p(self.B), _p(self.D),
+                                 ctypes.byref(nnz), _p(rowptr), _p(col), _p(val)), "hessian")
+        return rowptr, col, val
+
+
+def hessian_dense(st: Stencils) -> np.ndarray:
+    rowptr, col, val = st.hessian()
+    K = np.zeros((st.nv, st.nv))
+    for i in range(st.nv):
+        K[i, col[rowptr[i]:rowptr[i + 1]]] = val[rowptr[i]:rowptr[i + 1]]
+    return K
+
+
+def mass(X, tris, density, thickness):
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    tris = np.ascontiguousarray(tris, dtype=np.int32)
+    m = np.zeros(X.shape[0])
+    _check(lib().orc_mass(X.shape[0], _p(X), tris.shape[0], _p(tris), density, thickness, _p(m)), "mass")
+    return m
+
+
+def apply(csr, mass_v, dt2, p):
+    rowptr, col, val = csr
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    q = np.zeros_like(p)
+    _check(lib().orc_apply(p.shape[0], _p(rowptr), _p(col), _p(val), _p(mass_v), dt2, _p(p), _p(q)), "apply")
+    return q
+
+
+class Sim:
+    """Implicit-Euler state advanced by the oracle (Sec. 5, eqs 62-63 without contact)."""
+
+    def __init__(self, st: Stencils, material: dict, pinned, x0=None, v0=None):
+        self.st = st
+        self.csr = st.hessian()
+        self.mass = mass(st.X, st.tris, material["density"], material["thickness"])
+        self.pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
+        self.x = np.array(st.X if x0 is None else x0, dtype=np.float64, copy=True)
+        self.v = np.zeros_like(self.x) if v0 is None else np.array(v0, dtype=np.float64, copy=True)
+
+    def step(self, dt, gravity=(0.0, 0.0, -9.81), max_newton=1, newton_rtol=1e-8, pcg_rtol=1e-10,
+             max_pcg=200000, replay=None):
+        """Advance one step; returns (counts [max_newton,3], stats dict).  replay: counts to re-run."""
+        g = np.ascontiguousarray(gravity, dtype=np.float64)
+        counts = np.zeros((max(max_newton, 1), 3), dtype=np.int32)
+        stats = np.zeros(4)
+        rep = None if replay is None else np.ascontiguousarray(replay, dtype=np.int32).reshape(-1, 3)
+        if rep is not None and rep.shape[0] < max_newton:
+            raise ValueError("replay needs one row per Newton iteration")
+        rowptr, col, val = self.csr
+        st = self.st
+        rc = lib().orc_step(st.model, st.nv, st.ns, _p(st.idx), _p(st.B), _p(st.kappa0), _p(st.D), _p(rowptr),
+                            _p(col), _p(val), _p(self.mass), _p(self.pinned), _p(self.x), _p(self.v), dt, _p(g),
+                            max_newton, newton_rtol, pcg_rtol, max_pcg, _p(rep), _p(counts), _p(stats))
+        if rc not in (0, -5):
+            _check(rc, "step")
+        return counts, dict(newton_iters=int(stats[0]), pcg_total=int(stats[1]), grad_norm0=stats[2],
+                            grad_norm=stats[3], budget_hit=(rc == -5))
+
+
+def edge_normal_literal(x1, x2, x3, x4):
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (x1, x2, x3, x4)]
+    n = np.zeros(3)
+    _check(lib().orc_edge_normal_literal(*[_p(v) for v in a], _p(n)), "edge normal")
+    return n

@@ -1,0 +1,796 @@
+/*
+ * Plain FP64 CPU oracle for the corotational hinge plate/shell bending models.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by tests/, the smoke check and the
+ * benchmark's CPU-baseline leg, never by the product path.  Shares no code
+ * with the HIP library.
+ *
+ * Everything is written as plain loops in the order the paper states it:
+ *   Sec. 4.3  edge-based hinge: operator L_m (eqs 7, 9-10), curvature
+ *             kappa = L_m N^T x (eq 13), plate energy (eq 20), shell energy
+ *             and gradient (eqs 23-26), free boundary edges emit nothing.
+ *   Sec. 4.4  FVM hinge: directional operator L_p (eqs 37, 40 and App. C
+ *             eqs 76-78), transform R (eq 38), energies eqs 39-45, free-edge
+ *             fold and zero twist on free edges.
+ *   Sec. 4.5  smoothed hinge: quadratic fit C_p, L_g = (L_p C_p)^-1 L_p
+ *             (eqs 48-51), energies eqs 52-57, virtual-node folds eqs 58-61.
+ *   App. A    corotational frames (eq 65), App. B normal gradients (eqs 66-75).
+ *   Sec. 5    implicit Euler as the minimiser of the incremental potential
+ *             (eqs 62-63) with no contact terms, by Newton against the
+ *             constant Hessian of eqs 21/41/53.
+ *
+ * Readings where the paper is silent or ambiguous (each is also listed in the
+ * design notes of the repository):
+ *  - foot ratios are signed, s_p = (X1-X2).e/|e|^2 (the App. B definition),
+ *    so the operator annihilates constants even on obtuse stencils;
+ *  - heights and feet are measured on the projected (corotational) stencil;
+ *  - the edge-stencil normal is normalize(n_T123 + n_T432), the same line as
+ *    eq 8's sum of unit height vectors but with a sign that does not flip with
+ *    the bend direction (eq 8 itself is kept as orc_edge_normal_literal);
+ *  - D_b = k_b [[1,nu,0],[nu,1,0],[0,0,(1-nu)/2]] with k_b = E h^3/(12(1-nu^2)),
+ *    Voigt curvature [w_XX, w_YY, 2 w_XY];
+ *  - A_E is the sum of the two rest triangle areas; A the central triangle's;
+ *  - a missing flap L+3 is the point reflection of L through the midpoint of
+ *    the boundary edge, and the free fold w_{L'} = w_M + w_N - w_L is applied
+ *    to the operator's columns (eq 61) for both triangle models;
+ *  - FVM: when a stencil has a free edge, the twist component is zeroed in the
+ *    frame whose x axis runs along its first free edge (parity unpinned beyond
+ *    invariants, finite differences and Hessian checks);
+ *  - mass is lumped, m_v = rho h sum(A_T)/3; x_hat = x + dt v + dt^2 g;
+ *    v^{t+1} = (x^{t+1} - x^t)/dt; pinned vertices keep their position;
+ *  - linear solver: Jacobi-preconditioned CG per coordinate, x0 = 0, stop when
+ *    ||r|| <= rtol ||b||; alpha = 0 when p.q = 0, beta = 0 when r.z was 0.
+ */
+#include "shell_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---------------------------------------------------------------- vectors */
+
+static void sub3(const double* a, const double* b, double* o) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double* a, const double* b, double* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double norm3(const double* a) { return sqrt(dot3(a, a)); }
+static void scale3(const double* a, double s, double* o) { o[0] = a[0] * s; o[1] = a[1] * s; o[2] = a[2] * s; }
+static void axpy3(double s, const double* a, double* o) { o[0] += s * a[0]; o[1] += s * a[1]; o[2] += s * a[2]; }
+
+/* unit normal of triangle (a,b,c) and the length of (b-a)x(c-a) */
+static double tri_normal(const double* a, const double* b, const double* c, double* n) {
+    double ab[3], ac[3], u[3];
+    sub3(b, a, ab);
+    sub3(c, a, ac);
+    cross3(ab, ac, u);
+    double len = norm3(u);
+    if (len > 0) scale3(u, 1.0 / len, n);
+    else n[0] = n[1] = n[2] = 0;
+    return len;
+}
+
+int orc_stencil_size(int model) { return (model == 0 || model == 1) ? 4 : 6; }
+int orc_curv_size(int model) { return (model == 0 || model == 1) ? 1 : 3; }
+static int is_edge(int model) { return model == 0 || model == 1; }
+static int is_shell(int model) { return model == 1 || model == 3 || model == 5; }
+static int is_fvm(int model) { return model == 2 || model == 3; }
+
+/* --------------------------------------------------------------- topology */
+
+typedef struct { int32_t from, to, opp; } dedge_t;
+
+static int cmp_dedge(const void* pa, const void* pb) {
+    const dedge_t* a = (const dedge_t*)pa;
+    const dedge_t* b = (const dedge_t*)pb;
+    if (a->from != b->from) return a->from < b->from ? -1 : 1;
+    if (a->to != b->to) return a->to < b->to ? -1 : 1;
+    return 0;
+}
+
+/* all directed edges of the mesh, sorted by (from, to); validates the mesh */
+static int directed_edges(int64_t nv, int64_t nt, const int32_t* tris, dedge_t** out) {
+    dedge_t* de = (dedge_t*)malloc(sizeof(dedge_t) * (size_t)(3 * nt + 1));
+    if (!de) return ORC_E_ARG;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t* v = tris + 3 * t;
+        for (int i = 0; i < 3; ++i) {
+            if (v[i] < 0 || v[i] >= nv) { free(de); return ORC_E_ARG; }
+        }
+        if (v[0] == v[1] || v[1] == v[2] || v[2] == v[0]) { free(de); return ORC_E_DEGENERATE; }
+        for (int i = 0; i < 3; ++i) {
+            de[3 * t + i].from = v[i];
+            de[3 * t + i].to = v[(i + 1) % 3];
+            de[3 * t + i].opp = v[(i + 2) % 3];
+        }
+    }
+    qsort(de, (size_t)(3 * nt), sizeof(dedge_t), cmp_dedge);
+    for (int64_t e = 1; e < 3 * nt; ++e) {
+        if (de[e].from == de[e - 1].from && de[e].to == de[e - 1].to) {
+            /* the same directed edge in two triangles: a fan of three or more triangles when the
+               reverse direction is also present, otherwise two inconsistently oriented triangles */
+            dedge_t key = {de[e].to, de[e].from, 0};
+            int fan = bsearch(&key, de, (size_t)(3 * nt), sizeof(dedge_t), cmp_dedge) != NULL;
+            free(de);
+            return fan ? ORC_E_NONMANIFOLD : ORC_E_ORIENTATION;
+        }
+    }
+    *out = de;
+    return ORC_OK;
+}
+
+static const dedge_t* find_dedge(const dedge_t* de, int64_t n, int32_t from, int32_t to) {
+    dedge_t key = {from, to, 0};
+    return (const dedge_t*)bsearch(&key, de, (size_t)n, sizeof(dedge_t), cmp_dedge);
+}
+
+int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t* ns, int32_t* idx) {
+    if (model < 0 || model > 5 || nv < 0 || nt < 0 || !ns) return ORC_E_ARG;
+    dedge_t* de = NULL;
+    int rc = directed_edges(nv, nt, tris, &de);
+    if (rc) return rc;
+    int64_t nde = 3 * nt;
+    /* an undirected edge shared by two triangles must appear once in each direction;
+       a third triangle on the same pair of vertices makes the edge non-manifold */
+    int64_t count = 0;
+    for (int64_t e = 0; e < nde; ++e) {
+        const dedge_t* tw = find_dedge(de, nde, de[e].to, de[e].from);
+        if (tw && de[e].from < de[e].to) {
+            /* both directions present exactly once (directed_edges rejects repeats) */
+            if (is_edge(model)) {
+                if (idx) {
+                    int32_t* s = idx + 4 * count;
+                    s[0] = de[e].opp; /* vertex 1: T123 traverses 2->3 */
+                    s[1] = de[e].from;
+                    s[2] = de[e].to;
+                    s[3] = tw->opp; /* vertex 4: T432 traverses 3->2 */
+                }
+                ++count;
+            }
+        }
+    }
+    if (!is_edge(model)) {
+        count = nt;
+        if (idx) {
+            for (int64_t t = 0; t < nt; ++t) {
+                const int32_t* v = tris + 3 * t;
+                int32_t* s = idx + 6 * t;
+                s[0] = v[0];
+                s[1] = v[1];
+                s[2] = v[2];
+                for (int i = 0; i < 3; ++i) {
+                    /* flap i+3 lies across the edge opposite vertex i, i.e. (v[i+1], v[i+2]);
+                       the neighbour traverses that edge as v[i+2] -> v[i+1] */
+                    const dedge_t* nb = find_dedge(de, nde, v[(i + 2) % 3], v[(i + 1) % 3]);
+                    s[3 + i] = nb ? nb->opp : -1;
+                }
+            }
+        }
+    }
+    free(de);
+    *ns = count;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------ rest precompute */
+
+/* Edge-based hinge (Sec. 4.3): L_m = 2 L_theta/(h1+h4) on the projected stencil. */
+static int build_edge(int shell, const double* X1, const double* X2, const double* X3, const double* X4,
+                      double kb, double* L, double* kappa0, double* D) {
+    double na[3], nb[3], n0[3];
+    double Aa = 0.5 * tri_normal(X1, X2, X3, na);
+    double Ab = 0.5 * tri_normal(X4, X3, X2, nb);
+    if (!(Aa > 0) || !(Ab > 0)) return ORC_E_DEGENERATE;
+    double m[3] = {na[0] + nb[0], na[1] + nb[1], na[2] + nb[2]};
+    double mlen = norm3(m);
+    if (!(mlen > 1e-12)) return ORC_E_DEGENERATE;
+    scale3(m, 1.0 / mlen, n0);
+    /* corotational stencil: projection onto the tangent plane through X2 (X3 lies on it) */
+    const double* Xs[4] = {X1, X2, X3, X4};
+    double Xc[4][3];
+    for (int j = 0; j < 4; ++j) {
+        double d[3];
+        sub3(Xs[j], X2, d);
+        double w = dot3(n0, d);
+        for (int c = 0; c < 3; ++c) Xc[j][c] = Xs[j][c] - w * n0[c];
+    }
+    double e[3], d1[3], d4[3];
+    sub3(Xc[2], Xc[1], e);
+    double ee = dot3(e, e);
+    sub3(Xc[0], Xc[1], d1);
+    sub3(Xc[3], Xc[1], d4);
+    double sp = dot3(d1, e) / ee; /* signed foot ratio of vertex 1 along 2->3 */
+    double sq = dot3(d4, e) / ee; /* signed foot ratio of vertex 4 */
+    double p[3], q[3];
+    for (int c = 0; c < 3; ++c) {
+        p[c] = d1[c] - sp * e[c];
+        q[c] = d4[c] - sq * e[c];
+    }
+    double h1 = norm3(p), h4 = norm3(q);
+    double elen = sqrt(ee);
+    if (!(h1 > 1e-12 * elen) || !(h4 > 1e-12 * elen)) return ORC_E_DEGENERATE;
+    double c = 2.0 / (h1 + h4);
+    L[0] = c * (1.0 / h1);
+    L[1] = -c * ((1.0 - sp) / h1 + (1.0 - sq) / h4);
+    L[2] = -c * (sp / h1 + sq / h4);
+    L[3] = c * (1.0 / h4);
+    D[0] = kb * (Aa + Ab);
+    kappa0[0] = 0.0;
+    if (shell) {
+        for (int j = 0; j < 4; ++j) kappa0[0] += L[j] * dot3(n0, Xs[j]);
+    }
+    return ORC_OK;
+}
+
+/* 3x3 inverse by the adjugate; returns the 1-norm condition number (inf if singular). */
+static double inv3(const double M[3][3], double Mi[3][3]) {
+    double det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1])
+               - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0])
+               + M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+    if (det == 0.0 || !isfinite(det)) return INFINITY;
+    Mi[0][0] = (M[1][1] * M[2][2] - M[1][2] * M[2][1]) / det;
+    Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) / det;
+    Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / det;
+    Mi[1][0] = (M[1][2] * M[2][0] - M[1][0] * M[2][2]) / det;
+    Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / det;
+    Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / det;
+    Mi[2][0] = (M[1][0] * M[2][1] - M[1][1] * M[2][0]) / det;
+    Mi[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / det;
+    Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / det;
+    double n1 = 0, n2 = 0;
+    for (int j = 0; j < 3; ++j) {
+        double s1 = 0, s2 = 0;
+        for (int i = 0; i < 3; ++i) {
+            s1 += fabs(M[i][j]);
+            s2 += fabs(Mi[i][j]);
+        }
+        if (s1 > n1) n1 = s1;
+        if (s2 > n2) n2 = s2;
+    }
+    return n1 * n2;
+}
+
+/* Triangle-centred stencil (Secs 4.4, 4.5; App. A, C).  Xs[j] == NULL for a missing flap. */
+static int build_tri(int model, const double* Xs[6], const double Db[3][3], double* B, double* kappa0, double* D) {
+    const double *X1 = Xs[0], *X2 = Xs[1], *X3 = Xs[2];
+    /* rest corotational frame (eq 65): origin X1, x axis along X12, z the triangle normal */
+    double ex[3], ez[3], ey[3], d12[3];
+    double twoA = tri_normal(X1, X2, X3, ez);
+    if (!(twoA > 0)) return ORC_E_DEGENERATE;
+    sub3(X2, X1, d12);
+    scale3(d12, 1.0 / norm3(d12), ex);
+    cross3(ez, ex, ey);
+    /* projected 2D coordinates of the six points */
+    double P[6][2];
+    int missing[3] = {0, 0, 0};
+    for (int j = 0; j < 6; ++j) {
+        if (Xs[j]) {
+            double d[3];
+            sub3(Xs[j], X1, d);
+            P[j][0] = dot3(d, ex);
+            P[j][1] = dot3(d, ey);
+        }
+    }
+    for (int L = 0; L < 3; ++L) {
+        if (!Xs[L + 3]) {
+            /* virtual node: reflection of L through the midpoint of the boundary edge (M,N) */
+            int M = (L + 1) % 3, N = (L + 2) % 3;
+            missing[L] = 1;
+            P[L + 3][0] = P[M][0] + P[N][0] - P[L][0];
+            P[L + 3][1] = P[M][1] + P[N][1] - P[L][1];
+        }
+    }
+    /* directional operator L_p (3x6): row i is the hinge operator across the edge opposite i */
+    double Lp[3][6];
+    memset(Lp, 0, sizeof(Lp));
+    double emin = INFINITY;
+    for (int i = 0; i < 3; ++i) {
+        int a = (i + 1) % 3, b = (i + 2) % 3, f = i + 3;
+        double e[2] = {P[b][0] - P[a][0], P[b][1] - P[a][1]};
+        double ee = e[0] * e[0] + e[1] * e[1];
+        if (sqrt(ee) < emin) emin = sqrt(ee);
+        double dt[2] = {P[i][0] - P[a][0], P[i][1] - P[a][1]};
+        double df[2] = {P[f][0] - P[a][0], P[f][1] - P[a][1]};
+        double st = (dt[0] * e[0] + dt[1] * e[1]) / ee;
+        double sf = (df[0] * e[0] + df[1] * e[1]) / ee;
+        double ht = hypot(dt[0] - st * e[0], dt[1] - st * e[1]);
+        double hf = hypot(df[0] - sf * e[0], df[1] - sf * e[1]);
+        if (!(ht > 1e-12 * sqrt(ee)) || !(hf > 1e-12 * sqrt(ee))) return ORC_E_DEGENERATE;
+        double c = 2.0 / (ht + hf);
+        Lp[i][i] = c / ht;
+        Lp[i][a] = -c * ((1.0 - st) / ht + (1.0 - sf) / hf);
+        Lp[i][b] = -c * (st / ht + sf / hf);
+        Lp[i][f] = c / hf;
+    }
+    double Bm[3][6];
+    if (is_fvm(model)) {
+        /* R (eq 38): column i from the unit normal m of edge i in the rest X~Y~ plane */
+        double R[3][3];
+        for (int i = 0; i < 3; ++i) {
+            int a = (i + 1) % 3, b = (i + 2) % 3;
+            double e[2] = {P[b][0] - P[a][0], P[b][1] - P[a][1]};
+            double len = hypot(e[0], e[1]);
+            double ms = e[1] / len, mt = -e[0] / len;
+            R[0][i] = ms * ms;
+            R[1][i] = mt * mt;
+            R[2][i] = 2.0 * ms * mt;
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < 6; ++j) {
+                double s = 0;
+                for (int i = 0; i < 3; ++i) s += R[r][i] * Lp[i][j];
+                Bm[r][j] = s;
+            }
+    } else {
+        /* quadratic fit (eqs 48-50): C_p rows [X^2/2, Y^2/2, XY/2]; L_g = (L_p C_p)^-1 L_p */
+        double Cp[6][3];
+        for (int j = 0; j < 6; ++j) {
+            Cp[j][0] = 0.5 * P[j][0] * P[j][0];
+            Cp[j][1] = 0.5 * P[j][1] * P[j][1];
+            Cp[j][2] = 0.5 * P[j][0] * P[j][1];
+        }
+        double M3[3][3], Mi[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double s = 0;
+                for (int j = 0; j < 6; ++j) s += Lp[r][j] * Cp[j][c];
+                M3[r][c] = s;
+            }
+        double cond = inv3(M3, Mi);
+        if (!(cond < 1e12)) return ORC_E_DEGENERATE;
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < 6; ++j) {
+                double s = 0;
+                for (int i = 0; i < 3; ++i) s += Mi[r][i] * Lp[i][j];
+                Bm[r][j] = s;
+            }
+    }
+    /* free boundary fold (eq 61): w_{L+3} = w_M + w_N - w_L, superimposed per missing flap */
+    for (int L = 0; L < 3; ++L) {
+        if (!missing[L]) continue;
+        int M = (L + 1) % 3, N = (L + 2) % 3, F = L + 3;
+        for (int r = 0; r < 3; ++r) {
+            Bm[r][M] += Bm[r][F];
+            Bm[r][N] += Bm[r][F];
+            Bm[r][L] -= Bm[r][F];
+            Bm[r][F] = 0.0;
+        }
+    }
+    /* FVM free edge: zero the twist (mixed second derivative) in the frame of the first free edge */
+    if (is_fvm(model)) {
+        for (int L = 0; L < 3; ++L) {
+            if (!missing[L]) continue;
+            int M = (L + 1) % 3, N = (L + 2) % 3;
+            double e[2] = {P[N][0] - P[M][0], P[N][1] - P[M][1]};
+            double len = hypot(e[0], e[1]);
+            double c = e[0] / len, s = e[1] / len;
+            /* Voigt curvature rotation into the edge frame, T(phi), and back, T(-phi) */
+            double T[3][3] = {{c * c, s * s, c * s}, {s * s, c * c, -c * s}, {-2 * c * s, 2 * c * s, c * c - s * s}};
+            double Ti[3][3] = {{c * c, s * s, -c * s}, {s * s, c * c, c * s}, {2 * c * s, -2 * c * s, c * c - s * s}};
+            double Pz[3][3];
+            for (int r = 0; r < 3; ++r)
+                for (int q = 0; q < 3; ++q) {
+                    double acc = 0;
+                    for (int m = 0; m < 2; ++m) acc += Ti[r][m] * T[m][q]; /* drop the twist row */
+                    Pz[r][q] = acc;
+                }
+            double Bn[3][6];
+            for (int r = 0; r < 3; ++r)
+                for (int j = 0; j < 6; ++j) {
+                    double acc = 0;
+                    for (int q = 0; q < 3; ++q) acc += Pz[r][q] * Bm[q][j];
+                    Bn[r][j] = acc;
+                }
+            memcpy(Bm, Bn, sizeof(Bm));
+            break;
+        }
+    }
+    (void)emin;
+    double A = 0.5 * twoA;
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 6; ++j) B[r * 6 + j] = Bm[r][j];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) D[r * 3 + c] = A * Db[r][c];
+    for (int r = 0; r < 3; ++r) {
+        kappa0[r] = 0.0;
+        if (is_shell(model)) {
+            /* rest curvature kappa0 = B N0^T X (eqs 43, 51) */
+            for (int j = 0; j < 6; ++j)
+                if (Xs[j]) kappa0[r] += Bm[r][j] * dot3(ez, Xs[j]);
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t* idx,
+              double young, double poisson, double thickness, double* B, double* kappa0, double* D) {
+    if (model < 0 || model > 5 || !X || !idx || !B || !kappa0 || !D) return ORC_E_ARG;
+    double kb = young * thickness * thickness * thickness / (12.0 * (1.0 - poisson * poisson));
+    double Db[3][3] = {{kb, kb * poisson, 0}, {kb * poisson, kb, 0}, {0, 0, kb * (1.0 - poisson) / 2.0}};
+    int k = orc_stencil_size(model), r = orc_curv_size(model);
+    for (int64_t s = 0; s < ns; ++s) {
+        const int32_t* id = idx + k * s;
+        for (int j = 0; j < k; ++j)
+            if (id[j] >= nv || (id[j] < 0 && (is_edge(model) || j < 3))) return ORC_E_ARG;
+        int rc;
+        if (is_edge(model)) {
+            rc = build_edge(is_shell(model), X + 3 * id[0], X + 3 * id[1], X + 3 * id[2], X + 3 * id[3], kb,
+                            B + 4 * s, kappa0 + s, D + s);
+        } else {
+            const double* Xs[6];
+            for (int j = 0; j < 6; ++j) Xs[j] = id[j] >= 0 ? X + 3 * id[j] : NULL;
+            rc = build_tri(model, Xs, Db, B + 18 * s, kappa0 + 3 * s, D + 9 * s);
+        }
+        if (rc) return rc;
+    }
+    (void)r;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------ energy and force */
+
+/* (dn/dx_j)^T v for n = u/|u|, u = (b-a)x(c-a) at the triangle's vertices a, b, c:
+   w = (I - n n^T) v / |u|, then (du/da)^T w = w x (c-b), (du/db)^T w = w x (a-c),
+   (du/dc)^T w = w x (b-a)  (App. B, eqs 67, 73). Adds the results to ga, gb, gc. */
+static void normal_vjp(const double* a, const double* b, const double* c, const double* v, double* ga, double* gb,
+                       double* gc) {
+    double ab[3], ac[3], u[3], n[3];
+    sub3(b, a, ab);
+    sub3(c, a, ac);
+    cross3(ab, ac, u);
+    double len = norm3(u);
+    scale3(u, 1.0 / len, n);
+    double w[3];
+    double vn = dot3(v, n);
+    for (int i = 0; i < 3; ++i) w[i] = (v[i] - vn * n[i]) / len;
+    double cb[3], ca[3], ba[3], t[3];
+    sub3(c, b, cb);
+    sub3(a, c, ca);
+    sub3(b, a, ba);
+    cross3(w, cb, t);
+    axpy3(1.0, t, ga);
+    cross3(w, ca, t);
+    axpy3(1.0, t, gb);
+    cross3(w, ba, t);
+    axpy3(1.0, t, gc);
+}
+
+int orc_forces(int model, int64_t nv, const double* x, int64_t ns, const int32_t* idx, const double* B,
+               const double* kappa0, const double* D, double* f, double* energy) {
+    if (model < 0 || model > 5 || !x || !f) return ORC_E_ARG;
+    int k = orc_stencil_size(model), r = orc_curv_size(model);
+    memset(f, 0, sizeof(double) * (size_t)(3 * nv));
+    double E = 0.0;
+    for (int64_t s = 0; s < ns; ++s) {
+        const int32_t* id = idx + k * s;
+        const double* Bs = B + (size_t)(r * k) * s;
+        const double* Ds = D + (size_t)(r * r) * s;
+        const double* xs[6];
+        for (int j = 0; j < k; ++j) xs[j] = id[j] >= 0 ? x + 3 * id[j] : NULL;
+        /* curvature vectors C_i = sum_j B_ij x_j (eqs 13, 40, 47 with N^T applied later) */
+        double C[3][3];
+        for (int i = 0; i < r; ++i) {
+            C[i][0] = C[i][1] = C[i][2] = 0.0;
+            for (int j = 0; j < k; ++j)
+                if (xs[j]) axpy3(Bs[i * k + j], xs[j], C[i]);
+        }
+        double fs[6][3];
+        memset(fs, 0, sizeof(fs));
+        if (!is_shell(model)) {
+            /* plate: Psi = 1/2 sum_d C_d^T D C_d (eqs 20, 39, 52), f = -H x (eq 22) */
+            double DC[3][3];
+            for (int i = 0; i < r; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    double acc = 0;
+                    for (int m = 0; m < r; ++m) acc += Ds[i * r + m] * C[m][d];
+                    DC[i][d] = acc;
+                }
+            for (int i = 0; i < r; ++i) E += 0.5 * dot3(C[i], DC[i]);
+            for (int j = 0; j < k; ++j)
+                for (int i = 0; i < r; ++i) axpy3(-Bs[i * k + j], DC[i], fs[j]);
+        } else {
+            /* shell: delta = B N^T x - kappa0 (eqs 24, 43, 55), Psi = 1/2 delta^T D delta,
+               f_j = -sum_i g_i (B_ij n + (dn/dx_j)^T C_i), g = D delta (eqs 25-26, 44-45, 56-57) */
+            double n[3];
+            if (is_edge(model)) {
+                double na[3], nb[3];
+                tri_normal(xs[0], xs[1], xs[2], na);
+                tri_normal(xs[3], xs[2], xs[1], nb);
+                double m[3] = {na[0] + nb[0], na[1] + nb[1], na[2] + nb[2]};
+                scale3(m, 1.0 / norm3(m), n);
+            } else {
+                tri_normal(xs[0], xs[1], xs[2], n);
+            }
+            const double* k0 = kappa0 + r * s;
+            double delta[3], g[3];
+            for (int i = 0; i < r; ++i) delta[i] = dot3(n, C[i]) - k0[i];
+            for (int i = 0; i < r; ++i) {
+                g[i] = 0;
+                for (int m = 0; m < r; ++m) g[i] += Ds[i * r + m] * delta[m];
+            }
+            for (int i = 0; i < r; ++i) E += 0.5 * delta[i] * g[i];
+            double Cg[3] = {0, 0, 0};
+            for (int i = 0; i < r; ++i) axpy3(g[i], C[i], Cg);
+            for (int j = 0; j < k; ++j) {
+                double bj = 0;
+                for (int i = 0; i < r; ++i) bj += g[i] * Bs[i * k + j];
+                axpy3(-bj, n, fs[j]);
+            }
+            double gn[6][3];
+            memset(gn, 0, sizeof(gn));
+            if (is_edge(model)) {
+                /* n = m/|m|, m = n_a + n_b: chain through the two unit triangle normals */
+                double na[3], nb[3];
+                tri_normal(xs[0], xs[1], xs[2], na);
+                tri_normal(xs[3], xs[2], xs[1], nb);
+                double m[3] = {na[0] + nb[0], na[1] + nb[1], na[2] + nb[2]};
+                double mlen = norm3(m);
+                double w[3], cn = dot3(Cg, n);
+                for (int c = 0; c < 3; ++c) w[c] = (Cg[c] - cn * n[c]) / mlen;
+                normal_vjp(xs[0], xs[1], xs[2], w, gn[0], gn[1], gn[2]);
+                normal_vjp(xs[3], xs[2], xs[1], w, gn[3], gn[2], gn[1]);
+            } else {
+                normal_vjp(xs[0], xs[1], xs[2], Cg, gn[0], gn[1], gn[2]);
+            }
+            for (int j = 0; j < k; ++j) axpy3(-1.0, gn[j], fs[j]);
+        }
+        for (int j = 0; j < k; ++j)
+            if (id[j] >= 0) axpy3(1.0, fs[j], f + 3 * id[j]);
+    }
+    if (energy) *energy = E;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------ constant Hessian */
+
+typedef struct { int32_t col; double val; } entry_t;
+
+int orc_hessian(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* D,
+                int64_t* nnz, int64_t* rowptr, int32_t* col, double* val) {
+    if (model < 0 || model > 5 || !nnz || !rowptr) return ORC_E_ARG;
+    int k = orc_stencil_size(model), r = orc_curv_size(model);
+    /* per-row entry counts including duplicates */
+    int64_t* cnt = (int64_t*)calloc((size_t)nv + 1, sizeof(int64_t));
+    for (int64_t s = 0; s < ns; ++s) {
+        const int32_t* id = idx + k * s;
+        int present = 0;
+        for (int j = 0; j < k; ++j) present += id[j] >= 0;
+        for (int j = 0; j < k; ++j)
+            if (id[j] >= 0) cnt[id[j] + 1] += present;
+    }
+    for (int64_t i = 0; i < nv; ++i) cnt[i + 1] += cnt[i];
+    entry_t* ent = (entry_t*)malloc(sizeof(entry_t) * (size_t)(cnt[nv] + 1));
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nv + 1));
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)(nv + 1));
+    /* stencil Gram blocks G = B^T D B (eqs 21, 41, 53; scalar part of the Kronecker product) */
+    for (int64_t s = 0; s < ns; ++s) {
+        const int32_t* id = idx + k * s;
+        const double* Bs = B + (size_t)(r * k) * s;
+        const double* Ds = D + (size_t)(r * r) * s;
+        for (int j = 0; j < k; ++j) {
+            if (id[j] < 0) continue;
+            for (int l = 0; l < k; ++l) {
+                if (id[l] < 0) continue;
+                double g = 0;
+                for (int i = 0; i < r; ++i)
+                    for (int m = 0; m < r; ++m) g += Bs[i * k + j] * Ds[i * r + m] * Bs[m * k + l];
+                ent[fill[id[j]]].col = id[l];
+                ent[fill[id[j]]].val = g;
+                fill[id[j]]++;
+            }
+        }
+    }
+    /* per row: stable insertion sort by column, then merge duplicates in stencil order */
+    int64_t out = 0;
+    rowptr[0] = 0;
+    for (int64_t i = 0; i < nv; ++i) {
+        entry_t* row = ent + cnt[i];
+        int64_t len = cnt[i + 1] - cnt[i];
+        for (int64_t a = 1; a < len; ++a) {
+            entry_t t = row[a];
+            int64_t b = a - 1;
+            while (b >= 0 && row[b].col > t.col) {
+                row[b + 1] = row[b];
+                --b;
+            }
+            row[b + 1] = t;
+        }
+        for (int64_t a = 0; a < len;) {
+            int32_t c = row[a].col;
+            double acc = 0;
+            while (a < len && row[a].col == c) acc += row[a++].val;
+            if (col) {
+                col[out] = c;
+                val[out] = acc;
+            }
+            ++out;
+        }
+        rowptr[i + 1] = out;
+    }
+    *nnz = out;
+    free(cnt);
+    free(ent);
+    free(fill);
+    return ORC_OK;
+}
+
+int orc_mass(int64_t nv, const double* X, int64_t nt, const int32_t* tris, double density, double thickness,
+             double* mass) {
+    if (!X || !tris || !mass) return ORC_E_ARG;
+    memset(mass, 0, sizeof(double) * (size_t)nv);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t* v = tris + 3 * t;
+        double n[3];
+        double A = 0.5 * tri_normal(X + 3 * v[0], X + 3 * v[1], X + 3 * v[2], n);
+        for (int i = 0; i < 3; ++i) mass[v[i]] += density * thickness * A / 3.0;
+    }
+    return ORC_OK;
+}
+
+int orc_apply(int64_t nv, const int64_t* rowptr, const int32_t* col, const double* val, const double* mass,
+              double dt2, const double* p, double* q) {
+    for (int64_t i = 0; i < nv; ++i) {
+        double acc[3] = {0, 0, 0};
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) axpy3(val[e], p + 3 * col[e], acc);
+        for (int d = 0; d < 3; ++d) q[3 * i + d] = (mass ? mass[i] * p[3 * i + d] : 0.0) + dt2 * acc[d];
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------ implicit step */
+
+/* one column of (M + dt^2 K_s)_ff y = b by Jacobi-PCG; returns the iteration count */
+static int pcg_column(int64_t nv, const int64_t* rowptr, const int32_t* col, const double* val, const double* mass,
+                      const uint8_t* pinned, double dt2, const double* dinv, const double* b, double* y, double rtol,
+                      int max_pcg, int replay_count, int* budget_hit) {
+    double *r = (double*)malloc(sizeof(double) * (size_t)nv), *z = (double*)malloc(sizeof(double) * (size_t)nv);
+    double *p = (double*)malloc(sizeof(double) * (size_t)nv), *q = (double*)malloc(sizeof(double) * (size_t)nv);
+    double bn = 0;
+    for (int64_t i = 0; i < nv; ++i) {
+        y[i] = 0.0;
+        r[i] = pinned[i] ? 0.0 : b[i];
+        bn += r[i] * r[i];
+    }
+    bn = sqrt(bn);
+    int target = replay_count >= 0 ? replay_count : max_pcg;
+    int it = 0;
+    double rz = 0;
+    for (int64_t i = 0; i < nv; ++i) {
+        z[i] = dinv[i] * r[i];
+        p[i] = z[i];
+        rz += r[i] * z[i];
+    }
+    while (it < target) {
+        if (replay_count < 0) {
+            double rn = 0;
+            for (int64_t i = 0; i < nv; ++i) rn += r[i] * r[i];
+            if (sqrt(rn) <= rtol * bn) break;
+        }
+        double pq = 0;
+        for (int64_t i = 0; i < nv; ++i) {
+            double acc = 0;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) acc += val[e] * p[col[e]];
+            q[i] = pinned[i] ? 0.0 : mass[i] * p[i] + dt2 * acc;
+            pq += p[i] * q[i];
+        }
+        double alpha = pq != 0.0 ? rz / pq : 0.0;
+        for (int64_t i = 0; i < nv; ++i) {
+            y[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+        }
+        ++it;
+        double rz_new = 0;
+        for (int64_t i = 0; i < nv; ++i) {
+            z[i] = dinv[i] * r[i];
+            rz_new += r[i] * z[i];
+        }
+        double beta = rz != 0.0 ? rz_new / rz : 0.0;
+        rz = rz_new;
+        for (int64_t i = 0; i < nv; ++i) p[i] = z[i] + beta * p[i];
+    }
+    if (replay_count < 0 && it >= max_pcg) {
+        double rn = 0;
+        for (int64_t i = 0; i < nv; ++i) rn += r[i] * r[i];
+        if (sqrt(rn) > rtol * bn) *budget_hit = 1;
+    }
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    return it;
+}
+
+int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
+             const double* D, const int64_t* rowptr, const int32_t* col, const double* val, const double* mass,
+             const uint8_t* pinned, double* x, double* v, double dt, const double* gravity, int max_newton,
+             double newton_rtol, double pcg_rtol, int max_pcg, const int32_t* replay, int32_t* counts, double* stats) {
+    if (!x || !v || !mass || !pinned || dt <= 0 || max_newton < 0) return ORC_E_ARG;
+    size_t n3 = (size_t)(3 * nv);
+    double* xt = (double*)malloc(sizeof(double) * n3);
+    double* xhat = (double*)malloc(sizeof(double) * n3);
+    double* f = (double*)malloc(sizeof(double) * n3);
+    double* g = (double*)malloc(sizeof(double) * n3);
+    double* dinv = (double*)malloc(sizeof(double) * (size_t)nv);
+    double* bcol = (double*)malloc(sizeof(double) * (size_t)nv);
+    double* ycol = (double*)malloc(sizeof(double) * (size_t)nv);
+    double dt2 = dt * dt;
+    memcpy(xt, x, sizeof(double) * n3);
+    /* predictor x_hat = x^t + dt v^t + dt^2 M^-1 f_ext with f_ext = m g (eq 62) */
+    for (int64_t i = 0; i < nv; ++i)
+        for (int d = 0; d < 3; ++d)
+            xhat[3 * i + d] = pinned[i] ? xt[3 * i + d] : xt[3 * i + d] + dt * v[3 * i + d] + dt2 * gravity[d];
+    memcpy(x, xhat, sizeof(double) * n3);
+    /* Jacobi preconditioner: inverse diagonal of M_s + dt^2 K_s */
+    for (int64_t i = 0; i < nv; ++i) {
+        double kii = 0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            if (col[e] == i) kii = val[e];
+        dinv[i] = pinned[i] ? 0.0 : 1.0 / (mass[i] + dt2 * kii);
+    }
+    int newton = 0, pcg_total = 0, budget_hit = 0;
+    double gn0 = 0, gn = 0;
+    for (int k = 0;; ++k) {
+        /* gradient of the incremental potential, g = M(x - x_hat) - dt^2 f(x), pinned rows zero */
+        orc_forces(model, nv, x, ns, idx, B, kappa0, D, f, NULL);
+        double s = 0;
+        for (int64_t i = 0; i < nv; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double gi = pinned[i] ? 0.0 : mass[i] * (x[3 * i + d] - xhat[3 * i + d]) - dt2 * f[3 * i + d];
+                g[3 * i + d] = gi;
+                s += gi * gi;
+            }
+        gn = sqrt(s);
+        if (k == 0) gn0 = gn;
+        if (gn0 == 0.0 || (k > 0 && gn <= newton_rtol * gn0) || k == max_newton) break;
+        /* Newton direction against the constant matrix, one PCG per coordinate */
+        for (int d = 0; d < 3; ++d) {
+            for (int64_t i = 0; i < nv; ++i) bcol[i] = -g[3 * i + d];
+            int rc_count = replay ? replay[3 * k + d] : -1;
+            int it = pcg_column(nv, rowptr, col, val, mass, pinned, dt2, dinv, bcol, ycol, pcg_rtol, max_pcg,
+                                rc_count, &budget_hit);
+            if (counts) counts[3 * k + d] = it;
+            pcg_total += it;
+            for (int64_t i = 0; i < nv; ++i) x[3 * i + d] += ycol[i];
+        }
+        ++newton;
+    }
+    for (size_t i = 0; i < n3; ++i) v[i] = (x[i] - xt[i]) / dt;
+    if (stats) {
+        stats[0] = newton;
+        stats[1] = pcg_total;
+        stats[2] = gn0;
+        stats[3] = gn;
+    }
+    free(xt);
+    free(xhat);
+    free(f);
+    free(g);
+    free(dinv);
+    free(bcol);
+    free(ycol);
+    return budget_hit ? ORC_E_BUDGET : ORC_OK;
+}
+
+/* eq 8 as printed: n_c = p/|p| + q/|q| with p = x1 - x_P, q = x4 - x_Q the height vectors
+   to the feet on the hinge 2->3 (feet from the current geometry, App. B eqs 70-71) */
+int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3, const double* x4, double* n) {
+    double e[3], d1[3], d4[3], p[3], q[3];
+    sub3(x3, x2, e);
+    sub3(x1, x2, d1);
+    sub3(x4, x2, d4);
+    double ee = dot3(e, e);
+    double sp = dot3(d1, e) / ee, sq = dot3(d4, e) / ee;
+    for (int c = 0; c < 3; ++c) {
+        p[c] = d1[c] - sp * e[c];
+        q[c] = d4[c] - sq * e[c];
+    }
+    double pl = norm3(p), ql = norm3(q);
+    double m[3];
+    for (int c = 0; c < 3; ++c) m[c] = p[c] / pl + q[c] / ql;
+    double ml = norm3(m);
+    if (!(ml > 0)) return ORC_E_DEGENERATE;
+    scale3(m, 1.0 / ml, n);
+    return ORC_OK;
+}

@@ -1,0 +1,81 @@
+/*
+ * Plain FP64 CPU oracle for the corotational hinge plate/shell bending models
+ * (EP, ES, FP, FS, SP, SS of "Corotational Hinge-based Thin Plates/Shells").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
+ * definition the HIP library is checked against.  Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never calls it.  It shares no code, header or table with the
+ * HIP library.
+ *
+ * Every function returns 0 on success or a negative ORC_E_* code.
+ * Arrays are caller-owned, row-major, host memory.
+ *
+ * Parity status: every function is pinned by tests under tests/ (closed
+ * forms, invariants, finite differences, brute force) except the FVM
+ * free-edge twist reading (see orc_build), which is "parity unpinned" beyond
+ * the invariants, finite-difference and Hessian pins.
+ */
+#ifndef SHELL_ORACLE_H
+#define SHELL_ORACLE_H
+#include <stdint.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG (-1)
+#define ORC_E_NONMANIFOLD (-2)
+#define ORC_E_ORIENTATION (-3)
+#define ORC_E_DEGENERATE (-4)
+#define ORC_E_BUDGET (-5)
+
+/* model ids: 0 EP, 1 ES, 2 FP, 3 FS, 4 SP, 5 SS */
+int orc_stencil_size(int model);   /* 4 (edge) or 6 (triangle) */
+int orc_curv_size(int model);      /* 1 (edge) or 3 (triangle) */
+
+/* Stencil topology.  idx == NULL: only *ns is returned.  Edge stencils are
+ * (1,2,3,4) per interior edge with 2->3 the directed edge of the lower-id
+ * orientation; triangle stencils are (1,2,3,4,5,6) per triangle with flap
+ * i+3 across the edge opposite vertex i, -1 when that edge is a boundary. */
+int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t* ns, int32_t* idx);
+
+/* Rest precompute: operator B [ns][r][k], rest curvature kappa0 [ns][r]
+ * (zero for plates), material D [ns][r][r] (k_b*A_E for edges, A*D_b for
+ * triangles).  Free-edge folds are applied to B. */
+int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t* idx,
+              double young, double poisson, double thickness,
+              double* B, double* kappa0, double* D);
+
+/* Bending energy and force f = -dPsi/dx over all stencils. f [nv][3] is overwritten. */
+int orc_forces(int model, int64_t nv, const double* x, int64_t ns, const int32_t* idx,
+               const double* B, const double* kappa0, const double* D, double* f, double* energy);
+
+/* Constant bending Hessian, scalar part K_s (K = K_s (x) I3), CSR with sorted
+ * columns.  rowptr [nv+1]; col/val == NULL: only *nnz is returned. */
+int orc_hessian(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* D,
+                int64_t* nnz, int64_t* rowptr, int32_t* col, double* val);
+
+/* Lumped mass m_v = rho*h*sum(A_T)/3 over the rest triangles around v. */
+int orc_mass(int64_t nv, const double* X, int64_t nt, const int32_t* tris, double density, double thickness,
+             double* mass);
+
+/* q = diag(mass) p + dt2 * (K_s (x) I3) p, p and q [nv][3]. */
+int orc_apply(int64_t nv, const int64_t* rowptr, const int32_t* col, const double* val,
+              const double* mass, double dt2, const double* p, double* q);
+
+/* One implicit-Euler step (incremental potential without contact) by a
+ * Newton iteration against the constant matrix M + dt^2 K, each linear solve
+ * by three Jacobi-PCG recurrences (one per coordinate) sharing the operator.
+ * x, v: in x^t, v^t; out x^{t+1}, v^{t+1}.  replay [max_newton][3] or NULL:
+ * when given, every solve runs exactly that many PCG iterations per column.
+ * counts [max_newton][3] receives the iterations taken; stats[4] =
+ * {newton_iters, pcg_total, grad_norm0, grad_norm_final}. */
+int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
+             const double* D, const int64_t* rowptr, const int32_t* col, const double* val,
+             const double* mass, const uint8_t* pinned, double* x, double* v,
+             double dt, const double* gravity, int max_newton, double newton_rtol,
+             double pcg_rtol, int max_pcg, const int32_t* replay, int32_t* counts, double* stats);
+
+/* Normal of an edge stencil by the literal height-vector construction
+ * (sum of the unit height vectors of vertices 1 and 4), used only as a cross-check. */
+int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3, const double* x4, double* n);
+
+#endif
