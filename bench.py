@@ -1,0 +1,177 @@
+"""Benchmark: implicit steps/s and bending stencils/s at about 1M vertices, against the HBM roofline.
+
+Workload: the irregular sphere-cap shell, 1024 x 1024 vertices (2,093,058 triangle stencils), radius
+drawn from U[0.3, 2] m with its seed, in-plane jitter 0.2 of the spacing, smoothed-hinge shell model,
+boundary ring pinned, dt = 1/30 s, gravity; each step is one implicit-Euler step (predictor, Newton
+iterations with force evaluation, residual and a three-column Jacobi-PCG solve against the constant
+Hessian, velocity update).  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 is refused.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def algorithmic_bytes(info: dict, nnz: int, precision: int) -> dict:
+    """Bytes each kernel must move once (no re-reads): per-stencil streams, vertex in/out, matrix."""
+    nv, ns, k, r = info["nv"], info["ns"], info["k"], info["r"]
+    shell = info["model"] in (1, 3, 5)
+    real = 4 if precision == 1 else 8
+    force_out = 4 if precision == 1 else 8
+    per_stencil = 4 * k + real * r * k + (real * r if shell else 0)
+    force = ns * per_stencil + nv * (24 + 3 * force_out)
+    vec = 4 if precision == 1 else 8
+    # SpMV: values + column ids, own p read, q write, mass, pinned flag
+    spmv = nnz * (real + 4) + nv * (3 * vec + 3 * vec + 8 + 1)
+    return dict(force=force, spmv=spmv, force_per_stencil=per_stencil)
+
+
+def cpu_baseline(mesh, material, counts_per_step, newton_per_step, budget_s=30.0):
+    """The FP64 CPU oracle on the same mesh: one force evaluation and a short replayed PCG run are
+    timed, then scaled to the GPU step's measured Newton and PCG iteration counts."""
+    import oracle as O
+
+    st = O.Stencils("SS", mesh.X, mesh.tris, material["young"], material["poisson"], material["thickness"])
+    sim = O.Sim(st, material, mesh.pinned)
+    t0 = time.perf_counter()
+    st.forces(mesh.X)
+    t_force = time.perf_counter() - t0
+    # one Newton solve with 10 and with 20 replayed PCG iterations per coordinate
+    times = {}
+    for n in (10, 20):
+        sim.x[:] = mesh.X
+        sim.v[:] = 0.0
+        t0 = time.perf_counter()
+        sim.step(1 / 30, max_newton=1, replay=np.full((1, 3), n, np.int32))
+        times[n] = time.perf_counter() - t0
+    t_iter = max(times[20] - times[10], 1e-9) / 30.0  # one PCG iteration of one coordinate
+    t_newton = max(times[10] - 30 * t_iter, 0.0)  # predictor, 2 force evaluations and residuals, PCG setup
+    t_setup = max(t_newton - 2 * t_force, 0.0)
+    step_s = newton_per_step * t_setup + (newton_per_step + 1) * t_force + counts_per_step * t_iter
+    return dict(value=1.0 / step_s, unit="steps/s", cores=1, kind="oracle",
+                sample=(f"full 1024x1024 mesh: one force evaluation ({t_force:.2f} s) and one Newton solve with 10 "
+                        f"and 20 replayed PCG iterations per coordinate ({times[10]:.2f} s, {times[20]:.2f} s), "
+                        f"scaled to {newton_per_step:.1f} Newton solves and {counts_per_step:.0f} PCG "
+                        f"coordinate-iterations per step; single thread, {platform.processor() or 'host'} "
+                        f"({os.cpu_count()} logical cpus present)"),
+                seconds=dict(force=t_force, newton_overhead=t_newton, pcg_coord_iter=t_iter))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--max-newton", type=int, default=4)
+    ap.add_argument("--pcg-rtol", type=float, default=1e-2)
+    ap.add_argument("--reps", type=int, default=20, help="launches per kernel for the per-kernel timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-device by design",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2502_10872_amd import inputs as I
+    from paper_2502_10872_amd import shell as S
+
+    assert torch.cuda.is_available(), "needs a HIP device"
+    torch.cuda.set_device(0)
+    precision = S.SHELL_PREC_MIXED if args.precision == "mixed" else S.SHELL_PREC_FP64
+    mat = I.MATERIAL
+    mesh = I.workload_sphere_cap(args.size, "SS")
+    print(f"[bench] building {mesh.nv} vertices, SS, {args.precision}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    pb = S.Problem(mesh, mat, precision=precision)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    rp_nnz = _nnz(S, pb.h)
+    dt = 1.0 / 30.0
+    params, _ = S.step_params(dt, gravity=I.GRAVITY, max_newton=args.max_newton, max_pcg=400000,
+                              newton_rtol=1e-8, pcg_rtol=args.pcg_rtol)
+    for w in range(args.warmup):
+        rc, st = S.shell_step_implicit(pb.sim, params)
+        print(f"[bench] warmup {w}: newton {st['newton_iters']} pcg {st['pcg_total']}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    stats = []
+    t_start = time.perf_counter()
+    ev0.record(stream)
+    for k in range(args.steps):
+        rc, st = S.shell_step_implicit(pb.sim, params, stream=stream)
+        stats.append(st)
+        print(f"[bench] step {k}: newton {st['newton_iters']} pcg {st['pcg_total']} "
+              f"|g|/|g0| {st['grad_norm'] / max(st['grad_norm0'], 1e-300):.3e}", file=sys.stderr, flush=True)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    steps_per_s = args.steps / elapsed
+
+    kt = S.shell_sim_time_kernels(pb.sim, dt, reps=args.reps, stream=stream)
+    ab = algorithmic_bytes(pb.info, rp_nnz, precision)
+    spmv_gbs = ab["spmv"] / (kt["spmv_ms"] * 1e-3) / 1e9
+    force_gbs = ab["force"] / (kt["force_ms"] * 1e-3) / 1e9
+    stencils_per_s = pb.info["ns"] / (kt["force_ms"] * 1e-3)
+    pcg_per_step = float(np.mean([s["pcg_total"] for s in stats]))
+    newton_per_step = float(np.mean([s["newton_iters"] for s in stats]))
+
+    out = dict(
+        metric="implicit steps/s & bending stencils/s at 1M verts vs HBM roofline; p50/p99 latency",
+        value=steps_per_s, unit="steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f64" if precision == 0 else "f32+f64", data="synthetic",
+        config=dict(workload=f"sphere-cap smoothed-hinge shell (SS), {args.size}x{args.size} vertices, "
+                             f"R={mesh.meta['radius']:.4f} m, jitter 0.2, ring pinned, dt=1/30 s, "
+                             f"Newton budget {args.max_newton}, Jacobi-PCG rtol {args.pcg_rtol:g}",
+                    nv=mesh.nv, stencils=pb.info["ns"], nnz=rp_nnz, precision=args.precision,
+                    parallelism="single GPU"),
+        roofline=dict(bound="hbm", kernel="pcg_spmv (3-column SELL-64 product)", achieved=spmv_gbs,
+                      peak=HBM_PEAK_GBS, unit="GB/s", frac=spmv_gbs / HBM_PEAK_GBS, traffic=None,
+                      bytes_per_launch=ab["spmv"], avg_ms=kt["spmv_ms"]),
+        force_kernel=dict(stencils_per_s=stencils_per_s, achieved_gbs=force_gbs, frac=force_gbs / HBM_PEAK_GBS,
+                          bytes_per_launch=ab["force"], bytes_per_stencil_stream=ab["force_per_stencil"],
+                          avg_ms=kt["force_ms"]),
+        pcg_kernels_ms=dict(spmv=kt["spmv_ms"], update=kt["update_ms"], direction=kt["direction_ms"]),
+        per_step=dict(newton_iters=newton_per_step, pcg_coord_iters=pcg_per_step,
+                      grad_ratio=[s["grad_norm"] / max(s["grad_norm0"], 1e-300) for s in stats]),
+        setup_s=setup_s,
+    )
+    if not args.no_cpu_baseline and args.size == 1024:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)
+    pb.close()
+    print(json.dumps(out), flush=True)
+
+
+def _nnz(S, h):
+    import ctypes
+
+    nnz = ctypes.c_int64(0)
+    S._check(S.lib().shell_hessian_export_csr(h, ctypes.byref(nnz), None, None, None), "nnz")
+    return nnz.value
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,233 @@
+/*
+ * shell.h - C ABI of the MI355X (gfx950) library for the per-timestep hot path
+ * of the corotational hinge-based thin plate/shell bending models
+ * ("Corotational Hinge-based Thin Plates/Shells"):
+ *
+ *   EP, ES  edge-based hinge, plate / shell      (Sec. 4.3, eqs 4-29)
+ *   FP, FS  FVM hinge, plate / shell             (Sec. 4.4, eqs 32-45, App. C)
+ *   SP, SS  smoothed hinge, plate / shell        (Sec. 4.5, eqs 46-61)
+ *
+ * and the implicit-Euler step against their constant bending Hessian
+ * (Sec. 5, eqs 62-63; constant Hessians eqs 21, 41, 53).
+ *
+ * Conventions for every entry point:
+ *  - Return value: SHELL_OK (0) or a shell_status_t error; no C++ exception
+ *    crosses the ABI.  shell_last_error() gives a thread-local message.
+ *  - "host" pointers are read (or written) before the call returns; "device"
+ *    pointers are HIP device memory, read/written asynchronously on `stream`
+ *    and must stay valid until the stream reaches the work.
+ *  - `stream` is a hipStream_t; NULL selects the null stream.
+ *  - Vertex arrays are [nv][3] row-major float64 in the caller's vertex order.
+ *    The library keeps its own (Morton block) order internally and converts
+ *    at the boundary.
+ *  - Handles are owned by the library and released by shell_destroy_*; one
+ *    handle must not be used by two threads at once.
+ *  - Models are identified by shell_model_t; a model's curvature size r is 1
+ *    (edge) or 3 (triangle), its stencil size k is 4 (edge) or 6 (triangle).
+ */
+#ifndef SHELL_H
+#define SHELL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SHELL_OK = 0,
+    SHELL_E_INVALID_ARG = 1,  /* a null pointer, a size out of range, an unknown model */
+    SHELL_E_NONMANIFOLD = 2,  /* an edge shared by more than two triangles */
+    SHELL_E_ORIENTATION = 3,  /* two triangles traverse a shared edge in the same direction */
+    SHELL_E_DEGENERATE = 4,   /* a zero-area triangle, a zero height, or an ill-conditioned fit */
+    SHELL_E_NONFINITE = 5,    /* a NaN/Inf in a state or residual */
+    SHELL_E_BUDGET = 6,       /* PCG budget exhausted before the tolerance; state advanced, stats filled */
+    SHELL_E_OOM = 7,          /* device or host allocation failed */
+    SHELL_E_HIP = 8,          /* a HIP runtime call failed */
+    SHELL_E_UNSUPPORTED = 9   /* a valid request this library does not implement */
+} shell_status_t;
+
+typedef enum { SHELL_EP = 0, SHELL_ES = 1, SHELL_FP = 2, SHELL_FS = 3, SHELL_SP = 4, SHELL_SS = 5 } shell_model_t;
+
+typedef enum {
+    SHELL_PREC_FP64 = 0,  /* all arithmetic in float64 */
+    SHELL_PREC_MIXED = 1  /* float32 operators, stencil forces, SpMV and Jacobi preconditioner on float64
+                             stencil-local differences; float64 dot products, solution/residual updates,
+                             Newton residual and all rest precomputation */
+} shell_precision_t;
+
+/* Material (Sec. 3, eq 1; bending rigidity k_b = E h^3 / (12 (1 - nu^2)), Sec. 4.3). */
+typedef struct {
+    double young;      /* E [Pa] */
+    double poisson;    /* nu, in (-1, 0.5] */
+    double thickness;  /* h [m] */
+    double density;    /* rho [kg/m^3], used for the lumped mass rho h A/3 */
+} shell_material_t;
+
+typedef struct {
+    int32_t precision;       /* shell_precision_t */
+    int32_t block_vertices;  /* vertices per force work-group tile; 0 selects the default (1024) */
+    int32_t reorder;         /* 1: Morton vertex order inside the library (default), 0: keep the caller's */
+    int32_t reserved;
+} shell_config_t;
+
+typedef struct shell_stencils_s* shell_stencils_t;
+typedef struct shell_hessian_s* shell_hessian_t;
+typedef struct shell_sim_s* shell_sim_t;
+typedef struct shell_batch_s* shell_batch_t;
+typedef void* shell_stream_t; /* hipStream_t */
+
+/*
+ * shell_build_stencils - topology and rest precomputation of one mesh for one model.
+ *
+ * X     host [nv][3] rest positions (Sec. 4.1, x = X + u).
+ * tris  host [nt][3] vertex ids of a consistently oriented 2-manifold triangle mesh, boundary allowed.
+ * Edge models get one stencil (1,2,3,4) per interior edge (Sec. 4.3, Fig. of the edge hinge);
+ * triangle models one stencil (1,...,6) per triangle, flap i+3 across the edge opposite vertex i
+ * (Secs 4.4-4.5, App. C).  Boundary edges are free (Sec. 4.3: no energy; Secs 4.4-4.5: virtual
+ * node reflected through the edge midpoint and folded, eq 61; FVM additionally drops the twist
+ * across the free edge).  The rest operators (eqs 10, 37-38, 50, App. C eqs 76-78), rest curvature
+ * (eqs 14, 43, 51; shells only) and stencil areas are computed on the GPU in float64.
+ * Errors: SHELL_E_INVALID_ARG, SHELL_E_NONMANIFOLD, SHELL_E_ORIENTATION, SHELL_E_DEGENERATE,
+ * SHELL_E_OOM, SHELL_E_HIP.  The call synchronises `stream` before returning.
+ */
+shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* tris, int64_t nt, int32_t model,
+                                    const shell_material_t* mat, const shell_config_t* cfg, shell_stream_t stream,
+                                    shell_stencils_t* out);
+
+typedef struct {
+    int64_t nv, nt;
+    int64_t ns;             /* unique stencils */
+    int64_t ns_tiled;       /* stencil copies in the tiled force layout (halo stencils repeat) */
+    int64_t nblocks;        /* force work-group tiles */
+    int32_t model, k, r, precision;
+    int32_t block_vertices;
+    int32_t reserved;
+} shell_stencils_info_t;
+
+shell_status_t shell_stencils_info(shell_stencils_t st, shell_stencils_info_t* info);
+
+/*
+ * shell_stencils_export - host copies of the per-stencil rest data, for inspection and tests.
+ * idx     host [ns][k] vertex ids in the caller's order, -1 for a missing flap (may be NULL).
+ * B       host [ns][r][k] operator scaled by the square root of the stencil's stiffness:
+ *         edge sqrt(k_b A_E) L_m, triangle sqrt(A) R L_p (FVM) or sqrt(A) L_g (smoothed), free folds
+ *         applied (may be NULL).
+ * kappa0  host [ns][r] rest curvature scaled the same way; zero for plates (may be NULL).
+ * Stencils come in the library's internal order; match them by idx.
+ */
+shell_status_t shell_stencils_export(shell_stencils_t st, int32_t* idx, double* B, double* kappa0);
+
+/*
+ * shell_eval_forces - bending force f = -dPsi/dx of all stencils at positions x.
+ * Plates: f = -(K_s (x) I3) x through the per-stencil operator (eqs 20-22, 39-41, 52-53).
+ * Shells: the corotational gradient with the current stencil normal (eqs 24-26, 43-45, 55-57;
+ * normal gradients App. B).  x device [nv][3] float64; f device [nv][3], float64 for
+ * SHELL_PREC_FP64 stencils and float32 for SHELL_PREC_MIXED, overwritten.  energy: device float64
+ * scalar receiving the bending energy, or NULL.  Asynchronous on `stream`.
+ */
+shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, double* energy,
+                                 shell_stream_t stream);
+
+/*
+ * shell_assemble_constant_hessian - the constant bending Hessian K = K_s (x) I3 assembled once
+ * from the rest operators (eqs 21, 41, 53; the shells reuse the plate Hessian as the paper states
+ * for each model).  Only the scalar K_s is stored.  Synchronises `stream`.
+ */
+shell_status_t shell_assemble_constant_hessian(shell_stencils_t st, shell_stream_t stream, shell_hessian_t* out);
+
+/*
+ * shell_hessian_export_csr - host copy of K_s in the caller's vertex order, CSR with sorted columns.
+ * Call with col == val == NULL to get nnz; rowptr is [nv+1] and may be NULL in that call.
+ */
+shell_status_t shell_hessian_export_csr(shell_hessian_t h, int64_t* nnz, int64_t* rowptr, int32_t* col, double* val);
+
+/*
+ * shell_hessian_apply - q = diag(mass) p + dt2 (K_s (x) I3) p, the operator of the implicit step.
+ * mass device [nv] float64 or NULL (no mass term); p, q device [nv][3] float64, caller order.
+ */
+shell_status_t shell_hessian_apply(shell_hessian_t h, const double* mass, double dt2, const double* p, double* q,
+                                   shell_stream_t stream);
+
+/*
+ * shell_sim_create - simulation state for the implicit step (Sec. 5).
+ * x0, v0 host [nv][3] (v0 may be NULL = zero); pinned host [nv], 1 = all three coordinates held at
+ * x0 (fixed boundary nodes, Sec. 4.3), may be NULL.  The lumped mass rho h sum(A_T)/3 is computed
+ * from the rest mesh.  The stencils and Hessian must outlive the simulation.
+ */
+shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const double* x0, const double* v0,
+                                const uint8_t* pinned, shell_sim_t* out);
+
+#define SHELL_MAX_NEWTON 64
+
+typedef enum { SHELL_PCG_TOLERANCE = 0, SHELL_PCG_REPLAY = 1 } shell_pcg_mode_t;
+
+typedef struct {
+    double dt;             /* time step [s] */
+    double gravity[3];     /* acceleration [m/s^2]; f_ext = m g */
+    int32_t max_newton;    /* Newton solves per step, 0..SHELL_MAX_NEWTON */
+    int32_t max_pcg;       /* PCG iteration cap per column (tolerance mode) */
+    double newton_rtol;    /* stop when ||g_k|| <= newton_rtol ||g_0|| */
+    double pcg_rtol;       /* per column: stop when ||r|| <= pcg_rtol ||b|| */
+    int32_t mode;          /* shell_pcg_mode_t */
+    int32_t chunk;         /* PCG iterations launched between host convergence checks; 0 = default */
+    const int32_t* replay_counts; /* host [max_newton][3], REPLAY only: exact PCG iterations */
+} shell_step_params_t;
+
+typedef struct {
+    int32_t newton_iters;  /* Newton solves performed */
+    int32_t pcg_total;     /* PCG iterations summed over solves and columns */
+    int32_t status;        /* shell_status_t of the step (SHELL_E_BUDGET is a warning) */
+    int32_t reserved;
+    double grad_norm0;     /* ||g|| at the predictor */
+    double grad_norm;      /* ||g|| at the returned state */
+    int32_t counts[SHELL_MAX_NEWTON][3]; /* PCG iterations per Newton solve and coordinate */
+} shell_step_stats_t;
+
+/*
+ * shell_step_implicit - one implicit-Euler step x^t -> x^{t+1}: predictor x_hat = x + dt v + dt^2 g,
+ * Newton iterations on the incremental potential E(x) = 1/2 (x-x_hat)^T M (x-x_hat) + dt^2 Psi(x)
+ * (eq 62 without contact terms) against the constant matrix M + dt^2 K_s (x) I3, each solve by three
+ * Jacobi-PCG recurrences (one per coordinate) sharing one sparse product, then v = (x^{t+1}-x^t)/dt.
+ * stats (host, may be NULL): when given, the call synchronises `stream` and fills it.
+ * Returns SHELL_E_BUDGET when a PCG column hit max_pcg (the state is still advanced).
+ */
+shell_status_t shell_step_implicit(shell_sim_t sim, const shell_step_params_t* params, shell_step_stats_t* stats,
+                                   shell_stream_t stream);
+
+shell_status_t shell_sim_get_stats(shell_sim_t sim, shell_step_stats_t* out);
+/* host copies in caller order; x, v may be NULL; synchronises the simulation's last stream */
+shell_status_t shell_sim_get_state(shell_sim_t sim, double* x, double* v, int64_t* step);
+shell_status_t shell_sim_set_state(shell_sim_t sim, const double* x, const double* v, int64_t step);
+/* device views of the state in the library's internal order (for timing harnesses), may be NULL */
+shell_status_t shell_sim_device_state(shell_sim_t sim, double** x, double** v);
+
+/*
+ * shell_sim_time_kernels - timing harness: average duration of one launch of each hot kernel of the
+ * step, measured with HIP events on `stream` over `reps` back-to-back launches on the simulation's
+ * current state (forces at x, then the three PCG kernels on a freshly initialised recurrence).  The
+ * position and velocity are not modified; the solver's work vectors are.  Synchronises `stream`.
+ */
+typedef struct {
+    double force_ms;      /* bending force kernel over all stencils (internal vertex order) */
+    double spmv_ms;       /* PCG product q = (M + dt^2 K_s) p for the three coordinates */
+    double update_ms;     /* PCG y/r/z update with its dot products */
+    double direction_ms;  /* PCG search-direction update */
+    int32_t reps;
+    int32_t reserved;
+} shell_kernel_times_t;
+
+shell_status_t shell_sim_time_kernels(shell_sim_t sim, double dt, int32_t reps, shell_kernel_times_t* out,
+                                      shell_stream_t stream);
+
+void shell_destroy_stencils(shell_stencils_t st);
+void shell_destroy_hessian(shell_hessian_t h);
+void shell_destroy_sim(shell_sim_t sim);
+
+const char* shell_status_string(shell_status_t s);
+const char* shell_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

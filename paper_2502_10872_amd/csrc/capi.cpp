@@ -1,0 +1,461 @@
+// C ABI entry points (include/shell.h): argument checks, handle lifetime, caller <-> internal vertex
+// order, and translation of exceptions into status codes.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "internal.hpp"
+
+using namespace shell;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+template <typename F>
+shell_status_t guarded(F&& fn) {
+    try {
+        g_last_error.clear();
+        return fn();
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return SHELL_E_OOM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SHELL_E_INVALID_ARG;
+    }
+}
+
+hipStream_t as_stream(shell_stream_t s) { return static_cast<hipStream_t>(s); }
+
+__global__ void gather1(const double* __restrict__ src, const int32_t* __restrict__ perm, double* __restrict__ dst,
+                        long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* shell_status_string(shell_status_t s) {
+    switch (s) {
+        case SHELL_OK: return "ok";
+        case SHELL_E_INVALID_ARG: return "invalid argument";
+        case SHELL_E_NONMANIFOLD: return "non-manifold mesh";
+        case SHELL_E_ORIENTATION: return "inconsistent triangle orientation";
+        case SHELL_E_DEGENERATE: return "degenerate stencil";
+        case SHELL_E_NONFINITE: return "non-finite value";
+        case SHELL_E_BUDGET: return "iteration budget exhausted";
+        case SHELL_E_OOM: return "out of memory";
+        case SHELL_E_HIP: return "HIP runtime error";
+        case SHELL_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* shell_last_error(void) { return g_last_error.c_str(); }
+
+shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* tris, int64_t nt, int32_t model,
+                                    const shell_material_t* mat, const shell_config_t* cfg, shell_stream_t stream,
+                                    shell_stencils_t* out) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(out && mat && (X || nv == 0) && (tris || nt == 0), SHELL_E_INVALID_ARG, "null argument");
+        *out = nullptr;
+        SHELL_CHECK(model >= SHELL_EP && model <= SHELL_SS, SHELL_E_INVALID_ARG, "unknown model");
+        SHELL_CHECK(nv >= 0 && nt >= 0 && nv < (int64_t(1) << 31) && 3 * nt < (int64_t(1) << 31), SHELL_E_INVALID_ARG,
+                    "mesh size out of range");
+        SHELL_CHECK(mat->young > 0 && mat->thickness > 0 && mat->density >= 0 && mat->poisson > -1.0 &&
+                        mat->poisson < 1.0,
+                    SHELL_E_INVALID_ARG, "material out of range");
+        for (int64_t i = 0; i < 3 * nv; ++i)
+            SHELL_CHECK(std::isfinite(X[i]), SHELL_E_NONFINITE, "non-finite rest position");
+        int precision = cfg ? cfg->precision : SHELL_PREC_FP64;
+        SHELL_CHECK(precision == SHELL_PREC_FP64 || precision == SHELL_PREC_MIXED, SHELL_E_INVALID_ARG,
+                    "unknown precision");
+        int T = (cfg && cfg->block_vertices > 0) ? cfg->block_vertices : 1024;
+        SHELL_CHECK(T >= 64 && T <= 4096, SHELL_E_INVALID_ARG, "block_vertices must be in [64, 4096]");
+        bool reorder = cfg ? cfg->reorder != 0 : true;
+        hipStream_t s = as_stream(stream);
+
+        auto st = std::make_unique<shell_stencils_s>();
+        st->model = model;
+        st->k = model_k(model);
+        st->r = model_r(model);
+        st->precision = precision;
+        st->nv = nv;
+        st->nt = nt;
+        st->T = T;
+        st->young = mat->young;
+        st->poisson = mat->poisson;
+        st->thickness = mat->thickness;
+        st->density = mat->density;
+        st->kb = mat->young * std::pow(mat->thickness, 3) / (12.0 * (1.0 - mat->poisson * mat->poisson));
+
+        HostTopology topo = build_topology(model, nv, nt, tris);
+        const int k = st->k, r = st->r;
+        st->ns = topo.ns;
+        st->perm = vertex_order(X, nv, reorder);
+        st->reordered = reorder;
+        st->iperm.assign(size_t(nv), 0);
+        for (int64_t i = 0; i < nv; ++i) st->iperm[size_t(st->perm[size_t(i)])] = int32_t(i);
+        // stencils in internal ids, sorted by their first vertex for locality
+        std::vector<int64_t> order(size_t(st->ns));
+        for (int64_t q = 0; q < st->ns; ++q) order[size_t(q)] = q;
+        auto iid = [&](int32_t v) { return v < 0 ? -1 : st->iperm[size_t(v)]; };
+        std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+            return iid(topo.idx[size_t(k * a)]) < iid(topo.idx[size_t(k * b)]);
+        });
+        st->h_idx.resize(size_t(k * st->ns));
+        for (int64_t q = 0; q < st->ns; ++q)
+            for (int j = 0; j < k; ++j) st->h_idx[size_t(k * q + j)] = iid(topo.idx[size_t(k * order[size_t(q)] + j)]);
+        std::vector<double> Xi(size_t(3 * nv));
+        for (int64_t i = 0; i < nv; ++i)
+            for (int c = 0; c < 3; ++c) Xi[size_t(3 * i + c)] = X[3 * int64_t(st->perm[size_t(i)]) + c];
+        st->h_tris.resize(size_t(3 * nt));
+        for (int64_t t = 0; t < 3 * nt; ++t) st->h_tris[size_t(t)] = st->iperm[size_t(tris[t])];
+
+        const size_t ns = size_t(st->ns);
+        st->X.alloc(size_t(3 * nv));
+        st->X.upload(Xi.data(), Xi.size(), s);
+        st->tris.alloc(size_t(3 * nt));
+        st->tris.upload(st->h_tris.data(), st->h_tris.size(), s);
+        st->perm_d.alloc(size_t(nv));
+        st->perm_d.upload(st->perm.data(), size_t(nv), s);
+        // unique stencils, SoA; a missing flap points at vertex 1 (its operator column is zero)
+        std::vector<int32_t> soa(size_t(k) * ns);
+        for (size_t q = 0; q < ns; ++q)
+            for (int j = 0; j < k; ++j) {
+                int32_t v = st->h_idx[size_t(k) * q + j];
+                soa[size_t(j) * ns + q] = v < 0 ? st->h_idx[size_t(k) * q] : v;
+            }
+        st->idx.alloc(soa.size());
+        st->idx.upload(soa.data(), soa.size(), s);
+        st->B.alloc(size_t(r * k) * ns);
+        st->k0.alloc(size_t(r) * ns);
+        st->flags.alloc(ns);
+        launch_precompute(*st, s);
+        std::vector<int32_t> flags(ns);
+        st->flags.download(flags.data(), ns, s);
+        SHELL_HIP(hipStreamSynchronize(s));
+        for (size_t q = 0; q < ns; ++q)
+            SHELL_CHECK(flags[q] == 0, SHELL_E_DEGENERATE,
+                        "degenerate stencil (zero area or height, or ill-conditioned quadratic fit)");
+        // tiles for the force kernel
+        Tiling til = build_tiling(st->h_idx, k, st->ns, nv, T);
+        st->nblocks = til.nblocks;
+        st->ns_tiled = int64_t(til.src.size());
+        st->h_boff = til.boff;
+        st->boff.alloc(til.boff.size());
+        st->boff.upload(til.boff.data(), til.boff.size(), s);
+        st->tsrc.alloc(til.src.size());
+        st->tsrc.upload(til.src.data(), til.src.size(), s);
+        const size_t nst = size_t(st->ns_tiled);
+        st->tidx.alloc(size_t(k) * nst);
+        st->tB.alloc(size_t(r * k) * nst);
+        st->tk0.alloc(size_t(r) * nst);
+        if (precision == SHELL_PREC_MIXED) {
+            st->tBf.alloc(size_t(r * k) * nst);
+            st->tk0f.alloc(size_t(r) * nst);
+        }
+        launch_tile_copy(*st, s);
+        st->xin.alloc(size_t(3 * nv));
+        st->fout.alloc(size_t(3 * nv));
+        st->epart.alloc(size_t(st->nblocks));
+        SHELL_HIP(hipStreamSynchronize(s));
+        *out = st.release();
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_stencils_info(shell_stencils_t st, shell_stencils_info_t* info) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(st && info, SHELL_E_INVALID_ARG, "null argument");
+        std::memset(info, 0, sizeof(*info));
+        info->nv = st->nv;
+        info->nt = st->nt;
+        info->ns = st->ns;
+        info->ns_tiled = st->ns_tiled;
+        info->nblocks = st->nblocks;
+        info->model = st->model;
+        info->k = st->k;
+        info->r = st->r;
+        info->precision = st->precision;
+        info->block_vertices = st->T;
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_stencils_export(shell_stencils_t st, int32_t* idx, double* B, double* kappa0) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(st, SHELL_E_INVALID_ARG, "null handle");
+        const size_t ns = size_t(st->ns);
+        const int k = st->k, r = st->r;
+        if (idx)
+            for (size_t q = 0; q < ns; ++q)
+                for (int j = 0; j < k; ++j) {
+                    int32_t v = st->h_idx[size_t(k) * q + j];
+                    idx[size_t(k) * q + j] = v < 0 ? -1 : st->perm[size_t(v)];
+                }
+        if (B || kappa0) {
+            std::vector<double> hb(size_t(r * k) * ns), hk(size_t(r) * ns);
+            st->B.download(hb.data(), hb.size(), nullptr);
+            st->k0.download(hk.data(), hk.size(), nullptr);
+            SHELL_HIP(hipDeviceSynchronize());
+            for (size_t q = 0; q < ns; ++q) {
+                if (B)
+                    for (int c = 0; c < r * k; ++c) B[size_t(r * k) * q + c] = hb[size_t(c) * ns + q];
+                if (kappa0)
+                    for (int c = 0; c < r; ++c) kappa0[size_t(r) * q + c] = hk[size_t(c) * ns + q];
+            }
+        }
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, double* energy,
+                                 shell_stream_t stream) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(st && (x || st->nv == 0) && (f || st->nv == 0), SHELL_E_INVALID_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        const bool f32 = st->precision == SHELL_PREC_MIXED;
+        if (st->reordered) {
+            launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
+            launch_forces(*st, st->xin.p, st->fout.p, energy ? st->epart.p : nullptr, s);
+            launch_scatter_rows(st->fout.p, st->perm_d.p, f, st->nv, f32, s);
+        } else {
+            launch_forces(*st, x, f, energy ? st->epart.p : nullptr, s);
+        }
+        if (energy) {
+            if (st->nv == 0)
+                SHELL_HIP(hipMemsetAsync(energy, 0, sizeof(double), s));
+            else
+                launch_energy_finalize(st->epart.p, st->nblocks, energy, s);
+        }
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_assemble_constant_hessian(shell_stencils_t st, shell_stream_t stream, shell_hessian_t* out) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(st && out, SHELL_E_INVALID_ARG, "null argument");
+        *out = nullptr;
+        hipStream_t s = as_stream(stream);
+        auto h = std::make_unique<shell_hessian_s>();
+        h->st = st;
+        h->pat = build_sell_pattern(st->h_idx, st->k, st->ns, st->nv);
+        const auto& P = h->pat;
+        h->scol.alloc(size_t(P.nslots));
+        h->scol.upload(P.scol.data(), size_t(P.nslots), s);
+        h->width.alloc(size_t(P.nslices));
+        h->width.upload(P.width.data(), size_t(P.nslices), s);
+        h->sptr.alloc(size_t(P.nslices + 1));
+        h->sptr.upload(P.sptr.data(), size_t(P.nslices + 1), s);
+        h->rowlen.alloc(size_t(st->nv));
+        h->rowlen.upload(P.rowlen.data(), size_t(st->nv), s);
+        h->val.alloc(size_t(P.nslots));
+        if (st->precision == SHELL_PREC_MIXED) h->valf.alloc(size_t(P.nslots));
+        h->kdiag.alloc(size_t(st->nv));
+        h->pin.alloc(size_t(3 * st->nv));
+        h->qout.alloc(size_t(4 * st->nv));
+        launch_assemble(*h, s);
+        *out = h.release();
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_hessian_export_csr(shell_hessian_t h, int64_t* nnz, int64_t* rowptr, int32_t* col,
+                                        double* val) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(h && nnz, SHELL_E_INVALID_ARG, "null argument");
+        const auto& P = h->pat;
+        *nnz = P.nnz;
+        if (!col && !val && !rowptr) return SHELL_OK;
+        const shell_stencils_s& st = *h->st;
+        std::vector<double> sv(size_t(P.nslots));
+        h->val.download(sv.data(), sv.size(), nullptr);
+        SHELL_HIP(hipDeviceSynchronize());
+        const int64_t nv = st.nv;
+        // caller row u = perm[i]; its entries are internal row i's, columns mapped by perm and re-sorted
+        std::vector<int64_t> ptr(size_t(nv + 1), 0);
+        for (int64_t i = 0; i < nv; ++i) ptr[size_t(st.perm[size_t(i)]) + 1] = P.rowptr[i + 1] - P.rowptr[i];
+        for (int64_t u = 0; u < nv; ++u) ptr[u + 1] += ptr[u];
+        if (rowptr) std::copy(ptr.begin(), ptr.end(), rowptr);
+        if (!col && !val) return SHELL_OK;
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t u = 0; u < nv; ++u) {
+            int64_t i = st.iperm[size_t(u)];
+            row.clear();
+            for (int64_t e = P.rowptr[i]; e < P.rowptr[i + 1]; ++e)
+                row.emplace_back(st.perm[size_t(P.col[size_t(e)])], sv[size_t(P.csr2sell[size_t(e)])]);
+            std::sort(row.begin(), row.end(),
+                      [](const auto& a, const auto& b) { return a.first < b.first; });
+            for (size_t q = 0; q < row.size(); ++q) {
+                if (col) col[ptr[u] + int64_t(q)] = row[q].first;
+                if (val) val[ptr[u] + int64_t(q)] = row[q].second;
+            }
+        }
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_hessian_apply(shell_hessian_t h, const double* mass, double dt2, const double* p, double* q,
+                                   shell_stream_t stream) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(h && p && q, SHELL_E_INVALID_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        const shell_stencils_s& st = *h->st;
+        const long nv = st.nv;
+        if (!nv) return SHELL_OK;
+        double* min = nullptr;
+        if (mass) {
+            min = h->qout.p + 3 * nv;
+            gather1<<<(nv + 255) / 256, 256, 0, s>>>(mass, st.perm_d.p, min, nv);
+            SHELL_HIP(hipGetLastError());
+        }
+        launch_gather_rows(p, st.perm_d.p, h->pin.p, nv, s);
+        launch_apply(*h, min, dt2, h->pin.p, h->qout.p, s);
+        launch_scatter_rows(h->qout.p, st.perm_d.p, q, nv, false, s);
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const double* x0, const double* v0,
+                                const uint8_t* pinned, shell_sim_t* out) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(st && h && out && (x0 || st->nv == 0) && h->st == st, SHELL_E_INVALID_ARG, "bad argument");
+        *out = nullptr;
+        auto sim = std::make_unique<shell_sim_s>();
+        sim->st = st;
+        sim->h = h;
+        sim->nv = st->nv;
+        sim_alloc(*sim);
+        const int64_t nv = st->nv;
+        std::vector<double> xi(size_t(3 * nv)), vi(size_t(3 * nv), 0.0);
+        std::vector<uint8_t> pi(size_t(nv), 0);
+        for (int64_t i = 0; i < nv; ++i) {
+            int64_t u = st->perm[size_t(i)];
+            for (int c = 0; c < 3; ++c) {
+                xi[size_t(3 * i + c)] = x0[3 * u + c];
+                if (v0) vi[size_t(3 * i + c)] = v0[3 * u + c];
+            }
+            if (pinned) pi[size_t(i)] = pinned[u] ? 1 : 0;
+        }
+        hipStream_t s = nullptr;
+        sim->x.upload(xi.data(), xi.size(), s);
+        sim->v.upload(vi.data(), vi.size(), s);
+        sim->pinned.upload(pi.data(), pi.size(), s);
+        sim_mass(*sim, s);
+        SHELL_HIP(hipStreamSynchronize(s));
+        *out = sim.release();
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_step_implicit(shell_sim_t sim, const shell_step_params_t* params, shell_step_stats_t* stats,
+                                   shell_stream_t stream) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim && params, SHELL_E_INVALID_ARG, "null argument");
+        const shell_step_params_t& p = *params;
+        SHELL_CHECK(p.dt > 0 && std::isfinite(p.dt), SHELL_E_INVALID_ARG, "dt must be positive");
+        SHELL_CHECK(p.max_newton >= 0 && p.max_newton <= SHELL_MAX_NEWTON, SHELL_E_INVALID_ARG,
+                    "max_newton out of range");
+        SHELL_CHECK(p.mode == SHELL_PCG_TOLERANCE || p.mode == SHELL_PCG_REPLAY, SHELL_E_INVALID_ARG, "unknown mode");
+        SHELL_CHECK(p.mode != SHELL_PCG_REPLAY || p.replay_counts, SHELL_E_INVALID_ARG, "replay needs counts");
+        SHELL_CHECK(p.mode == SHELL_PCG_REPLAY || p.max_pcg > 0, SHELL_E_INVALID_ARG, "max_pcg must be positive");
+        SHELL_CHECK(p.chunk >= 0, SHELL_E_INVALID_ARG, "chunk must be >= 0");
+        if (p.mode == SHELL_PCG_REPLAY)
+            for (int q = 0; q < 3 * p.max_newton; ++q)
+                SHELL_CHECK(p.replay_counts[q] >= 0, SHELL_E_INVALID_ARG, "negative replay count");
+        shell_status_t rc = sim_step(*sim, p, as_stream(stream));
+        if (stats) {
+            SHELL_HIP(hipStreamSynchronize(as_stream(stream)));
+            *stats = sim->stats;
+        }
+        if (rc == SHELL_E_BUDGET) g_last_error = "PCG iteration budget exhausted";
+        if (rc == SHELL_E_NONFINITE) g_last_error = "non-finite residual";
+        return rc;
+    });
+}
+
+shell_status_t shell_sim_get_stats(shell_sim_t sim, shell_step_stats_t* out) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim && out, SHELL_E_INVALID_ARG, "null argument");
+        *out = sim->stats;
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_get_state(shell_sim_t sim, double* x, double* v, int64_t* step) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim, SHELL_E_INVALID_ARG, "null handle");
+        const int64_t nv = sim->nv;
+        const auto& perm = sim->st->perm;
+        SHELL_HIP(hipStreamSynchronize(sim->last_stream));
+        std::vector<double> buf(size_t(3 * nv));
+        for (int which = 0; which < 2; ++which) {
+            double* dst = which ? v : x;
+            if (!dst) continue;
+            (which ? sim->v : sim->x).download(buf.data(), buf.size(), nullptr);
+            SHELL_HIP(hipDeviceSynchronize());
+            for (int64_t i = 0; i < nv; ++i)
+                for (int c = 0; c < 3; ++c) dst[3 * int64_t(perm[size_t(i)]) + c] = buf[size_t(3 * i + c)];
+        }
+        if (step) *step = sim->step;
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_set_state(shell_sim_t sim, const double* x, const double* v, int64_t step) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim, SHELL_E_INVALID_ARG, "null handle");
+        const int64_t nv = sim->nv;
+        const auto& perm = sim->st->perm;
+        SHELL_HIP(hipStreamSynchronize(sim->last_stream));
+        std::vector<double> buf(size_t(3 * nv));
+        for (int which = 0; which < 2; ++which) {
+            const double* src = which ? v : x;
+            if (!src) continue;
+            for (int64_t i = 0; i < nv; ++i)
+                for (int c = 0; c < 3; ++c) buf[size_t(3 * i + c)] = src[3 * int64_t(perm[size_t(i)]) + c];
+            (which ? sim->v : sim->x).upload(buf.data(), buf.size(), nullptr);
+            SHELL_HIP(hipDeviceSynchronize());
+        }
+        sim->step = step;
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_device_state(shell_sim_t sim, double** x, double** v) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim, SHELL_E_INVALID_ARG, "null handle");
+        if (x) *x = sim->x.p;
+        if (v) *v = sim->v.p;
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_time_kernels(shell_sim_t sim, double dt, int32_t reps, shell_kernel_times_t* out,
+                                      shell_stream_t stream) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim && out && reps > 0 && dt > 0, SHELL_E_INVALID_ARG, "bad argument");
+        std::memset(out, 0, sizeof(*out));
+        sim_time_kernels(*sim, dt, reps, *out, as_stream(stream));
+        return SHELL_OK;
+    });
+}
+
+void shell_destroy_stencils(shell_stencils_t st) { delete st; }
+void shell_destroy_hessian(shell_hessian_t h) { delete h; }
+void shell_destroy_sim(shell_sim_t sim) {
+    if (!sim) return;
+    if (sim->state_host) (void)hipHostFree(sim->state_host);
+    delete sim;
+}
+
+}  // extern "C"

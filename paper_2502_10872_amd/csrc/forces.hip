@@ -1,0 +1,271 @@
+// Per-stencil bending forces, the per-timestep hot kernel.
+//
+// Layout: vertices are numbered in tiles of T consecutive (Morton-ordered) ids.  One work-group owns
+// one tile and walks the list of every stencil that touches the tile (stencils on a tile boundary
+// appear in each tile they touch).  Each stencil's force on the tile's own vertices is added into an
+// LDS accumulator; contributions to other tiles' vertices are left to those tiles.  The tile is
+// then written to HBM once: no global atomics, no zero-fill, one coalesced store per vertex.
+// Stencil data is streamed structure-of-arrays so every load is coalesced.
+//
+// Per stencil (operator B already scaled by the square root of its stiffness):
+//   C_i = sum_j B_ij (x_j - x_o)            curvature vectors, x_o the stencil origin (rows of B
+//                                          sum to zero, so local differences give the same C)
+//   plate: f_j = -sum_i B_ij (D C)_i                          eqs 20-22, 39-41, 52-53
+//   shell: delta = n.C - kappa0, g = D delta,
+//          f_j = -(sum_i g_i B_ij) n - (dn/dx_j)^T sum_i g_i C_i   eqs 24-26, 43-45, 55-57
+// with D = 1 (edge) or D_b / k_b-form [[1,nu,0],[nu,1,0],[0,0,(1-nu)/2]] * k_b (triangle), n the
+// unit normal of the central triangle (eq 15) or the bisector of the two hinge triangle normals
+// (edge; the line of eq 8), its gradient by the chain rule of App. B (eqs 67, 73).
+// Mixed precision: positions are gathered in float64 and differenced in float64; everything after
+// the difference is float32.
+#include "devmath.hpp"
+#include "internal.hpp"
+
+namespace shell {
+
+namespace {
+
+template <typename R, bool SHELL>
+__device__ __forceinline__ void edge_stencil(const V3<double> (&xg)[4], const R (&L)[4], R kappa0,
+                                             V3<R> (&f)[4], R& energy) {
+    V3<R> a = cvt<R>(xg[0] - xg[1]), c = cvt<R>(xg[2] - xg[1]), b = cvt<R>(xg[3] - xg[1]);
+    V3<R> C = L[0] * a;
+    fma3(C, L[2], c);
+    fma3(C, L[3], b);
+    if constexpr (!SHELL) {
+        energy = R(0.5) * dot(C, C);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) f[j] = (-L[j]) * C;
+    } else {
+        V3<R> ua = cross(c, a), ub = cross(b, c);
+        R ila = R(1) / norm(ua), ilb = R(1) / norm(ub);
+        V3<R> na = ila * ua, nb = ilb * ub;
+        V3<R> m = na + nb;
+        R ilm = R(1) / norm(m);
+        V3<R> n = ilm * m;
+        R delta = dot(n, C) - kappa0;
+        energy = R(0.5) * delta * delta;
+        // w = (I - n n^T) C / |m|, then through each unit triangle normal
+        V3<R> w = ilm * (C - dot(C, n) * n);
+        V3<R> wa = ila * (w - dot(w, na) * na);
+        V3<R> wb = ilb * (w - dot(w, nb) * nb);
+        V3<R> g1 = cross(wa, c);
+        V3<R> g2 = cross(wa, a - c) + cross(wb, c - b);
+        V3<R> g3 = cross(wb, b) - cross(wa, a);
+        V3<R> g4 = cross(c, wb);
+        f[0] = (-delta) * (L[0] * n + g1);
+        f[1] = (-delta) * (L[1] * n + g2);
+        f[2] = (-delta) * (L[2] * n + g3);
+        f[3] = (-delta) * (L[3] * n + g4);
+    }
+}
+
+template <typename R, bool SHELL>
+__device__ __forceinline__ void tri_stencil(const V3<double> (&xg)[6], const R (&B)[3][6], const R (&k0)[3], R kb,
+                                            R nu, V3<R> (&f)[6], R& energy) {
+    V3<R> d[6];
+    d[0] = mk(R(0), R(0), R(0));
+#pragma unroll
+    for (int j = 1; j < 6; ++j) d[j] = cvt<R>(xg[j] - xg[0]);
+    V3<R> C[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        C[i] = B[i][1] * d[1];
+#pragma unroll
+        for (int j = 2; j < 6; ++j) fma3(C[i], B[i][j], d[j]);
+    }
+    const R t = R(0.5) * (R(1) - nu);
+    if constexpr (!SHELL) {
+        V3<R> DC[3];
+        DC[0] = kb * (C[0] + nu * C[1]);
+        DC[1] = kb * (nu * C[0] + C[1]);
+        DC[2] = (kb * t) * C[2];
+        energy = R(0.5) * (dot(C[0], DC[0]) + dot(C[1], DC[1]) + dot(C[2], DC[2]));
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            V3<R> fj = (-B[0][j]) * DC[0];
+            fma3(fj, -B[1][j], DC[1]);
+            fma3(fj, -B[2][j], DC[2]);
+            f[j] = fj;
+        }
+    } else {
+        V3<R> u = cross(d[1], d[2]);
+        R ilu = R(1) / norm(u);
+        V3<R> n = ilu * u;
+        R de0 = dot(n, C[0]) - k0[0], de1 = dot(n, C[1]) - k0[1], de2 = dot(n, C[2]) - k0[2];
+        R g0 = kb * (de0 + nu * de1), g1 = kb * (nu * de0 + de1), g2 = kb * t * de2;
+        energy = R(0.5) * (de0 * g0 + de1 * g1 + de2 * g2);
+        V3<R> Cg = g0 * C[0];
+        fma3(Cg, g1, C[1]);
+        fma3(Cg, g2, C[2]);
+        V3<R> w = ilu * (Cg - dot(Cg, n) * n);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            R bj = g0 * B[0][j] + g1 * B[1][j] + g2 * B[2][j];
+            f[j] = (-bj) * n;
+        }
+        // (du/dx1)^T w = w x (x3 - x2), (du/dx2)^T w = w x (x1 - x3), (du/dx3)^T w = w x (x2 - x1)
+        f[0] = f[0] - cross(w, d[2] - d[1]);
+        f[1] = f[1] - cross(d[2], w);
+        f[2] = f[2] - cross(w, d[1]);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void lds_add(R* acc, int slot, V3<R> v) {
+    atomicAdd(acc + 3 * slot + 0, v.x);
+    atomicAdd(acc + 3 * slot + 1, v.y);
+    atomicAdd(acc + 3 * slot + 2, v.z);
+}
+
+// One work-group per vertex tile.  K = 4 (edge) or 6 (triangle) vertices per stencil.
+template <int MODEL, typename R>
+__global__ __launch_bounds__(256) void force_tiles(const double* __restrict__ x, const int64_t* __restrict__ boff,
+                                                   const int32_t* __restrict__ tidx, const R* __restrict__ tB,
+                                                   const R* __restrict__ tk0, long nst, long nv, int T,
+                                                   long nblocks, R kb, R nu, R* __restrict__ f,
+                                                   double* __restrict__ epart) {
+    constexpr bool EDGE = (MODEL == SHELL_EP || MODEL == SHELL_ES);
+    constexpr bool SHELL = (MODEL == SHELL_ES || MODEL == SHELL_FS || MODEL == SHELL_SS);
+    constexpr int K = EDGE ? 4 : 6;
+    extern __shared__ unsigned char smem_raw[];
+    R* acc = reinterpret_cast<R*>(smem_raw);
+    long blk = xcd_logical(blockIdx.x, gridDim.x);
+    if (blk >= nblocks) return;
+    const long base = blk * long(T);
+    const int nown = int(min(long(T), nv - base));
+    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) acc[i] = R(0);
+    __syncthreads();
+    double e_own = 0.0;
+    const long e0 = boff[blk], e1 = boff[blk + 1];
+    for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        int vid[K];
+        V3<double> xg[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            vid[j] = __builtin_nontemporal_load(tidx + j * nst + e);
+            xg[j] = load3(x, vid[j]);
+        }
+        V3<R> fs[K];
+        R en;
+        if constexpr (EDGE) {
+            R L[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) L[j] = __builtin_nontemporal_load(tB + j * nst + e);
+            R k0 = SHELL ? __builtin_nontemporal_load(tk0 + e) : R(0);
+            edge_stencil<R, SHELL>(xg, L, k0, fs, en);
+        } else {
+            R Bm[3][6], k0[3];
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+#pragma unroll
+                for (int j = 0; j < 6; ++j) Bm[i][j] = __builtin_nontemporal_load(tB + (i * 6 + j) * nst + e);
+                k0[i] = SHELL ? __builtin_nontemporal_load(tk0 + i * nst + e) : R(0);
+            }
+            tri_stencil<R, SHELL>(xg, Bm, k0, kb, nu, fs, en);
+        }
+        // the tile that owns vertex 1 of the stencil counts its energy
+        if (unsigned(vid[0] - base) < unsigned(nown)) e_own += double(en);
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            unsigned slot = unsigned(vid[j] - base);
+            if (slot < unsigned(nown)) lds_add(acc, int(slot), fs[j]);
+        }
+    }
+    __syncthreads();
+    R* out = f + 3 * base;
+    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = acc[i];
+    if (epart) {
+        __shared__ double sh[8];
+        double v[1] = {e_own};
+        block_sum<1>(v, sh);
+        if (threadIdx.x == 0) epart[blk] = v[0];
+    }
+}
+
+template <int MODEL>
+void launch_model(shell_stencils_s& st, const double* x, void* f, double* epart, hipStream_t s) {
+    const int blk = 256;
+    long grid = xcd_grid(st.nblocks);
+    if (st.precision == SHELL_PREC_FP64) {
+        size_t lds = size_t(3 * st.T) * sizeof(double);
+        force_tiles<MODEL, double><<<grid, blk, lds, s>>>(x, st.boff.p, st.tidx.p, st.tB.p, st.tk0.p, st.ns_tiled,
+                                                          st.nv, st.T, st.nblocks, st.kb, st.poisson,
+                                                          static_cast<double*>(f), epart);
+    } else {
+        size_t lds = size_t(3 * st.T) * sizeof(float);
+        force_tiles<MODEL, float><<<grid, blk, lds, s>>>(x, st.boff.p, st.tidx.p, st.tBf.p, st.tk0f.p, st.ns_tiled,
+                                                         st.nv, st.T, st.nblocks, float(st.kb), float(st.poisson),
+                                                         static_cast<float*>(f), epart);
+    }
+    SHELL_HIP(hipGetLastError());
+}
+
+__global__ void energy_finalize(const double* __restrict__ part, long n, double* __restrict__ out) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (long i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    double v[1] = {acc};
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) *out = v[0];
+}
+
+__global__ void gather_rows(const double* __restrict__ src, const int32_t* __restrict__ perm,
+                            double* __restrict__ dst, long nv) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    long u = perm[i];
+    dst[3 * i] = src[3 * u];
+    dst[3 * i + 1] = src[3 * u + 1];
+    dst[3 * i + 2] = src[3 * u + 2];
+}
+
+template <typename T>
+__global__ void scatter_rows(const T* __restrict__ src, const int32_t* __restrict__ perm, T* __restrict__ dst,
+                             long nv) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    long u = perm[i];
+    dst[3 * u] = src[3 * i];
+    dst[3 * u + 1] = src[3 * i + 1];
+    dst[3 * u + 2] = src[3 * i + 2];
+}
+
+}  // namespace
+
+void launch_forces(shell_stencils_s& st, const double* x, void* f, double* epart, hipStream_t s) {
+    if (st.nv == 0) return;
+    switch (st.model) {
+        case SHELL_EP: launch_model<SHELL_EP>(st, x, f, epart, s); break;
+        case SHELL_ES: launch_model<SHELL_ES>(st, x, f, epart, s); break;
+        case SHELL_FP: launch_model<SHELL_FP>(st, x, f, epart, s); break;
+        case SHELL_FS: launch_model<SHELL_FS>(st, x, f, epart, s); break;
+        case SHELL_SP: launch_model<SHELL_SP>(st, x, f, epart, s); break;
+        case SHELL_SS: launch_model<SHELL_SS>(st, x, f, epart, s); break;
+        default: throw Error(SHELL_E_INVALID_ARG, "unknown model");
+    }
+}
+
+void launch_energy_finalize(const double* epart, int64_t n, double* energy, hipStream_t s) {
+    energy_finalize<<<1, 256, 0, s>>>(epart, n, energy);
+    SHELL_HIP(hipGetLastError());
+}
+
+void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s) {
+    if (!nv) return;
+    gather_rows<<<(nv + 255) / 256, 256, 0, s>>>(src, perm, dst, nv);
+    SHELL_HIP(hipGetLastError());
+}
+
+void launch_scatter_rows(const void* src, const int32_t* perm, void* dst, int64_t nv, bool f32, hipStream_t s) {
+    if (!nv) return;
+    if (f32)
+        scatter_rows<float><<<(nv + 255) / 256, 256, 0, s>>>(static_cast<const float*>(src), perm,
+                                                             static_cast<float*>(dst), nv);
+    else
+        scatter_rows<double><<<(nv + 255) / 256, 256, 0, s>>>(static_cast<const double*>(src), perm,
+                                                              static_cast<double*>(dst), nv);
+    SHELL_HIP(hipGetLastError());
+}
+
+}  // namespace shell

@@ -1,0 +1,154 @@
+// Constant bending Hessian K = K_s (x) I3 (eqs 21, 41, 53; the shell models reuse it), assembled once,
+// and its product inside the implicit step.
+//
+// K_s = sum over stencils of P^T G P with G = B^T D B (k x k): every stencil block of the paper's
+// Hessian is G (x) I3, so only the scalar K_s is stored.  Storage is SELL-64: slice s holds rows
+// 64s..64s+63 and entry q of row i sits at sptr[s] + 64 q + (i mod 64), so the 64 lanes of a wave read
+// 64 consecutive values and column ids per step (fully coalesced), one row per lane, no reduction.
+#include "devmath.hpp"
+#include "internal.hpp"
+
+namespace shell {
+
+namespace {
+
+// slot of column c in row i (columns sorted within the row's rowlen entries)
+__device__ __forceinline__ long find_slot(const int32_t* __restrict__ scol, const int64_t* __restrict__ sptr,
+                                          const int32_t* __restrict__ rowlen, long i, int c) {
+    long s0 = sptr[i >> 6] + (i & 63);
+    int lo = 0, hi = rowlen[i] - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (scol[s0 + 64L * mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return s0 + 64L * lo;
+}
+
+template <int K, int R>
+__global__ void assemble_stencils(const int32_t* __restrict__ idx, const double* __restrict__ B, long ns,
+                                  const int32_t* __restrict__ missing, double kb, double nu,
+                                  const int32_t* __restrict__ scol, const int64_t* __restrict__ sptr,
+                                  const int32_t* __restrict__ rowlen, double* __restrict__ val) {
+    long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (s >= ns) return;
+    int v[K];
+    double Bm[R][K];
+    for (int j = 0; j < K; ++j) v[j] = idx[j * ns + s];
+    for (int i = 0; i < R; ++i)
+        for (int j = 0; j < K; ++j) Bm[i][j] = B[(i * K + j) * ns + s];
+    int miss = missing ? missing[s] : 0;
+    // D B (the stiffness is already folded into B for edges; triangles carry D_b)
+    double DB[R][K];
+    if constexpr (R == 1) {
+        for (int j = 0; j < K; ++j) DB[0][j] = Bm[0][j];
+    } else {
+        double t = 0.5 * (1.0 - nu);
+        for (int j = 0; j < K; ++j) {
+            DB[0][j] = kb * (Bm[0][j] + nu * Bm[1][j]);
+            DB[1][j] = kb * (nu * Bm[0][j] + Bm[1][j]);
+            DB[2][j] = kb * t * Bm[2][j];
+        }
+    }
+    for (int j = 0; j < K; ++j) {
+        if (j >= 3 && (miss & (1 << (j - 3)))) continue;
+        for (int l = 0; l < K; ++l) {
+            if (l >= 3 && (miss & (1 << (l - 3)))) continue;
+            double g = 0.0;
+            for (int i = 0; i < R; ++i) g += Bm[i][j] * DB[i][l];
+            atomicAdd(val + find_slot(scol, sptr, rowlen, v[j], v[l]), g);
+        }
+    }
+}
+
+__global__ void fill_zero(double* __restrict__ p, long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void extract_diag(const double* __restrict__ val, const int64_t* __restrict__ dslot, long nv,
+                             double* __restrict__ kdiag) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < nv) kdiag[i] = dslot[i] >= 0 ? val[dslot[i]] : 0.0;
+}
+
+__global__ void to_float(const double* __restrict__ a, float* __restrict__ b, long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) b[i] = float(a[i]);
+}
+
+// q = diag(mass) p + dt2 K_s p over 3 columns (caller order handled by the host wrapper)
+__global__ void apply_sell(const int32_t* __restrict__ scol, const double* __restrict__ val,
+                           const int64_t* __restrict__ sptr, const int32_t* __restrict__ width, long nv,
+                           const double* __restrict__ mass, double dt2, const double* __restrict__ p,
+                           double* __restrict__ q) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    long s = i >> 6;
+    long slot = sptr[s] + (i & 63);
+    int w = width[s];
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int k = 0; k < w; ++k, slot += 64) {
+        int c = scol[slot];
+        double a = val[slot];
+        ax = fma(a, p[3L * c], ax);
+        ay = fma(a, p[3L * c + 1], ay);
+        az = fma(a, p[3L * c + 2], az);
+    }
+    double m = mass ? mass[i] : 0.0;
+    q[3 * i] = fma(m, p[3 * i], dt2 * ax);
+    q[3 * i + 1] = fma(m, p[3 * i + 1], dt2 * ay);
+    q[3 * i + 2] = fma(m, p[3 * i + 2], dt2 * az);
+}
+
+}  // namespace
+
+void launch_assemble(shell_hessian_s& h, hipStream_t s) {
+    shell_stencils_s& st = *h.st;
+    const long nslots = h.pat.nslots;
+    fill_zero<<<(nslots + 255) / 256, 256, 0, s>>>(h.val.p, nslots);
+    SHELL_HIP(hipGetLastError());
+    const long ns = st.ns;
+    DevArray<int32_t> md;
+    if (!model_is_edge(st.model) && ns) {
+        std::vector<int32_t> mask(size_t(ns), 0);
+        for (long q = 0; q < ns; ++q)
+            for (int L = 0; L < 3; ++L)
+                if (st.h_idx[size_t(6 * q + 3 + L)] < 0) mask[size_t(q)] |= 1 << L;
+        md.alloc(size_t(ns));
+        md.upload(mask.data(), size_t(ns), s);
+    }
+    if (ns) {
+        long grid = (ns + 255) / 256;
+        if (model_is_edge(st.model))
+            assemble_stencils<4, 1><<<grid, 256, 0, s>>>(st.idx.p, st.B.p, ns, nullptr, st.kb, st.poisson, h.scol.p,
+                                                         h.sptr.p, h.rowlen.p, h.val.p);
+        else
+            assemble_stencils<6, 3><<<grid, 256, 0, s>>>(st.idx.p, st.B.p, ns, md.p, st.kb, st.poisson, h.scol.p,
+                                                         h.sptr.p, h.rowlen.p, h.val.p);
+        SHELL_HIP(hipGetLastError());
+    }
+    DevArray<int64_t> dslot(static_cast<size_t>(st.nv));
+    dslot.upload(h.pat.dslot.data(), size_t(st.nv), s);
+    if (st.nv) {
+        extract_diag<<<(st.nv + 255) / 256, 256, 0, s>>>(h.val.p, dslot.p, st.nv, h.kdiag.p);
+        SHELL_HIP(hipGetLastError());
+    }
+    if (h.valf.p) {
+        to_float<<<(nslots + 255) / 256, 256, 0, s>>>(h.val.p, h.valf.p, nslots);
+        SHELL_HIP(hipGetLastError());
+    }
+    SHELL_HIP(hipStreamSynchronize(s));  // temporaries are released on return
+}
+
+void launch_apply(const shell_hessian_s& h, const double* mass, double dt2, const double* p, double* q,
+                  hipStream_t s) {
+    const long nv = h.pat.nv;
+    if (!nv) return;
+    apply_sell<<<(nv + 255) / 256, 256, 0, s>>>(h.scol.p, h.val.p, h.sptr.p, h.width.p, nv, mass, dt2, p, q);
+    SHELL_HIP(hipGetLastError());
+}
+
+}  // namespace shell

@@ -1,0 +1,242 @@
+// Host-side mesh processing: validation, stencil enumeration (edge hinge, Sec. 4.3; triangle-centred
+// stencil with flap i+3 across the edge opposite vertex i, Secs 4.4-4.5 and App. C), Morton vertex
+// order, vertex tiles for the force kernel and the SELL-64 pattern of the constant Hessian.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "internal.hpp"
+
+namespace shell {
+
+namespace {
+
+inline uint64_t dkey(int32_t from, int32_t to) { return (uint64_t(uint32_t(from)) << 32) | uint32_t(to); }
+
+template <typename F>
+void parallel_for(int64_t n, F&& fn) {
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 4096 || nt == 1) {
+        fn(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        int64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a < b) th.emplace_back([=, &fn] { fn(a, b); });
+    }
+    for (auto& t : th) t.join();
+}
+
+}  // namespace
+
+HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tris) {
+    HostTopology topo;
+    topo.model = model;
+    topo.k = model_k(model);
+    // directed half-edges keyed by (from, to), each carrying the vertex opposite it
+    std::vector<std::pair<uint64_t, int32_t>> he(size_t(3 * nt));
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t* v = tris + 3 * t;
+        for (int c = 0; c < 3; ++c)
+            SHELL_CHECK(v[c] >= 0 && v[c] < nv, SHELL_E_INVALID_ARG, "triangle vertex id out of range");
+        SHELL_CHECK(v[0] != v[1] && v[1] != v[2] && v[0] != v[2], SHELL_E_DEGENERATE,
+                    "triangle with a repeated vertex");
+        he[3 * t + 0] = {dkey(v[0], v[1]), v[2]};
+        he[3 * t + 1] = {dkey(v[1], v[2]), v[0]};
+        he[3 * t + 2] = {dkey(v[2], v[0]), v[1]};
+    }
+    std::sort(he.begin(), he.end());
+    auto find = [&](int32_t from, int32_t to) -> const std::pair<uint64_t, int32_t>* {
+        uint64_t k = dkey(from, to);
+        auto it = std::lower_bound(he.begin(), he.end(), std::make_pair(k, INT32_MIN));
+        return (it != he.end() && it->first == k) ? &*it : nullptr;
+    };
+    for (size_t i = 1; i < he.size(); ++i) {
+        if (he[i].first == he[i - 1].first) {
+            int32_t from = int32_t(he[i].first >> 32), to = int32_t(he[i].first & 0xffffffffu);
+            bool fan = find(to, from) != nullptr;
+            throw Error(fan ? SHELL_E_NONMANIFOLD : SHELL_E_ORIENTATION,
+                        fan ? "edge shared by more than two triangles" : "inconsistently oriented triangles");
+        }
+    }
+    if (model_is_edge(model)) {
+        // one stencil per interior edge; 2->3 is the half-edge with the smaller source id
+        for (const auto& h : he) {
+            int32_t from = int32_t(h.first >> 32), to = int32_t(h.first & 0xffffffffu);
+            if (from > to) continue;
+            const auto* twin = find(to, from);
+            if (!twin) continue;  // boundary edge: free, no stencil
+            topo.idx.insert(topo.idx.end(), {h.second, from, to, twin->second});
+        }
+        topo.ns = int64_t(topo.idx.size() / 4);
+    } else {
+        topo.ns = nt;
+        topo.idx.resize(size_t(6 * nt));
+        for (int64_t t = 0; t < nt; ++t) {
+            const int32_t* v = tris + 3 * t;
+            int32_t* s = topo.idx.data() + 6 * t;
+            s[0] = v[0];
+            s[1] = v[1];
+            s[2] = v[2];
+            for (int i = 0; i < 3; ++i) {
+                const auto* nb = find(v[(i + 2) % 3], v[(i + 1) % 3]);
+                s[3 + i] = nb ? nb->second : -1;
+            }
+        }
+    }
+    return topo;
+}
+
+std::vector<int32_t> vertex_order(const double* X, int64_t nv, bool reorder) {
+    std::vector<int32_t> perm(static_cast<size_t>(nv));
+    std::iota(perm.begin(), perm.end(), 0);
+    if (!reorder || nv < 2) return perm;
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) lo[c] = hi[c] = X[c];
+    for (int64_t i = 0; i < nv; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], X[3 * i + c]);
+            hi[c] = std::max(hi[c], X[3 * i + c]);
+        }
+    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+    auto spread = [](uint64_t v) {  // 21 bits -> every third bit
+        v &= 0x1fffff;
+        v = (v | v << 32) & 0x1f00000000ffffull;
+        v = (v | v << 16) & 0x1f0000ff0000ffull;
+        v = (v | v << 8) & 0x100f00f00f00f00full;
+        v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+        v = (v | v << 2) & 0x1249249249249249ull;
+        return v;
+    };
+    std::vector<uint64_t> code(static_cast<size_t>(nv));
+    for (int64_t i = 0; i < nv; ++i) {
+        uint64_t q[3];
+        for (int c = 0; c < 3; ++c) q[c] = uint64_t((X[3 * i + c] - lo[c]) / ext * 2097151.0);
+        code[i] = spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2;
+    }
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    return perm;
+}
+
+Tiling build_tiling(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv, int T) {
+    Tiling t;
+    t.T = T;
+    t.nblocks = std::max<int64_t>(1, (nv + T - 1) / T);
+    std::vector<int64_t> cnt(size_t(t.nblocks + 1), 0);
+    auto blocks_of = [&](int64_t s, int32_t* out) {
+        int n = 0;
+        for (int j = 0; j < k; ++j) {
+            int32_t v = idx[size_t(k * s + j)];
+            if (v < 0) continue;
+            int32_t b = v / T;
+            bool seen = false;
+            for (int q = 0; q < n; ++q) seen |= out[q] == b;
+            if (!seen) out[n++] = b;
+        }
+        return n;
+    };
+    int32_t bl[6];
+    for (int64_t s = 0; s < ns; ++s) {
+        int n = blocks_of(s, bl);
+        for (int q = 0; q < n; ++q) cnt[size_t(bl[q]) + 1]++;
+    }
+    for (int64_t b = 0; b < t.nblocks; ++b) cnt[b + 1] += cnt[b];
+    t.boff = cnt;
+    t.src.resize(size_t(cnt[t.nblocks]));
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t s = 0; s < ns; ++s) {
+        int n = blocks_of(s, bl);
+        for (int q = 0; q < n; ++q) t.src[size_t(fill[bl[q]]++)] = int32_t(s);
+    }
+    return t;
+}
+
+SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv) {
+    SellPattern P;
+    P.nv = nv;
+    // vertex -> incident stencils
+    std::vector<int64_t> vptr(size_t(nv + 1), 0);
+    for (int64_t s = 0; s < ns; ++s)
+        for (int j = 0; j < k; ++j)
+            if (idx[size_t(k * s + j)] >= 0) vptr[size_t(idx[size_t(k * s + j)]) + 1]++;
+    for (int64_t v = 0; v < nv; ++v) vptr[v + 1] += vptr[v];
+    std::vector<int32_t> vst(static_cast<size_t>(vptr[nv]));
+    {
+        std::vector<int64_t> fill(vptr.begin(), vptr.end() - 1);
+        for (int64_t s = 0; s < ns; ++s)
+            for (int j = 0; j < k; ++j) {
+                int32_t v = idx[size_t(k * s + j)];
+                if (v >= 0) vst[size_t(fill[v]++)] = int32_t(s);
+            }
+    }
+    // row patterns: the union of the incident stencils' vertices
+    std::vector<int32_t> len(size_t(nv), 0);
+    parallel_for(nv, [&](int64_t a, int64_t b) {
+        std::vector<int32_t> buf;
+        for (int64_t v = a; v < b; ++v) {
+            buf.clear();
+            for (int64_t e = vptr[v]; e < vptr[v + 1]; ++e)
+                for (int j = 0; j < k; ++j) {
+                    int32_t u = idx[size_t(k * vst[size_t(e)] + j)];
+                    if (u >= 0) buf.push_back(u);
+                }
+            std::sort(buf.begin(), buf.end());
+            len[size_t(v)] = int32_t(std::unique(buf.begin(), buf.end()) - buf.begin());
+        }
+    });
+    P.rowptr.assign(size_t(nv + 1), 0);
+    for (int64_t v = 0; v < nv; ++v) P.rowptr[v + 1] = P.rowptr[v] + len[size_t(v)];
+    P.nnz = P.rowptr[nv];
+    P.col.resize(size_t(P.nnz));
+    parallel_for(nv, [&](int64_t a, int64_t b) {
+        std::vector<int32_t> buf;
+        for (int64_t v = a; v < b; ++v) {
+            buf.clear();
+            for (int64_t e = vptr[v]; e < vptr[v + 1]; ++e)
+                for (int j = 0; j < k; ++j) {
+                    int32_t u = idx[size_t(k * vst[size_t(e)] + j)];
+                    if (u >= 0) buf.push_back(u);
+                }
+            std::sort(buf.begin(), buf.end());
+            buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+            std::copy(buf.begin(), buf.end(), P.col.begin() + P.rowptr[v]);
+        }
+    });
+    // SELL-64: slice s holds rows 64s..64s+63, entry q of row i at sptr[s] + 64 q + (i mod 64)
+    P.nslices = (nv + 63) / 64;
+    P.width.assign(size_t(P.nslices), 0);
+    P.sptr.assign(size_t(P.nslices + 1), 0);
+    P.rowlen = len;
+    for (int64_t s = 0; s < P.nslices; ++s) {
+        int w = 0;
+        for (int64_t i = 64 * s; i < std::min(nv, 64 * s + 64); ++i) w = std::max(w, len[size_t(i)]);
+        P.width[size_t(s)] = std::max(w, 1);
+        P.sptr[s + 1] = P.sptr[s] + 64 * int64_t(P.width[size_t(s)]);
+    }
+    P.nslots = P.sptr[P.nslices];
+    P.scol.assign(size_t(P.nslots), 0);
+    P.csr2sell.resize(size_t(P.nnz));
+    P.dslot.assign(size_t(nv), -1);
+    for (int64_t s = 0; s < P.nslices; ++s) {
+        for (int lane = 0; lane < 64; ++lane) {
+            int64_t i = 64 * s + lane;
+            int32_t last = i < nv ? int32_t(i) : 0;
+            for (int q = 0; q < P.width[size_t(s)]; ++q) {
+                int64_t slot = P.sptr[s] + 64 * q + lane;
+                if (i < nv && q < len[size_t(i)]) {
+                    int64_t e = P.rowptr[i] + q;
+                    last = P.col[size_t(e)];
+                    P.csr2sell[size_t(e)] = slot;
+                    if (last == i) P.dslot[size_t(i)] = slot;
+                }
+                P.scol[size_t(slot)] = last;  // padding repeats the last column with a zero value
+            }
+        }
+    }
+    return P;
+}
+
+}  // namespace shell

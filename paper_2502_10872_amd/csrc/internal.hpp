@@ -1,0 +1,194 @@
+// Internal declarations of the HIP library behind include/shell.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "shell.h"
+
+namespace shell {
+
+// ------------------------------------------------------------------ errors
+
+struct Error : std::runtime_error {
+    shell_status_t status;
+    Error(shell_status_t s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define SHELL_HIP(call)                                                                                       \
+    do {                                                                                                      \
+        hipError_t e_ = (call);                                                                               \
+        if (e_ != hipSuccess)                                                                                 \
+            throw ::shell::Error(e_ == hipErrorOutOfMemory ? SHELL_E_OOM : SHELL_E_HIP,                       \
+                                 std::string(#call) + ": " + hipGetErrorString(e_));                          \
+    } while (0)
+
+#define SHELL_CHECK(cond, status, msg)                                     \
+    do {                                                                   \
+        if (!(cond)) throw ::shell::Error((status), (msg));                \
+    } while (0)
+
+// ------------------------------------------------------------------ device buffers
+
+template <typename T>
+struct DevArray {
+    T* p = nullptr;
+    size_t n = 0;
+    DevArray() = default;
+    explicit DevArray(size_t count) { alloc(count); }
+    DevArray(const DevArray&) = delete;
+    DevArray& operator=(const DevArray&) = delete;
+    ~DevArray() { release(); }
+    void alloc(size_t count) {
+        release();
+        n = count;
+        if (count) SHELL_HIP(hipMalloc(&p, count * sizeof(T)));
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    void upload(const T* h, size_t count, hipStream_t s) {
+        if (count) SHELL_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    }
+    void download(T* h, size_t count, hipStream_t s) const {
+        if (count) SHELL_HIP(hipMemcpyAsync(h, p, count * sizeof(T), hipMemcpyDeviceToHost, s));
+    }
+    size_t bytes() const { return n * sizeof(T); }
+};
+
+// ------------------------------------------------------------------ model traits
+
+inline bool model_is_edge(int m) { return m == SHELL_EP || m == SHELL_ES; }
+inline bool model_is_shell(int m) { return m == SHELL_ES || m == SHELL_FS || m == SHELL_SS; }
+inline bool model_is_fvm(int m) { return m == SHELL_FP || m == SHELL_FS; }
+inline int model_k(int m) { return model_is_edge(m) ? 4 : 6; }
+inline int model_r(int m) { return model_is_edge(m) ? 1 : 3; }
+
+// ------------------------------------------------------------------ host mesh processing (host_mesh.cpp)
+
+struct HostTopology {
+    int model = 0, k = 4;
+    int64_t ns = 0;
+    std::vector<int32_t> idx;  // [ns][k] caller ids, -1 = missing flap
+};
+// Validates the triangle mesh and enumerates the model's stencils.
+HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tris);
+
+// Vertex order: perm[internal] = caller id.  Morton order of the rest positions when reorder != 0.
+std::vector<int32_t> vertex_order(const double* X, int64_t nv, bool reorder);
+
+struct Tiling {
+    int T = 1024;                 // vertices per tile
+    int64_t nblocks = 0;
+    std::vector<int64_t> boff;    // [nblocks+1] offsets into the tiled stencil list
+    std::vector<int32_t> src;     // [ns_tiled] unique stencil of each tiled copy
+};
+// Groups stencils (internal vertex ids) by the vertex tiles they touch; halo stencils repeat.
+Tiling build_tiling(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv, int T);
+
+struct SellPattern {
+    int64_t nv = 0, nslices = 0, nnz = 0, nslots = 0;
+    std::vector<int64_t> rowptr;  // CSR of the pattern (internal order), sorted columns
+    std::vector<int32_t> col;
+    std::vector<int32_t> width;   // [nslices]
+    std::vector<int64_t> sptr;    // [nslices+1] slot offset of each 64-row slice
+    std::vector<int32_t> rowlen;  // [nv]
+    std::vector<int32_t> scol;    // [nslots] SELL-64 column ids (padded with the row's last column)
+    std::vector<int64_t> csr2sell;  // [nnz] slot of each CSR entry
+    std::vector<int64_t> dslot;   // [nv] slot of the diagonal entry (or -1)
+};
+SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv);
+
+// ------------------------------------------------------------------ handles
+
+}  // namespace shell
+
+struct shell_stencils_s {
+    int model = 0, k = 4, r = 1, precision = 0;
+    int64_t nv = 0, nt = 0, ns = 0, ns_tiled = 0, nblocks = 0;
+    int T = 1024;
+    bool reordered = false;
+    double young = 0, poisson = 0, thickness = 0, density = 0, kb = 0;
+    std::vector<int32_t> perm, iperm;    // internal -> caller, caller -> internal
+    std::vector<int32_t> h_idx;          // [ns][k] internal ids, -1 = missing
+    std::vector<int32_t> h_tris;         // [nt][3] internal ids
+    std::vector<int64_t> h_boff;
+    // device, internal order
+    shell::DevArray<double> X;           // [nv][3]
+    shell::DevArray<int32_t> tris;       // [nt][3]
+    shell::DevArray<int32_t> perm_d;     // [nv]
+    shell::DevArray<int32_t> idx;        // SoA [k][ns], a missing flap points at vertex 1
+    shell::DevArray<double> B;           // SoA [r*k][ns], scaled by sqrt(stiffness)
+    shell::DevArray<double> k0;          // SoA [r][ns]
+    shell::DevArray<int32_t> flags;      // [ns]
+    shell::DevArray<int64_t> boff;       // [nblocks+1]
+    shell::DevArray<int32_t> tsrc;       // [ns_tiled]
+    shell::DevArray<int32_t> tidx;       // SoA [k][ns_tiled]
+    shell::DevArray<double> tB;          // SoA [r*k][ns_tiled]
+    shell::DevArray<double> tk0;         // SoA [r][ns_tiled]
+    shell::DevArray<float> tBf;          // mixed-precision copies
+    shell::DevArray<float> tk0f;
+    // scratch for the caller-order entry point
+    shell::DevArray<double> xin;         // [nv][3]
+    shell::DevArray<double> fout;        // [nv][3] (float for mixed, sized in doubles)
+    shell::DevArray<double> epart;       // [nblocks] energy partials
+};
+
+struct shell_hessian_s {
+    shell_stencils_s* st = nullptr;
+    shell::SellPattern pat;
+    shell::DevArray<int32_t> scol;       // [nslots]
+    shell::DevArray<int32_t> width;      // [nslices]
+    shell::DevArray<int64_t> sptr;       // [nslices+1]
+    shell::DevArray<int32_t> rowlen;     // [nv]
+    shell::DevArray<double> val;         // [nslots]
+    shell::DevArray<float> valf;         // [nslots] mixed copy
+    shell::DevArray<double> kdiag;       // [nv]
+    shell::DevArray<double> pin, qout;   // caller-order scratch for hessian_apply
+};
+
+struct PcgState;  // device-side solver scalars (solver.hip)
+
+struct shell_sim_s {
+    shell_stencils_s* st = nullptr;
+    shell_hessian_s* h = nullptr;
+    int64_t nv = 0;
+    int64_t step = 0;
+    double dinv_dt = -1.0;               // dt the preconditioner was built for
+    hipStream_t last_stream = nullptr;
+    shell::DevArray<double> x, v, xt, xhat, g, mass, y, r;
+    shell::DevArray<double> f;           // float64 forces (or float32 in mixed, sized in doubles)
+    shell::DevArray<double> dinv;        // [nv] (float in mixed)
+    shell::DevArray<uint8_t> pinned;
+    shell::DevArray<double> z, p, q;     // PCG work vectors (float in mixed; sized in doubles)
+    shell::DevArray<double> partials;    // reduction partials
+    shell::DevArray<unsigned char> state;  // PcgState
+    unsigned char* state_host = nullptr;   // pinned host mirror
+    shell_step_stats_t stats{};
+};
+
+namespace shell {
+// precompute.hip
+void launch_precompute(shell_stencils_s& st, hipStream_t s);
+void launch_tile_copy(shell_stencils_s& st, hipStream_t s);
+// forces.hip
+void launch_forces(shell_stencils_s& st, const double* x, void* f, double* epart, hipStream_t s);
+void launch_energy_finalize(const double* epart, int64_t n, double* energy, hipStream_t s);
+void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
+void launch_scatter_rows(const void* src, const int32_t* perm, void* dst, int64_t nv, bool f32, hipStream_t s);
+// hessian.hip
+void launch_assemble(shell_hessian_s& h, hipStream_t s);
+void launch_apply(const shell_hessian_s& h, const double* mass, double dt2, const double* p, double* q,
+                  hipStream_t s);
+// solver.hip
+void sim_alloc(shell_sim_s& sim);
+void sim_mass(shell_sim_s& sim, hipStream_t s);
+shell_status_t sim_step(shell_sim_s& sim, const shell_step_params_t& p, hipStream_t s);
+void sim_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out, hipStream_t s);
+}  // namespace shell

@@ -1,0 +1,261 @@
+// Rest precomputation, one thread per stencil, float64 (done once per mesh).
+//
+// Edge hinge (Sec. 4.3): rest normal on the bisector of the two triangle normals, stencil projected
+// onto its tangent plane (the corotational stencil), signed feet ratios and heights of vertices 1
+// and 4 over the hinge 2->3, L_m = 2 L_theta/(h1 + h4) (eqs 7, 9-10), rest curvature
+// kappa0 = L_m N0^T X (eq 14).  Scaled by sqrt(k_b A_E), A_E the two rest triangle areas (eq 16).
+//
+// Triangle stencil (Secs 4.4-4.5, App. A/C): rest frame at X1 with x along X12 and z the triangle
+// normal (eq 65); the six points in that plane; a missing flap replaced by the reflection of its
+// tip through the boundary edge's midpoint; L_p = H L_theta row by row (eqs 76-78); FVM: R from the
+// in-plane edge normals (eq 38), B = R L_p; smoothed: C_p = [X^2/2, Y^2/2, XY/2] per point (eq 49),
+// B = (L_p C_p)^-1 L_p (eq 50); free fold w_L' = w_M + w_N - w_L on B's columns (eqs 60-61); FVM
+// free edge: twist dropped in the edge's frame; kappa0 = B N0^T X (eqs 43, 51).  Scaled by sqrt(A).
+#include "devmath.hpp"
+#include "internal.hpp"
+
+namespace shell {
+
+namespace {
+
+constexpr int kFlagDegenerate = 1;
+
+__global__ void precompute_edge(const double* __restrict__ X, const int32_t* __restrict__ idx, long ns,
+                                double kb, int shell_model, double* __restrict__ B, double* __restrict__ k0,
+                                int32_t* __restrict__ flags) {
+    long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (s >= ns) return;
+    V3<double> x1 = load3(X, idx[s]), x2 = load3(X, idx[ns + s]), x3 = load3(X, idx[2 * ns + s]),
+               x4 = load3(X, idx[3 * ns + s]);
+    V3<double> a = x1 - x2, e = x3 - x2, b = x4 - x2;
+    V3<double> ua = cross(e, a);  // (x2-x1) x (x3-x1)
+    V3<double> ub = cross(b, e);  // (x3-x4) x (x2-x4)
+    double la = norm(ua), lb = norm(ub);
+    int flag = 0;
+    if (!(la > 0.0) || !(lb > 0.0)) flag = kFlagDegenerate;
+    V3<double> m = (1.0 / la) * ua + (1.0 / lb) * ub;
+    double lm = norm(m);
+    if (!(lm > 1e-12)) flag = kFlagDegenerate;
+    V3<double> n0 = (1.0 / lm) * m;
+    // projection onto the tangent plane through x2
+    V3<double> ac = a - dot(n0, a) * n0, ec = e - dot(n0, e) * n0, bc = b - dot(n0, b) * n0;
+    double ee = dot(ec, ec);
+    double sp = dot(ac, ec) / ee, sq = dot(bc, ec) / ee;
+    double h1 = norm(ac - sp * ec), h4 = norm(bc - sq * ec);
+    double elen = sqrt(ee);
+    if (!(h1 > 1e-12 * elen) || !(h4 > 1e-12 * elen)) flag = kFlagDegenerate;
+    double c = 2.0 / (h1 + h4);
+    double scale = sqrt(kb * 0.5 * (la + lb));
+    double L1 = scale * c / h1;
+    double L2 = -scale * c * ((1.0 - sp) / h1 + (1.0 - sq) / h4);
+    double L3 = -scale * c * (sp / h1 + sq / h4);
+    double L4 = scale * c / h4;
+    B[s] = L1;
+    B[ns + s] = L2;
+    B[2 * ns + s] = L3;
+    B[3 * ns + s] = L4;
+    // rows sum to zero, so the rest curvature can be taken on differences from x2
+    k0[s] = shell_model ? L1 * dot(n0, a) + L3 * dot(n0, e) + L4 * dot(n0, b) : 0.0;
+    flags[s] = flag;
+}
+
+__device__ inline double inv3x3(const double (&M)[3][3], double (&Mi)[3][3]) {
+    double c00 = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    double c01 = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    double c02 = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    double det = M[0][0] * c00 + M[0][1] * c01 + M[0][2] * c02;
+    double id = 1.0 / det;
+    Mi[0][0] = c00 * id;
+    Mi[1][0] = c01 * id;
+    Mi[2][0] = c02 * id;
+    Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) * id;
+    Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) * id;
+    Mi[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) * id;
+    Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) * id;
+    Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) * id;
+    Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) * id;
+    double n1 = 0.0, n2 = 0.0;  // 1-norm condition number
+    for (int j = 0; j < 3; ++j) {
+        n1 = fmax(n1, fabs(M[0][j]) + fabs(M[1][j]) + fabs(M[2][j]));
+        n2 = fmax(n2, fabs(Mi[0][j]) + fabs(Mi[1][j]) + fabs(Mi[2][j]));
+    }
+    return (det != 0.0 && isfinite(det)) ? n1 * n2 : INFINITY;
+}
+
+__global__ void precompute_tri(const double* __restrict__ X, const int32_t* __restrict__ idx, long ns, int fvm,
+                               int shell_model, double* __restrict__ B, double* __restrict__ k0,
+                               int32_t* __restrict__ flags, const int32_t* __restrict__ missing_mask) {
+    long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (s >= ns) return;
+    int miss = missing_mask[s];  // bit L set: flap L+3 absent (its idx points at vertex 1)
+    V3<double> x1 = load3(X, idx[s]);
+    V3<double> d[6];
+    d[0] = mk(0.0, 0.0, 0.0);
+    for (int j = 1; j < 6; ++j) d[j] = load3(X, idx[j * ns + s]) - x1;
+    V3<double> u = cross(d[1], d[2]);
+    double twoA = norm(u);
+    int flag = twoA > 0.0 ? 0 : kFlagDegenerate;
+    V3<double> ez = (1.0 / twoA) * u;
+    V3<double> ex = (1.0 / norm(d[1])) * d[1];
+    V3<double> ey = cross(ez, ex);
+    double px[6], py[6];
+    for (int j = 0; j < 6; ++j) {
+        px[j] = dot(d[j], ex);
+        py[j] = dot(d[j], ey);
+    }
+    for (int L = 0; L < 3; ++L) {
+        if (miss & (1 << L)) {
+            int M = (L + 1) % 3, N = (L + 2) % 3;
+            px[L + 3] = px[M] + px[N] - px[L];
+            py[L + 3] = py[M] + py[N] - py[L];
+        }
+    }
+    // directional hinge operator across each edge of the central triangle
+    double Lp[3][6];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 6; ++j) Lp[i][j] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        int a = (i + 1) % 3, b = (i + 2) % 3, f = i + 3;
+        double ex2 = px[b] - px[a], ey2 = py[b] - py[a];
+        double ee = ex2 * ex2 + ey2 * ey2;
+        double tx = px[i] - px[a], ty = py[i] - py[a];
+        double fx = px[f] - px[a], fy = py[f] - py[a];
+        double st = (tx * ex2 + ty * ey2) / ee, sf = (fx * ex2 + fy * ey2) / ee;
+        double ht = hypot(tx - st * ex2, ty - st * ey2), hf = hypot(fx - sf * ex2, fy - sf * ey2);
+        double el = sqrt(ee);
+        if (!(ht > 1e-12 * el) || !(hf > 1e-12 * el)) flag = kFlagDegenerate;
+        double c = 2.0 / (ht + hf);
+        Lp[i][i] = c / ht;
+        Lp[i][a] = -c * ((1.0 - st) / ht + (1.0 - sf) / hf);
+        Lp[i][b] = -c * (st / ht + sf / hf);
+        Lp[i][f] = c / hf;
+    }
+    double Bm[3][6];
+    if (fvm) {
+        double R[3][3];
+        for (int i = 0; i < 3; ++i) {
+            int a = (i + 1) % 3, b = (i + 2) % 3;
+            double ex2 = px[b] - px[a], ey2 = py[b] - py[a];
+            double il = 1.0 / hypot(ex2, ey2);
+            double ms = ey2 * il, mt = -ex2 * il;  // in-plane unit normal of edge i
+            R[0][i] = ms * ms;
+            R[1][i] = mt * mt;
+            R[2][i] = 2.0 * ms * mt;
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < 6; ++j) Bm[r][j] = R[r][0] * Lp[0][j] + R[r][1] * Lp[1][j] + R[r][2] * Lp[2][j];
+    } else {
+        double M[3][3], Mi[3][3];
+        for (int r = 0; r < 3; ++r) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+            for (int j = 0; j < 6; ++j) {
+                a0 += Lp[r][j] * (0.5 * px[j] * px[j]);
+                a1 += Lp[r][j] * (0.5 * py[j] * py[j]);
+                a2 += Lp[r][j] * (0.5 * px[j] * py[j]);
+            }
+            M[r][0] = a0;
+            M[r][1] = a1;
+            M[r][2] = a2;
+        }
+        double cond = inv3x3(M, Mi);
+        if (!(cond < 1e12)) flag = kFlagDegenerate;
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < 6; ++j) Bm[r][j] = Mi[r][0] * Lp[0][j] + Mi[r][1] * Lp[1][j] + Mi[r][2] * Lp[2][j];
+    }
+    int first_free = -1;
+    for (int L = 0; L < 3; ++L) {
+        if (!(miss & (1 << L))) continue;
+        if (first_free < 0) first_free = L;
+        int M = (L + 1) % 3, N = (L + 2) % 3, F = L + 3;
+        for (int r = 0; r < 3; ++r) {
+            double w = Bm[r][F];
+            Bm[r][M] += w;
+            Bm[r][N] += w;
+            Bm[r][L] -= w;
+            Bm[r][F] = 0.0;
+        }
+    }
+    if (fvm && first_free >= 0) {
+        // keep only the curvature components normal and along the free edge: P = T(-phi) diag(1,1,0) T(phi)
+        int M = (first_free + 1) % 3, N = (first_free + 2) % 3;
+        double ex2 = px[N] - px[M], ey2 = py[N] - py[M];
+        double il = 1.0 / hypot(ex2, ey2);
+        double c = ex2 * il, sn = ey2 * il;
+        double T0[3] = {c * c, sn * sn, c * sn}, T1[3] = {sn * sn, c * c, -c * sn};   // rows of T(phi)
+        double Ic0[3] = {c * c, sn * sn, 2.0 * c * sn}, Ic1[3] = {sn * sn, c * c, -2.0 * c * sn};  // cols of T(-phi)
+        double Bn[3][6];
+        for (int j = 0; j < 6; ++j) {
+            double r0 = T0[0] * Bm[0][j] + T0[1] * Bm[1][j] + T0[2] * Bm[2][j];
+            double r1 = T1[0] * Bm[0][j] + T1[1] * Bm[1][j] + T1[2] * Bm[2][j];
+            for (int r = 0; r < 3; ++r) Bn[r][j] = Ic0[r] * r0 + Ic1[r] * r1;
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int j = 0; j < 6; ++j) Bm[r][j] = Bn[r][j];
+    }
+    double sc = sqrt(0.5 * twoA);
+    for (int r = 0; r < 3; ++r) {
+        double kr = 0.0;
+        for (int j = 0; j < 6; ++j) {
+            B[(r * 6 + j) * ns + s] = sc * Bm[r][j];
+            kr += Bm[r][j] * dot(ez, d[j]);
+        }
+        k0[r * ns + s] = shell_model ? sc * kr : 0.0;
+    }
+    flags[s] = flag;
+}
+
+__global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_t* __restrict__ idx,
+                          const double* __restrict__ B, const double* __restrict__ k0, long ns, int k, int r,
+                          int32_t* __restrict__ tidx, double* __restrict__ tB, double* __restrict__ tk0,
+                          float* __restrict__ tBf, float* __restrict__ tk0f) {
+    long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (e >= nt) return;
+    long s = src[e];
+    for (int j = 0; j < k; ++j) tidx[j * nt + e] = idx[j * ns + s];
+    for (int q = 0; q < r * k; ++q) {
+        double v = B[q * ns + s];
+        tB[q * nt + e] = v;
+        if (tBf) tBf[q * nt + e] = float(v);
+    }
+    for (int q = 0; q < r; ++q) {
+        double v = k0[q * ns + s];
+        tk0[q * nt + e] = v;
+        if (tk0f) tk0f[q * nt + e] = float(v);
+    }
+}
+
+}  // namespace
+
+void launch_precompute(shell_stencils_s& st, hipStream_t s) {
+    const long ns = st.ns;
+    if (ns == 0) return;
+    int blk = 256;
+    long grid = (ns + blk - 1) / blk;
+    if (model_is_edge(st.model)) {
+        precompute_edge<<<grid, blk, 0, s>>>(st.X.p, st.idx.p, ns, st.kb, model_is_shell(st.model), st.B.p, st.k0.p,
+                                             st.flags.p);
+    } else {
+        std::vector<int32_t> mask(size_t(ns), 0);
+        for (long q = 0; q < ns; ++q)
+            for (int L = 0; L < 3; ++L)
+                if (st.h_idx[size_t(6 * q + 3 + L)] < 0) mask[size_t(q)] |= 1 << L;
+        DevArray<int32_t> md(static_cast<size_t>(ns));
+        md.upload(mask.data(), size_t(ns), s);
+        precompute_tri<<<grid, blk, 0, s>>>(st.X.p, st.idx.p, ns, model_is_fvm(st.model), model_is_shell(st.model),
+                                            st.B.p, st.k0.p, st.flags.p, md.p);
+        SHELL_HIP(hipGetLastError());
+        SHELL_HIP(hipStreamSynchronize(s));  // md is released on return
+    }
+    SHELL_HIP(hipGetLastError());
+}
+
+void launch_tile_copy(shell_stencils_s& st, hipStream_t s) {
+    const long nt = st.ns_tiled;
+    if (nt == 0) return;
+    int blk = 256;
+    tile_copy<<<(nt + blk - 1) / blk, blk, 0, s>>>(st.tsrc.p, nt, st.idx.p, st.B.p, st.k0.p, st.ns, st.k, st.r,
+                                                   st.tidx.p, st.tB.p, st.tk0.p, st.tBf.p, st.tk0f.p);
+    SHELL_HIP(hipGetLastError());
+}
+
+}  // namespace shell
