@@ -40,6 +40,29 @@ def algorithmic_bytes(info: dict, nnz: int, precision: int) -> dict:
     return dict(force=force, spmv=spmv, force_per_stencil=per_stencil)
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_cap_1024_ss_fp64_hbm_traffic.md")
+TRAFFIC_SOURCES = ["paper_2502_10872_amd/csrc/spmv.hpp", "paper_2502_10872_amd/csrc/solver.hip",
+                   "paper_2502_10872_amd/csrc/forces.hip", "paper_2502_10872_amd/csrc/host_mesh.cpp"]
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch from the committed counter summary, or None when the kernels' sources have
+    changed since the counters were taken (or the summary is absent)."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith("|"))
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if fields.get("sources_sha256", "").strip() != h.hexdigest()[:16] or key not in fields:
+        return None
+    return float(fields[key])
+
+
 def cpu_baseline(mesh, material, counts_per_step, newton_per_step, budget_s=30.0):
     """The FP64 CPU oracle on the same mesh: one force evaluation and a short replayed PCG run are
     timed, then scaled to the GPU step's measured Newton and PCG iteration counts."""
@@ -82,6 +105,9 @@ def main(argv=None):
     ap.add_argument("--pcg-rtol", type=float, default=1e-2)
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel for the per-kernel timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-pcg", type=int, default=400000, help="PCG iteration cap per coordinate solve")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-device by design",
@@ -105,7 +131,7 @@ def main(argv=None):
     setup_s = time.perf_counter() - t0
     rp_nnz = _nnz(S, pb.h)
     dt = 1.0 / 30.0
-    params, _ = S.step_params(dt, gravity=I.GRAVITY, max_newton=args.max_newton, max_pcg=400000,
+    params, _ = S.step_params(dt, gravity=I.GRAVITY, max_newton=args.max_newton, max_pcg=args.max_pcg,
                               newton_rtol=1e-8, pcg_rtol=args.pcg_rtol)
     for w in range(args.warmup):
         rc, st = S.shell_step_implicit(pb.sim, params)
@@ -130,10 +156,20 @@ def main(argv=None):
     steps_per_s = args.steps / elapsed
 
     kt = S.shell_sim_time_kernels(pb.sim, dt, reps=args.reps, stream=stream)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     ab = algorithmic_bytes(pb.info, rp_nnz, precision)
     spmv_gbs = ab["spmv"] / (kt["spmv_ms"] * 1e-3) / 1e9
     force_gbs = ab["force"] / (kt["force_ms"] * 1e-3) / 1e9
     stencils_per_s = pb.info["ns"] / (kt["force_ms"] * 1e-3)
+    default_workload = args.size == 1024 and precision == S.SHELL_PREC_FP64
+    traffic_spmv = measured_traffic("spmv_traffic_bytes_per_launch") if default_workload else None
+    traffic_force = measured_traffic("force_traffic_bytes_per_launch") if default_workload else None
     pcg_per_step = float(np.mean([s["pcg_total"] for s in stats]))
     newton_per_step = float(np.mean([s["newton_iters"] for s in stats]))
 
@@ -148,15 +184,17 @@ def main(argv=None):
                     nv=mesh.nv, stencils=pb.info["ns"], nnz=rp_nnz, precision=args.precision,
                     parallelism="single GPU"),
         roofline=dict(bound="hbm", kernel="pcg_spmv (3-column SELL-64 product)", achieved=spmv_gbs,
-                      peak=HBM_PEAK_GBS, unit="GB/s", frac=spmv_gbs / HBM_PEAK_GBS, traffic=None,
+                      peak=HBM_PEAK_GBS, unit="GB/s", frac=spmv_gbs / HBM_PEAK_GBS, traffic=traffic_spmv,
                       bytes_per_launch=ab["spmv"], avg_ms=kt["spmv_ms"]),
         force_kernel=dict(stencils_per_s=stencils_per_s, achieved_gbs=force_gbs, frac=force_gbs / HBM_PEAK_GBS,
                           bytes_per_launch=ab["force"], bytes_per_stencil_stream=ab["force_per_stencil"],
-                          avg_ms=kt["force_ms"]),
+                          avg_ms=kt["force_ms"], traffic=traffic_force),
         pcg_kernels_ms=dict(spmv=kt["spmv_ms"], update=kt["update_ms"], direction=kt["direction_ms"]),
         per_step=dict(newton_iters=newton_per_step, pcg_coord_iters=pcg_per_step,
                       grad_ratio=[s["grad_norm"] / max(s["grad_norm0"], 1e-300) for s in stats]),
         setup_s=setup_s,
+        tiles=dict(block_vertices=pb.info["block_vertices"], nblocks=pb.info["nblocks"],
+                   halo_factor=pb.info["ns_tiled"] / max(pb.info["ns"], 1)),
     )
     if not args.no_cpu_baseline and args.size == 1024:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)

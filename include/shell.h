@@ -66,8 +66,9 @@ typedef struct {
 
 typedef struct {
     int32_t precision;       /* shell_precision_t */
-    int32_t block_vertices;  /* vertices per force work-group tile; 0 selects the default (1024) */
-    int32_t reorder;         /* 1: Morton vertex order inside the library (default), 0: keep the caller's */
+    int32_t block_vertices;  /* vertices per force work-group tile, 64..4096; 0 selects the default (2048) */
+    int32_t reorder;         /* internal vertex order: 1 (default) recursive coordinate bisection into compact
+                                tiles of block_vertices, 2 Morton order, 0 the caller's order */
     int32_t reserved;
 } shell_config_t;
 

@@ -32,14 +32,15 @@ def hipcc() -> str:
     return os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, defines=(), lib: str = LIB, obj: str = OBJ) -> str:
+    """Compile and link; `defines` are extra -D tunables (kernel batch sizes), `lib` the output path."""
+    os.makedirs(obj, exist_ok=True)
     procs = []
     objs = []
     for src in SOURCES:
-        obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-        objs.append(obj)
-        cmd = [hipcc(), *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        o = os.path.join(obj, os.path.splitext(src)[0] + ".o")
+        objs.append(o)
+        cmd = [hipcc(), *CFLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -56,10 +57,10 @@ def build(verbose: bool = False) -> str:
             print("\n".join(lines))
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     subprocess.run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

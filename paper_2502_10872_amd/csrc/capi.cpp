@@ -78,9 +78,10 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         int precision = cfg ? cfg->precision : SHELL_PREC_FP64;
         SHELL_CHECK(precision == SHELL_PREC_FP64 || precision == SHELL_PREC_MIXED, SHELL_E_INVALID_ARG,
                     "unknown precision");
-        int T = (cfg && cfg->block_vertices > 0) ? cfg->block_vertices : 1024;
+        int T = (cfg && cfg->block_vertices > 0) ? cfg->block_vertices : 2048;
         SHELL_CHECK(T >= 64 && T <= 4096, SHELL_E_INVALID_ARG, "block_vertices must be in [64, 4096]");
-        bool reorder = cfg ? cfg->reorder != 0 : true;
+        int reorder = cfg ? cfg->reorder : 1;
+        SHELL_CHECK(reorder >= 0 && reorder <= 2, SHELL_E_INVALID_ARG, "unknown vertex order");
         hipStream_t s = as_stream(stream);
 
         auto st = std::make_unique<shell_stencils_s>();
@@ -100,8 +101,8 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         HostTopology topo = build_topology(model, nv, nt, tris);
         const int k = st->k, r = st->r;
         st->ns = topo.ns;
-        st->perm = vertex_order(X, nv, reorder);
-        st->reordered = reorder;
+        st->perm = vertex_order(X, nv, reorder, T);
+        st->reordered = reorder != 0;
         st->iperm.assign(size_t(nv), 0);
         for (int64_t i = 0; i < nv; ++i) st->iperm[size_t(st->perm[size_t(i)])] = int32_t(i);
         // stencils in internal ids, sorted by their first vertex for locality

@@ -1,11 +1,13 @@
 // Per-stencil bending forces, the per-timestep hot kernel.
 //
-// Layout: vertices are numbered in tiles of T consecutive (Morton-ordered) ids.  One work-group owns
-// one tile and walks the list of every stencil that touches the tile (stencils on a tile boundary
-// appear in each tile they touch).  Each stencil's force on the tile's own vertices is added into an
-// LDS accumulator; contributions to other tiles' vertices are left to those tiles.  The tile is
-// then written to HBM once: no global atomics, no zero-fill, one coalesced store per vertex.
-// Stencil data is streamed structure-of-arrays so every load is coalesced.
+// Layout: vertices are numbered in tiles of T consecutive ids (compact surface patches).  One
+// work-group owns one tile and walks the list of every stencil that touches the tile (stencils on a
+// tile boundary appear in each tile they touch).  Each stencil's force on the tile's own vertices is
+// added into a float64 LDS accumulator; contributions to other tiles' vertices are left to those
+// tiles.  The tile is then written to HBM once: no global atomics, no zero-fill, one coalesced store
+// per vertex.  Stencil data is streamed structure-of-arrays so every load is coalesced; a tile's list
+// stays in spatial order so the gathers of one wave touch few cache lines.  (float32 LDS atomics
+// contended badly on shared vertices; the float64 accumulator does not.)
 //
 // Per stencil (operator B already scaled by the square root of its stiffness):
 //   C_i = sum_j B_ij (x_j - x_o)            curvature vectors, x_o the stencil origin (rows of B
@@ -111,11 +113,12 @@ __device__ __forceinline__ void tri_stencil(const V3<double> (&xg)[6], const R (
     }
 }
 
+// tile accumulator in float64 for both precisions (ds_add_f64)
 template <typename R>
-__device__ __forceinline__ void lds_add(R* acc, int slot, V3<R> v) {
-    atomicAdd(acc + 3 * slot + 0, v.x);
-    atomicAdd(acc + 3 * slot + 1, v.y);
-    atomicAdd(acc + 3 * slot + 2, v.z);
+__device__ __forceinline__ void lds_add(double* acc, int slot, V3<R> v) {
+    atomicAdd(acc + 3 * slot + 0, double(v.x));
+    atomicAdd(acc + 3 * slot + 1, double(v.y));
+    atomicAdd(acc + 3 * slot + 2, double(v.z));
 }
 
 // One work-group per vertex tile.  K = 4 (edge) or 6 (triangle) vertices per stencil.
@@ -129,12 +132,12 @@ __global__ __launch_bounds__(256) void force_tiles(const double* __restrict__ x,
     constexpr bool SHELL = (MODEL == SHELL_ES || MODEL == SHELL_FS || MODEL == SHELL_SS);
     constexpr int K = EDGE ? 4 : 6;
     extern __shared__ unsigned char smem_raw[];
-    R* acc = reinterpret_cast<R*>(smem_raw);
+    double* acc = reinterpret_cast<double*>(smem_raw);
     long blk = xcd_logical(blockIdx.x, gridDim.x);
     if (blk >= nblocks) return;
     const long base = blk * long(T);
     const int nown = int(min(long(T), nv - base));
-    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) acc[i] = R(0);
+    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
     double e_own = 0.0;
     const long e0 = boff[blk], e1 = boff[blk + 1];
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(256) void force_tiles(const double* __restrict__ x,
     }
     __syncthreads();
     R* out = f + 3 * base;
-    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = acc[i];
+    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
     if (epart) {
         __shared__ double sh[8];
         double v[1] = {e_own};
@@ -193,7 +196,7 @@ void launch_model(shell_stencils_s& st, const double* x, void* f, double* epart,
                                                           st.nv, st.T, st.nblocks, st.kb, st.poisson,
                                                           static_cast<double*>(f), epart);
     } else {
-        size_t lds = size_t(3 * st.T) * sizeof(float);
+        size_t lds = size_t(3 * st.T) * sizeof(double);
         force_tiles<MODEL, float><<<grid, blk, lds, s>>>(x, st.boff.p, st.tidx.p, st.tBf.p, st.tk0f.p, st.ns_tiled,
                                                          st.nv, st.T, st.nblocks, float(st.kb), float(st.poisson),
                                                          static_cast<float*>(f), epart);

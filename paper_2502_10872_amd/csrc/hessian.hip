@@ -7,6 +7,7 @@
 // 64 consecutive values and column ids per step (fully coalesced), one row per lane, no reduction.
 #include "devmath.hpp"
 #include "internal.hpp"
+#include "spmv.hpp"
 
 namespace shell {
 
@@ -86,17 +87,8 @@ __global__ void apply_sell(const int32_t* __restrict__ scol, const double* __res
                            double* __restrict__ q) {
     long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (i >= nv) return;
-    long s = i >> 6;
-    long slot = sptr[s] + (i & 63);
-    int w = width[s];
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int k = 0; k < w; ++k, slot += 64) {
-        int c = scol[slot];
-        double a = val[slot];
-        ax = fma(a, p[3L * c], ax);
-        ay = fma(a, p[3L * c + 1], ay);
-        az = fma(a, p[3L * c + 2], az);
-    }
+    double ax, ay, az;
+    sell_row_product<double, double>(scol, val, sptr, width, i, p, ax, ay, az);
     double m = mass ? mass[i] : 0.0;
     q[3 * i] = fma(m, p[3 * i], dt2 * ax);
     q[3 * i + 1] = fma(m, p[3 * i + 1], dt2 * ay);

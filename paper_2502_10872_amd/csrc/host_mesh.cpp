@@ -90,18 +90,9 @@ HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tr
     return topo;
 }
 
-std::vector<int32_t> vertex_order(const double* X, int64_t nv, bool reorder) {
-    std::vector<int32_t> perm(static_cast<size_t>(nv));
-    std::iota(perm.begin(), perm.end(), 0);
-    if (!reorder || nv < 2) return perm;
-    double lo[3], hi[3];
-    for (int c = 0; c < 3; ++c) lo[c] = hi[c] = X[c];
-    for (int64_t i = 0; i < nv; ++i)
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = std::min(lo[c], X[3 * i + c]);
-            hi[c] = std::max(hi[c], X[3 * i + c]);
-        }
-    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
+namespace {
+
+uint64_t morton3(const double* p, const double* lo, double ext) {
     auto spread = [](uint64_t v) {  // 21 bits -> every third bit
         v &= 0x1fffff;
         v = (v | v << 32) & 0x1f00000000ffffull;
@@ -111,13 +102,61 @@ std::vector<int32_t> vertex_order(const double* X, int64_t nv, bool reorder) {
         v = (v | v << 2) & 0x1249249249249249ull;
         return v;
     };
+    uint64_t q[3];
+    for (int c = 0; c < 3; ++c) q[c] = uint64_t((p[c] - lo[c]) / ext * 2097151.0);
+    return spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2;
+}
+
+// Recursive coordinate bisection: split the vertex range along its longest axis so that the left part
+// holds a whole number of tiles, until a range fits one tile; tiles come out as compact patches of the
+// surface whatever its curvature.  Ties are broken by vertex id, so the order is deterministic.
+void rcb(std::vector<int32_t>& perm, int64_t a, int64_t b, const double* X, int T) {
+    if (b - a <= T) return;
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) lo[c] = hi[c] = X[3 * int64_t(perm[size_t(a)]) + c];
+    for (int64_t i = a; i < b; ++i)
+        for (int c = 0; c < 3; ++c) {
+            double v = X[3 * int64_t(perm[size_t(i)]) + c];
+            lo[c] = std::min(lo[c], v);
+            hi[c] = std::max(hi[c], v);
+        }
+    int ax = 0;
+    for (int c = 1; c < 3; ++c)
+        if (hi[c] - lo[c] > hi[ax] - lo[ax]) ax = c;
+    int64_t tiles = (b - a + T - 1) / T;
+    int64_t mid = a + ((tiles + 1) / 2) * T;
+    std::nth_element(perm.begin() + a, perm.begin() + mid, perm.begin() + b, [&](int32_t u, int32_t v) {
+        double pu = X[3 * int64_t(u) + ax], pv = X[3 * int64_t(v) + ax];
+        return pu < pv || (pu == pv && u < v);
+    });
+    rcb(perm, a, mid, X, T);
+    rcb(perm, mid, b, X, T);
+}
+
+}  // namespace
+
+std::vector<int32_t> vertex_order(const double* X, int64_t nv, int mode, int T) {
+    std::vector<int32_t> perm(static_cast<size_t>(nv));
+    std::iota(perm.begin(), perm.end(), 0);
+    if (mode == 0 || nv < 2) return perm;
+    double lo[3], hi[3];
+    for (int c = 0; c < 3; ++c) lo[c] = hi[c] = X[c];
+    for (int64_t i = 0; i < nv; ++i)
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = std::min(lo[c], X[3 * i + c]);
+            hi[c] = std::max(hi[c], X[3 * i + c]);
+        }
+    double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2], 1e-300});
     std::vector<uint64_t> code(static_cast<size_t>(nv));
-    for (int64_t i = 0; i < nv; ++i) {
-        uint64_t q[3];
-        for (int c = 0; c < 3; ++c) q[c] = uint64_t((X[3 * i + c] - lo[c]) / ext * 2097151.0);
-        code[i] = spread(q[0]) | spread(q[1]) << 1 | spread(q[2]) << 2;
-    }
+    for (int64_t i = 0; i < nv; ++i) code[size_t(i)] = morton3(X + 3 * i, lo, ext);
+    // Morton order first (it also orders the vertices inside each bisection tile)
     std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return code[a] < code[b]; });
+    if (mode == 1) {
+        rcb(perm, 0, nv, X, T);
+        for (int64_t a = 0; a < nv; a += T)
+            std::sort(perm.begin() + a, perm.begin() + std::min<int64_t>(nv, a + T),
+                      [&](int32_t u, int32_t v) { return code[u] < code[v] || (code[u] == code[v] && u < v); });
+    }
     return perm;
 }
 

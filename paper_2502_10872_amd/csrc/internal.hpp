@@ -80,8 +80,9 @@ struct HostTopology {
 // Validates the triangle mesh and enumerates the model's stencils.
 HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tris);
 
-// Vertex order: perm[internal] = caller id.  Morton order of the rest positions when reorder != 0.
-std::vector<int32_t> vertex_order(const double* X, int64_t nv, bool reorder);
+// Vertex order: perm[internal] = caller id.  mode 0: the caller's order; 1: recursive coordinate
+// bisection into tiles of T vertices (Morton inside a tile); 2: Morton order of the rest positions.
+std::vector<int32_t> vertex_order(const double* X, int64_t nv, int mode, int T);
 
 struct Tiling {
     int T = 1024;                 // vertices per tile

@@ -4,9 +4,11 @@
 // sharing one sparse product, then v = (x^{t+1} - x^t)/dt.
 //
 // Every scalar of the recurrences lives on the device: each reduction kernel writes per-work-group
-// partial sums and the last work-group to finish (device-scope counter) sums them in a fixed order
-// and updates alpha, beta and the per-column activity flags.  Kernels of converged solves return at
-// once, so the host launches iterations in chunks and reads one flag per chunk.
+// partial sums and a one-work-group finalize kernel sums them in a fixed order and updates alpha, beta
+// and the per-column activity flags.  (Kernel boundaries make the partials visible across the XCDs'
+// private L2 caches; an in-kernel device-scope fence per work-group would write back the L2 each time.)
+// Kernels of converged solves return at once, so the host launches iterations in chunks and reads one
+// flag per chunk.
 //
 // Precision: FP64 throughout, or mixed: float32 matrix values, Jacobi diagonal and the vectors p, q,
 // z; float64 solution y, residual r, all dot products and the Newton residual.
@@ -15,13 +17,13 @@
 
 #include "devmath.hpp"
 #include "internal.hpp"
+#include "spmv.hpp"
 
 struct PcgState {
     double rz[3], rr[3], tol2[3], alpha[3], beta[3];
     double gsq;
     int32_t iters[3], target[3], active[3];
     int32_t done, budget, replay, nonfinite;
-    uint32_t counter[4];
 };
 
 namespace shell {
@@ -29,29 +31,20 @@ namespace shell {
 namespace {
 
 constexpr int kBlk = 256;
-constexpr int kMaxPart = 8;  // doubles of partials per work-group
+constexpr int kMaxPart = 8;  // partial quantities per work-group (buffer sized kMaxPart * groups)
 
-// last-work-group election: every group publishes its partials, then takes a ticket
-__device__ __forceinline__ bool last_group(uint32_t* counter, long ngroups) {
-    __shared__ bool last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        uint32_t t = atomicAdd(counter, 1u);
-        last = (t == uint32_t(ngroups - 1));
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last;
-}
+constexpr int kRedBlk = 512;  // finalize kernels: one work-group
 
-// fixed-order reduction of NQ partials over ngroups work-groups, result in thread 0's out[]
+// fixed-order sum of NQ partials over ngroups work-groups; result in thread 0's out[]
 template <int NQ>
 __device__ void reduce_partials(const double* __restrict__ part, long ngroups, double (&out)[NQ]) {
-    __shared__ double sh[NQ * (kBlk / 64)];
+    __shared__ double sh[NQ * (kRedBlk / 64)];
     for (int q = 0; q < NQ; ++q) out[q] = 0.0;
-    for (long b = threadIdx.x; b < ngroups; b += blockDim.x)
-        for (int q = 0; q < NQ; ++q) out[q] += part[b * kMaxPart + q];
+    // partials are stored quantity-major, part[q * ngroups + group], so these loads coalesce
+#pragma unroll 4
+    for (long b = threadIdx.x; b < ngroups; b += kRedBlk)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q] += part[q * ngroups + b];
     block_sum<NQ>(out, sh);
 }
 
@@ -74,7 +67,7 @@ __global__ void k_predictor(double* __restrict__ x, const double* __restrict__ v
 template <typename FR>
 __global__ void k_residual(const double* __restrict__ x, const double* __restrict__ xhat, const FR* __restrict__ f,
                            const double* __restrict__ mass, const uint8_t* __restrict__ pinned, long nv, double dt2,
-                           double* __restrict__ g, double* __restrict__ part, PcgState* __restrict__ st) {
+                           double* __restrict__ g, double* __restrict__ part) {
     long blk = xcd_logical(blockIdx.x, gridDim.x);
     long ngroups = (nv + kBlk - 1) / kBlk;
     if (blk >= ngroups) return;
@@ -91,15 +84,15 @@ __global__ void k_residual(const double* __restrict__ x, const double* __restric
     }
     __shared__ double sh[kBlk / 64];
     block_sum<1>(acc, sh);
-    if (threadIdx.x == 0) part[blk * kMaxPart] = acc[0];
-    if (last_group(&st->counter[0], ngroups)) {
-        double tot[1];
-        reduce_partials<1>(part, ngroups, tot);
-        if (threadIdx.x == 0) {
-            st->gsq = tot[0];
-            st->nonfinite = !isfinite(tot[0]);
-            st->counter[0] = 0;
-        }
+    if (threadIdx.x == 0) part[blk] = acc[0];
+}
+
+__global__ void k_fin_residual(const double* __restrict__ part, long ngroups, PcgState* __restrict__ st) {
+    double tot[1];
+    reduce_partials<1>(part, ngroups, tot);
+    if (threadIdx.x == 0) {
+        st->gsq = tot[0];
+        st->nonfinite = !isfinite(tot[0]);
     }
 }
 
@@ -107,8 +100,7 @@ __global__ void k_residual(const double* __restrict__ x, const double* __restric
 template <typename VR>
 __global__ void k_pcg_init(const double* __restrict__ g, const VR* __restrict__ dinv, long nv,
                            double* __restrict__ y, double* __restrict__ r, VR* __restrict__ z, VR* __restrict__ p,
-                           double* __restrict__ part, PcgState* __restrict__ st, double rtol2, int replay, int t0,
-                           int t1, int t2) {
+                           double* __restrict__ part) {
     long blk = xcd_logical(blockIdx.x, gridDim.x);
     long ngroups = (nv + kBlk - 1) / kBlk;
     if (blk >= ngroups) return;
@@ -130,30 +122,31 @@ __global__ void k_pcg_init(const double* __restrict__ g, const VR* __restrict__ 
     __shared__ double sh[6 * (kBlk / 64)];
     block_sum<6>(acc, sh);
     if (threadIdx.x == 0)
-        for (int q = 0; q < 6; ++q) part[blk * kMaxPart + q] = acc[q];
-    if (last_group(&st->counter[1], ngroups)) {
-        double tot[6];
-        reduce_partials<6>(part, ngroups, tot);
-        if (threadIdx.x == 0) {
-            const int tg[3] = {t0, t1, t2};
-            int any = 0;
-            for (int d = 0; d < 3; ++d) {
-                st->rz[d] = tot[d];
-                st->rr[d] = tot[3 + d];
-                st->tol2[d] = rtol2 * tot[3 + d];
-                st->alpha[d] = 0.0;
-                st->beta[d] = 0.0;
-                st->iters[d] = 0;
-                st->target[d] = tg[d];
-                st->active[d] = (0 < tg[d]) && (replay || tot[3 + d] > st->tol2[d]);
-                any |= st->active[d];
-            }
-            st->done = !any;
-            st->budget = 0;
-            st->replay = replay;
-            st->nonfinite = 0;
-            st->counter[1] = 0;
+        for (int q = 0; q < 6; ++q) part[q * ngroups + blk] = acc[q];
+}
+
+__global__ void k_fin_init(const double* __restrict__ part, long ngroups, PcgState* __restrict__ st, double rtol2,
+                           int replay, int t0, int t1, int t2) {
+    double tot[6];
+    reduce_partials<6>(part, ngroups, tot);
+    if (threadIdx.x == 0) {
+        const int tg[3] = {t0, t1, t2};
+        int any = 0;
+        for (int d = 0; d < 3; ++d) {
+            st->rz[d] = tot[d];
+            st->rr[d] = tot[3 + d];
+            st->tol2[d] = rtol2 * tot[3 + d];
+            st->alpha[d] = 0.0;
+            st->beta[d] = 0.0;
+            st->iters[d] = 0;
+            st->target[d] = tg[d];
+            st->active[d] = (0 < tg[d]) && (replay || tot[3 + d] > st->tol2[d]);
+            any |= st->active[d];
         }
+        st->done = !any;
+        st->budget = 0;
+        st->replay = replay;
+        st->nonfinite = 0;
     }
 }
 
@@ -163,7 +156,7 @@ __global__ void k_pcg_spmv(const int32_t* __restrict__ scol, const MR* __restric
                            const int64_t* __restrict__ sptr, const int32_t* __restrict__ width,
                            const double* __restrict__ mass, const uint8_t* __restrict__ pinned, long nv, MR dt2,
                            const VR* __restrict__ p, VR* __restrict__ q, double* __restrict__ part,
-                           PcgState* __restrict__ st) {
+                           const PcgState* __restrict__ st) {
     if (st->done) return;
     long blk = xcd_logical(blockIdx.x, gridDim.x);
     long ngroups = (nv + kBlk - 1) / kBlk;
@@ -171,17 +164,8 @@ __global__ void k_pcg_spmv(const int32_t* __restrict__ scol, const MR* __restric
     long i = blk * kBlk + threadIdx.x;
     double acc[3] = {0, 0, 0};
     if (i < nv) {
-        long s = i >> 6;
-        long slot = sptr[s] + (i & 63);
-        int w = width[s];
-        MR ax = 0, ay = 0, az = 0;
-        for (int k = 0; k < w; ++k, slot += 64) {
-            int c = __builtin_nontemporal_load(scol + slot);
-            MR a = __builtin_nontemporal_load(val + slot);
-            ax = fma(a, MR(p[3L * c]), ax);
-            ay = fma(a, MR(p[3L * c + 1]), ay);
-            az = fma(a, MR(p[3L * c + 2]), az);
-        }
+        MR ax, ay, az;
+        sell_row_product<MR, VR>(scol, val, sptr, width, i, p, ax, ay, az);
         VR px = p[3 * i], py = p[3 * i + 1], pz = p[3 * i + 2];
         VR qx = 0, qy = 0, qz = 0;
         if (!pinned[i]) {
@@ -200,23 +184,22 @@ __global__ void k_pcg_spmv(const int32_t* __restrict__ scol, const MR* __restric
     __shared__ double sh[3 * (kBlk / 64)];
     block_sum<3>(acc, sh);
     if (threadIdx.x == 0)
-        for (int q3 = 0; q3 < 3; ++q3) part[blk * kMaxPart + q3] = acc[q3];
-    if (last_group(&st->counter[2], ngroups)) {
-        double tot[3];
-        reduce_partials<3>(part, ngroups, tot);
-        if (threadIdx.x == 0) {
-            for (int d = 0; d < 3; ++d)
-                st->alpha[d] = (st->active[d] && tot[d] != 0.0) ? st->rz[d] / tot[d] : 0.0;
-            st->counter[2] = 0;
-        }
-    }
+        for (int q3 = 0; q3 < 3; ++q3) part[q3 * ngroups + blk] = acc[q3];
+}
+
+__global__ void k_fin_alpha(const double* __restrict__ part, long ngroups, PcgState* __restrict__ st) {
+    if (st->done) return;
+    double tot[3];
+    reduce_partials<3>(part, ngroups, tot);
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) st->alpha[d] = (st->active[d] && tot[d] != 0.0) ? st->rz[d] / tot[d] : 0.0;
 }
 
 // y += alpha p, r -= alpha q, z = D^-1 r; new r.z, r.r; beta and activity per column
 template <typename VR>
 __global__ void k_pcg_update(const VR* __restrict__ p, const VR* __restrict__ q, const VR* __restrict__ dinv, long nv,
                              double* __restrict__ y, double* __restrict__ r, VR* __restrict__ z,
-                             double* __restrict__ part, PcgState* __restrict__ st) {
+                             double* __restrict__ part, const PcgState* __restrict__ st) {
     if (st->done) return;
     long blk = xcd_logical(blockIdx.x, gridDim.x);
     long ngroups = (nv + kBlk - 1) / kBlk;
@@ -240,33 +223,34 @@ __global__ void k_pcg_update(const VR* __restrict__ p, const VR* __restrict__ q,
     __shared__ double sh[6 * (kBlk / 64)];
     block_sum<6>(acc, sh);
     if (threadIdx.x == 0)
-        for (int q6 = 0; q6 < 6; ++q6) part[blk * kMaxPart + q6] = acc[q6];
-    if (last_group(&st->counter[3], ngroups)) {
-        double tot[6];
-        reduce_partials<6>(part, ngroups, tot);
-        if (threadIdx.x == 0) {
-            int any = 0;
-            for (int d = 0; d < 3; ++d) {
-                if (st->active[d]) {
-                    st->beta[d] = st->rz[d] != 0.0 ? tot[d] / st->rz[d] : 0.0;
-                    st->rz[d] = tot[d];
-                    st->rr[d] = tot[3 + d];
-                    st->iters[d] += 1;
-                    bool more = st->replay || tot[3 + d] > st->tol2[d];
-                    if (!st->replay && st->iters[d] >= st->target[d] && more) st->budget = 1;
-                    st->active[d] = (st->iters[d] < st->target[d]) && more;
-                    if (!isfinite(tot[3 + d])) {
-                        st->nonfinite = 1;
-                        st->active[d] = 0;
-                    }
-                } else {
-                    st->beta[d] = 0.0;
+        for (int q6 = 0; q6 < 6; ++q6) part[q6 * ngroups + blk] = acc[q6];
+}
+
+__global__ void k_fin_beta(const double* __restrict__ part, long ngroups, PcgState* __restrict__ st) {
+    if (st->done) return;
+    double tot[6];
+    reduce_partials<6>(part, ngroups, tot);
+    if (threadIdx.x == 0) {
+        int any = 0;
+        for (int d = 0; d < 3; ++d) {
+            if (st->active[d]) {
+                st->beta[d] = st->rz[d] != 0.0 ? tot[d] / st->rz[d] : 0.0;
+                st->rz[d] = tot[d];
+                st->rr[d] = tot[3 + d];
+                st->iters[d] += 1;
+                bool more = st->replay || tot[3 + d] > st->tol2[d];
+                if (!st->replay && st->iters[d] >= st->target[d] && more) st->budget = 1;
+                st->active[d] = (st->iters[d] < st->target[d]) && more;
+                if (!isfinite(tot[3 + d])) {
+                    st->nonfinite = 1;
+                    st->active[d] = 0;
                 }
-                any |= st->active[d];
+            } else {
+                st->beta[d] = 0.0;
             }
-            st->done = !any;
-            st->counter[3] = 0;
+            any |= st->active[d];
         }
+        st->done = !any;
     }
 }
 
@@ -332,10 +316,13 @@ void pcg_iterations(shell_sim_s& sim, int count, double dt2, hipStream_t s) {
     VR* q = reinterpret_cast<VR*>(sim.q.p);
     VR* z = reinterpret_cast<VR*>(sim.z.p);
     const VR* dinv = reinterpret_cast<const VR*>(sim.dinv.p);
+    const long ng = blocks(nv);
     for (int it = 0; it < count; ++it) {
         k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(h.scol.p, val, h.sptr.p, h.width.p, sim.mass.p, sim.pinned.p, nv,
                                                  MR(dt2), p, q, sim.partials.p, st);
+        k_fin_alpha<<<1, kRedBlk, 0, s>>>(sim.partials.p, ng, st);
         k_pcg_update<VR><<<grid, kBlk, 0, s>>>(p, q, dinv, nv, sim.y.p, sim.r.p, z, sim.partials.p, st);
+        k_fin_beta<<<1, kRedBlk, 0, s>>>(sim.partials.p, ng, st);
         k_pcg_direction<VR><<<blocks(nv), kBlk, 0, s>>>(z, p, nv, st);
     }
     SHELL_HIP(hipGetLastError());
@@ -377,7 +364,8 @@ shell_status_t step_impl(shell_sim_s& sim, const shell_step_params_t& prm, hipSt
     for (int k = 0;; ++k) {
         launch_forces(st, sim.x.p, sim.f.p, nullptr, s);
         k_residual<VR><<<rgrid, kBlk, 0, s>>>(sim.x.p, sim.xhat.p, reinterpret_cast<const VR*>(sim.f.p), sim.mass.p,
-                                             sim.pinned.p, nv, dt2, sim.g.p, sim.partials.p, dst);
+                                             sim.pinned.p, nv, dt2, sim.g.p, sim.partials.p);
+        k_fin_residual<<<1, kRedBlk, 0, s>>>(sim.partials.p, blocks(nv), dst);
         SHELL_HIP(hipGetLastError());
         read_state(sim, s);
         if (hst->nonfinite) {
@@ -392,8 +380,9 @@ shell_status_t step_impl(shell_sim_s& sim, const shell_step_params_t& prm, hipSt
             tg[d] = prm.mode == SHELL_PCG_REPLAY ? prm.replay_counts[3 * k + d] : prm.max_pcg;
         k_pcg_init<VR><<<rgrid, kBlk, 0, s>>>(sim.g.p, reinterpret_cast<const VR*>(sim.dinv.p), nv, sim.y.p, sim.r.p,
                                              reinterpret_cast<VR*>(sim.z.p), reinterpret_cast<VR*>(sim.p.p),
-                                             sim.partials.p, dst, prm.pcg_rtol * prm.pcg_rtol,
-                                             prm.mode == SHELL_PCG_REPLAY, tg[0], tg[1], tg[2]);
+                                             sim.partials.p);
+        k_fin_init<<<1, kRedBlk, 0, s>>>(sim.partials.p, blocks(nv), dst, prm.pcg_rtol * prm.pcg_rtol,
+                                         prm.mode == SHELL_PCG_REPLAY, tg[0], tg[1], tg[2]);
         SHELL_HIP(hipGetLastError());
         if (prm.mode == SHELL_PCG_REPLAY) {
             int most = std::max(tg[0], std::max(tg[1], tg[2]));
@@ -483,11 +472,12 @@ void time_impl(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out,
         // a residual from the current forces, then an always-active recurrence
         launch_forces(st, sim.x.p, sim.f.p, nullptr, s);
         k_residual<VR><<<grid, kBlk, 0, s>>>(sim.x.p, sim.x.p, reinterpret_cast<const VR*>(sim.f.p), sim.mass.p,
-                                             sim.pinned.p, nv, dt2, sim.g.p, sim.partials.p, dst);
-        k_pcg_init<VR><<<grid, kBlk, 0, s>>>(sim.g.p, dinv, nv, sim.y.p, sim.r.p, z, p, sim.partials.p, dst, 0.0, 1,
-                                             1 << 30, 1 << 30, 1 << 30);
+                                             sim.pinned.p, nv, dt2, sim.g.p, sim.partials.p);
+        k_pcg_init<VR><<<grid, kBlk, 0, s>>>(sim.g.p, dinv, nv, sim.y.p, sim.r.p, z, p, sim.partials.p);
+        k_fin_init<<<1, kRedBlk, 0, s>>>(sim.partials.p, blocks(nv), dst, 0.0, 1, 1 << 30, 1 << 30, 1 << 30);
         k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(h.scol.p, val, h.sptr.p, h.width.p, sim.mass.p, sim.pinned.p, nv,
                                                  MR(dt2), p, q, sim.partials.p, dst);
+        k_fin_alpha<<<1, kRedBlk, 0, s>>>(sim.partials.p, blocks(nv), dst);
         SHELL_HIP(hipGetLastError());
     };
     auto timed = [&](auto&& launch) {

@@ -73,7 +73,7 @@ def test_stencil_operators_match_oracle(model):
 
 
 @pytest.mark.parametrize("model", I.MODELS)
-@pytest.mark.parametrize("block,reorder", [(64, 1), (256, 1), (4096, 1), (256, 0)])
+@pytest.mark.parametrize("block,reorder", [(64, 1), (256, 1), (4096, 1), (256, 0), (256, 2)])
 def test_forces_and_energy_match_oracle(model, block, reorder):
     mesh = mesh_for(model)
     ost = oracle_stencils(model, mesh)
