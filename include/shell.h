@@ -204,6 +204,23 @@ shell_status_t shell_sim_set_state(shell_sim_t sim, const double* x, const doubl
 shell_status_t shell_sim_device_state(shell_sim_t sim, double** x, double** v);
 
 /*
+ * Multi-mesh batch: simulations stepped together, one launch per phase over all of them (force
+ * tiles of every mesh, row groups of every mesh; reductions and Newton/PCG control per mesh).  Each
+ * mesh keeps its own model, size, parameters and iteration counts; the result of each mesh is that of
+ * stepping it alone (up to summation order of the tile accumulation).
+ *
+ * shell_batch_create: sims host [n] distinct handles of one precision, n >= 1; the simulations must
+ * outlive the batch and must not be stepped alone while the batch is in use.
+ * shell_batch_step: params host [nparams], nparams = 1 (shared) or n; stats host [n] or NULL.  Returns
+ * the worst per-mesh status (SHELL_E_NONFINITE, then SHELL_E_BUDGET); per-mesh statuses are in stats.
+ * Synchronises `stream` at the end of every Newton round.
+ */
+shell_status_t shell_batch_create(const shell_sim_t* sims, int32_t n, shell_batch_t* out);
+shell_status_t shell_batch_step(shell_batch_t batch, const shell_step_params_t* params, int32_t nparams,
+                                shell_step_stats_t* stats, shell_stream_t stream);
+void shell_destroy_batch(shell_batch_t batch);
+
+/*
  * shell_sim_time_kernels - timing harness: average duration of one launch of each hot kernel of the
  * step, measured with HIP events on `stream` over `reps` back-to-back launches on the simulation's
  * current state (forces at x, then the three PCG kernels on a freshly initialised recurrence).  The

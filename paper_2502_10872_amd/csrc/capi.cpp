@@ -33,6 +33,19 @@ shell_status_t guarded(F&& fn) {
 
 hipStream_t as_stream(shell_stream_t s) { return static_cast<hipStream_t>(s); }
 
+void check_params(const shell_step_params_t& p) {
+    SHELL_CHECK(p.dt > 0 && std::isfinite(p.dt), SHELL_E_INVALID_ARG, "dt must be positive");
+    SHELL_CHECK(p.max_newton >= 0 && p.max_newton <= SHELL_MAX_NEWTON, SHELL_E_INVALID_ARG, "max_newton out of range");
+    SHELL_CHECK(p.mode == SHELL_PCG_TOLERANCE || p.mode == SHELL_PCG_REPLAY, SHELL_E_INVALID_ARG, "unknown mode");
+    SHELL_CHECK(p.mode != SHELL_PCG_REPLAY || p.replay_counts, SHELL_E_INVALID_ARG, "replay needs counts");
+    SHELL_CHECK(p.mode == SHELL_PCG_REPLAY || p.max_pcg > 0, SHELL_E_INVALID_ARG, "max_pcg must be positive");
+    SHELL_CHECK(p.chunk >= 0, SHELL_E_INVALID_ARG, "chunk must be >= 0");
+    for (int c = 0; c < 3; ++c) SHELL_CHECK(std::isfinite(p.gravity[c]), SHELL_E_INVALID_ARG, "gravity not finite");
+    if (p.mode == SHELL_PCG_REPLAY)
+        for (int q = 0; q < 3 * p.max_newton; ++q)
+            SHELL_CHECK(p.replay_counts[q] >= 0, SHELL_E_INVALID_ARG, "negative replay count");
+}
+
 __global__ void gather1(const double* __restrict__ src, const int32_t* __restrict__ perm, double* __restrict__ dst,
                         long n) {
     long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
@@ -168,6 +181,31 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         st->xin.alloc(size_t(3 * nv));
         st->fout.alloc(size_t(3 * nv));
         st->epart.alloc(size_t(st->nblocks));
+        {
+            // descriptor and tile items of the caller-order entry point (staging buffers xin/fout)
+            ForceDesc d{};
+            d.x = st->xin.p;
+            d.f = st->fout.p;
+            d.epart = st->epart.p;
+            d.boff = st->boff.p;
+            d.tidx = st->tidx.p;
+            const bool f32 = precision == SHELL_PREC_MIXED;
+            d.tB = f32 ? static_cast<const void*>(st->tBf.p) : static_cast<const void*>(st->tB.p);
+            d.tk0 = f32 ? static_cast<const void*>(st->tk0f.p) : static_cast<const void*>(st->tk0.p);
+            d.nst = st->ns_tiled;
+            d.nv = nv;
+            d.T = T;
+            d.model = model;
+            d.kb = st->kb;
+            d.nu = st->poisson;
+            st->fdesc.alloc(1);
+            st->fdesc.upload(&d, 1, s);
+            std::vector<WorkItem> items(size_t(st->nblocks));
+            for (int64_t t = 0; t < st->nblocks; ++t) items[size_t(t)] = {0, int32_t(t)};
+            st->tile_items.alloc(items.size());
+            st->tile_items.upload(items.data(), items.size(), s);
+            SHELL_HIP(hipStreamSynchronize(s));
+        }
         SHELL_HIP(hipStreamSynchronize(s));
         *out = st.release();
         return SHELL_OK;
@@ -225,12 +263,10 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
         SHELL_CHECK(st && (x || st->nv == 0) && (f || st->nv == 0), SHELL_E_INVALID_ARG, "null argument");
         hipStream_t s = as_stream(stream);
         const bool f32 = st->precision == SHELL_PREC_MIXED;
-        if (st->reordered) {
+        if (st->nv > 0) {
             launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
-            launch_forces(*st, st->xin.p, st->fout.p, energy ? st->epart.p : nullptr, s);
+            launch_force_items(st->model, st->precision, st->fdesc.p, st->tile_items.p, st->nblocks, st->T, s);
             launch_scatter_rows(st->fout.p, st->perm_d.p, f, st->nv, f32, s);
-        } else {
-            launch_forces(*st, x, f, energy ? st->epart.p : nullptr, s);
         }
         if (energy) {
             if (st->nv == 0)
@@ -353,6 +389,12 @@ shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const do
         sim->pinned.upload(pi.data(), pi.size(), s);
         sim_mass(*sim, s);
         SHELL_HIP(hipStreamSynchronize(s));
+        if (nv > 0) {
+            auto solo = std::make_unique<shell_batch_s>();
+            solo->sims = {sim.get()};
+            batch_init(*solo);
+            sim->solo = solo.release();
+        }
         *out = sim.release();
         return SHELL_OK;
     });
@@ -363,17 +405,14 @@ shell_status_t shell_step_implicit(shell_sim_t sim, const shell_step_params_t* p
     return guarded([&]() -> shell_status_t {
         SHELL_CHECK(sim && params, SHELL_E_INVALID_ARG, "null argument");
         const shell_step_params_t& p = *params;
-        SHELL_CHECK(p.dt > 0 && std::isfinite(p.dt), SHELL_E_INVALID_ARG, "dt must be positive");
-        SHELL_CHECK(p.max_newton >= 0 && p.max_newton <= SHELL_MAX_NEWTON, SHELL_E_INVALID_ARG,
-                    "max_newton out of range");
-        SHELL_CHECK(p.mode == SHELL_PCG_TOLERANCE || p.mode == SHELL_PCG_REPLAY, SHELL_E_INVALID_ARG, "unknown mode");
-        SHELL_CHECK(p.mode != SHELL_PCG_REPLAY || p.replay_counts, SHELL_E_INVALID_ARG, "replay needs counts");
-        SHELL_CHECK(p.mode == SHELL_PCG_REPLAY || p.max_pcg > 0, SHELL_E_INVALID_ARG, "max_pcg must be positive");
-        SHELL_CHECK(p.chunk >= 0, SHELL_E_INVALID_ARG, "chunk must be >= 0");
-        if (p.mode == SHELL_PCG_REPLAY)
-            for (int q = 0; q < 3 * p.max_newton; ++q)
-                SHELL_CHECK(p.replay_counts[q] >= 0, SHELL_E_INVALID_ARG, "negative replay count");
-        shell_status_t rc = sim_step(*sim, p, as_stream(stream));
+        check_params(p);
+        shell_status_t rc = SHELL_OK;
+        if (sim->nv > 0) {
+            rc = batch_step(*sim->solo, &p, 1, nullptr, as_stream(stream));
+        } else {
+            sim->stats = shell_step_stats_t{};
+            sim->step++;
+        }
         if (stats) {
             SHELL_HIP(hipStreamSynchronize(as_stream(stream)));
             *stats = sim->stats;
@@ -446,7 +485,7 @@ shell_status_t shell_sim_time_kernels(shell_sim_t sim, double dt, int32_t reps, 
     return guarded([&]() -> shell_status_t {
         SHELL_CHECK(sim && out && reps > 0 && dt > 0, SHELL_E_INVALID_ARG, "bad argument");
         std::memset(out, 0, sizeof(*out));
-        sim_time_kernels(*sim, dt, reps, *out, as_stream(stream));
+        if (sim->solo) batch_time_kernels(*sim->solo, dt, reps, *out, as_stream(stream));
         return SHELL_OK;
     });
 }
@@ -455,8 +494,51 @@ void shell_destroy_stencils(shell_stencils_t st) { delete st; }
 void shell_destroy_hessian(shell_hessian_t h) { delete h; }
 void shell_destroy_sim(shell_sim_t sim) {
     if (!sim) return;
-    if (sim->state_host) (void)hipHostFree(sim->state_host);
+    if (sim->solo) {
+        batch_free_host(*sim->solo);
+        delete sim->solo;
+    }
     delete sim;
+}
+
+shell_status_t shell_batch_create(const shell_sim_t* sims, int32_t n, shell_batch_t* out) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sims && out && n >= 1, SHELL_E_INVALID_ARG, "bad argument");
+        *out = nullptr;
+        auto b = std::make_unique<shell_batch_s>();
+        for (int32_t m = 0; m < n; ++m) {
+            SHELL_CHECK(sims[m], SHELL_E_INVALID_ARG, "null simulation");
+            b->sims.push_back(sims[m]);
+        }
+        try {
+            batch_init(*b);
+        } catch (...) {
+            batch_free_host(*b);
+            throw;
+        }
+        *out = b.release();
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_batch_step(shell_batch_t batch, const shell_step_params_t* params, int32_t nparams,
+                                shell_step_stats_t* stats, shell_stream_t stream) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(batch && params && (nparams == 1 || nparams == int32_t(batch->sims.size())),
+                    SHELL_E_INVALID_ARG, "params must hold 1 or n entries");
+        for (int32_t q = 0; q < nparams; ++q) check_params(params[q]);
+        shell_status_t rc = batch_step(*batch, params, nparams, stats, as_stream(stream));
+        if (stats) SHELL_HIP(hipStreamSynchronize(as_stream(stream)));
+        if (rc == SHELL_E_BUDGET) g_last_error = "PCG iteration budget exhausted in at least one mesh";
+        if (rc == SHELL_E_NONFINITE) g_last_error = "non-finite residual in at least one mesh";
+        return rc;
+    });
+}
+
+void shell_destroy_batch(shell_batch_t batch) {
+    if (!batch) return;
+    batch_free_host(*batch);
+    delete batch;
 }
 
 }  // extern "C"

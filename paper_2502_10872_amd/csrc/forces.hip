@@ -121,26 +121,32 @@ __device__ __forceinline__ void lds_add(double* acc, int slot, V3<R> v) {
     atomicAdd(acc + 3 * slot + 2, double(v.z));
 }
 
-// One work-group per vertex tile.  K = 4 (edge) or 6 (triangle) vertices per stencil.
+// One work-group per (mesh, vertex tile) work item.  K = 4 (edge) or 6 (triangle) vertices per stencil.
 template <int MODEL, typename R>
-__global__ __launch_bounds__(256) void force_tiles(const double* __restrict__ x, const int64_t* __restrict__ boff,
-                                                   const int32_t* __restrict__ tidx, const R* __restrict__ tB,
-                                                   const R* __restrict__ tk0, long nst, long nv, int T,
-                                                   long nblocks, R kb, R nu, R* __restrict__ f,
-                                                   double* __restrict__ epart) {
+__global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__ descs,
+                                                   const WorkItem* __restrict__ items, long nitems) {
     constexpr bool EDGE = (MODEL == SHELL_EP || MODEL == SHELL_ES);
     constexpr bool SHELL = (MODEL == SHELL_ES || MODEL == SHELL_FS || MODEL == SHELL_SS);
     constexpr int K = EDGE ? 4 : 6;
     extern __shared__ unsigned char smem_raw[];
     double* acc = reinterpret_cast<double*>(smem_raw);
-    long blk = xcd_logical(blockIdx.x, gridDim.x);
-    if (blk >= nblocks) return;
-    const long base = blk * long(T);
-    const int nown = int(min(long(T), nv - base));
+    long it = xcd_logical(blockIdx.x, gridDim.x);
+    if (it >= nitems) return;
+    const WorkItem wi = items[it];
+    const ForceDesc& d = descs[wi.mesh];
+    const double* __restrict__ x = d.x;
+    const int32_t* __restrict__ tidx = d.tidx;
+    const R* __restrict__ tB = static_cast<const R*>(d.tB);
+    const R* __restrict__ tk0 = static_cast<const R*>(d.tk0);
+    const long nst = d.nst;
+    const R kb = R(d.kb), nu = R(d.nu);
+    const long blk = wi.unit;
+    const long base = blk * long(d.T);
+    const int nown = int(min(long(d.T), d.nv - base));
     for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
     double e_own = 0.0;
-    const long e0 = boff[blk], e1 = boff[blk + 1];
+    const long e0 = d.boff[blk], e1 = d.boff[blk + 1];
     for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
         int vid[K];
         V3<double> xg[K];
@@ -176,31 +182,26 @@ __global__ __launch_bounds__(256) void force_tiles(const double* __restrict__ x,
         }
     }
     __syncthreads();
-    R* out = f + 3 * base;
+    R* out = static_cast<R*>(d.f) + 3 * base;
     for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
-    if (epart) {
+    if (d.epart) {
         __shared__ double sh[8];
         double v[1] = {e_own};
         block_sum<1>(v, sh);
-        if (threadIdx.x == 0) epart[blk] = v[0];
+        if (threadIdx.x == 0) d.epart[blk] = v[0];
     }
 }
 
 template <int MODEL>
-void launch_model(shell_stencils_s& st, const double* x, void* f, double* epart, hipStream_t s) {
+void launch_model(int precision, const ForceDesc* descs, const WorkItem* items, long nitems, int lds_T,
+                  hipStream_t s) {
     const int blk = 256;
-    long grid = xcd_grid(st.nblocks);
-    if (st.precision == SHELL_PREC_FP64) {
-        size_t lds = size_t(3 * st.T) * sizeof(double);
-        force_tiles<MODEL, double><<<grid, blk, lds, s>>>(x, st.boff.p, st.tidx.p, st.tB.p, st.tk0.p, st.ns_tiled,
-                                                          st.nv, st.T, st.nblocks, st.kb, st.poisson,
-                                                          static_cast<double*>(f), epart);
-    } else {
-        size_t lds = size_t(3 * st.T) * sizeof(double);
-        force_tiles<MODEL, float><<<grid, blk, lds, s>>>(x, st.boff.p, st.tidx.p, st.tBf.p, st.tk0f.p, st.ns_tiled,
-                                                         st.nv, st.T, st.nblocks, float(st.kb), float(st.poisson),
-                                                         static_cast<float*>(f), epart);
-    }
+    long grid = xcd_grid(nitems);
+    size_t lds = size_t(3 * lds_T) * sizeof(double);
+    if (precision == SHELL_PREC_FP64)
+        force_tiles<MODEL, double><<<grid, blk, lds, s>>>(descs, items, nitems);
+    else
+        force_tiles<MODEL, float><<<grid, blk, lds, s>>>(descs, items, nitems);
     SHELL_HIP(hipGetLastError());
 }
 
@@ -236,15 +237,16 @@ __global__ void scatter_rows(const T* __restrict__ src, const int32_t* __restric
 
 }  // namespace
 
-void launch_forces(shell_stencils_s& st, const double* x, void* f, double* epart, hipStream_t s) {
-    if (st.nv == 0) return;
-    switch (st.model) {
-        case SHELL_EP: launch_model<SHELL_EP>(st, x, f, epart, s); break;
-        case SHELL_ES: launch_model<SHELL_ES>(st, x, f, epart, s); break;
-        case SHELL_FP: launch_model<SHELL_FP>(st, x, f, epart, s); break;
-        case SHELL_FS: launch_model<SHELL_FS>(st, x, f, epart, s); break;
-        case SHELL_SP: launch_model<SHELL_SP>(st, x, f, epart, s); break;
-        case SHELL_SS: launch_model<SHELL_SS>(st, x, f, epart, s); break;
+void launch_force_items(int model, int precision, const ForceDesc* descs, const WorkItem* items, long nitems,
+                        int lds_T, hipStream_t s) {
+    if (nitems <= 0) return;
+    switch (model) {
+        case SHELL_EP: launch_model<SHELL_EP>(precision, descs, items, nitems, lds_T, s); break;
+        case SHELL_ES: launch_model<SHELL_ES>(precision, descs, items, nitems, lds_T, s); break;
+        case SHELL_FP: launch_model<SHELL_FP>(precision, descs, items, nitems, lds_T, s); break;
+        case SHELL_FS: launch_model<SHELL_FS>(precision, descs, items, nitems, lds_T, s); break;
+        case SHELL_SP: launch_model<SHELL_SP>(precision, descs, items, nitems, lds_T, s); break;
+        case SHELL_SS: launch_model<SHELL_SS>(precision, descs, items, nitems, lds_T, s); break;
         default: throw Error(SHELL_E_INVALID_ARG, "unknown model");
     }
 }

@@ -106,6 +106,51 @@ struct SellPattern {
 };
 SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv);
 
+// ------------------------------------------------------------------ kernel descriptors
+
+// Per-mesh arguments of the force kernel.  Kernels take an array of descriptors and a list of work
+// items (mesh, unit): one launch covers any set of meshes, a single mesh being a set of one.
+struct ForceDesc {
+    const double* x;
+    void* f;               // double or float [nv][3]
+    double* epart;         // per-tile energy, or null
+    const int64_t* boff;   // tile offsets into the tiled stencil list
+    const int32_t* tidx;
+    const void* tB;        // double or float operator stream
+    const void* tk0;
+    int64_t nst, nv;
+    int32_t T, model;
+    double kb, nu;
+};
+
+// Per-mesh arguments of the implicit-step kernels.
+struct PcgState {
+    double rz[3], rr[3], tol2[3], alpha[3], beta[3];
+    double gsq;
+    int32_t iters[3], target[3], active[3];
+    int32_t done, budget, replay, nonfinite;
+};
+
+struct SolveDesc {
+    double *x, *xhat, *xt, *v, *g, *y, *r;
+    void *f, *z, *p, *q, *dinv;     // float in mixed precision
+    const double *mass, *kdiag;
+    const uint8_t* pinned;
+    const int32_t* scol;
+    const void* val;                // SELL values, float in mixed precision
+    const int64_t* sptr;
+    const int32_t* width;
+    PcgState* st;
+    double* part;                   // reduction partials, quantity-major [q][group]
+    int64_t nv, ngroups;
+    double dt, dt2, grav[3], rtol2;
+    int32_t replay, target[3];
+};
+
+struct WorkItem {
+    int32_t mesh, unit;
+};
+
 // ------------------------------------------------------------------ handles
 
 }  // namespace shell
@@ -139,6 +184,8 @@ struct shell_stencils_s {
     shell::DevArray<double> xin;         // [nv][3]
     shell::DevArray<double> fout;        // [nv][3] (float for mixed, sized in doubles)
     shell::DevArray<double> epart;       // [nblocks] energy partials
+    shell::DevArray<shell::ForceDesc> fdesc;     // descriptor for the caller-order entry point
+    shell::DevArray<shell::WorkItem> tile_items; // (0, tile) for every tile
 };
 
 struct shell_hessian_s {
@@ -154,7 +201,6 @@ struct shell_hessian_s {
     shell::DevArray<double> pin, qout;   // caller-order scratch for hessian_apply
 };
 
-struct PcgState;  // device-side solver scalars (solver.hip)
 
 struct shell_sim_s {
     shell_stencils_s* st = nullptr;
@@ -169,9 +215,25 @@ struct shell_sim_s {
     shell::DevArray<uint8_t> pinned;
     shell::DevArray<double> z, p, q;     // PCG work vectors (float in mixed; sized in doubles)
     shell::DevArray<double> partials;    // reduction partials
-    shell::DevArray<unsigned char> state;  // PcgState
-    unsigned char* state_host = nullptr;   // pinned host mirror
+    shell_batch_s* solo = nullptr;       // this simulation alone, as a batch of one
     shell_step_stats_t stats{};
+};
+
+// A set of simulations stepped together: one launch per phase covers all of them.
+struct shell_batch_s {
+    std::vector<shell_sim_s*> sims;
+    int precision = 0;
+    int max_T = 0;
+    shell::DevArray<shell::ForceDesc> fdesc;
+    shell::DevArray<shell::SolveDesc> sdesc;
+    shell::DevArray<shell::PcgState> state;
+    shell::PcgState* state_host = nullptr;
+    shell::SolveDesc* sdesc_host = nullptr;  // pinned staging
+    shell::WorkItem* items_host = nullptr;   // pinned staging
+    int32_t* mlist_host = nullptr;
+    size_t items_cap = 0;
+    shell::DevArray<shell::WorkItem> items;   // [rows | tiles of each model]
+    shell::DevArray<int32_t> mlist;
 };
 
 namespace shell {
@@ -179,7 +241,9 @@ namespace shell {
 void launch_precompute(shell_stencils_s& st, hipStream_t s);
 void launch_tile_copy(shell_stencils_s& st, hipStream_t s);
 // forces.hip
-void launch_forces(shell_stencils_s& st, const double* x, void* f, double* epart, hipStream_t s);
+// one launch per model over a list of (mesh, tile) items; lds_T = the largest tile among the meshes
+void launch_force_items(int model, int precision, const ForceDesc* descs, const WorkItem* items, long nitems,
+                        int lds_T, hipStream_t s);
 void launch_energy_finalize(const double* epart, int64_t n, double* energy, hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
 void launch_scatter_rows(const void* src, const int32_t* perm, void* dst, int64_t nv, bool f32, hipStream_t s);
@@ -189,7 +253,10 @@ void launch_apply(const shell_hessian_s& h, const double* mass, double dt2, cons
                   hipStream_t s);
 // solver.hip
 void sim_alloc(shell_sim_s& sim);
+void batch_init(shell_batch_s& b);
+void batch_free_host(shell_batch_s& b);
+shell_status_t batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams, shell_step_stats_t* stats,
+                          hipStream_t s);
+void batch_time_kernels(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out, hipStream_t s);
 void sim_mass(shell_sim_s& sim, hipStream_t s);
-shell_status_t sim_step(shell_sim_s& sim, const shell_step_params_t& p, hipStream_t s);
-void sim_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out, hipStream_t s);
 }  // namespace shell

@@ -3,15 +3,19 @@
 // by three Jacobi-PCG recurrences (x, y, z coordinates decouple exactly because A is A_s (x) I3)
 // sharing one sparse product, then v = (x^{t+1} - x^t)/dt.
 //
+// Every kernel takes an array of per-mesh descriptors and a list of (mesh, 256-row group) work items,
+// so one launch per phase advances any set of meshes (a single simulation is a set of one).
+//
 // Every scalar of the recurrences lives on the device: each reduction kernel writes per-work-group
-// partial sums and a one-work-group finalize kernel sums them in a fixed order and updates alpha, beta
-// and the per-column activity flags.  (Kernel boundaries make the partials visible across the XCDs'
-// private L2 caches; an in-kernel device-scope fence per work-group would write back the L2 each time.)
-// Kernels of converged solves return at once, so the host launches iterations in chunks and reads one
-// flag per chunk.
+// partial sums and a finalize kernel (one work-group per mesh) sums them in a fixed order and updates
+// alpha, beta and the per-column activity flags.  (Kernel boundaries make the partials visible across
+// the XCDs' private L2 caches; an in-kernel device-scope fence per work-group would write back the L2
+// each time.)  Kernels of converged meshes return at once, so the host launches iterations in chunks
+// and reads the flags once per chunk.
 //
 // Precision: FP64 throughout, or mixed: float32 matrix values, Jacobi diagonal and the vectors p, q,
-// z; float64 solution y, residual r, all dot products and the Newton residual.
+// z and f; float64 solution y, residual r, all dot products and the Newton residual.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -19,21 +23,15 @@
 #include "internal.hpp"
 #include "spmv.hpp"
 
-struct PcgState {
-    double rz[3], rr[3], tol2[3], alpha[3], beta[3];
-    double gsq;
-    int32_t iters[3], target[3], active[3];
-    int32_t done, budget, replay, nonfinite;
-};
-
 namespace shell {
 
 namespace {
 
-constexpr int kBlk = 256;
-constexpr int kMaxPart = 8;  // partial quantities per work-group (buffer sized kMaxPart * groups)
+constexpr int kBlk = 256;     // rows per work item
+constexpr int kRedBlk = 512;  // finalize kernels: one work-group per mesh
+constexpr int kMaxPart = 8;   // partial quantities per work-group (buffer sized kMaxPart * groups)
 
-constexpr int kRedBlk = 512;  // finalize kernels: one work-group
+inline long blocks(long n) { return (n + kBlk - 1) / kBlk; }
 
 // fixed-order sum of NQ partials over ngroups work-groups; result in thread 0's out[]
 template <int NQ>
@@ -48,128 +46,147 @@ __device__ void reduce_partials(const double* __restrict__ part, long ngroups, d
     block_sum<NQ>(out, sh);
 }
 
-__global__ void k_predictor(double* __restrict__ x, const double* __restrict__ v, double* __restrict__ xt,
-                            double* __restrict__ xhat, const uint8_t* __restrict__ pinned, long nv, double dt,
-                            double g0, double g1, double g2) {
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i >= nv) return;
-    const double gr[3] = {g0, g1, g2};
-    bool pin = pinned[i];
-    for (int d = 0; d < 3; ++d) {
-        double xi = x[3 * i + d];
-        xt[3 * i + d] = xi;
-        double xh = pin ? xi : xi + dt * v[3 * i + d] + dt * dt * gr[d];
-        xhat[3 * i + d] = xh;
-        x[3 * i + d] = xh;
+// this work-group's (mesh, row group); false if the grid slot is idle
+__device__ __forceinline__ bool work_item(const WorkItem* __restrict__ items, long nitems, WorkItem& wi) {
+    long it = xcd_logical(blockIdx.x, gridDim.x);
+    if (it >= nitems) return false;
+    wi = items[it];
+    return true;
+}
+
+__global__ void k_predictor(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    bool pin = d.pinned[i];
+    for (int c = 0; c < 3; ++c) {
+        double xi = d.x[3 * i + c];
+        d.xt[3 * i + c] = xi;
+        double xh = pin ? xi : xi + d.dt * d.v[3 * i + c] + d.dt * d.dt * d.grav[c];
+        d.xhat[3 * i + c] = xh;
+        d.x[3 * i + c] = xh;
     }
 }
 
-template <typename FR>
-__global__ void k_residual(const double* __restrict__ x, const double* __restrict__ xhat, const FR* __restrict__ f,
-                           const double* __restrict__ mass, const uint8_t* __restrict__ pinned, long nv, double dt2,
-                           double* __restrict__ g, double* __restrict__ part) {
-    long blk = xcd_logical(blockIdx.x, gridDim.x);
-    long ngroups = (nv + kBlk - 1) / kBlk;
-    if (blk >= ngroups) return;
-    long i = blk * kBlk + threadIdx.x;
+template <typename VR>
+__global__ void k_dinv(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    static_cast<VR*>(d.dinv)[i] = d.pinned[i] ? VR(0) : VR(1.0 / (d.mass[i] + d.dt2 * d.kdiag[i]));
+}
+
+// g = M (x - x_hat) - dt^2 f, fixed rows zero; partial |g|^2
+template <typename VR>
+__global__ void k_residual(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems,
+                           int from_xhat) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    const VR* __restrict__ f = static_cast<const VR*>(d.f);
+    const double* __restrict__ xh = from_xhat ? d.xhat : d.x;
+    long i = long(wi.unit) * kBlk + threadIdx.x;
     double acc[1] = {0.0};
-    if (i < nv) {
-        bool pin = pinned[i];
-        double m = mass[i];
-        for (int d = 0; d < 3; ++d) {
-            double gi = pin ? 0.0 : m * (x[3 * i + d] - xhat[3 * i + d]) - dt2 * double(f[3 * i + d]);
-            g[3 * i + d] = gi;
+    if (i < d.nv) {
+        bool pin = d.pinned[i];
+        double m = d.mass[i];
+        for (int c = 0; c < 3; ++c) {
+            double gi = pin ? 0.0 : m * (d.x[3 * i + c] - xh[3 * i + c]) - d.dt2 * double(f[3 * i + c]);
+            d.g[3 * i + c] = gi;
             acc[0] += gi * gi;
         }
     }
     __shared__ double sh[kBlk / 64];
     block_sum<1>(acc, sh);
-    if (threadIdx.x == 0) part[blk] = acc[0];
+    if (threadIdx.x == 0) d.part[wi.unit] = acc[0];
 }
 
-__global__ void k_fin_residual(const double* __restrict__ part, long ngroups, PcgState* __restrict__ st) {
+__global__ void k_fin_residual(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ meshes) {
+    const SolveDesc& d = descs[meshes[blockIdx.x]];
     double tot[1];
-    reduce_partials<1>(part, ngroups, tot);
+    reduce_partials<1>(d.part, d.ngroups, tot);
     if (threadIdx.x == 0) {
-        st->gsq = tot[0];
-        st->nonfinite = !isfinite(tot[0]);
+        d.st->gsq = tot[0];
+        d.st->nonfinite = !isfinite(tot[0]);
     }
 }
 
-// r = -g, y = 0, z = D^-1 r, p = z; column norms and tolerances
+// r = -g, y = 0, z = D^-1 r, p = z; partials of r.z and r.r
 template <typename VR>
-__global__ void k_pcg_init(const double* __restrict__ g, const VR* __restrict__ dinv, long nv,
-                           double* __restrict__ y, double* __restrict__ r, VR* __restrict__ z, VR* __restrict__ p,
-                           double* __restrict__ part) {
-    long blk = xcd_logical(blockIdx.x, gridDim.x);
-    long ngroups = (nv + kBlk - 1) / kBlk;
-    if (blk >= ngroups) return;
-    long i = blk * kBlk + threadIdx.x;
+__global__ void k_pcg_init(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    VR* __restrict__ z = static_cast<VR*>(d.z);
+    VR* __restrict__ p = static_cast<VR*>(d.p);
+    long i = long(wi.unit) * kBlk + threadIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (i < nv) {
-        VR di = dinv[i];
-        for (int d = 0; d < 3; ++d) {
-            double ri = -g[3 * i + d];
+    if (i < d.nv) {
+        VR di = static_cast<const VR*>(d.dinv)[i];
+        for (int c = 0; c < 3; ++c) {
+            double ri = -d.g[3 * i + c];
             VR zi = di * VR(ri);
-            r[3 * i + d] = ri;
-            y[3 * i + d] = 0.0;
-            z[3 * i + d] = zi;
-            p[3 * i + d] = zi;
-            acc[d] += ri * double(zi);
-            acc[3 + d] += ri * ri;
+            d.r[3 * i + c] = ri;
+            d.y[3 * i + c] = 0.0;
+            z[3 * i + c] = zi;
+            p[3 * i + c] = zi;
+            acc[c] += ri * double(zi);
+            acc[3 + c] += ri * ri;
         }
     }
     __shared__ double sh[6 * (kBlk / 64)];
     block_sum<6>(acc, sh);
     if (threadIdx.x == 0)
-        for (int q = 0; q < 6; ++q) part[q * ngroups + blk] = acc[q];
+        for (int q = 0; q < 6; ++q) d.part[q * d.ngroups + wi.unit] = acc[q];
 }
 
-__global__ void k_fin_init(const double* __restrict__ part, long ngroups, PcgState* __restrict__ st, double rtol2,
-                           int replay, int t0, int t1, int t2) {
+__global__ void k_fin_init(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ meshes) {
+    const SolveDesc& d = descs[meshes[blockIdx.x]];
     double tot[6];
-    reduce_partials<6>(part, ngroups, tot);
+    reduce_partials<6>(d.part, d.ngroups, tot);
     if (threadIdx.x == 0) {
-        const int tg[3] = {t0, t1, t2};
+        PcgState* st = d.st;
         int any = 0;
-        for (int d = 0; d < 3; ++d) {
-            st->rz[d] = tot[d];
-            st->rr[d] = tot[3 + d];
-            st->tol2[d] = rtol2 * tot[3 + d];
-            st->alpha[d] = 0.0;
-            st->beta[d] = 0.0;
-            st->iters[d] = 0;
-            st->target[d] = tg[d];
-            st->active[d] = (0 < tg[d]) && (replay || tot[3 + d] > st->tol2[d]);
-            any |= st->active[d];
+        for (int c = 0; c < 3; ++c) {
+            st->rz[c] = tot[c];
+            st->rr[c] = tot[3 + c];
+            st->tol2[c] = d.rtol2 * tot[3 + c];
+            st->alpha[c] = 0.0;
+            st->beta[c] = 0.0;
+            st->iters[c] = 0;
+            st->target[c] = d.target[c];
+            st->active[c] = (0 < d.target[c]) && (d.replay || tot[3 + c] > st->tol2[c]);
+            any |= st->active[c];
         }
         st->done = !any;
         st->budget = 0;
-        st->replay = replay;
+        st->replay = d.replay;
         st->nonfinite = 0;
     }
 }
 
-// q = (M + dt^2 K_s) p on the free rows (pinned rows 0); alpha = r.z / p.q per active column
+// q = (M + dt^2 K_s) p on the free rows (fixed rows 0); partials of p.q
 template <typename VR, typename MR>
-__global__ void k_pcg_spmv(const int32_t* __restrict__ scol, const MR* __restrict__ val,
-                           const int64_t* __restrict__ sptr, const int32_t* __restrict__ width,
-                           const double* __restrict__ mass, const uint8_t* __restrict__ pinned, long nv, MR dt2,
-                           const VR* __restrict__ p, VR* __restrict__ q, double* __restrict__ part,
-                           const PcgState* __restrict__ st) {
-    if (st->done) return;
-    long blk = xcd_logical(blockIdx.x, gridDim.x);
-    long ngroups = (nv + kBlk - 1) / kBlk;
-    if (blk >= ngroups) return;
-    long i = blk * kBlk + threadIdx.x;
+__global__ void k_pcg_spmv(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    if (d.st->done) return;
+    const VR* __restrict__ p = static_cast<const VR*>(d.p);
+    VR* __restrict__ q = static_cast<VR*>(d.q);
+    long i = long(wi.unit) * kBlk + threadIdx.x;
     double acc[3] = {0, 0, 0};
-    if (i < nv) {
+    if (i < d.nv) {
         MR ax, ay, az;
-        sell_row_product<MR, VR>(scol, val, sptr, width, i, p, ax, ay, az);
+        sell_row_product<MR, VR>(d.scol, static_cast<const MR*>(d.val), d.sptr, d.width, i, p, ax, ay, az);
         VR px = p[3 * i], py = p[3 * i + 1], pz = p[3 * i + 2];
         VR qx = 0, qy = 0, qz = 0;
-        if (!pinned[i]) {
-            MR m = MR(mass[i]);
+        if (!d.pinned[i]) {
+            const MR m = MR(d.mass[i]), dt2 = MR(d.dt2);
             qx = VR(fma(m, MR(px), dt2 * ax));
             qy = VR(fma(m, MR(py), dt2 * ay));
             qz = VR(fma(m, MR(pz), dt2 * az));
@@ -184,104 +201,115 @@ __global__ void k_pcg_spmv(const int32_t* __restrict__ scol, const MR* __restric
     __shared__ double sh[3 * (kBlk / 64)];
     block_sum<3>(acc, sh);
     if (threadIdx.x == 0)
-        for (int q3 = 0; q3 < 3; ++q3) part[q3 * ngroups + blk] = acc[q3];
+        for (int c = 0; c < 3; ++c) d.part[c * d.ngroups + wi.unit] = acc[c];
 }
 
-__global__ void k_fin_alpha(const double* __restrict__ part, long ngroups, PcgState* __restrict__ st) {
+__global__ void k_fin_alpha(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ meshes) {
+    const SolveDesc& d = descs[meshes[blockIdx.x]];
+    PcgState* st = d.st;
     if (st->done) return;
     double tot[3];
-    reduce_partials<3>(part, ngroups, tot);
+    reduce_partials<3>(d.part, d.ngroups, tot);
     if (threadIdx.x == 0)
-        for (int d = 0; d < 3; ++d) st->alpha[d] = (st->active[d] && tot[d] != 0.0) ? st->rz[d] / tot[d] : 0.0;
+        for (int c = 0; c < 3; ++c) st->alpha[c] = (st->active[c] && tot[c] != 0.0) ? st->rz[c] / tot[c] : 0.0;
 }
 
-// y += alpha p, r -= alpha q, z = D^-1 r; new r.z, r.r; beta and activity per column
+// y += alpha p, r -= alpha q, z = D^-1 r; partials of r.z and r.r
 template <typename VR>
-__global__ void k_pcg_update(const VR* __restrict__ p, const VR* __restrict__ q, const VR* __restrict__ dinv, long nv,
-                             double* __restrict__ y, double* __restrict__ r, VR* __restrict__ z,
-                             double* __restrict__ part, const PcgState* __restrict__ st) {
+__global__ void k_pcg_update(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    const PcgState* st = d.st;
     if (st->done) return;
-    long blk = xcd_logical(blockIdx.x, gridDim.x);
-    long ngroups = (nv + kBlk - 1) / kBlk;
-    if (blk >= ngroups) return;
-    long i = blk * kBlk + threadIdx.x;
+    const VR* __restrict__ p = static_cast<const VR*>(d.p);
+    const VR* __restrict__ q = static_cast<const VR*>(d.q);
+    VR* __restrict__ z = static_cast<VR*>(d.z);
+    long i = long(wi.unit) * kBlk + threadIdx.x;
     const double al[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (i < nv) {
-        VR di = dinv[i];
-        for (int d = 0; d < 3; ++d) {
-            double yi = fma(al[d], double(p[3 * i + d]), y[3 * i + d]);
-            double ri = fma(-al[d], double(q[3 * i + d]), r[3 * i + d]);
+    if (i < d.nv) {
+        VR di = static_cast<const VR*>(d.dinv)[i];
+        for (int c = 0; c < 3; ++c) {
+            double yi = fma(al[c], double(p[3 * i + c]), d.y[3 * i + c]);
+            double ri = fma(-al[c], double(q[3 * i + c]), d.r[3 * i + c]);
             VR zi = di * VR(ri);
-            y[3 * i + d] = yi;
-            r[3 * i + d] = ri;
-            z[3 * i + d] = zi;
-            acc[d] += ri * double(zi);
-            acc[3 + d] += ri * ri;
+            d.y[3 * i + c] = yi;
+            d.r[3 * i + c] = ri;
+            z[3 * i + c] = zi;
+            acc[c] += ri * double(zi);
+            acc[3 + c] += ri * ri;
         }
     }
     __shared__ double sh[6 * (kBlk / 64)];
     block_sum<6>(acc, sh);
     if (threadIdx.x == 0)
-        for (int q6 = 0; q6 < 6; ++q6) part[q6 * ngroups + blk] = acc[q6];
+        for (int q6 = 0; q6 < 6; ++q6) d.part[q6 * d.ngroups + wi.unit] = acc[q6];
 }
 
-__global__ void k_fin_beta(const double* __restrict__ part, long ngroups, PcgState* __restrict__ st) {
+__global__ void k_fin_beta(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ meshes) {
+    const SolveDesc& d = descs[meshes[blockIdx.x]];
+    PcgState* st = d.st;
     if (st->done) return;
     double tot[6];
-    reduce_partials<6>(part, ngroups, tot);
+    reduce_partials<6>(d.part, d.ngroups, tot);
     if (threadIdx.x == 0) {
         int any = 0;
-        for (int d = 0; d < 3; ++d) {
-            if (st->active[d]) {
-                st->beta[d] = st->rz[d] != 0.0 ? tot[d] / st->rz[d] : 0.0;
-                st->rz[d] = tot[d];
-                st->rr[d] = tot[3 + d];
-                st->iters[d] += 1;
-                bool more = st->replay || tot[3 + d] > st->tol2[d];
-                if (!st->replay && st->iters[d] >= st->target[d] && more) st->budget = 1;
-                st->active[d] = (st->iters[d] < st->target[d]) && more;
-                if (!isfinite(tot[3 + d])) {
+        for (int c = 0; c < 3; ++c) {
+            if (st->active[c]) {
+                st->beta[c] = st->rz[c] != 0.0 ? tot[c] / st->rz[c] : 0.0;
+                st->rz[c] = tot[c];
+                st->rr[c] = tot[3 + c];
+                st->iters[c] += 1;
+                bool more = st->replay || tot[3 + c] > st->tol2[c];
+                if (!st->replay && st->iters[c] >= st->target[c] && more) st->budget = 1;
+                st->active[c] = (st->iters[c] < st->target[c]) && more;
+                if (!isfinite(tot[3 + c])) {
                     st->nonfinite = 1;
-                    st->active[d] = 0;
+                    st->active[c] = 0;
                 }
             } else {
-                st->beta[d] = 0.0;
+                st->beta[c] = 0.0;
             }
-            any |= st->active[d];
+            any |= st->active[c];
         }
         st->done = !any;
     }
 }
 
 template <typename VR>
-__global__ void k_pcg_direction(const VR* __restrict__ z, VR* __restrict__ p, long nv,
-                                const PcgState* __restrict__ st) {
+__global__ void k_pcg_direction(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
+                                long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    const PcgState* st = d.st;
     if (st->done) return;
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i >= nv) return;
-    for (int d = 0; d < 3; ++d) {
-        VR b = VR(st->beta[d]);
-        p[3 * i + d] = fma(b, p[3 * i + d], z[3 * i + d]);
-    }
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    const VR* __restrict__ z = static_cast<const VR*>(d.z);
+    VR* __restrict__ p = static_cast<VR*>(d.p);
+    for (int c = 0; c < 3; ++c) p[3 * i + c] = fma(VR(st->beta[c]), p[3 * i + c], z[3 * i + c]);
 }
 
-__global__ void k_add(double* __restrict__ x, const double* __restrict__ y, long n) {
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i < n) x[i] += y[i];
+// x += y (Newton update)
+__global__ void k_newton_update(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
+                                long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    for (int c = 0; c < 3; ++c) d.x[3 * i + c] += d.y[3 * i + c];
 }
 
-__global__ void k_velocity(const double* __restrict__ x, const double* __restrict__ xt, double* __restrict__ v,
-                           long n, double dt) {
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i < n) v[i] = (x[i] - xt[i]) / dt;
-}
-
-template <typename VR>
-__global__ void k_dinv(const double* __restrict__ mass, const double* __restrict__ kdiag,
-                       const uint8_t* __restrict__ pinned, long nv, double dt2, VR* __restrict__ dinv) {
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i < nv) dinv[i] = pinned[i] ? VR(0) : VR(1.0 / (mass[i] + dt2 * kdiag[i]));
+__global__ void k_velocity(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    for (int c = 0; c < 3; ++c) d.v[3 * i + c] = (d.x[3 * i + c] - d.xt[3 * i + c]) / d.dt;
 }
 
 // lumped mass rho h sum(A_T)/3 from the rest triangles
@@ -302,182 +330,335 @@ __global__ void k_zero(double* __restrict__ p, long n) {
     if (i < n) p[i] = 0.0;
 }
 
-inline long blocks(long n) { return (n + kBlk - 1) / kBlk; }
+// ------------------------------------------------------------------ host driver
+
+// Device views of one launch set: the row-group items and, per model, the tile items.
+struct Launch {
+    const SolveDesc* sdesc;
+    const ForceDesc* fdesc;
+    const WorkItem* rows;
+    long nrows;
+    const WorkItem* tiles[6];
+    long ntiles[6];
+    const int32_t* meshes;
+    int nmeshes;
+    int precision;
+    int lds_T;
+};
 
 template <typename VR, typename MR>
-void pcg_iterations(shell_sim_s& sim, int count, double dt2, hipStream_t s) {
-    shell_hessian_s& h = *sim.h;
-    const long nv = sim.nv;
-    long grid = xcd_grid(blocks(nv));
-    PcgState* st = reinterpret_cast<PcgState*>(sim.state.p);
-    const MR* val = std::is_same<MR, float>::value ? reinterpret_cast<const MR*>(h.valf.p)
-                                                    : reinterpret_cast<const MR*>(h.val.p);
-    VR* p = reinterpret_cast<VR*>(sim.p.p);
-    VR* q = reinterpret_cast<VR*>(sim.q.p);
-    VR* z = reinterpret_cast<VR*>(sim.z.p);
-    const VR* dinv = reinterpret_cast<const VR*>(sim.dinv.p);
-    const long ng = blocks(nv);
+void pcg_chunk(const Launch& L, int count, hipStream_t s) {
+    const long grid = xcd_grid(L.nrows);
     for (int it = 0; it < count; ++it) {
-        k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(h.scol.p, val, h.sptr.p, h.width.p, sim.mass.p, sim.pinned.p, nv,
-                                                 MR(dt2), p, q, sim.partials.p, st);
-        k_fin_alpha<<<1, kRedBlk, 0, s>>>(sim.partials.p, ng, st);
-        k_pcg_update<VR><<<grid, kBlk, 0, s>>>(p, q, dinv, nv, sim.y.p, sim.r.p, z, sim.partials.p, st);
-        k_fin_beta<<<1, kRedBlk, 0, s>>>(sim.partials.p, ng, st);
-        k_pcg_direction<VR><<<blocks(nv), kBlk, 0, s>>>(z, p, nv, st);
+        k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_fin_alpha<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
+        k_pcg_update<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_fin_beta<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
+        k_pcg_direction<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
     }
     SHELL_HIP(hipGetLastError());
 }
 
-void read_state(shell_sim_s& sim, hipStream_t s) {
-    SHELL_HIP(hipMemcpyAsync(sim.state_host, sim.state.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+void forces(const Launch& L, hipStream_t s) {
+    for (int m = 0; m < 6; ++m)
+        if (L.ntiles[m]) launch_force_items(m, L.precision, L.fdesc, L.tiles[m], L.ntiles[m], L.lds_T, s);
+}
+
+struct ItemBuilder {
+    std::vector<WorkItem> rows, tiles[6];
+    std::vector<int32_t> meshes;
+    void build(const std::vector<shell_sim_s*>& sims, const std::vector<int>& subset) {
+        rows.clear();
+        meshes.clear();
+        for (auto& t : tiles) t.clear();
+        for (int m : subset) {
+            const shell_sim_s& sim = *sims[size_t(m)];
+            meshes.push_back(m);
+            for (long g = 0; g < blocks(sim.nv); ++g) rows.push_back({m, int32_t(g)});
+            for (long t = 0; t < sim.st->nblocks; ++t) tiles[sim.st->model].push_back({m, int32_t(t)});
+        }
+    }
+};
+
+// Copies the item lists through pinned staging to the batch's device item buffer.  The stream is
+// drained first: earlier copies from the staging and earlier kernels reading the device buffer must
+// have finished before either is overwritten.
+Launch upload(shell_batch_s& b, const ItemBuilder& ib, hipStream_t s) {
+    SHELL_HIP(hipStreamSynchronize(s));
+    size_t total = ib.rows.size();
+    for (const auto& t : ib.tiles) total += t.size();
+    if (total > b.items_cap || !b.items_host) {
+        if (b.items_host) (void)hipHostFree(b.items_host);
+        b.items_host = nullptr;
+        b.items_cap = std::max<size_t>(total, 64) * 2;
+        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.items_host), b.items_cap * sizeof(WorkItem)));
+        b.items.alloc(b.items_cap);
+    }
+    if (!b.mlist_host) {
+        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.mlist_host), (b.sims.size() + 1) * sizeof(int32_t)));
+        b.mlist.alloc(b.sims.size() + 1);
+    }
+    Launch L{};
+    std::copy(ib.rows.begin(), ib.rows.end(), b.items_host);
+    L.rows = b.items.p;
+    L.nrows = long(ib.rows.size());
+    size_t off = ib.rows.size();
+    for (int m = 0; m < 6; ++m) {
+        std::copy(ib.tiles[m].begin(), ib.tiles[m].end(), b.items_host + off);
+        L.tiles[m] = b.items.p + off;
+        L.ntiles[m] = long(ib.tiles[m].size());
+        off += ib.tiles[m].size();
+    }
+    std::copy(ib.meshes.begin(), ib.meshes.end(), b.mlist_host);
+    if (off) SHELL_HIP(hipMemcpyAsync(b.items.p, b.items_host, off * sizeof(WorkItem), hipMemcpyHostToDevice, s));
+    if (!ib.meshes.empty())
+        SHELL_HIP(hipMemcpyAsync(b.mlist.p, b.mlist_host, ib.meshes.size() * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, s));
+    L.meshes = b.mlist.p;
+    L.nmeshes = int(ib.meshes.size());
+    L.sdesc = b.sdesc.p;
+    L.fdesc = b.fdesc.p;
+    L.precision = b.precision;
+    L.lds_T = b.max_T;
+    return L;
+}
+
+void upload_descs(shell_batch_s& b, hipStream_t s) {
+    SHELL_HIP(hipMemcpyAsync(b.sdesc.p, b.sdesc_host, b.sims.size() * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
+}
+
+void read_states(shell_batch_s& b, hipStream_t s) {
+    SHELL_HIP(hipMemcpyAsync(b.state_host, b.state.p, b.sims.size() * sizeof(PcgState), hipMemcpyDeviceToHost, s));
     SHELL_HIP(hipStreamSynchronize(s));
 }
 
-template <typename VR, typename MR>
-shell_status_t step_impl(shell_sim_s& sim, const shell_step_params_t& prm, hipStream_t s) {
-    shell_stencils_s& st = *sim.st;
-    const long nv = sim.nv;
-    const long n3 = 3 * nv;
-    const double dt = prm.dt, dt2 = dt * dt;
-    PcgState* dst = reinterpret_cast<PcgState*>(sim.state.p);
-    const PcgState* hst = reinterpret_cast<const PcgState*>(sim.state_host);
+SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
+    SolveDesc d{};
+    d.x = sim.x.p;
+    d.xhat = sim.xhat.p;
+    d.xt = sim.xt.p;
+    d.v = sim.v.p;
+    d.g = sim.g.p;
+    d.y = sim.y.p;
+    d.r = sim.r.p;
+    d.f = sim.f.p;
+    d.z = sim.z.p;
+    d.p = sim.p.p;
+    d.q = sim.q.p;
+    d.dinv = sim.dinv.p;
+    d.mass = sim.mass.p;
+    d.kdiag = sim.h->kdiag.p;
+    d.pinned = sim.pinned.p;
+    d.scol = sim.h->scol.p;
+    d.val = sim.st->precision == SHELL_PREC_MIXED ? static_cast<const void*>(sim.h->valf.p)
+                                                   : static_cast<const void*>(sim.h->val.p);
+    d.sptr = sim.h->sptr.p;
+    d.width = sim.h->width.p;
+    d.st = st;
+    d.part = sim.partials.p;
+    d.nv = sim.nv;
+    d.ngroups = blocks(sim.nv);
+    return d;
+}
+
+ForceDesc force_desc(shell_sim_s& sim) {
+    const shell_stencils_s& st = *sim.st;
+    const bool f32 = st.precision == SHELL_PREC_MIXED;
+    ForceDesc d{};
+    d.x = sim.x.p;
+    d.f = sim.f.p;
+    d.epart = nullptr;
+    d.boff = st.boff.p;
+    d.tidx = st.tidx.p;
+    d.tB = f32 ? static_cast<const void*>(st.tBf.p) : static_cast<const void*>(st.tB.p);
+    d.tk0 = f32 ? static_cast<const void*>(st.tk0f.p) : static_cast<const void*>(st.tk0.p);
+    d.nst = st.ns_tiled;
+    d.nv = st.nv;
+    d.T = st.T;
+    d.model = st.model;
+    d.kb = st.kb;
+    d.nu = st.poisson;
+    return d;
+}
+
+struct MeshStep {
+    const shell_step_params_t* prm = nullptr;
     shell_step_stats_t stats{};
-    stats.status = SHELL_OK;
-    if (nv == 0) {
-        sim.stats = stats;
-        sim.step++;
-        return SHELL_OK;
-    }
-    if (sim.dinv_dt != dt) {
-        k_dinv<VR><<<blocks(nv), kBlk, 0, s>>>(sim.mass.p, sim.h->kdiag.p, sim.pinned.p, nv, dt2,
-                                              reinterpret_cast<VR*>(sim.dinv.p));
-        sim.dinv_dt = dt;
-    }
-    k_predictor<<<blocks(nv), kBlk, 0, s>>>(sim.x.p, sim.v.p, sim.xt.p, sim.xhat.p, sim.pinned.p, nv, dt,
-                                            prm.gravity[0], prm.gravity[1], prm.gravity[2]);
-    SHELL_HIP(hipGetLastError());
-    const long rgrid = xcd_grid(blocks(nv));
-    const int first_chunk = prm.chunk > 0 ? prm.chunk : 8;
-    const int max_chunk = prm.chunk > 0 ? prm.chunk : 128;
     bool budget = false;
-    double gn0 = 0.0, gn = 0.0;
-    for (int k = 0;; ++k) {
-        launch_forces(st, sim.x.p, sim.f.p, nullptr, s);
-        k_residual<VR><<<rgrid, kBlk, 0, s>>>(sim.x.p, sim.xhat.p, reinterpret_cast<const VR*>(sim.f.p), sim.mass.p,
-                                             sim.pinned.p, nv, dt2, sim.g.p, sim.partials.p);
-        k_fin_residual<<<1, kRedBlk, 0, s>>>(sim.partials.p, blocks(nv), dst);
-        SHELL_HIP(hipGetLastError());
-        read_state(sim, s);
-        if (hst->nonfinite) {
-            stats.status = SHELL_E_NONFINITE;
-            break;
+    double gn0 = 0, gn = 0;
+};
+
+// The step of every mesh of the batch: Newton rounds over the meshes still iterating; each round is
+// one force/residual launch set, then one PCG loop over the meshes that still need a solve.
+template <typename VR, typename MR>
+shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int nparams, shell_step_stats_t* out,
+                         hipStream_t s) {
+    const int n = int(b.sims.size());
+    std::vector<MeshStep> ms(static_cast<size_t>(n));
+    SHELL_HIP(hipStreamSynchronize(s));  // the descriptor staging is reused below
+    for (int m = 0; m < n; ++m) {
+        MeshStep& st = ms[size_t(m)];
+        st.prm = &prms[nparams == 1 ? 0 : m];
+        shell_sim_s& sim = *b.sims[size_t(m)];
+        SolveDesc d = solve_desc(sim, b.state.p + m);
+        d.dt = st.prm->dt;
+        d.dt2 = d.dt * d.dt;
+        for (int c = 0; c < 3; ++c) d.grav[c] = st.prm->gravity[c];
+        d.rtol2 = st.prm->pcg_rtol * st.prm->pcg_rtol;
+        b.sdesc_host[m] = d;
+    }
+    upload_descs(b, s);
+    std::vector<int> all(static_cast<size_t>(n)), need_dinv;
+    for (int m = 0; m < n; ++m) {
+        all[size_t(m)] = m;
+        shell_sim_s& sim = *b.sims[size_t(m)];
+        if (sim.dinv_dt != ms[size_t(m)].prm->dt) {
+            need_dinv.push_back(m);
+            sim.dinv_dt = ms[size_t(m)].prm->dt;
         }
-        gn = std::sqrt(hst->gsq);
-        if (k == 0) gn0 = gn;
-        if (gn0 == 0.0 || (k > 0 && gn <= prm.newton_rtol * gn0) || k == prm.max_newton) break;
-        int tg[3];
-        for (int d = 0; d < 3; ++d)
-            tg[d] = prm.mode == SHELL_PCG_REPLAY ? prm.replay_counts[3 * k + d] : prm.max_pcg;
-        k_pcg_init<VR><<<rgrid, kBlk, 0, s>>>(sim.g.p, reinterpret_cast<const VR*>(sim.dinv.p), nv, sim.y.p, sim.r.p,
-                                             reinterpret_cast<VR*>(sim.z.p), reinterpret_cast<VR*>(sim.p.p),
-                                             sim.partials.p);
-        k_fin_init<<<1, kRedBlk, 0, s>>>(sim.partials.p, blocks(nv), dst, prm.pcg_rtol * prm.pcg_rtol,
-                                         prm.mode == SHELL_PCG_REPLAY, tg[0], tg[1], tg[2]);
+    }
+    ItemBuilder ib;
+    Launch L;
+    if (!need_dinv.empty()) {
+        ib.build(b.sims, need_dinv);
+        L = upload(b, ib, s);
+        k_dinv<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+    }
+    ib.build(b.sims, all);
+    L = upload(b, ib, s);
+    k_predictor<<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+    SHELL_HIP(hipGetLastError());
+
+    std::vector<int> iterating = all;
+    for (int k = 0; !iterating.empty(); ++k) {
+        ib.build(b.sims, iterating);
+        L = upload(b, ib, s);
+        forces(L, s);
+        k_residual<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 1);
+        k_fin_residual<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
         SHELL_HIP(hipGetLastError());
-        if (prm.mode == SHELL_PCG_REPLAY) {
-            int most = std::max(tg[0], std::max(tg[1], tg[2]));
-            pcg_iterations<VR, MR>(sim, most, dt2, s);
-            read_state(sim, s);
+        read_states(b, s);
+        std::vector<int> solve;
+        for (int m : iterating) {
+            MeshStep& st = ms[size_t(m)];
+            const PcgState& ps = b.state_host[m];
+            if (ps.nonfinite) {
+                st.stats.status = SHELL_E_NONFINITE;
+                continue;
+            }
+            st.gn = std::sqrt(ps.gsq);
+            if (k == 0) st.gn0 = st.gn;
+            const shell_step_params_t& p = *st.prm;
+            if (st.gn0 == 0.0 || (k > 0 && st.gn <= p.newton_rtol * st.gn0) || k == p.max_newton) continue;
+            solve.push_back(m);
+        }
+        if (solve.empty()) break;
+        // per-mesh PCG targets of this Newton iteration (the staging is idle: read_states drained)
+        for (int m : solve) {
+            const shell_step_params_t& p = *ms[size_t(m)].prm;
+            SolveDesc& d = b.sdesc_host[m];
+            d.replay = p.mode == SHELL_PCG_REPLAY;
+            for (int c = 0; c < 3; ++c) d.target[c] = d.replay ? p.replay_counts[3 * k + c] : p.max_pcg;
+        }
+        upload_descs(b, s);
+        ib.build(b.sims, solve);
+        L = upload(b, ib, s);
+        k_pcg_init<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_fin_init<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
+        SHELL_HIP(hipGetLastError());
+        bool all_replay = true;
+        int most = 0, first_chunk = 8, max_chunk = 128;
+        for (int m : solve) {
+            const shell_step_params_t& p = *ms[size_t(m)].prm;
+            all_replay &= p.mode == SHELL_PCG_REPLAY;
+            for (int c = 0; c < 3; ++c) most = std::max(most, b.sdesc_host[m].target[c]);
+            if (p.chunk > 0) first_chunk = max_chunk = p.chunk;
+        }
+        if (all_replay) {
+            pcg_chunk<VR, MR>(L, most, s);
+            read_states(b, s);
         } else {
-            read_state(sim, s);
+            read_states(b, s);
             int chunk = first_chunk;
-            while (!hst->done) {
-                pcg_iterations<VR, MR>(sim, chunk, dt2, s);
-                read_state(sim, s);
+            for (;;) {
+                bool done = true;
+                for (int m : solve) done &= b.state_host[m].done != 0;
+                if (done) break;
+                pcg_chunk<VR, MR>(L, chunk, s);
+                read_states(b, s);
                 chunk = std::min(2 * chunk, max_chunk);
             }
         }
-        if (hst->nonfinite) {
-            stats.status = SHELL_E_NONFINITE;
-            break;
+        std::vector<int> next;
+        for (int m : solve) {
+            MeshStep& st = ms[size_t(m)];
+            const PcgState& ps = b.state_host[m];
+            if (ps.nonfinite) {
+                st.stats.status = SHELL_E_NONFINITE;
+                continue;
+            }
+            st.budget |= ps.budget != 0;
+            for (int c = 0; c < 3; ++c) {
+                st.stats.counts[k][c] = ps.iters[c];
+                st.stats.pcg_total += ps.iters[c];
+            }
+            st.stats.newton_iters++;
+            next.push_back(m);
         }
-        budget |= hst->budget != 0;
-        for (int d = 0; d < 3; ++d) {
-            stats.counts[k][d] = hst->iters[d];
-            stats.pcg_total += hst->iters[d];
-        }
-        k_add<<<blocks(n3), kBlk, 0, s>>>(sim.x.p, sim.y.p, n3);
+        k_newton_update<<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
         SHELL_HIP(hipGetLastError());
-        stats.newton_iters++;
+        iterating = next;
     }
-    k_velocity<<<blocks(n3), kBlk, 0, s>>>(sim.x.p, sim.xt.p, sim.v.p, n3, dt);
+    ib.build(b.sims, all);
+    L = upload(b, ib, s);
+    k_velocity<<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
     SHELL_HIP(hipGetLastError());
-    stats.grad_norm0 = gn0;
-    stats.grad_norm = gn;
-    if (stats.status == SHELL_OK && budget) stats.status = SHELL_E_BUDGET;
-    sim.stats = stats;
-    sim.step++;
-    sim.last_stream = s;
-    return shell_status_t(stats.status);
+    shell_status_t worst = SHELL_OK;
+    for (int m = 0; m < n; ++m) {
+        MeshStep& st = ms[size_t(m)];
+        st.stats.grad_norm0 = st.gn0;
+        st.stats.grad_norm = st.gn;
+        if (st.stats.status == SHELL_OK && st.budget) st.stats.status = SHELL_E_BUDGET;
+        shell_sim_s& sim = *b.sims[size_t(m)];
+        sim.stats = st.stats;
+        sim.step++;
+        sim.last_stream = s;
+        if (out) out[m] = st.stats;
+        if (st.stats.status == SHELL_E_NONFINITE || (st.stats.status == SHELL_E_BUDGET && worst == SHELL_OK))
+            worst = shell_status_t(st.stats.status);
+    }
+    return worst;
 }
-
-}  // namespace
-
-void sim_alloc(shell_sim_s& sim) {
-    const long nv = sim.nv, n3 = 3 * nv;
-    for (auto* a : {&sim.x, &sim.v, &sim.xt, &sim.xhat, &sim.g, &sim.y, &sim.r, &sim.f, &sim.z, &sim.p, &sim.q})
-        a->alloc(size_t(std::max(n3, 1L)));
-    sim.mass.alloc(size_t(std::max(nv, 1L)));
-    sim.dinv.alloc(size_t(std::max(nv, 1L)));
-    sim.pinned.alloc(size_t(std::max(nv, 1L)));
-    sim.partials.alloc(size_t(kMaxPart * std::max(blocks(nv), 1L) + kMaxPart));
-    sim.state.alloc(sizeof(PcgState));
-    SHELL_HIP(hipMemset(sim.state.p, 0, sizeof(PcgState)));
-    SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&sim.state_host), sizeof(PcgState)));
-    std::memset(sim.state_host, 0, sizeof(PcgState));
-}
-
-void sim_mass(shell_sim_s& sim, hipStream_t s) {
-    shell_stencils_s& st = *sim.st;
-    if (!sim.nv) return;
-    k_zero<<<blocks(sim.nv), kBlk, 0, s>>>(sim.mass.p, sim.nv);
-    if (st.nt) k_mass<<<blocks(st.nt), kBlk, 0, s>>>(st.X.p, st.tris.p, st.nt, st.density * st.thickness, sim.mass.p);
-    SHELL_HIP(hipGetLastError());
-}
-
-namespace {
 
 template <typename VR, typename MR>
-void time_impl(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {
-    shell_stencils_s& st = *sim.st;
-    shell_hessian_s& h = *sim.h;
-    const long nv = sim.nv;
-    const double dt2 = dt * dt;
-    PcgState* dst = reinterpret_cast<PcgState*>(sim.state.p);
-    const long grid = xcd_grid(blocks(nv));
-    const MR* val = std::is_same<MR, float>::value ? reinterpret_cast<const MR*>(h.valf.p)
-                                                    : reinterpret_cast<const MR*>(h.val.p);
-    VR* p = reinterpret_cast<VR*>(sim.p.p);
-    VR* q = reinterpret_cast<VR*>(sim.q.p);
-    VR* z = reinterpret_cast<VR*>(sim.z.p);
-    const VR* dinv = reinterpret_cast<const VR*>(sim.dinv.p);
-    if (sim.dinv_dt != dt) {
-        k_dinv<VR><<<blocks(nv), kBlk, 0, s>>>(sim.mass.p, h.kdiag.p, sim.pinned.p, nv, dt2, reinterpret_cast<VR*>(sim.dinv.p));
-        sim.dinv_dt = dt;
-    }
+void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {
+    shell_sim_s& sim = *b.sims[0];
+    SHELL_HIP(hipStreamSynchronize(s));
+    SolveDesc d = solve_desc(sim, b.state.p);
+    d.dt = dt;
+    d.dt2 = dt * dt;
+    d.rtol2 = 0.0;
+    d.replay = 1;
+    d.target[0] = d.target[1] = d.target[2] = 1 << 30;
+    b.sdesc_host[0] = d;
+    upload_descs(b, s);
+    ItemBuilder ib;
+    ib.build(b.sims, std::vector<int>{0});
+    Launch L = upload(b, ib, s);
+    const long grid = xcd_grid(L.nrows);
+    k_dinv<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+    sim.dinv_dt = dt;
     hipEvent_t e0, e1;
     SHELL_HIP(hipEventCreate(&e0));
     SHELL_HIP(hipEventCreate(&e1));
     auto init = [&]() {
         // a residual from the current forces, then an always-active recurrence
-        launch_forces(st, sim.x.p, sim.f.p, nullptr, s);
-        k_residual<VR><<<grid, kBlk, 0, s>>>(sim.x.p, sim.x.p, reinterpret_cast<const VR*>(sim.f.p), sim.mass.p,
-                                             sim.pinned.p, nv, dt2, sim.g.p, sim.partials.p);
-        k_pcg_init<VR><<<grid, kBlk, 0, s>>>(sim.g.p, dinv, nv, sim.y.p, sim.r.p, z, p, sim.partials.p);
-        k_fin_init<<<1, kRedBlk, 0, s>>>(sim.partials.p, blocks(nv), dst, 0.0, 1, 1 << 30, 1 << 30, 1 << 30);
-        k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(h.scol.p, val, h.sptr.p, h.width.p, sim.mass.p, sim.pinned.p, nv,
-                                                 MR(dt2), p, q, sim.partials.p, dst);
-        k_fin_alpha<<<1, kRedBlk, 0, s>>>(sim.partials.p, blocks(nv), dst);
+        forces(L, s);
+        k_residual<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 0);
+        k_pcg_init<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_fin_init<<<1, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
+        k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_fin_alpha<<<1, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
         SHELL_HIP(hipGetLastError());
     };
     auto timed = [&](auto&& launch) {
@@ -491,18 +672,13 @@ void time_impl(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out,
         return double(ms) / reps;
     };
     out.reps = reps;
-    out.force_ms = timed([&] { launch_forces(st, sim.x.p, sim.f.p, nullptr, s); });
+    out.force_ms = timed([&] { forces(L, s); });
     init();
-    out.spmv_ms = timed([&] {
-        k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(h.scol.p, val, h.sptr.p, h.width.p, sim.mass.p, sim.pinned.p, nv,
-                                                 MR(dt2), p, q, sim.partials.p, dst);
-    });
+    out.spmv_ms = timed([&] { k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows); });
     init();
-    out.update_ms = timed([&] {
-        k_pcg_update<VR><<<grid, kBlk, 0, s>>>(p, q, dinv, nv, sim.y.p, sim.r.p, z, sim.partials.p, dst);
-    });
+    out.update_ms = timed([&] { k_pcg_update<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows); });
     init();
-    out.direction_ms = timed([&] { k_pcg_direction<VR><<<blocks(nv), kBlk, 0, s>>>(z, p, nv, dst); });
+    out.direction_ms = timed([&] { k_pcg_direction<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows); });
     SHELL_HIP(hipGetLastError());
     SHELL_HIP(hipStreamSynchronize(s));
     (void)hipEventDestroy(e0);
@@ -511,17 +687,72 @@ void time_impl(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out,
 
 }  // namespace
 
-void sim_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {
-    if (sim.nv == 0) return;
-    if (sim.st->precision == SHELL_PREC_MIXED)
-        time_impl<float, float>(sim, dt, reps, out, s);
-    else
-        time_impl<double, double>(sim, dt, reps, out, s);
+void sim_alloc(shell_sim_s& sim) {
+    const long nv = sim.nv, n3 = 3 * nv;
+    for (auto* a : {&sim.x, &sim.v, &sim.xt, &sim.xhat, &sim.g, &sim.y, &sim.r, &sim.f, &sim.z, &sim.p, &sim.q})
+        a->alloc(size_t(std::max(n3, 1L)));
+    sim.mass.alloc(size_t(std::max(nv, 1L)));
+    sim.dinv.alloc(size_t(std::max(nv, 1L)));
+    sim.pinned.alloc(size_t(std::max(nv, 1L)));
+    sim.partials.alloc(size_t(kMaxPart * std::max(blocks(nv), 1L) + kMaxPart));
 }
 
-shell_status_t sim_step(shell_sim_s& sim, const shell_step_params_t& p, hipStream_t s) {
-    if (sim.st->precision == SHELL_PREC_MIXED) return step_impl<float, float>(sim, p, s);
-    return step_impl<double, double>(sim, p, s);
+void sim_mass(shell_sim_s& sim, hipStream_t s) {
+    shell_stencils_s& st = *sim.st;
+    if (!sim.nv) return;
+    k_zero<<<blocks(sim.nv), kBlk, 0, s>>>(sim.mass.p, sim.nv);
+    if (st.nt) k_mass<<<blocks(st.nt), kBlk, 0, s>>>(st.X.p, st.tris.p, st.nt, st.density * st.thickness, sim.mass.p);
+    SHELL_HIP(hipGetLastError());
+}
+
+void batch_init(shell_batch_s& b) {
+    const size_t n = b.sims.size();
+    SHELL_CHECK(n > 0, SHELL_E_INVALID_ARG, "empty batch");
+    b.precision = b.sims[0]->st->precision;
+    b.max_T = 64;
+    std::vector<ForceDesc> fd(n);
+    for (size_t m = 0; m < n; ++m) {
+        SHELL_CHECK(b.sims[m]->st->precision == b.precision, SHELL_E_INVALID_ARG,
+                    "all simulations of a batch need the same precision");
+        for (size_t q = 0; q < m; ++q)
+            SHELL_CHECK(b.sims[q] != b.sims[m], SHELL_E_INVALID_ARG, "a simulation appears twice in a batch");
+        b.max_T = std::max(b.max_T, b.sims[m]->st->T);
+        fd[m] = force_desc(*b.sims[m]);
+    }
+    b.fdesc.alloc(n);
+    b.fdesc.upload(fd.data(), n, nullptr);
+    b.sdesc.alloc(n);
+    b.state.alloc(n);
+    SHELL_HIP(hipMemset(b.state.p, 0, n * sizeof(PcgState)));
+    SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.state_host), n * sizeof(PcgState)));
+    SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.sdesc_host), n * sizeof(SolveDesc)));
+    SHELL_HIP(hipDeviceSynchronize());
+}
+
+void batch_free_host(shell_batch_s& b) {
+    if (b.state_host) (void)hipHostFree(b.state_host);
+    if (b.sdesc_host) (void)hipHostFree(b.sdesc_host);
+    if (b.items_host) (void)hipHostFree(b.items_host);
+    if (b.mlist_host) (void)hipHostFree(b.mlist_host);
+    b.state_host = nullptr;
+    b.sdesc_host = nullptr;
+    b.items_host = nullptr;
+    b.mlist_host = nullptr;
+}
+
+shell_status_t batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams, shell_step_stats_t* stats,
+                          hipStream_t s) {
+    for (shell_sim_s* sim : b.sims)
+        SHELL_CHECK(sim->nv > 0, SHELL_E_INVALID_ARG, "empty simulation in a batch");
+    if (b.precision == SHELL_PREC_MIXED) return step_impl<float, float>(b, p, nparams, stats, s);
+    return step_impl<double, double>(b, p, nparams, stats, s);
+}
+
+void batch_time_kernels(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {
+    if (b.precision == SHELL_PREC_MIXED)
+        time_impl<float, float>(b, dt, reps, out, s);
+    else
+        time_impl<double, double>(b, dt, reps, out, s);
 }
 
 }  // namespace shell

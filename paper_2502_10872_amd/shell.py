@@ -68,7 +68,8 @@ class shell_kernel_times_t(ctypes.Structure):
 EXPORTS = ("shell_build_stencils", "shell_stencils_info", "shell_stencils_export", "shell_eval_forces",
            "shell_assemble_constant_hessian", "shell_hessian_export_csr", "shell_hessian_apply", "shell_sim_create",
            "shell_step_implicit", "shell_sim_get_stats", "shell_sim_get_state", "shell_sim_set_state",
-           "shell_sim_device_state", "shell_sim_time_kernels", "shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim",
+           "shell_sim_device_state", "shell_sim_time_kernels", "shell_batch_create", "shell_batch_step",
+           "shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim", "shell_destroy_batch",
            "shell_status_string", "shell_last_error")
 
 _lib = None
@@ -96,7 +97,9 @@ def lib() -> ctypes.CDLL:
         L.shell_sim_set_state.argtypes = [P, P, P, i64]
         L.shell_sim_device_state.argtypes = [P, P, P]
         L.shell_sim_time_kernels.argtypes = [P, d, i32, P, P]
-        for name in ("shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim"):
+        L.shell_batch_create.argtypes = [P, i32, P]
+        L.shell_batch_step.argtypes = [P, P, i32, P, P]
+        for name in ("shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim", "shell_destroy_batch"):
             getattr(L, name).argtypes = [P]
             getattr(L, name).restype = None
         L.shell_status_string.argtypes = [ctypes.c_int]
@@ -279,6 +282,27 @@ def shell_sim_time_kernels(sim, dt, reps=20, stream=None) -> dict:
     _check(lib().shell_sim_time_kernels(sim, float(dt), int(reps), ctypes.byref(out), _stream(stream)),
            "shell_sim_time_kernels")
     return {name: getattr(out, name) for name, _ in shell_kernel_times_t._fields_ if name != "reserved"}
+
+
+def shell_batch_create(sims):
+    arr = (ctypes.c_void_p * len(sims))(*sims)
+    out = ctypes.c_void_p()
+    _check(lib().shell_batch_create(arr, len(sims), ctypes.byref(out)), "shell_batch_create")
+    return out.value
+
+
+def shell_batch_step(batch, params, n, with_stats=True, stream=None):
+    """params: one shell_step_params_t (shared) or a list of n.  Returns (status, [stats dict] or None)."""
+    plist = params if isinstance(params, (list, tuple)) else [params]
+    parr = (shell_step_params_t * len(plist))(*plist)
+    stats = (shell_step_stats_t * n)()
+    rc = lib().shell_batch_step(batch, parr, len(plist), stats if with_stats else None, _stream(stream))
+    _check(rc, "shell_batch_step", allow=(SHELL_OK, SHELL_E_BUDGET))
+    return rc, ([stats_dict(stats[m]) for m in range(n)] if with_stats else None)
+
+
+def shell_destroy_batch(batch):
+    lib().shell_destroy_batch(batch)
 
 
 def shell_destroy_stencils(st):

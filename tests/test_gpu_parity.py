@@ -299,3 +299,94 @@ def test_full_size_operator_properties(cap_problem):
     a = torch.sum(p2 * k1).item()
     b = torch.sum(p1 * k2).item()
     assert abs(a - b) <= 1e-11 * abs(a)
+
+
+# ------------------------------------------------------------------ multi-mesh batch
+
+
+def _batch_meshes():
+    """Six meshes, one per model, of uneven sizes (several tiles, ragged tails)."""
+    out = []
+    for k, model in enumerate(I.MODELS):
+        n = (9, 23, 17, 31, 12, 26)[k]
+        spec = dict(n=n, model=model, radius=0.4 + 0.2 * k, seed=100 + k)
+        out.append(I.mesh_from_spec(spec, spacing=0.02))
+    return out
+
+
+@pytest.mark.parametrize("precision", [S.SHELL_PREC_FP64, S.SHELL_PREC_MIXED])
+def test_batch_equals_each_mesh_alone(precision):
+    """Each mesh stepped inside a mixed batch equals the same mesh stepped alone (tolerance mode)."""
+    meshes = _batch_meshes()
+    params, _ = S.step_params(1 / 60, max_newton=3, pcg_rtol=1e-6)
+    alone, inbatch = [], []
+    try:
+        for m in meshes:
+            alone.append(S.Problem(m, MAT, precision=precision, block_vertices=128))
+            inbatch.append(S.Problem(m, MAT, precision=precision, block_vertices=128))
+        batch = S.shell_batch_create([pb.sim for pb in inbatch])
+        try:
+            for _ in range(3):
+                rc, bstats = S.shell_batch_step(batch, params, len(meshes))
+                for k, pb in enumerate(alone):
+                    _, st = S.shell_step_implicit(pb.sim, params)
+                    assert bstats[k]["newton_iters"] == st["newton_iters"]
+                    assert np.abs(bstats[k]["counts"] - st["counts"]).max() <= 1
+            tol = 1e-10 if precision == S.SHELL_PREC_FP64 else 1e-4
+            for m, a, b in zip(meshes, alone, inbatch):
+                xa, va, _ = S.shell_sim_get_state(a.sim, m.nv)
+                xb, vb, _ = S.shell_sim_get_state(b.sim, m.nv)
+                assert rel(xb - m.X, xa - m.X) <= tol, m.name
+        finally:
+            S.shell_destroy_batch(batch)
+    finally:
+        for pb in alone + inbatch:
+            pb.close()
+
+
+def test_batch_replay_matches_oracle_per_mesh():
+    """A batch of all six models, per-mesh parameters and replayed counts, against the oracle."""
+    meshes = _batch_meshes()
+    dts = [1 / 60, 1 / 30, 1 / 45, 1 / 60, 1 / 30, 1 / 50]
+    osims = []
+    for m in meshes:
+        ost = oracle_stencils(m.model, m)
+        osims.append(O.Sim(ost, MAT, m.pinned))
+    probs = [S.Problem(m, MAT, block_vertices=64) for m in meshes]
+    batch = S.shell_batch_create([pb.sim for pb in probs])
+    try:
+        for _ in range(2):
+            plist, keep = [], []
+            for k, m in enumerate(meshes):
+                counts, _ = osims[k].step(dts[k], max_newton=2, pcg_rtol=1e-9)
+                p, kp = S.step_params(dts[k], max_newton=2, pcg_rtol=1e-9, replay=counts)
+                plist.append(p)
+                keep.append(kp)
+            S.shell_batch_step(batch, plist, len(meshes))
+        for k, m in enumerate(meshes):
+            x, v, _ = S.shell_sim_get_state(probs[k].sim, m.nv)
+            assert rel(x - m.X, osims[k].x - m.X) <= TOL64, m.name
+            assert rel(v, osims[k].v) <= TOL64, m.name
+    finally:
+        S.shell_destroy_batch(batch)
+        for pb in probs:
+            pb.close()
+
+
+def test_mixed_precision_step_error_against_oracle():
+    """Mixed path, replaying the oracle's counts: per-step displacement error stays within 1e-6 (measured
+    about 5e-8; float32 operators with float64 Newton refinement) on the
+    clamped plate and the cylinder patch."""
+    for mesh, model, dt, newton, rtol in ((I.workload_plate32(), "EP", 1 / 60, 2, 1e-10),
+                                          (I.workload_cylinder(24, "FS"), "FS", 1 / 30, 3, 1e-8)):
+        ost = oracle_stencils(model, mesh)
+        osim = O.Sim(ost, MAT, mesh.pinned)
+        with S.Problem(mesh, MAT, model=model, precision=S.SHELL_PREC_MIXED, block_vertices=128) as pb:
+            for step in range(3):
+                counts, _ = osim.step(dt, max_newton=newton, pcg_rtol=rtol)
+                params, _k = S.step_params(dt, max_newton=newton, pcg_rtol=rtol, replay=counts)
+                S.shell_step_implicit(pb.sim, params)
+                x, _, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+                err = rel(x - mesh.X, osim.x - mesh.X)
+                print(f"{model} mixed step {step}: displacement rel err {err:.2e}")
+                assert err <= 1e-6
