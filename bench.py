@@ -94,6 +94,59 @@ def cpu_baseline(mesh, material, counts_per_step, newton_per_step, budget_s=30.0
                 seconds=dict(force=t_force, newton_overhead=t_newton, pcg_coord_iter=t_iter))
 
 
+def run_batch64(args):
+    """64 meshes (16^2..512^2 vertices, log-uniform, all six models, 1 cm spacing, mixed precision, Newton
+    budget 4, PCG rtol 1e-2, dt = 1/60) stepped as one batch, against the same meshes stepped one at a
+    time.  Prints one JSON line."""
+    import torch
+
+    from paper_2502_10872_amd import inputs as I
+    from paper_2502_10872_amd import shell as S
+
+    specs = I.batch_specs(64)
+    meshes = [I.mesh_from_spec(sp, spacing=0.01) for sp in specs]
+    precision = S.SHELL_PREC_MIXED if args.precision == "mixed" else S.SHELL_PREC_FP64
+    t0 = time.perf_counter()
+    probs = [S.Problem(m, I.MATERIAL, precision=precision) for m in meshes]
+    setup_s = time.perf_counter() - t0
+    nv_total = sum(m.nv for m in meshes)
+    params, _ = S.step_params(1.0 / 60.0, gravity=I.GRAVITY, max_newton=4, max_pcg=args.max_pcg, pcg_rtol=1e-2)
+    batch = S.shell_batch_create([pb.sim for pb in probs])
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        S.shell_batch_step(batch, params, len(probs), stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pcg = 0
+    for k in range(args.steps):
+        rc, st = S.shell_batch_step(batch, params, len(probs), stream=stream)
+        pcg += sum(x["pcg_total"] for x in st)
+        print(f"[bench] batch step {k}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / args.steps
+    S.shell_destroy_batch(batch)
+    # one mesh at a time, same number of steps per mesh
+    t0 = time.perf_counter()
+    for pb in probs:
+        for _ in range(args.steps):
+            S.shell_step_implicit(pb.sim, params, stream=stream)
+    torch.cuda.synchronize()
+    seq_s = (time.perf_counter() - t0) / args.steps
+    for pb in probs:
+        pb.close()
+    out = dict(metric="batched implicit steps/s (64 meshes per step)", value=1.0 / batch_s, unit="batch steps/s",
+               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * batch_s, higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f64" if precision == 0 else "f32+f64", data="synthetic",
+               config=dict(workload="64-mesh batch, sizes 16^2..512^2 log-uniform (seed 2502108724), all six models, "
+                                    "1 cm spacing, dt=1/60 s, Newton budget 4, Jacobi-PCG rtol 0.01",
+                           meshes=len(meshes), vertices=nv_total, precision=args.precision),
+               mesh_steps_per_s=len(meshes) / batch_s, vertex_steps_per_s=nv_total / batch_s,
+               one_at_a_time=dict(mesh_steps_per_s=len(meshes) / seq_s, ms_per_round=1e3 * seq_s),
+               speedup_vs_one_at_a_time=seq_s / batch_s, pcg_coord_iters_per_step=pcg / args.steps,
+               setup_s=setup_s)
+    print(json.dumps(out), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +159,7 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel for the per-kernel timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-pcg", type=int, default=400000, help="PCG iteration cap per coordinate solve")
+    ap.add_argument("--workload", choices=("sphere-cap", "batch64"), default="sphere-cap")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args(argv)
@@ -121,6 +175,10 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "needs a HIP device"
     torch.cuda.set_device(0)
+    if args.workload == "batch64":
+        if args.precision == "fp64" and "--precision" not in " ".join(sys.argv):
+            args.precision = "mixed"
+        return run_batch64(args)
     precision = S.SHELL_PREC_MIXED if args.precision == "mixed" else S.SHELL_PREC_FP64
     mat = I.MATERIAL
     mesh = I.workload_sphere_cap(args.size, "SS")

@@ -218,6 +218,14 @@ shell_status_t shell_sim_device_state(shell_sim_t sim, double** x, double** v);
 shell_status_t shell_batch_create(const shell_sim_t* sims, int32_t n, shell_batch_t* out);
 shell_status_t shell_batch_step(shell_batch_t batch, const shell_step_params_t* params, int32_t nparams,
                                 shell_step_stats_t* stats, shell_stream_t stream);
+/* shell_batch_reset: rebind an existing batch to another set of simulations (continuous batching: members
+ * join and leave between steps); buffers are reused and only grow.  Same rules as shell_batch_create. */
+shell_status_t shell_batch_reset(shell_batch_t batch, const shell_sim_t* sims, int32_t n);
+
+/* shell_sim_device_bytes: device memory held by the simulation's stencils, Hessian and state (host
+ * int64 outputs, each may be NULL); for admission by HBM footprint. */
+shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, int64_t* hessian_bytes,
+                                      int64_t* sim_bytes);
 void shell_destroy_batch(shell_batch_t batch);
 
 /*

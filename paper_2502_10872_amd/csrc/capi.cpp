@@ -171,41 +171,16 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         st->tsrc.upload(til.src.data(), til.src.size(), s);
         const size_t nst = size_t(st->ns_tiled);
         st->tidx.alloc(size_t(k) * nst);
-        st->tB.alloc(size_t(r * k) * nst);
-        st->tk0.alloc(size_t(r) * nst);
+        // only the precision the force kernel streams is kept in the tiled layout
         if (precision == SHELL_PREC_MIXED) {
             st->tBf.alloc(size_t(r * k) * nst);
             st->tk0f.alloc(size_t(r) * nst);
+        } else {
+            st->tB.alloc(size_t(r * k) * nst);
+            st->tk0.alloc(size_t(r) * nst);
         }
         launch_tile_copy(*st, s);
-        st->xin.alloc(size_t(3 * nv));
-        st->fout.alloc(size_t(3 * nv));
         st->epart.alloc(size_t(st->nblocks));
-        {
-            // descriptor and tile items of the caller-order entry point (staging buffers xin/fout)
-            ForceDesc d{};
-            d.x = st->xin.p;
-            d.f = st->fout.p;
-            d.epart = st->epart.p;
-            d.boff = st->boff.p;
-            d.tidx = st->tidx.p;
-            const bool f32 = precision == SHELL_PREC_MIXED;
-            d.tB = f32 ? static_cast<const void*>(st->tBf.p) : static_cast<const void*>(st->tB.p);
-            d.tk0 = f32 ? static_cast<const void*>(st->tk0f.p) : static_cast<const void*>(st->tk0.p);
-            d.nst = st->ns_tiled;
-            d.nv = nv;
-            d.T = T;
-            d.model = model;
-            d.kb = st->kb;
-            d.nu = st->poisson;
-            st->fdesc.alloc(1);
-            st->fdesc.upload(&d, 1, s);
-            std::vector<WorkItem> items(size_t(st->nblocks));
-            for (int64_t t = 0; t < st->nblocks; ++t) items[size_t(t)] = {0, int32_t(t)};
-            st->tile_items.alloc(items.size());
-            st->tile_items.upload(items.data(), items.size(), s);
-            SHELL_HIP(hipStreamSynchronize(s));
-        }
         SHELL_HIP(hipStreamSynchronize(s));
         *out = st.release();
         return SHELL_OK;
@@ -263,6 +238,32 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
         SHELL_CHECK(st && (x || st->nv == 0) && (f || st->nv == 0), SHELL_E_INVALID_ARG, "null argument");
         hipStream_t s = as_stream(stream);
         const bool f32 = st->precision == SHELL_PREC_MIXED;
+        if (st->nv > 0 && !st->fdesc.p) {
+            // caller-order staging, descriptor and tile items, made on first use
+            st->xin.alloc(size_t(3 * st->nv));
+            st->fout.alloc(size_t(3 * st->nv));
+            ForceDesc d{};
+            d.x = st->xin.p;
+            d.f = st->fout.p;
+            d.epart = st->epart.p;
+            d.boff = st->boff.p;
+            d.tidx = st->tidx.p;
+            d.tB = f32 ? static_cast<const void*>(st->tBf.p) : static_cast<const void*>(st->tB.p);
+            d.tk0 = f32 ? static_cast<const void*>(st->tk0f.p) : static_cast<const void*>(st->tk0.p);
+            d.nst = st->ns_tiled;
+            d.nv = st->nv;
+            d.T = st->T;
+            d.model = st->model;
+            d.kb = st->kb;
+            d.nu = st->poisson;
+            std::vector<WorkItem> items(size_t(st->nblocks));
+            for (int64_t t = 0; t < st->nblocks; ++t) items[size_t(t)] = {0, int32_t(t)};
+            st->fdesc.alloc(1);
+            st->tile_items.alloc(items.size());
+            SHELL_HIP(hipMemcpy(st->fdesc.p, &d, sizeof(d), hipMemcpyHostToDevice));
+            SHELL_HIP(hipMemcpy(st->tile_items.p, items.data(), items.size() * sizeof(WorkItem),
+                                hipMemcpyHostToDevice));
+        }
         if (st->nv > 0) {
             launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
             launch_force_items(st->model, st->precision, st->fdesc.p, st->tile_items.p, st->nblocks, st->T, s);
@@ -298,8 +299,6 @@ shell_status_t shell_assemble_constant_hessian(shell_stencils_t st, shell_stream
         h->val.alloc(size_t(P.nslots));
         if (st->precision == SHELL_PREC_MIXED) h->valf.alloc(size_t(P.nslots));
         h->kdiag.alloc(size_t(st->nv));
-        h->pin.alloc(size_t(3 * st->nv));
-        h->qout.alloc(size_t(4 * st->nv));
         launch_assemble(*h, s);
         *out = h.release();
         return SHELL_OK;
@@ -349,6 +348,10 @@ shell_status_t shell_hessian_apply(shell_hessian_t h, const double* mass, double
         const shell_stencils_s& st = *h->st;
         const long nv = st.nv;
         if (!nv) return SHELL_OK;
+        if (!h->pin.p) {  // caller-order staging, made on first use
+            h->pin.alloc(size_t(3 * nv));
+            h->qout.alloc(size_t(4 * nv));
+        }
         double* min = nullptr;
         if (mass) {
             min = h->qout.p + 3 * nv;
@@ -495,7 +498,7 @@ void shell_destroy_hessian(shell_hessian_t h) { delete h; }
 void shell_destroy_sim(shell_sim_t sim) {
     if (!sim) return;
     if (sim->solo) {
-        batch_free_host(*sim->solo);
+        batch_release(*sim->solo);
         delete sim->solo;
     }
     delete sim;
@@ -513,10 +516,55 @@ shell_status_t shell_batch_create(const shell_sim_t* sims, int32_t n, shell_batc
         try {
             batch_init(*b);
         } catch (...) {
-            batch_free_host(*b);
+            batch_release(*b);
             throw;
         }
         *out = b.release();
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_batch_reset(shell_batch_t batch, const shell_sim_t* sims, int32_t n) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(batch && sims && n >= 1, SHELL_E_INVALID_ARG, "bad argument");
+        std::vector<shell_sim_s*> next;
+        for (int32_t m = 0; m < n; ++m) {
+            SHELL_CHECK(sims[m], SHELL_E_INVALID_ARG, "null simulation");
+            next.push_back(sims[m]);
+        }
+        std::swap(batch->sims, next);
+        try {
+            batch_init(*batch);
+        } catch (...) {
+            std::swap(batch->sims, next);
+            throw;
+        }
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, int64_t* hessian_bytes,
+                                      int64_t* sim_bytes) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim, SHELL_E_INVALID_ARG, "null handle");
+        const shell_stencils_s& st = *sim->st;
+        const shell_hessian_s& h = *sim->h;
+        int64_t a = 0, b = 0, c = 0;
+        for (size_t v : {st.X.bytes(), st.tris.bytes(), st.perm_d.bytes(), st.idx.bytes(), st.B.bytes(),
+                         st.k0.bytes(), st.flags.bytes(), st.boff.bytes(), st.tsrc.bytes(), st.tidx.bytes(),
+                         st.tB.bytes(), st.tk0.bytes(), st.tBf.bytes(), st.tk0f.bytes(), st.xin.bytes(),
+                         st.fout.bytes(), st.epart.bytes(), st.fdesc.bytes(), st.tile_items.bytes()})
+            a += int64_t(v);
+        for (size_t v : {h.scol.bytes(), h.width.bytes(), h.sptr.bytes(), h.rowlen.bytes(), h.val.bytes(),
+                         h.valf.bytes(), h.kdiag.bytes(), h.pin.bytes(), h.qout.bytes()})
+            b += int64_t(v);
+        for (size_t v : {sim->x.bytes(), sim->v.bytes(), sim->xt.bytes(), sim->xhat.bytes(), sim->g.bytes(),
+                         sim->mass.bytes(), sim->y.bytes(), sim->r.bytes(), sim->f.bytes(), sim->dinv.bytes(),
+                         sim->pinned.bytes(), sim->z.bytes(), sim->p.bytes(), sim->q.bytes(), sim->partials.bytes()})
+            c += int64_t(v);
+        if (stencil_bytes) *stencil_bytes = a;
+        if (hessian_bytes) *hessian_bytes = b;
+        if (sim_bytes) *sim_bytes = c;
         return SHELL_OK;
     });
 }
@@ -537,7 +585,7 @@ shell_status_t shell_batch_step(shell_batch_t batch, const shell_step_params_t* 
 
 void shell_destroy_batch(shell_batch_t batch) {
     if (!batch) return;
-    batch_free_host(*batch);
+    batch_release(*batch);
     delete batch;
 }
 

@@ -224,12 +224,15 @@ struct shell_batch_s {
     std::vector<shell_sim_s*> sims;
     int precision = 0;
     int max_T = 0;
+    size_t capacity = 0;                     // meshes the descriptor buffers hold
+    bool fdesc_dirty = true;
     shell::DevArray<shell::ForceDesc> fdesc;
     shell::DevArray<shell::SolveDesc> sdesc;
     shell::DevArray<shell::PcgState> state;
     shell::PcgState* state_host = nullptr;
     shell::SolveDesc* sdesc_host = nullptr;  // pinned staging
-    shell::WorkItem* items_host = nullptr;   // pinned staging
+    shell::ForceDesc* fdesc_host = nullptr;
+    shell::WorkItem* items_host = nullptr;
     int32_t* mlist_host = nullptr;
     size_t items_cap = 0;
     shell::DevArray<shell::WorkItem> items;   // [rows | tiles of each model]
@@ -255,6 +258,7 @@ void launch_apply(const shell_hessian_s& h, const double* mass, double dt2, cons
 void sim_alloc(shell_sim_s& sim);
 void batch_init(shell_batch_s& b);
 void batch_free_host(shell_batch_s& b);
+void batch_release(shell_batch_s& b);
 shell_status_t batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams, shell_step_stats_t* stats,
                           hipStream_t s);
 void batch_time_kernels(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out, hipStream_t s);

@@ -214,12 +214,12 @@ __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_
     for (int j = 0; j < k; ++j) tidx[j * nt + e] = idx[j * ns + s];
     for (int q = 0; q < r * k; ++q) {
         double v = B[q * ns + s];
-        tB[q * nt + e] = v;
+        if (tB) tB[q * nt + e] = v;
         if (tBf) tBf[q * nt + e] = float(v);
     }
     for (int q = 0; q < r; ++q) {
         double v = k0[q * ns + s];
-        tk0[q * nt + e] = v;
+        if (tk0) tk0[q * nt + e] = v;
         if (tk0f) tk0f[q * nt + e] = float(v);
     }
 }

@@ -394,10 +394,6 @@ Launch upload(shell_batch_s& b, const ItemBuilder& ib, hipStream_t s) {
         SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.items_host), b.items_cap * sizeof(WorkItem)));
         b.items.alloc(b.items_cap);
     }
-    if (!b.mlist_host) {
-        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.mlist_host), (b.sims.size() + 1) * sizeof(int32_t)));
-        b.mlist.alloc(b.sims.size() + 1);
-    }
     Launch L{};
     std::copy(ib.rows.begin(), ib.rows.end(), b.items_host);
     L.rows = b.items.p;
@@ -496,6 +492,11 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
     const int n = int(b.sims.size());
     std::vector<MeshStep> ms(static_cast<size_t>(n));
     SHELL_HIP(hipStreamSynchronize(s));  // the descriptor staging is reused below
+    if (b.fdesc_dirty) {
+        for (int m = 0; m < n; ++m) b.fdesc_host[m] = force_desc(*b.sims[size_t(m)]);
+        SHELL_HIP(hipMemcpyAsync(b.fdesc.p, b.fdesc_host, size_t(n) * sizeof(ForceDesc), hipMemcpyHostToDevice, s));
+        b.fdesc_dirty = false;
+    }
     for (int m = 0; m < n; ++m) {
         MeshStep& st = ms[size_t(m)];
         st.prm = &prms[nparams == 1 ? 0 : m];
@@ -634,6 +635,11 @@ template <typename VR, typename MR>
 void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {
     shell_sim_s& sim = *b.sims[0];
     SHELL_HIP(hipStreamSynchronize(s));
+    if (b.fdesc_dirty) {
+        b.fdesc_host[0] = force_desc(sim);
+        SHELL_HIP(hipMemcpyAsync(b.fdesc.p, b.fdesc_host, sizeof(ForceDesc), hipMemcpyHostToDevice, s));
+        b.fdesc_dirty = false;
+    }
     SolveDesc d = solve_desc(sim, b.state.p);
     d.dt = dt;
     d.dt2 = dt * dt;
@@ -705,39 +711,48 @@ void sim_mass(shell_sim_s& sim, hipStream_t s) {
     SHELL_HIP(hipGetLastError());
 }
 
+// (Re)binds a batch to its member simulations.  Buffers only grow; the force descriptors are staged on
+// the host and uploaded on the stream of the next step, so this makes no device-wide synchronisation.
 void batch_init(shell_batch_s& b) {
     const size_t n = b.sims.size();
     SHELL_CHECK(n > 0, SHELL_E_INVALID_ARG, "empty batch");
     b.precision = b.sims[0]->st->precision;
     b.max_T = 64;
-    std::vector<ForceDesc> fd(n);
     for (size_t m = 0; m < n; ++m) {
         SHELL_CHECK(b.sims[m]->st->precision == b.precision, SHELL_E_INVALID_ARG,
                     "all simulations of a batch need the same precision");
         for (size_t q = 0; q < m; ++q)
             SHELL_CHECK(b.sims[q] != b.sims[m], SHELL_E_INVALID_ARG, "a simulation appears twice in a batch");
         b.max_T = std::max(b.max_T, b.sims[m]->st->T);
-        fd[m] = force_desc(*b.sims[m]);
     }
-    b.fdesc.alloc(n);
-    b.fdesc.upload(fd.data(), n, nullptr);
-    b.sdesc.alloc(n);
-    b.state.alloc(n);
-    SHELL_HIP(hipMemset(b.state.p, 0, n * sizeof(PcgState)));
-    SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.state_host), n * sizeof(PcgState)));
-    SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.sdesc_host), n * sizeof(SolveDesc)));
-    SHELL_HIP(hipDeviceSynchronize());
+    if (n > b.capacity) {
+        batch_free_host(b);
+        b.capacity = std::max<size_t>(n, 2 * b.capacity);
+        b.fdesc.alloc(b.capacity);
+        b.sdesc.alloc(b.capacity);
+        b.state.alloc(b.capacity);
+        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.state_host), b.capacity * sizeof(PcgState)));
+        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.sdesc_host), b.capacity * sizeof(SolveDesc)));
+        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.fdesc_host), b.capacity * sizeof(ForceDesc)));
+        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.mlist_host), (b.capacity + 1) * sizeof(int32_t)));
+        b.mlist.alloc(b.capacity + 1);
+    }
+    b.fdesc_dirty = true;
 }
 
 void batch_free_host(shell_batch_s& b) {
-    if (b.state_host) (void)hipHostFree(b.state_host);
-    if (b.sdesc_host) (void)hipHostFree(b.sdesc_host);
+    for (void** p : {reinterpret_cast<void**>(&b.state_host), reinterpret_cast<void**>(&b.sdesc_host),
+                     reinterpret_cast<void**>(&b.fdesc_host), reinterpret_cast<void**>(&b.mlist_host)}) {
+        if (*p) (void)hipHostFree(*p);
+        *p = nullptr;
+    }
+}
+
+void batch_release(shell_batch_s& b) {
+    batch_free_host(b);
     if (b.items_host) (void)hipHostFree(b.items_host);
-    if (b.mlist_host) (void)hipHostFree(b.mlist_host);
-    b.state_host = nullptr;
-    b.sdesc_host = nullptr;
     b.items_host = nullptr;
-    b.mlist_host = nullptr;
+    b.items_cap = 0;
 }
 
 shell_status_t batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams, shell_step_stats_t* stats,

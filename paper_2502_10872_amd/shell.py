@@ -69,6 +69,7 @@ EXPORTS = ("shell_build_stencils", "shell_stencils_info", "shell_stencils_export
            "shell_assemble_constant_hessian", "shell_hessian_export_csr", "shell_hessian_apply", "shell_sim_create",
            "shell_step_implicit", "shell_sim_get_stats", "shell_sim_get_state", "shell_sim_set_state",
            "shell_sim_device_state", "shell_sim_time_kernels", "shell_batch_create", "shell_batch_step",
+           "shell_batch_reset", "shell_sim_device_bytes",
            "shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim", "shell_destroy_batch",
            "shell_status_string", "shell_last_error")
 
@@ -99,6 +100,8 @@ def lib() -> ctypes.CDLL:
         L.shell_sim_time_kernels.argtypes = [P, d, i32, P, P]
         L.shell_batch_create.argtypes = [P, i32, P]
         L.shell_batch_step.argtypes = [P, P, i32, P, P]
+        L.shell_batch_reset.argtypes = [P, P, i32]
+        L.shell_sim_device_bytes.argtypes = [P, P, P, P]
         for name in ("shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim", "shell_destroy_batch"):
             getattr(L, name).argtypes = [P]
             getattr(L, name).restype = None
@@ -299,6 +302,18 @@ def shell_batch_step(batch, params, n, with_stats=True, stream=None):
     rc = lib().shell_batch_step(batch, parr, len(plist), stats if with_stats else None, _stream(stream))
     _check(rc, "shell_batch_step", allow=(SHELL_OK, SHELL_E_BUDGET))
     return rc, ([stats_dict(stats[m]) for m in range(n)] if with_stats else None)
+
+
+def shell_batch_reset(batch, sims):
+    arr = (ctypes.c_void_p * len(sims))(*sims)
+    _check(lib().shell_batch_reset(batch, arr, len(sims)), "shell_batch_reset")
+
+
+def shell_sim_device_bytes(sim) -> int:
+    a, b, c = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().shell_sim_device_bytes(sim, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "shell_sim_device_bytes")
+    return a.value + b.value + c.value
 
 
 def shell_destroy_batch(batch):
