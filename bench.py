@@ -26,23 +26,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def algorithmic_bytes(info: dict, nnz: int, precision: int) -> dict:
-    """Bytes each kernel must move once (no re-reads): per-stencil streams, vertex in/out, matrix."""
+def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
+    """Bytes each kernel must move once (no re-reads, no SELL padding), per launch.
+
+    force:  per stencil its k vertex ids, r x k operator and (shells) r rest curvatures; per vertex the
+            position read and the force written.
+    spmv:   (the product kernel, which also forms the new direction p = D^-1 r + beta p_old) every
+            nonzero's value and 16-bit local column id, each row group's distinct-column list, slice
+            widths and offsets, and per vertex r, D^-1, p_old read, mass and fixed flag read, p and q
+            written.
+    update: per vertex p, q, y, r, D^-1 read, y and r written."""
     nv, ns, k, r = info["nv"], info["ns"], info["k"], info["r"]
     shell = info["model"] in (1, 3, 5)
-    real = 4 if precision == 1 else 8
-    force_out = 4 if precision == 1 else 8
+    real = 4 if precision == 1 else 8  # stencil operators, matrix values, p, q, D^-1, forces
     per_stencil = 4 * k + real * r * k + (real * r if shell else 0)
-    force = ns * per_stencil + nv * (24 + 3 * force_out)
-    vec = 4 if precision == 1 else 8
-    # SpMV: values + column ids, own p read, q write, mass, pinned flag
-    spmv = nnz * (real + 4) + nv * (3 * vec + 3 * vec + 8 + 1)
-    return dict(force=force, spmv=spmv, force_per_stencil=per_stencil)
+    force = ns * per_stencil + nv * (24 + 3 * real)
+    ngroups = (nv + 255) // 256
+    idx = 2 if hinfo["staged"] else 4
+    spmv = (hinfo["nnz"] * (real + idx) + 4 * (hinfo["group_cols"] + ngroups + 1) + 12 * hinfo["nslices"]
+            + nv * (24 + real + 3 * real + 8 + 1 + 3 * real + 3 * real))
+    update = nv * (3 * real + 3 * real + 24 + 24 + real + 24 + 24)
+    return dict(force=force, spmv=spmv, update=update, force_per_stencil=per_stencil)
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_cap_1024_ss_fp64_hbm_traffic.md")
 TRAFFIC_SOURCES = ["paper_2502_10872_amd/csrc/spmv.hpp", "paper_2502_10872_amd/csrc/solver.hip",
-                   "paper_2502_10872_amd/csrc/forces.hip", "paper_2502_10872_amd/csrc/host_mesh.cpp"]
+                   "paper_2502_10872_amd/csrc/forces.hip", "paper_2502_10872_amd/csrc/host_mesh.cpp",
+                   "paper_2502_10872_amd/csrc/devmath.hpp"]
 
 
 def measured_traffic(key: str):
@@ -156,7 +166,9 @@ def main(argv=None):
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--max-newton", type=int, default=4)
     ap.add_argument("--pcg-rtol", type=float, default=1e-2)
-    ap.add_argument("--reps", type=int, default=20, help="launches per kernel for the per-kernel timing")
+    ap.add_argument("--reps", type=int, default=20, help="launches per kernel of the isolated back-to-back timing")
+    ap.add_argument("--sample-every", type=int, default=16,
+                    help="in the timed steps, time every n-th PCG iteration's kernels with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-pcg", type=int, default=400000, help="PCG iteration cap per coordinate solve")
     ap.add_argument("--workload", choices=("sphere-cap", "batch64"), default="sphere-cap")
@@ -187,7 +199,7 @@ def main(argv=None):
     pb = S.Problem(mesh, mat, precision=precision)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    rp_nnz = _nnz(S, pb.h)
+    rp_nnz = S.shell_hessian_info(pb.h)["nnz"]
     dt = 1.0 / 30.0
     params, _ = S.step_params(dt, gravity=I.GRAVITY, max_newton=args.max_newton, max_pcg=args.max_pcg,
                               newton_rtol=1e-8, pcg_rtol=args.pcg_rtol)
@@ -199,6 +211,9 @@ def main(argv=None):
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     stats = []
+    # kernel durations inside the timed steps: HIP events on the library's launch stream around every
+    # force launch set and every n-th PCG iteration's kernels
+    S.shell_sim_profile(pb.sim, args.sample_every)
     t_start = time.perf_counter()
     ev0.record(stream)
     for k in range(args.steps):
@@ -212,7 +227,11 @@ def main(argv=None):
     gpu_ms = ev0.elapsed_time(ev1)
     elapsed = max(wall, gpu_ms / 1e3)
     steps_per_s = args.steps / elapsed
+    prof = S.shell_sim_profile_read(pb.sim)
+    S.shell_sim_profile(pb.sim, 0)
 
+    # the same kernels launched back to back on one state (their working set then partly stays in the
+    # 256 MB last-level cache, so these read faster than the in-step figures; reported for reference)
     kt = S.shell_sim_time_kernels(pb.sim, dt, reps=args.reps, stream=stream)
     if args.calibrate_copy:
         a = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
@@ -221,12 +240,22 @@ def main(argv=None):
             torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         del a, b
-    ab = algorithmic_bytes(pb.info, rp_nnz, precision)
-    spmv_gbs = ab["spmv"] / (kt["spmv_ms"] * 1e-3) / 1e9
-    force_gbs = ab["force"] / (kt["force_ms"] * 1e-3) / 1e9
-    stencils_per_s = pb.info["ns"] / (kt["force_ms"] * 1e-3)
+    hinfo = S.shell_hessian_info(pb.h)
+    ab = algorithmic_bytes(pb.info, hinfo, precision)
+
+    def rate(nbytes, ms):
+        return nbytes / (ms * 1e-3) / 1e9 if ms else None
+
+    spmv_ms = prof["product"]["avg_ms"]
+    update_ms = prof["update"]["avg_ms"]
+    force_ms = prof["forces"]["avg_ms"]
+    spmv_gbs = rate(ab["spmv"], spmv_ms)
+    update_gbs = rate(ab["update"], update_ms)
+    force_gbs = rate(ab["force"], force_ms)
+    stencils_per_s = pb.info["ns"] / (force_ms * 1e-3) if force_ms else None
     default_workload = args.size == 1024 and precision == S.SHELL_PREC_FP64
     traffic_spmv = measured_traffic("spmv_traffic_bytes_per_launch") if default_workload else None
+    traffic_update = measured_traffic("update_traffic_bytes_per_launch") if default_workload else None
     traffic_force = measured_traffic("force_traffic_bytes_per_launch") if default_workload else None
     pcg_per_step = float(np.mean([s["pcg_total"] for s in stats]))
     newton_per_step = float(np.mean([s["newton_iters"] for s in stats]))
@@ -241,13 +270,22 @@ def main(argv=None):
                              f"Newton budget {args.max_newton}, Jacobi-PCG rtol {args.pcg_rtol:g}",
                     nv=mesh.nv, stencils=pb.info["ns"], nnz=rp_nnz, precision=args.precision,
                     parallelism="single GPU"),
-        roofline=dict(bound="hbm", kernel="pcg_spmv (3-column SELL-64 product)", achieved=spmv_gbs,
-                      peak=HBM_PEAK_GBS, unit="GB/s", frac=spmv_gbs / HBM_PEAK_GBS, traffic=traffic_spmv,
-                      bytes_per_launch=ab["spmv"], avg_ms=kt["spmv_ms"]),
-        force_kernel=dict(stencils_per_s=stencils_per_s, achieved_gbs=force_gbs, frac=force_gbs / HBM_PEAK_GBS,
-                          bytes_per_launch=ab["force"], bytes_per_stencil_stream=ab["force_per_stencil"],
-                          avg_ms=kt["force_ms"], traffic=traffic_force),
-        pcg_kernels_ms=dict(spmv=kt["spmv_ms"], update=kt["update_ms"], direction=kt["direction_ms"]),
+        roofline=dict(bound="hbm", kernel="k_pcg_spmv (direction update + 3-column SELL-64 product)",
+                      achieved=spmv_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=spmv_gbs / HBM_PEAK_GBS if spmv_gbs else None, traffic=traffic_spmv,
+                      bytes_per_launch=ab["spmv"], avg_ms=spmv_ms, sampled_launches=prof["product"]["count"]),
+        update_kernel=dict(kernel="k_pcg_update", achieved_gbs=update_gbs,
+                           frac=update_gbs / HBM_PEAK_GBS if update_gbs else None, bytes_per_launch=ab["update"],
+                           avg_ms=update_ms, traffic=traffic_update),
+        force_kernel=dict(kernel="force_tiles", stencils_per_s=stencils_per_s, achieved_gbs=force_gbs,
+                          frac=force_gbs / HBM_PEAK_GBS if force_gbs else None, bytes_per_launch=ab["force"],
+                          bytes_per_stencil_stream=ab["force_per_stencil"], avg_ms=force_ms, traffic=traffic_force,
+                          sampled_launches=prof["forces"]["count"]),
+        pcg_iteration_ms=dict(product=spmv_ms, update=update_ms,
+                              finalizers=(2 * prof["finalize"]["avg_ms"]) if prof["finalize"]["avg_ms"] else None),
+        isolated_back_to_back_ms=dict(force=kt["force_ms"], product=kt["spmv_ms"], update=kt["update_ms"]),
+        hessian=dict(nnz=hinfo["nnz"], slots=hinfo["slots"], group_cols=hinfo["group_cols"],
+                     max_group_cols=hinfo["max_group_cols"], staged=bool(hinfo["staged"])),
         per_step=dict(newton_iters=newton_per_step, pcg_coord_iters=pcg_per_step,
                       grad_ratio=[s["grad_norm"] / max(s["grad_norm0"], 1e-300) for s in stats]),
         setup_s=setup_s,
@@ -259,14 +297,6 @@ def main(argv=None):
         out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)
     pb.close()
     print(json.dumps(out), flush=True)
-
-
-def _nnz(S, h):
-    import ctypes
-
-    nnz = ctypes.c_int64(0)
-    S._check(S.lib().shell_hessian_export_csr(h, ctypes.byref(nnz), None, None, None), "nnz")
-    return nnz.value
 
 
 if __name__ == "__main__":

@@ -69,8 +69,13 @@ typedef struct {
     int32_t block_vertices;  /* vertices per force work-group tile, 64..4096; 0 selects the default (2048) */
     int32_t reorder;         /* internal vertex order: 1 (default) recursive coordinate bisection into compact
                                 tiles of block_vertices, 2 Morton order, 0 the caller's order */
-    int32_t reserved;
+    int32_t flags;           /* 0, or SHELL_FLAG_DIRECT_PRODUCT */
 } shell_config_t;
+
+/* The PCG product gathers each neighbour's entries straight from memory instead of staging every 256-row
+ * group's distinct columns in LDS.  Chosen by itself when a group has more than 4096 distinct columns;
+ * the flag forces it (to compare the two forms). */
+#define SHELL_FLAG_DIRECT_PRODUCT 1
 
 typedef struct shell_stencils_s* shell_stencils_t;
 typedef struct shell_hessian_s* shell_hessian_t;
@@ -142,6 +147,24 @@ shell_status_t shell_assemble_constant_hessian(shell_stencils_t st, shell_stream
  * Call with col == val == NULL to get nnz; rowptr is [nv+1] and may be NULL in that call.
  */
 shell_status_t shell_hessian_export_csr(shell_hessian_t h, int64_t* nnz, int64_t* rowptr, int32_t* col, double* val);
+
+/*
+ * shell_hessian_info - storage figures of the assembled K_s (for byte models and inspection).
+ * SELL-64 stores 64-row slices padded to the slice's longest row; rows are grouped 256 at a time and,
+ * when every group's distinct column set fits in LDS (max_group_cols <= 4096), the product stages
+ * each group's p entries once and stores 16-bit group-local column ids (staged == 1).
+ */
+typedef struct {
+    int64_t nv;              /* rows */
+    int64_t nnz;             /* structural nonzeros */
+    int64_t slots;           /* stored SELL-64 entries, padding included */
+    int64_t nslices;         /* 64-row slices */
+    int64_t group_cols;      /* sum over the 256-row groups of their distinct column counts (0 unless staged) */
+    int32_t max_group_cols;  /* largest distinct column count of a group */
+    int32_t staged;          /* 1: staged product with 16-bit local ids; 0: direct gathers, 32-bit ids */
+} shell_hessian_info_t;
+
+shell_status_t shell_hessian_info(shell_hessian_t h, shell_hessian_info_t* info);
 
 /*
  * shell_hessian_apply - q = diag(mass) p + dt2 (K_s (x) I3) p, the operator of the implicit step.
@@ -236,15 +259,41 @@ void shell_destroy_batch(shell_batch_t batch);
  */
 typedef struct {
     double force_ms;      /* bending force kernel over all stencils (internal vertex order) */
-    double spmv_ms;       /* PCG product q = (M + dt^2 K_s) p for the three coordinates */
-    double update_ms;     /* PCG y/r/z update with its dot products */
-    double direction_ms;  /* PCG search-direction update */
+    double spmv_ms;       /* PCG direction update p = D^-1 r + beta p and product q = (M + dt^2 K_s) p */
+    double update_ms;     /* PCG y/r update with its dot products */
+    double direction_ms;  /* always 0: the direction update is part of the product kernel */
     int32_t reps;
     int32_t reserved;
 } shell_kernel_times_t;
 
 shell_status_t shell_sim_time_kernels(shell_sim_t sim, double dt, int32_t reps, shell_kernel_times_t* out,
                                       shell_stream_t stream);
+
+/*
+ * Sampled kernel timing inside real steps.  With sampling on, every step of the batch (or simulation)
+ * records HIP events on its stream around every force launch set and around every `every`-th PCG
+ * iteration's four kernels, and sums the sampled durations per phase; the events are read at the
+ * step's existing host synchronisations, so the step's launches and results are unchanged.
+ *   shell_batch_profile(b, every)  every > 0: start sampling and clear the sums; every == 0: stop.
+ *   shell_batch_profile_read(b, out)  copy the sums (sampling continues).
+ * The simulation forms act on a simulation's own one-member batch.
+ */
+enum {
+    SHELL_PHASE_FORCES = 0,   /* force kernels of one Newton iteration (all tiles of all models) */
+    SHELL_PHASE_PRODUCT = 1,  /* PCG direction update + sparse product */
+    SHELL_PHASE_UPDATE = 2,   /* PCG y/r update */
+    SHELL_PHASE_FINALIZE = 3, /* the two per-mesh reduction finalizers of a PCG iteration (each launch) */
+    SHELL_NUM_PHASES = 4
+};
+typedef struct {
+    double ms[SHELL_NUM_PHASES];     /* summed durations of the sampled launches, milliseconds */
+    int64_t count[SHELL_NUM_PHASES]; /* number of sampled launches */
+} shell_profile_t;
+
+shell_status_t shell_batch_profile(shell_batch_t batch, int32_t every);
+shell_status_t shell_batch_profile_read(shell_batch_t batch, shell_profile_t* out);
+shell_status_t shell_sim_profile(shell_sim_t sim, int32_t every);
+shell_status_t shell_sim_profile_read(shell_sim_t sim, shell_profile_t* out);
 
 void shell_destroy_stencils(shell_stencils_t st);
 void shell_destroy_hessian(shell_hessian_t h);

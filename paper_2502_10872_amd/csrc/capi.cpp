@@ -95,6 +95,8 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         SHELL_CHECK(T >= 64 && T <= 4096, SHELL_E_INVALID_ARG, "block_vertices must be in [64, 4096]");
         int reorder = cfg ? cfg->reorder : 1;
         SHELL_CHECK(reorder >= 0 && reorder <= 2, SHELL_E_INVALID_ARG, "unknown vertex order");
+        const int cfg_flags = cfg ? cfg->flags : 0;
+        SHELL_CHECK((cfg_flags & ~SHELL_FLAG_DIRECT_PRODUCT) == 0, SHELL_E_INVALID_ARG, "unknown flag");
         hipStream_t s = as_stream(stream);
 
         auto st = std::make_unique<shell_stencils_s>();
@@ -105,6 +107,7 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         st->nv = nv;
         st->nt = nt;
         st->T = T;
+        st->cfg_flags = cfg_flags;
         st->young = mat->young;
         st->poisson = mat->poisson;
         st->thickness = mat->thickness;
@@ -286,7 +289,8 @@ shell_status_t shell_assemble_constant_hessian(shell_stencils_t st, shell_stream
         hipStream_t s = as_stream(stream);
         auto h = std::make_unique<shell_hessian_s>();
         h->st = st;
-        h->pat = build_sell_pattern(st->h_idx, st->k, st->ns, st->nv);
+        h->pat = build_sell_pattern(st->h_idx, st->k, st->ns, st->nv,
+                                    (st->cfg_flags & SHELL_FLAG_DIRECT_PRODUCT) == 0);
         const auto& P = h->pat;
         h->scol.alloc(size_t(P.nslots));
         h->scol.upload(P.scol.data(), size_t(P.nslots), s);
@@ -296,11 +300,35 @@ shell_status_t shell_assemble_constant_hessian(shell_stencils_t st, shell_stream
         h->sptr.upload(P.sptr.data(), size_t(P.nslices + 1), s);
         h->rowlen.alloc(size_t(st->nv));
         h->rowlen.upload(P.rowlen.data(), size_t(st->nv), s);
+        if (!P.gptr.empty()) {
+            h->gptr.alloc(P.gptr.size());
+            h->gptr.upload(P.gptr.data(), P.gptr.size(), s);
+            h->gcols.alloc(P.gcols.size());
+            h->gcols.upload(P.gcols.data(), P.gcols.size(), s);
+            h->lcol.alloc(P.lcol.size());
+            h->lcol.upload(P.lcol.data(), P.lcol.size(), s);
+        }
         h->val.alloc(size_t(P.nslots));
         if (st->precision == SHELL_PREC_MIXED) h->valf.alloc(size_t(P.nslots));
         h->kdiag.alloc(size_t(st->nv));
         launch_assemble(*h, s);
         *out = h.release();
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_hessian_info(shell_hessian_t h, shell_hessian_info_t* info) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(h && info, SHELL_E_INVALID_ARG, "null argument");
+        const auto& P = h->pat;
+        std::memset(info, 0, sizeof(*info));
+        info->nv = P.nv;
+        info->nnz = P.nnz;
+        info->slots = P.nslots;
+        info->nslices = P.nslices;
+        info->staged = h->gptr.n > 0 ? 1 : 0;
+        info->group_cols = info->staged ? int64_t(P.gcols.size()) : 0;
+        info->max_group_cols = P.max_gcols;
         return SHELL_OK;
     });
 }
@@ -493,6 +521,59 @@ shell_status_t shell_sim_time_kernels(shell_sim_t sim, double dt, int32_t reps, 
     });
 }
 
+namespace {
+void profile_set(shell_batch_s& b, int32_t every) {
+    if (every == 0) {
+        b.prof.reset();
+        return;
+    }
+    if (!b.prof) b.prof = std::make_unique<shell::StepProfiler>();
+    b.prof->every = every;
+    b.prof->reset();
+}
+
+void profile_read(const shell_batch_s* b, shell_profile_t* out) {
+    std::memset(out, 0, sizeof(*out));
+    if (!b || !b->prof) return;
+    for (int k = 0; k < SHELL_NUM_PHASES; ++k) {
+        out->ms[k] = b->prof->ms[k];
+        out->count[k] = b->prof->count[k];
+    }
+}
+}  // namespace
+
+shell_status_t shell_batch_profile(shell_batch_t batch, int32_t every) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(batch && every >= 0, SHELL_E_INVALID_ARG, "bad argument");
+        profile_set(*batch, every);
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_batch_profile_read(shell_batch_t batch, shell_profile_t* out) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(batch && out, SHELL_E_INVALID_ARG, "bad argument");
+        profile_read(batch, out);
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_profile(shell_sim_t sim, int32_t every) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim && every >= 0, SHELL_E_INVALID_ARG, "bad argument");
+        if (sim->solo) profile_set(*sim->solo, every);
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_profile_read(shell_sim_t sim, shell_profile_t* out) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim && out, SHELL_E_INVALID_ARG, "bad argument");
+        profile_read(sim->solo, out);
+        return SHELL_OK;
+    });
+}
+
 void shell_destroy_stencils(shell_stencils_t st) { delete st; }
 void shell_destroy_hessian(shell_hessian_t h) { delete h; }
 void shell_destroy_sim(shell_sim_t sim) {
@@ -556,11 +637,12 @@ shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, i
                          st.fout.bytes(), st.epart.bytes(), st.fdesc.bytes(), st.tile_items.bytes()})
             a += int64_t(v);
         for (size_t v : {h.scol.bytes(), h.width.bytes(), h.sptr.bytes(), h.rowlen.bytes(), h.val.bytes(),
-                         h.valf.bytes(), h.kdiag.bytes(), h.pin.bytes(), h.qout.bytes()})
+                         h.valf.bytes(), h.kdiag.bytes(), h.pin.bytes(), h.qout.bytes(), h.gptr.bytes(),
+                         h.gcols.bytes(), h.lcol.bytes()})
             b += int64_t(v);
         for (size_t v : {sim->x.bytes(), sim->v.bytes(), sim->xt.bytes(), sim->xhat.bytes(), sim->g.bytes(),
                          sim->mass.bytes(), sim->y.bytes(), sim->r.bytes(), sim->f.bytes(), sim->dinv.bytes(),
-                         sim->pinned.bytes(), sim->z.bytes(), sim->p.bytes(), sim->q.bytes(), sim->partials.bytes()})
+                         sim->pinned.bytes(), sim->p.bytes(), sim->p2.bytes(), sim->q.bytes(), sim->partials.bytes()})
             c += int64_t(v);
         if (stencil_bytes) *stencil_bytes = a;
         if (hessian_bytes) *hessian_bytes = b;

@@ -58,6 +58,16 @@ __device__ __forceinline__ V3<double> load3(const double* p, long i) {
     return {p[3 * i], p[3 * i + 1], p[3 * i + 2]};
 }
 
+// Pointers read out of a descriptor in memory are generic (flat) to the compiler.  Casting them to the
+// global address space gives global loads and stores, which count on the vector-memory counter only,
+// so LDS traffic and memory loads in flight no longer wait on each other.
+template <typename T>
+using gbl = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gbl<T>* G(T* p) {
+    return (gbl<T>*)p;
+}
+
 // MI355X dispatches consecutive work-groups round-robin over its 8 XCDs, each with a private L2.
 // Remap so that XCD x processes one contiguous range of logical work-groups (neighbouring vertices
 // and stencils then share an L2).  The grid must be launched with xcd_grid(n) work-groups; logical

@@ -82,13 +82,23 @@ __global__ void to_float(const double* __restrict__ a, float* __restrict__ b, lo
 
 // q = diag(mass) p + dt2 K_s p over 3 columns (caller order handled by the host wrapper)
 __global__ void apply_sell(const int32_t* __restrict__ scol, const double* __restrict__ val,
-                           const int64_t* __restrict__ sptr, const int32_t* __restrict__ width, long nv,
-                           const double* __restrict__ mass, double dt2, const double* __restrict__ p,
-                           double* __restrict__ q) {
+                           const int64_t* __restrict__ sptr, const int32_t* __restrict__ width,
+                           const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcols,
+                           const uint16_t* __restrict__ lcol, long nv, const double* __restrict__ mass, double dt2,
+                           const double* __restrict__ p, double* __restrict__ q) {
     long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    extern __shared__ unsigned char smem_raw[];
+    double* ps = reinterpret_cast<double*>(smem_raw);
+    if (gptr) {
+        stage_group_columns<double>(gptr, gcols, blockIdx.x, p, ps);
+        __syncthreads();
+    }
     if (i >= nv) return;
     double ax, ay, az;
-    sell_row_product<double, double>(scol, val, sptr, width, i, p, ax, ay, az);
+    if (gptr)
+        sell_row_product_staged<double, double>(lcol, val, sptr, width, i, ps, ax, ay, az);
+    else
+        sell_row_product<double, double>(scol, val, sptr, width, i, p, ax, ay, az);
     double m = mass ? mass[i] : 0.0;
     q[3 * i] = fma(m, p[3 * i], dt2 * ax);
     q[3 * i + 1] = fma(m, p[3 * i + 1], dt2 * ay);
@@ -139,7 +149,10 @@ void launch_apply(const shell_hessian_s& h, const double* mass, double dt2, cons
                   hipStream_t s) {
     const long nv = h.pat.nv;
     if (!nv) return;
-    apply_sell<<<(nv + 255) / 256, 256, 0, s>>>(h.scol.p, h.val.p, h.sptr.p, h.width.p, nv, mass, dt2, p, q);
+    size_t lds = h.gptr.p ? size_t(h.pat.max_gcols) * 3 * sizeof(double) : 0;
+    apply_sell<<<(nv + kRowGroup - 1) / kRowGroup, kRowGroup, lds, s>>>(h.scol.p, h.val.p, h.sptr.p, h.width.p,
+                                                                      h.gptr.p, h.gcols.p, h.lcol.p, nv, mass, dt2,
+                                                                      p, q);
     SHELL_HIP(hipGetLastError());
 }
 

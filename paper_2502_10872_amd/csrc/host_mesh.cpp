@@ -193,7 +193,7 @@ Tiling build_tiling(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t 
     return t;
 }
 
-SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv) {
+SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv, bool staging) {
     SellPattern P;
     P.nv = nv;
     // vertex -> incident stencils
@@ -274,6 +274,43 @@ SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t n
                 P.scol[size_t(slot)] = last;  // padding repeats the last column with a zero value
             }
         }
+    }
+    // distinct columns of each row group, and each slot's index into its group's list
+    const int64_t ng = (nv + kRowGroup - 1) / kRowGroup;
+    P.gptr.assign(size_t(ng + 1), 0);
+    std::vector<std::vector<int32_t>> gl(static_cast<size_t>(ng));
+    parallel_for(ng, [&](int64_t a, int64_t b) {
+        for (int64_t g = a; g < b; ++g) {
+            auto& v = gl[size_t(g)];
+            for (int64_t i = g * kRowGroup; i < std::min(nv, (g + 1) * kRowGroup); ++i) {
+                v.insert(v.end(), P.col.begin() + P.rowptr[i], P.col.begin() + P.rowptr[i + 1]);
+                if (P.rowptr[i] == P.rowptr[i + 1]) v.push_back(int32_t(i));  // an empty row pads with itself
+            }
+            std::sort(v.begin(), v.end());
+            v.erase(std::unique(v.begin(), v.end()), v.end());
+        }
+    });
+    for (int64_t g = 0; g < ng; ++g) {
+        P.gptr[size_t(g + 1)] = P.gptr[size_t(g)] + int32_t(gl[size_t(g)].size());
+        P.max_gcols = std::max<int32_t>(P.max_gcols, int32_t(gl[size_t(g)].size()));
+    }
+    if (staging && P.max_gcols <= kMaxGroupCols) {
+        P.gcols.reserve(size_t(P.gptr[size_t(ng)]));
+        for (const auto& v : gl) P.gcols.insert(P.gcols.end(), v.begin(), v.end());
+        P.lcol.assign(size_t(P.nslots), 0);
+        parallel_for(P.nslices, [&](int64_t a, int64_t b) {
+            for (int64_t sl = a; sl < b; ++sl) {
+                const auto& v = gl[size_t((64 * sl) / kRowGroup)];
+                for (int64_t slot = P.sptr[sl]; slot < P.sptr[sl + 1]; ++slot) {
+                    int32_t c = P.scol[size_t(slot)];
+                    auto it = std::lower_bound(v.begin(), v.end(), c);
+                    // rows past nv in the last slice pad with column 0, which may be absent: use entry 0
+                    P.lcol[size_t(slot)] = (it != v.end() && *it == c) ? uint16_t(it - v.begin()) : uint16_t(0);
+                }
+            }
+        });
+    } else {
+        P.gptr.clear();
     }
     return P;
 }

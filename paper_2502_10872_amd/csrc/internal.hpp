@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <stdexcept>
 #include <string>
+#include <memory>
 #include <vector>
 
 #include "shell.h"
@@ -103,8 +104,17 @@ struct SellPattern {
     std::vector<int32_t> scol;    // [nslots] SELL-64 column ids (padded with the row's last column)
     std::vector<int64_t> csr2sell;  // [nnz] slot of each CSR entry
     std::vector<int64_t> dslot;   // [nv] slot of the diagonal entry (or -1)
+    // row groups of kRowGroup rows: the distinct columns of each group, and every slot's column as an
+    // index into its group's list (the product stages the group's p entries in LDS)
+    std::vector<int32_t> gptr;    // [ngroups+1]
+    std::vector<int32_t> gcols;   // distinct columns, sorted per group
+    std::vector<uint16_t> lcol;   // [nslots] group-local column index
+    int32_t max_gcols = 0;
 };
-SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv);
+constexpr int kRowGroup = 256;     // rows per work-group of the row kernels
+constexpr int kMaxGroupCols = 4096;  // largest column set staged in LDS (larger: direct gathers)
+// staging: build the row groups' column lists (used when every group fits kMaxGroupCols)
+SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv, bool staging);
 
 // ------------------------------------------------------------------ kernel descriptors
 
@@ -129,17 +139,21 @@ struct PcgState {
     double gsq;
     int32_t iters[3], target[3], active[3];
     int32_t done, budget, replay, nonfinite;
+    int32_t pit;  // products done in this solve; selects which of the two p buffers is current
 };
 
 struct SolveDesc {
     double *x, *xhat, *xt, *v, *g, *y, *r;
-    void *f, *z, *p, *q, *dinv;     // float in mixed precision
+    void *f, *p0, *p1, *q, *dinv;   // float in mixed precision; p0/p1 alternate as the search direction
     const double *mass, *kdiag;
     const uint8_t* pinned;
     const int32_t* scol;
     const void* val;                // SELL values, float in mixed precision
     const int64_t* sptr;
     const int32_t* width;
+    const int32_t* gptr;            // group column lists (null: gather p directly)
+    const int32_t* gcols;
+    const uint16_t* lcol;
     PcgState* st;
     double* part;                   // reduction partials, quantity-major [q][group]
     int64_t nv, ngroups;
@@ -159,6 +173,7 @@ struct shell_stencils_s {
     int model = 0, k = 4, r = 1, precision = 0;
     int64_t nv = 0, nt = 0, ns = 0, ns_tiled = 0, nblocks = 0;
     int T = 1024;
+    int cfg_flags = 0;  // SHELL_FLAG_*
     bool reordered = false;
     double young = 0, poisson = 0, thickness = 0, density = 0, kb = 0;
     std::vector<int32_t> perm, iperm;    // internal -> caller, caller -> internal
@@ -195,6 +210,9 @@ struct shell_hessian_s {
     shell::DevArray<int32_t> width;      // [nslices]
     shell::DevArray<int64_t> sptr;       // [nslices+1]
     shell::DevArray<int32_t> rowlen;     // [nv]
+    shell::DevArray<int32_t> gptr;       // [ngroups+1], empty when a group's column set is too large
+    shell::DevArray<int32_t> gcols;
+    shell::DevArray<uint16_t> lcol;      // [nslots]
     shell::DevArray<double> val;         // [nslots]
     shell::DevArray<float> valf;         // [nslots] mixed copy
     shell::DevArray<double> kdiag;       // [nv]
@@ -213,17 +231,41 @@ struct shell_sim_s {
     shell::DevArray<double> f;           // float64 forces (or float32 in mixed, sized in doubles)
     shell::DevArray<double> dinv;        // [nv] (float in mixed)
     shell::DevArray<uint8_t> pinned;
-    shell::DevArray<double> z, p, q;     // PCG work vectors (float in mixed; sized in doubles)
+    shell::DevArray<double> p, p2, q;    // PCG work vectors (float in mixed; sized in doubles)
     shell::DevArray<double> partials;    // reduction partials
     shell_batch_s* solo = nullptr;       // this simulation alone, as a batch of one
     shell_step_stats_t stats{};
 };
 
 // A set of simulations stepped together: one launch per phase covers all of them.
+namespace shell {
+// Sampled in-step kernel timing: event pairs recorded on the step's stream around sampled launches,
+// read back after the step's own stream synchronisations.
+struct StepProfiler {
+    int every = 0;
+    long counter = 0;
+    struct Sample {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Sample> pending;
+    double ms[SHELL_NUM_PHASES] = {};
+    int64_t count[SHELL_NUM_PHASES] = {};
+    hipEvent_t take();
+    bool sample_iteration() { return every > 0 && (counter++ % every) == 0; }
+    void drain();  // the stream must be synchronised
+    void reset();
+    ~StepProfiler();
+};
+}  // namespace shell
+
 struct shell_batch_s {
     std::vector<shell_sim_s*> sims;
+    std::unique_ptr<shell::StepProfiler> prof;  // null unless sampling was requested
     int precision = 0;
     int max_T = 0;
+    size_t lds_spmv = 0;                     // staged p bytes per row group, largest over the members
     size_t capacity = 0;                     // meshes the descriptor buffers hold
     bool fdesc_dirty = true;
     shell::DevArray<shell::ForceDesc> fdesc;

@@ -13,8 +13,14 @@
 // each time.)  Kernels of converged meshes return at once, so the host launches iterations in chunks
 // and reads the flags once per chunk.
 //
-// Precision: FP64 throughout, or mixed: float32 matrix values, Jacobi diagonal and the vectors p, q,
-// z and f; float64 solution y, residual r, all dot products and the Newton residual.
+// One PCG iteration is two streaming kernels and two one-group finalizers: the product kernel first
+// forms the new search direction p = z + beta p_old (z = D^-1 r recomputed, never stored) for its row
+// group's distinct columns while staging them in LDS, writes p for its own rows and q = A p; the update
+// kernel advances y and r.  p alternates between two buffers because other row groups still read the
+// previous direction while it is rewritten.
+//
+// Precision: FP64 throughout, or mixed: float32 matrix values, Jacobi diagonal and the vectors p, q and
+// f; float64 solution y, residual r, all dot products and the Newton residual.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -115,27 +121,30 @@ __global__ void k_fin_residual(const SolveDesc* __restrict__ descs, const int32_
     }
 }
 
-// r = -g, y = 0, z = D^-1 r, p = z; partials of r.z and r.r
+// r = -g, y = 0; partials of r.z (z = D^-1 r) and r.r.  The first product forms p = z itself.
 template <typename VR>
 __global__ void k_pcg_init(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
     WorkItem wi;
     if (!work_item(items, nitems, wi)) return;
     const SolveDesc& d = descs[wi.mesh];
-    VR* __restrict__ z = static_cast<VR*>(d.z);
-    VR* __restrict__ p = static_cast<VR*>(d.p);
     long i = long(wi.unit) * kBlk + threadIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     if (i < d.nv) {
-        VR di = static_cast<const VR*>(d.dinv)[i];
+        const VR di = G(static_cast<const VR*>(d.dinv))[i];
+        const gbl<const double>* g = G(static_cast<const double*>(d.g));
+        double gi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gi[c] = g[3 * i + c];
+        gbl<double>* r = G(d.r);
+        gbl<double>* y = G(d.y);
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double ri = -d.g[3 * i + c];
-            VR zi = di * VR(ri);
-            d.r[3 * i + c] = ri;
-            d.y[3 * i + c] = 0.0;
-            z[3 * i + c] = zi;
-            p[3 * i + c] = zi;
-            acc[c] += ri * double(zi);
-            acc[3 + c] += ri * ri;
+            const double ri = -gi[c];
+            const VR zi = di * VR(ri);
+            r[3 * i + c] = ri;
+            y[3 * i + c] = 0.0;
+            acc[c] = ri * double(zi);
+            acc[3 + c] = ri * ri;
         }
     }
     __shared__ double sh[6 * (kBlk / 64)];
@@ -166,37 +175,142 @@ __global__ void k_fin_init(const SolveDesc* __restrict__ descs, const int32_t* _
         st->budget = 0;
         st->replay = d.replay;
         st->nonfinite = 0;
+        st->pit = 0;
     }
 }
 
+// Inputs of the search-direction update p = z + beta p_old, z = D^-1 r.
+template <typename VR>
+struct DirIn {
+    const gbl<const double>* r;
+    const gbl<const VR>* dinv;
+    const gbl<const VR>* pold;
+    VR beta[3];
+};
+
+// p of vertex j; every operand is loaded before use so the loads of several calls overlap.  p_old is
+// read even where beta is 0 (it is allocated; its contents then do not matter).
+template <typename VR>
+__device__ __forceinline__ void direction(const DirIn<VR>& in, long j, VR (&pj)[3]) {
+    const VR dj = in.dinv[j];
+    double rj[3];
+    VR po[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        rj[c] = in.r[3 * j + c];
+        po[c] = in.pold[3 * j + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const VR zj = dj * VR(rj[c]);
+        pj[c] = in.beta[c] != VR(0) ? fma(in.beta[c], po[c], zj) : zj;
+    }
+}
+
+// Row product for row groups too wide to stage: each neighbour's new direction is formed from its own
+// gathers (four entries in flight per lane).
+template <typename MR, typename VR>
+__device__ __forceinline__ void row_product_direction(const SolveDesc& d, long row, const DirIn<VR>& in, MR& ax,
+                                                      MR& ay, MR& az) {
+    const gbl<const int32_t>* scol = G(d.scol);
+    const gbl<const MR>* val = G(static_cast<const MR*>(d.val));
+    const long slice = row >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(G(d.width)[slice]);
+    const long s0 = G(d.sptr)[slice] + (row & 63);
+    ax = MR(0);
+    ay = MR(0);
+    az = MR(0);
+    constexpr int U = 4;
+    for (int k = 0; k < w; k += U) {
+        int c[U];
+        MR a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in_row = k + u < w;  // wave-uniform
+            c[u] = in_row ? scol[s0 + 64L * (k + u)] : int(row);
+            a[u] = in_row ? val[s0 + 64L * (k + u)] : MR(0);
+        }
+        VR pc[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) direction<VR>(in, c[u], pc[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ax = fma(a[u], MR(pc[u][0]), ax);
+            ay = fma(a[u], MR(pc[u][1]), ay);
+            az = fma(a[u], MR(pc[u][2]), az);
+        }
+    }
+}
+
+// p = z + beta p_old for the row group's distinct columns (staged in LDS) and own rows (written), then
 // q = (M + dt^2 K_s) p on the free rows (fixed rows 0); partials of p.q
 template <typename VR, typename MR>
 __global__ void k_pcg_spmv(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
     WorkItem wi;
     if (!work_item(items, nitems, wi)) return;
     const SolveDesc& d = descs[wi.mesh];
-    if (d.st->done) return;
-    const VR* __restrict__ p = static_cast<const VR*>(d.p);
-    VR* __restrict__ q = static_cast<VR*>(d.q);
-    long i = long(wi.unit) * kBlk + threadIdx.x;
+    const PcgState* st = d.st;
+    const int done = st->done, pit = st->pit;
+    const double b0 = st->beta[0], b1 = st->beta[1], b2 = st->beta[2];
+    if (done) return;
+    const bool odd = pit & 1;
+    DirIn<VR> in;
+    in.r = G(static_cast<const double*>(d.r));
+    in.dinv = G(static_cast<const VR*>(d.dinv));
+    in.pold = G(static_cast<const VR*>(odd ? d.p0 : d.p1));
+    in.beta[0] = VR(b0);
+    in.beta[1] = VR(b1);
+    in.beta[2] = VR(b2);
+    gbl<VR>* pnew = G(static_cast<VR*>(odd ? d.p1 : d.p0));
+    gbl<VR>* q = G(static_cast<VR*>(d.q));
+    const long i = long(wi.unit) * kBlk + threadIdx.x;
+    extern __shared__ unsigned char smem_raw[];
+    VR* ps = reinterpret_cast<VR*>(smem_raw);
+    const bool staged = d.gptr != nullptr;
+    if (staged) {
+        const int a = G(d.gptr)[wi.unit], n = G(d.gptr)[wi.unit + 1] - a;
+        const gbl<const int32_t>* gc = G(d.gcols + a);
+        // two columns per pass so that each lane has two sets of gathers in flight
+        // (a lane past the end repeats its first column: same value, same LDS slot)
+        for (int k = threadIdx.x; k < n; k += 2 * kBlk) {
+            const int k2 = k + kBlk < n ? k + kBlk : k;
+            const int j0 = gc[k], j1 = gc[k2];
+            VR p0[3], p1[3];
+            direction<VR>(in, j0, p0);
+            direction<VR>(in, j1, p1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                ps[3 * k + c] = p0[c];
+                ps[3 * k2 + c] = p1[c];
+            }
+        }
+        __syncthreads();
+    }
     double acc[3] = {0, 0, 0};
     if (i < d.nv) {
+        const MR m = MR(G(d.mass)[i]);
+        const bool pin = G(d.pinned)[i];
+        VR pi[3];
+        direction<VR>(in, i, pi);
         MR ax, ay, az;
-        sell_row_product<MR, VR>(d.scol, static_cast<const MR*>(d.val), d.sptr, d.width, i, p, ax, ay, az);
-        VR px = p[3 * i], py = p[3 * i + 1], pz = p[3 * i + 2];
-        VR qx = 0, qy = 0, qz = 0;
-        if (!d.pinned[i]) {
-            const MR m = MR(d.mass[i]), dt2 = MR(d.dt2);
-            qx = VR(fma(m, MR(px), dt2 * ax));
-            qy = VR(fma(m, MR(py), dt2 * ay));
-            qz = VR(fma(m, MR(pz), dt2 * az));
+        if (staged)
+            sell_row_product_staged<MR, VR>(d.lcol, static_cast<const MR*>(d.val), d.sptr, d.width, i, ps, ax, ay,
+                                            az);
+        else
+            row_product_direction<MR, VR>(d, i, in, ax, ay, az);
+        VR qv[3] = {0, 0, 0};
+        if (!pin) {
+            const MR dt2 = MR(d.dt2);
+            qv[0] = VR(fma(m, MR(pi[0]), dt2 * ax));
+            qv[1] = VR(fma(m, MR(pi[1]), dt2 * ay));
+            qv[2] = VR(fma(m, MR(pi[2]), dt2 * az));
         }
-        q[3 * i] = qx;
-        q[3 * i + 1] = qy;
-        q[3 * i + 2] = qz;
-        acc[0] = double(px) * double(qx);
-        acc[1] = double(py) * double(qy);
-        acc[2] = double(pz) * double(qz);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pnew[3 * i + c] = pi[c];
+            q[3 * i + c] = qv[c];
+            acc[c] = double(pi[c]) * double(qv[c]);
+        }
     }
     __shared__ double sh[3 * (kBlk / 64)];
     block_sum<3>(acc, sh);
@@ -214,31 +328,45 @@ __global__ void k_fin_alpha(const SolveDesc* __restrict__ descs, const int32_t* 
         for (int c = 0; c < 3; ++c) st->alpha[c] = (st->active[c] && tot[c] != 0.0) ? st->rz[c] / tot[c] : 0.0;
 }
 
-// y += alpha p, r -= alpha q, z = D^-1 r; partials of r.z and r.r
+// y += alpha p, r -= alpha q; partials of r.z (z = D^-1 r, not stored) and r.r
 template <typename VR>
 __global__ void k_pcg_update(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
     WorkItem wi;
     if (!work_item(items, nitems, wi)) return;
     const SolveDesc& d = descs[wi.mesh];
     const PcgState* st = d.st;
-    if (st->done) return;
-    const VR* __restrict__ p = static_cast<const VR*>(d.p);
-    const VR* __restrict__ q = static_cast<const VR*>(d.q);
-    VR* __restrict__ z = static_cast<VR*>(d.z);
-    long i = long(wi.unit) * kBlk + threadIdx.x;
+    const int done = st->done, pit = st->pit;
     const double al[3] = {st->alpha[0], st->alpha[1], st->alpha[2]};
+    if (done) return;
+    const long i = long(wi.unit) * kBlk + threadIdx.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     if (i < d.nv) {
-        VR di = static_cast<const VR*>(d.dinv)[i];
+        const gbl<const VR>* p = G(static_cast<const VR*>((pit & 1) ? d.p1 : d.p0));
+        const gbl<const VR>* q = G(static_cast<const VR*>(d.q));
+        gbl<double>* y = G(d.y);
+        gbl<double>* r = G(d.r);
+        const VR di = G(static_cast<const VR*>(d.dinv))[i];
+        VR pv[3], qv[3];
+        double yv[3], rv[3];
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            double yi = fma(al[c], double(p[3 * i + c]), d.y[3 * i + c]);
-            double ri = fma(-al[c], double(q[3 * i + c]), d.r[3 * i + c]);
-            VR zi = di * VR(ri);
-            d.y[3 * i + c] = yi;
-            d.r[3 * i + c] = ri;
-            z[3 * i + c] = zi;
-            acc[c] += ri * double(zi);
-            acc[3 + c] += ri * ri;
+            pv[c] = p[3 * i + c];
+            qv[c] = q[3 * i + c];
+            yv[c] = y[3 * i + c];
+            rv[c] = r[3 * i + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            yv[c] = fma(al[c], double(pv[c]), yv[c]);
+            rv[c] = fma(-al[c], double(qv[c]), rv[c]);
+            const VR zi = di * VR(rv[c]);
+            acc[c] = rv[c] * double(zi);
+            acc[3 + c] = rv[c] * rv[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            y[3 * i + c] = yv[c];
+            r[3 * i + c] = rv[c];
         }
     }
     __shared__ double sh[6 * (kBlk / 64)];
@@ -274,22 +402,8 @@ __global__ void k_fin_beta(const SolveDesc* __restrict__ descs, const int32_t* _
             any |= st->active[c];
         }
         st->done = !any;
+        st->pit += 1;
     }
-}
-
-template <typename VR>
-__global__ void k_pcg_direction(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
-                                long nitems) {
-    WorkItem wi;
-    if (!work_item(items, nitems, wi)) return;
-    const SolveDesc& d = descs[wi.mesh];
-    const PcgState* st = d.st;
-    if (st->done) return;
-    long i = long(wi.unit) * kBlk + threadIdx.x;
-    if (i >= d.nv) return;
-    const VR* __restrict__ z = static_cast<const VR*>(d.z);
-    VR* __restrict__ p = static_cast<VR*>(d.p);
-    for (int c = 0; c < 3; ++c) p[3 * i + c] = fma(VR(st->beta[c]), p[3 * i + c], z[3 * i + c]);
 }
 
 // x += y (Newton update)
@@ -333,6 +447,49 @@ __global__ void k_zero(double* __restrict__ p, long n) {
 // ------------------------------------------------------------------ host driver
 
 // Device views of one launch set: the row-group items and, per model, the tile items.
+}  // namespace
+
+hipEvent_t StepProfiler::take() {
+    if (pool.empty()) {
+        hipEvent_t e;
+        SHELL_HIP(hipEventCreate(&e));
+        return e;
+    }
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+}
+
+void StepProfiler::drain() {
+    for (const Sample& e : pending) {
+        float t = 0.f;
+        SHELL_HIP(hipEventElapsedTime(&t, e.a, e.b));
+        ms[e.phase] += double(t);
+        count[e.phase] += 1;
+        pool.push_back(e.a);
+        pool.push_back(e.b);
+    }
+    pending.clear();
+}
+
+void StepProfiler::reset() {
+    for (int k = 0; k < SHELL_NUM_PHASES; ++k) {
+        ms[k] = 0.0;
+        count[k] = 0;
+    }
+    counter = 0;
+}
+
+StepProfiler::~StepProfiler() {
+    for (const Sample& e : pending) {
+        pool.push_back(e.a);
+        pool.push_back(e.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+}
+
+namespace {
+
 struct Launch {
     const SolveDesc* sdesc;
     const ForceDesc* fdesc;
@@ -344,24 +501,45 @@ struct Launch {
     int nmeshes;
     int precision;
     int lds_T;
+    size_t lds_spmv;  // bytes of staged p entries per row group (largest over the meshes)
 };
 
+// Runs `launch` bracketed by a sampled event pair when `sample` is set.
+template <typename F>
+void timed_launch(StepProfiler* prof, bool sample, int phase, hipStream_t s, F&& launch) {
+    if (!sample) {
+        launch();
+        return;
+    }
+    StepProfiler::Sample e{phase, prof->take(), prof->take()};
+    SHELL_HIP(hipEventRecord(e.a, s));
+    launch();
+    SHELL_HIP(hipEventRecord(e.b, s));
+    prof->pending.push_back(e);
+}
+
 template <typename VR, typename MR>
-void pcg_chunk(const Launch& L, int count, hipStream_t s) {
+void pcg_chunk(const Launch& L, int count, hipStream_t s, StepProfiler* prof) {
     const long grid = xcd_grid(L.nrows);
     for (int it = 0; it < count; ++it) {
-        k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
-        k_fin_alpha<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
-        k_pcg_update<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
-        k_fin_beta<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
-        k_pcg_direction<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        const bool smp = prof && prof->sample_iteration();
+        timed_launch(prof, smp, SHELL_PHASE_PRODUCT, s,
+                     [&] { k_pcg_spmv<VR, MR><<<grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows); });
+        timed_launch(prof, smp, SHELL_PHASE_FINALIZE, s,
+                     [&] { k_fin_alpha<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes); });
+        timed_launch(prof, smp, SHELL_PHASE_UPDATE, s,
+                     [&] { k_pcg_update<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows); });
+        timed_launch(prof, smp, SHELL_PHASE_FINALIZE, s,
+                     [&] { k_fin_beta<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes); });
     }
     SHELL_HIP(hipGetLastError());
 }
 
-void forces(const Launch& L, hipStream_t s) {
-    for (int m = 0; m < 6; ++m)
-        if (L.ntiles[m]) launch_force_items(m, L.precision, L.fdesc, L.tiles[m], L.ntiles[m], L.lds_T, s);
+void forces(const Launch& L, hipStream_t s, StepProfiler* prof = nullptr) {
+    timed_launch(prof, prof && prof->every > 0, SHELL_PHASE_FORCES, s, [&] {
+        for (int m = 0; m < 6; ++m)
+            if (L.ntiles[m]) launch_force_items(m, L.precision, L.fdesc, L.tiles[m], L.ntiles[m], L.lds_T, s);
+    });
 }
 
 struct ItemBuilder {
@@ -416,6 +594,7 @@ Launch upload(shell_batch_s& b, const ItemBuilder& ib, hipStream_t s) {
     L.fdesc = b.fdesc.p;
     L.precision = b.precision;
     L.lds_T = b.max_T;
+    L.lds_spmv = b.lds_spmv;
     return L;
 }
 
@@ -426,6 +605,7 @@ void upload_descs(shell_batch_s& b, hipStream_t s) {
 void read_states(shell_batch_s& b, hipStream_t s) {
     SHELL_HIP(hipMemcpyAsync(b.state_host, b.state.p, b.sims.size() * sizeof(PcgState), hipMemcpyDeviceToHost, s));
     SHELL_HIP(hipStreamSynchronize(s));
+    if (b.prof) b.prof->drain();
 }
 
 SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
@@ -438,8 +618,8 @@ SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
     d.y = sim.y.p;
     d.r = sim.r.p;
     d.f = sim.f.p;
-    d.z = sim.z.p;
-    d.p = sim.p.p;
+    d.p0 = sim.p.p;
+    d.p1 = sim.p2.p;
     d.q = sim.q.p;
     d.dinv = sim.dinv.p;
     d.mass = sim.mass.p;
@@ -450,6 +630,9 @@ SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
                                                    : static_cast<const void*>(sim.h->val.p);
     d.sptr = sim.h->sptr.p;
     d.width = sim.h->width.p;
+    d.gptr = sim.h->gptr.p;  // null when the mesh's row groups are too wide to stage
+    d.gcols = sim.h->gcols.p;
+    d.lcol = sim.h->lcol.p;
     d.st = st;
     d.part = sim.partials.p;
     d.nv = sim.nv;
@@ -534,7 +717,7 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
     for (int k = 0; !iterating.empty(); ++k) {
         ib.build(b.sims, iterating);
         L = upload(b, ib, s);
-        forces(L, s);
+        forces(L, s, b.prof.get());
         k_residual<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 1);
         k_fin_residual<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
         SHELL_HIP(hipGetLastError());
@@ -576,7 +759,7 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
             if (p.chunk > 0) first_chunk = max_chunk = p.chunk;
         }
         if (all_replay) {
-            pcg_chunk<VR, MR>(L, most, s);
+            pcg_chunk<VR, MR>(L, most, s, b.prof.get());
             read_states(b, s);
         } else {
             read_states(b, s);
@@ -585,7 +768,7 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
                 bool done = true;
                 for (int m : solve) done &= b.state_host[m].done != 0;
                 if (done) break;
-                pcg_chunk<VR, MR>(L, chunk, s);
+                pcg_chunk<VR, MR>(L, chunk, s, b.prof.get());
                 read_states(b, s);
                 chunk = std::min(2 * chunk, max_chunk);
             }
@@ -663,7 +846,7 @@ void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out,
         k_residual<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 0);
         k_pcg_init<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
         k_fin_init<<<1, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
-        k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_pcg_spmv<VR, MR><<<grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows);
         k_fin_alpha<<<1, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
         SHELL_HIP(hipGetLastError());
     };
@@ -680,11 +863,11 @@ void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out,
     out.reps = reps;
     out.force_ms = timed([&] { forces(L, s); });
     init();
-    out.spmv_ms = timed([&] { k_pcg_spmv<VR, MR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows); });
+    out.spmv_ms = timed([&] { k_pcg_spmv<VR, MR><<<grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows); });
     init();
     out.update_ms = timed([&] { k_pcg_update<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows); });
     init();
-    out.direction_ms = timed([&] { k_pcg_direction<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows); });
+    out.direction_ms = 0.0;  // the direction update is part of the product kernel
     SHELL_HIP(hipGetLastError());
     SHELL_HIP(hipStreamSynchronize(s));
     (void)hipEventDestroy(e0);
@@ -695,7 +878,7 @@ void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out,
 
 void sim_alloc(shell_sim_s& sim) {
     const long nv = sim.nv, n3 = 3 * nv;
-    for (auto* a : {&sim.x, &sim.v, &sim.xt, &sim.xhat, &sim.g, &sim.y, &sim.r, &sim.f, &sim.z, &sim.p, &sim.q})
+    for (auto* a : {&sim.x, &sim.v, &sim.xt, &sim.xhat, &sim.g, &sim.y, &sim.r, &sim.f, &sim.p, &sim.p2, &sim.q})
         a->alloc(size_t(std::max(n3, 1L)));
     sim.mass.alloc(size_t(std::max(nv, 1L)));
     sim.dinv.alloc(size_t(std::max(nv, 1L)));
@@ -725,6 +908,11 @@ void batch_init(shell_batch_s& b) {
             SHELL_CHECK(b.sims[q] != b.sims[m], SHELL_E_INVALID_ARG, "a simulation appears twice in a batch");
         b.max_T = std::max(b.max_T, b.sims[m]->st->T);
     }
+    size_t vr = b.precision == SHELL_PREC_MIXED ? sizeof(float) : sizeof(double);
+    b.lds_spmv = 0;
+    for (size_t m = 0; m < n; ++m)
+        if (b.sims[m]->h->gptr.p)
+            b.lds_spmv = std::max(b.lds_spmv, size_t(b.sims[m]->h->pat.max_gcols) * 3 * vr);
     if (n > b.capacity) {
         batch_free_host(b);
         b.capacity = std::max<size_t>(n, 2 * b.capacity);

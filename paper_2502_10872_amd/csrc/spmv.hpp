@@ -8,6 +8,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "devmath.hpp"
+
 #ifndef SHELL_SPMV_BATCH
 #define SHELL_SPMV_BATCH 8  // entries per batch: loads in flight per lane
 #endif
@@ -18,7 +20,7 @@
 namespace shell {
 
 template <typename T>
-__device__ __forceinline__ T stream_load(const T* p) {
+__device__ __forceinline__ T stream_load(const gbl<const T>* p) {
 #if SHELL_SPMV_NT
     return __builtin_nontemporal_load(p);
 #else
@@ -31,11 +33,15 @@ __device__ __forceinline__ void sell_row_product(const int32_t* __restrict__ sco
                                                  const int64_t* __restrict__ sptr,
                                                  const int32_t* __restrict__ width, long row, const VR* __restrict__ p,
                                                  MR& ax, MR& ay, MR& az) {
+    const gbl<const int32_t>* gcol = G(scol);
+    const gbl<const MR>* gval = G(val);
+    const gbl<const VR>* gp = G(p);
     const long slice = row >> 6;
     // the whole wave shares the slice (work-groups are whole waves aligned to 64 rows)
-    const int w = __builtin_amdgcn_readfirstlane(width[slice]);
-    const long s0 = (long(__builtin_amdgcn_readfirstlane(int(sptr[slice] & 0xffffffff))) |
-                     (long(__builtin_amdgcn_readfirstlane(int(sptr[slice] >> 32))) << 32)) +
+    const int w = __builtin_amdgcn_readfirstlane(G(width)[slice]);
+    const int64_t sp = G(sptr)[slice];
+    const long s0 = (long(__builtin_amdgcn_readfirstlane(int(sp & 0xffffffff))) |
+                     (long(__builtin_amdgcn_readfirstlane(int(sp >> 32))) << 32)) +
                     (row & 63);
     ax = MR(0);
     ay = MR(0);
@@ -47,12 +53,87 @@ __device__ __forceinline__ void sell_row_product(const int32_t* __restrict__ sco
         MR a[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            c[u] = stream_load(scol + s0 + 64L * (k + u));
-            a[u] = stream_load(val + s0 + 64L * (k + u));
+            c[u] = stream_load(gcol + s0 + 64L * (k + u));
+            a[u] = stream_load(gval + s0 + 64L * (k + u));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const VR* pc = p + 3L * c[u];
+            const gbl<const VR>* pc = gp + 3L * c[u];
+            ax = fma(a[u], MR(pc[0]), ax);
+            ay = fma(a[u], MR(pc[1]), ay);
+            az = fma(a[u], MR(pc[2]), az);
+        }
+    }
+    const int rem = w - k;  // wave-uniform
+    if (rem > 0) {
+        // one more batch with the slots past the row's end clamped to its last entry and weighted 0, so
+        // that every load is issued at once (the clamped ones hit lines already being fetched)
+        int c[U];
+        MR a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long off = s0 + 64L * (k + (u < rem ? u : rem - 1));
+            c[u] = stream_load(gcol + off);
+            a[u] = stream_load(gval + off);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const gbl<const VR>* pc = gp + 3L * c[u];
+            const MR au = u < rem ? a[u] : MR(0);
+            ax = fma(au, MR(pc[0]), ax);
+            ay = fma(au, MR(pc[1]), ay);
+            az = fma(au, MR(pc[2]), az);
+        }
+    }
+}
+
+// Stage the p entries of a row group's distinct columns into LDS: ps[3k..3k+2] = p[gcols[k]].
+// Each distinct neighbour is fetched once per group instead of once per nonzero (about 12x fewer
+// gathers on triangle meshes).  Every thread of the work-group must call it.
+template <typename VR>
+__device__ __forceinline__ void stage_group_columns(const int32_t* __restrict__ gptr,
+                                                    const int32_t* __restrict__ gcols, long group,
+                                                    const VR* __restrict__ p, VR* __restrict__ ps) {
+    const int a = gptr[group], n = gptr[group + 1] - a;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+        const gbl<const VR>* pc = G(p) + 3L * G(gcols)[a + k];
+        ps[3 * k] = pc[0];
+        ps[3 * k + 1] = pc[1];
+        ps[3 * k + 2] = pc[2];
+    }
+}
+
+// The same row product with 16-bit group-local column indices and p read from the staged LDS copy.
+template <typename MR, typename VR>
+__device__ __forceinline__ void sell_row_product_staged(const uint16_t* __restrict__ lcol,
+                                                        const MR* __restrict__ val,
+                                                        const int64_t* __restrict__ sptr,
+                                                        const int32_t* __restrict__ width, long row,
+                                                        const VR* __restrict__ ps, MR& ax, MR& ay, MR& az) {
+    const gbl<const uint16_t>* glc = G(lcol);
+    const gbl<const MR>* gval = G(val);
+    const long slice = row >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(G(width)[slice]);
+    const int64_t sp = G(sptr)[slice];
+    const long s0 = (long(__builtin_amdgcn_readfirstlane(int(sp & 0xffffffff))) |
+                     (long(__builtin_amdgcn_readfirstlane(int(sp >> 32))) << 32)) +
+                    (row & 63);
+    ax = MR(0);
+    ay = MR(0);
+    az = MR(0);
+    constexpr int U = SHELL_SPMV_BATCH;
+    int k = 0;
+    for (; k + U <= w; k += U) {
+        int c[U];
+        MR a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = stream_load(glc + s0 + 64L * (k + u));
+            a[u] = stream_load(gval + s0 + 64L * (k + u));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const VR* pc = ps + 3 * c[u];
             ax = fma(a[u], MR(pc[0]), ax);
             ay = fma(a[u], MR(pc[1]), ay);
             az = fma(a[u], MR(pc[2]), az);
@@ -64,19 +145,17 @@ __device__ __forceinline__ void sell_row_product(const int32_t* __restrict__ sco
         MR a[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (u < rem) {
-                c[u] = stream_load(scol + s0 + 64L * (k + u));
-                a[u] = stream_load(val + s0 + 64L * (k + u));
-            }
+            const long off = s0 + 64L * (k + (u < rem ? u : rem - 1));
+            c[u] = stream_load(glc + off);
+            a[u] = stream_load(gval + off);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (u < rem) {
-                const VR* pc = p + 3L * c[u];
-                ax = fma(a[u], MR(pc[0]), ax);
-                ay = fma(a[u], MR(pc[1]), ay);
-                az = fma(a[u], MR(pc[2]), az);
-            }
+            const VR* pc = ps + 3 * c[u];
+            const MR au = u < rem ? a[u] : MR(0);
+            ax = fma(au, MR(pc[0]), ax);
+            ay = fma(au, MR(pc[1]), ay);
+            az = fma(au, MR(pc[2]), az);
         }
     }
 }

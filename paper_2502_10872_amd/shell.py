@@ -38,7 +38,10 @@ class shell_material_t(ctypes.Structure):
 
 class shell_config_t(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("block_vertices", ctypes.c_int32), ("reorder", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
+
+
+SHELL_FLAG_DIRECT_PRODUCT = 1
 
 
 class shell_stencils_info_t(ctypes.Structure):
@@ -65,11 +68,27 @@ class shell_kernel_times_t(ctypes.Structure):
                 ("direction_ms", ctypes.c_double), ("reps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class shell_hessian_info_t(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("nnz", ctypes.c_int64), ("slots", ctypes.c_int64),
+                ("nslices", ctypes.c_int64), ("group_cols", ctypes.c_int64), ("max_group_cols", ctypes.c_int32),
+                ("staged", ctypes.c_int32)]
+
+
+SHELL_NUM_PHASES = 4
+PHASES = ("forces", "product", "update", "finalize")  # SHELL_PHASE_* order
+
+
+class shell_profile_t(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * SHELL_NUM_PHASES), ("count", ctypes.c_int64 * SHELL_NUM_PHASES)]
+
+
 EXPORTS = ("shell_build_stencils", "shell_stencils_info", "shell_stencils_export", "shell_eval_forces",
-           "shell_assemble_constant_hessian", "shell_hessian_export_csr", "shell_hessian_apply", "shell_sim_create",
+           "shell_assemble_constant_hessian", "shell_hessian_export_csr", "shell_hessian_info",
+           "shell_hessian_apply", "shell_sim_create",
            "shell_step_implicit", "shell_sim_get_stats", "shell_sim_get_state", "shell_sim_set_state",
            "shell_sim_device_state", "shell_sim_time_kernels", "shell_batch_create", "shell_batch_step",
-           "shell_batch_reset", "shell_sim_device_bytes",
+           "shell_batch_reset", "shell_sim_device_bytes", "shell_batch_profile", "shell_batch_profile_read",
+           "shell_sim_profile", "shell_sim_profile_read",
            "shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim", "shell_destroy_batch",
            "shell_status_string", "shell_last_error")
 
@@ -90,6 +109,7 @@ def lib() -> ctypes.CDLL:
         L.shell_eval_forces.argtypes = [P, P, P, P, P]
         L.shell_assemble_constant_hessian.argtypes = [P, P, P]
         L.shell_hessian_export_csr.argtypes = [P, P, P, P, P]
+        L.shell_hessian_info.argtypes = [P, P]
         L.shell_hessian_apply.argtypes = [P, P, d, P, P, P]
         L.shell_sim_create.argtypes = [P, P, P, P, P, P]
         L.shell_step_implicit.argtypes = [P, P, P, P]
@@ -102,6 +122,10 @@ def lib() -> ctypes.CDLL:
         L.shell_batch_step.argtypes = [P, P, i32, P, P]
         L.shell_batch_reset.argtypes = [P, P, i32]
         L.shell_sim_device_bytes.argtypes = [P, P, P, P]
+        L.shell_batch_profile.argtypes = [P, i32]
+        L.shell_batch_profile_read.argtypes = [P, P]
+        L.shell_sim_profile.argtypes = [P, i32]
+        L.shell_sim_profile_read.argtypes = [P, P]
         for name in ("shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim", "shell_destroy_batch"):
             getattr(L, name).argtypes = [P]
             getattr(L, name).restype = None
@@ -148,12 +172,12 @@ def _model(m) -> int:
 
 
 def shell_build_stencils(X, tris, model, material: dict, precision=SHELL_PREC_FP64, block_vertices=0, reorder=1,
-                         stream=None):
+                         stream=None, flags=0):
     X = np.ascontiguousarray(X, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     mat = shell_material_t(material["young"], material["poisson"], material["thickness"],
                            material.get("density", 0.0))
-    cfg = shell_config_t(int(precision), int(block_vertices), int(reorder), 0)
+    cfg = shell_config_t(int(precision), int(block_vertices), int(reorder), int(flags))
     out = ctypes.c_void_p()
     _check(lib().shell_build_stencils(_np_ptr(X), X.shape[0], _np_ptr(tris), tris.shape[0], _model(model),
                                       ctypes.byref(mat), ctypes.byref(cfg), _stream(stream), ctypes.byref(out)),
@@ -316,6 +340,39 @@ def shell_sim_device_bytes(sim) -> int:
     return a.value + b.value + c.value
 
 
+def _profile_dict(out) -> dict:
+    return {name: {"ms": out.ms[k], "count": out.count[k],
+                   "avg_ms": out.ms[k] / out.count[k] if out.count[k] else None}
+            for k, name in enumerate(PHASES)}
+
+
+def shell_hessian_info(h) -> dict:
+    out = shell_hessian_info_t()
+    _check(lib().shell_hessian_info(h, ctypes.byref(out)), "shell_hessian_info")
+    return {name: getattr(out, name) for name, _ in shell_hessian_info_t._fields_}
+
+
+def shell_batch_profile(batch, every):
+    _check(lib().shell_batch_profile(batch, int(every)), "shell_batch_profile")
+
+
+def shell_batch_profile_read(batch) -> dict:
+    out = shell_profile_t()
+    _check(lib().shell_batch_profile_read(batch, ctypes.byref(out)), "shell_batch_profile_read")
+    return _profile_dict(out)
+
+
+def shell_sim_profile(sim, every):
+    _check(lib().shell_sim_profile(sim, int(every)), "shell_sim_profile")
+
+
+def shell_sim_profile_read(sim) -> dict:
+    """Per phase: summed sampled duration (ms), number of sampled launches and their average."""
+    out = shell_profile_t()
+    _check(lib().shell_sim_profile_read(sim, ctypes.byref(out)), "shell_sim_profile_read")
+    return _profile_dict(out)
+
+
 def shell_destroy_batch(batch):
     lib().shell_destroy_batch(batch)
 
@@ -343,11 +400,12 @@ class Problem:
     """One mesh with its stencils, constant Hessian and (optionally) a simulation, freed together."""
 
     def __init__(self, mesh, material: dict, model=None, precision=SHELL_PREC_FP64, block_vertices=0, reorder=1,
-                 sim=True):
+                 sim=True, flags=0):
         self.mesh = mesh
         self.nv = mesh.nv
         self.model = mesh.model if model is None else model
-        self.st = shell_build_stencils(mesh.X, mesh.tris, self.model, material, precision, block_vertices, reorder)
+        self.st = shell_build_stencils(mesh.X, mesh.tris, self.model, material, precision, block_vertices, reorder,
+                                       flags=flags)
         self.info = shell_stencils_info(self.st)
         self.h = shell_assemble_constant_hessian(self.st)
         self.sim = shell_sim_create(self.st, self.h, mesh.X, None, mesh.pinned) if sim else None

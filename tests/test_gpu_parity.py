@@ -134,10 +134,11 @@ def test_hessian_and_apply_match_oracle(model):
         assert rel(qd.cpu().numpy(), O.apply((rp, col, val), None, 1.0, p)) <= 1e-12
 
 
-def _replay_run(mesh, model, steps, dt, max_newton, pcg_rtol, block=256):
+def _replay_run(mesh, model, steps, dt, max_newton, pcg_rtol, block=256, flags=0, reorder=1):
     ost = oracle_stencils(model, mesh)
     osim = O.Sim(ost, MAT, mesh.pinned)
-    with S.Problem(mesh, MAT, model=model, block_vertices=block) as pb:
+    with S.Problem(mesh, MAT, model=model, block_vertices=block, flags=flags, reorder=reorder) as pb:
+        assert S.shell_hessian_info(pb.h)["staged"] == (0 if flags & S.SHELL_FLAG_DIRECT_PRODUCT else 1)
         for _ in range(steps):
             counts, ostats = osim.step(dt, max_newton=max_newton, pcg_rtol=pcg_rtol)
             params, _keep = S.step_params(dt, max_newton=max_newton, pcg_rtol=pcg_rtol, replay=counts)
@@ -164,6 +165,58 @@ def test_shell_steps_replay_match_oracle(model):
     x, v, osim = _replay_run(mesh, model, 3, 1 / 30, 3, 1e-8, block=128)
     assert rel(x - mesh.X, osim.x - mesh.X) <= TOL64
     assert rel(v, osim.v) <= TOL64
+
+
+@pytest.mark.parametrize("model,reorder", [("SS", 1), ("EP", 0), ("FS", 2)])
+def test_direct_product_replay_matches_oracle(model, reorder):
+    """The product without LDS staging (each neighbour gathered from memory) gives the same steps."""
+    mesh = I.workload_cylinder(24, model) if model.endswith("S") else I.plate_mesh(24, 0.6, 0.2, 4, model)
+    x, v, osim = _replay_run(mesh, model, 2, 1 / 30, 2, 1e-8, block=128, flags=S.SHELL_FLAG_DIRECT_PRODUCT,
+                             reorder=reorder)
+    assert rel(x - mesh.X, osim.x - mesh.X) <= TOL64
+    assert rel(v, osim.v) <= TOL64
+
+
+def test_hessian_info_counts():
+    """Storage figures against the pattern itself (caller order kept, so slices and groups are known)."""
+    mesh = mesh_for("SS", 29)
+    rp, col, _ = oracle_stencils("SS", mesh).hessian()
+    with S.Problem(mesh, MAT, block_vertices=128, reorder=0, sim=False) as pb:
+        hi = S.shell_hessian_info(pb.h)
+    assert hi["nv"] == mesh.nv and hi["nnz"] == len(col)
+    assert hi["nslices"] == (mesh.nv + 63) // 64
+    lens = np.diff(rp)
+    # every 64-row slice is padded to its longest row
+    assert hi["slots"] == sum(64 * int(lens[a:a + 64].max()) for a in range(0, mesh.nv, 64))
+    groups = [np.unique(col[rp[a]:rp[min(a + 256, mesh.nv)]]) for a in range(0, mesh.nv, 256)]
+    assert hi["staged"] == 1
+    assert hi["group_cols"] == sum(len(g) for g in groups)
+    assert hi["max_group_cols"] == max(len(g) for g in groups)
+
+
+def test_in_step_profiling_changes_nothing():
+    """Event sampling inside the steps changes no result (beyond the rounding by which any two builds
+    differ: force tiles add with LDS atomics) and counts its samples."""
+    mesh = I.workload_cylinder(24, "SS")
+    params, _ = S.step_params(1 / 30, max_newton=2, pcg_rtol=1e-6)
+    out = []
+    for every in (0, 3):
+        with S.Problem(mesh, MAT) as pb:
+            S.shell_sim_profile(pb.sim, every)
+            for _ in range(2):
+                rc, st = S.shell_step_implicit(pb.sim, params)
+            prof = S.shell_sim_profile_read(pb.sim)
+            x, v, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+            out.append((x, v, st, prof))
+    (xa, va, sa, pa), (xb, vb, sb, pb_) = out
+    assert rel(xa - mesh.X, xb - mesh.X) <= 1e-11 and rel(va, vb) <= 1e-11
+    assert all(pa[k]["count"] == 0 for k in pa)
+    iters = max(int(sb["counts"][k].max()) for k in range(sb["newton_iters"]))
+    assert pb_["product"]["count"] >= 2 and pb_["product"]["count"] == pb_["update"]["count"]
+    assert pb_["finalize"]["count"] == 2 * pb_["product"]["count"]
+    assert pb_["forces"]["count"] >= 2 and iters > 0
+    for k in pb_:
+        assert pb_[k]["ms"] > 0 and pb_[k]["avg_ms"] < 100.0
 
 
 def test_tolerance_mode_counts_close_to_oracle():
