@@ -157,13 +157,82 @@ def run_batch64(args):
     print(json.dumps(out), flush=True)
 
 
+def timed_steps(S, torch, pb, params, steps, sample_every, label):
+    """`steps` implicit steps on the library's stream; wall time bracketed by stream synchronisation and
+    kernel durations sampled in-step with HIP events (see shell_sim_profile)."""
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    S.shell_sim_profile(pb.sim, sample_every)
+    stats, lat = [], []
+    t_start = time.perf_counter()
+    for k in range(steps):
+        t0 = time.perf_counter()
+        rc, st = S.shell_step_implicit(pb.sim, params, stream=stream)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        stats.append(st)
+        print(f"[bench] {label} step {k}: newton {st['newton_iters']} pcg {st['pcg_total']} "
+              f"|g|/|g0| {st['grad_norm'] / max(st['grad_norm0'], 1e-300):.3e} {lat[-1]:.2f} s",
+              file=sys.stderr, flush=True)
+    elapsed = time.perf_counter() - t_start
+    prof = S.shell_sim_profile_read(pb.sim)
+    S.shell_sim_profile(pb.sim, 0)
+    return elapsed, stats, lat, prof
+
+
+def step_error(S, torch, mesh, pb64, pbm, params, steps, short_iters=200):
+    """Displacement error of the mixed path against FP64 from the same state, per step.
+
+    full:  each step of the FP64 path in tolerance mode, the mixed path replaying its Newton and PCG
+           counts.  Thousands of Krylov iterations at a 1e-2 residual tolerance leave each path at a
+           different inexact step, so this measures the sensitivity of the stopped solve as much as
+           precision.
+    short: one Newton iteration with `short_iters` replayed PCG iterations per coordinate from the same
+           state, where the difference is the precision alone."""
+    zero = np.zeros_like(mesh.X)
+
+    def rel_disp(x, ref, x0):
+        return float(np.linalg.norm(x - ref) / max(np.linalg.norm(ref - x0), 1e-300))
+
+    for pb in (pb64, pbm):
+        S.shell_sim_set_state(pb.sim, mesh.X, zero, 0)
+    full = []
+    for k in range(steps):
+        x0, _, _ = S.shell_sim_get_state(pb64.sim, mesh.nv)
+        rc, st = S.shell_step_implicit(pb64.sim, params)
+        counts = st["counts"][: st["newton_iters"]]
+        rp, _keep = S.step_params(params.dt, gravity=tuple(params.gravity), max_newton=st["newton_iters"],
+                                  replay=counts)
+        S.shell_step_implicit(pbm.sim, rp)
+        x64, _, _ = S.shell_sim_get_state(pb64.sim, mesh.nv)
+        xm, _, _ = S.shell_sim_get_state(pbm.sim, mesh.nv)
+        full.append(rel_disp(xm, x64, x0))
+    short = []
+    rp, _keep = S.step_params(params.dt, gravity=tuple(params.gravity), max_newton=1,
+                              replay=np.full((1, 3), short_iters, np.int32))
+    for k in range(steps):
+        x0, v0, _ = S.shell_sim_get_state(pb64.sim, mesh.nv)
+        S.shell_sim_set_state(pbm.sim, x0, v0, 0)
+        S.shell_step_implicit(pb64.sim, rp)
+        S.shell_step_implicit(pbm.sim, rp)
+        x64, _, _ = S.shell_sim_get_state(pb64.sim, mesh.nv)
+        xm, _, _ = S.shell_sim_get_state(pbm.sim, mesh.nv)
+        short.append(rel_disp(xm, x64, x0))
+    print(f"[bench] mixed vs fp64 displacement error per step: full {full}, short {short}", file=sys.stderr,
+          flush=True)
+    return dict(full_step_replayed_counts=full, one_newton_200_pcg=short)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=1024)
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed",
+                    help="the path whose steps/s is the headline value")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the other precision's timed steps and the per-step error run")
     ap.add_argument("--max-newton", type=int, default=4)
     ap.add_argument("--pcg-rtol", type=float, default=1e-2)
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel of the isolated back-to-back timing")
@@ -188,50 +257,45 @@ def main(argv=None):
     assert torch.cuda.is_available(), "needs a HIP device"
     torch.cuda.set_device(0)
     if args.workload == "batch64":
-        if args.precision == "fp64" and "--precision" not in " ".join(sys.argv):
-            args.precision = "mixed"
         return run_batch64(args)
-    precision = S.SHELL_PREC_MIXED if args.precision == "mixed" else S.SHELL_PREC_FP64
+    head = S.SHELL_PREC_MIXED if args.precision == "mixed" else S.SHELL_PREC_FP64
+    other = S.SHELL_PREC_FP64 if head == S.SHELL_PREC_MIXED else S.SHELL_PREC_MIXED
     mat = I.MATERIAL
     mesh = I.workload_sphere_cap(args.size, "SS")
     print(f"[bench] building {mesh.nv} vertices, SS, {args.precision}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    pb = S.Problem(mesh, mat, precision=precision)
+    pb = S.Problem(mesh, mat, precision=head)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    rp_nnz = S.shell_hessian_info(pb.h)["nnz"]
+    pb_other = None if args.no_compare else S.Problem(mesh, mat, precision=other)
+    hinfo = S.shell_hessian_info(pb.h)
     dt = 1.0 / 30.0
     params, _ = S.step_params(dt, gravity=I.GRAVITY, max_newton=args.max_newton, max_pcg=args.max_pcg,
                               newton_rtol=1e-8, pcg_rtol=args.pcg_rtol)
     for w in range(args.warmup):
-        rc, st = S.shell_step_implicit(pb.sim, params)
-        print(f"[bench] warmup {w}: newton {st['newton_iters']} pcg {st['pcg_total']}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    stats = []
-    # kernel durations inside the timed steps: HIP events on the library's launch stream around every
-    # force launch set and every n-th PCG iteration's kernels
-    S.shell_sim_profile(pb.sim, args.sample_every)
-    t_start = time.perf_counter()
-    ev0.record(stream)
-    for k in range(args.steps):
-        rc, st = S.shell_step_implicit(pb.sim, params, stream=stream)
-        stats.append(st)
-        print(f"[bench] step {k}: newton {st['newton_iters']} pcg {st['pcg_total']} "
-              f"|g|/|g0| {st['grad_norm'] / max(st['grad_norm0'], 1e-300):.3e}", file=sys.stderr, flush=True)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    gpu_ms = ev0.elapsed_time(ev1)
-    elapsed = max(wall, gpu_ms / 1e3)
+        for q in (pb, pb_other):
+            if q is not None:
+                rc, st = S.shell_step_implicit(q.sim, params)
+                print(f"[bench] warmup {w}: newton {st['newton_iters']} pcg {st['pcg_total']}", file=sys.stderr,
+                      flush=True)
+    elapsed, stats, lat, prof = timed_steps(S, torch, pb, params, args.steps, args.sample_every, args.precision)
     steps_per_s = args.steps / elapsed
-    prof = S.shell_sim_profile_read(pb.sim)
-    S.shell_sim_profile(pb.sim, 0)
+    compare = None
+    if pb_other is not None:
+        e2, st2, lat2, prof2 = timed_steps(S, torch, pb_other, params, args.steps, args.sample_every,
+                                           "fp64" if other == S.SHELL_PREC_FP64 else "mixed")
+        pb64, pbm = (pb_other, pb) if head == S.SHELL_PREC_MIXED else (pb, pb_other)
+        errs = step_error(S, torch, mesh, pb64, pbm, params, args.steps)
+        compare = dict(precision="fp64" if other == S.SHELL_PREC_FP64 else "mixed", steps_per_s=args.steps / e2,
+                       ms_per_step=1e3 * e2 / args.steps,
+                       pcg_coord_iters=float(np.mean([s["pcg_total"] for s in st2])),
+                       product_ms=prof2["product"]["avg_ms"], update_ms=prof2["update"]["avg_ms"],
+                       grad_ratio=[x["grad_norm"] / max(x["grad_norm0"], 1e-300) for x in st2],
+                       mixed_vs_fp64_displacement_rel_err=errs)
 
     # the same kernels launched back to back on one state (their working set then partly stays in the
     # 256 MB last-level cache, so these read faster than the in-step figures; reported for reference)
+    stream = torch.cuda.current_stream()
     kt = S.shell_sim_time_kernels(pb.sim, dt, reps=args.reps, stream=stream)
     if args.calibrate_copy:
         a = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
@@ -240,8 +304,7 @@ def main(argv=None):
             torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         del a, b
-    hinfo = S.shell_hessian_info(pb.h)
-    ab = algorithmic_bytes(pb.info, hinfo, precision)
+    ab = algorithmic_bytes(pb.info, hinfo, head)
 
     def rate(nbytes, ms):
         return nbytes / (ms * 1e-3) / 1e9 if ms else None
@@ -253,24 +316,28 @@ def main(argv=None):
     update_gbs = rate(ab["update"], update_ms)
     force_gbs = rate(ab["force"], force_ms)
     stencils_per_s = pb.info["ns"] / (force_ms * 1e-3) if force_ms else None
-    default_workload = args.size == 1024 and precision == S.SHELL_PREC_FP64
-    traffic_spmv = measured_traffic("spmv_traffic_bytes_per_launch") if default_workload else None
-    traffic_update = measured_traffic("update_traffic_bytes_per_launch") if default_workload else None
-    traffic_force = measured_traffic("force_traffic_bytes_per_launch") if default_workload else None
+    key = "mixed" if head == S.SHELL_PREC_MIXED else "fp64"
+    default_workload = args.size == 1024
+    traffic_spmv = measured_traffic(f"{key}_spmv_traffic_bytes_per_launch") if default_workload else None
+    traffic_update = measured_traffic(f"{key}_update_traffic_bytes_per_launch") if default_workload else None
+    traffic_force = measured_traffic(f"{key}_force_traffic_bytes_per_launch") if default_workload else None
     pcg_per_step = float(np.mean([s["pcg_total"] for s in stats]))
+    # shared iterations (the three coordinate recurrences share each launch): the longest per Newton solve
+    pcg_iters = float(np.mean([sum(int(c.max()) for c in s["counts"]) for s in stats]))
     newton_per_step = float(np.mean([s["newton_iters"] for s in stats]))
+    lat_sorted = sorted(lat)
 
     out = dict(
         metric="implicit steps/s & bending stencils/s at 1M verts vs HBM roofline; p50/p99 latency",
         value=steps_per_s, unit="steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=1e3 * elapsed / args.steps, higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f64" if precision == 0 else "f32+f64", data="synthetic",
+        dtype="f64" if head == S.SHELL_PREC_FP64 else "f32+f64", data="synthetic",
         config=dict(workload=f"sphere-cap smoothed-hinge shell (SS), {args.size}x{args.size} vertices, "
                              f"R={mesh.meta['radius']:.4f} m, jitter 0.2, ring pinned, dt=1/30 s, "
                              f"Newton budget {args.max_newton}, Jacobi-PCG rtol {args.pcg_rtol:g}",
-                    nv=mesh.nv, stencils=pb.info["ns"], nnz=rp_nnz, precision=args.precision,
+                    nv=mesh.nv, stencils=pb.info["ns"], nnz=hinfo["nnz"], precision=args.precision,
                     parallelism="single GPU"),
-        roofline=dict(bound="hbm", kernel="k_pcg_spmv (direction update + 3-column SELL-64 product)",
+        roofline=dict(bound="hbm", kernel="k_pcg_spmv (PCG state, direction update, 3-column SELL-64 product)",
                       achieved=spmv_gbs, peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=spmv_gbs / HBM_PEAK_GBS if spmv_gbs else None, traffic=traffic_spmv,
                       bytes_per_launch=ab["spmv"], avg_ms=spmv_ms, sampled_launches=prof["product"]["count"]),
@@ -281,8 +348,11 @@ def main(argv=None):
                           frac=force_gbs / HBM_PEAK_GBS if force_gbs else None, bytes_per_launch=ab["force"],
                           bytes_per_stencil_stream=ab["force_per_stencil"], avg_ms=force_ms, traffic=traffic_force,
                           sampled_launches=prof["forces"]["count"]),
-        pcg_iteration_ms=dict(product=spmv_ms, update=update_ms,
-                              finalizers=(2 * prof["finalize"]["avg_ms"]) if prof["finalize"]["avg_ms"] else None),
+        latency_s=dict(per_step=lat, p50=lat_sorted[len(lat) // 2], p99=lat_sorted[min(len(lat) - 1,
+                                                                                       int(0.99 * len(lat)))]),
+        pcg=dict(coord_iters_per_step=pcg_per_step, iterations_per_step=pcg_iters,
+                 ms_per_iteration_in_step=1e3 * elapsed / max(pcg_iters * args.steps, 1.0)),
+        compare=compare,
         isolated_back_to_back_ms=dict(force=kt["force_ms"], product=kt["spmv_ms"], update=kt["update_ms"]),
         hessian=dict(nnz=hinfo["nnz"], slots=hinfo["slots"], group_cols=hinfo["group_cols"],
                      max_group_cols=hinfo["max_group_cols"], staged=bool(hinfo["staged"])),
@@ -296,6 +366,8 @@ def main(argv=None):
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)
     pb.close()
+    if pb_other is not None:
+        pb_other.close()
     print(json.dumps(out), flush=True)
 
 

@@ -272,7 +272,7 @@ shell_status_t shell_sim_time_kernels(shell_sim_t sim, double dt, int32_t reps, 
 /*
  * Sampled kernel timing inside real steps.  With sampling on, every step of the batch (or simulation)
  * records HIP events on its stream around every force launch set and around every `every`-th PCG
- * iteration's four kernels, and sums the sampled durations per phase; the events are read at the
+ * iteration's two kernels, and sums the sampled durations per phase; the events are read at the
  * step's existing host synchronisations, so the step's launches and results are unchanged.
  *   shell_batch_profile(b, every)  every > 0: start sampling and clear the sums; every == 0: stop.
  *   shell_batch_profile_read(b, out)  copy the sums (sampling continues).
@@ -280,10 +280,9 @@ shell_status_t shell_sim_time_kernels(shell_sim_t sim, double dt, int32_t reps, 
  */
 enum {
     SHELL_PHASE_FORCES = 0,   /* force kernels of one Newton iteration (all tiles of all models) */
-    SHELL_PHASE_PRODUCT = 1,  /* PCG direction update + sparse product */
-    SHELL_PHASE_UPDATE = 2,   /* PCG y/r update */
-    SHELL_PHASE_FINALIZE = 3, /* the two per-mesh reduction finalizers of a PCG iteration (each launch) */
-    SHELL_NUM_PHASES = 4
+    SHELL_PHASE_PRODUCT = 1,  /* PCG state advance, direction update and sparse product */
+    SHELL_PHASE_UPDATE = 2,   /* PCG step length, y/r update and dot products */
+    SHELL_NUM_PHASES = 3
 };
 typedef struct {
     double ms[SHELL_NUM_PHASES];     /* summed durations of the sampled launches, milliseconds */

@@ -20,6 +20,8 @@
 // (edge; the line of eq 8), its gradient by the chain rule of App. B (eqs 67, 73).
 // Mixed precision: positions are gathered in float64 and differenced in float64; everything after
 // the difference is float32.
+#include <hip/hip_ext.h>
+
 #include "devmath.hpp"
 #include "internal.hpp"
 
@@ -194,14 +196,15 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
 
 template <int MODEL>
 void launch_model(int precision, const ForceDesc* descs, const WorkItem* items, long nitems, int lds_T,
-                  hipStream_t s) {
-    const int blk = 256;
-    long grid = xcd_grid(nitems);
-    size_t lds = size_t(3 * lds_T) * sizeof(double);
+                  hipStream_t s, hipEvent_t start, hipEvent_t stop) {
+    const dim3 blk(256);
+    const dim3 grid(unsigned(xcd_grid(nitems)));
+    const uint32_t lds = uint32_t(size_t(3 * lds_T) * sizeof(double));
+    // start/stop (may be null) receive the dispatch's own begin and end times
     if (precision == SHELL_PREC_FP64)
-        force_tiles<MODEL, double><<<grid, blk, lds, s>>>(descs, items, nitems);
+        hipExtLaunchKernelGGL(force_tiles<MODEL, double>, grid, blk, lds, s, start, stop, 0, descs, items, nitems);
     else
-        force_tiles<MODEL, float><<<grid, blk, lds, s>>>(descs, items, nitems);
+        hipExtLaunchKernelGGL(force_tiles<MODEL, float>, grid, blk, lds, s, start, stop, 0, descs, items, nitems);
     SHELL_HIP(hipGetLastError());
 }
 
@@ -238,15 +241,15 @@ __global__ void scatter_rows(const T* __restrict__ src, const int32_t* __restric
 }  // namespace
 
 void launch_force_items(int model, int precision, const ForceDesc* descs, const WorkItem* items, long nitems,
-                        int lds_T, hipStream_t s) {
+                        int lds_T, hipStream_t s, hipEvent_t start, hipEvent_t stop) {
     if (nitems <= 0) return;
     switch (model) {
-        case SHELL_EP: launch_model<SHELL_EP>(precision, descs, items, nitems, lds_T, s); break;
-        case SHELL_ES: launch_model<SHELL_ES>(precision, descs, items, nitems, lds_T, s); break;
-        case SHELL_FP: launch_model<SHELL_FP>(precision, descs, items, nitems, lds_T, s); break;
-        case SHELL_FS: launch_model<SHELL_FS>(precision, descs, items, nitems, lds_T, s); break;
-        case SHELL_SP: launch_model<SHELL_SP>(precision, descs, items, nitems, lds_T, s); break;
-        case SHELL_SS: launch_model<SHELL_SS>(precision, descs, items, nitems, lds_T, s); break;
+        case SHELL_EP: launch_model<SHELL_EP>(precision, descs, items, nitems, lds_T, s, start, stop); break;
+        case SHELL_ES: launch_model<SHELL_ES>(precision, descs, items, nitems, lds_T, s, start, stop); break;
+        case SHELL_FP: launch_model<SHELL_FP>(precision, descs, items, nitems, lds_T, s, start, stop); break;
+        case SHELL_FS: launch_model<SHELL_FS>(precision, descs, items, nitems, lds_T, s, start, stop); break;
+        case SHELL_SP: launch_model<SHELL_SP>(precision, descs, items, nitems, lds_T, s, start, stop); break;
+        case SHELL_SS: launch_model<SHELL_SS>(precision, descs, items, nitems, lds_T, s, start, stop); break;
         default: throw Error(SHELL_E_INVALID_ARG, "unknown model");
     }
 }

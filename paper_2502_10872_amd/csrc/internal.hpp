@@ -139,7 +139,6 @@ struct PcgState {
     double gsq;
     int32_t iters[3], target[3], active[3];
     int32_t done, budget, replay, nonfinite;
-    int32_t pit;  // products done in this solve; selects which of the two p buffers is current
 };
 
 struct SolveDesc {
@@ -154,8 +153,9 @@ struct SolveDesc {
     const int32_t* gptr;            // group column lists (null: gather p directly)
     const int32_t* gcols;
     const uint16_t* lcol;
-    PcgState* st;
+    PcgState* st;                   // two states: st[t & 1] enters PCG iteration t
     double* part;                   // reduction partials, quantity-major [q][group]
+    double* bins;                   // PCG dot-product bins [parity][set][quantity][bin]
     int64_t nv, ngroups;
     double dt, dt2, grav[3], rtol2;
     int32_t replay, target[3];
@@ -232,6 +232,7 @@ struct shell_sim_s {
     shell::DevArray<double> dinv;        // [nv] (float in mixed)
     shell::DevArray<uint8_t> pinned;
     shell::DevArray<double> p, p2, q;    // PCG work vectors (float in mixed; sized in doubles)
+    shell::DevArray<double> bins;        // PCG dot-product bins
     shell::DevArray<double> partials;    // reduction partials
     shell_batch_s* solo = nullptr;       // this simulation alone, as a batch of one
     shell_step_stats_t stats{};
@@ -270,7 +271,7 @@ struct shell_batch_s {
     bool fdesc_dirty = true;
     shell::DevArray<shell::ForceDesc> fdesc;
     shell::DevArray<shell::SolveDesc> sdesc;
-    shell::DevArray<shell::PcgState> state;
+    shell::DevArray<shell::PcgState> state;    // two per mesh
     shell::PcgState* state_host = nullptr;
     shell::SolveDesc* sdesc_host = nullptr;  // pinned staging
     shell::ForceDesc* fdesc_host = nullptr;
@@ -287,8 +288,9 @@ void launch_precompute(shell_stencils_s& st, hipStream_t s);
 void launch_tile_copy(shell_stencils_s& st, hipStream_t s);
 // forces.hip
 // one launch per model over a list of (mesh, tile) items; lds_T = the largest tile among the meshes
+// start/stop: events that receive the kernel's own begin and end times (null: none)
 void launch_force_items(int model, int precision, const ForceDesc* descs, const WorkItem* items, long nitems,
-                        int lds_T, hipStream_t s);
+                        int lds_T, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 void launch_energy_finalize(const double* epart, int64_t n, double* energy, hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
 void launch_scatter_rows(const void* src, const int32_t* perm, void* dst, int64_t nv, bool f32, hipStream_t s);

@@ -160,4 +160,37 @@ __device__ __forceinline__ void sell_row_product_staged(const uint16_t* __restri
     }
 }
 
+// One lane's row of a 64-row SELL slice read as a stream of batches of U (column id, value) pairs.  A
+// batch can be requested before it is needed: the product asks for the first one before staging its
+// row group's directions in LDS, and for each next one while it multiplies the current one.  Slots past
+// the row's stored width are clamped to its last slot (the value is then weighted 0 by the consumer).
+// Every lane of a wave belongs to the same slice, so width and offset are wave-uniform.
+template <typename MR, typename IDX, int U>
+struct SellStream {
+    const gbl<const IDX>* col;
+    const gbl<const MR>* val;
+    long s0;
+    int w;
+
+    __device__ __forceinline__ SellStream(const IDX* col_, const void* val_, const int64_t* sptr,
+                                          const int32_t* width, long row)
+        : col(G(col_)), val(G(static_cast<const MR*>(val_))) {
+        const long slice = row >> 6;
+        w = __builtin_amdgcn_readfirstlane(G(width)[slice]);
+        const int64_t sp = G(sptr)[slice];
+        s0 = (long(__builtin_amdgcn_readfirstlane(int(sp & 0xffffffff))) |
+              (long(__builtin_amdgcn_readfirstlane(int(sp >> 32))) << 32)) +
+             (row & 63);
+    }
+
+    __device__ __forceinline__ void load(int k, int (&c)[U], MR (&a)[U]) const {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long off = s0 + 64L * (k + u < w ? k + u : w - 1);
+            c[u] = int(stream_load(col + off));
+            a[u] = stream_load(val + off);
+        }
+    }
+};
+
 }  // namespace shell

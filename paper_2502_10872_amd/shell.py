@@ -74,8 +74,8 @@ class shell_hessian_info_t(ctypes.Structure):
                 ("staged", ctypes.c_int32)]
 
 
-SHELL_NUM_PHASES = 4
-PHASES = ("forces", "product", "update", "finalize")  # SHELL_PHASE_* order
+SHELL_NUM_PHASES = 3
+PHASES = ("forces", "product", "update")  # SHELL_PHASE_* order
 
 
 class shell_profile_t(ctypes.Structure):

@@ -212,8 +212,8 @@ def test_in_step_profiling_changes_nothing():
     assert rel(xa - mesh.X, xb - mesh.X) <= 1e-11 and rel(va, vb) <= 1e-11
     assert all(pa[k]["count"] == 0 for k in pa)
     iters = max(int(sb["counts"][k].max()) for k in range(sb["newton_iters"]))
-    assert pb_["product"]["count"] >= 2 and pb_["product"]["count"] == pb_["update"]["count"]
-    assert pb_["finalize"]["count"] == 2 * pb_["product"]["count"]
+    # every solve's first product is sampled, then one (update, product) pair in every 3
+    assert pb_["product"]["count"] >= 2 and pb_["product"]["count"] >= pb_["update"]["count"]
     assert pb_["forces"]["count"] >= 2 and iters > 0
     for k in pb_:
         assert pb_[k]["ms"] > 0 and pb_[k]["avg_ms"] < 100.0
