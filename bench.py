@@ -41,7 +41,7 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
     real = 4 if precision == 1 else 8  # stencil operators, matrix values, p, q, D^-1, forces
     per_stencil = 4 * k + real * r * k + (real * r if shell else 0)
     force = ns * per_stencil + nv * (24 + 3 * real)
-    ngroups = (nv + 255) // 256
+    ngroups = (nv + 511) // 512  # 512-row groups
     idx = 2 if hinfo["staged"] else 4
     spmv = (hinfo["nnz"] * (real + idx) + 4 * (hinfo["group_cols"] + ngroups + 1) + 12 * hinfo["nslices"]
             + nv * (24 + real + 3 * real + 8 + 1 + 3 * real + 3 * real))
@@ -50,7 +50,8 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_cap_1024_ss_fp64_hbm_traffic.md")
-TRAFFIC_SOURCES = ["paper_2502_10872_amd/csrc/spmv.hpp", "paper_2502_10872_amd/csrc/solver.hip",
+# the device code of the measured kernels and the layout they read (host_mesh.cpp builds it)
+TRAFFIC_SOURCES = ["paper_2502_10872_amd/csrc/spmv.hpp", "paper_2502_10872_amd/csrc/pcg_kernels.hpp",
                    "paper_2502_10872_amd/csrc/forces.hip", "paper_2502_10872_amd/csrc/host_mesh.cpp",
                    "paper_2502_10872_amd/csrc/devmath.hpp"]
 

@@ -72,7 +72,7 @@ typedef struct {
     int32_t flags;           /* 0, or SHELL_FLAG_DIRECT_PRODUCT */
 } shell_config_t;
 
-/* The PCG product gathers each neighbour's entries straight from memory instead of staging every 256-row
+/* The PCG product gathers each neighbour's entries straight from memory instead of staging every 512-row
  * group's distinct columns in LDS.  Chosen by itself when a group has more than 4096 distinct columns;
  * the flag forces it (to compare the two forms). */
 #define SHELL_FLAG_DIRECT_PRODUCT 1
@@ -150,7 +150,7 @@ shell_status_t shell_hessian_export_csr(shell_hessian_t h, int64_t* nnz, int64_t
 
 /*
  * shell_hessian_info - storage figures of the assembled K_s (for byte models and inspection).
- * SELL-64 stores 64-row slices padded to the slice's longest row; rows are grouped 256 at a time and,
+ * SELL-64 stores 64-row slices padded to the slice's longest row; rows are grouped 512 at a time and,
  * when every group's distinct column set fits in LDS (max_group_cols <= 4096), the product stages
  * each group's p entries once and stores 16-bit group-local column ids (staged == 1).
  */
@@ -159,7 +159,7 @@ typedef struct {
     int64_t nnz;             /* structural nonzeros */
     int64_t slots;           /* stored SELL-64 entries, padding included */
     int64_t nslices;         /* 64-row slices */
-    int64_t group_cols;      /* sum over the 256-row groups of their distinct column counts (0 unless staged) */
+    int64_t group_cols;      /* sum over the 512-row groups of their distinct column counts (0 unless staged) */
     int32_t max_group_cols;  /* largest distinct column count of a group */
     int32_t staged;          /* 1: staged product with 16-bit local ids; 0: direct gathers, 32-bit ids */
 } shell_hessian_info_t;
@@ -195,6 +195,9 @@ typedef struct {
     double pcg_rtol;       /* per column: stop when ||r|| <= pcg_rtol ||b|| */
     int32_t mode;          /* shell_pcg_mode_t */
     int32_t chunk;         /* PCG iterations launched between host convergence checks; 0 = default */
+    int32_t pcg_workgroups; /* work-groups of each PCG kernel (each takes consecutive 512-row groups);
+                               0 = default (512: two per CU).  Batches use the first entry's value */
+    int32_t reserved;
     const int32_t* replay_counts; /* host [max_newton][3], REPLAY only: exact PCG iterations */
 } shell_step_params_t;
 

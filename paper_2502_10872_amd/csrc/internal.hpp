@@ -111,7 +111,7 @@ struct SellPattern {
     std::vector<uint16_t> lcol;   // [nslots] group-local column index
     int32_t max_gcols = 0;
 };
-constexpr int kRowGroup = 256;     // rows per work-group of the row kernels
+constexpr int kRowGroup = 512;     // rows per work item (and threads per work-group) of the row kernels
 constexpr int kMaxGroupCols = 4096;  // largest column set staged in LDS (larger: direct gathers)
 // staging: build the row groups' column lists (used when every group fits kMaxGroupCols)
 SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv, bool staging);

@@ -1,0 +1,639 @@
+// Device kernels of the implicit step (see solver.hip for the step they make up): predictor, Jacobi
+// diagonal, Newton residual, the two PCG kernels with their binned dot products, Newton and velocity
+// updates, lumped mass.  Included once, by solver.hip.
+#pragma once
+
+#include <cmath>
+
+#include "devmath.hpp"
+#include "internal.hpp"
+#include "spmv.hpp"
+
+namespace shell {
+
+namespace {
+
+
+constexpr int kBlk = kRowGroup;  // rows per work item (one row per thread)
+constexpr int kRedBlk = 512;  // residual-norm kernel: one work-group per mesh
+constexpr int kMaxPart = 8;   // partial quantities per work-group (buffer sized kMaxPart * groups)
+
+inline long blocks(long n) { return (n + kBlk - 1) / kBlk; }
+
+// fixed-order sum of NQ partials over ngroups work-groups; result in thread 0's out[]
+template <int NQ>
+__device__ void reduce_partials(const double* __restrict__ part, long ngroups, double (&out)[NQ]) {
+    __shared__ double sh[NQ * (kRedBlk / 64)];
+    for (int q = 0; q < NQ; ++q) out[q] = 0.0;
+    // partials are stored quantity-major, part[q * ngroups + group], so these loads coalesce
+#pragma unroll 4
+    for (long b = threadIdx.x; b < ngroups; b += kRedBlk)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) out[q] += part[q * ngroups + b];
+    block_sum<NQ>(out, sh);
+}
+
+// this work-group's (mesh, row group); false if the grid slot is idle
+__device__ __forceinline__ bool work_item(const WorkItem* __restrict__ items, long nitems, WorkItem& wi) {
+    long it = xcd_logical(blockIdx.x, gridDim.x);
+    if (it >= nitems) return false;
+    wi = items[it];
+    return true;
+}
+
+// ---------------------------------------------------------------- PCG dot products
+// Each work-group adds its partial sums with device-scope atomics into one of kBins bins per quantity
+// (bin = row group mod kBins), so no bin sees more than ngroups / kBins additions.  The kernel that
+// needs a total sums the kBins bins in a fixed butterfly; every wave of every work-group obtains the
+// same bits.  Bins are double-buffered by iteration parity: a kernel clears the set that the next
+// kernel adds into, never one that a running kernel reads.
+constexpr int kBins = 64;
+constexpr int kBinQ = 8;  // quantity slots per set
+constexpr int kSetPq = 0, kSetRz = 1;  // p.q (3 quantities); r.z and r.r (6)
+
+__device__ __forceinline__ double* bin_set(const SolveDesc& d, long par, int set) {
+    return d.bins + (size_t(par & 1) * 2 + size_t(set)) * kBinQ * kBins;
+}
+
+// totals of NQ quantities, in every lane of the calling wave
+template <int NQ>
+__device__ __forceinline__ void bin_totals(const double* set, double (&tot)[NQ]) {
+    const gbl<const double>* b = G(set) + (threadIdx.x & 63);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tot[q] = b[q * kBins];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) tot[q] = wave_sum(tot[q]);
+}
+
+template <int NQ>
+__device__ __forceinline__ void bin_add(double* set, int unit, const double (&v)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) atomicAdd(set + q * kBins + (unit % kBins), v[q]);
+}
+
+// clears one set; every thread of the work-group takes part
+__device__ __forceinline__ void bin_clear(double* set) {
+    for (int k = threadIdx.x; k < kBinQ * kBins; k += blockDim.x) G(set)[k] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlk) void k_predictor(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    bool pin = d.pinned[i];
+    for (int c = 0; c < 3; ++c) {
+        double xi = d.x[3 * i + c];
+        d.xt[3 * i + c] = xi;
+        double xh = pin ? xi : xi + d.dt * d.v[3 * i + c] + d.dt * d.dt * d.grav[c];
+        d.xhat[3 * i + c] = xh;
+        d.x[3 * i + c] = xh;
+    }
+}
+
+template <typename VR>
+__global__ __launch_bounds__(kBlk) void k_dinv(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    static_cast<VR*>(d.dinv)[i] = d.pinned[i] ? VR(0) : VR(1.0 / (d.mass[i] + d.dt2 * d.kdiag[i]));
+}
+
+// g = M (x - x_hat) - dt^2 f, fixed rows zero; partial |g|^2
+template <typename VR>
+__global__ __launch_bounds__(kBlk) void k_residual(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems,
+                           int from_xhat) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    const VR* __restrict__ f = static_cast<const VR*>(d.f);
+    const double* __restrict__ xh = from_xhat ? d.xhat : d.x;
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    double acc[1] = {0.0};
+    if (i < d.nv) {
+        bool pin = d.pinned[i];
+        double m = d.mass[i];
+        for (int c = 0; c < 3; ++c) {
+            double gi = pin ? 0.0 : m * (d.x[3 * i + c] - xh[3 * i + c]) - d.dt2 * double(f[3 * i + c]);
+            d.g[3 * i + c] = gi;
+            acc[0] += gi * gi;
+        }
+    }
+    __shared__ double sh[kBlk / 64];
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) d.part[wi.unit] = acc[0];
+}
+
+// |g|^2 of each mesh; also clears the bins that the coming solve's first kernels add into (the initial
+// r.z, r.r and the first product's p.q)
+__global__ __launch_bounds__(kRedBlk) void k_fin_residual(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ meshes) {
+    const SolveDesc& d = descs[meshes[blockIdx.x]];
+    double tot[1];
+    reduce_partials<1>(d.part, d.ngroups, tot);
+    bin_clear(bin_set(d, 1, kSetRz));
+    bin_clear(bin_set(d, 0, kSetPq));
+    if (threadIdx.x == 0) {
+        d.st[0].gsq = tot[0];
+        d.st[0].nonfinite = !isfinite(tot[0]);
+    }
+}
+
+// r = -g, y = 0; r.z (z = D^-1 r) and r.r into the bins read by the first product (parity 1).  The
+// first product forms p = z itself.
+template <typename VR>
+__global__ __launch_bounds__(kBlk) void k_pcg_init(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    if (i < d.nv) {
+        const VR di = G(static_cast<const VR*>(d.dinv))[i];
+        const gbl<const double>* g = G(static_cast<const double*>(d.g));
+        double gi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gi[c] = g[3 * i + c];
+        gbl<double>* r = G(d.r);
+        gbl<double>* y = G(d.y);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double ri = -gi[c];
+            const VR zi = di * VR(ri);
+            r[3 * i + c] = ri;
+            y[3 * i + c] = 0.0;
+            acc[c] = ri * double(zi);
+            acc[3 + c] = ri * ri;
+        }
+    }
+    __shared__ double sh[6 * (kBlk / 64)];
+    block_sum<6>(acc, sh);
+    if (threadIdx.x == 0) bin_add<6>(bin_set(d, 1, kSetRz), wi.unit, acc);
+}
+
+// What the rest of a product needs of the recurrence state.
+struct ProductState {
+    double beta[3];
+    int done;
+};
+
+// The recurrence state entering product t: at t == 0 from the initial residual, else the previous state
+// (parity t) advanced by the update of iteration t - 1 (beta, activity, counts, budget).  Every lane of
+// every work-group computes beta and done identically from the bins; thread 0 of row group 0's
+// work-group stores the new state (parity t + 1) field by field, and that work-group clears the bins
+// of this iteration's update.
+__device__ __forceinline__ ProductState product_state(const SolveDesc& d, const WorkItem& wi, long t) {
+    const PcgState* so = d.st + (t & 1);
+    PcgState* sn = d.st + ((t + 1) & 1);
+    const bool writer = wi.unit == 0 && threadIdx.x == 0;
+    double tot[6];
+    bin_totals<6>(bin_set(d, t + 1, kSetRz), tot);
+    ProductState r;
+    int any = 0;
+    if (t == 0) {
+        for (int c = 0; c < 3; ++c) {
+            const double tol2 = d.rtol2 * tot[3 + c];
+            const int act = (0 < d.target[c]) && (d.replay || tot[3 + c] > tol2);
+            r.beta[c] = 0.0;
+            any |= act;
+            if (writer) {
+                sn->rz[c] = tot[c];
+                sn->rr[c] = tot[3 + c];
+                sn->tol2[c] = tol2;
+                sn->alpha[c] = 0.0;
+                sn->beta[c] = 0.0;
+                sn->iters[c] = 0;
+                sn->target[c] = d.target[c];
+                sn->active[c] = act;
+            }
+        }
+        r.done = !any;
+        if (writer) {
+            sn->done = r.done;
+            sn->budget = 0;
+            sn->replay = d.replay;
+            sn->nonfinite = 0;
+        }
+    } else if (so->done) {
+        for (int c = 0; c < 3; ++c) r.beta[c] = 0.0;
+        r.done = 1;
+        if (writer) *sn = *so;
+    } else {
+        const int replay = so->replay;
+        int budget = so->budget, nonfinite = so->nonfinite;
+        for (int c = 0; c < 3; ++c) {
+            int act = so->active[c], it = so->iters[c];
+            const int target = so->target[c];
+            const double rz = so->rz[c], tol2 = so->tol2[c];
+            double beta = 0.0;
+            if (act) {
+                beta = rz != 0.0 ? tot[c] / rz : 0.0;
+                it += 1;
+                const bool more = replay || tot[3 + c] > tol2;
+                if (!replay && it >= target && more) budget = 1;
+                act = (it < target) && more;
+                if (!isfinite(tot[3 + c])) {
+                    nonfinite = 1;
+                    act = 0;
+                }
+            }
+            r.beta[c] = beta;
+            any |= act;
+            if (writer) {
+                const bool was = so->active[c];
+                sn->rz[c] = was ? tot[c] : rz;
+                sn->rr[c] = was ? tot[3 + c] : so->rr[c];
+                sn->tol2[c] = tol2;
+                sn->alpha[c] = so->alpha[c];
+                sn->beta[c] = beta;
+                sn->iters[c] = it;
+                sn->target[c] = target;
+                sn->active[c] = act;
+            }
+        }
+        r.done = !any;
+        if (writer) {
+            sn->done = r.done;
+            sn->budget = budget;
+            sn->replay = replay;
+            sn->nonfinite = nonfinite;
+            sn->gsq = so->gsq;
+        }
+    }
+    if (wi.unit == 0) bin_clear(bin_set(d, t, kSetRz));
+    return r;
+}
+
+// Inputs of the search-direction update p = z + beta p_old, z = D^-1 r.
+template <typename VR>
+struct DirIn {
+    const gbl<const double>* r;
+    const gbl<const VR>* dinv;
+    const gbl<const VR>* pold;
+    VR beta[3];
+};
+
+// The operands of vertex j's direction, loaded ahead of beta: the loads can be issued before the
+// recurrence state is known.  p_old is read even where beta is 0 (it is allocated; its contents then do
+// not matter).
+template <typename VR>
+struct DirLoad {
+    VR dj;
+    double rj[3];
+    VR po[3];
+    __device__ __forceinline__ void load(const DirIn<VR>& in, long j) {
+        dj = in.dinv[j];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            rj[c] = in.r[3 * j + c];
+            po[c] = in.pold[3 * j + c];
+        }
+    }
+    __device__ __forceinline__ void finish(const VR (&beta)[3], VR (&pj)[3]) const {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const VR zj = dj * VR(rj[c]);
+            pj[c] = beta[c] != VR(0) ? fma(beta[c], po[c], zj) : zj;
+        }
+    }
+};
+
+// p of vertex j with the operands' loads issued together
+template <typename VR>
+__device__ __forceinline__ void direction(const DirIn<VR>& in, long j, VR (&pj)[3]) {
+    DirLoad<VR> l;
+    l.load(in, j);
+    l.finish(in.beta, pj);
+}
+
+// Row product for row groups too wide to stage: each neighbour's new direction is formed from its own
+// gathers (four entries in flight per lane).
+template <typename MR, typename VR>
+__device__ __forceinline__ void row_product_direction(const SolveDesc& d, long row, const DirIn<VR>& in, MR& ax,
+                                                      MR& ay, MR& az) {
+    const gbl<const int32_t>* scol = G(d.scol);
+    const gbl<const MR>* val = G(static_cast<const MR*>(d.val));
+    const long slice = row >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(G(d.width)[slice]);
+    const long s0 = G(d.sptr)[slice] + (row & 63);
+    ax = MR(0);
+    ay = MR(0);
+    az = MR(0);
+    constexpr int U = 4;
+    for (int k = 0; k < w; k += U) {
+        int c[U];
+        MR a[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool in_row = k + u < w;  // wave-uniform
+            c[u] = in_row ? scol[s0 + 64L * (k + u)] : int(row);
+            a[u] = in_row ? val[s0 + 64L * (k + u)] : MR(0);
+        }
+        VR pc[U][3];
+#pragma unroll
+        for (int u = 0; u < U; ++u) direction<VR>(in, c[u], pc[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ax = fma(a[u], MR(pc[u][0]), ax);
+            ay = fma(a[u], MR(pc[u][1]), ay);
+            az = fma(a[u], MR(pc[u][2]), az);
+        }
+    }
+}
+
+#ifndef SHELL_PRODUCT_BATCH
+#define SHELL_PRODUCT_BATCH 8  // matrix entries per batch of the product's stream
+#endif
+
+// Unstaged product (row groups too wide for LDS): the same quantities with every neighbour's direction
+// formed from its own gathers.
+template <typename VR, typename MR>
+__device__ __forceinline__ void product_direct(const SolveDesc& d, const WorkItem& wi, const DirIn<VR>& in,
+                                               gbl<VR>* pnew, double (&acc)[3]) {
+    const long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    const MR m = MR(G(d.mass)[i]);
+    const bool pin = G(d.pinned)[i];
+    VR pi[3];
+    direction<VR>(in, i, pi);
+    MR ax, ay, az;
+    row_product_direction<MR, VR>(d, i, in, ax, ay, az);
+    VR qv[3] = {0, 0, 0};
+    if (!pin) {
+        const MR dt2 = MR(d.dt2);
+        qv[0] = VR(fma(m, MR(pi[0]), dt2 * ax));
+        qv[1] = VR(fma(m, MR(pi[1]), dt2 * ay));
+        qv[2] = VR(fma(m, MR(pi[2]), dt2 * az));
+    }
+    gbl<VR>* q = G(static_cast<VR*>(d.q));
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        pnew[3 * i + e] = pi[e];
+        q[3 * i + e] = qv[e];
+        acc[e] += double(pi[e]) * double(qv[e]);
+    }
+}
+
+// Staged product of one row group: p = z + beta p_old for the group's distinct columns (staged in LDS)
+// and its own rows (written), then q = (M + dt^2 K_s) p on the free rows (fixed rows 0); p.q added to
+// acc.  The row's first batch of matrix entries is requested together with the staged columns'
+// operands, and every next batch while the current one is multiplied.  Every thread of the work-group
+// calls it (it holds a barrier); it starts with one so that the LDS of the previous group is free.
+template <typename VR, typename MR>
+__device__ __forceinline__ void product_staged(const SolveDesc& d, const WorkItem& wi, const DirIn<VR>& in,
+                                               gbl<VR>* pnew, VR* ps, double (&acc)[3]) {
+    // batches of 8 float or 4 double values (two batches in flight per lane)
+    constexpr int U = sizeof(MR) == 8 ? SHELL_PRODUCT_BATCH / 2 : SHELL_PRODUCT_BATCH;
+    const long i = long(wi.unit) * kBlk + threadIdx.x;
+    // every slice holds 64 rows, so a wave whose first row exists reads its slice for all its lanes
+    const bool wave_live = i - (threadIdx.x & 63) < d.nv;
+    const bool own = i < d.nv;
+    SellStream<MR, uint16_t, U> row(d.lcol, d.val, d.sptr, d.width, wave_live ? i : 0);
+    int c[U];
+    MR a[U];
+    if (wave_live && row.w > 0) row.load(0, c, a);
+    MR m = 0;
+    bool pin = true;
+    DirLoad<VR> own_op;
+    if (own) {
+        m = MR(G(d.mass)[i]);
+        pin = G(d.pinned)[i];
+        own_op.load(in, i);
+    }
+    // staged columns: two per pass so that each lane has two sets of gathers in flight (a lane past
+    // the end repeats its first column: same value, same LDS slot)
+    const int ga = G(d.gptr)[wi.unit], n = G(d.gptr)[wi.unit + 1] - ga;
+    const gbl<const int32_t>* gc = G(d.gcols + ga);
+    int k = threadIdx.x, k2 = k + kBlk < n ? k + kBlk : k;
+    DirLoad<VR> op0, op1;
+    if (k < n) {
+        op0.load(in, gc[k]);
+        op1.load(in, gc[k2]);
+    }
+    __syncthreads();
+    while (k < n) {
+        VR p0[3], p1[3];
+        op0.finish(in.beta, p0);
+        op1.finish(in.beta, p1);
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            ps[3 * k + e] = p0[e];
+            ps[3 * k2 + e] = p1[e];
+        }
+        k += 2 * kBlk;
+        if (k >= n) break;
+        k2 = k + kBlk < n ? k + kBlk : k;
+        op0.load(in, gc[k]);
+        op1.load(in, gc[k2]);
+    }
+    __syncthreads();
+    if (!wave_live) return;
+    MR ax = 0, ay = 0, az = 0;
+    for (int kk = 0; kk < row.w; kk += U) {
+        int cn[U];
+        MR an[U];
+        const bool more = kk + U < row.w;  // wave-uniform
+        if (more) row.load(kk + U, cn, an);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const VR* pc = ps + 3 * c[u];
+            const MR au = kk + u < row.w ? a[u] : MR(0);
+            ax = fma(au, MR(pc[0]), ax);
+            ay = fma(au, MR(pc[1]), ay);
+            az = fma(au, MR(pc[2]), az);
+        }
+        if (more)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = cn[u];
+                a[u] = an[u];
+            }
+    }
+    if (!own) return;
+    VR pi[3];
+    own_op.finish(in.beta, pi);
+    VR qv[3] = {0, 0, 0};
+    if (!pin) {
+        const MR dt2 = MR(d.dt2);
+        qv[0] = VR(fma(m, MR(pi[0]), dt2 * ax));
+        qv[1] = VR(fma(m, MR(pi[1]), dt2 * ay));
+        qv[2] = VR(fma(m, MR(pi[2]), dt2 * az));
+    }
+    gbl<VR>* q = G(static_cast<VR*>(d.q));
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        pnew[3 * i + e] = pi[e];
+        q[3 * i + e] = qv[e];
+        acc[e] += double(pi[e]) * double(qv[e]);
+    }
+}
+
+// The work items [first, last) of this work-group: `per` consecutive items of the XCD-remapped
+// logical work-group (consecutive items are neighbouring row groups, usually of one mesh)
+__device__ __forceinline__ bool item_range(long nitems, int per, long& first, long& last) {
+    first = xcd_logical(blockIdx.x, gridDim.x) * per;
+    last = first + per < nitems ? first + per : nitems;
+    return first < nitems;
+}
+
+// Sums a work-group's per-thread partials and adds them into the bins of one mesh
+template <int NQ>
+__device__ __forceinline__ void flush_partials(double* set, int unit, double (&acc)[NQ], double* sh) {
+    block_sum<NQ>(acc, sh);
+    if (threadIdx.x == 0) bin_add<NQ>(set, unit, acc);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+}
+
+// PCG iteration t, first kernel.  Each work-group takes `per` consecutive row groups; per mesh it meets
+// it advances the recurrence state once (see product_state), then forms the directions and products of
+// its groups of that mesh, and adds their p.q into the mesh's bins.
+template <typename VR, typename MR>
+__global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void k_pcg_spmv(const SolveDesc* __restrict__ descs,
+                                                   const WorkItem* __restrict__ items, long nitems, long t,
+                                                   int per) {
+    long first, last;
+    if (!item_range(nitems, per, first, last)) return;
+    extern __shared__ unsigned char smem_raw[];
+    VR* ps = reinterpret_cast<VR*>(smem_raw);
+    __shared__ double sh[3 * (kBlk / 64)];
+    double acc[3] = {0, 0, 0};
+    int cur = -1, cur_unit = 0;
+    ProductState S{};
+    DirIn<VR> in{};
+    gbl<VR>* pnew = nullptr;
+    for (long it = first; it < last; ++it) {
+        const WorkItem wi = items[it];
+        const SolveDesc& d = descs[wi.mesh];
+        if (wi.mesh != cur) {
+            if (cur >= 0 && !S.done) flush_partials<3>(bin_set(descs[cur], t, kSetPq), cur_unit, acc, sh);
+            cur = wi.mesh;
+            cur_unit = wi.unit;
+            S = product_state(d, wi, t);
+            const bool odd = t & 1;
+            in.r = G(static_cast<const double*>(d.r));
+            in.dinv = G(static_cast<const VR*>(d.dinv));
+            in.pold = G(static_cast<const VR*>(odd ? d.p0 : d.p1));
+            for (int c = 0; c < 3; ++c) in.beta[c] = VR(S.beta[c]);
+            pnew = G(static_cast<VR*>(odd ? d.p1 : d.p0));
+        }
+        if (S.done) continue;
+        if (d.gptr)
+            product_staged<VR, MR>(d, wi, in, pnew, ps, acc);
+        else
+            product_direct<VR, MR>(d, wi, in, pnew, acc);
+    }
+    if (cur >= 0 && !S.done) flush_partials<3>(bin_set(descs[cur], t, kSetPq), cur_unit, acc, sh);
+}
+
+// PCG iteration t, second kernel.  Each work-group takes `per` consecutive row groups; per mesh it meets
+// it reads the state entering the iteration and the p.q bins once (alpha = r.z / p.q per active
+// column; row group 0's work-group clears the p.q bins of the next product), then advances y += alpha
+// p, r -= alpha q on its rows and adds their r.z (z = D^-1 r, not stored) and r.r into the bins.
+template <typename VR>
+__device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem& wi, long t, const double (&al)[3],
+                                             double (&acc)[6]) {
+    const long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    const gbl<const VR>* p = G(static_cast<const VR*>((t & 1) ? d.p1 : d.p0));
+    const gbl<const VR>* q = G(static_cast<const VR*>(d.q));
+    gbl<double>* y = G(d.y);
+    gbl<double>* r = G(d.r);
+    const VR di = G(static_cast<const VR*>(d.dinv))[i];
+    VR pv[3], qv[3];
+    double yv[3], rv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        pv[c] = p[3 * i + c];
+        qv[c] = q[3 * i + c];
+        yv[c] = y[3 * i + c];
+        rv[c] = r[3 * i + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        yv[c] = fma(al[c], double(pv[c]), yv[c]);
+        rv[c] = fma(-al[c], double(qv[c]), rv[c]);
+        const VR zi = di * VR(rv[c]);
+        acc[c] += rv[c] * double(zi);
+        acc[3 + c] += rv[c] * rv[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        y[3 * i + c] = yv[c];
+        r[3 * i + c] = rv[c];
+    }
+}
+
+template <typename VR>
+__global__ __launch_bounds__(kBlk) void k_pcg_update(const SolveDesc* __restrict__ descs,
+                                                     const WorkItem* __restrict__ items, long nitems, long t,
+                                                     int per) {
+    long first, last;
+    if (!item_range(nitems, per, first, last)) return;
+    __shared__ double sh[6 * (kBlk / 64)];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    int cur = -1, cur_unit = 0, done = 1;
+    double al[3] = {0, 0, 0};
+    for (long it = first; it < last; ++it) {
+        const WorkItem wi = items[it];
+        const SolveDesc& d = descs[wi.mesh];
+        if (wi.mesh != cur) {
+            if (cur >= 0 && !done) flush_partials<6>(bin_set(descs[cur], t, kSetRz), cur_unit, acc, sh);
+            cur = wi.mesh;
+            cur_unit = wi.unit;
+            const PcgState* st = d.st + ((t + 1) & 1);
+            double pq[3];
+            bin_totals<3>(bin_set(d, t, kSetPq), pq);
+            done = st->done;
+            for (int c = 0; c < 3; ++c) al[c] = (st->active[c] && pq[c] != 0.0) ? st->rz[c] / pq[c] : 0.0;
+            if (!done && wi.unit == 0) bin_clear(bin_set(d, t + 1, kSetPq));
+        }
+        if (done) continue;
+        update_group<VR>(d, wi, t, al, acc);
+    }
+    if (cur >= 0 && !done) flush_partials<6>(bin_set(descs[cur], t, kSetRz), cur_unit, acc, sh);
+}
+
+// x += y (Newton update)
+__global__ __launch_bounds__(kBlk) void k_newton_update(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
+                                long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    for (int c = 0; c < 3; ++c) d.x[3 * i + c] += d.y[3 * i + c];
+}
+
+__global__ __launch_bounds__(kBlk) void k_velocity(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    for (int c = 0; c < 3; ++c) d.v[3 * i + c] = (d.x[3 * i + c] - d.xt[3 * i + c]) / d.dt;
+}
+
+// lumped mass rho h sum(A_T)/3 from the rest triangles
+__global__ void k_mass(const double* __restrict__ X, const int32_t* __restrict__ tris, long nt, double rho_h,
+                       double* __restrict__ mass) {
+    long t = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (t >= nt) return;
+    int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
+    V3<double> xa = load3(X, a);
+    double third = rho_h * 0.5 * norm(cross(load3(X, b) - xa, load3(X, c) - xa)) / 3.0;
+    atomicAdd(mass + a, third);
+    atomicAdd(mass + b, third);
+    atomicAdd(mass + c, third);
+}
+
+__global__ void k_zero(double* __restrict__ p, long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+}  // namespace shell

@@ -134,14 +134,15 @@ def test_hessian_and_apply_match_oracle(model):
         assert rel(qd.cpu().numpy(), O.apply((rp, col, val), None, 1.0, p)) <= 1e-12
 
 
-def _replay_run(mesh, model, steps, dt, max_newton, pcg_rtol, block=256, flags=0, reorder=1):
+def _replay_run(mesh, model, steps, dt, max_newton, pcg_rtol, block=256, flags=0, reorder=1, wg=0):
     ost = oracle_stencils(model, mesh)
     osim = O.Sim(ost, MAT, mesh.pinned)
     with S.Problem(mesh, MAT, model=model, block_vertices=block, flags=flags, reorder=reorder) as pb:
         assert S.shell_hessian_info(pb.h)["staged"] == (0 if flags & S.SHELL_FLAG_DIRECT_PRODUCT else 1)
         for _ in range(steps):
             counts, ostats = osim.step(dt, max_newton=max_newton, pcg_rtol=pcg_rtol)
-            params, _keep = S.step_params(dt, max_newton=max_newton, pcg_rtol=pcg_rtol, replay=counts)
+            params, _keep = S.step_params(dt, max_newton=max_newton, pcg_rtol=pcg_rtol, replay=counts,
+                                          pcg_workgroups=wg)
             rc, gstats = S.shell_step_implicit(pb.sim, params)
             assert gstats["newton_iters"] == ostats["newton_iters"]
             assert np.array_equal(gstats["counts"], counts[: gstats["newton_iters"]])
@@ -167,6 +168,21 @@ def test_shell_steps_replay_match_oracle(model):
     assert rel(v, osim.v) <= TOL64
 
 
+@pytest.mark.parametrize("model,n,wg", [("SS", 40, 1), ("FS", 36, 1), ("SS", 46, 2), ("EP", 32, 1)])
+def test_several_row_groups_per_pcg_workgroup(model, n, wg):
+    """Few PCG work-groups, each walking several consecutive row groups (the large-mesh launch shape).
+    The plate case is the clamped 32 x 32 plate configuration (dt = 1/60, one Newton solve, which is
+    exact for a plate)."""
+    if model.endswith("S"):
+        mesh = I.workload_cylinder(n, model)
+        x, v, osim = _replay_run(mesh, model, 2, 1 / 30, 2, 1e-8, block=128, wg=wg)
+    else:
+        mesh = I.workload_plate32()
+        x, v, osim = _replay_run(mesh, model, 3, 1 / 60, 1, 1e-10, block=128, wg=wg)
+    assert rel(x - mesh.X, osim.x - mesh.X) <= TOL64
+    assert rel(v, osim.v) <= TOL64
+
+
 @pytest.mark.parametrize("model,reorder", [("SS", 1), ("EP", 0), ("FS", 2)])
 def test_direct_product_replay_matches_oracle(model, reorder):
     """The product without LDS staging (each neighbour gathered from memory) gives the same steps."""
@@ -188,7 +204,7 @@ def test_hessian_info_counts():
     lens = np.diff(rp)
     # every 64-row slice is padded to its longest row
     assert hi["slots"] == sum(64 * int(lens[a:a + 64].max()) for a in range(0, mesh.nv, 64))
-    groups = [np.unique(col[rp[a]:rp[min(a + 256, mesh.nv)]]) for a in range(0, mesh.nv, 256)]
+    groups = [np.unique(col[rp[a]:rp[min(a + 512, mesh.nv)]]) for a in range(0, mesh.nv, 512)]
     assert hi["staged"] == 1
     assert hi["group_cols"] == sum(len(g) for g in groups)
     assert hi["max_group_cols"] == max(len(g) for g in groups)
@@ -424,6 +440,36 @@ def test_batch_replay_matches_oracle_per_mesh():
                 plist.append(p)
                 keep.append(kp)
             S.shell_batch_step(batch, plist, len(meshes))
+        for k, m in enumerate(meshes):
+            x, v, _ = S.shell_sim_get_state(probs[k].sim, m.nv)
+            assert rel(x - m.X, osims[k].x - m.X) <= TOL64, m.name
+            assert rel(v, osims[k].v) <= TOL64, m.name
+    finally:
+        S.shell_destroy_batch(batch)
+        for pb in probs:
+            pb.close()
+
+
+def test_batch_of_staged_and_direct_products_with_profiling_matches_oracle():
+    """One batch holding meshes of both product forms (LDS-staged and direct gathers), PCG work-groups
+    that walk row groups of several meshes, and in-step sampling on: every mesh matches the oracle."""
+    meshes = _batch_meshes()[:4]
+    flags = [0, S.SHELL_FLAG_DIRECT_PRODUCT, 0, S.SHELL_FLAG_DIRECT_PRODUCT]
+    osims = [O.Sim(oracle_stencils(m.model, m), MAT, m.pinned) for m in meshes]
+    probs = [S.Problem(m, MAT, block_vertices=64, flags=f) for m, f in zip(meshes, flags)]
+    batch = S.shell_batch_create([pb.sim for pb in probs])
+    try:
+        S.shell_batch_profile(batch, 2)
+        for _ in range(2):
+            plist, keep = [], []
+            for k, m in enumerate(meshes):
+                counts, _ = osims[k].step(1 / 45, max_newton=2, pcg_rtol=1e-9)
+                p, kp = S.step_params(1 / 45, max_newton=2, pcg_rtol=1e-9, replay=counts, pcg_workgroups=3)
+                plist.append(p)
+                keep.append(kp)
+            S.shell_batch_step(batch, plist, len(meshes))
+        prof = S.shell_batch_profile_read(batch)
+        assert prof["product"]["count"] > 0 and prof["update"]["count"] > 0 and prof["forces"]["count"] >= 4
         for k, m in enumerate(meshes):
             x, v, _ = S.shell_sim_get_state(probs[k].sim, m.nv)
             assert rel(x - m.X, osims[k].x - m.X) <= TOL64, m.name
