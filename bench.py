@@ -49,7 +49,7 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
     return dict(force=force, spmv=spmv, update=update, force_per_stencil=per_stencil)
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_cap_1024_ss_fp64_hbm_traffic.md")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_cap_1024_ss_hbm_traffic.md")
 # the device code of the measured kernels and the layout they read (host_mesh.cpp builds it)
 TRAFFIC_SOURCES = ["paper_2502_10872_amd/csrc/spmv.hpp", "paper_2502_10872_amd/csrc/pcg_kernels.hpp",
                    "paper_2502_10872_amd/csrc/forces.hip", "paper_2502_10872_amd/csrc/host_mesh.cpp",
