@@ -197,9 +197,14 @@ typedef struct {
     int32_t chunk;         /* PCG iterations launched between host convergence checks; 0 = default */
     int32_t pcg_workgroups; /* work-groups of each PCG kernel (each takes consecutive 512-row groups);
                                0 = default (512: two per CU).  Batches use the first entry's value */
-    int32_t reserved;
+    int32_t flags;         /* 0 or SHELL_STEP_NO_GRAPHS; batches use the first entry's value */
     const int32_t* replay_counts; /* host [max_newton][3], REPLAY only: exact PCG iterations */
 } shell_step_params_t;
+
+/* PCG iterations are launched as captured HIP graphs of 8..128 iterations (replayed from a cache
+ * keyed by the launch shape); this flag launches every kernel directly instead.  Graphs are not used
+ * while in-step sampling is on. */
+#define SHELL_STEP_NO_GRAPHS 1
 
 typedef struct {
     int32_t newton_iters;  /* Newton solves performed */

@@ -41,6 +41,7 @@ void check_params(const shell_step_params_t& p) {
     SHELL_CHECK(p.mode == SHELL_PCG_REPLAY || p.max_pcg > 0, SHELL_E_INVALID_ARG, "max_pcg must be positive");
     SHELL_CHECK(p.chunk >= 0, SHELL_E_INVALID_ARG, "chunk must be >= 0");
     SHELL_CHECK(p.pcg_workgroups >= 0, SHELL_E_INVALID_ARG, "pcg_workgroups must be >= 0");
+    SHELL_CHECK((p.flags & ~SHELL_STEP_NO_GRAPHS) == 0, SHELL_E_INVALID_ARG, "unknown step flag");
     for (int c = 0; c < 3; ++c) SHELL_CHECK(std::isfinite(p.gravity[c]), SHELL_E_INVALID_ARG, "gravity not finite");
     if (p.mode == SHELL_PCG_REPLAY)
         for (int q = 0; q < 3 * p.max_newton; ++q)

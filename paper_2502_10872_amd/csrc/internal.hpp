@@ -261,9 +261,31 @@ struct StepProfiler {
 };
 }  // namespace shell
 
+namespace shell {
+// Instantiated HIP graphs of PCG chunks, keyed by everything their kernel arguments bake in (the
+// buffers' contents are read when a graph runs, so the same key serves any meshes and step).
+struct GraphCache {
+    struct Key {
+        const void* sdesc;
+        const void* rows;
+        long nrows, grid;
+        size_t lds;
+        int per, count, parity, precision;
+        bool operator==(const Key& o) const {
+            return sdesc == o.sdesc && rows == o.rows && nrows == o.nrows && grid == o.grid && lds == o.lds &&
+                   per == o.per && count == o.count && parity == o.parity && precision == o.precision;
+        }
+    };
+    std::vector<std::pair<Key, hipGraphExec_t>> entries;  // oldest first
+    hipStream_t capture = nullptr;                        // private stream the chunks are captured on
+    ~GraphCache();
+};
+}  // namespace shell
+
 struct shell_batch_s {
     std::vector<shell_sim_s*> sims;
     std::unique_ptr<shell::StepProfiler> prof;  // null unless sampling was requested
+    std::unique_ptr<shell::GraphCache> graphs;  // created on first use
     int precision = 0;
     int max_T = 0;
     size_t lds_spmv = 0;                     // staged p bytes per row group, largest over the members

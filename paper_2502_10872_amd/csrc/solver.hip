@@ -61,6 +61,11 @@ void StepProfiler::reset() {
     counter = 0;
 }
 
+GraphCache::~GraphCache() {
+    for (auto& e : entries) (void)hipGraphExecDestroy(e.second);
+    if (capture) (void)hipStreamDestroy(capture);
+}
+
 StepProfiler::~StepProfiler() {
     for (const Sample& e : pending) {
         pool.push_back(e.a);
@@ -113,16 +118,70 @@ long pcg_chunk(const Launch& L, long t, int count, hipStream_t s, StepProfiler* 
     const long grid = L.pcg_grid;
     for (int it = 0; it < count; ++it, ++t) {
         const bool smp = prof && prof->sample_iteration();
-        timed_launch(prof, smp, SHELL_PHASE_UPDATE, s, [&](hipEvent_t e0, hipEvent_t e1) {
+        if (!smp) {  // plain launches (also the form recorded into graphs)
+            k_pcg_update<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, t, L.per);
+            k_pcg_spmv<VR, MR><<<grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows, t + 1, L.per);
+            continue;
+        }
+        timed_launch(prof, true, SHELL_PHASE_UPDATE, s, [&](hipEvent_t e0, hipEvent_t e1) {
             hipExtLaunchKernelGGL(k_pcg_update<VR>, dim3(unsigned(grid)), dim3(kBlk), 0, s, e0, e1, 0, L.sdesc, L.rows,
                                   L.nrows, t, L.per);
         });
-        timed_launch(prof, smp, SHELL_PHASE_PRODUCT, s, [&](hipEvent_t e0, hipEvent_t e1) {
+        timed_launch(prof, true, SHELL_PHASE_PRODUCT, s, [&](hipEvent_t e0, hipEvent_t e1) {
             hipExtLaunchKernelGGL(k_pcg_spmv<VR, MR>, dim3(unsigned(grid)), dim3(kBlk), uint32_t(L.lds_spmv), s, e0,
                                   e1, 0, L.sdesc, L.rows, L.nrows, t + 1, L.per);
         });
     }
     SHELL_HIP(hipGetLastError());
+    return t;
+}
+
+constexpr int kMinGraphChunk = 8, kMaxGraphChunk = 128, kMaxGraphs = 32;
+
+// `count` PCG iterations after product t through the batch's graph cache: power-of-two pieces of
+// 8..128 iterations are replayed from captured graphs (captured on first use on a private stream),
+// a remainder below 8 is launched directly.  A captured piece is valid for any start with the same
+// parity: the kernels use t only for buffer parity and t > 0.
+template <typename VR, typename MR>
+long pcg_iterations(shell_batch_s& b, const Launch& L, long t, int count, hipStream_t s, bool use_graphs) {
+    StepProfiler* prof = b.prof.get();
+    if (!use_graphs || (prof && prof->every > 0)) return pcg_chunk<VR, MR>(L, t, count, s, prof);
+    if (!b.graphs) b.graphs = std::make_unique<GraphCache>();
+    GraphCache& gc = *b.graphs;
+    if (!gc.capture) SHELL_HIP(hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking));
+    while (count > 0) {
+        int c = kMinGraphChunk;
+        while (2 * c <= count && 2 * c <= kMaxGraphChunk) c *= 2;
+        if (c > count) return pcg_chunk<VR, MR>(L, t, count, s, nullptr);
+        const GraphCache::Key key{L.sdesc, L.rows, L.nrows, L.pcg_grid, L.lds_spmv, L.per, c, int(t & 1),
+                                  L.precision};
+        hipGraphExec_t ex = nullptr;
+        for (auto& e : gc.entries)
+            if (e.first == key) ex = e.second;
+        if (!ex) {
+            hipGraph_t g = nullptr;
+            SHELL_HIP(hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal));
+            try {
+                pcg_chunk<VR, MR>(L, t, c, gc.capture, nullptr);
+            } catch (...) {
+                (void)hipStreamEndCapture(gc.capture, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            SHELL_HIP(hipStreamEndCapture(gc.capture, &g));
+            const hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            SHELL_HIP(err);
+            if (int(gc.entries.size()) >= kMaxGraphs) {
+                (void)hipGraphExecDestroy(gc.entries.front().second);
+                gc.entries.erase(gc.entries.begin());
+            }
+            gc.entries.emplace_back(key, ex);
+        }
+        SHELL_HIP(hipGraphLaunch(ex, s));
+        t += c;
+        count -= c;
+    }
     return t;
 }
 
@@ -282,6 +341,7 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
                          hipStream_t s) {
     const int n = int(b.sims.size());
     const int wg = prms[0].pcg_workgroups > 0 ? prms[0].pcg_workgroups : SHELL_PCG_WORKGROUPS;
+    const bool graphs = (prms[0].flags & SHELL_STEP_NO_GRAPHS) == 0;
     std::vector<MeshStep> ms(static_cast<size_t>(n));
     SHELL_HIP(hipStreamSynchronize(s));  // the descriptor staging is reused below
     if (b.fdesc_dirty) {
@@ -374,7 +434,7 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
             if (p.chunk > 0) first_chunk = max_chunk = p.chunk;
         }
         if (all_replay) {
-            t = pcg_chunk<VR, MR>(L, t, most, s, b.prof.get());
+            t = pcg_iterations<VR, MR>(b, L, t, most, s, graphs);
             read_states(b, s);
         } else {
             read_states(b, s);
@@ -383,7 +443,7 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
                 bool done = true;
                 for (int m : solve) done &= b.state_host[2 * m + ((t + 1) & 1)].done != 0;
                 if (done) break;
-                t = pcg_chunk<VR, MR>(L, t, chunk, s, b.prof.get());
+                t = pcg_iterations<VR, MR>(b, L, t, chunk, s, graphs);
                 read_states(b, s);
                 chunk = std::min(2 * chunk, max_chunk);
             }
@@ -518,6 +578,7 @@ void sim_mass(shell_sim_s& sim, hipStream_t s) {
 // the host and uploaded on the stream of the next step, so this makes no device-wide synchronisation.
 void batch_init(shell_batch_s& b) {
     const size_t n = b.sims.size();
+    b.graphs.reset();  // graphs bake in buffer addresses of the previous members
     SHELL_CHECK(n > 0, SHELL_E_INVALID_ARG, "empty batch");
     b.precision = b.sims[0]->st->precision;
     b.max_T = 64;
@@ -557,6 +618,7 @@ void batch_free_host(shell_batch_s& b) {
 }
 
 void batch_release(shell_batch_s& b) {
+    b.graphs.reset();
     batch_free_host(b);
     if (b.items_host) (void)hipHostFree(b.items_host);
     b.items_host = nullptr;

@@ -55,7 +55,10 @@ class shell_step_params_t(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("gravity", ctypes.c_double * 3), ("max_newton", ctypes.c_int32),
                 ("max_pcg", ctypes.c_int32), ("newton_rtol", ctypes.c_double), ("pcg_rtol", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("chunk", ctypes.c_int32), ("pcg_workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("replay_counts", ctypes.c_void_p)]
+                ("flags", ctypes.c_int32), ("replay_counts", ctypes.c_void_p)]
+
+
+SHELL_STEP_NO_GRAPHS = 1
 
 
 class shell_step_stats_t(ctypes.Structure):
@@ -241,7 +244,7 @@ def shell_sim_create(st, h, x0, v0=None, pinned=None):
 
 
 def step_params(dt, gravity=(0.0, 0.0, -9.81), max_newton=1, max_pcg=200000, newton_rtol=1e-8, pcg_rtol=1e-10,
-                replay=None, chunk=0, pcg_workgroups=0):
+                replay=None, chunk=0, pcg_workgroups=0, flags=0):
     p = shell_step_params_t()
     p.dt = dt
     p.gravity[:] = list(gravity)
@@ -251,6 +254,7 @@ def step_params(dt, gravity=(0.0, 0.0, -9.81), max_newton=1, max_pcg=200000, new
     p.pcg_rtol = pcg_rtol
     p.chunk = chunk
     p.pcg_workgroups = pcg_workgroups
+    p.flags = flags
     keep = None
     if replay is not None:
         keep = np.ascontiguousarray(replay, dtype=np.int32).reshape(-1, 3)

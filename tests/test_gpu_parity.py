@@ -193,6 +193,52 @@ def test_direct_product_replay_matches_oracle(model, reorder):
     assert rel(v, osim.v) <= TOL64
 
 
+@pytest.mark.parametrize("model", ["SS", "EP"])
+def test_graph_replays_equal_direct_launches(model):
+    """PCG chunks replayed from captured HIP graphs against the same chunks launched kernel by kernel:
+    several steps, so each graph is replayed many times with eager work and host synchronisation in
+    between; both runs replay the oracle's counts (not powers of two, so graph pieces and direct
+    remainders mix) and each must match the oracle."""
+    mesh = I.workload_cylinder(28, model) if model.endswith("S") else I.workload_plate32()
+    dt, newton = (1 / 30, 2) if model.endswith("S") else (1 / 60, 1)
+    ost = oracle_stencils(model, mesh)
+    osim = O.Sim(ost, MAT, mesh.pinned)
+    runs = []
+    with S.Problem(mesh, MAT, model=model, block_vertices=128) as pa, \
+            S.Problem(mesh, MAT, model=model, block_vertices=128) as pb:
+        for _ in range(4):
+            counts, _ = osim.step(dt, max_newton=newton, pcg_rtol=1e-9)
+            for pb_, flags in ((pa, 0), (pb, S.SHELL_STEP_NO_GRAPHS)):
+                prm, _keep = S.step_params(dt, max_newton=newton, pcg_rtol=1e-9, replay=counts, flags=flags)
+                rc, st = S.shell_step_implicit(pb_.sim, prm)
+                assert np.array_equal(st["counts"], counts[: st["newton_iters"]])
+        for pb_ in (pa, pb):
+            x, v, _ = S.shell_sim_get_state(pb_.sim, mesh.nv)
+            runs.append((x, v))
+    for x, v in runs:
+        assert rel(x - mesh.X, osim.x - mesh.X) <= TOL64
+        assert rel(v, osim.v) <= TOL64
+    assert rel(runs[0][0] - mesh.X, runs[1][0] - mesh.X) <= 1e-11
+
+
+def test_graphs_in_tolerance_mode_match_direct_launches():
+    """Tolerance mode launches chunks of 8, 16, ..., 128 iterations, all from graphs after the first."""
+    mesh = I.workload_cylinder(32, "SS")
+    out = []
+    for flags in (0, S.SHELL_STEP_NO_GRAPHS):
+        with S.Problem(mesh, MAT) as pb:
+            prm, _ = S.step_params(1 / 30, max_newton=2, pcg_rtol=1e-8, flags=flags)
+            tot = 0
+            for _ in range(3):
+                rc, st = S.shell_step_implicit(pb.sim, prm)
+                tot += st["pcg_total"]
+            x, v, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+            out.append((x, v, tot))
+    (xa, va, ta), (xb, vb, tb) = out
+    assert abs(ta - tb) <= 6
+    assert rel(xa - mesh.X, xb - mesh.X) <= 1e-8 and rel(va, vb) <= 1e-8
+
+
 def test_hessian_info_counts():
     """Storage figures against the pattern itself (caller order kept, so slices and groups are known)."""
     mesh = mesh_for("SS", 29)
