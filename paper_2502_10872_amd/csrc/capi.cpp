@@ -168,13 +168,14 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         // tiles for the force kernel
         Tiling til = build_tiling(st->h_idx, k, st->ns, nv, T);
         st->nblocks = til.nblocks;
-        st->ns_tiled = int64_t(til.src.size());
+        st->ns_tiled = til.count;
+        st->nst_pad = int64_t(til.src.size());
         st->h_boff = til.boff;
         st->boff.alloc(til.boff.size());
         st->boff.upload(til.boff.data(), til.boff.size(), s);
         st->tsrc.alloc(til.src.size());
         st->tsrc.upload(til.src.data(), til.src.size(), s);
-        const size_t nst = size_t(st->ns_tiled);
+        const size_t nst = size_t(st->nst_pad);
         st->tidx.alloc(size_t(k) * nst);
         // only the precision the force kernel streams is kept in the tiled layout
         if (precision == SHELL_PREC_MIXED) {
@@ -255,7 +256,7 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
             d.tidx = st->tidx.p;
             d.tB = f32 ? static_cast<const void*>(st->tBf.p) : static_cast<const void*>(st->tB.p);
             d.tk0 = f32 ? static_cast<const void*>(st->tk0f.p) : static_cast<const void*>(st->tk0.p);
-            d.nst = st->ns_tiled;
+            d.nst = st->nst_pad;
             d.nv = st->nv;
             d.T = st->T;
             d.model = st->model;

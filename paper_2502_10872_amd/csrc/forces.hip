@@ -5,8 +5,9 @@
 // tile boundary appear in each tile they touch).  Each stencil's force on the tile's own vertices is
 // added into a float64 LDS accumulator; contributions to other tiles' vertices are left to those
 // tiles.  The tile is then written to HBM once: no global atomics, no zero-fill, one coalesced store
-// per vertex.  Stencil data is streamed structure-of-arrays so every load is coalesced; a tile's list
-// stays in spatial order so the gathers of one wave touch few cache lines.  (float32 LDS atomics
+// per vertex.  Stencil data is streamed in blocks of 64 stencils (each field of a wave's 64 stencils is
+// one contiguous run, so every load is coalesced and a wave touches one region of memory); a tile's
+// list stays in spatial order so the gathers of one wave touch few cache lines.  (float32 LDS atomics
 // contended badly on shared vertices; the float64 accumulator does not.)
 //
 // Per stencil (operator B already scaled by the square root of its stiffness):
@@ -115,6 +116,16 @@ __device__ __forceinline__ void tri_stencil(const V3<double> (&xg)[6], const R (
     }
 }
 
+// Stencil-stream load: non-temporal for the FP64 kernels, plain for the mixed ones (measured: each form
+// is the faster one for its precision by 4-6%).
+template <typename R, typename T>
+__device__ __forceinline__ T stream_ld(const T* p) {
+    if constexpr (sizeof(R) == 8)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
 // tile accumulator in float64 for both precisions (ds_add_f64)
 template <typename R>
 __device__ __forceinline__ void lds_add(double* acc, int slot, V3<R> v) {
@@ -140,7 +151,6 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
     const int32_t* __restrict__ tidx = d.tidx;
     const R* __restrict__ tB = static_cast<const R*>(d.tB);
     const R* __restrict__ tk0 = static_cast<const R*>(d.tk0);
-    const long nst = d.nst;
     const R kb = R(d.kb), nu = R(d.nu);
     const long blk = wi.unit;
     const long base = blk * long(d.T);
@@ -148,13 +158,17 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
     for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) acc[i] = 0.0;
     __syncthreads();
     double e_own = 0.0;
-    const long e0 = d.boff[blk], e1 = d.boff[blk + 1];
+    // a tile's list starts on a 64-stencil block and the work-group's stride is a whole number of
+    // blocks, so each wave reads whole blocks: every field of its 64 stencils is one contiguous run
+    const long e0 = d.boff[2 * blk], e1 = d.boff[2 * blk + 1];
     for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const long sb = (e / kStreamBlock) * kStreamBlock, lane = e % kStreamBlock;
+        auto at = [&](int nf, int f) { return sb * nf + f * kStreamBlock + lane; };
         int vid[K];
         V3<double> xg[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            vid[j] = __builtin_nontemporal_load(tidx + j * nst + e);
+            vid[j] = stream_ld<R>(tidx + at(K, j));
             xg[j] = load3(x, vid[j]);
         }
         V3<R> fs[K];
@@ -162,16 +176,16 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
         if constexpr (EDGE) {
             R L[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) L[j] = __builtin_nontemporal_load(tB + j * nst + e);
-            R k0 = SHELL ? __builtin_nontemporal_load(tk0 + e) : R(0);
+            for (int j = 0; j < 4; ++j) L[j] = stream_ld<R>(tB + at(4, j));
+            R k0 = SHELL ? stream_ld<R>(tk0 + at(1, 0)) : R(0);
             edge_stencil<R, SHELL>(xg, L, k0, fs, en);
         } else {
             R Bm[3][6], k0[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
 #pragma unroll
-                for (int j = 0; j < 6; ++j) Bm[i][j] = __builtin_nontemporal_load(tB + (i * 6 + j) * nst + e);
-                k0[i] = SHELL ? __builtin_nontemporal_load(tk0 + i * nst + e) : R(0);
+                for (int j = 0; j < 6; ++j) Bm[i][j] = stream_ld<R>(tB + at(18, i * 6 + j));
+                k0[i] = SHELL ? stream_ld<R>(tk0 + at(3, i)) : R(0);
             }
             tri_stencil<R, SHELL>(xg, Bm, k0, kb, nu, fs, en);
         }

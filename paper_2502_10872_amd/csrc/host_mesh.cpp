@@ -182,13 +182,21 @@ Tiling build_tiling(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t 
         int n = blocks_of(s, bl);
         for (int q = 0; q < n; ++q) cnt[size_t(bl[q]) + 1]++;
     }
-    for (int64_t b = 0; b < t.nblocks; ++b) cnt[b + 1] += cnt[b];
-    t.boff = cnt;
-    t.src.resize(size_t(cnt[t.nblocks]));
-    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    // each tile's list starts on a 64-stencil block
+    t.boff.assign(size_t(2 * t.nblocks), 0);
+    int64_t at = 0;
+    for (int64_t b = 0; b < t.nblocks; ++b) {
+        t.boff[size_t(2 * b)] = at;
+        t.boff[size_t(2 * b + 1)] = at + cnt[b + 1];
+        t.count += cnt[b + 1];
+        at = (at + cnt[b + 1] + kStreamBlock - 1) / kStreamBlock * kStreamBlock;
+    }
+    t.src.assign(size_t(at), -1);
+    std::vector<int64_t> fill(size_t(t.nblocks));
+    for (int64_t b = 0; b < t.nblocks; ++b) fill[size_t(b)] = t.boff[size_t(2 * b)];
     for (int64_t s = 0; s < ns; ++s) {
         int n = blocks_of(s, bl);
-        for (int q = 0; q < n; ++q) t.src[size_t(fill[bl[q]]++)] = int32_t(s);
+        for (int q = 0; q < n; ++q) t.src[size_t(fill[size_t(bl[q])]++)] = int32_t(s);
     }
     return t;
 }

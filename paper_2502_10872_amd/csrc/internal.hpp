@@ -85,11 +85,18 @@ HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tr
 // bisection into tiles of T vertices (Morton inside a tile); 2: Morton order of the rest positions.
 std::vector<int32_t> vertex_order(const double* X, int64_t nv, int mode, int T);
 
+// Tiled stencil streams are stored in blocks of 64 stencils (one wave): field f of list entry e sits at
+// ((e / 64) * nfields + f) * 64 + e % 64, so a wave reads each of its stencils' fields as one contiguous
+// run.  Every tile's list starts at a multiple of 64; the slots between a list's end and the next start
+// are padding that no kernel reads.
+constexpr int kStreamBlock = 64;
+
 struct Tiling {
     int T = 1024;                 // vertices per tile
     int64_t nblocks = 0;
-    std::vector<int64_t> boff;    // [nblocks+1] offsets into the tiled stencil list
-    std::vector<int32_t> src;     // [ns_tiled] unique stencil of each tiled copy
+    int64_t count = 0;            // tiled stencils (halo copies included, padding not)
+    std::vector<int64_t> boff;    // [2 nblocks]: start (a multiple of 64) and end of each tile's list
+    std::vector<int32_t> src;     // [padded length] source stencil of each list slot, -1 for padding
 };
 // Groups stencils (internal vertex ids) by the vertex tiles they touch; halo stencils repeat.
 Tiling build_tiling(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv, int T);
@@ -124,7 +131,7 @@ struct ForceDesc {
     const double* x;
     void* f;               // double or float [nv][3]
     double* epart;         // per-tile energy, or null
-    const int64_t* boff;   // tile offsets into the tiled stencil list
+    const int64_t* boff;   // [2 tiles]: start and end of each tile's stencil list
     const int32_t* tidx;
     const void* tB;        // double or float operator stream
     const void* tk0;
@@ -172,6 +179,7 @@ struct WorkItem {
 struct shell_stencils_s {
     int model = 0, k = 4, r = 1, precision = 0;
     int64_t nv = 0, nt = 0, ns = 0, ns_tiled = 0, nblocks = 0;
+    int64_t nst_pad = 0;  // tiled list length with the per-tile alignment padding
     int T = 1024;
     int cfg_flags = 0;  // SHELL_FLAG_*
     bool reordered = false;
@@ -188,11 +196,11 @@ struct shell_stencils_s {
     shell::DevArray<double> B;           // SoA [r*k][ns], scaled by sqrt(stiffness)
     shell::DevArray<double> k0;          // SoA [r][ns]
     shell::DevArray<int32_t> flags;      // [ns]
-    shell::DevArray<int64_t> boff;       // [nblocks+1]
-    shell::DevArray<int32_t> tsrc;       // [ns_tiled]
-    shell::DevArray<int32_t> tidx;       // SoA [k][ns_tiled]
-    shell::DevArray<double> tB;          // SoA [r*k][ns_tiled]
-    shell::DevArray<double> tk0;         // SoA [r][ns_tiled]
+    shell::DevArray<int64_t> boff;       // [2 nblocks] start, end
+    shell::DevArray<int32_t> tsrc;       // [nst_pad]
+    shell::DevArray<int32_t> tidx;       // blocks of 64: [nst_pad / 64][k][64]
+    shell::DevArray<double> tB;          // blocks of 64: [nst_pad / 64][r*k][64]
+    shell::DevArray<double> tk0;         // blocks of 64: [nst_pad / 64][r][64]
     shell::DevArray<float> tBf;          // mixed-precision copies
     shell::DevArray<float> tk0f;
     // scratch for the caller-order entry point

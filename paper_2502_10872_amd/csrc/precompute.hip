@@ -210,17 +210,19 @@ __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_
                           float* __restrict__ tBf, float* __restrict__ tk0f) {
     long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (e >= nt) return;
-    long s = src[e];
-    for (int j = 0; j < k; ++j) tidx[j * nt + e] = idx[j * ns + s];
+    const long s = src[e];  // -1: alignment padding, filled with vertex 0 and zeros (never read)
+    const long blk = e / kStreamBlock, lane = e % kStreamBlock;
+    auto at = [&](int nf, int f) { return (blk * nf + f) * kStreamBlock + lane; };
+    for (int j = 0; j < k; ++j) tidx[at(k, j)] = s < 0 ? 0 : idx[j * ns + s];
     for (int q = 0; q < r * k; ++q) {
-        double v = B[q * ns + s];
-        if (tB) tB[q * nt + e] = v;
-        if (tBf) tBf[q * nt + e] = float(v);
+        const double v = s < 0 ? 0.0 : B[q * ns + s];
+        if (tB) tB[at(r * k, q)] = v;
+        if (tBf) tBf[at(r * k, q)] = float(v);
     }
     for (int q = 0; q < r; ++q) {
-        double v = k0[q * ns + s];
-        if (tk0) tk0[q * nt + e] = v;
-        if (tk0f) tk0f[q * nt + e] = float(v);
+        const double v = s < 0 ? 0.0 : k0[q * ns + s];
+        if (tk0) tk0[at(r, q)] = v;
+        if (tk0f) tk0f[at(r, q)] = float(v);
     }
 }
 
@@ -250,7 +252,7 @@ void launch_precompute(shell_stencils_s& st, hipStream_t s) {
 }
 
 void launch_tile_copy(shell_stencils_s& st, hipStream_t s) {
-    const long nt = st.ns_tiled;
+    const long nt = st.nst_pad;
     if (nt == 0) return;
     int blk = 256;
     tile_copy<<<(nt + blk - 1) / blk, blk, 0, s>>>(st.tsrc.p, nt, st.idx.p, st.B.p, st.k0.p, st.ns, st.k, st.r,

@@ -318,7 +318,7 @@ ForceDesc force_desc(shell_sim_s& sim) {
     d.tidx = st.tidx.p;
     d.tB = f32 ? static_cast<const void*>(st.tBf.p) : static_cast<const void*>(st.tB.p);
     d.tk0 = f32 ? static_cast<const void*>(st.tk0f.p) : static_cast<const void*>(st.tk0.p);
-    d.nst = st.ns_tiled;
+    d.nst = st.nst_pad;
     d.nv = st.nv;
     d.T = st.T;
     d.model = st.model;
