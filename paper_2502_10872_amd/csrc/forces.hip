@@ -119,7 +119,7 @@ __device__ __forceinline__ void tri_stencil(const V3<double> (&xg)[6], const R (
 // Stencil-stream load: non-temporal for the FP64 kernels, plain for the mixed ones (measured: each form
 // is the faster one for its precision by 4-6%).
 template <typename R, typename T>
-__device__ __forceinline__ T stream_ld(const T* p) {
+__device__ __forceinline__ T stream_ld(const gbl<const T>* p) {
     if constexpr (sizeof(R) == 8)
         return __builtin_nontemporal_load(p);
     else
@@ -147,10 +147,12 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
     if (it >= nitems) return;
     const WorkItem wi = items[it];
     const ForceDesc& d = descs[wi.mesh];
-    const double* __restrict__ x = d.x;
-    const int32_t* __restrict__ tidx = d.tidx;
-    const R* __restrict__ tB = static_cast<const R*>(d.tB);
-    const R* __restrict__ tk0 = static_cast<const R*>(d.tk0);
+    // global-address views of the descriptor's pointers: global loads wait on the vector-memory counter
+    // only, so the LDS accumulation does not stall behind loads in flight
+    const gbl<const double>* x = G(static_cast<const double*>(d.x));
+    const gbl<const int32_t>* tidx = G(d.tidx);
+    const gbl<const R>* tB = G(static_cast<const R*>(d.tB));
+    const gbl<const R>* tk0 = G(static_cast<const R*>(d.tk0));
     const R kb = R(d.kb), nu = R(d.nu);
     const long blk = wi.unit;
     const long base = blk * long(d.T);
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             vid[j] = stream_ld<R>(tidx + at(K, j));
-            xg[j] = load3(x, vid[j]);
+            xg[j] = {x[3L * vid[j]], x[3L * vid[j] + 1], x[3L * vid[j] + 2]};
         }
         V3<R> fs[K];
         R en;
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
         }
     }
     __syncthreads();
-    R* out = static_cast<R*>(d.f) + 3 * base;
+    gbl<R>* out = G(static_cast<R*>(d.f)) + 3 * base;
     for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
     if (d.epart) {
         __shared__ double sh[8];
