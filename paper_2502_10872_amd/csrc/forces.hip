@@ -162,41 +162,68 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
     double e_own = 0.0;
     // a tile's list starts on a 64-stencil block and the work-group's stride is a whole number of
     // blocks, so each wave reads whole blocks: every field of its 64 stencils is one contiguous run
-    const long e0 = d.boff[2 * blk], e1 = d.boff[2 * blk + 1];
-    for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const long sb = (e / kStreamBlock) * kStreamBlock, lane = e % kStreamBlock;
-        auto at = [&](int nf, int f) { return sb * nf + f * kStreamBlock + lane; };
+    constexpr int NB = EDGE ? 4 : 18;               // operator entries per stencil
+    constexpr int NK = EDGE ? 1 : 3;                // rest-curvature slots per stencil (read for shells)
+    struct In {
         int vid[K];
         V3<double> xg[K];
+        R ob[NB + NK];
+    };
+    auto load = [&](long e, In& in) {
+        const long sb = (e / kStreamBlock) * kStreamBlock, lane = e % kStreamBlock;
+        auto at = [&](int nf, int f) { return sb * nf + f * kStreamBlock + lane; };
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-            vid[j] = stream_ld<R>(tidx + at(K, j));
-            xg[j] = {x[3L * vid[j]], x[3L * vid[j] + 1], x[3L * vid[j] + 2]};
-        }
+        for (int j = 0; j < K; ++j) in.vid[j] = stream_ld<R>(tidx + at(K, j));
+#pragma unroll
+        for (int q = 0; q < NB; ++q) in.ob[q] = stream_ld<R>(tB + at(NB, q));
+#pragma unroll
+        for (int q = 0; q < NK; ++q) in.ob[NB + q] = SHELL ? stream_ld<R>(tk0 + at(NK, q)) : R(0);
+#pragma unroll
+        for (int j = 0; j < K; ++j) in.xg[j] = {x[3L * in.vid[j]], x[3L * in.vid[j] + 1], x[3L * in.vid[j] + 2]};
+    };
+    auto compute = [&](const In& in) {
         V3<R> fs[K];
         R en;
         if constexpr (EDGE) {
-            R L[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) L[j] = stream_ld<R>(tB + at(4, j));
-            R k0 = SHELL ? stream_ld<R>(tk0 + at(1, 0)) : R(0);
-            edge_stencil<R, SHELL>(xg, L, k0, fs, en);
+            const R L[4] = {in.ob[0], in.ob[1], in.ob[2], in.ob[3]};
+            edge_stencil<R, SHELL>(in.xg, L, in.ob[4], fs, en);
         } else {
             R Bm[3][6], k0[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
 #pragma unroll
-                for (int j = 0; j < 6; ++j) Bm[i][j] = stream_ld<R>(tB + at(18, i * 6 + j));
-                k0[i] = SHELL ? stream_ld<R>(tk0 + at(3, i)) : R(0);
+                for (int j = 0; j < 6; ++j) Bm[i][j] = in.ob[i * 6 + j];
+                k0[i] = in.ob[NB + i];
             }
-            tri_stencil<R, SHELL>(xg, Bm, k0, kb, nu, fs, en);
+            tri_stencil<R, SHELL>(in.xg, Bm, k0, kb, nu, fs, en);
         }
         // the tile that owns vertex 1 of the stencil counts its energy
-        if (unsigned(vid[0] - base) < unsigned(nown)) e_own += double(en);
+        if (unsigned(in.vid[0] - base) < unsigned(nown)) e_own += double(en);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
-            unsigned slot = unsigned(vid[j] - base);
+            unsigned slot = unsigned(in.vid[j] - base);
             if (slot < unsigned(nown)) lds_add(acc, int(slot), fs[j]);
+        }
+    };
+    const long e0 = d.boff[2 * blk], e1 = d.boff[2 * blk + 1];
+    const long S = blockDim.x;
+    if constexpr (sizeof(R) == 4) {
+        // mixed: two stencils per pass, both loaded before either is computed (a lane whose second
+        // stencil is past the end loads its first one twice and computes it once); measured 9% faster
+        // in float, slower in double (twice the registers)
+        for (long e = e0 + threadIdx.x; e < e1; e += 2 * S) {
+            const bool two = e + S < e1;
+            In a, b;
+            load(e, a);
+            load(two ? e + S : e, b);
+            compute(a);
+            if (two) compute(b);
+        }
+    } else {
+        for (long e = e0 + threadIdx.x; e < e1; e += S) {
+            In a;
+            load(e, a);
+            compute(a);
         }
     }
     __syncthreads();

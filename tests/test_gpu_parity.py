@@ -110,12 +110,14 @@ def test_mixed_precision_forces_within_bound(model):
         S.shell_destroy_stencils(st)
 
 
-@pytest.mark.parametrize("model", I.MODELS)
-def test_hessian_and_apply_match_oracle(model):
+@pytest.mark.parametrize("model,flags", [(m, 0) for m in I.MODELS] + [("SS", 1), ("EP", 1)])
+def test_hessian_and_apply_match_oracle(model, flags):
+    """flags = 1: the product without LDS staging (32-bit column ids, direct gathers)."""
     mesh = mesh_for(model, 29)
     ost = oracle_stencils(model, mesh)
     rp, col, val = ost.hessian()
-    with S.Problem(mesh, MAT, block_vertices=128, sim=False) as pb:
+    with S.Problem(mesh, MAT, block_vertices=128, sim=False, flags=flags) as pb:
+        assert S.shell_hessian_info(pb.h)["staged"] == (0 if flags else 1)
         grp, gcol, gval = S.shell_hessian_export_csr(pb.h, mesh.nv)
         assert np.array_equal(grp, rp) and np.array_equal(gcol, col)
         assert rel(gval, val) <= 1e-12
