@@ -31,21 +31,23 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
 
     force:  per stencil its k vertex ids, r x k operator and (shells) r rest curvatures; per vertex the
             position read and the force written.
-    spmv:   (the product kernel, which also forms the new direction p = D^-1 r + beta p_old) every
-            nonzero's value and 16-bit local column id, each row group's distinct-column list, slice
-            widths and offsets, and per vertex r, D^-1, p_old read, mass and fixed flag read, p and q
-            written.
-    update: per vertex p, q, y, r, D^-1 read, y and r written."""
+    spmv:   (the product kernel, which also forms the new direction p = z + beta p_old) every nonzero's
+            value and 16-bit local column id, each row group's distinct-column list, slice widths and
+            offsets, and per vertex the direction's inputs (FP64: r and D^-1; mixed: the stored float z)
+            and p_old, mass and fixed flag read, p and q written.
+    update: per vertex p, q, y, r, D^-1 read, y and r written (mixed: z written too)."""
     nv, ns, k, r = info["nv"], info["ns"], info["k"], info["r"]
     shell = info["model"] in (1, 3, 5)
-    real = 4 if precision == 1 else 8  # stencil operators, matrix values, p, q, D^-1, forces
+    mixed = precision == 1
+    real = 4 if mixed else 8  # stencil operators, matrix values, p, q, z, D^-1, forces
     per_stencil = 4 * k + real * r * k + (real * r if shell else 0)
     force = ns * per_stencil + nv * (24 + 3 * real)
     ngroups = (nv + 511) // 512  # 512-row groups
     idx = 2 if hinfo["staged"] else 4
+    direction_in = 3 * real if mixed else 24 + real
     spmv = (hinfo["nnz"] * (real + idx) + 4 * (hinfo["group_cols"] + ngroups + 1) + 12 * hinfo["nslices"]
-            + nv * (24 + real + 3 * real + 8 + 1 + 3 * real + 3 * real))
-    update = nv * (3 * real + 3 * real + 24 + 24 + real + 24 + 24)
+            + nv * (direction_in + 3 * real + 8 + 1 + 3 * real + 3 * real))
+    update = nv * (3 * real + 3 * real + 24 + 24 + real + 24 + 24 + (3 * real if mixed else 0))
     return dict(force=force, spmv=spmv, update=update, force_per_stencil=per_stencil)
 
 

@@ -151,6 +151,7 @@ struct PcgState {
 struct SolveDesc {
     double *x, *xhat, *xt, *v, *g, *y, *r;
     void *f, *p0, *p1, *q, *dinv;   // float in mixed precision; p0/p1 alternate as the search direction
+    float* z;                       // mixed precision only: z = D^-1 r as float (null in FP64: recomputed)
     const double *mass, *kdiag;
     const uint8_t* pinned;
     const int32_t* scol;
@@ -240,6 +241,7 @@ struct shell_sim_s {
     shell::DevArray<double> dinv;        // [nv] (float in mixed)
     shell::DevArray<uint8_t> pinned;
     shell::DevArray<double> p, p2, q;    // PCG work vectors (float in mixed; sized in doubles)
+    shell::DevArray<float> z;            // mixed only: the preconditioned residual, read by the product
     shell::DevArray<double> bins;        // PCG dot-product bins
     shell::DevArray<double> partials;    // reduction partials
     shell_batch_s* solo = nullptr;       // this simulation alone, as a batch of one

@@ -20,6 +20,11 @@ constexpr int kMaxPart = 8;   // partial quantities per work-group (buffer sized
 
 inline long blocks(long n) { return (n + kBlk - 1) / kBlk; }
 
+// Whether z = D^-1 r is stored (mixed precision: a float z, 12 B, is read instead of the FP64 r and the
+// Jacobi entry, 28 B, for every staged column; in FP64 storing z would cost more than it saves).
+template <typename VR>
+constexpr bool kStoredZ = sizeof(VR) == 4;
+
 // fixed-order sum of NQ partials over ngroups work-groups; result in thread 0's out[]
 template <int NQ>
 __device__ void reduce_partials(const double* __restrict__ part, long ngroups, double (&out)[NQ]) {
@@ -164,6 +169,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(const SolveDesc* __restrict__
             const VR zi = di * VR(ri);
             r[3 * i + c] = ri;
             y[3 * i + c] = 0.0;
+            if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zi;
             acc[c] = ri * double(zi);
             acc[3 + c] = ri * ri;
         }
@@ -271,31 +277,39 @@ template <typename VR>
 struct DirIn {
     const gbl<const double>* r;
     const gbl<const VR>* dinv;
+    const gbl<const VR>* z;  // stored z (mixed precision)
     const gbl<const VR>* pold;
     VR beta[3];
 };
 
 // The operands of vertex j's direction, loaded ahead of beta: the loads can be issued before the
 // recurrence state is known.  p_old is read even where beta is 0 (it is allocated; its contents then do
-// not matter).
+// not matter).  The stored z equals D^-1 r computed the same way, so both forms give the same bits.
 template <typename VR>
 struct DirLoad {
     VR dj;
     double rj[3];
-    VR po[3];
+    VR zj[3], po[3];
     __device__ __forceinline__ void load(const DirIn<VR>& in, long j) {
-        dj = in.dinv[j];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            rj[c] = in.r[3 * j + c];
+            if constexpr (kStoredZ<VR>)
+                zj[c] = in.z[3 * j + c];
+            else
+                rj[c] = in.r[3 * j + c];
             po[c] = in.pold[3 * j + c];
         }
+        if constexpr (!kStoredZ<VR>) dj = in.dinv[j];
     }
     __device__ __forceinline__ void finish(const VR (&beta)[3], VR (&pj)[3]) const {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const VR zj = dj * VR(rj[c]);
-            pj[c] = beta[c] != VR(0) ? fma(beta[c], po[c], zj) : zj;
+            VR z;
+            if constexpr (kStoredZ<VR>)
+                z = zj[c];
+            else
+                z = dj * VR(rj[c]);
+            pj[c] = beta[c] != VR(0) ? fma(beta[c], po[c], z) : z;
         }
     }
 };
@@ -515,6 +529,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
             const bool odd = t & 1;
             in.r = G(static_cast<const double*>(d.r));
             in.dinv = G(static_cast<const VR*>(d.dinv));
+            in.z = G(reinterpret_cast<const VR*>(d.z));
             in.pold = G(static_cast<const VR*>(odd ? d.p0 : d.p1));
             for (int c = 0; c < 3; ++c) in.beta[c] = VR(S.beta[c]);
             pnew = G(static_cast<VR*>(odd ? d.p1 : d.p0));
@@ -531,7 +546,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
 // PCG iteration t, second kernel.  Each work-group takes `per` consecutive row groups; per mesh it meets
 // it reads the state entering the iteration and the p.q bins once (alpha = r.z / p.q per active
 // column; row group 0's work-group clears the p.q bins of the next product), then advances y += alpha
-// p, r -= alpha q on its rows and adds their r.z (z = D^-1 r, not stored) and r.r into the bins.
+// p, r -= alpha q on its rows and adds their r.z (z = D^-1 r; stored in mixed precision) and r.r into
+// the bins.
 template <typename VR>
 __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem& wi, long t, const double (&al)[3],
                                              double (&acc)[6]) {
@@ -551,18 +567,20 @@ __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem&
         yv[c] = y[3 * i + c];
         rv[c] = r[3 * i + c];
     }
+    VR zv[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         yv[c] = fma(al[c], double(pv[c]), yv[c]);
         rv[c] = fma(-al[c], double(qv[c]), rv[c]);
-        const VR zi = di * VR(rv[c]);
-        acc[c] += rv[c] * double(zi);
+        zv[c] = di * VR(rv[c]);
+        acc[c] += rv[c] * double(zv[c]);
         acc[3 + c] += rv[c] * rv[c];
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         y[3 * i + c] = yv[c];
         r[3 * i + c] = rv[c];
+        if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zv[c];
     }
 }
 

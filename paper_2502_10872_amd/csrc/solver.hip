@@ -288,6 +288,7 @@ SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
     d.p1 = sim.p2.p;
     d.q = sim.q.p;
     d.dinv = sim.dinv.p;
+    d.z = sim.z.p;  // null in FP64
     d.mass = sim.mass.p;
     d.kdiag = sim.h->kdiag.p;
     d.pinned = sim.pinned.p;
@@ -560,6 +561,7 @@ void sim_alloc(shell_sim_s& sim) {
     for (auto* a : {&sim.x, &sim.v, &sim.xt, &sim.xhat, &sim.g, &sim.y, &sim.r, &sim.f, &sim.p, &sim.p2, &sim.q})
         a->alloc(size_t(std::max(n3, 1L)));
     sim.bins.alloc(size_t(2 * 2 * kBinQ * kBins));
+    if (sim.st->precision == SHELL_PREC_MIXED) sim.z.alloc(size_t(std::max(n3, 1L)));
     sim.mass.alloc(size_t(std::max(nv, 1L)));
     sim.dinv.alloc(size_t(std::max(nv, 1L)));
     sim.pinned.alloc(size_t(std::max(nv, 1L)));
