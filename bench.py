@@ -226,6 +226,18 @@ def step_error(S, torch, mesh, pb64, pbm, params, steps, short_iters=200):
     return dict(full_step_replayed_counts=full, one_newton_200_pcg=short)
 
 
+def force_error(S, torch, mesh, pb64, pbm):
+    """Relative force error of the mixed path against FP64 at the mixed simulation's current state."""
+    x, _, _ = S.shell_sim_get_state(pbm.sim, mesh.nv)
+    xd = torch.tensor(x, device="cuda")
+    f64 = torch.zeros_like(xd)
+    f32 = torch.zeros(xd.shape, dtype=torch.float32, device="cuda")
+    S.shell_eval_forces(pb64.st, xd, f64, None)
+    S.shell_eval_forces(pbm.st, xd, f32, None)
+    torch.cuda.synchronize()
+    return float(torch.linalg.norm(f32.double() - f64) / torch.linalg.norm(f64))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -288,7 +300,9 @@ def main(argv=None):
         e2, st2, lat2, prof2 = timed_steps(S, torch, pb_other, params, args.steps, args.sample_every,
                                            "fp64" if other == S.SHELL_PREC_FP64 else "mixed")
         pb64, pbm = (pb_other, pb) if head == S.SHELL_PREC_MIXED else (pb, pb_other)
+        ferr = force_error(S, torch, mesh, pb64, pbm)
         errs = step_error(S, torch, mesh, pb64, pbm, params, args.steps)
+        errs["force_rel_err"] = ferr
         compare = dict(precision="fp64" if other == S.SHELL_PREC_FP64 else "mixed", steps_per_s=args.steps / e2,
                        ms_per_step=1e3 * e2 / args.steps,
                        pcg_coord_iters=float(np.mean([s["pcg_total"] for s in st2])),

@@ -94,12 +94,16 @@ typedef void* shell_stream_t; /* hipStream_t */
  * node reflected through the edge midpoint and folded, eq 61; FVM additionally drops the twist
  * across the free edge).  The rest operators (eqs 10, 37-38, 50, App. C eqs 76-78), rest curvature
  * (eqs 14, 43, 51; shells only) and stencil areas are computed on the GPU in float64.
+ * clamped_edges  host [n_clamped][2] vertex pairs of boundary edges to clamp (the clamped operators of
+ *                eqs 30-31 and 59), or NULL with n_clamped = 0.  Not implemented: a non-empty list returns
+ *                SHELL_E_UNSUPPORTED; clamp by holding the clamped side's two vertex rows fixed instead
+ *                (the paper's own cantilever setting).
  * Errors: SHELL_E_INVALID_ARG, SHELL_E_NONMANIFOLD, SHELL_E_ORIENTATION, SHELL_E_DEGENERATE,
- * SHELL_E_OOM, SHELL_E_HIP.  The call synchronises `stream` before returning.
+ * SHELL_E_UNSUPPORTED, SHELL_E_OOM, SHELL_E_HIP.  The call synchronises `stream` before returning.
  */
 shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* tris, int64_t nt, int32_t model,
-                                    const shell_material_t* mat, const shell_config_t* cfg, shell_stream_t stream,
-                                    shell_stencils_t* out);
+                                    const shell_material_t* mat, const int32_t* clamped_edges, int64_t n_clamped,
+                                    const shell_config_t* cfg, shell_stream_t stream, shell_stencils_t* out);
 
 typedef struct {
     int64_t nv, nt;

@@ -77,14 +77,20 @@ const char* shell_status_string(shell_status_t s) {
 const char* shell_last_error(void) { return g_last_error.c_str(); }
 
 shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* tris, int64_t nt, int32_t model,
-                                    const shell_material_t* mat, const shell_config_t* cfg, shell_stream_t stream,
-                                    shell_stencils_t* out) {
+                                    const shell_material_t* mat, const int32_t* clamped_edges, int64_t n_clamped,
+                                    const shell_config_t* cfg, shell_stream_t stream, shell_stencils_t* out) {
     return guarded([&]() -> shell_status_t {
         SHELL_CHECK(out && mat && (X || nv == 0) && (tris || nt == 0), SHELL_E_INVALID_ARG, "null argument");
         *out = nullptr;
         SHELL_CHECK(model >= SHELL_EP && model <= SHELL_SS, SHELL_E_INVALID_ARG, "unknown model");
         SHELL_CHECK(nv >= 0 && nt >= 0 && nv < (int64_t(1) << 31) && 3 * nt < (int64_t(1) << 31), SHELL_E_INVALID_ARG,
                     "mesh size out of range");
+        SHELL_CHECK(n_clamped >= 0 && (clamped_edges || n_clamped == 0), SHELL_E_INVALID_ARG, "bad clamped edge list");
+        for (int64_t e = 0; e < 2 * n_clamped; ++e)
+            SHELL_CHECK(clamped_edges[e] >= 0 && clamped_edges[e] < nv, SHELL_E_INVALID_ARG,
+                        "clamped edge vertex out of range");
+        SHELL_CHECK(n_clamped == 0, SHELL_E_UNSUPPORTED,
+                    "clamped edge operators (eqs 30-31, 59) are not implemented; hold the clamped rows fixed");
         SHELL_CHECK(mat->young > 0 && mat->thickness > 0 && mat->density >= 0 && mat->poisson > -1.0 &&
                         mat->poisson < 1.0,
                     SHELL_E_INVALID_ARG, "material out of range");

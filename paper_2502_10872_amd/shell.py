@@ -16,6 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIBRARY = os.path.join(_HERE, "libshell_hip.so")
 
 SHELL_OK, SHELL_E_BUDGET, SHELL_E_NONFINITE = 0, 6, 5
+SHELL_E_INVALID_ARG, SHELL_E_UNSUPPORTED = 1, 9
 SHELL_PREC_FP64, SHELL_PREC_MIXED = 0, 1
 SHELL_PCG_TOLERANCE, SHELL_PCG_REPLAY = 0, 1
 SHELL_MAX_NEWTON = 64
@@ -107,7 +108,7 @@ def lib() -> ctypes.CDLL:
             raise RuntimeError(f"{LIBRARY} is missing: build it with `python -m paper_2502_10872_amd.build`")
         L = ctypes.CDLL(LIBRARY)
         P, i64, i32, d = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
-        L.shell_build_stencils.argtypes = [P, i64, P, i64, i32, P, P, P, P]
+        L.shell_build_stencils.argtypes = [P, i64, P, i64, i32, P, P, i64, P, P, P]
         L.shell_stencils_info.argtypes = [P, P]
         L.shell_stencils_export.argtypes = [P, P, P, P]
         L.shell_eval_forces.argtypes = [P, P, P, P, P]
@@ -176,15 +177,18 @@ def _model(m) -> int:
 
 
 def shell_build_stencils(X, tris, model, material: dict, precision=SHELL_PREC_FP64, block_vertices=0, reorder=1,
-                         stream=None, flags=0):
+                         stream=None, flags=0, clamped_edges=None):
     X = np.ascontiguousarray(X, dtype=np.float64)
     tris = np.ascontiguousarray(tris, dtype=np.int32)
     mat = shell_material_t(material["young"], material["poisson"], material["thickness"],
                            material.get("density", 0.0))
     cfg = shell_config_t(int(precision), int(block_vertices), int(reorder), int(flags))
+    ce = None if clamped_edges is None else np.ascontiguousarray(clamped_edges, dtype=np.int32).reshape(-1, 2)
     out = ctypes.c_void_p()
     _check(lib().shell_build_stencils(_np_ptr(X), X.shape[0], _np_ptr(tris), tris.shape[0], _model(model),
-                                      ctypes.byref(mat), ctypes.byref(cfg), _stream(stream), ctypes.byref(out)),
+                                      ctypes.byref(mat), None if ce is None else _np_ptr(ce),
+                                      0 if ce is None else ce.shape[0], ctypes.byref(cfg), _stream(stream),
+                                      ctypes.byref(out)),
            "shell_build_stencils")
     return out.value
 
