@@ -226,6 +226,48 @@ def step_error(S, torch, mesh, pb64, pbm, params, steps, short_iters=200):
     return dict(full_step_replayed_counts=full, one_newton_200_pcg=short)
 
 
+def stream_copy_gbs(torch):
+    """Read + write bandwidth of a plain elementwise kernel over 1 GiB (the practical streaming ceiling)."""
+    a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del a, b
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def force_models(S, I, torch, precisions, reps=20):
+    """Force kernel of every model on a 1024 x 1024 mesh (shells: the sphere cap; plates: a flat square
+    of the same side), launched back to back on one state (shell_sim_time_kernels)."""
+    out = {}
+    cap = I.workload_sphere_cap(1024, "SS")
+    side = cap.meta.get("side", 1.2 * cap.meta["radius"])
+    for model in I.MODELS:
+        if model.endswith("S"):
+            mesh = I.workload_sphere_cap(1024, model)
+        else:
+            mesh = I.plate_mesh(1024, side, 0.2, 2502108723, model, "ring")
+        for prec in precisions:
+            pb = S.Problem(mesh, I.MATERIAL, precision=prec)
+            kt = S.shell_sim_time_kernels(pb.sim, 1.0 / 30.0, reps=reps)
+            hinfo = S.shell_hessian_info(pb.h)
+            ab = algorithmic_bytes(pb.info, hinfo, prec)
+            ms = kt["force_ms"]
+            out[f"{model}_{'mixed' if prec == S.SHELL_PREC_MIXED else 'fp64'}"] = dict(
+                stencils=pb.info["ns"], force_ms=ms, stencils_per_s=pb.info["ns"] / (ms * 1e-3),
+                gbs=ab["force"] / (ms * 1e-3) / 1e9, frac=ab["force"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+            pb.close()
+        print(f"[bench] force timing {model} done", file=sys.stderr, flush=True)
+    return out
+
+
 def force_error(S, torch, mesh, pb64, pbm):
     """Relative force error of the mixed path against FP64 at the mixed simulation's current state."""
     x, _, _ = S.shell_sim_get_state(pbm.sim, mesh.nv)
@@ -241,7 +283,10 @@ def force_error(S, torch, mesh, pb64, pbm):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=6,
+                    help="timed steps (the PCG iteration count per step varies by tens of percent along the "
+                         "trajectory, so several steps are averaged)")
+    ap.add_argument("--error-steps", type=int, default=2, help="steps of the mixed-vs-FP64 error runs")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=1024)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed",
@@ -256,6 +301,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--max-pcg", type=int, default=400000, help="PCG iteration cap per coordinate solve")
     ap.add_argument("--workload", choices=("sphere-cap", "batch64"), default="sphere-cap")
+    ap.add_argument("--no-force-models", action="store_true",
+                    help="skip the per-model force kernel timing (six 1M-vertex meshes, both precisions)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args(argv)
@@ -301,7 +348,7 @@ def main(argv=None):
                                            "fp64" if other == S.SHELL_PREC_FP64 else "mixed")
         pb64, pbm = (pb_other, pb) if head == S.SHELL_PREC_MIXED else (pb, pb_other)
         ferr = force_error(S, torch, mesh, pb64, pbm)
-        errs = step_error(S, torch, mesh, pb64, pbm, params, args.steps)
+        errs = step_error(S, torch, mesh, pb64, pbm, params, args.error_steps)
         errs["force_rel_err"] = ferr
         compare = dict(precision="fp64" if other == S.SHELL_PREC_FP64 else "mixed", steps_per_s=args.steps / e2,
                        ms_per_step=1e3 * e2 / args.steps,
@@ -379,12 +426,15 @@ def main(argv=None):
         tiles=dict(block_vertices=pb.info["block_vertices"], nblocks=pb.info["nblocks"],
                    halo_factor=pb.info["ns_tiled"] / max(pb.info["ns"], 1)),
     )
-    if not args.no_cpu_baseline and args.size == 1024:
-        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)
+    out["roofline"]["stream_copy_gbs"] = stream_copy_gbs(torch)
     pb.close()
     if pb_other is not None:
         pb_other.close()
+    if not args.no_force_models and args.size == 1024:
+        out["force_models_isolated"] = force_models(S, I, torch, (S.SHELL_PREC_MIXED, S.SHELL_PREC_FP64))
+    if not args.no_cpu_baseline and args.size == 1024:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)
     print(json.dumps(out), flush=True)
 
 
