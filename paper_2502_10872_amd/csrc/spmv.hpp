@@ -183,12 +183,21 @@ struct SellStream {
              (row & 63);
     }
 
+    // A float64 matrix (twice the bytes of the vectors it meets) is read with non-temporal loads, which
+    // keep it from displacing the direction and product vectors that the update kernel reads next from
+    // the last-level cache (measured: FP64 iteration 105 -> 96 us on a 1M-vertex mesh); a float32 matrix
+    // is read with plain loads (non-temporal measured slower there).
     __device__ __forceinline__ void load(int k, int (&c)[U], MR (&a)[U]) const {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const long off = s0 + 64L * (k + u < w ? k + u : w - 1);
-            c[u] = int(stream_load(col + off));
-            a[u] = stream_load(val + off);
+            if constexpr (sizeof(MR) == 8) {
+                c[u] = int(__builtin_nontemporal_load(col + off));
+                a[u] = __builtin_nontemporal_load(val + off);
+            } else {
+                c[u] = int(col[off]);
+                a[u] = val[off];
+            }
         }
     }
 };
