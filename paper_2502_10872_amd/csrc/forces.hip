@@ -23,6 +23,8 @@
 // the difference is float32.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "devmath.hpp"
 #include "internal.hpp"
 
@@ -134,9 +136,12 @@ __device__ __forceinline__ void lds_add(double* acc, int slot, V3<R> v) {
     atomicAdd(acc + 3 * slot + 2, double(v.z));
 }
 
+// Largest force work-group; the kernels are compiled for it, so any size up to it can be launched.
+constexpr int kMaxForceThreads = 1024;
+
 // One work-group per (mesh, vertex tile) work item.  K = 4 (edge) or 6 (triangle) vertices per stencil.
 template <int MODEL, typename R>
-__global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__ descs,
+__global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc* __restrict__ descs,
                                                    const WorkItem* __restrict__ items, long nitems) {
     constexpr bool EDGE = (MODEL == SHELL_EP || MODEL == SHELL_ES);
     constexpr bool SHELL = (MODEL == SHELL_ES || MODEL == SHELL_FS || MODEL == SHELL_SS);
@@ -206,48 +211,53 @@ __global__ __launch_bounds__(256) void force_tiles(const ForceDesc* __restrict__
         }
     };
     const long e0 = d.boff[2 * blk], e1 = d.boff[2 * blk + 1];
-    const long S = blockDim.x;
-    if constexpr (sizeof(R) == 4) {
-        // mixed: two stencils per pass, both loaded before either is computed (a lane whose second
-        // stencil is past the end loads its first one twice and computes it once); measured 9% faster
-        // in float, slower in double (twice the registers)
-        for (long e = e0 + threadIdx.x; e < e1; e += 2 * S) {
-            const bool two = e + S < e1;
-            In a, b;
-            load(e, a);
-            load(two ? e + S : e, b);
-            compute(a);
-            if (two) compute(b);
-        }
-    } else {
-        for (long e = e0 + threadIdx.x; e < e1; e += S) {
-            In a;
-            load(e, a);
-            compute(a);
-        }
+    for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        In a;
+        load(e, a);
+        compute(a);
     }
     __syncthreads();
     gbl<R>* out = G(static_cast<R*>(d.f)) + 3 * base;
     for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
     if (d.epart) {
-        __shared__ double sh[8];
+        __shared__ double sh[kMaxForceThreads / 64];
         double v[1] = {e_own};
         block_sum<1>(v, sh);
         if (threadIdx.x == 0) d.epart[blk] = v[0];
     }
 }
 
+// Work-group size of a force kernel.  A launch has one work-group per tile (512 on a 1M-vertex mesh, two
+// per CU), so the waves in flight, which hide the latency of the stencil stream and of the position
+// gathers, come from the work-group size.  It is the largest multiple of 256 threads (one wave per
+// SIMD; uneven multiples leave a SIMD short of room for the second work-group) whose two work-groups
+// per CU fit the waves per SIMD that the kernel's VGPR count allows (512 VGPRs per SIMD lane, allocated
+// in granules of 8, at most 8 waves).  Edge kernels (46-86 VGPRs) get 512-1024 threads, triangle kernels
+// 512-768.  (Measured against a fixed 256 threads with two stencils per thread and pass: edge models
+// 9-15% faster, float shells 5%, the rest equal or up to 4% faster.)
+template <typename Kernel>
+int force_threads(Kernel kernel) {
+    hipFuncAttributes a{};
+    SHELL_HIP(hipFuncGetAttributes(&a, reinterpret_cast<const void*>(kernel)));
+    const int vgprs = std::max(8, (a.numRegs + 7) / 8 * 8);
+    const int waves = std::min(8, 512 / vgprs);  // per SIMD
+    return std::min(kMaxForceThreads, 256 * std::max(1, waves / 2));
+}
+
 template <int MODEL>
 void launch_model(int precision, const ForceDesc* descs, const WorkItem* items, long nitems, int lds_T,
                   hipStream_t s, hipEvent_t start, hipEvent_t stop) {
-    const dim3 blk(256);
+    static const int threads_d = force_threads(force_tiles<MODEL, double>);
+    static const int threads_f = force_threads(force_tiles<MODEL, float>);
     const dim3 grid(unsigned(xcd_grid(nitems)));
     const uint32_t lds = uint32_t(size_t(3 * lds_T) * sizeof(double));
     // start/stop (may be null) receive the dispatch's own begin and end times
     if (precision == SHELL_PREC_FP64)
-        hipExtLaunchKernelGGL(force_tiles<MODEL, double>, grid, blk, lds, s, start, stop, 0, descs, items, nitems);
+        hipExtLaunchKernelGGL(force_tiles<MODEL, double>, grid, dim3(threads_d), lds, s, start, stop, 0, descs,
+                              items, nitems);
     else
-        hipExtLaunchKernelGGL(force_tiles<MODEL, float>, grid, blk, lds, s, start, stop, 0, descs, items, nitems);
+        hipExtLaunchKernelGGL(force_tiles<MODEL, float>, grid, dim3(threads_f), lds, s, start, stop, 0, descs,
+                              items, nitems);
     SHELL_HIP(hipGetLastError());
 }
 
