@@ -187,6 +187,7 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         if (precision == SHELL_PREC_MIXED) {
             st->tBf.alloc(size_t(r * k) * nst);
             st->tk0f.alloc(size_t(r) * nst);
+            st->tC0f.alloc(size_t(3 * r) * nst);
         } else {
             st->tB.alloc(size_t(r * k) * nst);
             st->tk0.alloc(size_t(r) * nst);
@@ -262,6 +263,8 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
             d.tidx = st->tidx.p;
             d.tB = f32 ? static_cast<const void*>(st->tBf.p) : static_cast<const void*>(st->tB.p);
             d.tk0 = f32 ? static_cast<const void*>(st->tk0f.p) : static_cast<const void*>(st->tk0.p);
+            d.X0 = st->X.p;
+            d.tC0 = st->tC0f.p;
             d.nst = st->nst_pad;
             d.nv = st->nv;
             d.T = st->T;
@@ -642,7 +645,7 @@ shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, i
         int64_t a = 0, b = 0, c = 0;
         for (size_t v : {st.X.bytes(), st.tris.bytes(), st.perm_d.bytes(), st.idx.bytes(), st.B.bytes(),
                          st.k0.bytes(), st.flags.bytes(), st.boff.bytes(), st.tsrc.bytes(), st.tidx.bytes(),
-                         st.tB.bytes(), st.tk0.bytes(), st.tBf.bytes(), st.tk0f.bytes(), st.xin.bytes(),
+                         st.tB.bytes(), st.tk0.bytes(), st.tBf.bytes(), st.tk0f.bytes(), st.tC0f.bytes(), st.xin.bytes(),
                          st.fout.bytes(), st.epart.bytes(), st.fdesc.bytes(), st.tile_items.bytes()})
             a += int64_t(v);
         for (size_t v : {h.scol.bytes(), h.width.bytes(), h.sptr.bytes(), h.rowlen.bytes(), h.val.bytes(),

@@ -20,7 +20,12 @@
 // unit normal of the central triangle (eq 15) or the bisector of the two hinge triangle normals
 // (edge; the line of eq 8), its gradient by the chain rule of App. B (eqs 67, 73).
 // Mixed precision: positions are gathered in float64 and differenced in float64; everything after
-// the difference is float32.
+// the difference is float32.  The curvature is formed relative to the rest shape, C = C0 + B (x^e - X^e)
+// with C0 = B X^e precomputed in float64, so float32 rounds the displacement differences (of the size
+// of the deformation) instead of the position differences (of the size of an edge): the net force of
+// a smooth deformation is a cancelling sum over stencils, and with world differences its relative
+// error grew with the mesh resolution and with the inverse of the deformation (2e-3 at 1024x1024 for an
+// amplitude of side/100).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -32,13 +37,11 @@ namespace shell {
 
 namespace {
 
+// Edge stencil (vertices 0-3, hinge 1-2) from the differences a = x0 - x1, c = x2 - x1, b = x3 - x1 and the
+// curvature vector C = sum_j L_j x_j formed by the caller.
 template <typename R, bool SHELL>
-__device__ __forceinline__ void edge_stencil(const V3<double> (&xg)[4], const R (&L)[4], R kappa0,
+__device__ __forceinline__ void edge_stencil(V3<R> a, V3<R> c, V3<R> b, V3<R> C, const R (&L)[4], R kappa0,
                                              V3<R> (&f)[4], R& energy) {
-    V3<R> a = cvt<R>(xg[0] - xg[1]), c = cvt<R>(xg[2] - xg[1]), b = cvt<R>(xg[3] - xg[1]);
-    V3<R> C = L[0] * a;
-    fma3(C, L[2], c);
-    fma3(C, L[3], b);
     if constexpr (!SHELL) {
         energy = R(0.5) * dot(C, C);
 #pragma unroll
@@ -67,20 +70,11 @@ __device__ __forceinline__ void edge_stencil(const V3<double> (&xg)[4], const R 
     }
 }
 
+// Triangle stencil from the differences d_j = x_j - x_0 (d_0 = 0) and the curvature vectors
+// C_i = sum_j B_ij x_j formed by the caller.
 template <typename R, bool SHELL>
-__device__ __forceinline__ void tri_stencil(const V3<double> (&xg)[6], const R (&B)[3][6], const R (&k0)[3], R kb,
-                                            R nu, V3<R> (&f)[6], R& energy) {
-    V3<R> d[6];
-    d[0] = mk(R(0), R(0), R(0));
-#pragma unroll
-    for (int j = 1; j < 6; ++j) d[j] = cvt<R>(xg[j] - xg[0]);
-    V3<R> C[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        C[i] = B[i][1] * d[1];
-#pragma unroll
-        for (int j = 2; j < 6; ++j) fma3(C[i], B[i][j], d[j]);
-    }
+__device__ __forceinline__ void tri_stencil(const V3<R> (&d)[6], const V3<R> (&C)[3], const R (&B)[3][6],
+                                            const R (&k0)[3], R kb, R nu, V3<R> (&f)[6], R& energy) {
     const R t = R(0.5) * (R(1) - nu);
     if constexpr (!SHELL) {
         V3<R> DC[3];
@@ -169,10 +163,17 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
     // blocks, so each wave reads whole blocks: every field of its 64 stencils is one contiguous run
     constexpr int NB = EDGE ? 4 : 18;               // operator entries per stencil
     constexpr int NK = EDGE ? 1 : 3;                // rest-curvature slots per stencil (read for shells)
+    constexpr bool REL = sizeof(R) == 4;            // float: curvature relative to the rest shape
+    constexpr int NC = REL ? 3 * NK : 1;            // rest curvature vector components (float only)
+    constexpr int KX = REL ? K : 1;
+    const gbl<const double>* X0 = G(d.X0);
+    const gbl<const float>* tC0 = G(d.tC0);
     struct In {
         int vid[K];
         V3<double> xg[K];
+        V3<double> Xg[KX];
         R ob[NB + NK];
+        R c0[NC];
     };
     auto load = [&](long e, In& in) {
         const long sb = (e / kStreamBlock) * kStreamBlock, lane = e % kStreamBlock;
@@ -183,15 +184,42 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
         for (int q = 0; q < NB; ++q) in.ob[q] = stream_ld<R>(tB + at(NB, q));
 #pragma unroll
         for (int q = 0; q < NK; ++q) in.ob[NB + q] = SHELL ? stream_ld<R>(tk0 + at(NK, q)) : R(0);
+        if constexpr (REL) {
+#pragma unroll
+            for (int q = 0; q < NC; ++q) in.c0[q] = stream_ld<R>(tC0 + at(NC, q));
+        }
 #pragma unroll
         for (int j = 0; j < K; ++j) in.xg[j] = {x[3L * in.vid[j]], x[3L * in.vid[j] + 1], x[3L * in.vid[j] + 2]};
+        if constexpr (REL) {
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                in.Xg[j] = {X0[3L * in.vid[j]], X0[3L * in.vid[j] + 1], X0[3L * in.vid[j] + 2]};
+        }
+    };
+    // float64 difference of vertex j from the origin o, rounded to R: of the positions, and (float only)
+    // of the displacements from the rest shape
+    auto diff = [&](const In& in, int j, int o) { return cvt<R>(in.xg[j] - in.xg[o]); };
+    auto udiff = [&](const In& in, int j, int o) {
+        return cvt<R>((in.xg[j] - in.xg[o]) - (in.Xg[REL ? j : 0] - in.Xg[REL ? o : 0]));
     };
     auto compute = [&](const In& in) {
         V3<R> fs[K];
         R en;
         if constexpr (EDGE) {
             const R L[4] = {in.ob[0], in.ob[1], in.ob[2], in.ob[3]};
-            edge_stencil<R, SHELL>(in.xg, L, in.ob[4], fs, en);
+            const V3<R> a = diff(in, 0, 1), c = diff(in, 2, 1), b = diff(in, 3, 1);
+            V3<R> C;
+            if constexpr (REL) {
+                C = mk(in.c0[0], in.c0[1], in.c0[2]);
+                fma3(C, L[0], udiff(in, 0, 1));
+                fma3(C, L[2], udiff(in, 2, 1));
+                fma3(C, L[3], udiff(in, 3, 1));
+            } else {
+                C = L[0] * a;
+                fma3(C, L[2], c);
+                fma3(C, L[3], b);
+            }
+            edge_stencil<R, SHELL>(a, c, b, C, L, in.ob[4], fs, en);
         } else {
             R Bm[3][6], k0[3];
 #pragma unroll
@@ -200,7 +228,29 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
                 for (int j = 0; j < 6; ++j) Bm[i][j] = in.ob[i * 6 + j];
                 k0[i] = in.ob[NB + i];
             }
-            tri_stencil<R, SHELL>(in.xg, Bm, k0, kb, nu, fs, en);
+            V3<R> dd[6], C[3];
+            dd[0] = mk(R(0), R(0), R(0));
+#pragma unroll
+            for (int j = 1; j < 6; ++j) dd[j] = diff(in, j, 0);
+            if constexpr (REL) {
+                V3<R> du[6];
+#pragma unroll
+                for (int j = 1; j < 6; ++j) du[j] = udiff(in, j, 0);
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    C[i] = mk(in.c0[3 * i], in.c0[3 * i + 1], in.c0[3 * i + 2]);
+#pragma unroll
+                    for (int j = 1; j < 6; ++j) fma3(C[i], Bm[i][j], du[j]);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    C[i] = Bm[i][1] * dd[1];
+#pragma unroll
+                    for (int j = 2; j < 6; ++j) fma3(C[i], Bm[i][j], dd[j]);
+                }
+            }
+            tri_stencil<R, SHELL>(dd, C, Bm, k0, kb, nu, fs, en);
         }
         // the tile that owns vertex 1 of the stencil counts its energy
         if (unsigned(in.vid[0] - base) < unsigned(nown)) e_own += double(en);

@@ -135,6 +135,10 @@ struct ForceDesc {
     const int32_t* tidx;
     const void* tB;        // double or float operator stream
     const void* tk0;
+    // mixed precision only: rest positions and the float stream of rest curvature vectors C0 = B X^e
+    // (r x 3 per stencil); the float kernels form C = C0 + B (x^e - X^e)
+    const double* X0;
+    const float* tC0;
     int64_t nst, nv;
     int32_t T, model;
     double kb, nu;
@@ -204,6 +208,7 @@ struct shell_stencils_s {
     shell::DevArray<double> tk0;         // blocks of 64: [nst_pad / 64][r][64]
     shell::DevArray<float> tBf;          // mixed-precision copies
     shell::DevArray<float> tk0f;
+    shell::DevArray<float> tC0f;         // mixed: rest curvature vectors [r][3] per stencil
     // scratch for the caller-order entry point
     shell::DevArray<double> xin;         // [nv][3]
     shell::DevArray<double> fout;        // [nv][3] (float for mixed, sized in doubles)

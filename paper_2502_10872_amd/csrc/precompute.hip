@@ -205,9 +205,10 @@ __global__ void precompute_tri(const double* __restrict__ X, const int32_t* __re
 }
 
 __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_t* __restrict__ idx,
-                          const double* __restrict__ B, const double* __restrict__ k0, long ns, int k, int r,
-                          int32_t* __restrict__ tidx, double* __restrict__ tB, double* __restrict__ tk0,
-                          float* __restrict__ tBf, float* __restrict__ tk0f) {
+                          const double* __restrict__ B, const double* __restrict__ k0, const double* __restrict__ X,
+                          long ns, int k, int r, int32_t* __restrict__ tidx, double* __restrict__ tB,
+                          double* __restrict__ tk0, float* __restrict__ tBf, float* __restrict__ tk0f,
+                          float* __restrict__ tC0f) {
     long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (e >= nt) return;
     const long s = src[e];  // -1: alignment padding, filled with vertex 0 and zeros (never read)
@@ -223,6 +224,21 @@ __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_
         const double v = s < 0 ? 0.0 : k0[q * ns + s];
         if (tk0) tk0[at(r, q)] = v;
         if (tk0f) tk0f[at(r, q)] = float(v);
+    }
+    if (tC0f) {
+        // rest curvature vectors C0_i = sum_j B_ij (X_j - X_1) in float64 (rows of B sum to zero)
+        for (int i = 0; i < r; ++i) {
+            double c[3] = {0.0, 0.0, 0.0};
+            if (s >= 0) {
+                const long o = idx[s];
+                for (int j = 1; j < k; ++j) {
+                    const long v = idx[j * ns + s];
+                    const double b = B[(i * k + j) * ns + s];
+                    for (int a = 0; a < 3; ++a) c[a] += b * (X[3 * v + a] - X[3 * o + a]);
+                }
+            }
+            for (int a = 0; a < 3; ++a) tC0f[at(3 * r, 3 * i + a)] = float(c[a]);
+        }
     }
 }
 
@@ -255,8 +271,9 @@ void launch_tile_copy(shell_stencils_s& st, hipStream_t s) {
     const long nt = st.nst_pad;
     if (nt == 0) return;
     int blk = 256;
-    tile_copy<<<(nt + blk - 1) / blk, blk, 0, s>>>(st.tsrc.p, nt, st.idx.p, st.B.p, st.k0.p, st.ns, st.k, st.r,
-                                                   st.tidx.p, st.tB.p, st.tk0.p, st.tBf.p, st.tk0f.p);
+    tile_copy<<<(nt + blk - 1) / blk, blk, 0, s>>>(st.tsrc.p, nt, st.idx.p, st.B.p, st.k0.p, st.X.p, st.ns, st.k,
+                                                   st.r, st.tidx.p, st.tB.p, st.tk0.p, st.tBf.p, st.tk0f.p,
+                                                   st.tC0f.p);
     SHELL_HIP(hipGetLastError());
 }
 

@@ -319,6 +319,8 @@ ForceDesc force_desc(shell_sim_s& sim) {
     d.tidx = st.tidx.p;
     d.tB = f32 ? static_cast<const void*>(st.tBf.p) : static_cast<const void*>(st.tB.p);
     d.tk0 = f32 ? static_cast<const void*>(st.tk0f.p) : static_cast<const void*>(st.tk0.p);
+    d.X0 = st.X.p;
+    d.tC0 = st.tC0f.p;
     d.nst = st.nst_pad;
     d.nv = st.nv;
     d.T = st.T;

@@ -110,6 +110,34 @@ def test_mixed_precision_forces_within_bound(model):
         S.shell_destroy_stencils(st)
 
 
+@pytest.mark.parametrize("model", I.MODELS)
+def test_mixed_forces_of_a_small_smooth_deformation(model):
+    """Mixed precision on a 128 x 128 mesh deformed from rest by a smooth field of amplitude side/10^4.
+    The net force is a cancelling sum over stencils; the float kernels form the curvature from the
+    displacement differences, C = C0 + B (x^e - X^e), which keeps the error near 1e-5 (plates) and 2e-4
+    (shells, whose bending strain n.C - kappa0 keeps a float cancellation).  Float position differences
+    gave 2e-2 here."""
+    if model.endswith("S"):
+        mesh = I.workload_sphere_cap(128, model)
+    else:
+        mesh = I.plate_mesh(128, 1.0, 0.2, 5, model, "ring")
+    X = mesh.X
+    side = float(X[:, 0].max() - X[:, 0].min())
+    k, a = 2.0 * np.pi / side, 1e-4 * side
+    u = np.stack([np.sin(k * X[:, 0]) * np.cos(k * X[:, 1]), np.cos(k * X[:, 0]) * np.sin(k * X[:, 1]),
+                  np.sin(k * X[:, 0]) * np.sin(k * X[:, 1])], axis=1)
+    x = X + a * u
+    f_ref, _ = oracle_stencils(model, mesh).forces(x)
+    st = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, precision=S.SHELL_PREC_MIXED)
+    try:
+        f, _ = gpu_forces(st, x, f32=True)
+        err = rel(f, f_ref)
+        print(f"{model} mixed force rel err at a smooth deformation of amplitude side/1e4: {err:.2e}")
+        assert err <= (5e-4 if model.endswith("S") else 1e-4)
+    finally:
+        S.shell_destroy_stencils(st)
+
+
 @pytest.mark.parametrize("model,flags", [(m, 0) for m in I.MODELS] + [("SS", 1), ("EP", 1)])
 def test_hessian_and_apply_match_oracle(model, flags):
     """flags = 1: the product without LDS staging (32-bit column ids, direct gathers)."""
