@@ -29,9 +29,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
     """Bytes each kernel must move once (no re-reads, no SELL padding), per launch.
 
-    force:  per stencil its k vertex ids, r x k operator, (shells) r rest curvatures and (mixed) the r x 3
-            rest curvature vectors; per vertex the position read (mixed: also the rest position) and the
-            force written.
+    force:  per stencil its k vertex ids, r x k operator, (shells) r rest curvatures and, in mixed
+            precision, the r x 3 rest curvature vectors and (shells) the rest differences of the normal;
+            per vertex the position (mixed: displacement from rest) read and the force written.
     spmv:   (the product kernel, which also forms the new direction p = z + beta p_old) every nonzero's
             value and 16-bit local column id, each row group's distinct-column list, slice widths and
             offsets, and per vertex the direction's inputs (FP64: r and D^-1; mixed: the stored float z)
@@ -41,8 +41,9 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
     shell = info["model"] in (1, 3, 5)
     mixed = precision == 1
     real = 4 if mixed else 8  # stencil operators, matrix values, p, q, z, D^-1, forces
-    per_stencil = 4 * k + real * r * k + (real * r if shell else 0) + (4 * 3 * r if mixed else 0)
-    force = ns * per_stencil + nv * (24 + 3 * real + (24 if mixed else 0))
+    rest_diffs = (9 if k == 4 else 6) if shell else 0
+    per_stencil = 4 * k + real * r * k + (real * r if shell else 0) + (4 * (3 * r + rest_diffs) if mixed else 0)
+    force = ns * per_stencil + nv * (24 + 3 * real)
     ngroups = (nv + 511) // 512  # 512-row groups
     idx = 2 if hinfo["staged"] else 4
     direction_in = 3 * real if mixed else 24 + real

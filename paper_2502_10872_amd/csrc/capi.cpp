@@ -182,15 +182,12 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         st->tsrc.alloc(til.src.size());
         st->tsrc.upload(til.src.data(), til.src.size(), s);
         const size_t nst = size_t(st->nst_pad);
-        st->tidx.alloc(size_t(k) * nst);
         // only the precision the force kernel streams is kept in the tiled layout
         if (precision == SHELL_PREC_MIXED) {
-            st->tBf.alloc(size_t(r * k) * nst);
-            st->tk0f.alloc(size_t(r) * nst);
-            st->tC0f.alloc(size_t(3 * r) * nst);
+            st->trec32.alloc(size_t(4 * stream_chunks(rec32_fields(k, r, model_is_shell(model)), 4)) * nst);
         } else {
-            st->tB.alloc(size_t(r * k) * nst);
-            st->tk0.alloc(size_t(r) * nst);
+            st->tidx.alloc(size_t(4 * stream_chunks(k, 4)) * nst);
+            st->trec64.alloc(size_t(2 * stream_chunks(rec64_fields(k, r), 2)) * nst);
         }
         launch_tile_copy(*st, s);
         st->epart.alloc(size_t(st->nblocks));
@@ -253,7 +250,7 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
         const bool f32 = st->precision == SHELL_PREC_MIXED;
         if (st->nv > 0 && !st->fdesc.p) {
             // caller-order staging, descriptor and tile items, made on first use
-            st->xin.alloc(size_t(3 * st->nv));
+            st->xin.alloc(size_t((f32 ? 4 : 3) * st->nv));  // mixed: padded displacements
             st->fout.alloc(size_t(3 * st->nv));
             ForceDesc d{};
             d.x = st->xin.p;
@@ -261,10 +258,7 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
             d.epart = st->epart.p;
             d.boff = st->boff.p;
             d.tidx = st->tidx.p;
-            d.tB = f32 ? static_cast<const void*>(st->tBf.p) : static_cast<const void*>(st->tB.p);
-            d.tk0 = f32 ? static_cast<const void*>(st->tk0f.p) : static_cast<const void*>(st->tk0.p);
-            d.X0 = st->X.p;
-            d.tC0 = st->tC0f.p;
+            d.trec = f32 ? static_cast<const void*>(st->trec32.p) : static_cast<const void*>(st->trec64.p);
             d.nst = st->nst_pad;
             d.nv = st->nv;
             d.T = st->T;
@@ -280,7 +274,10 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
                                 hipMemcpyHostToDevice));
         }
         if (st->nv > 0) {
-            launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
+            if (f32)
+                launch_gather_displacements(x, st->perm_d.p, st->X.p, st->xin.p, st->nv, s);
+            else
+                launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
             launch_force_items(st->model, st->precision, st->fdesc.p, st->tile_items.p, st->nblocks, st->T, s);
             launch_scatter_rows(st->fout.p, st->perm_d.p, f, st->nv, f32, s);
         }
@@ -645,7 +642,7 @@ shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, i
         int64_t a = 0, b = 0, c = 0;
         for (size_t v : {st.X.bytes(), st.tris.bytes(), st.perm_d.bytes(), st.idx.bytes(), st.B.bytes(),
                          st.k0.bytes(), st.flags.bytes(), st.boff.bytes(), st.tsrc.bytes(), st.tidx.bytes(),
-                         st.tB.bytes(), st.tk0.bytes(), st.tBf.bytes(), st.tk0f.bytes(), st.tC0f.bytes(), st.xin.bytes(),
+                         st.trec64.bytes(), st.trec32.bytes(), st.xin.bytes(),
                          st.fout.bytes(), st.epart.bytes(), st.fdesc.bytes(), st.tile_items.bytes()})
             a += int64_t(v);
         for (size_t v : {h.scol.bytes(), h.width.bytes(), h.sptr.bytes(), h.rowlen.bytes(), h.val.bytes(),

@@ -112,15 +112,12 @@ __device__ __forceinline__ void tri_stencil(const V3<R> (&d)[6], const V3<R> (&C
     }
 }
 
-// Stencil-stream load: non-temporal for the FP64 kernels, plain for the mixed ones (measured: each form
-// is the faster one for its precision by 4-6%).
-template <typename R, typename T>
-__device__ __forceinline__ T stream_ld(const gbl<const T>* p) {
-    if constexpr (sizeof(R) == 8)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
+// 16-byte stream chunks (clang vector types, which load through address-space pointers in one
+// instruction).  The FP64 streams are read with non-temporal loads, the float record with plain loads
+// (each the faster form for its precision).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // tile accumulator in float64 for both precisions (ds_add_f64)
 template <typename R>
@@ -149,9 +146,6 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
     // global-address views of the descriptor's pointers: global loads wait on the vector-memory counter
     // only, so the LDS accumulation does not stall behind loads in flight
     const gbl<const double>* x = G(static_cast<const double*>(d.x));
-    const gbl<const int32_t>* tidx = G(d.tidx);
-    const gbl<const R>* tB = G(static_cast<const R*>(d.tB));
-    const gbl<const R>* tk0 = G(static_cast<const R*>(d.tk0));
     const R kb = R(d.kb), nu = R(d.nu);
     const long blk = wi.unit;
     const long base = blk * long(d.T);
@@ -162,58 +156,103 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
     // a tile's list starts on a 64-stencil block and the work-group's stride is a whole number of
     // blocks, so each wave reads whole blocks: every field of its 64 stencils is one contiguous run
     constexpr int NB = EDGE ? 4 : 18;               // operator entries per stencil
-    constexpr int NK = EDGE ? 1 : 3;                // rest-curvature slots per stencil (read for shells)
+    constexpr int NK = EDGE ? 1 : 3;                // rest-curvature slots per stencil (zero for plates)
     constexpr bool REL = sizeof(R) == 4;            // float: curvature relative to the rest shape
     constexpr int NC = REL ? 3 * NK : 1;            // rest curvature vector components (float only)
-    constexpr int KX = REL ? K : 1;
-    const gbl<const double>* X0 = G(d.X0);
-    const gbl<const float>* tC0 = G(d.tC0);
+    constexpr int ND = REL ? (rec32_rest_diffs(K, SHELL) ? rec32_rest_diffs(K, SHELL) : 1) : 1;
+    // 16-byte chunks per stencil: mixed, one record of ids, operator, rest curvatures, C0 and rest
+    // differences; FP64, the ids and the float64 values in two streams
+    constexpr int NCH32 = stream_chunks(rec32_fields(K, NK, SHELL), 4);
+    constexpr int NCHI = stream_chunks(K, 4);
+    constexpr int NCHV = stream_chunks(rec64_fields(K, NK), 2);
     struct In {
         int vid[K];
-        V3<double> xg[K];
-        V3<double> Xg[KX];
+        V3<double> pg[K];  // FP64: positions; mixed: displacements from the rest shape
         R ob[NB + NK];
         R c0[NC];
+        R rd[ND];          // mixed shells: rest differences
     };
     auto load = [&](long e, In& in) {
-        const long sb = (e / kStreamBlock) * kStreamBlock, lane = e % kStreamBlock;
-        auto at = [&](int nf, int f) { return sb * nf + f * kStreamBlock + lane; };
-#pragma unroll
-        for (int j = 0; j < K; ++j) in.vid[j] = stream_ld<R>(tidx + at(K, j));
-#pragma unroll
-        for (int q = 0; q < NB; ++q) in.ob[q] = stream_ld<R>(tB + at(NB, q));
-#pragma unroll
-        for (int q = 0; q < NK; ++q) in.ob[NB + q] = SHELL ? stream_ld<R>(tk0 + at(NK, q)) : R(0);
+        const long first = (e / kStreamBlock) * kStreamBlock, lane = e % kStreamBlock;
         if constexpr (REL) {
+            const gbl<const f32x4>* rec = G(static_cast<const f32x4*>(d.trec)) + first * NCH32 + lane;
+            float f[4 * NCH32];
 #pragma unroll
-            for (int q = 0; q < NC; ++q) in.c0[q] = stream_ld<R>(tC0 + at(NC, q));
-        }
+            for (int c = 0; c < NCH32; ++c) {
+                const f32x4 v = rec[c * kStreamBlock];
+                f[4 * c] = v.x;
+                f[4 * c + 1] = v.y;
+                f[4 * c + 2] = v.z;
+                f[4 * c + 3] = v.w;
+            }
 #pragma unroll
-        for (int j = 0; j < K; ++j) in.xg[j] = {x[3L * in.vid[j]], x[3L * in.vid[j] + 1], x[3L * in.vid[j] + 2]};
-        if constexpr (REL) {
+            for (int j = 0; j < K; ++j) in.vid[j] = __float_as_int(f[j]);
+#pragma unroll
+            for (int q = 0; q < NB + NK; ++q) in.ob[q] = f[K + q];
+#pragma unroll
+            for (int q = 0; q < NC; ++q) in.c0[q] = f[K + NB + NK + q];
+            if constexpr (SHELL) {
+#pragma unroll
+                for (int q = 0; q < ND; ++q) in.rd[q] = f[K + NB + NK + NC + q];
+            }
+            // padded displacements: (x, y) and (z, 0) are two aligned 16-byte loads per vertex
+            const gbl<const f64x2>* u2 = G(reinterpret_cast<const f64x2*>(d.x));
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const f64x2 a = u2[2L * in.vid[j]], b = u2[2L * in.vid[j] + 1];
+                in.pg[j] = {a.x, a.y, b.x};
+            }
+        } else {
+            const gbl<const i32x4>* ti = G(reinterpret_cast<const i32x4*>(d.tidx)) + first * NCHI + lane;
+            const gbl<const f64x2>* tv = G(static_cast<const f64x2*>(d.trec)) + first * NCHV + lane;
+            int fi[4 * NCHI];
+            double fv[2 * NCHV];
+#pragma unroll
+            for (int c = 0; c < NCHI; ++c) {
+                const i32x4 v = __builtin_nontemporal_load(ti + c * kStreamBlock);
+                fi[4 * c] = v.x;
+                fi[4 * c + 1] = v.y;
+                fi[4 * c + 2] = v.z;
+                fi[4 * c + 3] = v.w;
+            }
+#pragma unroll
+            for (int c = 0; c < NCHV; ++c) {
+                const f64x2 v = __builtin_nontemporal_load(tv + c * kStreamBlock);
+                fv[2 * c] = v.x;
+                fv[2 * c + 1] = v.y;
+            }
+#pragma unroll
+            for (int j = 0; j < K; ++j) in.vid[j] = fi[j];
+#pragma unroll
+            for (int q = 0; q < NB + NK; ++q) in.ob[q] = R(fv[q]);
 #pragma unroll
             for (int j = 0; j < K; ++j)
-                in.Xg[j] = {X0[3L * in.vid[j]], X0[3L * in.vid[j] + 1], X0[3L * in.vid[j] + 2]};
+                in.pg[j] = {x[3L * in.vid[j]], x[3L * in.vid[j] + 1], x[3L * in.vid[j] + 2]};
         }
     };
-    // float64 difference of vertex j from the origin o, rounded to R: of the positions, and (float only)
-    // of the displacements from the rest shape
-    auto diff = [&](const In& in, int j, int o) { return cvt<R>(in.xg[j] - in.xg[o]); };
-    auto udiff = [&](const In& in, int j, int o) {
-        return cvt<R>((in.xg[j] - in.xg[o]) - (in.Xg[REL ? j : 0] - in.Xg[REL ? o : 0]));
-    };
+    // float64 difference of the gathered vectors of vertices j and o, rounded to R (FP64: of positions;
+    // mixed: of displacements)
+    auto diff = [&](const In& in, int j, int o) { return cvt<R>(in.pg[j] - in.pg[o]); };
+    auto rest = [&](const In& in, int q) { return mk(in.rd[3 * q], in.rd[3 * q + 1], in.rd[3 * q + 2]); };
     auto compute = [&](const In& in) {
         V3<R> fs[K];
         R en;
         if constexpr (EDGE) {
             const R L[4] = {in.ob[0], in.ob[1], in.ob[2], in.ob[3]};
-            const V3<R> a = diff(in, 0, 1), c = diff(in, 2, 1), b = diff(in, 3, 1);
+            V3<R> a = diff(in, 0, 1), c = diff(in, 2, 1), b = diff(in, 3, 1);
             V3<R> C;
             if constexpr (REL) {
+                // a, c, b are displacement differences here: C = C0 + B u^e, then the position
+                // differences of the normal are the rest ones plus these
                 C = mk(in.c0[0], in.c0[1], in.c0[2]);
-                fma3(C, L[0], udiff(in, 0, 1));
-                fma3(C, L[2], udiff(in, 2, 1));
-                fma3(C, L[3], udiff(in, 3, 1));
+                fma3(C, L[0], a);
+                fma3(C, L[2], c);
+                fma3(C, L[3], b);
+                if constexpr (SHELL) {
+                    a = rest(in, 0) + a;
+                    c = rest(in, 1) + c;
+                    b = rest(in, 2) + b;
+                }
             } else {
                 C = L[0] * a;
                 fma3(C, L[2], c);
@@ -232,23 +271,19 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
             dd[0] = mk(R(0), R(0), R(0));
 #pragma unroll
             for (int j = 1; j < 6; ++j) dd[j] = diff(in, j, 0);
-            if constexpr (REL) {
-                V3<R> du[6];
 #pragma unroll
-                for (int j = 1; j < 6; ++j) du[j] = udiff(in, j, 0);
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
+            for (int i = 0; i < 3; ++i) {
+                if constexpr (REL)
                     C[i] = mk(in.c0[3 * i], in.c0[3 * i + 1], in.c0[3 * i + 2]);
+                else
+                    C[i] = mk(R(0), R(0), R(0));
 #pragma unroll
-                    for (int j = 1; j < 6; ++j) fma3(C[i], Bm[i][j], du[j]);
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < 3; ++i) {
-                    C[i] = Bm[i][1] * dd[1];
-#pragma unroll
-                    for (int j = 2; j < 6; ++j) fma3(C[i], Bm[i][j], dd[j]);
-                }
+                for (int j = 1; j < 6; ++j) fma3(C[i], Bm[i][j], dd[j]);
+            }
+            if constexpr (REL && SHELL) {
+                // the normal and its gradient use the position differences of the central triangle
+                dd[1] = rest(in, 0) + dd[1];
+                dd[2] = rest(in, 1) + dd[2];
             }
             tri_stencil<R, SHELL>(dd, C, Bm, k0, kb, nu, fs, en);
         }
@@ -320,6 +355,17 @@ __global__ void energy_finalize(const double* __restrict__ part, long n, double*
     if (threadIdx.x == 0) *out = v[0];
 }
 
+// dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order displacements from the rest
+// shape, padded to four doubles (the mixed-precision force kernels' input)
+__global__ void gather_displacements(const double* __restrict__ src, const int32_t* __restrict__ perm,
+                                     const double* __restrict__ X, double* __restrict__ dst, long nv) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    long u = perm[i];
+    for (int c = 0; c < 3; ++c) dst[4 * i + c] = src[3 * u + c] - X[3 * i + c];
+    dst[4 * i + 3] = 0.0;
+}
+
 __global__ void gather_rows(const double* __restrict__ src, const int32_t* __restrict__ perm,
                             double* __restrict__ dst, long nv) {
     long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
@@ -359,6 +405,13 @@ void launch_force_items(int model, int precision, const ForceDesc* descs, const 
 
 void launch_energy_finalize(const double* epart, int64_t n, double* energy, hipStream_t s) {
     energy_finalize<<<1, 256, 0, s>>>(epart, n, energy);
+    SHELL_HIP(hipGetLastError());
+}
+
+void launch_gather_displacements(const double* src, const int32_t* perm, const double* X, double* dst, int64_t nv,
+                                 hipStream_t s) {
+    if (!nv) return;
+    gather_displacements<<<(nv + 255) / 256, 256, 0, s>>>(src, perm, X, dst, nv);
     SHELL_HIP(hipGetLastError());
 }
 

@@ -85,11 +85,24 @@ HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tr
 // bisection into tiles of T vertices (Morton inside a tile); 2: Morton order of the rest positions.
 std::vector<int32_t> vertex_order(const double* X, int64_t nv, int mode, int T);
 
-// Tiled stencil streams are stored in blocks of 64 stencils (one wave): field f of list entry e sits at
-// ((e / 64) * nfields + f) * 64 + e % 64, so a wave reads each of its stencils' fields as one contiguous
-// run.  Every tile's list starts at a multiple of 64; the slots between a list's end and the next start
-// are padding that no kernel reads.
+// Tiled stencil streams are stored in blocks of 64 stencils (one wave).  A stream's fields are grouped in
+// chunks of 16 bytes (four 32-bit or two 64-bit fields): chunk c of list entry e sits at chunk index
+// ((e / 64) * nchunks + c) * 64 + e % 64, so each lane reads a chunk with one 16-byte load and a wave's
+// loads of one chunk are one contiguous 1 KB run.  Every tile's list starts at a multiple of 64; the
+// slots between a list's end and the next start are padding (vertex 0, zeros) that no kernel reads.
 constexpr int kStreamBlock = 64;
+__host__ __device__ constexpr int stream_chunks(int nfields, int per_chunk) {
+    return (nfields + per_chunk - 1) / per_chunk;
+}
+// Fields per stencil.  Mixed precision: one 32-bit record of k vertex ids, r*k operator entries, r rest
+// curvatures, the 3r components of the rest curvature vectors C0 = B X^e and, for shells, the rest
+// differences that the normal needs (edge: X0 - X1, X2 - X1, X3 - X1; triangle: X1 - X0, X2 - X0).
+// FP64: the k ids in one stream and the r*k + r operator entries and rest curvatures in another.
+__host__ __device__ constexpr int rec32_rest_diffs(int k, bool shell) { return shell ? (k == 4 ? 9 : 6) : 0; }
+__host__ __device__ constexpr int rec32_fields(int k, int r, bool shell) {
+    return k + r * k + r + 3 * r + rec32_rest_diffs(k, shell);
+}
+__host__ __device__ constexpr int rec64_fields(int k, int r) { return r * k + r; }
 
 struct Tiling {
     int T = 1024;                 // vertices per tile
@@ -128,17 +141,12 @@ SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t n
 // Per-mesh arguments of the force kernel.  Kernels take an array of descriptors and a list of work
 // items (mesh, unit): one launch covers any set of meshes, a single mesh being a set of one.
 struct ForceDesc {
-    const double* x;
+    const double* x;       // FP64: positions [nv][3]; mixed: displacements from the rest shape [nv][4]
     void* f;               // double or float [nv][3]
     double* epart;         // per-tile energy, or null
     const int64_t* boff;   // [2 tiles]: start and end of each tile's stencil list
-    const int32_t* tidx;
-    const void* tB;        // double or float operator stream
-    const void* tk0;
-    // mixed precision only: rest positions and the float stream of rest curvature vectors C0 = B X^e
-    // (r x 3 per stencil); the float kernels form C = C0 + B (x^e - X^e)
-    const double* X0;
-    const float* tC0;
+    const int32_t* tidx;   // FP64: vertex id stream
+    const void* trec;      // mixed: the 32-bit record stream; FP64: the operator and rest-curvature stream
     int64_t nst, nv;
     int32_t T, model;
     double kb, nu;
@@ -154,6 +162,8 @@ struct PcgState {
 
 struct SolveDesc {
     double *x, *xhat, *xt, *v, *g, *y, *r;
+    double* u4;                     // mixed precision only: x - X padded to [nv][4], the force kernel's input
+    const double* X;                // rest positions
     void *f, *p0, *p1, *q, *dinv;   // float in mixed precision; p0/p1 alternate as the search direction
     float* z;                       // mixed precision only: z = D^-1 r as float (null in FP64: recomputed)
     const double *mass, *kdiag;
@@ -203,12 +213,10 @@ struct shell_stencils_s {
     shell::DevArray<int32_t> flags;      // [ns]
     shell::DevArray<int64_t> boff;       // [2 nblocks] start, end
     shell::DevArray<int32_t> tsrc;       // [nst_pad]
-    shell::DevArray<int32_t> tidx;       // blocks of 64: [nst_pad / 64][k][64]
-    shell::DevArray<double> tB;          // blocks of 64: [nst_pad / 64][r*k][64]
-    shell::DevArray<double> tk0;         // blocks of 64: [nst_pad / 64][r][64]
-    shell::DevArray<float> tBf;          // mixed-precision copies
-    shell::DevArray<float> tk0f;
-    shell::DevArray<float> tC0f;         // mixed: rest curvature vectors [r][3] per stencil
+    // tiled streams, only those of the configured precision: [nst_pad / 64][chunks][64][fields per chunk]
+    shell::DevArray<int32_t> tidx;       // FP64: vertex ids
+    shell::DevArray<double> trec64;      // FP64: operator entries and rest curvatures
+    shell::DevArray<float> trec32;       // mixed: ids (bit patterns), operator, rest curvatures, C0
     // scratch for the caller-order entry point
     shell::DevArray<double> xin;         // [nv][3]
     shell::DevArray<double> fout;        // [nv][3] (float for mixed, sized in doubles)
@@ -247,6 +255,7 @@ struct shell_sim_s {
     shell::DevArray<uint8_t> pinned;
     shell::DevArray<double> p, p2, q;    // PCG work vectors (float in mixed; sized in doubles)
     shell::DevArray<float> z;            // mixed only: the preconditioned residual, read by the product
+    shell::DevArray<double> u4;          // mixed only: displacements from the rest shape, [nv][4]
     shell::DevArray<double> bins;        // PCG dot-product bins
     shell::DevArray<double> partials;    // reduction partials
     shell_batch_s* solo = nullptr;       // this simulation alone, as a batch of one
@@ -330,6 +339,9 @@ void launch_force_items(int model, int precision, const ForceDesc* descs, const 
                         int lds_T, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 void launch_energy_finalize(const double* epart, int64_t n, double* energy, hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
+// dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order padded displacements
+void launch_gather_displacements(const double* src, const int32_t* perm, const double* X, double* dst, int64_t nv,
+                                 hipStream_t s);
 void launch_scatter_rows(const void* src, const int32_t* perm, void* dst, int64_t nv, bool f32, hipStream_t s);
 // hessian.hip
 void launch_assemble(shell_hessian_s& h, hipStream_t s);

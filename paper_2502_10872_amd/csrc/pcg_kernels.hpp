@@ -631,6 +631,19 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(const SolveDesc* __restrict
     if (cur >= 0 && !done) flush_partials<6>(bin_set(descs[cur], t, kSetRz), cur_unit, acc, sh);
 }
 
+// u = x - X, padded to four doubles per vertex (mixed precision: the force kernels' input, gathered with
+// two aligned 16-byte loads per vertex)
+__global__ __launch_bounds__(kBlk) void k_displacements(const SolveDesc* __restrict__ descs,
+                                                        const WorkItem* __restrict__ items, long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    for (int c = 0; c < 3; ++c) d.u4[4 * i + c] = d.x[3 * i + c] - d.X[3 * i + c];
+    d.u4[4 * i + 3] = 0.0;
+}
+
 // x += y (Newton update)
 __global__ __launch_bounds__(kBlk) void k_newton_update(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
                                 long nitems) {

@@ -206,27 +206,21 @@ __global__ void precompute_tri(const double* __restrict__ X, const int32_t* __re
 
 __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_t* __restrict__ idx,
                           const double* __restrict__ B, const double* __restrict__ k0, const double* __restrict__ X,
-                          long ns, int k, int r, int32_t* __restrict__ tidx, double* __restrict__ tB,
-                          double* __restrict__ tk0, float* __restrict__ tBf, float* __restrict__ tk0f,
-                          float* __restrict__ tC0f) {
+                          long ns, int k, int r, bool shell, int32_t* __restrict__ tidx,
+                          double* __restrict__ trec64, float* __restrict__ trec32) {
     long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (e >= nt) return;
     const long s = src[e];  // -1: alignment padding, filled with vertex 0 and zeros (never read)
     const long blk = e / kStreamBlock, lane = e % kStreamBlock;
-    auto at = [&](int nf, int f) { return (blk * nf + f) * kStreamBlock + lane; };
-    for (int j = 0; j < k; ++j) tidx[at(k, j)] = s < 0 ? 0 : idx[j * ns + s];
-    for (int q = 0; q < r * k; ++q) {
-        const double v = s < 0 ? 0.0 : B[q * ns + s];
-        if (tB) tB[at(r * k, q)] = v;
-        if (tBf) tBf[at(r * k, q)] = float(v);
-    }
-    for (int q = 0; q < r; ++q) {
-        const double v = s < 0 ? 0.0 : k0[q * ns + s];
-        if (tk0) tk0[at(r, q)] = v;
-        if (tk0f) tk0f[at(r, q)] = float(v);
-    }
-    if (tC0f) {
-        // rest curvature vectors C0_i = sum_j B_ij (X_j - X_1) in float64 (rows of B sum to zero)
+    if (trec32) {
+        // mixed: ids, operator, rest curvatures, the rest curvature vectors C0_i = sum_j B_ij (X_j - X_1)
+        // (float64 sums; the rows of B sum to zero) and (shells) rest differences in one 32-bit record
+        const int nf = rec32_fields(k, r, shell), nch = stream_chunks(nf, 4);
+        float* base = trec32 + (blk * nch * kStreamBlock + lane) * 4;
+        auto put = [&](int f, float v) { base[(f / 4) * kStreamBlock * 4 + f % 4] = v; };
+        for (int j = 0; j < k; ++j) put(j, __int_as_float(s < 0 ? 0 : idx[j * ns + s]));
+        for (int q = 0; q < r * k; ++q) put(k + q, s < 0 ? 0.0f : float(B[q * ns + s]));
+        for (int q = 0; q < r; ++q) put(k + r * k + q, s < 0 ? 0.0f : float(k0[q * ns + s]));
         for (int i = 0; i < r; ++i) {
             double c[3] = {0.0, 0.0, 0.0};
             if (s >= 0) {
@@ -237,8 +231,31 @@ __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_
                     for (int a = 0; a < 3; ++a) c[a] += b * (X[3 * v + a] - X[3 * o + a]);
                 }
             }
-            for (int a = 0; a < 3; ++a) tC0f[at(3 * r, 3 * i + a)] = float(c[a]);
+            for (int a = 0; a < 3; ++a) put(k + r * k + r + 3 * i + a, float(c[a]));
         }
+        if (shell) {
+            // edge: X0 - X1, X2 - X1, X3 - X1; triangle: X1 - X0, X2 - X0 (the differences the normal uses)
+            const int f0 = k + r * k + r + 3 * r;
+            const int o = k == 4 ? 1 : 0;
+            const int js[3] = {k == 4 ? 0 : 1, 2, 3};
+            const int nd = k == 4 ? 3 : 2;
+            for (int q = 0; q < nd; ++q)
+                for (int a = 0; a < 3; ++a) {
+                    const double v = s < 0 ? 0.0 : X[3L * idx[js[q] * ns + s] + a] - X[3L * idx[o * ns + s] + a];
+                    put(f0 + 3 * q + a, float(v));
+                }
+        }
+        for (int f = nf; f < 4 * nch; ++f) put(f, 0.0f);
+    } else {
+        const int nchi = stream_chunks(k, 4), nchv = stream_chunks(rec64_fields(k, r), 2);
+        int32_t* bi = tidx + (blk * nchi * kStreamBlock + lane) * 4;
+        double* bv = trec64 + (blk * nchv * kStreamBlock + lane) * 2;
+        auto put_i = [&](int f, int32_t v) { bi[(f / 4) * kStreamBlock * 4 + f % 4] = v; };
+        auto put_v = [&](int f, double v) { bv[(f / 2) * kStreamBlock * 2 + f % 2] = v; };
+        for (int j = 0; j < 4 * nchi; ++j) put_i(j, (s < 0 || j >= k) ? 0 : idx[j * ns + s]);
+        for (int q = 0; q < r * k; ++q) put_v(q, s < 0 ? 0.0 : B[q * ns + s]);
+        for (int q = 0; q < r; ++q) put_v(r * k + q, s < 0 ? 0.0 : k0[q * ns + s]);
+        for (int f = rec64_fields(k, r); f < 2 * nchv; ++f) put_v(f, 0.0);
     }
 }
 
@@ -272,8 +289,8 @@ void launch_tile_copy(shell_stencils_s& st, hipStream_t s) {
     if (nt == 0) return;
     int blk = 256;
     tile_copy<<<(nt + blk - 1) / blk, blk, 0, s>>>(st.tsrc.p, nt, st.idx.p, st.B.p, st.k0.p, st.X.p, st.ns, st.k,
-                                                   st.r, st.tidx.p, st.tB.p, st.tk0.p, st.tBf.p, st.tk0f.p,
-                                                   st.tC0f.p);
+                                                   st.r, model_is_shell(st.model), st.tidx.p, st.trec64.p,
+                                                   st.trec32.p);
     SHELL_HIP(hipGetLastError());
 }
 

@@ -186,6 +186,11 @@ long pcg_iterations(shell_batch_s& b, const Launch& L, long t, int count, hipStr
 }
 
 void forces(const Launch& L, hipStream_t s, StepProfiler* prof = nullptr) {
+    // mixed precision: the force kernels read the displacements from the rest shape
+    if (L.precision == SHELL_PREC_MIXED && L.nrows) {
+        k_displacements<<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        SHELL_HIP(hipGetLastError());
+    }
     timed_launch(prof, prof && prof->every > 0, SHELL_PHASE_FORCES, s, [&](hipEvent_t e0, hipEvent_t e1) {
         // the first model's kernel starts the interval, the last one's ends it
         int first = -1, last = -1;
@@ -277,6 +282,8 @@ void read_states(shell_batch_s& b, hipStream_t s) {
 SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
     SolveDesc d{};
     d.x = sim.x.p;
+    d.u4 = sim.u4.p;  // null in FP64
+    d.X = sim.st->X.p;
     d.xhat = sim.xhat.p;
     d.xt = sim.xt.p;
     d.v = sim.v.p;
@@ -312,15 +319,12 @@ ForceDesc force_desc(shell_sim_s& sim) {
     const shell_stencils_s& st = *sim.st;
     const bool f32 = st.precision == SHELL_PREC_MIXED;
     ForceDesc d{};
-    d.x = sim.x.p;
+    d.x = f32 ? sim.u4.p : sim.x.p;
     d.f = sim.f.p;
     d.epart = nullptr;
     d.boff = st.boff.p;
     d.tidx = st.tidx.p;
-    d.tB = f32 ? static_cast<const void*>(st.tBf.p) : static_cast<const void*>(st.tB.p);
-    d.tk0 = f32 ? static_cast<const void*>(st.tk0f.p) : static_cast<const void*>(st.tk0.p);
-    d.X0 = st.X.p;
-    d.tC0 = st.tC0f.p;
+    d.trec = f32 ? static_cast<const void*>(st.trec32.p) : static_cast<const void*>(st.trec64.p);
     d.nst = st.nst_pad;
     d.nv = st.nv;
     d.T = st.T;
@@ -563,7 +567,10 @@ void sim_alloc(shell_sim_s& sim) {
     for (auto* a : {&sim.x, &sim.v, &sim.xt, &sim.xhat, &sim.g, &sim.y, &sim.r, &sim.f, &sim.p, &sim.p2, &sim.q})
         a->alloc(size_t(std::max(n3, 1L)));
     sim.bins.alloc(size_t(2 * 2 * kBinQ * kBins));
-    if (sim.st->precision == SHELL_PREC_MIXED) sim.z.alloc(size_t(std::max(n3, 1L)));
+    if (sim.st->precision == SHELL_PREC_MIXED) {
+        sim.z.alloc(size_t(std::max(n3, 1L)));
+        sim.u4.alloc(size_t(std::max(4 * nv, 1L)));
+    }
     sim.mass.alloc(size_t(std::max(nv, 1L)));
     sim.dinv.alloc(size_t(std::max(nv, 1L)));
     sim.pinned.alloc(size_t(std::max(nv, 1L)));
