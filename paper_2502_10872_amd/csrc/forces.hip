@@ -113,8 +113,9 @@ __device__ __forceinline__ void tri_stencil(const V3<R> (&d)[6], const V3<R> (&C
 }
 
 // 16-byte stream chunks (clang vector types, which load through address-space pointers in one
-// instruction).  The FP64 streams are read with non-temporal loads, the float record with plain loads
-// (each the faster form for its precision).
+// instruction).  The streams are read with non-temporal loads, which keep them from displacing the
+// gathered positions or displacements from L2 (measured 2-5% faster than plain loads for the float
+// record).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -179,7 +180,7 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
             float f[4 * NCH32];
 #pragma unroll
             for (int c = 0; c < NCH32; ++c) {
-                const f32x4 v = rec[c * kStreamBlock];
+                const f32x4 v = __builtin_nontemporal_load(rec + c * kStreamBlock);
                 f[4 * c] = v.x;
                 f[4 * c + 1] = v.y;
                 f[4 * c + 2] = v.z;
