@@ -270,7 +270,8 @@ void shell_destroy_batch(shell_batch_t batch);
  * position and velocity are not modified; the solver's work vectors are.  Synchronises `stream`.
  */
 typedef struct {
-    double force_ms;      /* bending force kernel over all stencils (internal vertex order) */
+    double force_ms;      /* bending force kernel over all stencils (internal vertex order; mixed: without
+                             the pass that writes the displacements from the rest shape) */
     double spmv_ms;       /* PCG direction update p = D^-1 r + beta p and product q = (M + dt^2 K_s) p */
     double update_ms;     /* PCG y/r update with its dot products */
     double direction_ms;  /* always 0: the direction update is part of the product kernel */
