@@ -161,7 +161,8 @@ struct PcgState {
 };
 
 struct SolveDesc {
-    double *x, *xhat, *xt, *v, *g, *y, *r;
+    double *x, *xhat, *xt, *v, *g, *r;
+    void* y;                        // the Newton increment the PCG builds (float in mixed precision)
     double* u4;                     // mixed precision only: x - X padded to [nv][4], the force kernel's input
     const double* X;                // rest positions
     void *f, *p0, *p1, *q, *dinv;   // float in mixed precision; p0/p1 alternate as the search direction

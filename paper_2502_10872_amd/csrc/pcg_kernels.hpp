@@ -162,13 +162,13 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(const SolveDesc* __restrict__
 #pragma unroll
         for (int c = 0; c < 3; ++c) gi[c] = g[3 * i + c];
         gbl<double>* r = G(d.r);
-        gbl<double>* y = G(d.y);
+        gbl<VR>* y = G(static_cast<VR*>(d.y));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double ri = -gi[c];
             const VR zi = di * VR(ri);
             r[3 * i + c] = ri;
-            y[3 * i + c] = 0.0;
+            y[3 * i + c] = VR(0);
             if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zi;
             acc[c] = ri * double(zi);
             acc[3 + c] = ri * ri;
@@ -564,7 +564,9 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
 // it reads the state entering the iteration and the p.q bins once (alpha = r.z / p.q per active
 // column; row group 0's work-group clears the p.q bins of the next product), then advances y += alpha
 // p, r -= alpha q on its rows and adds their r.z (z = D^-1 r; stored in mixed precision) and r.r into
-// the bins.
+// the bins.  In mixed precision the increment y is stored in float (the update is formed in float64):
+// it feeds nothing inside the solve, and the Newton loop recomputes the residual of x + y in float64,
+// which corrects its rounding at the next iteration; r stays float64.
 template <typename VR>
 __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem& wi, long t, const double (&al)[3],
                                              double (&acc)[6]) {
@@ -572,7 +574,7 @@ __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem&
     if (i >= d.nv) return;
     const gbl<const VR>* p = G(static_cast<const VR*>((t & 1) ? d.p1 : d.p0));
     const gbl<const VR>* q = G(static_cast<const VR*>(d.q));
-    gbl<double>* y = G(d.y);
+    gbl<VR>* y = G(static_cast<VR*>(d.y));
     gbl<double>* r = G(d.r);
     const VR di = G(static_cast<const VR*>(d.dinv))[i];
     VR pv[3], qv[3];
@@ -581,7 +583,7 @@ __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem&
     for (int c = 0; c < 3; ++c) {
         pv[c] = p[3 * i + c];
         qv[c] = q[3 * i + c];
-        yv[c] = y[3 * i + c];
+        yv[c] = double(y[3 * i + c]);
         rv[c] = r[3 * i + c];
     }
     VR zv[3];
@@ -595,7 +597,7 @@ __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem&
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        y[3 * i + c] = yv[c];
+        y[3 * i + c] = VR(yv[c]);
         r[3 * i + c] = rv[c];
         if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zv[c];
     }
@@ -645,6 +647,7 @@ __global__ __launch_bounds__(kBlk) void k_displacements(const SolveDesc* __restr
 }
 
 // x += y (Newton update)
+template <typename VR>
 __global__ __launch_bounds__(kBlk) void k_newton_update(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
                                 long nitems) {
     WorkItem wi;
@@ -652,7 +655,8 @@ __global__ __launch_bounds__(kBlk) void k_newton_update(const SolveDesc* __restr
     const SolveDesc& d = descs[wi.mesh];
     long i = long(wi.unit) * kBlk + threadIdx.x;
     if (i >= d.nv) return;
-    for (int c = 0; c < 3; ++c) d.x[3 * i + c] += d.y[3 * i + c];
+    const VR* y = static_cast<const VR*>(d.y);
+    for (int c = 0; c < 3; ++c) d.x[3 * i + c] += double(y[3 * i + c]);
 }
 
 __global__ __launch_bounds__(kBlk) void k_velocity(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {

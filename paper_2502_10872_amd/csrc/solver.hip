@@ -471,7 +471,7 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
             st.stats.newton_iters++;
             next.push_back(m);
         }
-        k_newton_update<<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_newton_update<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
         SHELL_HIP(hipGetLastError());
         iterating = next;
     }

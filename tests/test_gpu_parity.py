@@ -138,6 +138,29 @@ def test_mixed_forces_of_a_small_smooth_deformation(model):
         S.shell_destroy_stencils(st)
 
 
+@pytest.mark.parametrize("model", ["ES", "FS", "SS"])
+def test_mixed_shell_forces_vanish_at_rest(model):
+    """At the rest shape the float shell kernels' bending strain n.C - kappa0 (C = C0 + B u^e with u = 0)
+    cancels to the rounding of the float C0 and kappa0: the rest force stays below 1e-3 of the force of a
+    smooth deformation of amplitude side/10^4 (observed 3e-5 to 8e-5)."""
+    mesh = mesh_for(model)
+    X = mesh.X
+    side = float(X[:, 0].max() - X[:, 0].min())
+    k = 2.0 * np.pi / side
+    u = np.stack([np.sin(k * X[:, 0]) * np.cos(k * X[:, 1]), np.cos(k * X[:, 0]) * np.sin(k * X[:, 1]),
+                  np.sin(k * X[:, 0]) * np.sin(k * X[:, 1])], axis=1)
+    st = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, precision=S.SHELL_PREC_MIXED, block_vertices=256)
+    try:
+        f0, e0 = gpu_forces(st, X, f32=True)
+        f1, e1 = gpu_forces(st, X + 1e-4 * side * u, f32=True)
+        ratio = np.linalg.norm(f0) / np.linalg.norm(f1)
+        print(f"{model} mixed rest force / force of a side/1e4 deformation: {ratio:.2e}")
+        assert ratio <= 1e-3
+        assert abs(e0) <= 1e-4 * abs(e1)
+    finally:
+        S.shell_destroy_stencils(st)
+
+
 @pytest.mark.parametrize("model,flags", [(m, 0) for m in I.MODELS] + [("SS", 1), ("EP", 1)])
 def test_hessian_and_apply_match_oracle(model, flags):
     """flags = 1: the product without LDS staging (32-bit column ids, direct gathers)."""
