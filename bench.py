@@ -35,7 +35,7 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
     spmv:   (the product kernel, which also forms the new direction p = z + beta p_old) every nonzero's
             value and 16-bit local column id, each row group's distinct-column list, slice widths and
             offsets, and per vertex the direction's inputs (FP64: r and D^-1; mixed: the stored float z)
-            and p_old, mass and fixed flag read, p and q written.
+            and p_old, the mass (-1 on fixed rows, in the vector precision) read, p and q written.
     update: per vertex p, q, y, r, D^-1 read, y and r written (mixed: z written too; y is float in mixed
             precision, r float64 in both)."""
     nv, ns, k, r = info["nv"], info["ns"], info["k"], info["r"]
@@ -49,7 +49,7 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
     idx = 2 if hinfo["staged"] else 4
     direction_in = 3 * real if mixed else 24 + real
     spmv = (hinfo["nnz"] * (real + idx) + 4 * (hinfo["group_cols"] + ngroups + 1) + 12 * hinfo["nslices"]
-            + nv * (direction_in + 3 * real + 8 + 1 + 3 * real + 3 * real))
+            + nv * (direction_in + 3 * real + real + 3 * real + 3 * real))
     update = nv * (3 * real + 3 * real + 3 * real + 24 + real + 3 * real + 24 + (3 * real if mixed else 0))
     return dict(force=force, spmv=spmv, update=update, force_per_stencil=per_stencil)
 

@@ -169,6 +169,7 @@ struct SolveDesc {
     float* z;                       // mixed precision only: z = D^-1 r as float (null in FP64: recomputed)
     const double *mass, *kdiag;
     const uint8_t* pinned;
+    void* mq;                       // the product's mass, in the vector precision; -1 on fixed rows
     const int32_t* scol;
     const void* val;                // SELL values, float in mixed precision
     const int64_t* sptr;
@@ -253,6 +254,7 @@ struct shell_sim_s {
     shell::DevArray<double> x, v, xt, xhat, g, mass, y, r;
     shell::DevArray<double> f;           // float64 forces (or float32 in mixed, sized in doubles)
     shell::DevArray<double> dinv;        // [nv] (float in mixed)
+    shell::DevArray<double> mq;          // [nv] mass for the product, -1 on fixed rows (float in mixed)
     shell::DevArray<uint8_t> pinned;
     shell::DevArray<double> p, p2, q;    // PCG work vectors (float in mixed; sized in doubles)
     shell::DevArray<float> z;            // mixed only: the preconditioned residual, read by the product

@@ -104,7 +104,10 @@ __global__ __launch_bounds__(kBlk) void k_dinv(const SolveDesc* __restrict__ des
     const SolveDesc& d = descs[wi.mesh];
     long i = long(wi.unit) * kBlk + threadIdx.x;
     if (i >= d.nv) return;
-    static_cast<VR*>(d.dinv)[i] = d.pinned[i] ? VR(0) : VR(1.0 / (d.mass[i] + d.dt2 * d.kdiag[i]));
+    const bool pin = d.pinned[i];
+    static_cast<VR*>(d.dinv)[i] = pin ? VR(0) : VR(1.0 / (d.mass[i] + d.dt2 * d.kdiag[i]));
+    // the product reads one value per row for both the mass and the fixed flag
+    static_cast<VR*>(d.mq)[i] = pin ? VR(-1) : VR(d.mass[i]);
 }
 
 // g = M (x - x_hat) - dt^2 f, fixed rows zero; partial |g|^2
@@ -368,8 +371,9 @@ __device__ __forceinline__ void product_direct(const SolveDesc& d, const WorkIte
                                                gbl<VR>* pnew, double (&acc)[3]) {
     const long i = long(wi.unit) * kBlk + threadIdx.x;
     if (i >= d.nv) return;
-    const MR m = MR(G(d.mass)[i]);
-    const bool pin = G(d.pinned)[i];
+    const VR mq = G(static_cast<const VR*>(d.mq))[i];
+    const MR m = MR(mq);
+    const bool pin = mq < VR(0);
     VR pi[3];
     direction<VR>(in, i, pi);
     MR ax, ay, az;
@@ -412,8 +416,9 @@ __device__ __forceinline__ void product_staged(const SolveDesc& d, const WorkIte
     bool pin = true;
     DirLoad<VR> own_op;
     if (own) {
-        m = MR(G(d.mass)[i]);
-        pin = G(d.pinned)[i];
+        const VR mq = G(static_cast<const VR*>(d.mq))[i];
+        m = MR(mq);
+        pin = mq < VR(0);
         own_op.load(in, i);
     }
     // staged columns: two per pass so that each lane has two sets of gathers in flight (a lane past

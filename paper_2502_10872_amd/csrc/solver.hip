@@ -295,6 +295,7 @@ SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
     d.p1 = sim.p2.p;
     d.q = sim.q.p;
     d.dinv = sim.dinv.p;
+    d.mq = sim.mq.p;
     d.z = sim.z.p;  // null in FP64
     d.mass = sim.mass.p;
     d.kdiag = sim.h->kdiag.p;
@@ -575,6 +576,7 @@ void sim_alloc(shell_sim_s& sim) {
     }
     sim.mass.alloc(size_t(std::max(nv, 1L)));
     sim.dinv.alloc(size_t(std::max(nv, 1L)));
+    sim.mq.alloc(size_t(std::max(nv, 1L)));
     sim.pinned.alloc(size_t(std::max(nv, 1L)));
     sim.partials.alloc(size_t(kMaxPart * std::max(blocks(nv), 1L) + kMaxPart));
 }
