@@ -91,10 +91,22 @@ struct Launch {
     size_t lds_spmv;  // bytes of staged p entries per row group (largest over the meshes)
     int per;          // row groups per work-group of the PCG kernels
     long pcg_grid;    // their grid
+    int per_u;        // row groups per work-group of the update kernel
+    long upd_grid;    // its grid
 };
 
 #ifndef SHELL_PCG_WORKGROUPS
 #define SHELL_PCG_WORKGROUPS 512  // work-groups of a PCG kernel: two of 512 threads resident per CU
+#endif
+// The update kernel's work-groups take per * MERGE / SPLIT row groups each.  Its work per row is short,
+// so its fixed cost per work-group (reading the bins and the state, adding its partial sums) weighs
+// more: on a 1M-vertex mesh twice the row groups per work-group (one work-group per CU) measured 1%
+// faster, half as many 5% slower and a quarter 29% slower.
+#ifndef SHELL_UPDATE_SPLIT
+#define SHELL_UPDATE_SPLIT 1
+#endif
+#ifndef SHELL_UPDATE_MERGE
+#define SHELL_UPDATE_MERGE 2
 #endif
 
 // Sampled timing: `launch(start, stop)` launches its kernel(s) with hipExtLaunchKernelGGL, which writes
@@ -119,13 +131,13 @@ long pcg_chunk(const Launch& L, long t, int count, hipStream_t s, StepProfiler* 
     for (int it = 0; it < count; ++it, ++t) {
         const bool smp = prof && prof->sample_iteration();
         if (!smp) {  // plain launches (also the form recorded into graphs)
-            k_pcg_update<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, t, L.per);
+            k_pcg_update<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, t, L.per_u);
             k_pcg_spmv<VR, MR><<<grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows, t + 1, L.per);
             continue;
         }
         timed_launch(prof, true, SHELL_PHASE_UPDATE, s, [&](hipEvent_t e0, hipEvent_t e1) {
-            hipExtLaunchKernelGGL(k_pcg_update<VR>, dim3(unsigned(grid)), dim3(kBlk), 0, s, e0, e1, 0, L.sdesc, L.rows,
-                                  L.nrows, t, L.per);
+            hipExtLaunchKernelGGL(k_pcg_update<VR>, dim3(unsigned(L.upd_grid)), dim3(kBlk), 0, s, e0, e1, 0, L.sdesc,
+                                  L.rows, L.nrows, t, L.per_u);
         });
         timed_launch(prof, true, SHELL_PHASE_PRODUCT, s, [&](hipEvent_t e0, hipEvent_t e1) {
             hipExtLaunchKernelGGL(k_pcg_spmv<VR, MR>, dim3(unsigned(grid)), dim3(kBlk), uint32_t(L.lds_spmv), s, e0,
@@ -265,6 +277,8 @@ Launch upload(shell_batch_s& b, const ItemBuilder& ib, hipStream_t s, int pcg_wo
     L.lds_spmv = b.lds_spmv;
     L.per = int(std::max<long>(1, (L.nrows + pcg_workgroups - 1) / pcg_workgroups));
     L.pcg_grid = xcd_grid((L.nrows + L.per - 1) / L.per);
+    L.per_u = std::max(1, L.per * SHELL_UPDATE_MERGE / SHELL_UPDATE_SPLIT);
+    L.upd_grid = xcd_grid((L.nrows + L.per_u - 1) / L.per_u);
     return L;
 }
 
@@ -530,7 +544,7 @@ void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out,
         k_fin_residual<<<1, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
         k_pcg_init<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
         k_pcg_spmv<VR, MR><<<L.pcg_grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows, 0, L.per);
-        k_pcg_update<VR><<<L.pcg_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 0, L.per);
+        k_pcg_update<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 0, L.per_u);
         SHELL_HIP(hipGetLastError());
     };
     auto timed = [&](auto&& launch) {
@@ -554,7 +568,7 @@ void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out,
         k_pcg_spmv<VR, MR><<<L.pcg_grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows, 1, L.per);
     });
     init();
-    out.update_ms = timed([&] { k_pcg_update<VR><<<L.pcg_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 0, L.per); });
+    out.update_ms = timed([&] { k_pcg_update<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 0, L.per_u); });
     init();
     out.direction_ms = 0.0;  // the direction update is part of the product kernel
     SHELL_HIP(hipGetLastError());
