@@ -297,10 +297,11 @@ struct GraphCache {
         const void* rows;
         long nrows, grid;
         size_t lds;
-        int per, count, parity, precision;
+        int per, per_u, count, parity, precision;
         bool operator==(const Key& o) const {
             return sdesc == o.sdesc && rows == o.rows && nrows == o.nrows && grid == o.grid && lds == o.lds &&
-                   per == o.per && count == o.count && parity == o.parity && precision == o.precision;
+                   per == o.per && per_u == o.per_u && count == o.count && parity == o.parity &&
+                   precision == o.precision;
         }
     };
     std::vector<std::pair<Key, hipGraphExec_t>> entries;  // oldest first

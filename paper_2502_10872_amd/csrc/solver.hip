@@ -98,10 +98,12 @@ struct Launch {
 #ifndef SHELL_PCG_WORKGROUPS
 #define SHELL_PCG_WORKGROUPS 512  // work-groups of a PCG kernel: two of 512 threads resident per CU
 #endif
-// The update kernel's work-groups take per * MERGE / SPLIT row groups each.  Its work per row is short,
-// so its fixed cost per work-group (reading the bins and the state, adding its partial sums) weighs
-// more: on a 1M-vertex mesh twice the row groups per work-group (one work-group per CU) measured 1%
-// faster, half as many 5% slower and a quarter 29% slower.
+// The update kernel's work-groups take per * MERGE / SPLIT row groups each when the launch holds one mesh
+// (per otherwise).  Its work per row is short, so its fixed cost per work-group (reading the bins and
+// the state, adding its partial sums) weighs more: on a 1M-vertex mesh twice the row groups per
+// work-group (one work-group per CU) measured 1% faster, half as many 5% slower and a quarter 29%
+// slower.  With many meshes longer walks cross more meshes, each crossing a re-read of bins and state:
+// twice the groups made the 64-mesh batch's update 19% slower.
 #ifndef SHELL_UPDATE_SPLIT
 #define SHELL_UPDATE_SPLIT 1
 #endif
@@ -165,7 +167,7 @@ long pcg_iterations(shell_batch_s& b, const Launch& L, long t, int count, hipStr
         int c = kMinGraphChunk;
         while (2 * c <= count && 2 * c <= kMaxGraphChunk) c *= 2;
         if (c > count) return pcg_chunk<VR, MR>(L, t, count, s, nullptr);
-        const GraphCache::Key key{L.sdesc, L.rows, L.nrows, L.pcg_grid, L.lds_spmv, L.per, c, int(t & 1),
+        const GraphCache::Key key{L.sdesc, L.rows, L.nrows, L.pcg_grid, L.lds_spmv, L.per, L.per_u, c, int(t & 1),
                                   L.precision};
         hipGraphExec_t ex = nullptr;
         for (auto& e : gc.entries)
@@ -277,7 +279,7 @@ Launch upload(shell_batch_s& b, const ItemBuilder& ib, hipStream_t s, int pcg_wo
     L.lds_spmv = b.lds_spmv;
     L.per = int(std::max<long>(1, (L.nrows + pcg_workgroups - 1) / pcg_workgroups));
     L.pcg_grid = xcd_grid((L.nrows + L.per - 1) / L.per);
-    L.per_u = std::max(1, L.per * SHELL_UPDATE_MERGE / SHELL_UPDATE_SPLIT);
+    L.per_u = L.nmeshes == 1 ? std::max(1, L.per * SHELL_UPDATE_MERGE / SHELL_UPDATE_SPLIT) : L.per;
     L.upd_grid = xcd_grid((L.nrows + L.per_u - 1) / L.per_u);
     return L;
 }
