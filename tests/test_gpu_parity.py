@@ -469,11 +469,17 @@ def cap_problem():
     pb.close()
 
 
-def test_full_size_sphere_cap_forces_match_oracle(cap_problem):
+@pytest.fixture(scope="module")
+def cap_oracle(cap_problem):
+    mesh, _ = cap_problem
+    return oracle_stencils("SS", mesh)
+
+
+def test_full_size_sphere_cap_forces_match_oracle(cap_problem, cap_oracle):
     """1024 x 1024 smoothed-hinge shell cap (2,093,058 stencils): every vertex's force."""
     mesh, pb = cap_problem
     assert pb.info["ns"] == 2 * 1023 * 1023
-    ost = oracle_stencils("SS", mesh)
+    ost = cap_oracle
     x = mesh.X + 1e-4 * I.rng(21).standard_normal(mesh.X.shape)
     f_ref, e_ref = ost.forces(x)
     f, e = gpu_forces(pb.st, x)
@@ -501,6 +507,38 @@ def test_full_size_operator_properties(cap_problem):
     a = torch.sum(p2 * k1).item()
     b = torch.sum(p1 * k2).item()
     assert abs(a - b) <= 1e-11 * abs(a)
+
+
+@pytest.fixture(scope="module")
+def cap_oracle_newton(cap_problem, cap_oracle):
+    """The oracle's state after one Newton iteration from rest with 20 PCG iterations per coordinate."""
+    mesh, _ = cap_problem
+    osim = O.Sim(cap_oracle, MAT, mesh.pinned)
+    counts = np.full((1, 3), 20, np.int32)
+    osim.step(1 / 30, gravity=I.GRAVITY, max_newton=1, replay=counts)
+    return counts, osim.x.copy()
+
+
+@pytest.mark.parametrize("precision", [S.SHELL_PREC_FP64, S.SHELL_PREC_MIXED])
+def test_full_size_newton_iteration_matches_oracle(cap_problem, cap_oracle_newton, precision):
+    """The benchmark's configuration (1024 x 1024 SS cap, default tiles, PCG launch shape and captured
+    graphs): one Newton iteration from rest with 20 replayed PCG iterations per coordinate, every vertex
+    against the oracle.  FP64 to 1e-10 (observed 4e-14); mixed to 1e-5 (float matrix, forces and
+    increment; observed 1.2e-7)."""
+    mesh, pb64 = cap_problem
+    counts, x_ref = cap_oracle_newton
+    params, _keep = S.step_params(1 / 30, gravity=I.GRAVITY, max_newton=1, replay=counts)
+    if precision == S.SHELL_PREC_FP64:
+        S.shell_sim_set_state(pb64.sim, mesh.X, np.zeros_like(mesh.X), 0)
+        S.shell_step_implicit(pb64.sim, params)
+        x, _, _ = S.shell_sim_get_state(pb64.sim, mesh.nv)
+    else:
+        with S.Problem(mesh, MAT, precision=precision) as pb:
+            S.shell_step_implicit(pb.sim, params)
+            x, _, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+    err = rel(x - mesh.X, x_ref - mesh.X)
+    print(f"full-size Newton iteration, precision {precision}: displacement rel err {err:.2e}")
+    assert err <= (TOL64 if precision == S.SHELL_PREC_FP64 else 1e-5)
 
 
 # ------------------------------------------------------------------ multi-mesh batch
