@@ -55,26 +55,39 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_cap_1024_ss_hbm_traffic.md")
-# the device code of the measured kernels and the layout they read (host_mesh.cpp builds it)
+# the device code of the measured kernels, the layouts they read (host_mesh.cpp and precompute.hip build
+# them) and their launch shapes (solver.hip)
 TRAFFIC_SOURCES = ["paper_2502_10872_amd/csrc/spmv.hpp", "paper_2502_10872_amd/csrc/pcg_kernels.hpp",
                    "paper_2502_10872_amd/csrc/forces.hip", "paper_2502_10872_amd/csrc/host_mesh.cpp",
-                   "paper_2502_10872_amd/csrc/devmath.hpp"]
+                   "paper_2502_10872_amd/csrc/devmath.hpp", "paper_2502_10872_amd/csrc/precompute.hip",
+                   "paper_2502_10872_amd/csrc/solver.hip"]
+
+
+def sources_digest(files=TRAFFIC_SOURCES) -> str:
+    """sha256 prefix of the code of the measured kernels: the sources with comments and blank lines
+    removed, so that a change to a comment does not retire the counter summary while any change to the
+    code does."""
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for f in files:
+        text = open(os.path.join(ROOT, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines()]
+        h.update("\n".join(line for line in lines if line.strip()).encode())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(key: str):
-    """HBM bytes per launch from the committed counter summary, or None when the kernels' sources have
+    """HBM bytes per launch from the committed counter summary, or None when the kernels' code has
     changed since the counters were taken (or the summary is absent)."""
-    import hashlib
-
     try:
         text = open(TRAFFIC_SUMMARY).read()
     except OSError:
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line and not line.startswith("|"))
-    h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
-    if fields.get("sources_sha256", "").strip() != h.hexdigest()[:16] or key not in fields:
+    if fields.get("sources_sha256", "").strip() != sources_digest() or key not in fields:
         return None
     return float(fields[key])
 

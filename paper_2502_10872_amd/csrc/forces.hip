@@ -5,10 +5,11 @@
 // tile boundary appear in each tile they touch).  Each stencil's force on the tile's own vertices is
 // added into a float64 LDS accumulator; contributions to other tiles' vertices are left to those
 // tiles.  The tile is then written to HBM once: no global atomics, no zero-fill, one coalesced store
-// per vertex.  Stencil data is streamed in blocks of 64 stencils (each field of a wave's 64 stencils is
-// one contiguous run, so every load is coalesced and a wave touches one region of memory); a tile's
-// list stays in spatial order so the gathers of one wave touch few cache lines.  (float32 LDS atomics
-// contended badly on shared vertices; the float64 accumulator does not.)
+// per vertex.  Stencil data is streamed in blocks of 64 stencils, in 16-byte chunks of fields (a
+// wave's 64 loads of one chunk are one contiguous 1 KB run, so every load is coalesced and a wave
+// touches one region of memory); a tile's list stays in spatial order so the gathers of one wave touch
+// few cache lines.  (float32 LDS atomics contended badly on shared vertices; the float64 accumulator
+// does not.)
 //
 // Per stencil (operator B already scaled by the square root of its stiffness):
 //   C_i = sum_j B_ij (x_j - x_o)            curvature vectors, x_o the stencil origin (rows of B
@@ -19,13 +20,15 @@
 // with D = 1 (edge) or D_b / k_b-form [[1,nu,0],[nu,1,0],[0,0,(1-nu)/2]] * k_b (triangle), n the
 // unit normal of the central triangle (eq 15) or the bisector of the two hinge triangle normals
 // (edge; the line of eq 8), its gradient by the chain rule of App. B (eqs 67, 73).
-// Mixed precision: positions are gathered in float64 and differenced in float64; everything after
-// the difference is float32.  The curvature is formed relative to the rest shape, C = C0 + B (x^e - X^e)
-// with C0 = B X^e precomputed in float64, so float32 rounds the displacement differences (of the size
-// of the deformation) instead of the position differences (of the size of an edge): the net force of
-// a smooth deformation is a cancelling sum over stencils, and with world differences its relative
-// error grew with the mesh resolution and with the inverse of the deformation (2e-3 at 1024x1024 for an
-// amplitude of side/100).
+// Mixed precision: the kernels gather the float64 displacements u = x - X from the rest shape and
+// difference them in float64; everything after the difference is float32.  The curvature is formed
+// relative to the rest shape, C = C0 + B (u^e), with C0 = B X^e precomputed in float64, so float32
+// rounds the displacement differences (of the size of the deformation) instead of the position
+// differences (of the size of an edge): the net force of a smooth deformation is a cancelling sum over
+// stencils, and with position differences its relative error grew with the mesh resolution and with
+// the inverse of the deformation (2e-3 at 1024x1024 for an amplitude of side/100).  The shell normals
+// use the position differences of their vertices, rebuilt as the streamed rest differences plus the
+// displacement differences.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
