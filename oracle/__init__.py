@@ -18,6 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "shell_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+WORLD_FRAME = 1  # orc_build flag: the world-frame (App. D) edge operator
 
 MODELS = ("EP", "ES", "FP", "FS", "SP", "SS")
 ERRORS = {-1: "invalid argument", -2: "non-manifold mesh", -3: "inconsistent orientation",
@@ -51,7 +52,7 @@ def lib():
         d = ctypes.c_double
         i = ctypes.c_int
         L.orc_topology.argtypes = [i, i64, i64, P, P, P]
-        L.orc_build.argtypes = [i, i64, P, i64, P, d, d, d, P, P, P]
+        L.orc_build.argtypes = [i, i64, P, i64, P, d, d, d, i, P, P, P]
         L.orc_forces.argtypes = [i, i64, P, i64, P, P, P, P, P, P]
         L.orc_hessian.argtypes = [i, i64, i64, P, P, P, P, P, P, P]
         L.orc_mass.argtypes = [i64, P, i64, P, d, d, P]
@@ -84,9 +85,10 @@ def curv_size(model) -> int:
 
 
 class Stencils:
-    """Rest-precomputed stencils of one mesh for one model."""
+    """Rest-precomputed stencils of one mesh for one model.  world_frame (edge models): the quadratic
+    thin plate/shell operator of App. D (eq 79) instead of the projected one."""
 
-    def __init__(self, model, X, tris, young, poisson, thickness):
+    def __init__(self, model, X, tris, young, poisson, thickness, world_frame=False):
         self.model = model_id(model)
         self.X = np.ascontiguousarray(X, dtype=np.float64)
         self.tris = np.ascontiguousarray(tris, dtype=np.int32)
@@ -103,8 +105,9 @@ class Stencils:
         self.B = np.zeros((self.ns, self.r, self.k))
         self.kappa0 = np.zeros((self.ns, self.r))
         self.D = np.zeros((self.ns, self.r, self.r))
+        self.world_frame = bool(world_frame)
         _check(lib().orc_build(self.model, self.nv, _p(self.X), self.ns, _p(self.idx), young, poisson, thickness,
-                               _p(self.B), _p(self.kappa0), _p(self.D)), "build")
+                               WORLD_FRAME if world_frame else 0, _p(self.B), _p(self.kappa0), _p(self.D)), "build")
 
     def forces(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

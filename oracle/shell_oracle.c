@@ -176,8 +176,10 @@ int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t
 
 /* ------------------------------------------------------ rest precompute */
 
-/* Edge-based hinge (Sec. 4.3): L_m = 2 L_theta/(h1+h4) on the projected stencil. */
-static int build_edge(int shell, const double* X1, const double* X2, const double* X3, const double* X4,
+/* Edge-based hinge (Sec. 4.3): L_m = 2 L_theta/(h1+h4) on the projected stencil.  world != 0: the
+   quadratic thin plate/shell variant (App. D, eq 79), whose operator L_n takes the heights and feet of
+   the rest stencil as it lies in the world frame, without the projection. */
+static int build_edge(int shell, int world, const double* X1, const double* X2, const double* X3, const double* X4,
                       double kb, double* L, double* kappa0, double* D) {
     double na[3], nb[3], n0[3];
     double Aa = 0.5 * tri_normal(X1, X2, X3, na);
@@ -193,7 +195,7 @@ static int build_edge(int shell, const double* X1, const double* X2, const doubl
     for (int j = 0; j < 4; ++j) {
         double d[3];
         sub3(Xs[j], X2, d);
-        double w = dot3(n0, d);
+        double w = world ? 0.0 : dot3(n0, d);
         for (int c = 0; c < 3; ++c) Xc[j][c] = Xs[j][c] - w * n0[c];
     }
     double e[3], d1[3], d4[3];
@@ -405,8 +407,9 @@ static int build_tri(int model, const double* Xs[6], const double Db[3][3], doub
 }
 
 int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t* idx,
-              double young, double poisson, double thickness, double* B, double* kappa0, double* D) {
+              double young, double poisson, double thickness, int flags, double* B, double* kappa0, double* D) {
     if (model < 0 || model > 5 || !X || !idx || !B || !kappa0 || !D) return ORC_E_ARG;
+    if ((flags & ~ORC_WORLD_FRAME) || ((flags & ORC_WORLD_FRAME) && !is_edge(model))) return ORC_E_ARG;
     double kb = young * thickness * thickness * thickness / (12.0 * (1.0 - poisson * poisson));
     double Db[3][3] = {{kb, kb * poisson, 0}, {kb * poisson, kb, 0}, {0, 0, kb * (1.0 - poisson) / 2.0}};
     int k = orc_stencil_size(model), r = orc_curv_size(model);
@@ -416,8 +419,8 @@ int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t*
             if (id[j] >= nv || (id[j] < 0 && (is_edge(model) || j < 3))) return ORC_E_ARG;
         int rc;
         if (is_edge(model)) {
-            rc = build_edge(is_shell(model), X + 3 * id[0], X + 3 * id[1], X + 3 * id[2], X + 3 * id[3], kb,
-                            B + 4 * s, kappa0 + s, D + s);
+            rc = build_edge(is_shell(model), (flags & ORC_WORLD_FRAME) != 0, X + 3 * id[0], X + 3 * id[1],
+                            X + 3 * id[2], X + 3 * id[3], kb, B + 4 * s, kappa0 + s, D + s);
         } else {
             const double* Xs[6];
             for (int j = 0; j < 6; ++j) Xs[j] = id[j] >= 0 ? X + 3 * id[j] : NULL;

@@ -39,9 +39,12 @@ int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t
 
 /* Rest precompute: operator B [ns][r][k], rest curvature kappa0 [ns][r]
  * (zero for plates), material D [ns][r][r] (k_b*A_E for edges, A*D_b for
- * triangles).  Free-edge folds are applied to B. */
+ * triangles).  Free-edge folds are applied to B.  flags: ORC_WORLD_FRAME
+ * (edge models only) builds the quadratic thin plate/shell operator L_n of
+ * App. D (eq 79), heights and feet taken on the unprojected rest stencil. */
+#define ORC_WORLD_FRAME 1
 int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t* idx,
-              double young, double poisson, double thickness,
+              double young, double poisson, double thickness, int flags,
               double* B, double* kappa0, double* D);
 
 /* Bending energy and force f = -dPsi/dx over all stencils. f [nv][3] is overwritten. */

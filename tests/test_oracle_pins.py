@@ -150,6 +150,98 @@ def test_edge_normal_is_the_line_of_eq8():
     assert signs == {-1, 1}  # eq 8's direction flips with the bend, the stencil normal does not
 
 
+# ------------------------------------------------------------------ quadratic thin plate/shell (App. D)
+
+
+def _rest_normal_angles(X, idx):
+    """Angle between the two rest triangle normals of each edge stencil (1,2,3) and (4,3,2)."""
+    def unit(u):
+        return u / np.linalg.norm(u, axis=1, keepdims=True)
+    a = unit(np.cross(X[idx[:, 1]] - X[idx[:, 0]], X[idx[:, 2]] - X[idx[:, 0]]))
+    b = unit(np.cross(X[idx[:, 2]] - X[idx[:, 3]], X[idx[:, 1]] - X[idx[:, 3]]))
+    return np.arccos(np.clip((a * b).sum(axis=1), -1.0, 1.0))
+
+
+@pytest.mark.parametrize("model", ["EP", "ES"])
+def test_world_frame_operator_on_a_flat_rest_is_the_projected_one(model):
+    """On a flat rest the projection does nothing, so L_n of eq 79 equals L_m (and QTP/QTS equal EP/ES)."""
+    m = I.plate_mesh(9, 1.0, 0.2, 3, model, "none")
+    a, b = stencils(model, m.X, m.tris), O.Stencils(model, m.X, m.tris, 1.0, 0.3, 1.0, world_frame=True)
+    assert np.abs(b.B - a.B).max() <= 1e-13 * np.abs(a.B).max()
+    np.testing.assert_array_equal(b.D, a.D)
+
+
+@pytest.mark.parametrize("model", ["EP", "ES"])
+def test_world_frame_operator_is_cos2_half_angle_times_projected(model):
+    """Both wings of a hinge make the angle phi0/2 with the bisector tangent plane (phi0: angle between
+    the rest triangle normals), so projected heights are cos(phi0/2) times the world-frame ones while the
+    feet along the hinge do not move; every entry of L ~ 1/h^2, hence L_n = cos^2(phi0/2) L_m, and the
+    shell's rest curvature scales the same way."""
+    m = I.cylinder_mesh(9, 0.5, 0.6, 0.6, 0.2, 4, model, "none")
+    a, b = stencils(model, m.X, m.tris), O.Stencils(model, m.X, m.tris, 1.0, 0.3, 1.0, world_frame=True)
+    phi0 = _rest_normal_angles(m.X, a.idx)
+    assert phi0.max() > 0.05  # a curved rest
+    g = np.cos(phi0 / 2) ** 2
+    assert np.abs(b.B[:, 0, :] - g[:, None] * a.B[:, 0, :]).max() <= 1e-12 * np.abs(a.B).max()
+    assert np.abs(b.kappa0[:, 0] - g * a.kappa0[:, 0]).max() <= 1e-12 * max(np.abs(a.kappa0).max(), 1e-300) + 1e-300
+    np.testing.assert_array_equal(b.D, a.D)
+
+
+def test_quadratic_shell_energy_is_three_times_the_quadratic_plate_energy():
+    """App. D: the Quadratic Shell bends a hinge of length l by theta with the energy
+    1/2 A' k_b (theta l / A')^2 over the area A' = (A1 + A4)/3; the quadratic thin plate's energy of the
+    same bend tends to a third of that as theta -> 0."""
+    X = np.array([[0.1, -0.7, 0], [-0.5, 0, 0], [0.6, 0.1, 0], [-0.2, 0.9, 0]], float)
+    tris = np.array([[0, 1, 2], [3, 2, 1]], np.int32)
+    st = O.Stencils("EP", X, tris, 1.0, 0.3, 1.0, world_frame=True)
+    A1 = 0.5 * np.linalg.norm(np.cross(X[1] - X[0], X[2] - X[0]))
+    A4 = 0.5 * np.linalg.norm(np.cross(X[2] - X[3], X[1] - X[3]))
+    hinge = X[2] - X[1]
+    l = np.linalg.norm(hinge)
+    axis = hinge / l
+    ratios = []
+    for theta in (1e-2, 1e-3):
+        # rotate vertex 4 about the hinge line by theta
+        v = X[3] - X[1]
+        vr = (v * math.cos(theta) + np.cross(axis, v) * math.sin(theta)
+              + axis * (axis @ v) * (1 - math.cos(theta)))
+        x = X.copy()
+        x[3] = X[1] + vr
+        psi_qtp = st.energy(x)
+        Ap = (A1 + A4) / 3
+        psi_qs = 0.5 * Ap * KB1 * (theta * l / Ap) ** 2
+        ratios.append(psi_qs / psi_qtp)
+    assert abs(ratios[0] - 3.0) < 1e-3
+    assert abs(ratios[1] - 3.0) < 1e-5
+
+
+@pytest.mark.parametrize("model", ["EP", "ES"])
+def test_world_frame_variant_invariants(model):
+    """QTP/QTS on a curved rest: zero force at rest and under rigid motions, force = -dPsi/dx, and a
+    symmetric PSD constant Hessian."""
+    m = I.cylinder_mesh(8, 0.5, 0.6, 0.6, 0.2, 6, model, "none")
+    st = O.Stencils(model, m.X, m.tris, 1.0, 0.3, 1.0, world_frame=True)
+    scale = np.abs(st.B).max() * np.abs(st.D).max()
+    g = I.rng(31)
+    if model == "ES":
+        f0, _ = st.forces(m.X)
+        assert np.abs(f0).max() < 1e-13 * scale
+        Q = I.random_rotation(g)
+        f1, _ = st.forces(m.X @ Q.T + g.standard_normal(3))
+        assert np.abs(f1).max() < 1e-12 * scale
+    x = m.X + 1e-2 * g.standard_normal(m.X.shape)
+    f, _ = st.forces(x)
+    d = g.standard_normal(x.shape)
+    h = 1e-5
+    e = [st.energy(x + s * h * d) for s in (-2, -1, 1, 2)]
+    fd = (e[0] - 8 * e[1] + 8 * e[2] - e[3]) / (12 * h)
+    assert abs(fd + (f * d).sum()) <= 1e-8 * abs((f * d).sum())
+    rp, col, val = st.hessian()
+    K = sp.csr_matrix((val, col, rp), shape=(m.nv, m.nv)).toarray()
+    assert np.abs(K - K.T).max() <= 1e-13 * np.abs(K).max()
+    assert np.linalg.eigvalsh(K).min() >= -1e-12 * np.abs(K).max()
+
+
 # ------------------------------------------------------------------ P2: invariance (eq 12)
 
 
