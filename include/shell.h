@@ -69,13 +69,20 @@ typedef struct {
     int32_t block_vertices;  /* vertices per force work-group tile, 64..4096; 0 selects the default (2048) */
     int32_t reorder;         /* internal vertex order: 1 (default) recursive coordinate bisection into compact
                                 tiles of block_vertices, 2 Morton order, 0 the caller's order */
-    int32_t flags;           /* 0, or SHELL_FLAG_DIRECT_PRODUCT */
+    int32_t flags;           /* 0, or SHELL_FLAG_DIRECT_PRODUCT and/or SHELL_FLAG_WORLD_FRAME */
 } shell_config_t;
 
 /* The PCG product gathers each neighbour's entries straight from memory instead of staging every 512-row
  * group's distinct columns in LDS.  Chosen by itself when a group has more than 4096 distinct columns;
  * the flag forces it (to compare the two forms). */
 #define SHELL_FLAG_DIRECT_PRODUCT 1
+
+/* Edge models only (EP, ES): the quadratic thin plate/shell variant of App. D (eq 79), whose curvature
+ * operator L_n takes the heights and the feet on the hinge of the rest stencil as it lies in the world
+ * frame instead of on its projection onto the tangent plane (for a rest dihedral phi0, L_n = cos^2(phi0/2)
+ * L_m; identical on a flat rest).  The force and step kernels are those of EP and ES.  With a triangle
+ * model the build returns SHELL_E_INVALID_ARG. */
+#define SHELL_FLAG_WORLD_FRAME 2
 
 typedef struct shell_stencils_s* shell_stencils_t;
 typedef struct shell_hessian_s* shell_hessian_t;

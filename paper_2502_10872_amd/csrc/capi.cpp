@@ -104,7 +104,10 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         int reorder = cfg ? cfg->reorder : 1;
         SHELL_CHECK(reorder >= 0 && reorder <= 2, SHELL_E_INVALID_ARG, "unknown vertex order");
         const int cfg_flags = cfg ? cfg->flags : 0;
-        SHELL_CHECK((cfg_flags & ~SHELL_FLAG_DIRECT_PRODUCT) == 0, SHELL_E_INVALID_ARG, "unknown flag");
+        SHELL_CHECK((cfg_flags & ~(SHELL_FLAG_DIRECT_PRODUCT | SHELL_FLAG_WORLD_FRAME)) == 0, SHELL_E_INVALID_ARG,
+                    "unknown flag");
+        SHELL_CHECK(!(cfg_flags & SHELL_FLAG_WORLD_FRAME) || model_is_edge(model), SHELL_E_INVALID_ARG,
+                    "the world-frame operator applies to the edge models (EP, ES)");
         hipStream_t s = as_stream(stream);
 
         auto st = std::make_unique<shell_stencils_s>();

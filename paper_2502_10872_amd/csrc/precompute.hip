@@ -21,8 +21,8 @@ namespace {
 constexpr int kFlagDegenerate = 1;
 
 __global__ void precompute_edge(const double* __restrict__ X, const int32_t* __restrict__ idx, long ns,
-                                double kb, int shell_model, double* __restrict__ B, double* __restrict__ k0,
-                                int32_t* __restrict__ flags) {
+                                double kb, int shell_model, int world_frame, double* __restrict__ B,
+                                double* __restrict__ k0, int32_t* __restrict__ flags) {
     long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (s >= ns) return;
     V3<double> x1 = load3(X, idx[s]), x2 = load3(X, idx[ns + s]), x3 = load3(X, idx[2 * ns + s]),
@@ -37,8 +37,10 @@ __global__ void precompute_edge(const double* __restrict__ X, const int32_t* __r
     double lm = norm(m);
     if (!(lm > 1e-12)) flag = kFlagDegenerate;
     V3<double> n0 = (1.0 / lm) * m;
-    // projection onto the tangent plane through x2
-    V3<double> ac = a - dot(n0, a) * n0, ec = e - dot(n0, e) * n0, bc = b - dot(n0, b) * n0;
+    // projection onto the tangent plane through x2 (eq 7); the world-frame operator of the quadratic thin
+    // plate/shell (App. D, eq 79) measures the unprojected stencil
+    const double wp = world_frame ? 0.0 : 1.0;
+    V3<double> ac = a - (wp * dot(n0, a)) * n0, ec = e - (wp * dot(n0, e)) * n0, bc = b - (wp * dot(n0, b)) * n0;
     double ee = dot(ec, ec);
     double sp = dot(ac, ec) / ee, sq = dot(bc, ec) / ee;
     double h1 = norm(ac - sp * ec), h4 = norm(bc - sq * ec);
@@ -267,7 +269,8 @@ void launch_precompute(shell_stencils_s& st, hipStream_t s) {
     int blk = 256;
     long grid = (ns + blk - 1) / blk;
     if (model_is_edge(st.model)) {
-        precompute_edge<<<grid, blk, 0, s>>>(st.X.p, st.idx.p, ns, st.kb, model_is_shell(st.model), st.B.p, st.k0.p,
+        precompute_edge<<<grid, blk, 0, s>>>(st.X.p, st.idx.p, ns, st.kb, model_is_shell(st.model),
+                                             (st.cfg_flags & SHELL_FLAG_WORLD_FRAME) != 0, st.B.p, st.k0.p,
                                              st.flags.p);
     } else {
         std::vector<int32_t> mask(size_t(ns), 0);

@@ -43,6 +43,7 @@ class shell_config_t(ctypes.Structure):
 
 
 SHELL_FLAG_DIRECT_PRODUCT = 1
+SHELL_FLAG_WORLD_FRAME = 2  # edge models: the quadratic thin plate/shell operator (App. D, eq 79)
 
 
 class shell_stencils_info_t(ctypes.Structure):

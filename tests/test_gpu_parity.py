@@ -221,6 +221,72 @@ def test_shell_steps_replay_match_oracle(model):
     assert rel(v, osim.v) <= TOL64
 
 
+# ------------------------------------------------------------------ quadratic thin plate/shell (App. D)
+
+
+def _qt_mesh(model, n=25):
+    """A curved rest for both edge models (on a flat rest the variant equals EP/ES)."""
+    return I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 9, model, "ends")
+
+
+@pytest.mark.parametrize("model", ["EP", "ES"])
+def test_world_frame_variant_matches_oracle(model):
+    """SHELL_FLAG_WORLD_FRAME (QTP/QTS, eq 79) on a cylinder rest: operators, K_s, forces and energy
+    against the oracle's world-frame build, FP64, and mixed forces within the mixed bound."""
+    mesh = _qt_mesh(model)
+    ost = O.Stencils(model, mesh.X, mesh.tris, MAT["young"], MAT["poisson"], MAT["thickness"], world_frame=True)
+    plain = oracle_stencils(model, mesh)
+    assert np.abs(ost.B - plain.B).max() > 1e-3 * np.abs(plain.B).max()  # the variant differs here
+    x = mesh.X + 2e-3 * I.rng(41).standard_normal(mesh.X.shape)
+    f_ref, e_ref = ost.forces(x)
+    with S.Problem(mesh, MAT, model=model, block_vertices=128, sim=False, flags=S.SHELL_FLAG_WORLD_FRAME) as pb:
+        idx, B, k0 = S.shell_stencils_export(pb.st)
+        scale = np.sqrt(ost.D[:, 0, 0])
+        where = {tuple(r): i for i, r in enumerate(ost.idx.tolist())}
+        order = np.array([where[tuple(r)] for r in idx.tolist()])
+        assert rel(B, (ost.B * scale[:, None, None])[order]) <= 1e-12
+        if model == "ES":
+            assert rel(k0, (ost.kappa0 * scale[:, None])[order]) <= 1e-12
+        rp, col, val = ost.hessian()
+        grp, gcol, gval = S.shell_hessian_export_csr(pb.h, mesh.nv)
+        assert np.array_equal(grp, rp) and np.array_equal(gcol, col)
+        assert rel(gval, val) <= 1e-12
+        f, e = gpu_forces(pb.st, x)
+        assert rel(f, f_ref) <= TOL64
+        assert abs(e - e_ref) <= TOL64 * abs(e_ref)
+    st32 = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, precision=S.SHELL_PREC_MIXED,
+                                  flags=S.SHELL_FLAG_WORLD_FRAME)
+    try:
+        f32, _ = gpu_forces(st32, x, f32=True)
+        assert rel(f32, f_ref) <= TOL_MIXED_FORCE
+    finally:
+        S.shell_destroy_stencils(st32)
+
+
+def test_world_frame_shell_steps_replay_match_oracle():
+    """QTS steps on the cylinder rest: three steps of two Newton solves, counts replayed, against the
+    oracle's world-frame simulation."""
+    mesh = _qt_mesh("ES", 24)
+    ost = O.Stencils("ES", mesh.X, mesh.tris, MAT["young"], MAT["poisson"], MAT["thickness"], world_frame=True)
+    osim = O.Sim(ost, MAT, mesh.pinned)
+    with S.Problem(mesh, MAT, model="ES", block_vertices=128, flags=S.SHELL_FLAG_WORLD_FRAME) as pb:
+        for _ in range(3):
+            counts, ostats = osim.step(1 / 30, max_newton=2, pcg_rtol=1e-8)
+            params, _keep = S.step_params(1 / 30, max_newton=2, pcg_rtol=1e-8, replay=counts)
+            rc, gstats = S.shell_step_implicit(pb.sim, params)
+            assert gstats["newton_iters"] == ostats["newton_iters"]
+        x, v, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+    assert rel(x - mesh.X, osim.x - mesh.X) <= TOL64
+    assert rel(v, osim.v) <= TOL64
+
+
+def test_world_frame_flag_is_rejected_for_triangle_models():
+    mesh = _qt_mesh("SS", 9)
+    with pytest.raises(S.ShellError) as ei:
+        S.shell_build_stencils(mesh.X, mesh.tris, "SS", MAT, flags=S.SHELL_FLAG_WORLD_FRAME)
+    assert ei.value.status == S.SHELL_E_INVALID_ARG
+
+
 @pytest.mark.parametrize("model,n,wg", [("SS", 40, 1), ("FS", 36, 1), ("SS", 46, 2), ("EP", 32, 1)])
 def test_several_row_groups_per_pcg_workgroup(model, n, wg):
     """Few PCG work-groups, each walking several consecutive row groups (the large-mesh launch shape).
