@@ -275,17 +275,19 @@ def stream_copy_gbs(torch):
 
 def force_models(S, I, torch, precisions, reps=20):
     """Force kernel of every model on a 1024 x 1024 mesh (shells: the sphere cap; plates: a flat square
-    of the same side), launched back to back on one state (shell_sim_time_kernels)."""
+    of the same side), launched back to back on one state (shell_sim_time_kernels); QTS is the edge shell
+    with the world-frame operator (App. D) on the cap."""
     out = {}
     cap = I.workload_sphere_cap(1024, "SS")
     side = cap.meta.get("side", 1.2 * cap.meta["radius"])
-    for model in I.MODELS:
+    for model in list(I.MODELS) + ["QTS"]:
+        flags = S.SHELL_FLAG_WORLD_FRAME if model == "QTS" else 0
         if model.endswith("S"):
-            mesh = I.workload_sphere_cap(1024, model)
+            mesh = I.workload_sphere_cap(1024, "ES" if model == "QTS" else model)
         else:
             mesh = I.plate_mesh(1024, side, 0.2, 2502108723, model, "ring")
         for prec in precisions:
-            pb = S.Problem(mesh, I.MATERIAL, precision=prec)
+            pb = S.Problem(mesh, I.MATERIAL, precision=prec, flags=flags)
             kt = S.shell_sim_time_kernels(pb.sim, 1.0 / 30.0, reps=reps)
             hinfo = S.shell_hessian_info(pb.h)
             ab = algorithmic_bytes(pb.info, hinfo, prec)
