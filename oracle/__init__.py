@@ -51,13 +51,13 @@ def lib():
         i64 = ctypes.c_int64
         d = ctypes.c_double
         i = ctypes.c_int
-        L.orc_topology.argtypes = [i, i64, i64, P, P, P]
-        L.orc_build.argtypes = [i, i64, P, i64, P, d, d, d, i, P, P, P]
-        L.orc_forces.argtypes = [i, i64, P, i64, P, P, P, P, P, P]
+        L.orc_topology.argtypes = [i, i64, i64, P, i64, P, P, P, P]
+        L.orc_build.argtypes = [i, i64, P, i64, P, P, d, d, d, i, P, P, P, P]
+        L.orc_forces.argtypes = [i, i64, P, i64, P, P, P, P, P, P, P]
         L.orc_hessian.argtypes = [i, i64, i64, P, P, P, P, P, P, P]
         L.orc_mass.argtypes = [i64, P, i64, P, d, d, P]
         L.orc_apply.argtypes = [i64, P, P, P, P, d, P, P]
-        L.orc_step.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, P, P, P, d, P, i, d, d, i, P, P, P]
+        L.orc_step.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, P, P, P, P, d, P, i, d, d, i, P, P, P]
         L.orc_edge_normal_literal.argtypes = [P, P, P, P, P]
         _lib = L
     return _lib
@@ -86,9 +86,10 @@ def curv_size(model) -> int:
 
 class Stencils:
     """Rest-precomputed stencils of one mesh for one model.  world_frame (edge models): the quadratic
-    thin plate/shell operator of App. D (eq 79) instead of the projected one."""
+    thin plate/shell operator of App. D (eq 79) instead of the projected one.  clamped: [n][2] vertex
+    pairs of boundary edges with the clamped condition (eqs 30-31, 59); other boundary edges are free."""
 
-    def __init__(self, model, X, tris, young, poisson, thickness, world_frame=False):
+    def __init__(self, model, X, tris, young, poisson, thickness, world_frame=False, clamped=None):
         self.model = model_id(model)
         self.X = np.ascontiguousarray(X, dtype=np.float64)
         self.tris = np.ascontiguousarray(tris, dtype=np.int32)
@@ -96,25 +97,32 @@ class Stencils:
         self.nt = self.tris.shape[0]
         self.k = stencil_size(self.model)
         self.r = curv_size(self.model)
+        cl = np.zeros((0, 2), dtype=np.int32) if clamped is None else \
+            np.ascontiguousarray(clamped, dtype=np.int32).reshape(-1, 2)
+        self.clamped = cl
         ns = ctypes.c_int64(0)
-        _check(lib().orc_topology(self.model, self.nv, self.nt, _p(self.tris), ctypes.byref(ns), None), "topology")
+        _check(lib().orc_topology(self.model, self.nv, self.nt, _p(self.tris), cl.shape[0], _p(cl),
+                                  ctypes.byref(ns), None, None), "topology")
         self.ns = ns.value
         self.idx = np.zeros((self.ns, self.k), dtype=np.int32)
-        _check(lib().orc_topology(self.model, self.nv, self.nt, _p(self.tris), ctypes.byref(ns), _p(self.idx)),
-               "topology")
+        self.bc = np.zeros(self.ns, dtype=np.uint8)
+        _check(lib().orc_topology(self.model, self.nv, self.nt, _p(self.tris), cl.shape[0], _p(cl),
+                                  ctypes.byref(ns), _p(self.idx), _p(self.bc)), "topology")
         self.B = np.zeros((self.ns, self.r, self.k))
         self.kappa0 = np.zeros((self.ns, self.r))
         self.D = np.zeros((self.ns, self.r, self.r))
+        self.Crest = np.zeros((self.ns, self.r, 3))
         self.world_frame = bool(world_frame)
-        _check(lib().orc_build(self.model, self.nv, _p(self.X), self.ns, _p(self.idx), young, poisson, thickness,
-                               WORLD_FRAME if world_frame else 0, _p(self.B), _p(self.kappa0), _p(self.D)), "build")
+        _check(lib().orc_build(self.model, self.nv, _p(self.X), self.ns, _p(self.idx), _p(self.bc), young, poisson,
+                               thickness, WORLD_FRAME if world_frame else 0, _p(self.B), _p(self.kappa0),
+                               _p(self.D), _p(self.Crest)), "build")
 
     def forces(self, x):
         x = np.ascontiguousarray(x, dtype=np.float64)
         f = np.zeros((self.nv, 3))
         e = ctypes.c_double(0.0)
         _check(lib().orc_forces(self.model, self.nv, _p(x), self.ns, _p(self.idx), _p(self.B), _p(self.kappa0),
-                                _p(self.D), _p(f), ctypes.byref(e)), "forces")
+                                _p(self.Crest), _p(self.D), _p(f), ctypes.byref(e)), "forces")
         return f, e.value
 
     def energy(self, x):
@@ -179,8 +187,9 @@ class Sim:
             raise ValueError("replay needs one row per Newton iteration")
         rowptr, col, val = self.csr
         st = self.st
-        rc = lib().orc_step(st.model, st.nv, st.ns, _p(st.idx), _p(st.B), _p(st.kappa0), _p(st.D), _p(rowptr),
-                            _p(col), _p(val), _p(self.mass), _p(self.pinned), _p(self.x), _p(self.v), dt, _p(g),
+        rc = lib().orc_step(st.model, st.nv, st.ns, _p(st.idx), _p(st.B), _p(st.kappa0), _p(st.Crest), _p(st.D),
+                            _p(rowptr), _p(col), _p(val), _p(self.mass), _p(self.pinned), _p(self.x), _p(self.v), dt,
+                            _p(g),
                             max_newton, newton_rtol, pcg_rtol, max_pcg, _p(rep), _p(counts), _p(stats))
         if rc not in (0, -5):
             _check(rc, "step")

@@ -36,6 +36,13 @@
  *  - FVM: when a stencil has a free edge, the twist component is zeroed in the
  *    frame whose x axis runs along its first free edge (parity unpinned beyond
  *    invariants, finite differences and Hessian checks);
+ *  - clamped edges (eqs 30-31, 59): the virtual node moves with L, so its
+ *    operator column joins L's; the edge plate's boundary stencil weighs its one
+ *    real triangle's area; a plate stencil with a clamped edge measures its
+ *    curvature vectors from the rest shape, C = B (x - X), since the clamped
+ *    fold does not annihilate the flat rest coordinates; FVM keeps the twist on
+ *    clamped edges; the edge shell emits no clamped stencil (its energy would
+ *    vanish identically in its own triangle's frame);
  *  - mass is lumped, m_v = rho h sum(A_T)/3; x_hat = x + dt v + dt^2 g;
  *    v^{t+1} = (x^{t+1} - x^t)/dt; pinned vertices keep their position;
  *  - linear solver: Jacobi-preconditioned CG per coordinate, x0 = 0, stop when
@@ -126,12 +133,43 @@ static const dedge_t* find_dedge(const dedge_t* de, int64_t n, int32_t from, int
     return (const dedge_t*)bsearch(&key, de, (size_t)n, sizeof(dedge_t), cmp_dedge);
 }
 
-int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t* ns, int32_t* idx) {
-    if (model < 0 || model > 5 || nv < 0 || nt < 0 || !ns) return ORC_E_ARG;
+/* undirected vertex pair, smaller id first, for the clamped-edge lookup */
+typedef struct { int32_t a, b; } upair_t;
+
+static int cmp_upair(const void* pa, const void* pb) {
+    const upair_t* x = (const upair_t*)pa;
+    const upair_t* y = (const upair_t*)pb;
+    if (x->a != y->a) return x->a < y->a ? -1 : 1;
+    if (x->b != y->b) return x->b < y->b ? -1 : 1;
+    return 0;
+}
+
+static int is_clamped(const upair_t* cl, int64_t ncl, int32_t u, int32_t v) {
+    upair_t key = {u < v ? u : v, u < v ? v : u};
+    return ncl > 0 && bsearch(&key, cl, (size_t)ncl, sizeof(upair_t), cmp_upair) != NULL;
+}
+
+int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t n_clamped,
+                 const int32_t* clamped, int64_t* ns, int32_t* idx, uint8_t* bc) {
+    if (model < 0 || model > 5 || nv < 0 || nt < 0 || !ns || n_clamped < 0 || (n_clamped > 0 && !clamped) ||
+        (idx && !bc))
+        return ORC_E_ARG;
     dedge_t* de = NULL;
     int rc = directed_edges(nv, nt, tris, &de);
     if (rc) return rc;
     int64_t nde = 3 * nt;
+    /* clamped edges (Sec. 4.3 boundary conditions): each must be a boundary edge, i.e. traversed by
+       exactly one triangle */
+    upair_t* cl = (upair_t*)malloc(sizeof(upair_t) * (size_t)(n_clamped + 1));
+    if (!cl) { free(de); return ORC_E_ARG; }
+    for (int64_t e = 0; e < n_clamped; ++e) {
+        int32_t u = clamped[2 * e], v = clamped[2 * e + 1];
+        int one = (find_dedge(de, nde, u, v) != NULL) + (find_dedge(de, nde, v, u) != NULL);
+        if (u < 0 || v < 0 || u >= nv || v >= nv || one != 1) { free(cl); free(de); return ORC_E_ARG; }
+        cl[e].a = u < v ? u : v;
+        cl[e].b = u < v ? v : u;
+    }
+    qsort(cl, (size_t)n_clamped, sizeof(upair_t), cmp_upair);
     /* an undirected edge shared by two triangles must appear once in each direction;
        a third triangle on the same pair of vertices makes the edge non-manifold */
     int64_t count = 0;
@@ -146,9 +184,29 @@ int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t
                     s[1] = de[e].from;
                     s[2] = de[e].to;
                     s[3] = tw->opp; /* vertex 4: T432 traverses 3->2 */
+                    bc[count] = 0;
                 }
                 ++count;
             }
+        }
+    }
+    if (is_edge(model) && !is_shell(model)) {
+        /* plate: a clamped boundary edge gets the stencil (L, M, N, L') of its one triangle, the virtual
+           node L' (-1 here) being the reflection of L through the edge's midpoint.  The edge shell's
+           boundary stencil is not emitted: measured along its own triangle's normal, every transverse
+           displacement of the folded stencil is zero, so its energy vanishes identically. */
+        for (int64_t e = 0; e < nde; ++e) {
+            if (find_dedge(de, nde, de[e].to, de[e].from)) continue;
+            if (!is_clamped(cl, n_clamped, de[e].from, de[e].to)) continue;
+            if (idx) {
+                int32_t* s = idx + 4 * count;
+                s[0] = de[e].opp;
+                s[1] = de[e].from;
+                s[2] = de[e].to;
+                s[3] = -1;
+                bc[count] = 1;
+            }
+            ++count;
         }
     }
     if (!is_edge(model)) {
@@ -166,9 +224,15 @@ int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t
                     const dedge_t* nb = find_dedge(de, nde, v[(i + 2) % 3], v[(i + 1) % 3]);
                     s[3 + i] = nb ? nb->opp : -1;
                 }
+                /* bit i: the missing flap i+3 lies across a clamped edge */
+                bc[t] = 0;
+                for (int i = 0; i < 3; ++i)
+                    if (s[3 + i] < 0 && is_clamped(cl, n_clamped, v[(i + 1) % 3], v[(i + 2) % 3]))
+                        bc[t] |= (uint8_t)(1 << i);
             }
         }
     }
+    free(cl);
     free(de);
     *ns = count;
     return ORC_OK;
@@ -179,8 +243,8 @@ int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t
 /* Edge-based hinge (Sec. 4.3): L_m = 2 L_theta/(h1+h4) on the projected stencil.  world != 0: the
    quadratic thin plate/shell variant (App. D, eq 79), whose operator L_n takes the heights and feet of
    the rest stencil as it lies in the world frame, without the projection. */
-static int build_edge(int shell, int world, const double* X1, const double* X2, const double* X3, const double* X4,
-                      double kb, double* L, double* kappa0, double* D) {
+static int build_edge(int shell, int world, int clamped, const double* X1, const double* X2, const double* X3,
+                      const double* X4, double kb, double* L, double* kappa0, double* D) {
     double na[3], nb[3], n0[3];
     double Aa = 0.5 * tri_normal(X1, X2, X3, na);
     double Ab = 0.5 * tri_normal(X4, X3, X2, nb);
@@ -219,6 +283,13 @@ static int build_edge(int shell, int world, const double* X1, const double* X2, 
     L[2] = -c * (sp / h1 + sq / h4);
     L[3] = c * (1.0 / h4);
     D[0] = kb * (Aa + Ab);
+    if (clamped) {
+        /* clamped boundary edge (eqs 30-31): the virtual node moves with L, so its column joins L's; the
+           stencil's area is its one real triangle's, the virtual one lying outside the plate */
+        L[0] += L[3];
+        L[3] = 0.0;
+        D[0] = kb * Aa;
+    }
     kappa0[0] = 0.0;
     if (shell) {
         for (int j = 0; j < 4; ++j) kappa0[0] += L[j] * dot3(n0, Xs[j]);
@@ -255,7 +326,8 @@ static double inv3(const double M[3][3], double Mi[3][3]) {
 }
 
 /* Triangle-centred stencil (Secs 4.4, 4.5; App. A, C).  Xs[j] == NULL for a missing flap. */
-static int build_tri(int model, const double* Xs[6], const double Db[3][3], double* B, double* kappa0, double* D) {
+static int build_tri(int model, int clampmask, const double* Xs[6], const double Db[3][3], double* B, double* kappa0,
+                     double* D) {
     const double *X1 = Xs[0], *X2 = Xs[1], *X3 = Xs[2];
     /* rest corotational frame (eq 65): origin X1, x axis along X12, z the triangle normal */
     double ex[3], ez[3], ey[3], d12[3];
@@ -349,21 +421,27 @@ static int build_tri(int model, const double* Xs[6], const double Db[3][3], doub
                 Bm[r][j] = s;
             }
     }
-    /* free boundary fold (eq 61): w_{L+3} = w_M + w_N - w_L, superimposed per missing flap */
+    /* boundary folds, superimposed per missing flap: clamped w_{L+3} = w_L (eq 59), free
+       w_{L+3} = w_M + w_N - w_L (eq 61) */
     for (int L = 0; L < 3; ++L) {
         if (!missing[L]) continue;
         int M = (L + 1) % 3, N = (L + 2) % 3, F = L + 3;
         for (int r = 0; r < 3; ++r) {
-            Bm[r][M] += Bm[r][F];
-            Bm[r][N] += Bm[r][F];
-            Bm[r][L] -= Bm[r][F];
+            if (clampmask & (1 << L)) {
+                Bm[r][L] += Bm[r][F];
+            } else {
+                Bm[r][M] += Bm[r][F];
+                Bm[r][N] += Bm[r][F];
+                Bm[r][L] -= Bm[r][F];
+            }
             Bm[r][F] = 0.0;
         }
     }
-    /* FVM free edge: zero the twist (mixed second derivative) in the frame of the first free edge */
+    /* FVM free edge: zero the twist (mixed second derivative) in the frame of the first free edge;
+       clamped edges keep it */
     if (is_fvm(model)) {
         for (int L = 0; L < 3; ++L) {
-            if (!missing[L]) continue;
+            if (!missing[L] || (clampmask & (1 << L))) continue;
             int M = (L + 1) % 3, N = (L + 2) % 3;
             double e[2] = {P[N][0] - P[M][0], P[N][1] - P[M][1]};
             double len = hypot(e[0], e[1]);
@@ -406,29 +484,48 @@ static int build_tri(int model, const double* Xs[6], const double Db[3][3], doub
     return ORC_OK;
 }
 
-int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t* idx,
-              double young, double poisson, double thickness, int flags, double* B, double* kappa0, double* D) {
-    if (model < 0 || model > 5 || !X || !idx || !B || !kappa0 || !D) return ORC_E_ARG;
+int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t* idx, const uint8_t* bc,
+              double young, double poisson, double thickness, int flags, double* B, double* kappa0, double* D,
+              double* Crest) {
+    if (model < 0 || model > 5 || !X || !idx || !bc || !B || !kappa0 || !D || !Crest) return ORC_E_ARG;
     if ((flags & ~ORC_WORLD_FRAME) || ((flags & ORC_WORLD_FRAME) && !is_edge(model))) return ORC_E_ARG;
     double kb = young * thickness * thickness * thickness / (12.0 * (1.0 - poisson * poisson));
     double Db[3][3] = {{kb, kb * poisson, 0}, {kb * poisson, kb, 0}, {0, 0, kb * (1.0 - poisson) / 2.0}};
     int k = orc_stencil_size(model), r = orc_curv_size(model);
     for (int64_t s = 0; s < ns; ++s) {
         const int32_t* id = idx + k * s;
+        int edge_boundary = is_edge(model) && bc[s];
+        if (edge_boundary && (is_shell(model) || id[3] >= 0)) return ORC_E_ARG;
         for (int j = 0; j < k; ++j)
-            if (id[j] >= nv || (id[j] < 0 && (is_edge(model) || j < 3))) return ORC_E_ARG;
+            if (id[j] >= nv || (id[j] < 0 && (j < 3 || (is_edge(model) && !edge_boundary)))) return ORC_E_ARG;
         int rc;
         if (is_edge(model)) {
-            rc = build_edge(is_shell(model), (flags & ORC_WORLD_FRAME) != 0, X + 3 * id[0], X + 3 * id[1],
-                            X + 3 * id[2], X + 3 * id[3], kb, B + 4 * s, kappa0 + s, D + s);
+            double Xv[3];
+            const double* X4 = X + 3 * id[3];
+            if (edge_boundary) {
+                /* virtual node: reflection of vertex 1 through the midpoint of the boundary edge 2-3 */
+                for (int c = 0; c < 3; ++c) Xv[c] = X[3 * id[1] + c] + X[3 * id[2] + c] - X[3 * id[0] + c];
+                X4 = Xv;
+            }
+            rc = build_edge(is_shell(model), (flags & ORC_WORLD_FRAME) != 0, edge_boundary, X + 3 * id[0],
+                            X + 3 * id[1], X + 3 * id[2], X4, kb, B + 4 * s, kappa0 + s, D + s);
         } else {
             const double* Xs[6];
             for (int j = 0; j < 6; ++j) Xs[j] = id[j] >= 0 ? X + 3 * id[j] : NULL;
-            rc = build_tri(model, Xs, Db, B + 18 * s, kappa0 + 3 * s, D + 9 * s);
+            rc = build_tri(model, bc[s], Xs, Db, B + 18 * s, kappa0 + 3 * s, D + 9 * s);
         }
         if (rc) return rc;
+        /* plate stencil with a clamped edge: its curvature vectors are measured from the rest shape,
+           C = B (x - X), since the clamped fold does not annihilate the flat rest coordinates */
+        double* Cr = Crest + 3 * r * s;
+        for (int q = 0; q < 3 * r; ++q) Cr[q] = 0.0;
+        if (!is_shell(model) && bc[s]) {
+            const double* Bs = B + (size_t)(r * k) * s;
+            for (int i = 0; i < r; ++i)
+                for (int j = 0; j < k; ++j)
+                    if (id[j] >= 0) axpy3(Bs[i * k + j], X + 3 * id[j], Cr + 3 * i);
+        }
     }
-    (void)r;
     return ORC_OK;
 }
 
@@ -461,7 +558,7 @@ static void normal_vjp(const double* a, const double* b, const double* c, const 
 }
 
 int orc_forces(int model, int64_t nv, const double* x, int64_t ns, const int32_t* idx, const double* B,
-               const double* kappa0, const double* D, double* f, double* energy) {
+               const double* kappa0, const double* Crest, const double* D, double* f, double* energy) {
     if (model < 0 || model > 5 || !x || !f) return ORC_E_ARG;
     int k = orc_stencil_size(model), r = orc_curv_size(model);
     memset(f, 0, sizeof(double) * (size_t)(3 * nv));
@@ -478,6 +575,7 @@ int orc_forces(int model, int64_t nv, const double* x, int64_t ns, const int32_t
             C[i][0] = C[i][1] = C[i][2] = 0.0;
             for (int j = 0; j < k; ++j)
                 if (xs[j]) axpy3(Bs[i * k + j], xs[j], C[i]);
+            if (Crest && !is_shell(model)) axpy3(-1.0, Crest + 3 * (r * s + i), C[i]);
         }
         double fs[6][3];
         memset(fs, 0, sizeof(fs));
@@ -706,7 +804,7 @@ static int pcg_column(int64_t nv, const int64_t* rowptr, const int32_t* col, con
 }
 
 int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
-             const double* D, const int64_t* rowptr, const int32_t* col, const double* val, const double* mass,
+             const double* Crest, const double* D, const int64_t* rowptr, const int32_t* col, const double* val, const double* mass,
              const uint8_t* pinned, double* x, double* v, double dt, const double* gravity, int max_newton,
              double newton_rtol, double pcg_rtol, int max_pcg, const int32_t* replay, int32_t* counts, double* stats) {
     if (!x || !v || !mass || !pinned || dt <= 0 || max_newton < 0) return ORC_E_ARG;
@@ -736,7 +834,7 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
     double gn0 = 0, gn = 0;
     for (int k = 0;; ++k) {
         /* gradient of the incremental potential, g = M(x - x_hat) - dt^2 f(x), pinned rows zero */
-        orc_forces(model, nv, x, ns, idx, B, kappa0, D, f, NULL);
+        orc_forces(model, nv, x, ns, idx, B, kappa0, Crest, D, f, NULL);
         double s = 0;
         for (int64_t i = 0; i < nv; ++i)
             for (int d = 0; d < 3; ++d) {

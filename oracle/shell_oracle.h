@@ -34,22 +34,32 @@ int orc_curv_size(int model);      /* 1 (edge) or 3 (triangle) */
 /* Stencil topology.  idx == NULL: only *ns is returned.  Edge stencils are
  * (1,2,3,4) per interior edge with 2->3 the directed edge of the lower-id
  * orientation; triangle stencils are (1,2,3,4,5,6) per triangle with flap
- * i+3 across the edge opposite vertex i, -1 when that edge is a boundary. */
-int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t* ns, int32_t* idx);
+ * i+3 across the edge opposite vertex i, -1 when that edge is a boundary.
+ * clamped [n_clamped][2]: vertex pairs of boundary edges to clamp (any other
+ * pair is ORC_E_ARG).  The edge plate (EP) then also gets one stencil
+ * (L, M, N, -1) per clamped edge, after the interior ones, bc = 1; the edge
+ * shell (ES) gets none.  Triangle stencils: bc bit i = flap i+3 is missing
+ * and its edge clamped.  bc [ns] is required with idx. */
+int orc_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t n_clamped,
+                 const int32_t* clamped, int64_t* ns, int32_t* idx, uint8_t* bc);
 
 /* Rest precompute: operator B [ns][r][k], rest curvature kappa0 [ns][r]
  * (zero for plates), material D [ns][r][r] (k_b*A_E for edges, A*D_b for
- * triangles).  Free-edge folds are applied to B.  flags: ORC_WORLD_FRAME
+ * triangles), rest curvature vectors Crest [ns][r][3] = B X of plate
+ * stencils with a clamped edge (zero otherwise).  Free and clamped folds
+ * (eqs 30-31, 59-61) are applied to B per bc from orc_topology.  flags: ORC_WORLD_FRAME
  * (edge models only) builds the quadratic thin plate/shell operator L_n of
  * App. D (eq 79), heights and feet taken on the unprojected rest stencil. */
 #define ORC_WORLD_FRAME 1
-int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t* idx,
+int orc_build(int model, int64_t nv, const double* X, int64_t ns, const int32_t* idx, const uint8_t* bc,
               double young, double poisson, double thickness, int flags,
-              double* B, double* kappa0, double* D);
+              double* B, double* kappa0, double* D, double* Crest);
 
-/* Bending energy and force f = -dPsi/dx over all stencils. f [nv][3] is overwritten. */
+/* Bending energy and force f = -dPsi/dx over all stencils. f [nv][3] is overwritten.
+ * Crest (may be NULL): plate curvature vectors are C = B x - Crest. */
 int orc_forces(int model, int64_t nv, const double* x, int64_t ns, const int32_t* idx,
-               const double* B, const double* kappa0, const double* D, double* f, double* energy);
+               const double* B, const double* kappa0, const double* Crest, const double* D, double* f,
+               double* energy);
 
 /* Constant bending Hessian, scalar part K_s (K = K_s (x) I3), CSR with sorted
  * columns.  rowptr [nv+1]; col/val == NULL: only *nnz is returned. */
@@ -72,7 +82,7 @@ int orc_apply(int64_t nv, const int64_t* rowptr, const int32_t* col, const doubl
  * counts [max_newton][3] receives the iterations taken; stats[4] =
  * {newton_iters, pcg_total, grad_norm0, grad_norm_final}. */
 int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
-             const double* D, const int64_t* rowptr, const int32_t* col, const double* val,
+             const double* Crest, const double* D, const int64_t* rowptr, const int32_t* col, const double* val,
              const double* mass, const uint8_t* pinned, double* x, double* v,
              double dt, const double* gravity, int max_newton, double newton_rtol,
              double pcg_rtol, int max_pcg, const int32_t* replay, int32_t* counts, double* stats);

@@ -118,6 +118,15 @@ def equilateral_mesh(nx: int, ny: int, spacing: float = 1.0):
     return X, np.array(tris, dtype=np.int32)
 
 
+def boundary_edges(tris: np.ndarray) -> np.ndarray:
+    """Undirected edges used by exactly one triangle, [n][2] with the smaller vertex id first, sorted."""
+    t = np.asarray(tris, dtype=np.int64)
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    e.sort(axis=1)
+    u, cnt = np.unique(e, axis=0, return_counts=True)
+    return u[cnt == 1].astype(np.int32)
+
+
 def random_rotation(g: np.random.Generator) -> np.ndarray:
     q, r = np.linalg.qr(g.standard_normal((3, 3)))
     q = q * np.sign(np.diag(r))

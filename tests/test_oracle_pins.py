@@ -502,6 +502,224 @@ def test_linear_plate_edge_model_is_mesh_dependent_on_regular_grid():
     assert 0.5 < r < 0.6
 
 
+# ------------------------------------------------------------------ P13: clamped boundary operators
+
+
+def _fd_clamped_plate_alpha(N):
+    """Centre deflection coefficient alpha (w = alpha q a^4 / D) of the clamped square plate by the
+    13-point finite-difference biharmonic on an N x N grid; the zero slope enters through ghost nodes
+    mirroring the first interior row (w_{-1} = w_1), w = 0 on the boundary."""
+    n = N - 1
+    rows, cols, vals = [], [], []
+
+    def add(r, i, j, v):
+        i = -i if i < 0 else (2 * N - i if i > N else i)
+        j = -j if j < 0 else (2 * N - j if j > N else j)
+        if i in (0, N) or j in (0, N):
+            return
+        rows.append(r)
+        cols.append((i - 1) * n + j - 1)
+        vals.append(v)
+
+    for i in range(1, N):
+        for j in range(1, N):
+            r = (i - 1) * n + j - 1
+            add(r, i, j, 20.0)
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                add(r, i + di, j + dj, -8.0)
+            for di, dj in ((1, 1), (1, -1), (-1, 1), (-1, -1)):
+                add(r, i + di, j + dj, 2.0)
+            for di, dj in ((2, 0), (-2, 0), (0, 2), (0, -2)):
+                add(r, i + di, j + dj, 1.0)
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n * n, n * n)) * float(N) ** 4
+    w = spl.spsolve(A.tocsc(), np.ones(n * n))
+    return w[(N // 2 - 1) * n + N // 2 - 1]
+
+
+def _clamped_alpha():
+    a32, a64 = _fd_clamped_plate_alpha(32), _fd_clamped_plate_alpha(64)
+    return (4.0 * a64 - a32) / 3.0  # Richardson: the scheme is second order
+
+
+def test_fd_clamped_plate_coefficient_is_the_classical_value():
+    """Timoshenko and Woinowsky-Krieger tabulate alpha = 0.00126 for the clamped square plate under
+    uniform load (Theory of Plates and Shells, clamped rectangular plates)."""
+    assert abs(_clamped_alpha() - 0.00126) < 0.000006
+
+
+def _clamped_plate_ratio(model, n, jitter=0.0):
+    a, q, E, nu, h = 8.0, 9.81, 2e11, 0.3, 0.01
+    m = I.plate_mesh(n, a, jitter, 5, model, "ring")  # clamped: every boundary edge, boundary held
+    st = O.Stencils(model, m.X, m.tris, E, nu, h, clamped=I.boundary_edges(m.tris))
+    rowptr, col, val = st.hessian()
+    K = sp.csr_matrix((val, col, rowptr), shape=(m.nv, m.nv))
+    area = O.mass(m.X, m.tris, 1.0, 1.0)
+    free = np.where(m.pinned == 0)[0]
+    w = np.zeros(m.nv)
+    w[free] = spl.spsolve(K[free][:, free].tocsc(), q * area[free])
+    return w.max() / (_ALPHA_CACHE.setdefault("a", _clamped_alpha()) * q * a**4 * 12 * (1 - nu**2) / (E * h**3))
+
+
+_ALPHA_CACHE = {}
+
+
+def test_clamped_linear_plate_converges_at_second_order():
+    """Clamped folds (eq 59 for the smoothed hinge, the edge fold reused by the FVM hinge): the
+    triangle plates converge to the clamped plate from above, the error falling fourfold per halving."""
+    for model in ("FP", "SP"):
+        r = [_clamped_plate_ratio(model, n) for n in (17, 33, 65)]
+        assert 1.0 < r[2] < 1.004 and r[2] < r[1] < r[0]
+        assert 3.5 < (r[0] - 1.0) / (r[1] - 1.0) < 4.5 and 3.5 < (r[1] - 1.0) / (r[2] - 1.0) < 4.5
+    assert abs(_clamped_plate_ratio("SP", 33, 0.2) - 1.0) < 0.025
+    # the edge model stays mesh dependent on the regular grid, as with simply supported edges
+    assert 0.6 < _clamped_plate_ratio("EP", 33) < 0.8
+
+
+def _equilateral_strip(model, ny, clamp):
+    """Strip of equilateral triangles, 4 ny vertices long, held on its two long sides (rows 0 and
+    ny-1), uniform load; returns the mid-strip deflection over the cylindrical-bending beam value
+    q b^4/(384 D) (clamped sides) or 5 q b^4/(384 D) (simply supported sides)."""
+    E, nu, h, q = 1.0e6, 0.3, 0.01, 1.0
+    nx = 4 * ny
+    X, tris = I.equilateral_mesh(nx, ny, 1.0)
+    row = np.arange(nx * ny) // nx
+    held = (row == 0) | (row == ny - 1)
+    be = I.boundary_edges(tris)
+    st = O.Stencils(model, X, tris, E, nu, h, clamped=be[held[be[:, 0]] & held[be[:, 1]]] if clamp else None)
+    rowptr, col, val = st.hessian()
+    K = sp.csr_matrix((val, col, rowptr), shape=(st.nv, st.nv))
+    area = O.mass(X, tris, 1.0, 1.0)
+    free = np.where(~held)[0]
+    w = np.zeros(st.nv)
+    w[free] = spl.spsolve(K[free][:, free].tocsc(), q * area[free])
+    b = (ny - 1) * math.sqrt(3.0) / 2.0
+    D = E * h**3 / (12.0 * (1.0 - nu * nu))
+    return w[(ny // 2) * nx + nx // 2] / (q * b**4 / (384.0 * D) * (1.0 if clamp else 5.0))
+
+
+def test_clamped_edge_model_strip_converges_on_equilateral_mesh():
+    """The edge plate passes on equilateral meshes (Sec. 6 linear benchmark); clamped long sides give
+    the clamped beam (one fifth of the simply supported deflection), at second order.  This fixes the
+    boundary stencil's area as its one real triangle's: counting the virtual triangle as well makes
+    the clamp too stiff near the edge and the convergence first order from below."""
+    r = [_equilateral_strip("EP", ny, True) for ny in (9, 17, 33)]
+    assert 1.0 < r[2] < 1.01 and r[2] < r[1] < r[0]
+    assert 3.5 < (r[0] - 1.0) / (r[1] - 1.0) < 4.5
+    ss = _equilateral_strip("EP", 33, False)
+    assert abs(ss - 1.0) < 0.005
+    for model in ("FP", "SP"):
+        assert abs(_equilateral_strip(model, 33, True) - 1.0) < 0.01
+
+
+def test_clamped_edge_operator_is_eq31():
+    """On a boundary stencil the virtual node mirrors L through the edge midpoint, so h4 = h1 and the
+    feet swap; eq 31 then reads L'_m = [2, -1, -1, 0] / h1^2 on any triangle, obtuse ones included."""
+    X = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [1.7, 0.4, 0.0], [-0.5, 1.1, 0.0]])
+    tris = np.array([[0, 1, 2], [0, 2, 3]], dtype=np.int32)
+    be = I.boundary_edges(tris)
+    st = O.Stencils("EP", X, tris, 1.0, 0.3, 1.0, clamped=be)
+    assert st.ns == 1 + len(be) and (st.bc == 1).sum() == len(be)
+    for s in np.where(st.bc == 1)[0]:
+        L, M, N, v = st.idx[s]
+        assert v == -1
+        e = X[N] - X[M]
+        d = X[L] - X[M]
+        h1 = np.linalg.norm(d - (d @ e) / (e @ e) * e)
+        np.testing.assert_allclose(st.B[s, 0], np.array([2.0, -1.0, -1.0, 0.0]) / h1**2, rtol=1e-13)
+        tri_area = 0.5 * np.linalg.norm(np.cross(X[M] - X[L], X[N] - X[L]))
+        assert abs(st.D[s, 0, 0] - KB1 * tri_area) < 1e-14
+
+
+@pytest.mark.parametrize("model", ["EP", "FP", "SP"])
+def test_clamped_plate_is_rest_relative(model):
+    """Clamped plates measure curvature from the rest shape: no force at rest or under translation,
+    f = -(K_s (x) I3)(x - X) exactly, and a restoring force when the plate turns about its clamped
+    edges, which the free plate does not resist."""
+    m = I.plate_mesh(9, 1.0, 0.2, 3, model, "none")
+    be = I.boundary_edges(m.tris)
+    st = O.Stencils(model, m.X, m.tris, 1.0, 0.3, 1.0, clamped=be)
+    free = O.Stencils(model, m.X, m.tris, 1.0, 0.3, 1.0)
+    scale = np.abs(st.B).max() ** 2 * np.abs(st.D).max()
+    assert np.abs(st.Crest).max() > 1e-3 * np.abs(st.B).max()  # the fold does not annihilate the rest
+    for x in (m.X, m.X + np.array([0.3, -0.2, 0.7])):
+        f, e = st.forces(x)
+        assert np.abs(f).max() < 1e-12 * scale and abs(e) < 1e-20 * scale
+    rowptr, col, val = st.hessian()
+    K = sp.csr_matrix((val, col, rowptr), shape=(m.nv, m.nv))
+    g = I.rng(41)
+    u = 0.05 * g.standard_normal(m.X.shape)
+    f, e = st.forces(m.X + u)
+    Ku = K @ u
+    assert np.abs(f + Ku).max() <= 1e-11 * np.abs(Ku).max()
+    assert abs(e - 0.5 * (u * Ku).sum()) <= 1e-11 * abs((u * Ku).sum())
+    c, s_ = math.cos(0.01), math.sin(0.01)
+    Q = np.array([[1.0, 0.0, 0.0], [0.0, c, -s_], [0.0, s_, c]])  # a turn about the x axis
+    fr, _ = st.forces(m.X @ Q.T)
+    ff, _ = free.forces(m.X @ Q.T)
+    assert np.abs(fr).max() > 1e-3 * abs(K).max() * 0.01  # about 1e-2 |K| theta on this 1 m plate
+    assert np.abs(ff).max() < 1e-12 * scale
+
+
+@pytest.mark.parametrize("model", ["FS", "SS"])
+def test_clamped_shell_invariants(model):
+    """Triangle shells with clamped edges: zero force at rest and under rigid motions, force equal to
+    minus the energy gradient, K_s symmetric PSD with constants in its null space."""
+    m = rest_mesh(model, n=8)
+    be = I.boundary_edges(m.tris)
+    st = O.Stencils(model, m.X, m.tris, 1.0, 0.3, 1.0, clamped=be)
+    assert (st.bc != 0).sum() > 0
+    scale = np.abs(st.B).max() * np.abs(st.D).max()
+    g = I.rng(42)
+    f0, _ = st.forces(m.X)
+    assert np.abs(f0).max() < 1e-13 * scale
+    Q = I.random_rotation(g)
+    f1, _ = st.forces(m.X @ Q.T + g.standard_normal(3))
+    assert np.abs(f1).max() < 1e-12 * scale
+    x = m.X + 1e-2 * g.standard_normal(m.X.shape)
+    f, _ = st.forces(x)
+    d = g.standard_normal(x.shape)
+    h = 1e-5
+    e = [st.energy(x + s * h * d) for s in (-2, -1, 1, 2)]
+    fd = (e[0] - 8 * e[1] + 8 * e[2] - e[3]) / (12 * h)
+    assert abs(fd + (f * d).sum()) <= 1e-8 * abs((f * d).sum())
+    K = O.hessian_dense(st)
+    assert np.abs(K - K.T).max() <= 1e-13 * np.abs(K).max()
+    assert np.linalg.eigvalsh(K).min() >= -1e-12 * np.abs(K).max()
+    assert np.abs(K.sum(axis=1)).max() <= 1e-12 * np.abs(K).max()
+
+
+def test_clamped_and_free_folds_agree_in_the_smoothed_shell_form():
+    """In the shell form every vertex of the central triangle has zero transverse displacement in the
+    stencil's corotational frame, so the clamped (eq 59) and free (eq 61) folds give the same
+    curvature change at any state; only the constant Hessian, built from the folded operator, differs."""
+    m = rest_mesh("SS", n=8)
+    be = I.boundary_edges(m.tris)
+    cl = O.Stencils("SS", m.X, m.tris, 1.0, 0.3, 1.0, clamped=be)
+    fr = O.Stencils("SS", m.X, m.tris, 1.0, 0.3, 1.0)
+    assert not np.allclose(cl.B, fr.B)
+    g = I.rng(43)
+    for amp in (1e-3, 0.1):
+        x = m.X + amp * g.standard_normal(m.X.shape)
+        fc, ec = cl.forces(x)
+        ff, ef = fr.forces(x)
+        assert abs(ec - ef) <= 1e-12 * abs(ef)
+        assert np.abs(fc - ff).max() <= 1e-11 * np.abs(ff).max()
+
+
+def test_edge_shell_emits_no_clamped_stencil_and_bad_pairs_are_rejected():
+    """The edge shell's boundary stencil would measure its virtual node along its own triangle's
+    normal, where every transverse displacement vanishes: none is emitted.  A pair that is not a
+    boundary edge is an argument error."""
+    m = rest_mesh("ES", n=6)
+    be = I.boundary_edges(m.tris)
+    assert O.Stencils("ES", m.X, m.tris, 1.0, 0.3, 1.0, clamped=be).ns == O.Stencils(
+        "ES", m.X, m.tris, 1.0, 0.3, 1.0).ns
+    interior = m.tris[len(m.tris) // 2][:2]
+    for bad in ([interior], [[0, m.nv - 1]], [[0, m.nv]]):
+        with pytest.raises(O.OracleError):
+            O.Stencils("FP", m.X, m.tris, 1.0, 0.3, 1.0, clamped=np.array(bad))
+
+
 # ------------------------------------------------------------------ P9/P10: dynamics
 
 
