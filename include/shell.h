@@ -101,12 +101,21 @@ typedef void* shell_stream_t; /* hipStream_t */
  * node reflected through the edge midpoint and folded, eq 61; FVM additionally drops the twist
  * across the free edge).  The rest operators (eqs 10, 37-38, 50, App. C eqs 76-78), rest curvature
  * (eqs 14, 43, 51; shells only) and stencil areas are computed on the GPU in float64.
- * clamped_edges  host [n_clamped][2] vertex pairs of boundary edges to clamp (the clamped operators of
- *                eqs 30-31 and 59), or NULL with n_clamped = 0.  Not implemented: a non-empty list returns
- *                SHELL_E_UNSUPPORTED; clamp by holding the clamped side's two vertex rows fixed instead
- *                (the paper's own cantilever setting).
+ * clamped_edges  host [n_clamped][2] vertex pairs (either order) of boundary edges with the clamped
+ *                condition (eqs 30-31, 59), or NULL with n_clamped = 0; any pair that is not an edge of
+ *                exactly one triangle is SHELL_E_INVALID_ARG.  The virtual node moves with the vertex it
+ *                mirrors, so its operator column is added to that vertex's.  Edge plate (EP): one extra
+ *                stencil (L, M, N, L') per clamped edge, weighted by its one real triangle's area; the
+ *                edge shell (ES) gets none (along its own triangle's normal the folded stencil has no
+ *                transverse displacement, so its energy vanishes identically).  Triangle models: the
+ *                missing flap is folded onto L; FVM keeps the twist across a clamped edge.  Plates
+ *                measure the curvature of a stencil with a clamped edge from the rest shape,
+ *                C = B (x - X), since the clamped fold does not annihilate the flat rest coordinates.
+ *                In the shell forms the clamped and free folds give the same curvature change (the
+ *                central triangle's vertices have no transverse displacement in the stencil frame);
+ *                only K_s and FVM's twist differ.  A shell edge is held by fixing its vertex rows.
  * Errors: SHELL_E_INVALID_ARG, SHELL_E_NONMANIFOLD, SHELL_E_ORIENTATION, SHELL_E_DEGENERATE,
- * SHELL_E_UNSUPPORTED, SHELL_E_OOM, SHELL_E_HIP.  The call synchronises `stream` before returning.
+ * SHELL_E_OOM, SHELL_E_HIP.  The call synchronises `stream` before returning.
  */
 shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* tris, int64_t nt, int32_t model,
                                     const shell_material_t* mat, const int32_t* clamped_edges, int64_t n_clamped,

@@ -89,8 +89,6 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         for (int64_t e = 0; e < 2 * n_clamped; ++e)
             SHELL_CHECK(clamped_edges[e] >= 0 && clamped_edges[e] < nv, SHELL_E_INVALID_ARG,
                         "clamped edge vertex out of range");
-        SHELL_CHECK(n_clamped == 0, SHELL_E_UNSUPPORTED,
-                    "clamped edge operators (eqs 30-31, 59) are not implemented; hold the clamped rows fixed");
         SHELL_CHECK(mat->young > 0 && mat->thickness > 0 && mat->density >= 0 && mat->poisson > -1.0 &&
                         mat->poisson < 1.0,
                     SHELL_E_INVALID_ARG, "material out of range");
@@ -125,7 +123,7 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         st->density = mat->density;
         st->kb = mat->young * std::pow(mat->thickness, 3) / (12.0 * (1.0 - mat->poisson * mat->poisson));
 
-        HostTopology topo = build_topology(model, nv, nt, tris);
+        HostTopology topo = build_topology(model, nv, nt, tris, n_clamped, clamped_edges);
         const int k = st->k, r = st->r;
         st->ns = topo.ns;
         st->perm = vertex_order(X, nv, reorder, T);
@@ -140,8 +138,13 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
             return iid(topo.idx[size_t(k * a)]) < iid(topo.idx[size_t(k * b)]);
         });
         st->h_idx.resize(size_t(k * st->ns));
-        for (int64_t q = 0; q < st->ns; ++q)
+        std::vector<int32_t> h_bc(size_t(st->ns));
+        bool any_clamped = false;
+        for (int64_t q = 0; q < st->ns; ++q) {
             for (int j = 0; j < k; ++j) st->h_idx[size_t(k * q + j)] = iid(topo.idx[size_t(k * order[size_t(q)] + j)]);
+            h_bc[size_t(q)] = topo.bc[size_t(order[size_t(q)])];
+            any_clamped = any_clamped || (h_bc[size_t(q)] & kBcClampedAny) != 0;
+        }
         std::vector<double> Xi(size_t(3 * nv));
         for (int64_t i = 0; i < nv; ++i)
             for (int c = 0; c < 3; ++c) Xi[size_t(3 * i + c)] = X[3 * int64_t(st->perm[size_t(i)]) + c];
@@ -167,7 +170,9 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         st->B.alloc(size_t(r * k) * ns);
         st->k0.alloc(size_t(r) * ns);
         st->flags.alloc(ns);
-        launch_precompute(*st, s);
+        DevArray<int32_t> bc_d(ns);
+        bc_d.upload(h_bc.data(), ns, s);
+        launch_precompute(*st, bc_d.p, s);
         std::vector<int32_t> flags(ns);
         st->flags.download(flags.data(), ns, s);
         SHELL_HIP(hipStreamSynchronize(s));
@@ -192,7 +197,8 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
             st->tidx.alloc(size_t(4 * stream_chunks(k, 4)) * nst);
             st->trec64.alloc(size_t(2 * stream_chunks(rec64_fields(k, r), 2)) * nst);
         }
-        launch_tile_copy(*st, s);
+        launch_tile_copy(*st, bc_d.p, s);
+        if (any_clamped && precision == SHELL_PREC_FP64 && !model_is_shell(model)) launch_clamp_bias(*st, bc_d.p, s);
         st->epart.alloc(size_t(st->nblocks));
         SHELL_HIP(hipStreamSynchronize(s));
         *out = st.release();
@@ -259,6 +265,7 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
             d.x = st->xin.p;
             d.f = st->fout.p;
             d.epart = st->epart.p;
+            d.bias = st->bias.p;
             d.boff = st->boff.p;
             d.tidx = st->tidx.p;
             d.trec = f32 ? static_cast<const void*>(st->trec32.p) : static_cast<const void*>(st->trec64.p);
@@ -288,7 +295,7 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
             if (st->nv == 0)
                 SHELL_HIP(hipMemsetAsync(energy, 0, sizeof(double), s));
             else
-                launch_energy_finalize(st->epart.p, st->nblocks, energy, s);
+                launch_energy_finalize(st->epart.p, st->nblocks, st->bias_e0, energy, s);
         }
         return SHELL_OK;
     });

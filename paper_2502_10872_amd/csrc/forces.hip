@@ -307,7 +307,22 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
     }
     __syncthreads();
     gbl<R>* out = G(static_cast<R*>(d.f)) + 3 * base;
-    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
+    if constexpr (!REL) {
+        if (d.bias) {
+            // plates with clamped edges: the constant force and energy terms that make the clamped
+            // stencils rest-relative, f + F0 and E - F0 . x (+ E0 once, when the partials are summed)
+            const gbl<const double>* b = G(d.bias) + 3 * base;
+            for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) {
+                const double bi = b[i];
+                out[i] = acc[i] + bi;
+                e_own -= bi * x[3 * base + i];
+            }
+        } else {
+            for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
+        }
+    } else {
+        for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
+    }
     if (d.epart) {
         __shared__ double sh[kMaxForceThreads / 64];
         double v[1] = {e_own};
@@ -350,13 +365,13 @@ void launch_model(int precision, const ForceDesc* descs, const WorkItem* items, 
     SHELL_HIP(hipGetLastError());
 }
 
-__global__ void energy_finalize(const double* __restrict__ part, long n, double* __restrict__ out) {
+__global__ void energy_finalize(const double* __restrict__ part, long n, double add, double* __restrict__ out) {
     __shared__ double sh[16];
     double acc = 0.0;
     for (long i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
     double v[1] = {acc};
     block_sum<1>(v, sh);
-    if (threadIdx.x == 0) *out = v[0];
+    if (threadIdx.x == 0) *out = v[0] + add;
 }
 
 // dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order displacements from the rest
@@ -407,8 +422,8 @@ void launch_force_items(int model, int precision, const ForceDesc* descs, const 
     }
 }
 
-void launch_energy_finalize(const double* epart, int64_t n, double* energy, hipStream_t s) {
-    energy_finalize<<<1, 256, 0, s>>>(epart, n, energy);
+void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s) {
+    energy_finalize<<<1, 256, 0, s>>>(epart, n, add, energy);
     SHELL_HIP(hipGetLastError());
 }
 

@@ -32,7 +32,8 @@ void parallel_for(int64_t n, F&& fn) {
 
 }  // namespace
 
-HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tris) {
+HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t n_clamped,
+                            const int32_t* clamped) {
     HostTopology topo;
     topo.model = model;
     topo.k = model_k(model);
@@ -62,6 +63,19 @@ HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tr
                         fan ? "edge shared by more than two triangles" : "inconsistently oriented triangles");
         }
     }
+    // clamped edges as undirected keys; each must be traversed by exactly one triangle
+    std::vector<uint64_t> ckeys(static_cast<size_t>(n_clamped));
+    for (int64_t e = 0; e < n_clamped; ++e) {
+        const int32_t u = clamped[2 * e], v = clamped[2 * e + 1];
+        SHELL_CHECK(u >= 0 && u < nv && v >= 0 && v < nv, SHELL_E_INVALID_ARG, "clamped edge vertex out of range");
+        SHELL_CHECK((find(u, v) != nullptr) + (find(v, u) != nullptr) == 1, SHELL_E_INVALID_ARG,
+                    "a clamped edge is not a boundary edge of the mesh");
+        ckeys[size_t(e)] = dkey(std::min(u, v), std::max(u, v));
+    }
+    std::sort(ckeys.begin(), ckeys.end());
+    auto is_clamped = [&](int32_t u, int32_t v) {
+        return std::binary_search(ckeys.begin(), ckeys.end(), dkey(std::min(u, v), std::max(u, v)));
+    };
     if (model_is_edge(model)) {
         // one stencil per interior edge; 2->3 is the half-edge with the smaller source id
         for (const auto& h : he) {
@@ -71,20 +85,34 @@ HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tr
             if (!twin) continue;  // boundary edge: free, no stencil
             topo.idx.insert(topo.idx.end(), {h.second, from, to, twin->second});
         }
+        topo.bc.assign(topo.idx.size() / 4, 0);
+        if (!model_is_shell(model) && n_clamped > 0) {
+            // clamped boundary edge of the plate: (L, M, N, virtual), M->N as its triangle traverses it
+            for (const auto& h : he) {
+                int32_t from = int32_t(h.first >> 32), to = int32_t(h.first & 0xffffffffu);
+                if (find(to, from) || !is_clamped(from, to)) continue;
+                topo.idx.insert(topo.idx.end(), {h.second, from, to, -1});
+                topo.bc.push_back(kBcEdgeClamped);
+            }
+        }
         topo.ns = int64_t(topo.idx.size() / 4);
     } else {
         topo.ns = nt;
         topo.idx.resize(size_t(6 * nt));
+        topo.bc.assign(size_t(nt), 0);
         for (int64_t t = 0; t < nt; ++t) {
             const int32_t* v = tris + 3 * t;
             int32_t* s = topo.idx.data() + 6 * t;
             s[0] = v[0];
             s[1] = v[1];
             s[2] = v[2];
+            int32_t bits = 0;
             for (int i = 0; i < 3; ++i) {
                 const auto* nb = find(v[(i + 2) % 3], v[(i + 1) % 3]);
                 s[3 + i] = nb ? nb->second : -1;
+                if (!nb) bits |= (1 << i) | (is_clamped(v[(i + 1) % 3], v[(i + 2) % 3]) ? 1 << (3 + i) : 0);
             }
+            topo.bc[size_t(t)] = bits;
         }
     }
     return topo;

@@ -73,13 +73,23 @@ inline int model_r(int m) { return model_is_edge(m) ? 1 : 3; }
 
 // ------------------------------------------------------------------ host mesh processing (host_mesh.cpp)
 
+// Boundary bits of a stencil.  Triangle stencils: bit L, flap L+3 missing; bit 3+L, that flap's edge
+// clamped.  Edge stencils: kBcEdgeClamped, the stencil (L, M, N, -1) of a clamped boundary edge.
+constexpr int32_t kBcEdgeClamped = 1 << 6;
+constexpr int32_t kBcClampedAny = (7 << 3) | kBcEdgeClamped;
+
 struct HostTopology {
     int model = 0, k = 4;
     int64_t ns = 0;
-    std::vector<int32_t> idx;  // [ns][k] caller ids, -1 = missing flap
+    std::vector<int32_t> idx;  // [ns][k] caller ids, -1 = missing flap (or the clamped edge's virtual node)
+    std::vector<int32_t> bc;   // [ns] boundary bits
 };
-// Validates the triangle mesh and enumerates the model's stencils.
-HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tris);
+// Validates the triangle mesh and enumerates the model's stencils.  clamped [n_clamped][2]: boundary edges
+// with the clamped condition (eqs 30-31, 59); a pair that is not a boundary edge is an argument error.
+// The edge plate gets one stencil per clamped edge; the edge shell none (measured along its own
+// triangle's normal, the folded stencil's transverse displacements all vanish).
+HostTopology build_topology(int model, int64_t nv, int64_t nt, const int32_t* tris, int64_t n_clamped,
+                            const int32_t* clamped);
 
 // Vertex order: perm[internal] = caller id.  mode 0: the caller's order; 1: recursive coordinate
 // bisection into tiles of T vertices (Morton inside a tile); 2: Morton order of the rest positions.
@@ -144,6 +154,7 @@ struct ForceDesc {
     const double* x;       // FP64: positions [nv][3]; mixed: displacements from the rest shape [nv][4]
     void* f;               // double or float [nv][3]
     double* epart;         // per-tile energy, or null
+    const double* bias;    // FP64 plates with clamped edges: constant force [nv][3] added to f, or null
     const int64_t* boff;   // [2 tiles]: start and end of each tile's stencil list
     const int32_t* tidx;   // FP64: vertex id stream
     const void* trec;      // mixed: the 32-bit record stream; FP64: the operator and rest-curvature stream
@@ -213,6 +224,10 @@ struct shell_stencils_s {
     shell::DevArray<double> B;           // SoA [r*k][ns], scaled by sqrt(stiffness)
     shell::DevArray<double> k0;          // SoA [r][ns]
     shell::DevArray<int32_t> flags;      // [ns]
+    // FP64 plates with clamped edges: F0 = -(force of the clamped stencils at the rest shape) [nv][3] and
+    // E0 = their energy there, which turn the plain plate force and energy into rest-relative ones
+    shell::DevArray<double> bias;
+    double bias_e0 = 0.0;
     shell::DevArray<int64_t> boff;       // [2 nblocks] start, end
     shell::DevArray<int32_t> tsrc;       // [nst_pad]
     // tiled streams, only those of the configured precision: [nst_pad / 64][chunks][64][fields per chunk]
@@ -334,14 +349,18 @@ struct shell_batch_s {
 
 namespace shell {
 // precompute.hip
-void launch_precompute(shell_stencils_s& st, hipStream_t s);
-void launch_tile_copy(shell_stencils_s& st, hipStream_t s);
+// bc: device [ns] boundary bits of the stencils (internal order)
+void launch_precompute(shell_stencils_s& st, const int32_t* bc, hipStream_t s);
+void launch_tile_copy(shell_stencils_s& st, const int32_t* bc, hipStream_t s);
+// FP64 plates: st.bias and st.bias_e0 from the clamped stencils (synchronises s)
+void launch_clamp_bias(shell_stencils_s& st, const int32_t* bc, hipStream_t s);
 // forces.hip
 // one launch per model over a list of (mesh, tile) items; lds_T = the largest tile among the meshes
 // start/stop: events that receive the kernel's own begin and end times (null: none)
 void launch_force_items(int model, int precision, const ForceDesc* descs, const WorkItem* items, long nitems,
                         int lds_T, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
-void launch_energy_finalize(const double* epart, int64_t n, double* energy, hipStream_t s);
+// energy = add + sum of the n partials
+void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
 // dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order padded displacements
 void launch_gather_displacements(const double* src, const int32_t* perm, const double* X, double* dst, int64_t nv,

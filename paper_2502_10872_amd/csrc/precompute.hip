@@ -3,14 +3,21 @@
 // Edge hinge (Sec. 4.3): rest normal on the bisector of the two triangle normals, stencil projected
 // onto its tangent plane (the corotational stencil), signed feet ratios and heights of vertices 1
 // and 4 over the hinge 2->3, L_m = 2 L_theta/(h1 + h4) (eqs 7, 9-10), rest curvature
-// kappa0 = L_m N0^T X (eq 14).  Scaled by sqrt(k_b A_E), A_E the two rest triangle areas (eq 16).
+// kappa0 = L_m N0^T X (eq 14).  Scaled by sqrt(k_b A_E), A_E the two rest triangle areas (eq 16).  A
+// clamped boundary edge's stencil (L, M, N, L') takes L' as the reflection of L through the edge's
+// midpoint, folds L's column onto L (eqs 30-31) and weighs its one real triangle.
 //
 // Triangle stencil (Secs 4.4-4.5, App. A/C): rest frame at X1 with x along X12 and z the triangle
 // normal (eq 65); the six points in that plane; a missing flap replaced by the reflection of its
 // tip through the boundary edge's midpoint; L_p = H L_theta row by row (eqs 76-78); FVM: R from the
 // in-plane edge normals (eq 38), B = R L_p; smoothed: C_p = [X^2/2, Y^2/2, XY/2] per point (eq 49),
-// B = (L_p C_p)^-1 L_p (eq 50); free fold w_L' = w_M + w_N - w_L on B's columns (eqs 60-61); FVM
-// free edge: twist dropped in the edge's frame; kappa0 = B N0^T X (eqs 43, 51).  Scaled by sqrt(A).
+// B = (L_p C_p)^-1 L_p (eq 50); folds on B's columns, free w_L' = w_M + w_N - w_L (eqs 60-61), clamped
+// w_L' = w_L (eq 59); FVM free edge: twist dropped in the edge's frame (clamped edges keep it);
+// kappa0 = B N0^T X (eqs 43, 51).  Scaled by sqrt(A).
+//
+// Plate stencils with a clamped edge measure their curvature vectors from the rest shape, the clamped
+// fold not annihilating the flat rest coordinates: the mixed record stores C0 = 0 for them, and FP64
+// adds the constant force F0 = -f(X) of those stencils (clamp_bias).
 #include "devmath.hpp"
 #include "internal.hpp"
 
@@ -21,12 +28,14 @@ namespace {
 constexpr int kFlagDegenerate = 1;
 
 __global__ void precompute_edge(const double* __restrict__ X, const int32_t* __restrict__ idx, long ns,
-                                double kb, int shell_model, int world_frame, double* __restrict__ B,
-                                double* __restrict__ k0, int32_t* __restrict__ flags) {
+                                double kb, int shell_model, int world_frame, const int32_t* __restrict__ bcm,
+                                double* __restrict__ B, double* __restrict__ k0, int32_t* __restrict__ flags) {
     long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (s >= ns) return;
+    const bool clamped = (bcm[s] & kBcEdgeClamped) != 0;
     V3<double> x1 = load3(X, idx[s]), x2 = load3(X, idx[ns + s]), x3 = load3(X, idx[2 * ns + s]),
                x4 = load3(X, idx[3 * ns + s]);
+    if (clamped) x4 = x2 + x3 - x1;  // the virtual node
     V3<double> a = x1 - x2, e = x3 - x2, b = x4 - x2;
     V3<double> ua = cross(e, a);  // (x2-x1) x (x3-x1)
     V3<double> ub = cross(b, e);  // (x3-x4) x (x2-x4)
@@ -47,11 +56,15 @@ __global__ void precompute_edge(const double* __restrict__ X, const int32_t* __r
     double elen = sqrt(ee);
     if (!(h1 > 1e-12 * elen) || !(h4 > 1e-12 * elen)) flag = kFlagDegenerate;
     double c = 2.0 / (h1 + h4);
-    double scale = sqrt(kb * 0.5 * (la + lb));
+    double scale = sqrt(kb * 0.5 * (clamped ? la : la + lb));
     double L1 = scale * c / h1;
     double L2 = -scale * c * ((1.0 - sp) / h1 + (1.0 - sq) / h4);
     double L3 = -scale * c * (sp / h1 + sq / h4);
     double L4 = scale * c / h4;
+    if (clamped) {
+        L1 += L4;
+        L4 = 0.0;
+    }
     B[s] = L1;
     B[ns + s] = L2;
     B[2 * ns + s] = L3;
@@ -86,10 +99,11 @@ __device__ inline double inv3x3(const double (&M)[3][3], double (&Mi)[3][3]) {
 
 __global__ void precompute_tri(const double* __restrict__ X, const int32_t* __restrict__ idx, long ns, int fvm,
                                int shell_model, double* __restrict__ B, double* __restrict__ k0,
-                               int32_t* __restrict__ flags, const int32_t* __restrict__ missing_mask) {
+                               int32_t* __restrict__ flags, const int32_t* __restrict__ bc) {
     long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (s >= ns) return;
-    int miss = missing_mask[s];  // bit L set: flap L+3 absent (its idx points at vertex 1)
+    const int miss = bc[s] & 7;          // bit L set: flap L+3 absent (its idx points at vertex 1)
+    const int clamp = (bc[s] >> 3) & 7;  // bit L set: and its edge clamped
     V3<double> x1 = load3(X, idx[s]);
     V3<double> d[6];
     d[0] = mk(0.0, 0.0, 0.0);
@@ -167,13 +181,18 @@ __global__ void precompute_tri(const double* __restrict__ X, const int32_t* __re
     int first_free = -1;
     for (int L = 0; L < 3; ++L) {
         if (!(miss & (1 << L))) continue;
-        if (first_free < 0) first_free = L;
         int M = (L + 1) % 3, N = (L + 2) % 3, F = L + 3;
+        const bool cl = (clamp >> L) & 1;
+        if (!cl && first_free < 0) first_free = L;
         for (int r = 0; r < 3; ++r) {
             double w = Bm[r][F];
-            Bm[r][M] += w;
-            Bm[r][N] += w;
-            Bm[r][L] -= w;
+            if (cl) {
+                Bm[r][L] += w;
+            } else {
+                Bm[r][M] += w;
+                Bm[r][N] += w;
+                Bm[r][L] -= w;
+            }
             Bm[r][F] = 0.0;
         }
     }
@@ -208,7 +227,7 @@ __global__ void precompute_tri(const double* __restrict__ X, const int32_t* __re
 
 __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_t* __restrict__ idx,
                           const double* __restrict__ B, const double* __restrict__ k0, const double* __restrict__ X,
-                          long ns, int k, int r, bool shell, int32_t* __restrict__ tidx,
+                          const int32_t* __restrict__ bc, long ns, int k, int r, bool shell, int32_t* __restrict__ tidx,
                           double* __restrict__ trec64, float* __restrict__ trec32) {
     long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (e >= nt) return;
@@ -223,9 +242,11 @@ __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_
         for (int j = 0; j < k; ++j) put(j, __int_as_float(s < 0 ? 0 : idx[j * ns + s]));
         for (int q = 0; q < r * k; ++q) put(k + q, s < 0 ? 0.0f : float(B[q * ns + s]));
         for (int q = 0; q < r; ++q) put(k + r * k + q, s < 0 ? 0.0f : float(k0[q * ns + s]));
+        // a clamped plate stencil keeps C0 = 0: its curvature is measured from the rest shape
+        const bool rest_relative = s >= 0 && !shell && (bc[s] & kBcClampedAny) != 0;
         for (int i = 0; i < r; ++i) {
             double c[3] = {0.0, 0.0, 0.0};
-            if (s >= 0) {
+            if (s >= 0 && !rest_relative) {
                 const long o = idx[s];
                 for (int j = 1; j < k; ++j) {
                     const long v = idx[j * ns + s];
@@ -261,40 +282,94 @@ __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_
     }
 }
 
+__global__ void fill_zero(double* __restrict__ p, long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// FP64 plates: the clamped stencils' rest curvature vectors C0_i = sum_j B_ij X_j (on differences from
+// vertex 1; B's rows sum to zero), their force at the rest shape, f_j = -sum_i B_ij (D C0)_i, and energy
+// 1/2 C0 . D C0.  bias accumulates -f (so that f(x) + bias is the force of C = B (x - X)), e0 the energy.
+// D is 1 for the edge operator (k_b A_E is folded into B) and D_b for triangles (A is folded into B).
+__global__ void clamp_bias(const double* __restrict__ X, const int32_t* __restrict__ idx,
+                           const double* __restrict__ B, const int32_t* __restrict__ bc, long ns, int k, int r,
+                           double kb, double nu, double* __restrict__ bias, double* __restrict__ e0) {
+    long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (s >= ns || !(bc[s] & kBcClampedAny)) return;
+    const long o = idx[s];
+    double C[3][3];
+    for (int i = 0; i < r; ++i) {
+        C[i][0] = C[i][1] = C[i][2] = 0.0;
+        for (int j = 1; j < k; ++j) {
+            const long v = idx[j * ns + s];
+            const double b = B[(i * k + j) * ns + s];
+            for (int a = 0; a < 3; ++a) C[i][a] += b * (X[3 * v + a] - X[3 * o + a]);
+        }
+    }
+    double g[3][3];
+    if (r == 1) {
+        for (int a = 0; a < 3; ++a) g[0][a] = C[0][a];
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            g[0][a] = kb * (C[0][a] + nu * C[1][a]);
+            g[1][a] = kb * (nu * C[0][a] + C[1][a]);
+            g[2][a] = kb * 0.5 * (1.0 - nu) * C[2][a];
+        }
+    }
+    double en = 0.0;
+    for (int i = 0; i < r; ++i)
+        for (int a = 0; a < 3; ++a) en += 0.5 * C[i][a] * g[i][a];
+    atomicAdd(e0, en);
+    for (int j = 0; j < k; ++j) {
+        const long v = idx[j * ns + s];
+        for (int a = 0; a < 3; ++a) {
+            double fb = 0.0;
+            for (int i = 0; i < r; ++i) fb += B[(i * k + j) * ns + s] * g[i][a];
+            if (fb != 0.0) atomicAdd(bias + 3 * v + a, fb);
+        }
+    }
+}
+
 }  // namespace
 
-void launch_precompute(shell_stencils_s& st, hipStream_t s) {
+void launch_precompute(shell_stencils_s& st, const int32_t* bc, hipStream_t s) {
     const long ns = st.ns;
     if (ns == 0) return;
     int blk = 256;
     long grid = (ns + blk - 1) / blk;
     if (model_is_edge(st.model)) {
         precompute_edge<<<grid, blk, 0, s>>>(st.X.p, st.idx.p, ns, st.kb, model_is_shell(st.model),
-                                             (st.cfg_flags & SHELL_FLAG_WORLD_FRAME) != 0, st.B.p, st.k0.p,
+                                             (st.cfg_flags & SHELL_FLAG_WORLD_FRAME) != 0, bc, st.B.p, st.k0.p,
                                              st.flags.p);
     } else {
-        std::vector<int32_t> mask(size_t(ns), 0);
-        for (long q = 0; q < ns; ++q)
-            for (int L = 0; L < 3; ++L)
-                if (st.h_idx[size_t(6 * q + 3 + L)] < 0) mask[size_t(q)] |= 1 << L;
-        DevArray<int32_t> md(static_cast<size_t>(ns));
-        md.upload(mask.data(), size_t(ns), s);
         precompute_tri<<<grid, blk, 0, s>>>(st.X.p, st.idx.p, ns, model_is_fvm(st.model), model_is_shell(st.model),
-                                            st.B.p, st.k0.p, st.flags.p, md.p);
-        SHELL_HIP(hipGetLastError());
-        SHELL_HIP(hipStreamSynchronize(s));  // md is released on return
+                                            st.B.p, st.k0.p, st.flags.p, bc);
     }
     SHELL_HIP(hipGetLastError());
 }
 
-void launch_tile_copy(shell_stencils_s& st, hipStream_t s) {
+void launch_tile_copy(shell_stencils_s& st, const int32_t* bc, hipStream_t s) {
     const long nt = st.nst_pad;
     if (nt == 0) return;
     int blk = 256;
-    tile_copy<<<(nt + blk - 1) / blk, blk, 0, s>>>(st.tsrc.p, nt, st.idx.p, st.B.p, st.k0.p, st.X.p, st.ns, st.k,
-                                                   st.r, model_is_shell(st.model), st.tidx.p, st.trec64.p,
+    tile_copy<<<(nt + blk - 1) / blk, blk, 0, s>>>(st.tsrc.p, nt, st.idx.p, st.B.p, st.k0.p, st.X.p, bc, st.ns,
+                                                   st.k, st.r, model_is_shell(st.model), st.tidx.p, st.trec64.p,
                                                    st.trec32.p);
     SHELL_HIP(hipGetLastError());
+}
+
+void launch_clamp_bias(shell_stencils_s& st, const int32_t* bc, hipStream_t s) {
+    const long ns = st.ns;
+    st.bias.alloc(size_t(3 * st.nv));
+    DevArray<double> e0(1);
+    fill_zero<<<int((3 * st.nv + 255) / 256), 256, 0, s>>>(st.bias.p, 3 * st.nv);
+    fill_zero<<<1, 64, 0, s>>>(e0.p, 1);
+    if (ns > 0)
+        clamp_bias<<<int((ns + 255) / 256), 256, 0, s>>>(st.X.p, st.idx.p, st.B.p, bc, ns, st.k, st.r, st.kb,
+                                                         st.poisson, st.bias.p, e0.p);
+    SHELL_HIP(hipGetLastError());
+    e0.download(&st.bias_e0, 1, s);
+    SHELL_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace shell

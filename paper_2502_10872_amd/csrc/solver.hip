@@ -339,6 +339,7 @@ ForceDesc force_desc(shell_sim_s& sim) {
     d.x = f32 ? sim.u4.p : sim.x.p;
     d.f = sim.f.p;
     d.epart = nullptr;
+    d.bias = st.bias.p;
     d.boff = st.boff.p;
     d.tidx = st.tidx.p;
     d.trec = f32 ? static_cast<const void*>(st.trec32.p) : static_cast<const void*>(st.trec64.p);

@@ -411,12 +411,12 @@ class Problem:
     """One mesh with its stencils, constant Hessian and (optionally) a simulation, freed together."""
 
     def __init__(self, mesh, material: dict, model=None, precision=SHELL_PREC_FP64, block_vertices=0, reorder=1,
-                 sim=True, flags=0):
+                 sim=True, flags=0, clamped_edges=None):
         self.mesh = mesh
         self.nv = mesh.nv
         self.model = mesh.model if model is None else model
         self.st = shell_build_stencils(mesh.X, mesh.tris, self.model, material, precision, block_vertices, reorder,
-                                       flags=flags)
+                                       flags=flags, clamped_edges=clamped_edges)
         self.info = shell_stencils_info(self.st)
         self.h = shell_assemble_constant_hessian(self.st)
         self.sim = shell_sim_create(self.st, self.h, mesh.X, None, mesh.pinned) if sim else None

@@ -287,6 +287,75 @@ def test_world_frame_flag_is_rejected_for_triangle_models():
     assert ei.value.status == S.SHELL_E_INVALID_ARG
 
 
+# ------------------------------------------------------------------ clamped boundary operators
+
+
+def _clamp_mesh(model, n=23):
+    """Plates: a flat jittered square; shells: a cylinder patch.  Clamped: the edges on the sides
+    x = 0 and y = 0 (so stencils carry clamped and free flaps, and corners both)."""
+    mesh = I.plate_mesh(n, 1.0, 0.2, 6, model, "clamp_x0") if model.endswith("P") else \
+        I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 6, model, "ends")
+    be = I.boundary_edges(mesh.tris)
+    i, j = be % n, be // n
+    side = ((i[:, 0] == 0) & (i[:, 1] == 0)) | ((j[:, 0] == 0) & (j[:, 1] == 0))
+    return mesh, be[side]
+
+
+@pytest.mark.parametrize("model", I.MODELS)
+def test_clamped_operators_forces_and_hessian_match_oracle(model):
+    """Clamped folds (eqs 30-31, 59): operators, rest curvatures, K_s, forces and energy at a deformed
+    state against the oracle, FP64 (plates rest-relative through the constant clamp force), and mixed
+    forces within the mixed bound."""
+    mesh, cl = _clamp_mesh(model)
+    ost = O.Stencils(model, mesh.X, mesh.tris, MAT["young"], MAT["poisson"], MAT["thickness"], clamped=cl)
+    assert (ost.bc != 0).any() or model == "ES"
+    x = mesh.X + 2e-3 * I.rng(44).standard_normal(mesh.X.shape)
+    f_ref, e_ref = ost.forces(x)
+    with S.Problem(mesh, MAT, model=model, block_vertices=128, sim=False, clamped_edges=cl) as pb:
+        idx, B, k0 = S.shell_stencils_export(pb.st)
+        assert idx.shape == ost.idx.shape
+        kb = MAT["young"] * MAT["thickness"] ** 3 / (12 * (1 - MAT["poisson"] ** 2))
+        scale = np.sqrt(ost.D[:, 0, 0] if model in ("EP", "ES") else ost.D[:, 0, 0] / kb)
+        where = {tuple(r): i for i, r in enumerate(ost.idx.tolist())}
+        order = np.array([where[tuple(r)] for r in idx.tolist()])
+        assert rel(B, (ost.B * scale[:, None, None])[order]) <= 1e-12
+        if model.endswith("S"):
+            assert rel(k0, (ost.kappa0 * scale[:, None])[order]) <= 1e-12
+        rp, col, val = ost.hessian()
+        grp, gcol, gval = S.shell_hessian_export_csr(pb.h, mesh.nv)
+        assert np.array_equal(grp, rp) and np.array_equal(gcol, col)
+        assert rel(gval, val) <= 1e-12
+        f, e = gpu_forces(pb.st, x)
+        assert rel(f, f_ref) <= TOL64
+        assert abs(e - e_ref) <= TOL64 * abs(e_ref)
+        f0, e0 = gpu_forces(pb.st, mesh.X)  # rest: no force, no energy
+        assert np.abs(f0).max() <= 1e-12 * np.abs(f_ref).max() and abs(e0) <= 1e-12 * abs(e_ref)
+    st32 = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, precision=S.SHELL_PREC_MIXED, clamped_edges=cl)
+    try:
+        f32, _ = gpu_forces(st32, x, f32=True)
+        assert rel(f32, f_ref) <= TOL_MIXED_FORCE
+    finally:
+        S.shell_destroy_stencils(st32)
+
+
+@pytest.mark.parametrize("model", ["EP", "SP", "FS"])
+def test_clamped_steps_replay_match_oracle(model):
+    """Three steps of the clamped meshes under gravity, counts replayed, against the oracle (the
+    plates rest-relative, FS keeping its twist on clamped edges)."""
+    mesh, cl = _clamp_mesh(model, 24)
+    ost = O.Stencils(model, mesh.X, mesh.tris, MAT["young"], MAT["poisson"], MAT["thickness"], clamped=cl)
+    osim = O.Sim(ost, MAT, mesh.pinned)
+    with S.Problem(mesh, MAT, model=model, block_vertices=128, clamped_edges=cl) as pb:
+        for _ in range(3):
+            counts, ostats = osim.step(1 / 30, max_newton=2, pcg_rtol=1e-8)
+            params, _keep = S.step_params(1 / 30, max_newton=2, pcg_rtol=1e-8, replay=counts)
+            rc, gstats = S.shell_step_implicit(pb.sim, params)
+            assert gstats["newton_iters"] == ostats["newton_iters"]
+        x, v, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+    assert rel(x - mesh.X, osim.x - mesh.X) <= TOL64
+    assert rel(v, osim.v) <= TOL64
+
+
 @pytest.mark.parametrize("model,n,wg", [("SS", 40, 1), ("FS", 36, 1), ("SS", 46, 2), ("EP", 32, 1)])
 def test_several_row_groups_per_pcg_workgroup(model, n, wg):
     """Few PCG work-groups, each walking several consecutive row groups (the large-mesh launch shape).
@@ -498,14 +567,12 @@ def test_single_and_two_triangle_meshes(model):
             S.shell_destroy_stencils(st)
 
 
-def test_clamped_edges_are_reported_unsupported():
+def test_clamped_edge_that_is_not_a_boundary_edge_is_rejected():
     mesh = I.plate_mesh(8, 1.0, 0.0, 1, "FP")
-    with pytest.raises(S.ShellError) as err:
-        S.shell_build_stencils(mesh.X, mesh.tris, "FP", MAT, clamped_edges=[[0, 1]])
-    assert err.value.status == S.SHELL_E_UNSUPPORTED
-    with pytest.raises(S.ShellError) as err:
-        S.shell_build_stencils(mesh.X, mesh.tris, "FP", MAT, clamped_edges=[[0, mesh.nv]])
-    assert err.value.status == S.SHELL_E_INVALID_ARG
+    for bad in ([[0, mesh.nv]], [[0, 9]], [[0, 63]]):  # out of range, interior diagonal, not an edge
+        with pytest.raises(S.ShellError) as err:
+            S.shell_build_stencils(mesh.X, mesh.tris, "FP", MAT, clamped_edges=bad)
+        assert err.value.status == S.SHELL_E_INVALID_ARG
 
 
 def test_invalid_meshes_are_rejected():
