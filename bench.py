@@ -26,12 +26,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
+def algorithmic_bytes(info: dict, hinfo: dict, precision: int, clamp_bias: bool = False) -> dict:
     """Bytes each kernel must move once (no re-reads, no SELL padding), per launch.
 
     force:  per stencil its k vertex ids, r x k operator, (shells) r rest curvatures and, in mixed
             precision, the r x 3 rest curvature vectors and (shells) the rest differences of the normal;
-            per vertex the position (mixed: displacement from rest) read and the force written.
+            per vertex the position (mixed: displacement from rest) read and the force written; FP64
+            plates with clamped edges also read the constant clamp force per vertex.
     spmv:   (the product kernel, which also forms the new direction p = z + beta p_old) every nonzero's
             value and 16-bit local column id, each row group's distinct-column list, slice widths and
             offsets, and per vertex the direction's inputs (FP64: r and D^-1; mixed: the stored float z)
@@ -44,7 +45,7 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int) -> dict:
     real = 4 if mixed else 8  # stencil operators, matrix values, p, q, z, D^-1, forces
     rest_diffs = (9 if k == 4 else 6) if shell else 0
     per_stencil = 4 * k + real * r * k + (real * r if shell else 0) + (4 * (3 * r + rest_diffs) if mixed else 0)
-    force = ns * per_stencil + nv * (24 + 3 * real)
+    force = ns * per_stencil + nv * (24 + 3 * real) + (nv * 24 if clamp_bias and not mixed else 0)
     ngroups = (nv + 511) // 512  # 512-row groups
     idx = 2 if hinfo["staged"] else 4
     direction_in = 3 * real if mixed else 24 + real
@@ -276,27 +277,30 @@ def stream_copy_gbs(torch):
 def force_models(S, I, torch, precisions, reps=20):
     """Force kernel of every model on a 1024 x 1024 mesh (shells: the sphere cap; plates: a flat square
     of the same side), launched back to back on one state (shell_sim_time_kernels); QTS is the edge shell
-    with the world-frame operator (App. D) on the cap."""
+    with the world-frame operator (App. D) on the cap; EP_clamped and SP_clamped are the plates with every
+    boundary edge clamped (eqs 30-31, 59)."""
     out = {}
     cap = I.workload_sphere_cap(1024, "SS")
     side = cap.meta.get("side", 1.2 * cap.meta["radius"])
-    for model in list(I.MODELS) + ["QTS"]:
-        flags = S.SHELL_FLAG_WORLD_FRAME if model == "QTS" else 0
+    for name in list(I.MODELS) + ["QTS", "EP_clamped", "SP_clamped"]:
+        model = {"QTS": "ES"}.get(name, name.split("_")[0])
+        flags = S.SHELL_FLAG_WORLD_FRAME if name == "QTS" else 0
         if model.endswith("S"):
-            mesh = I.workload_sphere_cap(1024, "ES" if model == "QTS" else model)
+            mesh = I.workload_sphere_cap(1024, model)
         else:
             mesh = I.plate_mesh(1024, side, 0.2, 2502108723, model, "ring")
+        clamped = I.boundary_edges(mesh.tris) if name.endswith("_clamped") else None
         for prec in precisions:
-            pb = S.Problem(mesh, I.MATERIAL, precision=prec, flags=flags)
+            pb = S.Problem(mesh, I.MATERIAL, model=model, precision=prec, flags=flags, clamped_edges=clamped)
             kt = S.shell_sim_time_kernels(pb.sim, 1.0 / 30.0, reps=reps)
             hinfo = S.shell_hessian_info(pb.h)
-            ab = algorithmic_bytes(pb.info, hinfo, prec)
+            ab = algorithmic_bytes(pb.info, hinfo, prec, clamp_bias=clamped is not None)
             ms = kt["force_ms"]
-            out[f"{model}_{'mixed' if prec == S.SHELL_PREC_MIXED else 'fp64'}"] = dict(
+            out[f"{name}_{'mixed' if prec == S.SHELL_PREC_MIXED else 'fp64'}"] = dict(
                 stencils=pb.info["ns"], force_ms=ms, stencils_per_s=pb.info["ns"] / (ms * 1e-3),
                 gbs=ab["force"] / (ms * 1e-3) / 1e9, frac=ab["force"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
             pb.close()
-        print(f"[bench] force timing {model} done", file=sys.stderr, flush=True)
+        print(f"[bench] force timing {name} done", file=sys.stderr, flush=True)
     return out
 
 

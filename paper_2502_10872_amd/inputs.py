@@ -123,8 +123,10 @@ def boundary_edges(tris: np.ndarray) -> np.ndarray:
     t = np.asarray(tris, dtype=np.int64)
     e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
     e.sort(axis=1)
-    u, cnt = np.unique(e, axis=0, return_counts=True)
-    return u[cnt == 1].astype(np.int32)
+    base = int(t.max()) + 1 if len(t) else 1
+    u, cnt = np.unique(e[:, 0] * base + e[:, 1], return_counts=True)
+    u = u[cnt == 1]
+    return np.stack([u // base, u % base], axis=1).astype(np.int32)
 
 
 def random_rotation(g: np.random.Generator) -> np.ndarray:
