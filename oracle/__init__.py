@@ -58,6 +58,7 @@ def lib():
         L.orc_mass.argtypes = [i64, P, i64, P, d, d, P]
         L.orc_apply.argtypes = [i64, P, P, P, P, d, P, P]
         L.orc_step.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, P, P, P, P, d, P, i, d, d, i, P, P, P]
+        L.orc_static.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, P, P, P, d, d, i, d, i, P, P, P]
         L.orc_edge_normal_literal.argtypes = [P, P, P, P, P]
         _lib = L
     return _lib
@@ -195,6 +196,27 @@ class Sim:
             _check(rc, "step")
         return counts, dict(newton_iters=int(stats[0]), pcg_total=int(stats[1]), grad_norm0=stats[2],
                             grad_norm=stats[3], budget_hit=(rc == -5))
+
+
+def solve_static(st: Stencils, pinned, load=None, x0=None, eps_f=1e-3, eps_u=0.0, max_newton=20, pcg_rtol=1e-10,
+                 max_pcg=200000, replay=None):
+    """Quasi-static equilibrium under the applied load (Sec. 5, eq 64); returns (x, counts, stats)."""
+    rowptr, col, val = st.hessian()
+    x = np.array(st.X if x0 is None else x0, dtype=np.float64, copy=True)
+    pin = np.ascontiguousarray(pinned, dtype=np.uint8)
+    F = None if load is None else np.ascontiguousarray(load, dtype=np.float64)
+    counts = np.zeros((max(max_newton, 1), 3), dtype=np.int32)
+    stats = np.zeros(4)
+    rep = None if replay is None else np.ascontiguousarray(replay, dtype=np.int32).reshape(-1, 3)
+    if rep is not None and rep.shape[0] < max_newton:
+        raise ValueError("replay needs one row per Newton iteration")
+    rc = lib().orc_static(st.model, st.nv, st.ns, _p(st.idx), _p(st.B), _p(st.kappa0), _p(st.Crest), _p(st.D),
+                          _p(rowptr), _p(col), _p(val), _p(pin), _p(F), _p(x), eps_f, eps_u, max_newton, pcg_rtol,
+                          max_pcg, _p(rep), _p(counts), _p(stats))
+    if rc not in (0, -5):
+        _check(rc, "static")
+    return x, counts, dict(newton_iters=int(stats[0]), pcg_total=int(stats[1]), resid0=stats[2], resid=stats[3],
+                           budget_hit=(rc == -5))
 
 
 def edge_normal_literal(x1, x2, x3, x4):

@@ -17,7 +17,8 @@
  *   App. A    corotational frames (eq 65), App. B normal gradients (eqs 66-75).
  *   Sec. 5    implicit Euler as the minimiser of the incremental potential
  *             (eqs 62-63) with no contact terms, by Newton against the
- *             constant Hessian of eqs 21/41/53.
+ *             constant Hessian of eqs 21/41/53; quasi-static equilibrium
+ *             (eq 64) by Newton-Raphson with the eps_f / eps_u controls.
  *
  * Readings where the paper is silent or ambiguous (each is also listed in the
  * design notes of the repository):
@@ -876,6 +877,75 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
 
 /* eq 8 as printed: n_c = p/|p| + q/|q| with p = x1 - x_P, q = x4 - x_Q the height vectors
    to the feet on the hinge 2->3 (feet from the current geometry, App. B eqs 70-71) */
+/* Quasi-static equilibrium (Sec. 5, eq 64) by Newton-Raphson in one load step: the residual
+   r = dPsi/dx - F (F the applied load, the bending force f = -dPsi/dx, fixed rows zero) is driven below
+   eps_f; each iteration solves K dx = -r against the constant Hessian (one Jacobi-PCG per coordinate, no
+   mass term) and, when ||dx||_inf exceeds eps_u > 0, scales dx by eps_u/||dx||_inf before x += dx. */
+int orc_static(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
+               const double* Crest, const double* D, const int64_t* rowptr, const int32_t* col, const double* val,
+               const uint8_t* pinned, const double* load, double* x, double eps_f, double eps_u, int max_newton,
+               double pcg_rtol, int max_pcg, const int32_t* replay, int32_t* counts, double* stats) {
+    if (!x || !pinned || max_newton < 0) return ORC_E_ARG;
+    size_t n3 = (size_t)(3 * nv);
+    double* f = (double*)malloc(sizeof(double) * n3);
+    double* r = (double*)malloc(sizeof(double) * n3);
+    double* dx = (double*)malloc(sizeof(double) * n3);
+    double* zero = (double*)calloc((size_t)nv + 1, sizeof(double));
+    double* dinv = (double*)malloc(sizeof(double) * (size_t)nv);
+    double* bcol = (double*)malloc(sizeof(double) * (size_t)nv);
+    double* ycol = (double*)malloc(sizeof(double) * (size_t)nv);
+    /* Jacobi preconditioner of K_s alone */
+    for (int64_t i = 0; i < nv; ++i) {
+        double kii = 0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            if (col[e] == i) kii = val[e];
+        dinv[i] = (pinned[i] || kii == 0.0) ? 0.0 : 1.0 / kii;
+    }
+    int newton = 0, pcg_total = 0, budget_hit = 0;
+    double rn0 = 0, rn = 0;
+    for (int k = 0;; ++k) {
+        orc_forces(model, nv, x, ns, idx, B, kappa0, Crest, D, f, NULL);
+        double s2 = 0;
+        for (int64_t i = 0; i < nv; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double ri = pinned[i] ? 0.0 : -f[3 * i + d] - (load ? load[3 * i + d] : 0.0);
+                r[3 * i + d] = ri;
+                s2 += ri * ri;
+            }
+        rn = sqrt(s2);
+        if (k == 0) rn0 = rn;
+        if (rn == 0.0 || rn < eps_f || k == max_newton) break;
+        for (int d = 0; d < 3; ++d) {
+            for (int64_t i = 0; i < nv; ++i) bcol[i] = -r[3 * i + d];
+            int it = pcg_column(nv, rowptr, col, val, zero, pinned, 1.0, dinv, bcol, ycol, pcg_rtol, max_pcg,
+                                replay ? replay[3 * k + d] : -1, &budget_hit);
+            if (counts) counts[3 * k + d] = it;
+            pcg_total += it;
+            for (int64_t i = 0; i < nv; ++i) dx[3 * i + d] = ycol[i];
+        }
+        /* incremental displacement limit */
+        double dmax = 0;
+        for (size_t i = 0; i < n3; ++i) dmax = fmax(dmax, fabs(dx[i]));
+        double scale = (eps_u > 0.0 && dmax > eps_u) ? eps_u / dmax : 1.0;
+        for (size_t i = 0; i < n3; ++i) x[i] += scale * dx[i];
+        ++newton;
+    }
+    if (stats) {
+        stats[0] = newton;
+        stats[1] = pcg_total;
+        stats[2] = rn0;
+        stats[3] = rn;
+    }
+    free(f);
+    free(r);
+    free(dx);
+    free(zero);
+    free(dinv);
+    free(bcol);
+    free(ycol);
+    return budget_hit ? ORC_E_BUDGET : ORC_OK;
+}
+
 int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3, const double* x4, double* n) {
     double e[3], d1[3], d4[3], p[3], q[3];
     sub3(x3, x2, e);

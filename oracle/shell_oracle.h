@@ -89,6 +89,15 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
 
 /* Normal of an edge stencil by the literal height-vector construction
  * (sum of the unit height vectors of vertices 1 and 4), used only as a cross-check. */
+/* Quasi-static Newton-Raphson (eq 64): x [nv][3] in/out; load [nv][3] the applied force F (may be NULL);
+ * stop when ||dPsi/dx - F|| < eps_f (fixed rows excluded) or after max_newton solves of K dx = -r;
+ * eps_u > 0 caps ||dx||_inf by scaling dx.  replay/counts [max_newton][3] as in orc_step; stats [4] =
+ * (Newton solves, PCG iterations, ||r_0||, ||r||). */
+int orc_static(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
+               const double* Crest, const double* D, const int64_t* rowptr, const int32_t* col, const double* val,
+               const uint8_t* pinned, const double* load, double* x, double eps_f, double eps_u, int max_newton,
+               double pcg_rtol, int max_pcg, const int32_t* replay, int32_t* counts, double* stats);
+
 int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3, const double* x4, double* n);
 
 #endif

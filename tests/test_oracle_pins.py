@@ -720,6 +720,68 @@ def test_edge_shell_emits_no_clamped_stencil_and_bad_pairs_are_rejected():
             O.Stencils("FP", m.X, m.tris, 1.0, 0.3, 1.0, clamped=np.array(bad))
 
 
+# ------------------------------------------------------------------ P14: quasi-static Newton-Raphson (eq 64)
+
+
+def _loaded_plate(model, n, clamp):
+    a, q, E, nu, h = 8.0, 9.81, 2e11, 0.3, 0.01
+    m = I.plate_mesh(n, a, 0.2, 5, model, "ring")
+    st = O.Stencils(model, m.X, m.tris, E, nu, h, clamped=I.boundary_edges(m.tris) if clamp else None)
+    load = np.zeros((m.nv, 3))
+    load[:, 2] = -q * O.mass(m.X, m.tris, 1.0, 1.0)
+    return m, st, load
+
+
+@pytest.mark.parametrize("model,clamp", [("SP", False), ("FP", True), ("EP", True)])
+def test_static_linear_plate_is_one_sparse_solve(model, clamp):
+    """Plates are linear (f = -K (x - X)): the first Newton-Raphson iterate is the sparse direct solution
+    of K w = F on the free vertices, and the residual then meets eps_f with no second solve."""
+    m, st, load = _loaded_plate(model, 17, clamp)
+    x, counts, stats = O.solve_static(st, m.pinned, load, eps_f=1e-6 * np.abs(load).sum(), max_newton=5,
+                                      pcg_rtol=1e-13)
+    rowptr, col, val = st.hessian()
+    K = sp.csr_matrix((val, col, rowptr), shape=(m.nv, m.nv))
+    free = np.where(m.pinned == 0)[0]
+    w = np.zeros(m.nv)
+    w[free] = spl.spsolve(K[free][:, free].tocsc(), load[free, 2])
+    assert stats["newton_iters"] == 1
+    np.testing.assert_allclose(x[:, 2] - m.X[:, 2], w, atol=1e-9 * np.abs(w).max())
+    assert np.abs(x[:, :2] - m.X[:, :2]).max() <= 1e-9 * np.abs(w).max()
+
+
+def test_static_increment_limit_scales_the_newton_step():
+    """eps_u: an increment whose largest entry exceeds eps_u is scaled to exactly eps_u, direction kept."""
+    m, st, load = _loaded_plate("SP", 17, False)
+    full, _, _ = O.solve_static(st, m.pinned, load, eps_f=0.0, max_newton=1, pcg_rtol=1e-13)
+    lim = 0.1 * np.abs(full - m.X).max()
+    x, _, stats = O.solve_static(st, m.pinned, load, eps_f=0.0, eps_u=lim, max_newton=1, pcg_rtol=1e-13)
+    assert abs(np.abs(x - m.X).max() - lim) <= 1e-12 * lim
+    np.testing.assert_allclose(x - m.X, 0.1 * (full - m.X), atol=1e-12 * lim)
+    x3, _, stats3 = O.solve_static(st, m.pinned, load, eps_f=0.0, eps_u=lim, max_newton=3, pcg_rtol=1e-13)
+    assert stats3["newton_iters"] == 3 and stats3["resid"] < stats["resid"]
+
+
+@pytest.mark.parametrize("model", ["ES", "FS", "SS"])
+def test_static_shell_first_iterate_and_second_order_residual(model):
+    """Shells on a flat rest under a transverse load: the constant Hessian is the plate's, so the first
+    Newton-Raphson iterate from the rest shape is the plate's linear solution, and the residual it leaves
+    (the shell's geometric terms) is second order in the load: ten times the load, a hundred times the
+    residual."""
+    plate = {"ES": "EP", "FS": "FP", "SS": "SP"}[model]
+    m = I.plate_mesh(9, 1.0, 0.2, 3, model, "ring")
+    st = O.Stencils(model, m.X, m.tris, 1.0e6, 0.3, 1e-2)
+    pst = O.Stencils(plate, m.X, m.tris, 1.0e6, 0.3, 1e-2)
+    res = []
+    for q in (0.01, 0.1):
+        load = np.zeros((m.nv, 3))
+        load[:, 2] = -q * O.mass(m.X, m.tris, 1.0, 1.0)
+        x, _, stats = O.solve_static(st, m.pinned, load, eps_f=0.0, max_newton=1, pcg_rtol=1e-13)
+        xp, _, _ = O.solve_static(pst, m.pinned, load, eps_f=0.0, max_newton=1, pcg_rtol=1e-13)
+        np.testing.assert_allclose(x, xp, atol=1e-11 * np.abs(xp - m.X).max())
+        res.append(stats["resid"] / stats["resid0"])
+    assert 0.99 < res[1] / res[0] / 10.0 < 1.01
+
+
 # ------------------------------------------------------------------ P9/P10: dynamics
 
 
