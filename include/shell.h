@@ -247,6 +247,36 @@ typedef struct {
 shell_status_t shell_step_implicit(shell_sim_t sim, const shell_step_params_t* params, shell_step_stats_t* stats,
                                    shell_stream_t stream);
 
+/*
+ * shell_solve_static - quasi-static equilibrium (Sec. 5, eq 64) by Newton-Raphson in one load step: from
+ * the simulation's current positions, iterate x += s dx with K dx = -r, r = dPsi/dx - F the residual
+ * force (fixed rows excluded), K = K_s (x) I3 the constant bending Hessian (no mass term), each solve by
+ * the three Jacobi-PCG recurrences of the implicit step; stop when ||r|| < eps_f or after max_newton
+ * solves.  s = eps_u / ||dx||_inf when that is below one (the incremental displacement limit), else 1.
+ * Plates are linear (f = -K (x - X)), so one solve is exact; the bending-only shells' in-plane modes
+ * have no stiffness of their own, so their iteration stalls at a residual of second order in the load.
+ * The velocity and the step counter are not touched.  stats (host, may be NULL) as for the step:
+ * grad_norm0 = ||r|| at the start, grad_norm = at the returned state.  Synchronises `stream`.
+ * Errors: SHELL_E_INVALID_ARG, SHELL_E_BUDGET (a PCG column hit max_pcg; the state is still updated),
+ * SHELL_E_NONFINITE, SHELL_E_HIP.
+ */
+typedef struct {
+    const double* load;    /* host [nv][3] applied force F in caller order, or NULL (no load) */
+    double eps_f;          /* residual force tolerance, >= 0 */
+    double eps_u;          /* incremental displacement limit (max norm), > 0; 0 = no limit */
+    int32_t max_newton;    /* Newton-Raphson solves, 0..SHELL_MAX_NEWTON */
+    int32_t max_pcg;       /* PCG iteration cap per column (tolerance mode) */
+    double pcg_rtol;       /* per column: stop when ||r_pcg|| <= pcg_rtol ||b|| */
+    int32_t mode;          /* shell_pcg_mode_t */
+    int32_t chunk;         /* as in shell_step_params_t */
+    int32_t pcg_workgroups;
+    int32_t flags;         /* 0 or SHELL_STEP_NO_GRAPHS */
+    const int32_t* replay_counts; /* host [max_newton][3], REPLAY only */
+} shell_static_params_t;
+
+shell_status_t shell_solve_static(shell_sim_t sim, const shell_static_params_t* params, shell_step_stats_t* stats,
+                                  shell_stream_t stream);
+
 shell_status_t shell_sim_get_stats(shell_sim_t sim, shell_step_stats_t* out);
 /* host copies in caller order; x, v may be NULL; synchronises the simulation's last stream */
 shell_status_t shell_sim_get_state(shell_sim_t sim, double* x, double* v, int64_t* step);

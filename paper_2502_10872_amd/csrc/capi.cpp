@@ -473,6 +473,63 @@ shell_status_t shell_step_implicit(shell_sim_t sim, const shell_step_params_t* p
     });
 }
 
+shell_status_t shell_solve_static(shell_sim_t sim, const shell_static_params_t* params, shell_step_stats_t* stats,
+                                  shell_stream_t stream) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim && params, SHELL_E_INVALID_ARG, "null argument");
+        const shell_static_params_t& q = *params;
+        SHELL_CHECK(q.eps_f >= 0.0 && std::isfinite(q.eps_f), SHELL_E_INVALID_ARG, "eps_f must be >= 0");
+        SHELL_CHECK(q.eps_u >= 0.0 && std::isfinite(q.eps_u), SHELL_E_INVALID_ARG, "eps_u must be >= 0");
+        shell_step_params_t p{};
+        p.dt = 1.0;  // unused by the quasi-static path
+        p.max_newton = q.max_newton;
+        p.max_pcg = q.max_pcg;
+        p.pcg_rtol = q.pcg_rtol;
+        p.mode = q.mode;
+        p.chunk = q.chunk;
+        p.pcg_workgroups = q.pcg_workgroups;
+        p.flags = q.flags;
+        p.replay_counts = q.replay_counts;
+        check_params(p);
+        hipStream_t s = as_stream(stream);
+        shell_status_t rc = SHELL_OK;
+        StaticMode qs;
+        qs.eps_f = q.eps_f;
+        qs.eps_u = q.eps_u;
+        qs.has_load = q.load != nullptr;
+        const int64_t nv = sim->nv;
+        if (nv > 0) {
+            if (!sim->zmass.p) {
+                sim->zmass.alloc(size_t(nv));
+                SHELL_HIP(hipMemsetAsync(sim->zmass.p, 0, size_t(nv) * sizeof(double), s));
+                sim->ustep.alloc(1);
+            }
+            if (q.load) {
+                for (int64_t i = 0; i < 3 * nv; ++i)
+                    SHELL_CHECK(std::isfinite(q.load[i]), SHELL_E_INVALID_ARG, "non-finite load");
+                // caller order to internal order
+                std::vector<double> h(size_t(3 * nv));
+                const std::vector<int32_t>& perm = sim->st->perm;
+                for (int64_t i = 0; i < nv; ++i)
+                    for (int c = 0; c < 3; ++c) h[size_t(3 * i + c)] = q.load[3 * int64_t(perm[size_t(i)]) + c];
+                if (!sim->fext.p) sim->fext.alloc(size_t(3 * nv));
+                sim->fext.upload(h.data(), h.size(), s);
+                SHELL_HIP(hipStreamSynchronize(s));  // h is released on return
+            }
+            rc = batch_step(*sim->solo, &p, 1, nullptr, s, &qs);
+        } else {
+            sim->stats = shell_step_stats_t{};
+        }
+        if (stats) {
+            SHELL_HIP(hipStreamSynchronize(s));
+            *stats = sim->stats;
+        }
+        if (rc == SHELL_E_BUDGET) g_last_error = "PCG iteration budget exhausted";
+        if (rc == SHELL_E_NONFINITE) g_last_error = "non-finite residual";
+        return rc;
+    });
+}
+
 shell_status_t shell_sim_get_stats(shell_sim_t sim, shell_step_stats_t* out) {
     return guarded([&]() -> shell_status_t {
         SHELL_CHECK(sim && out, SHELL_E_INVALID_ARG, "null argument");

@@ -173,6 +173,9 @@ struct PcgState {
 
 struct SolveDesc {
     double *x, *xhat, *xt, *v, *g, *r;
+    const double* fext;             // quasi-static: the applied load F [nv][3] (internal order), or null
+    double* ustep;                  // quasi-static with an increment limit: the Newton step's scale, or null
+    double eps_u;                   // quasi-static increment limit (max |dx| per Newton iteration)
     void* y;                        // the Newton increment the PCG builds (float in mixed precision)
     double* u4;                     // mixed precision only: x - X padded to [nv][4], the force kernel's input
     const double* X;                // rest positions
@@ -264,7 +267,7 @@ struct shell_sim_s {
     shell_hessian_s* h = nullptr;
     int64_t nv = 0;
     int64_t step = 0;
-    double dinv_dt = -1.0;               // dt the preconditioner was built for
+    double dinv_dt = -1.0;               // dt the preconditioner was built for (0: the quasi-static K alone)
     hipStream_t last_stream = nullptr;
     shell::DevArray<double> x, v, xt, xhat, g, mass, y, r;
     shell::DevArray<double> f;           // float64 forces (or float32 in mixed, sized in doubles)
@@ -276,6 +279,8 @@ struct shell_sim_s {
     shell::DevArray<double> u4;          // mixed only: displacements from the rest shape, [nv][4]
     shell::DevArray<double> bins;        // PCG dot-product bins
     shell::DevArray<double> partials;    // reduction partials
+    // quasi-static solves only: zero mass, the applied load (internal order), the Newton step's scale
+    shell::DevArray<double> zmass, fext, ustep;
     shell_batch_s* solo = nullptr;       // this simulation alone, as a batch of one
     shell_step_stats_t stats{};
 };
@@ -375,8 +380,15 @@ void sim_alloc(shell_sim_s& sim);
 void batch_init(shell_batch_s& b);
 void batch_free_host(shell_batch_s& b);
 void batch_release(shell_batch_s& b);
+// Quasi-static Newton-Raphson (eq 64) in place of a time step: no mass, no predictor motion, the residual
+// dPsi/dx - F with F the simulation's fext (when has_load), stop when ||r|| < eps_f, increments capped at
+// eps_u (> 0) in the max norm; the velocity and the step counter are left alone.
+struct StaticMode {
+    double eps_f = 0.0, eps_u = 0.0;
+    bool has_load = false;
+};
 shell_status_t batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams, shell_step_stats_t* stats,
-                          hipStream_t s);
+                          hipStream_t s, const StaticMode* qs = nullptr);
 void batch_time_kernels(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out, hipStream_t s);
 void sim_mass(shell_sim_s& sim, hipStream_t s);
 }  // namespace shell

@@ -91,7 +91,8 @@ __global__ __launch_bounds__(kBlk) void k_predictor(const SolveDesc* __restrict_
     for (int c = 0; c < 3; ++c) {
         double xi = d.x[3 * i + c];
         d.xt[3 * i + c] = xi;
-        double xh = pin ? xi : xi + d.dt * d.v[3 * i + c] + d.dt * d.dt * d.grav[c];
+        // dt = 0 (the quasi-static solve): x_hat = x without reading the velocity
+        double xh = (pin || d.dt == 0.0) ? xi : xi + d.dt * d.v[3 * i + c] + d.dt * d.dt * d.grav[c];
         d.xhat[3 * i + c] = xh;
         d.x[3 * i + c] = xh;
     }
@@ -105,12 +106,14 @@ __global__ __launch_bounds__(kBlk) void k_dinv(const SolveDesc* __restrict__ des
     long i = long(wi.unit) * kBlk + threadIdx.x;
     if (i >= d.nv) return;
     const bool pin = d.pinned[i];
-    static_cast<VR*>(d.dinv)[i] = pin ? VR(0) : VR(1.0 / (d.mass[i] + d.dt2 * d.kdiag[i]));
+    const double den = d.mass[i] + d.dt2 * d.kdiag[i];  // zero only for a quasi-static row without stiffness
+    static_cast<VR*>(d.dinv)[i] = (pin || den == 0.0) ? VR(0) : VR(1.0 / den);
     // the product reads one value per row for both the mass and the fixed flag
     static_cast<VR*>(d.mq)[i] = pin ? VR(-1) : VR(d.mass[i]);
 }
 
-// g = M (x - x_hat) - dt^2 f, fixed rows zero; partial |g|^2
+// g = M (x - x_hat) - dt^2 (f + F), fixed rows zero (F: the quasi-static load, absent in a time step);
+// partial |g|^2
 template <typename VR>
 __global__ __launch_bounds__(kBlk) void k_residual(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems,
                            int from_xhat) {
@@ -125,7 +128,9 @@ __global__ __launch_bounds__(kBlk) void k_residual(const SolveDesc* __restrict__
         bool pin = d.pinned[i];
         double m = d.mass[i];
         for (int c = 0; c < 3; ++c) {
-            double gi = pin ? 0.0 : m * (d.x[3 * i + c] - xh[3 * i + c]) - d.dt2 * double(f[3 * i + c]);
+            double fi = double(f[3 * i + c]);
+            if (d.fext) fi += d.fext[3 * i + c];
+            double gi = pin ? 0.0 : m * (d.x[3 * i + c] - xh[3 * i + c]) - d.dt2 * fi;
             d.g[3 * i + c] = gi;
             acc[0] += gi * gi;
         }
@@ -651,7 +656,7 @@ __global__ __launch_bounds__(kBlk) void k_displacements(const SolveDesc* __restr
     d.u4[4 * i + 3] = 0.0;
 }
 
-// x += y (Newton update)
+// x += s y (Newton update); s = 1 unless a quasi-static increment limit set it
 template <typename VR>
 __global__ __launch_bounds__(kBlk) void k_newton_update(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
                                 long nitems) {
@@ -661,7 +666,47 @@ __global__ __launch_bounds__(kBlk) void k_newton_update(const SolveDesc* __restr
     long i = long(wi.unit) * kBlk + threadIdx.x;
     if (i >= d.nv) return;
     const VR* y = static_cast<const VR*>(d.y);
-    for (int c = 0; c < 3; ++c) d.x[3 * i + c] += double(y[3 * i + c]);
+    const double sc = d.ustep ? *d.ustep : 1.0;
+    for (int c = 0; c < 3; ++c) d.x[3 * i + c] += sc * double(y[3 * i + c]);
+}
+
+// largest |y| entry of each row group, into the partials
+template <typename VR>
+__global__ __launch_bounds__(kBlk) void k_absmax(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
+                                                 long nitems) {
+    WorkItem wi;
+    if (!work_item(items, nitems, wi)) return;
+    const SolveDesc& d = descs[wi.mesh];
+    long i = long(wi.unit) * kBlk + threadIdx.x;
+    double m = 0.0;
+    if (i < d.nv) {
+        const VR* y = static_cast<const VR*>(d.y);
+        for (int c = 0; c < 3; ++c) m = fmax(m, fabs(double(y[3 * i + c])));
+    }
+    __shared__ double sh[kBlk];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kBlk / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.part[wi.unit] = sh[0];
+}
+
+// incremental displacement limit (eq 64's eps_u): s = eps_u / max|y| when that is below one
+__global__ __launch_bounds__(kRedBlk) void k_fin_step_limit(const SolveDesc* __restrict__ descs,
+                                                            const int32_t* __restrict__ meshes) {
+    const SolveDesc& d = descs[meshes[blockIdx.x]];
+    double m = 0.0;
+    for (long b = threadIdx.x; b < d.ngroups; b += kRedBlk) m = fmax(m, d.part[b]);
+    __shared__ double sh[kRedBlk];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kRedBlk / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && d.ustep) *d.ustep = sh[0] > d.eps_u ? d.eps_u / sh[0] : 1.0;
 }
 
 __global__ __launch_bounds__(kBlk) void k_velocity(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {

@@ -363,7 +363,7 @@ struct MeshStep {
 // one force/residual launch set, then one PCG loop over the meshes that still need a solve.
 template <typename VR, typename MR>
 shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int nparams, shell_step_stats_t* out,
-                         hipStream_t s) {
+                         hipStream_t s, const StaticMode* qs) {
     const int n = int(b.sims.size());
     const int wg = prms[0].pcg_workgroups > 0 ? prms[0].pcg_workgroups : SHELL_PCG_WORKGROUPS;
     const bool graphs = (prms[0].flags & SHELL_STEP_NO_GRAPHS) == 0;
@@ -382,6 +382,17 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
         d.dt = st.prm->dt;
         d.dt2 = d.dt * d.dt;
         for (int c = 0; c < 3; ++c) d.grav[c] = st.prm->gravity[c];
+        if (qs) {
+            // quasi-static: the matrix is K alone and the residual dPsi/dx - F; dt = 0 keeps the predictor
+            // from moving x (x_hat = x)
+            d.dt = 0.0;
+            d.dt2 = 1.0;
+            for (int c = 0; c < 3; ++c) d.grav[c] = 0.0;
+            d.mass = sim.zmass.p;
+            d.fext = qs->has_load ? sim.fext.p : nullptr;
+            d.ustep = qs->eps_u > 0.0 ? sim.ustep.p : nullptr;
+            d.eps_u = qs->eps_u;
+        }
         d.rtol2 = st.prm->pcg_rtol * st.prm->pcg_rtol;
         b.sdesc_host[m] = d;
     }
@@ -390,9 +401,10 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
     for (int m = 0; m < n; ++m) {
         all[size_t(m)] = m;
         shell_sim_s& sim = *b.sims[size_t(m)];
-        if (sim.dinv_dt != ms[size_t(m)].prm->dt) {
+        const double key = b.sdesc_host[m].dt;  // 0 for the quasi-static matrix
+        if (sim.dinv_dt != key) {
             need_dinv.push_back(m);
-            sim.dinv_dt = ms[size_t(m)].prm->dt;
+            sim.dinv_dt = key;
         }
     }
     ItemBuilder ib;
@@ -427,7 +439,11 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
             st.gn = std::sqrt(ps.gsq);
             if (k == 0) st.gn0 = st.gn;
             const shell_step_params_t& p = *st.prm;
-            if (st.gn0 == 0.0 || (k > 0 && st.gn <= p.newton_rtol * st.gn0) || k == p.max_newton) continue;
+            if (qs) {
+                if (st.gn0 == 0.0 || st.gn < qs->eps_f || k == p.max_newton) continue;
+            } else if (st.gn0 == 0.0 || (k > 0 && st.gn <= p.newton_rtol * st.gn0) || k == p.max_newton) {
+                continue;
+            }
             solve.push_back(m);
         }
         if (solve.empty()) break;
@@ -489,14 +505,20 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
             st.stats.newton_iters++;
             next.push_back(m);
         }
+        if (qs && qs->eps_u > 0.0) {
+            k_absmax<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+            k_fin_step_limit<<<L.nmeshes, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
+        }
         k_newton_update<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
         SHELL_HIP(hipGetLastError());
         iterating = next;
     }
-    ib.build(b.sims, all);
-    L = upload(b, ib, s, wg);
-    k_velocity<<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
-    SHELL_HIP(hipGetLastError());
+    if (!qs) {
+        ib.build(b.sims, all);
+        L = upload(b, ib, s, wg);
+        k_velocity<<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        SHELL_HIP(hipGetLastError());
+    }
     shell_status_t worst = SHELL_OK;
     for (int m = 0; m < n; ++m) {
         MeshStep& st = ms[size_t(m)];
@@ -505,7 +527,7 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
         if (st.stats.status == SHELL_OK && st.budget) st.stats.status = SHELL_E_BUDGET;
         shell_sim_s& sim = *b.sims[size_t(m)];
         sim.stats = st.stats;
-        sim.step++;
+        if (!qs) sim.step++;
         sim.last_stream = s;
         if (out) out[m] = st.stats;
         if (st.stats.status == SHELL_E_NONFINITE || (st.stats.status == SHELL_E_BUDGET && worst == SHELL_OK))
@@ -658,11 +680,11 @@ void batch_release(shell_batch_s& b) {
 }
 
 shell_status_t batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams, shell_step_stats_t* stats,
-                          hipStream_t s) {
+                          hipStream_t s, const StaticMode* qs) {
     for (shell_sim_s* sim : b.sims)
         SHELL_CHECK(sim->nv > 0, SHELL_E_INVALID_ARG, "empty simulation in a batch");
-    if (b.precision == SHELL_PREC_MIXED) return step_impl<float, float>(b, p, nparams, stats, s);
-    return step_impl<double, double>(b, p, nparams, stats, s);
+    if (b.precision == SHELL_PREC_MIXED) return step_impl<float, float>(b, p, nparams, stats, s, qs);
+    return step_impl<double, double>(b, p, nparams, stats, s, qs);
 }
 
 void batch_time_kernels(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {

@@ -63,6 +63,13 @@ class shell_step_params_t(ctypes.Structure):
 SHELL_STEP_NO_GRAPHS = 1
 
 
+class shell_static_params_t(ctypes.Structure):
+    _fields_ = [("load", ctypes.c_void_p), ("eps_f", ctypes.c_double), ("eps_u", ctypes.c_double),
+                ("max_newton", ctypes.c_int32), ("max_pcg", ctypes.c_int32), ("pcg_rtol", ctypes.c_double),
+                ("mode", ctypes.c_int32), ("chunk", ctypes.c_int32), ("pcg_workgroups", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("replay_counts", ctypes.c_void_p)]
+
+
 class shell_step_stats_t(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("pcg_total", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("grad_norm0", ctypes.c_double), ("grad_norm", ctypes.c_double),
@@ -91,7 +98,7 @@ class shell_profile_t(ctypes.Structure):
 EXPORTS = ("shell_build_stencils", "shell_stencils_info", "shell_stencils_export", "shell_eval_forces",
            "shell_assemble_constant_hessian", "shell_hessian_export_csr", "shell_hessian_info",
            "shell_hessian_apply", "shell_sim_create",
-           "shell_step_implicit", "shell_sim_get_stats", "shell_sim_get_state", "shell_sim_set_state",
+           "shell_step_implicit", "shell_solve_static", "shell_sim_get_stats", "shell_sim_get_state", "shell_sim_set_state",
            "shell_sim_device_state", "shell_sim_time_kernels", "shell_batch_create", "shell_batch_step",
            "shell_batch_reset", "shell_sim_device_bytes", "shell_batch_profile", "shell_batch_profile_read",
            "shell_sim_profile", "shell_sim_profile_read",
@@ -119,6 +126,7 @@ def lib() -> ctypes.CDLL:
         L.shell_hessian_apply.argtypes = [P, P, d, P, P, P]
         L.shell_sim_create.argtypes = [P, P, P, P, P, P]
         L.shell_step_implicit.argtypes = [P, P, P, P]
+        L.shell_solve_static.argtypes = [P, P, P, P]
         L.shell_sim_get_stats.argtypes = [P, P]
         L.shell_sim_get_state.argtypes = [P, P, P, P]
         L.shell_sim_set_state.argtypes = [P, P, P, i64]
@@ -288,6 +296,36 @@ def shell_step_implicit(sim, params: shell_step_params_t, with_stats=True, strea
     return rc, (stats_dict(stats) if with_stats else None)
 
 
+def shell_solve_static(sim, load=None, eps_f=0.0, eps_u=0.0, max_newton=1, pcg_rtol=1e-10, max_pcg=200000,
+                       replay=None, chunk=0, pcg_workgroups=0, flags=0, stream=None):
+    """Quasi-static Newton-Raphson from the simulation's current state (eq 64).  load: host [nv][3] applied
+    force in caller order, or None.  Returns (status, stats dict); SHELL_E_BUDGET is returned, not raised."""
+    p = shell_static_params_t()
+    F = None if load is None else np.ascontiguousarray(load, dtype=np.float64)
+    p.load = None if F is None else F.ctypes.data
+    p.eps_f = eps_f
+    p.eps_u = eps_u
+    p.max_newton = max_newton
+    p.max_pcg = max_pcg
+    p.pcg_rtol = pcg_rtol
+    p.chunk = chunk
+    p.pcg_workgroups = pcg_workgroups
+    p.flags = flags
+    keep = None
+    if replay is not None:
+        keep = np.ascontiguousarray(replay, dtype=np.int32).reshape(-1, 3)
+        if keep.shape[0] < max_newton:
+            raise ValueError("replay needs one row of counts per Newton iteration")
+        p.mode = SHELL_PCG_REPLAY
+        p.replay_counts = keep.ctypes.data
+    else:
+        p.mode = SHELL_PCG_TOLERANCE
+    stats = shell_step_stats_t()
+    rc = lib().shell_solve_static(sim, ctypes.byref(p), ctypes.byref(stats), _stream(stream))
+    _check(rc, "shell_solve_static", allow=(SHELL_OK, SHELL_E_BUDGET))
+    return rc, stats_dict(stats)
+
+
 def shell_sim_get_stats(sim) -> dict:
     stats = shell_step_stats_t()
     _check(lib().shell_sim_get_stats(sim, ctypes.byref(stats)), "shell_sim_get_stats")
@@ -303,8 +341,9 @@ def shell_sim_get_state(sim, nv: int):
 
 
 def shell_sim_set_state(sim, x, v, step: int):
-    x = np.ascontiguousarray(x, dtype=np.float64)
-    v = np.ascontiguousarray(v, dtype=np.float64)
+    """x, v: host [nv][3] in caller order, or None to keep the current one."""
+    x = None if x is None else np.ascontiguousarray(x, dtype=np.float64)
+    v = None if v is None else np.ascontiguousarray(v, dtype=np.float64)
     _check(lib().shell_sim_set_state(sim, _np_ptr(x), _np_ptr(v), int(step)), "shell_sim_set_state")
 
 

@@ -356,6 +356,82 @@ def test_clamped_steps_replay_match_oracle(model):
     assert rel(v, osim.v) <= TOL64
 
 
+# ------------------------------------------------------------------ quasi-static Newton-Raphson (eq 64)
+
+
+def _static_plate(model, n, clamp, q=9.81):
+    """Square plate of side 8 (the linear benchmark's), jittered, boundary held, uniform transverse load
+    per unit area; clamp: every boundary edge clamped, else simply supported."""
+    m = I.plate_mesh(n, 8.0, 0.2, 5, model, "ring")
+    cl = I.boundary_edges(m.tris) if clamp else None
+    load = np.zeros((m.nv, 3))
+    load[:, 2] = -q * O.mass(m.X, m.tris, 1.0, 1.0)
+    return m, cl, load
+
+
+@pytest.mark.parametrize("model,clamp", [("SP", False), ("FP", True), ("EP", True), ("SS", False)])
+def test_static_linear_plate_matches_oracle(model, clamp):
+    """The linear plate benchmark as one Newton-Raphson solve: replayed PCG counts give the oracle's
+    deflection to 1e-10 (the flat-rest shell SS too: its first iterate is the plate's); in tolerance mode
+    one solve meets eps_f for the plates, which are linear."""
+    m, cl, load = _static_plate(model, 33, clamp)
+    mat = dict(MAT, young=2e11, poisson=0.3, thickness=0.01)
+    ost = O.Stencils(model, m.X, m.tris, mat["young"], mat["poisson"], mat["thickness"], clamped=cl)
+    xo, counts, ostats = O.solve_static(ost, m.pinned, load, eps_f=0.0, max_newton=1, pcg_rtol=1e-12)
+    with S.Problem(m, mat, model=model, block_vertices=128, clamped_edges=cl) as pb:
+        rc, gs = S.shell_solve_static(pb.sim, load, eps_f=0.0, max_newton=1, replay=counts)
+        x, v, step = S.shell_sim_get_state(pb.sim, m.nv)
+        assert gs["newton_iters"] == 1 and step == 0 and np.abs(v).max() == 0.0
+        assert rel(x - m.X, xo - m.X) <= TOL64
+        if model == "SS":
+            return
+        S.shell_sim_set_state(pb.sim, m.X, None, 0)
+        eps_f = 1e-6 * np.linalg.norm(load)
+        rc, gs = S.shell_solve_static(pb.sim, load, eps_f=eps_f, max_newton=4, pcg_rtol=1e-12)
+        x2, _, _ = S.shell_sim_get_state(pb.sim, m.nv)
+        assert rc == S.SHELL_OK and gs["newton_iters"] == 1 and gs["grad_norm"] < eps_f
+        assert rel(x2 - m.X, xo - m.X) <= 1e-9
+
+
+def test_static_increment_limit_and_shell_iterations_match_oracle():
+    """eps_u active for three Newton-Raphson iterations, counts replayed: the smoothed plate and the
+    smoothed shell on a flat rest (whose iterations carry the geometric terms) against the oracle."""
+    for model in ("SP", "SS"):
+        m, cl, load = _static_plate(model, 25, False)
+        mat = dict(MAT, young=2e11, poisson=0.3, thickness=0.01)
+        ost = O.Stencils(model, m.X, m.tris, mat["young"], mat["poisson"], mat["thickness"])
+        full, _, _ = O.solve_static(ost, m.pinned, load, eps_f=0.0, max_newton=1, pcg_rtol=1e-12)
+        lim = 0.4 * np.abs(full - m.X).max()
+        xo, counts, ostats = O.solve_static(ost, m.pinned, load, eps_f=0.0, eps_u=lim, max_newton=3,
+                                            pcg_rtol=1e-12)
+        if model == "SP":  # linear: steps of 0.4, 0.4 and 0.2 of the solution land on it
+            assert np.abs(xo - full).max() <= 1e-9 * lim
+        with S.Problem(m, mat, model=model, block_vertices=128) as pb:
+            rc, gs = S.shell_solve_static(pb.sim, load, eps_f=0.0, eps_u=lim, max_newton=3, replay=counts)
+            x, _, _ = S.shell_sim_get_state(pb.sim, m.nv)
+            assert gs["newton_iters"] == 3
+            assert rel(x - m.X, xo - m.X) <= TOL64
+            assert abs(gs["grad_norm"] - ostats["resid"]) <= 1e-8 * ostats["resid0"]
+
+
+def test_static_mixed_precision_refines_to_the_oracle():
+    """Mixed precision: float PCG solves refined by the float64 residual until eps_f, against the
+    oracle's FP64 solution of the clamped FVM plate.  The float force carries a rounding error of order
+    1e-7 |B||u| against a curvature of order u / a^2, about 1e-4 relative on this 33 x 33 mesh, which
+    bounds what the refinement can reach."""
+    m, cl, load = _static_plate("FP", 33, True)
+    mat = dict(MAT, young=2e11, poisson=0.3, thickness=0.01)
+    ost = O.Stencils("FP", m.X, m.tris, mat["young"], mat["poisson"], mat["thickness"], clamped=cl)
+    xo, _, _ = O.solve_static(ost, m.pinned, load, eps_f=0.0, max_newton=1, pcg_rtol=1e-13)
+    with S.Problem(m, mat, model="FP", precision=S.SHELL_PREC_MIXED, block_vertices=128, clamped_edges=cl) as pb:
+        eps_f = 2e-4 * np.linalg.norm(load)
+        rc, gs = S.shell_solve_static(pb.sim, load, eps_f=eps_f, max_newton=12, pcg_rtol=1e-4)
+        x, _, _ = S.shell_sim_get_state(pb.sim, m.nv)
+        err = rel(x - m.X, xo - m.X)
+        assert rc == S.SHELL_OK and gs["grad_norm"] < eps_f and gs["newton_iters"] > 1, (gs, err)
+        assert err <= 1e-4, (gs, err)
+
+
 @pytest.mark.parametrize("model,n,wg", [("SS", 40, 1), ("FS", 36, 1), ("SS", 46, 2), ("EP", 32, 1)])
 def test_several_row_groups_per_pcg_workgroup(model, n, wg):
     """Few PCG work-groups, each walking several consecutive row groups (the large-mesh launch shape).

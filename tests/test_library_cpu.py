@@ -50,6 +50,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(S.shell_config_t) == 16 and S.shell_config_t.flags.offset == 12
     assert ctypes.sizeof(S.shell_step_stats_t) == 4 * 4 + 2 * 8 + 64 * 3 * 4
     assert ctypes.sizeof(S.shell_step_params_t) == 8 + 24 + 8 + 16 + 8 + 8 + 8
+    assert ctypes.sizeof(S.shell_static_params_t) == 8 + 8 + 8 + 8 + 8 + 16 + 8
+    assert S.shell_static_params_t.pcg_rtol.offset == 32 and S.shell_static_params_t.replay_counts.offset == 56
     assert ctypes.sizeof(S.shell_profile_t) == S.SHELL_NUM_PHASES * (8 + 8)
     assert ctypes.sizeof(S.shell_hessian_info_t) == 5 * 8 + 2 * 4
 
