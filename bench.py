@@ -124,6 +124,65 @@ def cpu_baseline(mesh, material, counts_per_step, newton_per_step, budget_s=30.0
                 seconds=dict(force=t_force, newton_overhead=t_newton, pcg_coord_iter=t_iter))
 
 
+CLAMPED_PLATE_ALPHA = 0.0012653  # clamped square plate, w_max = alpha q a^4 / D (Timoshenko & Woinowsky-Krieger)
+
+
+def static_plate(I, n):
+    """The linear plate benchmark's square (side 8, E = 2e11, nu = 0.3, h = 0.01, load 9.81 per unit area),
+    n x n vertices, jitter 0.2, every boundary edge clamped and held."""
+    m = I.plate_mesh(n, 8.0, 0.2, 5, "SP", "ring")
+    mat = dict(young=2e11, poisson=0.3, thickness=0.01, density=1.0)
+    area = np.zeros(m.nv)
+    t = m.tris
+    a = 0.5 * np.linalg.norm(np.cross(m.X[t[:, 1]] - m.X[t[:, 0]], m.X[t[:, 2]] - m.X[t[:, 0]]), axis=1)
+    for c in range(3):
+        np.add.at(area, t[:, c], a / 3.0)
+    load = np.zeros((m.nv, 3))
+    load[:, 2] = -9.81 * area
+    return m, mat, I.boundary_edges(m.tris), load
+
+
+def quasi_static(S, I, torch, sizes=(65, 257)):
+    """Quasi-static Newton-Raphson (eq 64) on the linear plate benchmark with clamped edges (SP, FP64):
+    one solve to PCG rtol 1e-10 (the plate is linear), timed end to end on the device-resident state;
+    the centre deflection against the classical clamped-plate value."""
+    out = {}
+    for n in sizes:
+        m, mat, cl, load = static_plate(I, n)
+        pb = S.Problem(m, mat, model="SP", clamped_edges=cl)
+        eps_f = 1e-8 * float(np.linalg.norm(load))
+        S.shell_solve_static(pb.sim, load, eps_f=eps_f, max_newton=1, pcg_rtol=1e-10)  # warm-up (graphs)
+        S.shell_sim_set_state(pb.sim, m.X, None, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = S.shell_solve_static(pb.sim, load, eps_f=eps_f, max_newton=2, pcg_rtol=1e-10)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        x, _, _ = S.shell_sim_get_state(pb.sim, m.nv)
+        D = mat["young"] * mat["thickness"] ** 3 / (12 * (1 - mat["poisson"] ** 2))
+        ratio = float(-(x[:, 2] - m.X[:, 2]).min() / (CLAMPED_PLATE_ALPHA * 9.81 * 8.0**4 / D))
+        iters = int(np.max(st["counts"][: st["newton_iters"]].sum(axis=0))) if st["newton_iters"] else 0
+        out[f"SP_clamped_{n}"] = dict(nv=m.nv, newton_iters=st["newton_iters"], pcg_iters=iters, ms=ms,
+                                      us_per_pcg_iteration=ms * 1e3 / max(iters, 1), deflection_ratio=ratio,
+                                      residual_rel=st["grad_norm"] / max(st["grad_norm0"], 1e-300), status=rc)
+        pb.close()
+        print(f"[bench] quasi-static plate {n} done", file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_static(I, n=65):
+    """The oracle's quasi-static solve of the same clamped plate (one Newton-Raphson solve, PCG rtol 1e-10)."""
+    import oracle as O
+
+    m, mat, cl, load = static_plate(I, n)
+    st = O.Stencils("SP", m.X, m.tris, mat["young"], mat["poisson"], mat["thickness"], clamped=cl)
+    t0 = time.perf_counter()
+    _, counts, stats = O.solve_static(st, m.pinned, load, eps_f=1e-8 * float(np.linalg.norm(load)), max_newton=2,
+                                      pcg_rtol=1e-10)
+    return dict(workload=f"SP_clamped_{n}", seconds=time.perf_counter() - t0, pcg_coord_iters=stats["pcg_total"],
+                cores=1)
+
+
 def run_batch64(args):
     """64 meshes (16^2..512^2 vertices, log-uniform, all six models, 1 cm spacing, mixed precision, Newton
     budget 4, PCG rtol 1e-2, dt = 1/60) stepped as one batch, against the same meshes stepped one at a
@@ -349,6 +408,8 @@ def main(argv=None):
     ap.add_argument("--sample-every", type=int, default=16,
                     help="in the timed steps, time every n-th PCG iteration's kernels with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-quasi-static", action="store_true",
+                    help="skip the quasi-static linear plate solves (about 1e5 PCG launches; kept out of profiles)")
     ap.add_argument("--max-pcg", type=int, default=400000, help="PCG iteration cap per coordinate solve")
     ap.add_argument("--workload", choices=("sphere-cap", "batch64"), default="sphere-cap")
     ap.add_argument("--no-force-models", action="store_true",
@@ -483,9 +544,13 @@ def main(argv=None):
         pb_other.close()
     if not args.no_force_models and args.size == 1024:
         out["force_models_isolated"] = force_models(S, I, torch, (S.SHELL_PREC_MIXED, S.SHELL_PREC_FP64))
+        if not args.no_quasi_static:
+            out["quasi_static"] = quasi_static(S, I, torch)
     if not args.no_cpu_baseline and args.size == 1024:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)
+        if not args.no_quasi_static:
+            out["cpu_baseline"]["quasi_static"] = cpu_static(I)
     print(json.dumps(out), flush=True)
 
 
