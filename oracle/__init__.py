@@ -59,6 +59,8 @@ def lib():
         L.orc_apply.argtypes = [i64, P, P, P, P, d, P, P]
         L.orc_step.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, P, P, P, P, d, P, i, d, d, i, P, P, P]
         L.orc_static.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, P, P, P, d, d, i, d, i, P, P, P]
+        L.orc_membrane.argtypes = [i64, P, i64, P, P, d, d, d, P, P]
+        L.orc_membrane_rest_hessian.argtypes = [i64, P, P, d, d, d, P]
         L.orc_edge_normal_literal.argtypes = [P, P, P, P, P]
         _lib = L
     return _lib
@@ -114,6 +116,7 @@ class Stencils:
         self.D = np.zeros((self.ns, self.r, self.r))
         self.Crest = np.zeros((self.ns, self.r, 3))
         self.world_frame = bool(world_frame)
+        self.young, self.poisson, self.thickness = float(young), float(poisson), float(thickness)
         _check(lib().orc_build(self.model, self.nv, _p(self.X), self.ns, _p(self.idx), _p(self.bc), young, poisson,
                                thickness, WORLD_FRAME if world_frame else 0, _p(self.B), _p(self.kappa0),
                                _p(self.D), _p(self.Crest)), "build")
@@ -164,6 +167,24 @@ def apply(csr, mass_v, dt2, p):
     q = np.zeros_like(p)
     _check(lib().orc_apply(p.shape[0], _p(rowptr), _p(col), _p(val), _p(mass_v), dt2, _p(p), _p(q)), "apply")
     return q
+
+
+def membrane_forces(st: Stencils, x):
+    """Membrane force and energy (Sec. 3, eq 1; constant strain triangles, Saint Venant-Kirchhoff)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    f = np.zeros((st.nv, 3))
+    e = ctypes.c_double(0.0)
+    _check(lib().orc_membrane(st.nv, _p(x), st.nt, _p(st.tris), _p(st.X), st.young, st.poisson, st.thickness,
+                              _p(f), ctypes.byref(e)), "membrane")
+    return f, e.value
+
+
+def membrane_rest_hessian(st: Stencils):
+    """Per-triangle membrane Hessian at rest, [nt][9][9] (vertex-major, coordinate-minor)."""
+    K9 = np.zeros((st.nt, 9, 9))
+    _check(lib().orc_membrane_rest_hessian(st.nt, _p(st.tris), _p(st.X), st.young, st.poisson, st.thickness,
+                                           _p(K9)), "membrane hessian")
+    return K9
 
 
 class Sim:

@@ -19,6 +19,8 @@
  *             (eqs 62-63) with no contact terms, by Newton against the
  *             constant Hessian of eqs 21/41/53; quasi-static equilibrium
  *             (eq 64) by Newton-Raphson with the eps_f / eps_u controls.
+ *   Sec. 3    membrane energy (eq 1) on constant strain triangles with the
+ *             Saint Venant-Kirchhoff model and its Hessian at rest.
  *
  * Readings where the paper is silent or ambiguous (each is also listed in the
  * design notes of the repository):
@@ -877,6 +879,107 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
 
 /* eq 8 as printed: n_c = p/|p| + q/|q| with p = x1 - x_P, q = x4 - x_Q the height vectors
    to the feet on the hinge 2->3 (feet from the current geometry, App. B eqs 70-71) */
+/* ------------------------------------------------------ membrane (CST) */
+
+/* Rest frame of a triangle for the constant strain triangle: e1 along X1-X0, e2 = n x e1 in its plane;
+   G = Dm^-1 with Dm the 2x2 matrix of the rest edge vectors X1-X0, X2-X0 in (e1, e2); returns the area. */
+static double cst_frame(const double* X0, const double* X1, const double* X2, double e1[3], double e2[3],
+                        double G[2][2]) {
+    double a[3], b[3], n[3];
+    sub3(X1, X0, a);
+    sub3(X2, X0, b);
+    double twoA = tri_normal(X0, X1, X2, n);
+    double la = norm3(a);
+    scale3(a, 1.0 / la, e1);
+    cross3(n, e1, e2);
+    double Dm[2][2] = {{dot3(a, e1), dot3(b, e1)}, {dot3(a, e2), dot3(b, e2)}};
+    double det = Dm[0][0] * Dm[1][1] - Dm[0][1] * Dm[1][0];
+    G[0][0] = Dm[1][1] / det;
+    G[0][1] = -Dm[0][1] / det;
+    G[1][0] = -Dm[1][0] / det;
+    G[1][1] = Dm[0][0] / det;
+    return 0.5 * twoA;
+}
+
+/* Membrane energy of Sec. 3 (eq 1) on constant strain triangles with the Saint Venant-Kirchhoff model:
+   F = Ds Dm^-1 (Ds the current edge vectors x1-x0, x2-x0), Green strain E = (F^T F - I)/2 in Voigt form
+   [E11, E22, 2 E12], D_m = h E_el with the plane-stress matrix E_el, Psi_m = A/2 eps^T D_m eps per
+   triangle.  The force is -dPsi/dx = -A F S Dm^-T on the edge vectors (S the second Piola-Kirchhoff
+   stress from D_m eps), and minus their sum on vertex 0.  Adds into f; *energy receives the sum. */
+int orc_membrane(int64_t nv, const double* x, int64_t nt, const int32_t* tris, const double* X, double young,
+                 double poisson, double thickness, double* f, double* energy) {
+    if (!x || !tris || !X || !f) return ORC_E_ARG;
+    double c = young * thickness / (1.0 - poisson * poisson);
+    double E = 0.0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t* v = tris + 3 * t;
+        if (v[0] < 0 || v[1] < 0 || v[2] < 0 || v[0] >= nv || v[1] >= nv || v[2] >= nv) return ORC_E_ARG;
+        double e1[3], e2[3], G[2][2];
+        double A = cst_frame(X + 3 * v[0], X + 3 * v[1], X + 3 * v[2], e1, e2, G);
+        if (!(A > 0)) return ORC_E_DEGENERATE;
+        double d1[3], d2[3], F[3][2];
+        sub3(x + 3 * v[1], x + 3 * v[0], d1);
+        sub3(x + 3 * v[2], x + 3 * v[0], d2);
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 2; ++b) F[i][b] = d1[i] * G[0][b] + d2[i] * G[1][b];
+        double C[2][2];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) C[a][b] = F[0][a] * F[0][b] + F[1][a] * F[1][b] + F[2][a] * F[2][b];
+        double eps[3] = {0.5 * (C[0][0] - 1.0), 0.5 * (C[1][1] - 1.0), C[0][1]};
+        double sig[3] = {c * (eps[0] + poisson * eps[1]), c * (poisson * eps[0] + eps[1]),
+                         c * 0.5 * (1.0 - poisson) * eps[2]};
+        E += 0.5 * A * (eps[0] * sig[0] + eps[1] * sig[1] + eps[2] * sig[2]);
+        double S[2][2] = {{sig[0], sig[2]}, {sig[2], sig[1]}};
+        /* P = A F S, then dPsi/dDs = P G^T */
+        double P[3][2], H[3][2];
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 2; ++b) P[i][b] = A * (F[i][0] * S[0][b] + F[i][1] * S[1][b]);
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 2; ++k) H[i][k] = P[i][0] * G[k][0] + P[i][1] * G[k][1];
+        for (int i = 0; i < 3; ++i) {
+            f[3 * v[1] + i] -= H[i][0];
+            f[3 * v[2] + i] -= H[i][1];
+            f[3 * v[0] + i] += H[i][0] + H[i][1];
+        }
+    }
+    if (energy) *energy = E;
+    return ORC_OK;
+}
+
+/* Hessian of the membrane energy at the rest shape, per triangle: K = A B^T D_m B (9x9, vertex-major,
+   coordinate-minor), B the linear strain of the rest frame, rows [g_j0 e1^T], [g_j1 e2^T],
+   [g_j1 e1^T + g_j0 e2^T] for vertex j with shape-function gradient g_j (the stress vanishes at rest, so
+   this is the whole Hessian there). */
+int orc_membrane_rest_hessian(int64_t nt, const int32_t* tris, const double* X, double young, double poisson,
+                              double thickness, double* K9) {
+    if (!tris || !X || !K9) return ORC_E_ARG;
+    double c = young * thickness / (1.0 - poisson * poisson);
+    double Dm[3][3] = {{c, c * poisson, 0}, {c * poisson, c, 0}, {0, 0, c * 0.5 * (1.0 - poisson)}};
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t* v = tris + 3 * t;
+        double e1[3], e2[3], G[2][2];
+        double A = cst_frame(X + 3 * v[0], X + 3 * v[1], X + 3 * v[2], e1, e2, G);
+        if (!(A > 0)) return ORC_E_DEGENERATE;
+        double g[3][2] = {{-G[0][0] - G[1][0], -G[0][1] - G[1][1]}, {G[0][0], G[0][1]}, {G[1][0], G[1][1]}};
+        double B[3][9];
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                B[0][3 * j + i] = g[j][0] * e1[i];
+                B[1][3 * j + i] = g[j][1] * e2[i];
+                B[2][3 * j + i] = g[j][1] * e1[i] + g[j][0] * e2[i];
+            }
+        double* K = K9 + 81 * t;
+        for (int p = 0; p < 9; ++p)
+            for (int q = 0; q < 9; ++q) {
+                double acc = 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) acc += B[a][p] * Dm[a][b] * B[b][q];
+                K[9 * p + q] = A * acc;
+            }
+    }
+    return ORC_OK;
+}
+
 /* Quasi-static equilibrium (Sec. 5, eq 64) by Newton-Raphson in one load step: the residual
    r = dPsi/dx - F (F the applied load, the bending force f = -dPsi/dx, fixed rows zero) is driven below
    eps_f; each iteration solves K dx = -r against the constant Hessian (one Jacobi-PCG per coordinate, no

@@ -98,6 +98,13 @@ int orc_static(int model, int64_t nv, int64_t ns, const int32_t* idx, const doub
                const uint8_t* pinned, const double* load, double* x, double eps_f, double eps_u, int max_newton,
                double pcg_rtol, int max_pcg, const int32_t* replay, int32_t* counts, double* stats);
 
+/* Membrane (Sec. 3, eq 1): constant strain triangles, Saint Venant-Kirchhoff, D_m = h E_el.
+ * orc_membrane adds the force into f [nv][3] and returns the energy; orc_membrane_rest_hessian writes
+ * the rest Hessian per triangle, K9 [nt][9][9] (vertex-major, coordinate-minor). */
+int orc_membrane(int64_t nv, const double* x, int64_t nt, const int32_t* tris, const double* X, double young,
+                 double poisson, double thickness, double* f, double* energy);
+int orc_membrane_rest_hessian(int64_t nt, const int32_t* tris, const double* X, double young, double poisson,
+                              double thickness, double* K9);
 int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3, const double* x4, double* n);
 
 #endif

@@ -782,6 +782,76 @@ def test_static_shell_first_iterate_and_second_order_residual(model):
     assert 0.99 < res[1] / res[0] / 10.0 < 1.01
 
 
+# ------------------------------------------------------------------ P15: membrane (Sec. 3, eq 1)
+
+
+def test_membrane_patch_test_closed_form():
+    """A uniform in-plane deformation F of a jittered flat mesh: the Green strain E = (F^T F - I)/2 is the
+    same on every triangle, so the energy is the total area times (h/2) eps^T E_el eps, and the interior
+    vertices carry no force (constant stress is in equilibrium)."""
+    E, nu, h = 2.0e5, 0.3, 0.02
+    m = I.plate_mesh(9, 1.0, 0.2, 4, "FP", "none")
+    st = O.Stencils("FP", m.X, m.tris, E, nu, h)
+    F = np.array([[1.03, 0.02], [-0.01, 0.98]])
+    x = m.X.copy()
+    x[:, :2] = m.X[:, :2] @ F.T
+    f, e = O.membrane_forces(st, x)
+    G = 0.5 * (F.T @ F - np.eye(2))
+    eps = np.array([G[0, 0], G[1, 1], 2 * G[0, 1]])
+    c = E * h / (1 - nu * nu)
+    Dm = c * np.array([[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu) / 2]])
+    assert abs(e - 0.5 * 1.0 * eps @ Dm @ eps) <= 1e-12 * e
+    interior = ~I.grid_boundary_mask(9, 9)
+    assert np.abs(f[interior]).max() <= 1e-10 * np.abs(f).max()
+
+
+def test_membrane_invariants_and_gradient():
+    """Curved rest: no force or energy at rest and under rigid motions; the force is minus the energy
+    gradient (central differences)."""
+    m = rest_mesh("SS", n=8)
+    st = O.Stencils("SS", m.X, m.tris, 1.0e6, 0.3, 1e-2)
+    g = I.rng(61)
+    f0, e0 = O.membrane_forces(st, m.X)
+    x = m.X + 1e-2 * g.standard_normal(m.X.shape)
+    f, e = O.membrane_forces(st, x)
+    assert np.abs(f0).max() <= 1e-12 * np.abs(f).max() and e0 <= 1e-24 * e
+    Q = I.random_rotation(g)
+    fr, er = O.membrane_forces(st, m.X @ Q.T + g.standard_normal(3))
+    assert np.abs(fr).max() <= 1e-11 * np.abs(f).max()
+    fx, ex = O.membrane_forces(st, x @ Q.T)
+    assert np.abs(fx - f @ Q.T).max() <= 1e-11 * np.abs(f).max() and abs(ex - e) <= 1e-12 * e
+    for _ in range(3):
+        d = g.standard_normal(x.shape)
+        hh = 1e-6
+        es = [O.membrane_forces(st, x + t * hh * d)[1] for t in (-2, -1, 1, 2)]
+        fd = (es[0] - 8 * es[1] + 8 * es[2] - es[3]) / (12 * hh)
+        assert abs(fd + (f * d).sum()) <= 1e-7 * abs((f * d).sum())
+
+
+def test_membrane_rest_hessian_is_the_force_jacobian_at_rest():
+    """K_m at rest equals minus the central-difference Jacobian of the membrane force there; each
+    triangle's 9x9 block is symmetric PSD of rank 3 (three strain components)."""
+    m = rest_mesh("FS", n=5)
+    st = O.Stencils("FS", m.X, m.tris, 1.0e6, 0.3, 1e-2)
+    K9 = O.membrane_rest_hessian(st)
+    nv = m.nv
+    K = np.zeros((3 * nv, 3 * nv))
+    for t, tv in enumerate(st.tris):
+        ii = np.array([3 * tv[j] + c for j in range(3) for c in range(3)])
+        K[np.ix_(ii, ii)] += K9[t]
+    g = I.rng(62)
+    for _ in range(3):
+        d = g.standard_normal(3 * nv)
+        hh = 1e-7
+        fp, _ = O.membrane_forces(st, m.X + hh * d.reshape(-1, 3))
+        fm, _ = O.membrane_forces(st, m.X - hh * d.reshape(-1, 3))
+        assert np.abs(-(fp - fm).ravel() / (2 * hh) - K @ d).max() <= 1e-6 * np.abs(K @ d).max()
+    for Kt in K9[:4]:
+        assert np.abs(Kt - Kt.T).max() <= 1e-12 * np.abs(Kt).max()
+        ev = np.linalg.eigvalsh(Kt)
+        assert ev.min() >= -1e-12 * ev.max() and (ev > 1e-9 * ev.max()).sum() == 3
+
+
 # ------------------------------------------------------------------ P9/P10: dynamics
 
 
