@@ -801,6 +801,45 @@ def test_batch_equals_each_mesh_alone(precision):
             pb.close()
 
 
+def test_batch_of_clamped_and_world_frame_meshes_matches_oracle():
+    """One batch of a clamped edge plate and a clamped smoothed plate (each with its own constant clamp
+    force), a world-frame edge shell and a plain smoothed shell, FP64, counts replayed per mesh: every
+    mesh equals the oracle's run of it to 1e-10."""
+    cases = []
+    for model, n in (("EP", 19), ("SP", 23)):
+        mesh, cl = _clamp_mesh(model, n)
+        cases.append((mesh, model, dict(clamped_edges=cl), dict(clamped=cl)))
+    cyl = _qt_mesh("ES", 21)
+    cases.append((cyl, "ES", dict(flags=S.SHELL_FLAG_WORLD_FRAME), dict(world_frame=True)))
+    cap = I.sphere_cap_mesh(27, 0.8, jitter=0.2, seed=7, model="SS")
+    cases.append((cap, "SS", {}, {}))
+    osims, probs = [], []
+    try:
+        for mesh, model, gkw, okw in cases:
+            ost = O.Stencils(model, mesh.X, mesh.tris, MAT["young"], MAT["poisson"], MAT["thickness"], **okw)
+            osims.append(O.Sim(ost, MAT, mesh.pinned))
+            probs.append(S.Problem(mesh, MAT, model=model, block_vertices=128, **gkw))
+        batch = S.shell_batch_create([pb.sim for pb in probs])
+        try:
+            for _ in range(2):
+                plist, keep = [], []
+                for osim in osims:
+                    counts, ost = osim.step(1 / 30, max_newton=2, pcg_rtol=1e-8)
+                    p, kp = S.step_params(1 / 30, max_newton=ost["newton_iters"], pcg_rtol=1e-8, replay=counts)
+                    plist.append(p)
+                    keep.append(kp)
+                S.shell_batch_step(batch, plist, len(plist))
+        finally:
+            S.shell_destroy_batch(batch)
+        for (mesh, model, _, _), osim, pb in zip(cases, osims, probs):
+            x, v, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+            assert rel(x - mesh.X, osim.x - mesh.X) <= TOL64, model
+            assert rel(v, osim.v) <= TOL64, model
+    finally:
+        for pb in probs:
+            pb.close()
+
+
 def test_batch_replay_matches_oracle_per_mesh():
     """A batch of all six models, per-mesh parameters and replayed counts, against the oracle."""
     meshes = _batch_meshes()
