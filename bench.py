@@ -170,6 +170,53 @@ def quasi_static(S, I, torch, sizes=(65, 257)):
     return out
 
 
+def navier_rectangle(a, b, nterm=199):
+    """Navier's series for the centre deflection of a simply supported a x b plate, w = alpha q / D."""
+    s = 0.0
+    for mm in range(1, nterm, 2):
+        for nn in range(1, nterm, 2):
+            s += (-1) ** ((mm + nn) // 2 - 1) / (mm * nn * (mm * mm / a**2 + nn * nn / b**2) ** 2)
+    return 16.0 / np.pi**6 * s
+
+
+def linear_plate_sweep(S, I, torch, n=65):
+    """The linear plate benchmark (simply supported, side 8, the benchmark's material and load) for the
+    three plate models on the equilateral, regular and irregular (jitter 0.2) meshes of about n vertices a
+    side, each one quasi-static solve on the GPU (FP64, PCG rtol 1e-10): centre deflection over Navier's
+    value for the plate's sides, and the time."""
+    mat = dict(young=2e11, poisson=0.3, thickness=0.01, density=1.0)
+    D = mat["young"] * mat["thickness"] ** 3 / (12 * (1 - mat["poisson"] ** 2))
+    out = {}
+    for mesh_kind in ("equilateral", "regular", "irregular"):
+        for model in ("EP", "FP", "SP"):
+            if mesh_kind == "equilateral":
+                m = I.equilateral_plate(n, 8.0, model)
+                b = m.meta["height"]
+            else:
+                m = I.plate_mesh(n, 8.0, 0.2 if mesh_kind == "irregular" else 0.0, 5, model, "ring")
+                b = 8.0
+            area = np.zeros(m.nv)
+            t = m.tris
+            a3 = 0.5 * np.linalg.norm(np.cross(m.X[t[:, 1]] - m.X[t[:, 0]], m.X[t[:, 2]] - m.X[t[:, 0]]), axis=1)
+            for c in range(3):
+                np.add.at(area, t[:, c], a3 / 3.0)
+            load = np.zeros((m.nv, 3))
+            load[:, 2] = -9.81 * area
+            pb = S.Problem(m, mat, model=model)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = S.shell_solve_static(pb.sim, load, eps_f=1e-8 * float(np.linalg.norm(load)), max_newton=2,
+                                          pcg_rtol=1e-10)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            x, _, _ = S.shell_sim_get_state(pb.sim, m.nv)
+            pb.close()
+            ratio = float(-(x[:, 2] - m.X[:, 2]).min() / (navier_rectangle(8.0, b) * 9.81 / D))
+            out[f"{model}_{mesh_kind}"] = dict(nv=m.nv, deflection_ratio=ratio, ms=ms, status=rc)
+    print("[bench] linear plate sweep done", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_static(I, n=65):
     """The oracle's quasi-static solve of the same clamped plate (one Newton-Raphson solve, PCG rtol 1e-10)."""
     import oracle as O
@@ -546,6 +593,7 @@ def main(argv=None):
         out["force_models_isolated"] = force_models(S, I, torch, (S.SHELL_PREC_MIXED, S.SHELL_PREC_FP64))
         if not args.no_quasi_static:
             out["quasi_static"] = quasi_static(S, I, torch)
+            out["quasi_static"]["linear_plate_sweep"] = linear_plate_sweep(S, I, torch)
     if not args.no_cpu_baseline and args.size == 1024:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)

@@ -184,6 +184,45 @@ def plate_mesh(n: int, side: float = 1.0, jitter: float = 0.0, seed: int = 0, mo
     return Mesh(f"plate{n}", X, grid_tris(n, n), pinned, model, l, dict(n=n, side=side, jitter=jitter, seed=seed))
 
 
+def equilateral_plate(n: int, side: float = 1.0, model: str = "EP") -> Mesh:
+    """Flat plate of equilateral triangles with straight sides: rows s sqrt(3)/2 apart, even rows n vertices
+    at i s (s = side / (n - 1)), odd rows shifted by s/2 and closed by a vertex on each side, so every side
+    triangle is a half triangle; as many rows as make the height nearest the side.  Boundary held (the
+    simply supported setting); meta['height'] is the plate's height."""
+    s = side / (n - 1)
+    hgt = s * math.sqrt(3.0) / 2.0
+    ny = int(round(side / hgt)) + 1
+    rows, pts = [], []
+    for j in range(ny):
+        if j % 2 == 0:
+            xs = [i * s for i in range(n)]
+        else:
+            xs = [0.0] + [(k - 0.5) * s for k in range(1, n)] + [(n - 1) * s]
+        rows.append(list(range(len(pts), len(pts) + len(xs))))
+        pts += [(x, j * hgt, 0.0) for x in xs]
+    tris = []
+    for j in range(ny - 1):
+        lo, hi = rows[j], rows[j + 1]
+        if j % 2 == 0:  # even row below, odd row above
+            E, Od = lo, hi
+            tris.append((E[0], Od[1], Od[0]))
+            tris += [(E[i], E[i + 1], Od[i + 1]) for i in range(n - 1)]
+            tris += [(E[i + 1], Od[i + 2], Od[i + 1]) for i in range(n - 2)]
+            tris.append((E[n - 1], Od[n], Od[n - 1]))
+        else:  # odd row below, even row above
+            Od, E = lo, hi
+            tris.append((Od[0], Od[1], E[0]))
+            tris += [(Od[k], Od[k + 1], E[k]) for k in range(1, n - 1)]
+            tris += [(Od[k], E[k], E[k - 1]) for k in range(1, n)]
+            tris.append((Od[n - 1], Od[n], E[n - 1]))
+    X = np.array(pts, dtype=np.float64)
+    height = (ny - 1) * hgt
+    tol = 1e-9 * side
+    held = (X[:, 0] < tol) | (X[:, 0] > side - tol) | (X[:, 1] < tol) | (X[:, 1] > height - tol)
+    return Mesh(f"eqplate{n}", X, np.array(tris, dtype=np.int32), held.astype(np.uint8), model, s,
+                dict(n=n, side=side, height=height))
+
+
 def cylinder_mesh(n: int, radius: float = 0.5, arc: float = math.pi / 4 * 1.0, axial: float = None,
                   jitter: float = 0.0, seed: int = 0, model: str = "FS", pins: str = "ends") -> Mesh:
     """Cylindrical patch of radius R: arc length `arc` around, `axial` along y, n x n vertices.
