@@ -230,6 +230,24 @@ def cpu_static(I, n=65):
                 cores=1)
 
 
+def run_linear_plate(args):
+    """The quasi-static solves alone (the clamped plate at 65^2 and 257^2 and the sweep of the three plate
+    models over three meshes), one JSON line; no other kernels run, so a kernel trace of this workload
+    shows the quasi-static PCG by itself."""
+    import torch
+
+    from paper_2502_10872_amd import inputs as I
+    from paper_2502_10872_amd import shell as S
+
+    S.lib()
+    qs = quasi_static(S, I, torch)
+    sweep = linear_plate_sweep(S, I, torch)
+    big = qs["SP_clamped_257"]
+    print(json.dumps(dict(metric="linear plate solve time (SP, clamped, 257x257, FP64, PCG rtol 1e-10)",
+                          value=big["ms"] / 1e3, unit="s", higher_is_better=False, n_gpus=1, data="synthetic",
+                          quasi_static=qs, linear_plate_sweep=sweep)), flush=True)
+
+
 def run_batch64(args):
     """64 meshes (16^2..512^2 vertices, log-uniform, all six models, 1 cm spacing, mixed precision, Newton
     budget 4, PCG rtol 1e-2, dt = 1/60) stepped as one batch, against the same meshes stepped one at a
@@ -458,7 +476,7 @@ def main(argv=None):
     ap.add_argument("--no-quasi-static", action="store_true",
                     help="skip the quasi-static linear plate solves (about 1e5 PCG launches; kept out of profiles)")
     ap.add_argument("--max-pcg", type=int, default=400000, help="PCG iteration cap per coordinate solve")
-    ap.add_argument("--workload", choices=("sphere-cap", "batch64"), default="sphere-cap")
+    ap.add_argument("--workload", choices=("sphere-cap", "batch64", "linear-plate"), default="sphere-cap")
     ap.add_argument("--no-force-models", action="store_true",
                     help="skip the per-model force kernel timing (six 1M-vertex meshes, both precisions)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -478,6 +496,8 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if args.workload == "batch64":
         return run_batch64(args)
+    if args.workload == "linear-plate":
+        return run_linear_plate(args)
     head = S.SHELL_PREC_MIXED if args.precision == "mixed" else S.SHELL_PREC_FP64
     other = S.SHELL_PREC_FP64 if head == S.SHELL_PREC_MIXED else S.SHELL_PREC_MIXED
     mat = I.MATERIAL
