@@ -69,7 +69,7 @@ typedef struct {
     int32_t block_vertices;  /* vertices per force work-group tile, 64..4096; 0 selects the default (2048) */
     int32_t reorder;         /* internal vertex order: 1 (default) recursive coordinate bisection into compact
                                 tiles of block_vertices, 2 Morton order, 0 the caller's order */
-    int32_t flags;           /* 0, or SHELL_FLAG_DIRECT_PRODUCT and/or SHELL_FLAG_WORLD_FRAME */
+    int32_t flags;           /* 0, or SHELL_FLAG_DIRECT_PRODUCT, SHELL_FLAG_WORLD_FRAME, SHELL_FLAG_MEMBRANE */
 } shell_config_t;
 
 /* The PCG product gathers each neighbour's entries straight from memory instead of staging every 512-row
@@ -83,6 +83,14 @@ typedef struct {
  * L_m; identical on a flat rest).  The force and step kernels are those of EP and ES.  With a triangle
  * model the build returns SHELL_E_INVALID_ARG. */
 #define SHELL_FLAG_WORLD_FRAME 2
+
+/* Adds the membrane of Sec. 3 (eq 1) to shell_eval_forces: constant strain triangles with the Saint
+ * Venant-Kirchhoff model, D_m = h E_el (plane stress), energy A/2 eps^T D_m eps of the Green strain per
+ * triangle, on every triangle of the mesh and for any model.  The implicit step does not take it
+ * (shell_sim_create returns SHELL_E_UNSUPPORTED): the membrane's Hessian couples the coordinates and must
+ * follow the deformation, which the step's constant K_s (x) I3 matrix cannot carry.  A degenerate
+ * triangle is SHELL_E_DEGENERATE. */
+#define SHELL_FLAG_MEMBRANE 4
 
 typedef struct shell_stencils_s* shell_stencils_t;
 typedef struct shell_hessian_s* shell_hessian_t;
@@ -197,7 +205,8 @@ shell_status_t shell_hessian_apply(shell_hessian_t h, const double* mass, double
  * shell_sim_create - simulation state for the implicit step (Sec. 5).
  * x0, v0 host [nv][3] (v0 may be NULL = zero); pinned host [nv], 1 = all three coordinates held at
  * x0 (fixed boundary nodes, Sec. 4.3), may be NULL.  The lumped mass rho h sum(A_T)/3 is computed
- * from the rest mesh.  The stencils and Hessian must outlive the simulation.
+ * from the rest mesh.  The stencils and Hessian must outlive the simulation.  Stencils built with
+ * SHELL_FLAG_MEMBRANE are refused (SHELL_E_UNSUPPORTED).
  */
 shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const double* x0, const double* v0,
                                 const uint8_t* pinned, shell_sim_t* out);

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libshell_hip.so")
-SOURCES = ["host_mesh.cpp", "precompute.hip", "forces.hip", "hessian.hip", "solver.hip", "capi.cpp"]
+SOURCES = ["host_mesh.cpp", "precompute.hip", "forces.hip", "membrane.hip", "hessian.hip", "solver.hip", "capi.cpp"]
 ARCH = os.environ.get("SHELL_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [

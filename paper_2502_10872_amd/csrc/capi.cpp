@@ -102,8 +102,8 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         int reorder = cfg ? cfg->reorder : 1;
         SHELL_CHECK(reorder >= 0 && reorder <= 2, SHELL_E_INVALID_ARG, "unknown vertex order");
         const int cfg_flags = cfg ? cfg->flags : 0;
-        SHELL_CHECK((cfg_flags & ~(SHELL_FLAG_DIRECT_PRODUCT | SHELL_FLAG_WORLD_FRAME)) == 0, SHELL_E_INVALID_ARG,
-                    "unknown flag");
+        SHELL_CHECK((cfg_flags & ~(SHELL_FLAG_DIRECT_PRODUCT | SHELL_FLAG_WORLD_FRAME | SHELL_FLAG_MEMBRANE)) == 0,
+                    SHELL_E_INVALID_ARG, "unknown flag");
         SHELL_CHECK(!(cfg_flags & SHELL_FLAG_WORLD_FRAME) || model_is_edge(model), SHELL_E_INVALID_ARG,
                     "the world-frame operator applies to the edge models (EP, ES)");
         hipStream_t s = as_stream(stream);
@@ -200,6 +200,7 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         launch_tile_copy(*st, bc_d.p, s);
         if (any_clamped && precision == SHELL_PREC_FP64 && !model_is_shell(model)) launch_clamp_bias(*st, bc_d.p, s);
         st->epart.alloc(size_t(st->nblocks));
+        if (cfg_flags & SHELL_FLAG_MEMBRANE) launch_membrane_rest(*st, s);
         SHELL_HIP(hipStreamSynchronize(s));
         *out = st.release();
         return SHELL_OK;
@@ -289,13 +290,16 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
             else
                 launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
             launch_force_items(st->model, st->precision, st->fdesc.p, st->tile_items.p, st->nblocks, st->T, s);
+            if (st->cfg_flags & SHELL_FLAG_MEMBRANE)
+                launch_membrane_forces(*st, f32 ? nullptr : st->xin.p, f32 ? st->xin.p : nullptr, st->fout.p, s);
             launch_scatter_rows(st->fout.p, st->perm_d.p, f, st->nv, f32, s);
         }
         if (energy) {
             if (st->nv == 0)
                 SHELL_HIP(hipMemsetAsync(energy, 0, sizeof(double), s));
             else
-                launch_energy_finalize(st->epart.p, st->nblocks, st->bias_e0, energy, s);
+                launch_energy_finalize(st->epart.p, st->nblocks, st->bias_e0, energy, s, st->mepart.p,
+                                       int64_t(st->mepart.n));
         }
         return SHELL_OK;
     });
@@ -417,6 +421,9 @@ shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const do
     return guarded([&]() -> shell_status_t {
         SHELL_CHECK(st && h && out && (x0 || st->nv == 0) && h->st == st, SHELL_E_INVALID_ARG, "bad argument");
         *out = nullptr;
+        SHELL_CHECK(!(st->cfg_flags & SHELL_FLAG_MEMBRANE), SHELL_E_UNSUPPORTED,
+                    "the implicit step does not take the membrane (its Hessian couples the coordinates and follows "
+                    "the deformation); build the stencils without SHELL_FLAG_MEMBRANE");
         auto sim = std::make_unique<shell_sim_s>();
         sim->st = st;
         sim->h = h;
@@ -710,7 +717,8 @@ shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, i
         for (size_t v : {st.X.bytes(), st.tris.bytes(), st.perm_d.bytes(), st.idx.bytes(), st.B.bytes(),
                          st.k0.bytes(), st.flags.bytes(), st.boff.bytes(), st.tsrc.bytes(), st.tidx.bytes(),
                          st.trec64.bytes(), st.trec32.bytes(), st.xin.bytes(),
-                         st.fout.bytes(), st.epart.bytes(), st.fdesc.bytes(), st.tile_items.bytes()})
+                         st.fout.bytes(), st.epart.bytes(), st.fdesc.bytes(), st.tile_items.bytes(), st.bias.bytes(),
+                         st.memb.bytes(), st.mepart.bytes()})
             a += int64_t(v);
         for (size_t v : {h.scol.bytes(), h.width.bytes(), h.sptr.bytes(), h.rowlen.bytes(), h.val.bytes(),
                          h.valf.bytes(), h.kdiag.bytes(), h.pin.bytes(), h.qout.bytes(), h.gptr.bytes(),

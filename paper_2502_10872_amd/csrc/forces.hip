@@ -365,10 +365,12 @@ void launch_model(int precision, const ForceDesc* descs, const WorkItem* items, 
     SHELL_HIP(hipGetLastError());
 }
 
-__global__ void energy_finalize(const double* __restrict__ part, long n, double add, double* __restrict__ out) {
+__global__ void energy_finalize(const double* __restrict__ part, long n, double add, const double* __restrict__ extra,
+                                long m, double* __restrict__ out) {
     __shared__ double sh[16];
     double acc = 0.0;
     for (long i = threadIdx.x; i < n; i += blockDim.x) acc += part[i];
+    for (long i = threadIdx.x; i < m; i += blockDim.x) acc += extra[i];
     double v[1] = {acc};
     block_sum<1>(v, sh);
     if (threadIdx.x == 0) *out = v[0] + add;
@@ -422,8 +424,9 @@ void launch_force_items(int model, int precision, const ForceDesc* descs, const 
     }
 }
 
-void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s) {
-    energy_finalize<<<1, 256, 0, s>>>(epart, n, add, energy);
+void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s,
+                            const double* extra, int64_t m) {
+    energy_finalize<<<1, 256, 0, s>>>(epart, n, add, extra, m, energy);
     SHELL_HIP(hipGetLastError());
 }
 

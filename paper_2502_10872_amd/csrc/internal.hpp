@@ -231,6 +231,8 @@ struct shell_stencils_s {
     // E0 = their energy there, which turn the plain plate force and energy into rest-relative ones
     shell::DevArray<double> bias;
     double bias_e0 = 0.0;
+    // SHELL_FLAG_MEMBRANE: per triangle G = Dm^-1 (2x2) and the rest area [nt][5]; membrane energy partials
+    shell::DevArray<double> memb, mepart;
     shell::DevArray<int64_t> boff;       // [2 nblocks] start, end
     shell::DevArray<int32_t> tsrc;       // [nst_pad]
     // tiled streams, only those of the configured precision: [nst_pad / 64][chunks][64][fields per chunk]
@@ -364,8 +366,13 @@ void launch_clamp_bias(shell_stencils_s& st, const int32_t* bc, hipStream_t s);
 // start/stop: events that receive the kernel's own begin and end times (null: none)
 void launch_force_items(int model, int precision, const ForceDesc* descs, const WorkItem* items, long nitems,
                         int lds_T, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
-// energy = add + sum of the n partials
-void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s);
+// energy = add + sum of the n partials (+ the m partials of `extra`, when given)
+void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s,
+                            const double* extra = nullptr, int64_t m = 0);
+// membrane.hip: rest data of the membrane (SHELL_FLAG_MEMBRANE); its force added into f (internal order),
+// from positions (FP64) or from displacements u4 [nv][4] and the rest positions (mixed)
+void launch_membrane_rest(shell_stencils_s& st, hipStream_t s);
+void launch_membrane_forces(shell_stencils_s& st, const double* pos, const double* u4, void* f, hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
 // dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order padded displacements
 void launch_gather_displacements(const double* src, const int32_t* perm, const double* X, double* dst, int64_t nv,

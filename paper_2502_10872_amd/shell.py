@@ -44,6 +44,7 @@ class shell_config_t(ctypes.Structure):
 
 SHELL_FLAG_DIRECT_PRODUCT = 1
 SHELL_FLAG_WORLD_FRAME = 2  # edge models: the quadratic thin plate/shell operator (App. D, eq 79)
+SHELL_FLAG_MEMBRANE = 4  # shell_eval_forces adds the membrane of Sec. 3 (eq 1); not taken by the step
 
 
 class shell_stencils_info_t(ctypes.Structure):

@@ -356,6 +356,46 @@ def test_clamped_steps_replay_match_oracle(model):
     assert rel(v, osim.v) <= TOL64
 
 
+# ------------------------------------------------------------------ membrane (Sec. 3, eq 1)
+
+
+@pytest.mark.parametrize("model", ["SS", "EP", "FS"])
+def test_membrane_forces_match_oracle(model):
+    """SHELL_FLAG_MEMBRANE: bending plus membrane force and energy at a deformed state against the oracle
+    (FP64 to 1e-10, mixed within its bound), on a curved rest for shells and a flat one for the plate."""
+    mesh = mesh_for(model, 23) if model != "EP" else I.plate_mesh(23, 1.0, 0.2, 3, "EP", "none")
+    ost = oracle_stencils(model, mesh)
+    x = mesh.X + 2e-3 * I.rng(71).standard_normal(mesh.X.shape)
+    fb, eb = ost.forces(x)
+    fm, em = O.membrane_forces(ost, x)
+    f_ref, e_ref = fb + fm, eb + em
+    assert np.abs(fm).max() > np.abs(fb).max()  # the membrane matters at this state
+    st = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, block_vertices=128, flags=S.SHELL_FLAG_MEMBRANE)
+    try:
+        f, e = gpu_forces(st, x)
+        assert rel(f, f_ref) <= TOL64
+        assert abs(e - e_ref) <= TOL64 * abs(e_ref)
+        f0, e0 = gpu_forces(st, mesh.X)
+        assert np.abs(f0).max() <= 1e-11 * np.abs(f_ref).max() and abs(e0) <= 1e-12 * abs(e_ref)
+        h = S.shell_assemble_constant_hessian(st)
+        try:
+            with pytest.raises(S.ShellError) as ei:
+                S.shell_sim_create(st, h, mesh.X, None, mesh.pinned)
+            assert ei.value.status == S.SHELL_E_UNSUPPORTED
+        finally:
+            S.shell_destroy_hessian(h)
+    finally:
+        S.shell_destroy_stencils(st)
+    st32 = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, precision=S.SHELL_PREC_MIXED,
+                                  flags=S.SHELL_FLAG_MEMBRANE)
+    try:
+        f32, e32 = gpu_forces(st32, x, f32=True)
+        assert rel(f32, f_ref) <= TOL_MIXED_FORCE
+        assert abs(e32 - e_ref) <= 1e-4 * abs(e_ref)
+    finally:
+        S.shell_destroy_stencils(st32)
+
+
 # ------------------------------------------------------------------ quasi-static Newton-Raphson (eq 64)
 
 
