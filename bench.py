@@ -170,6 +170,40 @@ def quasi_static(S, I, torch, sizes=(65, 257)):
     return out
 
 
+def membrane_timing(S, I, torch, reps=20):
+    """The membrane pass (SHELL_FLAG_MEMBRANE) on the 1024 x 1024 sphere cap: shell_eval_forces timed with
+    and without it on the same state, the difference being the membrane kernel (one thread per triangle,
+    atomic adds into the force).  Algorithmic bytes: per triangle its ids and rest data (52 B), per vertex
+    the positions (FP64) or rest positions and displacements (mixed) read once and the force read and
+    written once."""
+    cap = I.workload_sphere_cap(1024, "SS")
+    x = torch.tensor(cap.X + 1e-4 * I.rng(5).standard_normal(cap.X.shape), device="cuda")
+    out = {}
+    for prec in (S.SHELL_PREC_MIXED, S.SHELL_PREC_FP64):
+        mixed = prec == S.SHELL_PREC_MIXED
+        f = torch.zeros(x.shape, dtype=torch.float32 if mixed else torch.float64, device="cuda")
+        ms = {}
+        for flags in (0, S.SHELL_FLAG_MEMBRANE):
+            st = S.shell_build_stencils(cap.X, cap.tris, "SS", I.MATERIAL, precision=prec, flags=flags)
+            S.shell_eval_forces(st, x, f, None)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                S.shell_eval_forces(st, x, f, None)
+            e1.record()
+            torch.cuda.synchronize()
+            ms[flags] = e0.elapsed_time(e1) / reps
+            S.shell_destroy_stencils(st)
+        nv, nt = cap.nv, len(cap.tris)
+        alg = nt * 52 + nv * ((24 + 32 + 24) if mixed else (24 + 48))
+        dm = ms[S.SHELL_FLAG_MEMBRANE] - ms[0]
+        out["mixed" if mixed else "fp64"] = dict(triangles=nt, eval_forces_ms=ms[0], with_membrane_ms=ms[S.SHELL_FLAG_MEMBRANE],
+                                                 membrane_ms=dm, gbs=alg / (dm * 1e-3) / 1e9 if dm > 0 else None)
+    print("[bench] membrane timing done", file=sys.stderr, flush=True)
+    return out
+
+
 def navier_rectangle(a, b, nterm=199):
     """Navier's series for the centre deflection of a simply supported a x b plate, w = alpha q / D."""
     s = 0.0
@@ -611,6 +645,7 @@ def main(argv=None):
         pb_other.close()
     if not args.no_force_models and args.size == 1024:
         out["force_models_isolated"] = force_models(S, I, torch, (S.SHELL_PREC_MIXED, S.SHELL_PREC_FP64))
+        out["membrane_forces"] = membrane_timing(S, I, torch)
         if not args.no_quasi_static:
             out["quasi_static"] = quasi_static(S, I, torch)
             out["quasi_static"]["linear_plate_sweep"] = linear_plate_sweep(S, I, torch)

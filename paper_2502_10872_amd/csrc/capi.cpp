@@ -718,7 +718,7 @@ shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, i
                          st.k0.bytes(), st.flags.bytes(), st.boff.bytes(), st.tsrc.bytes(), st.tidx.bytes(),
                          st.trec64.bytes(), st.trec32.bytes(), st.xin.bytes(),
                          st.fout.bytes(), st.epart.bytes(), st.fdesc.bytes(), st.tile_items.bytes(), st.bias.bytes(),
-                         st.memb.bytes(), st.mepart.bytes()})
+                         st.mtid.bytes(), st.mtrest.bytes(), st.mboff.bytes(), st.mepart.bytes()})
             a += int64_t(v);
         for (size_t v : {h.scol.bytes(), h.width.bytes(), h.sptr.bytes(), h.rowlen.bytes(), h.val.bytes(),
                          h.valf.bytes(), h.kdiag.bytes(), h.pin.bytes(), h.qout.bytes(), h.gptr.bytes(),

@@ -231,8 +231,11 @@ struct shell_stencils_s {
     // E0 = their energy there, which turn the plain plate force and energy into rest-relative ones
     shell::DevArray<double> bias;
     double bias_e0 = 0.0;
-    // SHELL_FLAG_MEMBRANE: per triangle G = Dm^-1 (2x2) and the rest area [nt][5]; membrane energy partials
-    shell::DevArray<double> memb, mepart;
+    // SHELL_FLAG_MEMBRANE: the triangles in the force tiles (halo copies repeat): ids [n][4], rest data
+    // [n][6] (G = Dm^-1 row-major, area, 0), each tile's list [2 nblocks]; energy partials [nblocks]
+    shell::DevArray<int32_t> mtid;
+    shell::DevArray<double> mtrest, mepart;
+    shell::DevArray<int64_t> mboff;
     shell::DevArray<int64_t> boff;       // [2 nblocks] start, end
     shell::DevArray<int32_t> tsrc;       // [nst_pad]
     // tiled streams, only those of the configured precision: [nst_pad / 64][chunks][64][fields per chunk]

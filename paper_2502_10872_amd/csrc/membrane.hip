@@ -1,13 +1,14 @@
 // Membrane (Sec. 3, eq 1) on constant strain triangles with the Saint Venant-Kirchhoff model, float64.
 //
 // Rest data per triangle (membrane_rest): the rest frame e1 along X1 - X0, e2 = n x e1; Dm the 2x2 matrix
-// of the rest edge vectors in that frame; G = Dm^-1 and the area A.  Force (membrane_forces): with Ds the
+// of the rest edge vectors in that frame; G = Dm^-1 and the area A.  Force (membrane_tiles): with Ds the
 // current edge vectors x1 - x0, x2 - x0, F = Ds G (3x2), Green strain E = (F^T F - I)/2 in Voigt form
 // [E11, E22, 2 E12], stress sigma = D_m eps with D_m = h E_el (plane stress), energy A/2 eps . sigma;
 // dPsi/dDs = A F S G^T (S the stress as a 2x2 tensor), so f1 and f2 are minus its columns and f0 their
-// sum.  One thread per triangle; the three vertex forces are added atomically into the force array the
-// bending kernel wrote (float64, or float in mixed precision, where the edge vectors are formed in float64
-// from the rest edges plus the displacement differences).
+// sum.  The triangles are grouped by the same vertex tiles as the bending stencils (halo triangles
+// repeat): each work-group accumulates the forces of its own vertices in LDS and adds them to the force
+// the bending kernel stored, one read and one write per vertex and no global atomics.  In mixed precision
+// the edge vectors are the rest edges plus the displacement differences, in float64.
 #include "devmath.hpp"
 #include "internal.hpp"
 
@@ -40,76 +41,121 @@ __global__ void membrane_rest(const double* __restrict__ X, const int32_t* __res
     rest[5 * t + 4] = 0.5 * twoA;
 }
 
+// tiled record of the membrane: ids [n][4] (int32, last unused) and rest data [n][6] (G, A, 0)
+__global__ void membrane_tile_copy(const int32_t* __restrict__ src, long n, const int32_t* __restrict__ tris,
+                                   const double* __restrict__ rest, int32_t* __restrict__ tid,
+                                   double* __restrict__ trest) {
+    long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (e >= n) return;
+    const long t = src[e];  // -1: alignment padding (never read)
+    for (int j = 0; j < 3; ++j) tid[4 * e + j] = t < 0 ? 0 : tris[3 * t + j];
+    tid[4 * e + 3] = 0;
+    for (int k = 0; k < 5; ++k) trest[6 * e + k] = t < 0 ? 0.0 : rest[5 * t + k];
+    trest[6 * e + 5] = 0.0;
+}
+
+constexpr int kMembThreads = 512;
+
 template <typename R>
-__global__ void membrane_forces(const double* __restrict__ pos, const double* __restrict__ u4,
-                                const double* __restrict__ X, const int32_t* __restrict__ tris,
-                                const double* __restrict__ rest, long nt, double c, double nu, R* __restrict__ f,
-                                double* __restrict__ epart) {
-    long t = blockIdx.x * long(blockDim.x) + threadIdx.x;
+__global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __restrict__ pos,
+                                                               const double* __restrict__ u4,
+                                                               const double* __restrict__ X,
+                                                               const int32_t* __restrict__ tid,
+                                                               const double* __restrict__ trest,
+                                                               const int64_t* __restrict__ boff, long nv, int T,
+                                                               double c, double nu, R* __restrict__ f,
+                                                               double* __restrict__ epart) {
+    extern __shared__ unsigned char smem_raw[];
+    double* acc = reinterpret_cast<double*>(smem_raw);
+    const long blk = blockIdx.x;
+    const long base = blk * long(T);
+    const int nown = int(min(long(T), nv - base));
+    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) acc[i] = 0.0;
+    __syncthreads();
     double en[1] = {0.0};
-    if (t < nt) {
-        const long v0 = tris[3 * t], v1 = tris[3 * t + 1], v2 = tris[3 * t + 2];
+    const long e0 = boff[2 * blk], e1 = boff[2 * blk + 1];
+    for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const long v[3] = {tid[4 * e], tid[4 * e + 1], tid[4 * e + 2]};
         double d1[3], d2[3];
         for (int i = 0; i < 3; ++i) {
             if (pos) {
-                d1[i] = pos[3 * v1 + i] - pos[3 * v0 + i];
-                d2[i] = pos[3 * v2 + i] - pos[3 * v0 + i];
+                d1[i] = pos[3 * v[1] + i] - pos[3 * v[0] + i];
+                d2[i] = pos[3 * v[2] + i] - pos[3 * v[0] + i];
             } else {
-                d1[i] = (X[3 * v1 + i] - X[3 * v0 + i]) + (u4[4 * v1 + i] - u4[4 * v0 + i]);
-                d2[i] = (X[3 * v2 + i] - X[3 * v0 + i]) + (u4[4 * v2 + i] - u4[4 * v0 + i]);
+                d1[i] = (X[3 * v[1] + i] - X[3 * v[0] + i]) + (u4[4 * v[1] + i] - u4[4 * v[0] + i]);
+                d2[i] = (X[3 * v[2] + i] - X[3 * v[0] + i]) + (u4[4 * v[2] + i] - u4[4 * v[0] + i]);
             }
         }
-        const double G[2][2] = {{rest[5 * t], rest[5 * t + 1]}, {rest[5 * t + 2], rest[5 * t + 3]}};
-        const double A = rest[5 * t + 4];
+        const double G[2][2] = {{trest[6 * e], trest[6 * e + 1]}, {trest[6 * e + 2], trest[6 * e + 3]}};
+        const double A = trest[6 * e + 4];
         double F[3][2];
         for (int i = 0; i < 3; ++i)
             for (int b = 0; b < 2; ++b) F[i][b] = d1[i] * G[0][b] + d2[i] * G[1][b];
-        double C00 = F[0][0] * F[0][0] + F[1][0] * F[1][0] + F[2][0] * F[2][0];
-        double C11 = F[0][1] * F[0][1] + F[1][1] * F[1][1] + F[2][1] * F[2][1];
-        double C01 = F[0][0] * F[0][1] + F[1][0] * F[1][1] + F[2][0] * F[2][1];
-        const double e0 = 0.5 * (C00 - 1.0), e1 = 0.5 * (C11 - 1.0), e2 = C01;
-        const double s0 = c * (e0 + nu * e1), s1 = c * (nu * e0 + e1), s2 = c * 0.5 * (1.0 - nu) * e2;
-        en[0] = 0.5 * A * (e0 * s0 + e1 * s1 + e2 * s2);
+        const double C00 = F[0][0] * F[0][0] + F[1][0] * F[1][0] + F[2][0] * F[2][0];
+        const double C11 = F[0][1] * F[0][1] + F[1][1] * F[1][1] + F[2][1] * F[2][1];
+        const double C01 = F[0][0] * F[0][1] + F[1][0] * F[1][1] + F[2][0] * F[2][1];
+        const double s0e = 0.5 * (C00 - 1.0), s1e = 0.5 * (C11 - 1.0), s2e = C01;
+        const double s0 = c * (s0e + nu * s1e), s1 = c * (nu * s0e + s1e), s2 = c * 0.5 * (1.0 - nu) * s2e;
+        const unsigned o0 = unsigned(v[0] - base), o1 = unsigned(v[1] - base), o2 = unsigned(v[2] - base);
+        if (o0 < unsigned(nown)) en[0] += 0.5 * A * (s0e * s0 + s1e * s1 + s2e * s2);
         for (int i = 0; i < 3; ++i) {
             const double P0 = A * (F[i][0] * s0 + F[i][1] * s2), P1 = A * (F[i][0] * s2 + F[i][1] * s1);
             const double h0 = P0 * G[0][0] + P1 * G[0][1], h1 = P0 * G[1][0] + P1 * G[1][1];
-            atomicAdd(f + 3 * v1 + i, R(-h0));
-            atomicAdd(f + 3 * v2 + i, R(-h1));
-            atomicAdd(f + 3 * v0 + i, R(h0 + h1));
+            if (o1 < unsigned(nown)) atomicAdd(acc + 3 * o1 + i, -h0);
+            if (o2 < unsigned(nown)) atomicAdd(acc + 3 * o2 + i, -h1);
+            if (o0 < unsigned(nown)) atomicAdd(acc + 3 * o0 + i, h0 + h1);
         }
     }
-    __shared__ double sh[256 / 64];
+    __syncthreads();
+    R* out = f + 3 * base;
+    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(double(out[i]) + acc[i]);
+    __shared__ double sh[kMembThreads / 64];
     block_sum<1>(en, sh);
-    if (threadIdx.x == 0 && epart) epart[blockIdx.x] = en[0];
+    if (threadIdx.x == 0) epart[blk] = en[0];
 }
 
 }  // namespace
 
 void launch_membrane_rest(shell_stencils_s& st, hipStream_t s) {
     const long nt = st.nt;
-    st.memb.alloc(size_t(5 * nt));
+    DevArray<double> rest(size_t(5 * nt));
     DevArray<int32_t> bad(1);
     SHELL_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
-    if (nt > 0) membrane_rest<<<int((nt + 255) / 256), 256, 0, s>>>(st.X.p, st.tris.p, nt, st.memb.p, bad.p);
+    if (nt > 0) membrane_rest<<<int((nt + 255) / 256), 256, 0, s>>>(st.X.p, st.tris.p, nt, rest.p, bad.p);
     SHELL_HIP(hipGetLastError());
     int32_t h = 0;
     bad.download(&h, 1, s);
     SHELL_HIP(hipStreamSynchronize(s));
     SHELL_CHECK(h == 0, SHELL_E_DEGENERATE, "degenerate triangle (zero area) for the membrane");
-    st.mepart.alloc(size_t((nt + 255) / 256));
+    // the triangles in the bending kernel's vertex tiles
+    Tiling til = build_tiling(st.h_tris, 3, nt, st.nv, st.T);
+    st.mboff.alloc(til.boff.size());
+    st.mboff.upload(til.boff.data(), til.boff.size(), s);
+    DevArray<int32_t> src(til.src.size());
+    src.upload(til.src.data(), til.src.size(), s);
+    const long n = long(til.src.size());
+    st.mtid.alloc(size_t(4 * n));
+    st.mtrest.alloc(size_t(6 * n));
+    if (n > 0)
+        membrane_tile_copy<<<int((n + 255) / 256), 256, 0, s>>>(src.p, n, st.tris.p, rest.p, st.mtid.p, st.mtrest.p);
+    SHELL_HIP(hipGetLastError());
+    st.mepart.alloc(size_t(st.nblocks));
+    SHELL_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
 }
 
 void launch_membrane_forces(shell_stencils_s& st, const double* pos, const double* u4, void* f, hipStream_t s) {
-    const long nt = st.nt;
-    if (nt == 0) return;
+    if (st.nv == 0 || st.nblocks == 0) return;
     const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
-    const int grid = int((nt + 255) / 256);
+    const size_t lds = size_t(3 * st.T) * sizeof(double);
+    const unsigned grid = unsigned(st.nblocks);
     if (st.precision == SHELL_PREC_MIXED)
-        membrane_forces<float><<<grid, 256, 0, s>>>(pos, u4, st.X.p, st.tris.p, st.memb.p, nt, c, st.poisson,
-                                                    static_cast<float*>(f), st.mepart.p);
+        membrane_tiles<float><<<grid, kMembThreads, lds, s>>>(pos, u4, st.X.p, st.mtid.p, st.mtrest.p, st.mboff.p,
+                                                              st.nv, st.T, c, st.poisson, static_cast<float*>(f),
+                                                              st.mepart.p);
     else
-        membrane_forces<double><<<grid, 256, 0, s>>>(pos, u4, st.X.p, st.tris.p, st.memb.p, nt, c, st.poisson,
-                                                     static_cast<double*>(f), st.mepart.p);
+        membrane_tiles<double><<<grid, kMembThreads, lds, s>>>(pos, u4, st.X.p, st.mtid.p, st.mtrest.p, st.mboff.p,
+                                                               st.nv, st.T, c, st.poisson, static_cast<double*>(f),
+                                                               st.mepart.p);
     SHELL_HIP(hipGetLastError());
 }
 
