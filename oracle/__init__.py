@@ -61,6 +61,9 @@ def lib():
         L.orc_static.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, P, P, P, d, d, i, d, i, P, P, P]
         L.orc_membrane.argtypes = [i64, P, i64, P, P, d, d, d, P, P]
         L.orc_membrane_rest_hessian.argtypes = [i64, P, P, d, d, d, P]
+        L.orc_membrane_gn_hessian.argtypes = [i64, P, P, P, d, d, d, P]
+        L.orc_step_membrane.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, i64, P, P, d, d, d, P, P, P, P, d, P,
+                                        i, d, d, i, P, P, P, P, P]
         L.orc_edge_normal_literal.argtypes = [P, P, P, P, P]
         _lib = L
     return _lib
@@ -185,6 +188,50 @@ def membrane_rest_hessian(st: Stencils):
     _check(lib().orc_membrane_rest_hessian(st.nt, _p(st.tris), _p(st.X), st.young, st.poisson, st.thickness,
                                            _p(K9)), "membrane hessian")
     return K9
+
+
+def membrane_gn_hessian(st: Stencils, x):
+    """Per-triangle Gauss-Newton membrane tangent at x, [nt][9][9]."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    K9 = np.zeros((st.nt, 9, 9))
+    _check(lib().orc_membrane_gn_hessian(st.nt, _p(st.tris), _p(st.X), _p(x), st.young, st.poisson, st.thickness,
+                                         _p(K9)), "membrane gn hessian")
+    return K9
+
+
+class MembraneSim:
+    """Implicit-Euler state of the shell with its membrane (Sec. 3 and Sec. 5): Gauss-Newton matrix, one
+    coupled Jacobi-PCG per Newton solve, Armijo backtracking on the incremental potential."""
+
+    def __init__(self, st: Stencils, material: dict, pinned, x0=None, v0=None):
+        self.st = st
+        self.csr = st.hessian()
+        self.mass = mass(st.X, st.tris, material["density"], material["thickness"])
+        self.pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
+        self.x = np.array(st.X if x0 is None else x0, dtype=np.float64, copy=True)
+        self.v = np.zeros_like(self.x) if v0 is None else np.array(v0, dtype=np.float64, copy=True)
+
+    def step(self, dt, gravity=(0.0, 0.0, -9.81), max_newton=4, newton_rtol=1e-8, pcg_rtol=1e-10, max_pcg=200000,
+             replay_pcg=None, replay_halvings=None):
+        """Returns (counts [max_newton], halvings [max_newton], stats dict)."""
+        g = np.ascontiguousarray(gravity, dtype=np.float64)
+        n = max(max_newton, 1)
+        counts = np.zeros(n, dtype=np.int32)
+        halv = np.zeros(n, dtype=np.int32)
+        stats = np.zeros(4)
+        rp = None if replay_pcg is None else np.ascontiguousarray(replay_pcg, dtype=np.int32)
+        rh = None if replay_halvings is None else np.ascontiguousarray(replay_halvings, dtype=np.int32)
+        rowptr, col, val = self.csr
+        st = self.st
+        rc = lib().orc_step_membrane(st.model, st.nv, st.ns, _p(st.idx), _p(st.B), _p(st.kappa0), _p(st.Crest),
+                                     _p(st.D), _p(rowptr), _p(col), _p(val), st.nt, _p(st.tris), _p(st.X), st.young,
+                                     st.poisson, st.thickness, _p(self.mass), _p(self.pinned), _p(self.x),
+                                     _p(self.v), dt, _p(g), max_newton, newton_rtol, pcg_rtol, max_pcg, _p(rp),
+                                     _p(rh), _p(counts), _p(halv), _p(stats))
+        if rc not in (0, -5):
+            _check(rc, "membrane step")
+        return counts, halv, dict(newton_iters=int(stats[0]), pcg_total=int(stats[1]), grad_norm0=stats[2],
+                                  grad_norm=stats[3], budget_hit=(rc == -5))
 
 
 class Sim:

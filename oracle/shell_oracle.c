@@ -20,7 +20,9 @@
  *             constant Hessian of eqs 21/41/53; quasi-static equilibrium
  *             (eq 64) by Newton-Raphson with the eps_f / eps_u controls.
  *   Sec. 3    membrane energy (eq 1) on constant strain triangles with the
- *             Saint Venant-Kirchhoff model and its Hessian at rest.
+ *             Saint Venant-Kirchhoff model, its Hessian at rest, its
+ *             Gauss-Newton tangent, and the implicit step of the shell with
+ *             its membrane (Gauss-Newton matrix, Armijo backtracking).
  *
  * Readings where the paper is silent or ambiguous (each is also listed in the
  * design notes of the repository):
@@ -978,6 +980,225 @@ int orc_membrane_rest_hessian(int64_t nt, const int32_t* tris, const double* X, 
             }
     }
     return ORC_OK;
+}
+
+/* Gauss-Newton tangent of the membrane energy at the state x, per triangle: K = A B(F)^T D_m B(F) (9x9,
+   vertex-major, coordinate-minor), B(F) the linearised Green strain, rows [g_j0 F0^T], [g_j1 F1^T],
+   [g_j1 F0^T + g_j0 F1^T] for vertex j (F0, F1 the columns of F); positive semi-definite, and the rest
+   Hessian at x = X. */
+int orc_membrane_gn_hessian(int64_t nt, const int32_t* tris, const double* X, const double* x, double young,
+                            double poisson, double thickness, double* K9) {
+    if (!tris || !X || !x || !K9) return ORC_E_ARG;
+    double c = young * thickness / (1.0 - poisson * poisson);
+    double Dm[3][3] = {{c, c * poisson, 0}, {c * poisson, c, 0}, {0, 0, c * 0.5 * (1.0 - poisson)}};
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t* v = tris + 3 * t;
+        double e1[3], e2[3], G[2][2];
+        double A = cst_frame(X + 3 * v[0], X + 3 * v[1], X + 3 * v[2], e1, e2, G);
+        if (!(A > 0)) return ORC_E_DEGENERATE;
+        double d1[3], d2[3], F[3][2];
+        sub3(x + 3 * v[1], x + 3 * v[0], d1);
+        sub3(x + 3 * v[2], x + 3 * v[0], d2);
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 2; ++b) F[i][b] = d1[i] * G[0][b] + d2[i] * G[1][b];
+        double g[3][2] = {{-G[0][0] - G[1][0], -G[0][1] - G[1][1]}, {G[0][0], G[0][1]}, {G[1][0], G[1][1]}};
+        double Bm[3][9];
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                Bm[0][3 * j + i] = g[j][0] * F[i][0];
+                Bm[1][3 * j + i] = g[j][1] * F[i][1];
+                Bm[2][3 * j + i] = g[j][1] * F[i][0] + g[j][0] * F[i][1];
+            }
+        double* K = K9 + 81 * t;
+        for (int p = 0; p < 9; ++p)
+            for (int q = 0; q < 9; ++q) {
+                double acc = 0;
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) acc += Bm[a][p] * Dm[a][b] * Bm[b][q];
+                K[9 * p + q] = A * acc;
+            }
+    }
+    return ORC_OK;
+}
+
+/* incremental potential of the step with the membrane: 1/2 (x - x_hat)^T M (x - x_hat) + dt^2 (Psi_b + Psi_m);
+   also returns the total force (bending plus membrane) in f */
+static double membrane_step_energy(int model, int64_t nv, const double* x, int64_t ns, const int32_t* idx,
+                                   const double* B, const double* kappa0, const double* Crest, const double* D,
+                                   int64_t nt, const int32_t* tris, const double* X, double young, double poisson,
+                                   double thickness, const double* mass, const double* xhat, double dt2,
+                                   double* f) {
+    double eb = 0, em = 0, ei = 0;
+    orc_forces(model, nv, x, ns, idx, B, kappa0, Crest, D, f, &eb);
+    orc_membrane(nv, x, nt, tris, X, young, poisson, thickness, f, &em);
+    for (int64_t i = 0; i < nv; ++i)
+        for (int d = 0; d < 3; ++d) {
+            double u = x[3 * i + d] - xhat[3 * i + d];
+            ei += 0.5 * mass[i] * u * u;
+        }
+    return ei + dt2 * (eb + em);
+}
+
+/* One implicit-Euler step (eq 62) of the shell with its membrane.  Each Newton iteration solves
+   (M + dt^2 (K_s (x) I3 + K_GN(x))) y = -g by one Jacobi-PCG over all 3 nv coordinates (the membrane
+   couples them; the preconditioner is 1/(m + dt^2 (K_s,ii + tr(K_GN,ii)/3)) per vertex), then takes
+   x += 2^-h y with h the fewest halvings (at most 6) that satisfy Armijo's condition
+   E(x + a y) <= E(x) + 1e-4 a g.y on the incremental potential E.  replay_pcg / replay_halvings
+   [max_newton] (may be NULL) fix the iteration counts and the halvings; counts and halvings
+   [max_newton] receive them. */
+int orc_step_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
+                      const double* Crest, const double* D, const int64_t* rowptr, const int32_t* col,
+                      const double* val, int64_t nt, const int32_t* tris, const double* X, double young,
+                      double poisson, double thickness, const double* mass, const uint8_t* pinned, double* x,
+                      double* v, double dt, const double* gravity, int max_newton, double newton_rtol,
+                      double pcg_rtol, int max_pcg, const int32_t* replay_pcg, const int32_t* replay_halvings,
+                      int32_t* counts, int32_t* halvings, double* stats) {
+    if (!x || !v || !mass || !pinned || dt <= 0 || max_newton < 0) return ORC_E_ARG;
+    size_t n3 = (size_t)(3 * nv);
+    double* xt = (double*)malloc(sizeof(double) * n3);
+    double* xhat = (double*)malloc(sizeof(double) * n3);
+    double* xtry = (double*)malloc(sizeof(double) * n3);
+    double* f = (double*)malloc(sizeof(double) * n3);
+    double* g = (double*)malloc(sizeof(double) * n3);
+    double* r = (double*)malloc(sizeof(double) * n3);
+    double* z = (double*)malloc(sizeof(double) * n3);
+    double* p = (double*)malloc(sizeof(double) * n3);
+    double* q = (double*)malloc(sizeof(double) * n3);
+    double* y = (double*)malloc(sizeof(double) * n3);
+    double* dinv = (double*)malloc(sizeof(double) * (size_t)nv);
+    double* K9 = (double*)malloc(sizeof(double) * (size_t)(81 * nt + 1));
+    double dt2 = dt * dt;
+    memcpy(xt, x, sizeof(double) * n3);
+    for (int64_t i = 0; i < nv; ++i)
+        for (int d = 0; d < 3; ++d)
+            xhat[3 * i + d] = pinned[i] ? xt[3 * i + d] : xt[3 * i + d] + dt * v[3 * i + d] + dt2 * gravity[d];
+    memcpy(x, xhat, sizeof(double) * n3);
+    int newton = 0, pcg_total = 0, budget_hit = 0, rc = ORC_OK;
+    double gn0 = 0, gn = 0;
+    double E = membrane_step_energy(model, nv, x, ns, idx, B, kappa0, Crest, D, nt, tris, X, young, poisson,
+                                    thickness, mass, xhat, dt2, f);
+    for (int k = 0;; ++k) {
+        double s2 = 0;
+        for (int64_t i = 0; i < nv; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double gi = pinned[i] ? 0.0 : mass[i] * (x[3 * i + d] - xhat[3 * i + d]) - dt2 * f[3 * i + d];
+                g[3 * i + d] = gi;
+                s2 += gi * gi;
+            }
+        gn = sqrt(s2);
+        if (k == 0) gn0 = gn;
+        if (gn0 == 0.0 || (k > 0 && gn <= newton_rtol * gn0) || k == max_newton) break;
+        rc = orc_membrane_gn_hessian(nt, tris, X, x, young, poisson, thickness, K9);
+        if (rc) break;
+        for (int64_t i = 0; i < nv; ++i) {
+            double kii = 0;
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+                if (col[e] == i) kii = val[e];
+            dinv[i] = kii;
+        }
+        for (int64_t t = 0; t < nt; ++t)
+            for (int j = 0; j < 3; ++j)
+                for (int d = 0; d < 3; ++d)
+                    dinv[tris[3 * t + j]] += K9[81 * t + (3 * j + d) * 9 + 3 * j + d] / 3.0;
+        for (int64_t i = 0; i < nv; ++i) dinv[i] = pinned[i] ? 0.0 : 1.0 / (mass[i] + dt2 * dinv[i]);
+        /* Jacobi-PCG, y0 = 0 */
+        double bn = 0, rz = 0;
+        for (size_t i = 0; i < n3; ++i) {
+            y[i] = 0.0;
+            r[i] = -g[i];
+            bn += r[i] * r[i];
+            z[i] = dinv[i / 3] * r[i];
+            p[i] = z[i];
+            rz += r[i] * z[i];
+        }
+        bn = sqrt(bn);
+        int target = replay_pcg ? replay_pcg[k] : max_pcg, it = 0;
+        while (it < target) {
+            if (!replay_pcg) {
+                double rn = 0;
+                for (size_t i = 0; i < n3; ++i) rn += r[i] * r[i];
+                if (sqrt(rn) <= pcg_rtol * bn) break;
+            }
+            for (int64_t i = 0; i < nv; ++i) {
+                double acc[3] = {0, 0, 0};
+                for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) axpy3(val[e], p + 3 * col[e], acc);
+                for (int d = 0; d < 3; ++d) q[3 * i + d] = mass[i] * p[3 * i + d] + dt2 * acc[d];
+            }
+            for (int64_t t = 0; t < nt; ++t) {
+                const int32_t* tv = tris + 3 * t;
+                const double* K = K9 + 81 * t;
+                for (int a = 0; a < 9; ++a) {
+                    double acc = 0;
+                    for (int b = 0; b < 9; ++b) acc += K[9 * a + b] * p[3 * tv[b / 3] + b % 3];
+                    q[3 * tv[a / 3] + a % 3] += dt2 * acc;
+                }
+            }
+            double pq = 0;
+            for (int64_t i = 0; i < nv; ++i)
+                for (int d = 0; d < 3; ++d) {
+                    if (pinned[i]) q[3 * i + d] = 0.0;
+                    pq += p[3 * i + d] * q[3 * i + d];
+                }
+            double alpha = pq != 0.0 ? rz / pq : 0.0;
+            double rz_new = 0;
+            for (size_t i = 0; i < n3; ++i) {
+                y[i] += alpha * p[i];
+                r[i] -= alpha * q[i];
+                z[i] = dinv[i / 3] * r[i];
+                rz_new += r[i] * z[i];
+            }
+            double beta = rz != 0.0 ? rz_new / rz : 0.0;
+            rz = rz_new;
+            for (size_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
+            ++it;
+        }
+        if (!replay_pcg && it >= max_pcg) {
+            double rn = 0;
+            for (size_t i = 0; i < n3; ++i) rn += r[i] * r[i];
+            if (sqrt(rn) > pcg_rtol * bn) budget_hit = 1;
+        }
+        if (counts) counts[k] = it;
+        pcg_total += it;
+        /* backtracking line search on the incremental potential */
+        double slope = 0;
+        for (size_t i = 0; i < n3; ++i) slope += g[i] * y[i];
+        int h = 0;
+        double a = 1.0, Etry = 0;
+        for (;;) {
+            for (size_t i = 0; i < n3; ++i) xtry[i] = x[i] + a * y[i];
+            Etry = membrane_step_energy(model, nv, xtry, ns, idx, B, kappa0, Crest, D, nt, tris, X, young, poisson,
+                                        thickness, mass, xhat, dt2, f);
+            int done = replay_halvings ? (h >= replay_halvings[k]) : (Etry <= E + 1e-4 * a * slope || h == 6);
+            if (done) break;
+            a *= 0.5;
+            ++h;
+        }
+        if (halvings) halvings[k] = h;
+        memcpy(x, xtry, sizeof(double) * n3);
+        E = Etry;  /* f already holds the force at the new x */
+        ++newton;
+    }
+    for (size_t i = 0; i < n3; ++i) v[i] = (x[i] - xt[i]) / dt;
+    if (stats) {
+        stats[0] = newton;
+        stats[1] = pcg_total;
+        stats[2] = gn0;
+        stats[3] = gn;
+    }
+    free(xt);
+    free(xhat);
+    free(xtry);
+    free(f);
+    free(g);
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(y);
+    free(dinv);
+    free(K9);
+    if (rc) return rc;
+    return budget_hit ? ORC_E_BUDGET : ORC_OK;
 }
 
 /* Quasi-static equilibrium (Sec. 5, eq 64) by Newton-Raphson in one load step: the residual

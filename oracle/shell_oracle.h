@@ -105,6 +105,20 @@ int orc_membrane(int64_t nv, const double* x, int64_t nt, const int32_t* tris, c
                  double poisson, double thickness, double* f, double* energy);
 int orc_membrane_rest_hessian(int64_t nt, const int32_t* tris, const double* X, double young, double poisson,
                               double thickness, double* K9);
+/* Gauss-Newton membrane tangent at x per triangle, K9 [nt][9][9] (PSD; the rest Hessian at x = X). */
+int orc_membrane_gn_hessian(int64_t nt, const int32_t* tris, const double* X, const double* x, double young,
+                            double poisson, double thickness, double* K9);
+/* Implicit-Euler step with bending and membrane: Newton matrix M + dt^2 (K_s (x) I3 + K_GN(x)), one
+ * Jacobi-PCG over all coordinates, Armijo backtracking (at most 6 halvings) on the incremental potential.
+ * replay_pcg, replay_halvings [max_newton] (may be NULL); counts, halvings [max_newton] out. */
+int orc_step_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
+                      const double* Crest, const double* D, const int64_t* rowptr, const int32_t* col,
+                      const double* val, int64_t nt, const int32_t* tris, const double* X, double young,
+                      double poisson, double thickness, const double* mass, const uint8_t* pinned, double* x,
+                      double* v, double dt, const double* gravity, int max_newton, double newton_rtol,
+                      double pcg_rtol, int max_pcg, const int32_t* replay_pcg, const int32_t* replay_halvings,
+                      int32_t* counts, int32_t* halvings, double* stats);
+
 int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3, const double* x4, double* n);
 
 #endif

@@ -885,6 +885,71 @@ def test_membrane_rest_hessian_is_the_force_jacobian_at_rest():
         assert ev.min() >= -1e-12 * ev.max() and (ev > 1e-9 * ev.max()).sum() == 3
 
 
+def _assemble9(st, K9):
+    K = np.zeros((3 * st.nv, 3 * st.nv))
+    for t, tv in enumerate(st.tris):
+        ii = np.array([3 * tv[j] + c for j in range(3) for c in range(3)])
+        K[np.ix_(ii, ii)] += K9[t]
+    return K
+
+
+def test_membrane_gauss_newton_tangent():
+    """The Gauss-Newton tangent equals the rest Hessian at rest, equals the force's central-difference
+    Jacobian on a rigidly turned rest (no stress there, so the geometric term vanishes), and is PSD at a
+    deformed state."""
+    m = rest_mesh("SS", n=5)
+    st = O.Stencils("SS", m.X, m.tris, 1.0e6, 0.3, 1e-2)
+    assert np.abs(O.membrane_gn_hessian(st, m.X) - O.membrane_rest_hessian(st)).max() <= 1e-12 * np.abs(
+        O.membrane_rest_hessian(st)).max()
+    g = I.rng(63)
+    Q = I.random_rotation(g)
+    xr = m.X @ Q.T + g.standard_normal(3)
+    K = _assemble9(st, O.membrane_gn_hessian(st, xr))
+    for _ in range(2):
+        d = g.standard_normal(3 * st.nv)
+        hh = 1e-7
+        fp, _ = O.membrane_forces(st, xr + hh * d.reshape(-1, 3))
+        fm, _ = O.membrane_forces(st, xr - hh * d.reshape(-1, 3))
+        assert np.abs(-(fp - fm).ravel() / (2 * hh) - K @ d).max() <= 1e-6 * np.abs(K @ d).max()
+    Kx = _assemble9(st, O.membrane_gn_hessian(st, m.X + 0.05 * g.standard_normal(m.X.shape)))
+    ev = np.linalg.eigvalsh(0.5 * (Kx + Kx.T))
+    assert ev.min() >= -1e-10 * ev.max()
+
+
+def _membrane_energy(st, mass, xhat, x, dt):
+    eb = st.energy(x)
+    _, em = O.membrane_forces(st, x)
+    return 0.5 * float((mass[:, None] * (x - xhat) ** 2).sum()) + dt * dt * (eb + em)
+
+
+def test_membrane_step_descends_and_solves_the_step_equation():
+    """The step with the membrane: each Newton iteration lowers the incremental potential (recomputed here
+    from the energies), and with a small time step it converges to the step equation
+    M (x - x_hat) = dt^2 (f_b + f_m) on the free vertices (forces evaluated afresh)."""
+    m = I.cylinder_mesh(8, 0.5, 0.6, 0.6, 0.1, 3, "SS", "ends")
+    mat = dict(I.MATERIAL)
+    st = O.Stencils("SS", m.X, m.tris, mat["young"], mat["poisson"], mat["thickness"])
+    mass = O.mass(m.X, m.tris, mat["density"], mat["thickness"])
+    dt = 1 / 30
+    grav = np.array([0.0, 0.0, -9.81])
+    xhat = m.X + dt * dt * grav * (m.pinned == 0)[:, None]
+    energies = [_membrane_energy(st, mass, xhat, xhat, dt)]
+    for k in (1, 2, 3, 4):
+        sim = O.MembraneSim(st, mat, m.pinned)
+        sim.step(dt, max_newton=k, newton_rtol=0.0, pcg_rtol=1e-10)
+        energies.append(_membrane_energy(st, mass, xhat, sim.x, dt))
+    assert all(b < a for a, b in zip(energies, energies[1:]))
+    dt = 1e-3
+    sim = O.MembraneSim(st, mat, m.pinned)
+    counts, halv, stats = sim.step(dt, max_newton=20, newton_rtol=1e-8, pcg_rtol=1e-12)
+    assert stats["grad_norm"] <= 1e-8 * stats["grad_norm0"] and stats["newton_iters"] < 20
+    fb, _ = st.forces(sim.x)
+    fm, _ = O.membrane_forces(st, sim.x)
+    xh = m.X + dt * dt * grav * (m.pinned == 0)[:, None]
+    res = (mass[:, None] * (sim.x - xh) - dt * dt * (fb + fm))[m.pinned == 0]
+    assert np.abs(res).max() <= 1e-8 * np.abs(dt * dt * fm).max()
+
+
 # ------------------------------------------------------------------ P9/P10: dynamics
 
 
