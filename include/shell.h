@@ -84,11 +84,17 @@ typedef struct {
  * model the build returns SHELL_E_INVALID_ARG. */
 #define SHELL_FLAG_WORLD_FRAME 2
 
-/* Adds the membrane of Sec. 3 (eq 1) to shell_eval_forces: constant strain triangles with the Saint
- * Venant-Kirchhoff model, D_m = h E_el (plane stress), energy A/2 eps^T D_m eps of the Green strain per
- * triangle, on every triangle of the mesh and for any model.  The implicit step does not take it
- * (shell_sim_create returns SHELL_E_UNSUPPORTED): the membrane's Hessian couples the coordinates and must
- * follow the deformation, which the step's constant K_s (x) I3 matrix cannot carry.  A degenerate
+/* Adds the membrane of Sec. 3 (eq 1): constant strain triangles with the Saint Venant-Kirchhoff model,
+ * D_m = h E_el (plane stress), energy A/2 eps^T D_m eps of the Green strain per triangle, on every
+ * triangle of the mesh and for any model.  shell_eval_forces adds its force and energy (both precisions).
+ * The implicit step takes it in float64, one simulation at a time: each Newton iteration assembles the
+ * membrane's Gauss-Newton tangent A B(F)^T D_m B(F) (positive semi-definite; its Hessian at rest) into
+ * 3x3 blocks, solves (M + dt^2 (K_s (x) I3 + K_GN)) y = -g by one Jacobi-PCG over all coordinates (the
+ * membrane couples them; 1/(m + dt^2 (K_s,ii + tr(K_GN,ii)/3)) per vertex), then backtracks x += 2^-h y,
+ * h the fewest halvings (at most 6) that satisfy Armijo's condition E(x + a y) <= E(x) + 1e-4 a g.y on
+ * the incremental potential.  In its step statistics counts[k][0] is the PCG count and counts[k][1] the
+ * halvings of Newton iteration k; REPLAY takes both from replay_counts the same way.  Batches, the
+ * quasi-static solve and mixed precision refuse such simulations (SHELL_E_UNSUPPORTED).  A degenerate
  * triangle is SHELL_E_DEGENERATE. */
 #define SHELL_FLAG_MEMBRANE 4
 
@@ -206,7 +212,7 @@ shell_status_t shell_hessian_apply(shell_hessian_t h, const double* mass, double
  * x0, v0 host [nv][3] (v0 may be NULL = zero); pinned host [nv], 1 = all three coordinates held at
  * x0 (fixed boundary nodes, Sec. 4.3), may be NULL.  The lumped mass rho h sum(A_T)/3 is computed
  * from the rest mesh.  The stencils and Hessian must outlive the simulation.  Stencils built with
- * SHELL_FLAG_MEMBRANE are refused (SHELL_E_UNSUPPORTED).
+ * SHELL_FLAG_MEMBRANE give the step with the membrane (float64 only, else SHELL_E_UNSUPPORTED).
  */
 shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const double* x0, const double* v0,
                                 const uint8_t* pinned, shell_sim_t* out);

@@ -421,9 +421,9 @@ shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const do
     return guarded([&]() -> shell_status_t {
         SHELL_CHECK(st && h && out && (x0 || st->nv == 0) && h->st == st, SHELL_E_INVALID_ARG, "bad argument");
         *out = nullptr;
-        SHELL_CHECK(!(st->cfg_flags & SHELL_FLAG_MEMBRANE), SHELL_E_UNSUPPORTED,
-                    "the implicit step does not take the membrane (its Hessian couples the coordinates and follows "
-                    "the deformation); build the stencils without SHELL_FLAG_MEMBRANE");
+        const bool membrane = (st->cfg_flags & SHELL_FLAG_MEMBRANE) != 0;
+        SHELL_CHECK(!membrane || st->precision == SHELL_PREC_FP64, SHELL_E_UNSUPPORTED,
+                    "the implicit step with the membrane runs in float64 only");
         auto sim = std::make_unique<shell_sim_s>();
         sim->st = st;
         sim->h = h;
@@ -446,7 +446,9 @@ shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const do
         sim->pinned.upload(pi.data(), pi.size(), s);
         sim_mass(*sim, s);
         SHELL_HIP(hipStreamSynchronize(s));
-        if (nv > 0) {
+        if (nv > 0 && membrane) {
+            membrane_sim_init(*sim, s);
+        } else if (nv > 0) {
             auto solo = std::make_unique<shell_batch_s>();
             solo->sims = {sim.get()};
             batch_init(*solo);
@@ -464,7 +466,11 @@ shell_status_t shell_step_implicit(shell_sim_t sim, const shell_step_params_t* p
         const shell_step_params_t& p = *params;
         check_params(p);
         shell_status_t rc = SHELL_OK;
-        if (sim->nv > 0) {
+        if (sim->ms) {
+            SHELL_CHECK(p.max_newton <= SHELL_MAX_NEWTON, SHELL_E_INVALID_ARG, "max_newton out of range");
+            shell_step_stats_t st{};
+            rc = membrane_step(*sim, p, st, as_stream(stream));
+        } else if (sim->nv > 0) {
             rc = batch_step(*sim->solo, &p, 1, nullptr, as_stream(stream));
         } else {
             sim->stats = shell_step_stats_t{};
@@ -487,6 +493,7 @@ shell_status_t shell_solve_static(shell_sim_t sim, const shell_static_params_t* 
         const shell_static_params_t& q = *params;
         SHELL_CHECK(q.eps_f >= 0.0 && std::isfinite(q.eps_f), SHELL_E_INVALID_ARG, "eps_f must be >= 0");
         SHELL_CHECK(q.eps_u >= 0.0 && std::isfinite(q.eps_u), SHELL_E_INVALID_ARG, "eps_u must be >= 0");
+        SHELL_CHECK(!sim->ms, SHELL_E_UNSUPPORTED, "the quasi-static solve does not take the membrane");
         shell_step_params_t p{};
         p.dt = 1.0;  // unused by the quasi-static path
         p.max_newton = q.max_newton;

@@ -267,6 +267,26 @@ struct shell_hessian_s {
 };
 
 
+namespace shell {
+// The implicit step of a shell with its membrane (SHELL_FLAG_MEMBRANE), float64: K_s as CSR, the membrane's
+// Gauss-Newton tangent as 3x3 blocks on the triangle adjacency, one PCG over all coordinates, line search.
+struct MembraneSolve {
+    DevArray<int64_t> srow;  // K_s CSR (internal order)
+    DevArray<int32_t> scol;
+    DevArray<double> sval;
+    DevArray<int64_t> mrow;  // membrane block pattern: each vertex and its triangle neighbours, sorted
+    DevArray<int32_t> mcol;
+    DevArray<int64_t> mdiag; // [nv] slot of the diagonal block
+    DevArray<double> mval;   // [nnz][9] row-major 3x3 blocks
+    DevArray<double> rest;   // [nt][5] G = Dm^-1 and the rest area
+    DevArray<double> xtry, ftry, z, p, q, y, r, dinv, part;
+    DevArray<double> scal;   // device scalars of the PCG and the energies
+    DevArray<ForceDesc> fdesc;   // bending force at xtry with energy partials
+    DevArray<WorkItem> items;
+    int64_t ngroups = 0;
+};
+}  // namespace shell
+
 struct shell_sim_s {
     shell_stencils_s* st = nullptr;
     shell_hessian_s* h = nullptr;
@@ -287,6 +307,7 @@ struct shell_sim_s {
     // quasi-static solves only: zero mass, the applied load (internal order), the Newton step's scale
     shell::DevArray<double> zmass, fext, ustep;
     shell_batch_s* solo = nullptr;       // this simulation alone, as a batch of one
+    std::unique_ptr<shell::MembraneSolve> ms;  // stencils built with SHELL_FLAG_MEMBRANE
     shell_step_stats_t stats{};
 };
 
@@ -376,6 +397,10 @@ void launch_energy_finalize(const double* epart, int64_t n, double add, double* 
 // from positions (FP64) or from displacements u4 [nv][4] and the rest positions (mixed)
 void launch_membrane_rest(shell_stencils_s& st, hipStream_t s);
 void launch_membrane_forces(shell_stencils_s& st, const double* pos, const double* u4, void* f, hipStream_t s);
+// the implicit step with the membrane: set-up once per simulation, then one step (float64)
+void membrane_sim_init(shell_sim_s& sim, hipStream_t s);
+shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, shell_step_stats_t& out,
+                             hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
 // dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order padded displacements
 void launch_gather_displacements(const double* src, const int32_t* perm, const double* X, double* dst, int64_t nv,

@@ -9,6 +9,9 @@
 // repeat): each work-group accumulates the forces of its own vertices in LDS and adds them to the force
 // the bending kernel stored, one read and one write per vertex and no global atomics.  In mixed precision
 // the edge vectors are the rest edges plus the displacement differences, in float64.
+#include <algorithm>
+#include <cmath>
+
 #include "devmath.hpp"
 #include "internal.hpp"
 
@@ -114,6 +117,319 @@ __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __r
     if (threadIdx.x == 0) epart[blk] = en[0];
 }
 
+// ---------------------------------------------------------------- implicit step with the membrane
+//
+// Sec. 5's step (eq 62) with the membrane of Sec. 3 added to the bending energy.  Each Newton iteration:
+// g = M (x - x_hat) - dt^2 f (fixed rows zero); the matrix M + dt^2 (K_s (x) I3 + K_GN(x)) with K_GN the
+// membrane's Gauss-Newton tangent A B(F)^T D_m B(F) per triangle (B(F) the linearised Green strain, rows
+// g_j0 F0^T, g_j1 F1^T, g_j1 F0^T + g_j0 F1^T), assembled into 3x3 blocks on the triangle adjacency; one
+// Jacobi-PCG over all coordinates (1/(m + dt^2 (K_s,ii + tr(K_GN,ii)/3)) per vertex); then x += 2^-h y
+// with h the fewest halvings (at most 6) meeting Armijo's condition E(x + a y) <= E(x) + 1e-4 a g.y on the
+// incremental potential E = 1/2 (x - x_hat)^T M (x - x_hat) + dt^2 (Psi_b + Psi_m).  Sums are per
+// 256-thread block, then in a fixed order by one block, so they do not depend on scheduling.
+
+constexpr int kMsBlk = 256;
+// device scalars
+enum : int { S_RZ, S_RZN, S_PQ, S_RR, S_RR0, S_TOL2, S_ALPHA, S_BETA, S_GSQ, S_SLOPE, S_E, S_IT, S_TARGET,
+             S_ACTIVE, S_REPLAY, S_BUDGET, S_COUNT };
+
+template <int NQ>
+__device__ __forceinline__ void ms_partials(double (&v)[NQ], double* part, long ngroups) {
+    __shared__ double sh[NQ * (kMsBlk / 64)];
+    block_sum<NQ>(v, sh);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < NQ; ++q) part[q * ngroups + blockIdx.x] = v[q];
+}
+
+// totals of NQ partial arrays, valid in thread 0 of a single block
+template <int NQ>
+__device__ __forceinline__ void ms_totals(const double* part, long ngroups, double (&out)[NQ]) {
+    for (int q = 0; q < NQ; ++q) out[q] = 0.0;
+    for (long b = threadIdx.x; b < ngroups; b += blockDim.x)
+        for (int q = 0; q < NQ; ++q) out[q] += part[q * ngroups + b];
+    __shared__ double sh[NQ * (kMsBlk / 64)];
+    block_sum<NQ>(out, sh);
+}
+
+__global__ void ms_predictor(double* __restrict__ x, const double* __restrict__ v, double* __restrict__ xt,
+                             double* __restrict__ xhat, const uint8_t* __restrict__ pinned, long nv, double dt,
+                             double gx, double gy, double gz) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    const double gr[3] = {gx, gy, gz};
+    for (int c = 0; c < 3; ++c) {
+        const double xi = x[3 * i + c];
+        const double xh = pinned[i] ? xi : xi + dt * v[3 * i + c] + dt * dt * gr[c];
+        xt[3 * i + c] = xi;
+        xhat[3 * i + c] = xh;
+        x[3 * i + c] = xh;
+    }
+}
+
+__global__ void ms_axpy(const double* __restrict__ x, const double* __restrict__ y, double a, double* __restrict__ out,
+                        long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) out[i] = x[i] + a * y[i];
+}
+
+__global__ void ms_velocity(const double* __restrict__ x, const double* __restrict__ xt, double* __restrict__ v,
+                            long n, double dt) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) v[i] = (x[i] - xt[i]) / dt;
+}
+
+// partials of the inertia term 1/2 m |x - x_hat|^2
+__global__ __launch_bounds__(kMsBlk) void ms_inertia(const double* __restrict__ x, const double* __restrict__ xhat,
+                                                     const double* __restrict__ mass, long nv,
+                                                     double* __restrict__ part, long ngroups) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < nv)
+        for (int c = 0; c < 3; ++c) {
+            const double u = x[3 * i + c] - xhat[3 * i + c];
+            v[0] += 0.5 * mass[i] * u * u;
+        }
+    ms_partials<1>(v, part, ngroups);
+}
+
+// E = inertia + dt^2 (bending + membrane) into the scalars
+__global__ __launch_bounds__(kMsBlk) void ms_energy(const double* __restrict__ eb, long nb,
+                                                    const double* __restrict__ em, long nm, double add,
+                                                    const double* __restrict__ part, long ngroups, double dt2,
+                                                    double* __restrict__ scal) {
+    double t[1];
+    ms_totals<1>(part, ngroups, t);
+    double b = 0.0;
+    for (long k = threadIdx.x; k < nb; k += blockDim.x) b += eb[k];
+    for (long k = threadIdx.x; k < nm; k += blockDim.x) b += em[k];
+    double v[1] = {b};
+    __shared__ double sh[kMsBlk / 64];
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) scal[S_E] = t[0] + dt2 * (v[0] + add);
+}
+
+// g = M (x - x_hat) - dt^2 f, fixed rows zero; partial |g|^2
+__global__ __launch_bounds__(kMsBlk) void ms_grad(const double* __restrict__ x, const double* __restrict__ xhat,
+                                                  const double* __restrict__ mass, const double* __restrict__ f,
+                                                  const uint8_t* __restrict__ pinned, long nv, double dt2,
+                                                  double* __restrict__ g, double* __restrict__ part, long ngroups) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < nv)
+        for (int c = 0; c < 3; ++c) {
+            const double gi = pinned[i] ? 0.0 : mass[i] * (x[3 * i + c] - xhat[3 * i + c]) - dt2 * f[3 * i + c];
+            g[3 * i + c] = gi;
+            v[0] += gi * gi;
+        }
+    ms_partials<1>(v, part, ngroups);
+}
+
+__global__ __launch_bounds__(kMsBlk) void ms_dot(const double* __restrict__ a, const double* __restrict__ b, long n,
+                                                 double* __restrict__ part, long ngroups) {
+    double v[1] = {0.0};
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x)
+        v[0] += a[i] * b[i];
+    ms_partials<1>(v, part, ngroups);
+}
+
+__global__ __launch_bounds__(kMsBlk) void ms_fin1(const double* __restrict__ part, long ngroups,
+                                                  double* __restrict__ scal, int slot) {
+    double t[1];
+    ms_totals<1>(part, ngroups, t);
+    if (threadIdx.x == 0) scal[slot] = t[0];
+}
+
+__device__ __forceinline__ long ms_find(const int64_t* __restrict__ row, const int32_t* __restrict__ col, long i,
+                                        int j) {
+    long lo = row[i], hi = row[i + 1] - 1;
+    while (lo < hi) {
+        const long mid = (lo + hi) >> 1;
+        if (col[mid] < j) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Gauss-Newton tangent of the membrane per triangle, added into the 3x3 blocks
+__global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict__ tris, long nt,
+                      const double* __restrict__ x, double c, double nu, const int64_t* __restrict__ mrow,
+                      const int32_t* __restrict__ mcol, double* __restrict__ mval) {
+    long t = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (t >= nt) return;
+    const long v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+    const double G[2][2] = {{rest[5 * t], rest[5 * t + 1]}, {rest[5 * t + 2], rest[5 * t + 3]}};
+    const double A = rest[5 * t + 4];
+    double F[3][2];
+    for (int i = 0; i < 3; ++i) {
+        const double d1 = x[3 * v[1] + i] - x[3 * v[0] + i], d2 = x[3 * v[2] + i] - x[3 * v[0] + i];
+        for (int b = 0; b < 2; ++b) F[i][b] = d1 * G[0][b] + d2 * G[1][b];
+    }
+    const double g[3][2] = {{-G[0][0] - G[1][0], -G[0][1] - G[1][1]}, {G[0][0], G[0][1]}, {G[1][0], G[1][1]}};
+    double Bm[3][9];
+    for (int j = 0; j < 3; ++j)
+        for (int i = 0; i < 3; ++i) {
+            Bm[0][3 * j + i] = g[j][0] * F[i][0];
+            Bm[1][3 * j + i] = g[j][1] * F[i][1];
+            Bm[2][3 * j + i] = g[j][1] * F[i][0] + g[j][0] * F[i][1];
+        }
+    // D_m B (D_m = c [[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu)/2]])
+    double DB[3][9];
+    for (int q = 0; q < 9; ++q) {
+        DB[0][q] = c * (Bm[0][q] + nu * Bm[1][q]);
+        DB[1][q] = c * (nu * Bm[0][q] + Bm[1][q]);
+        DB[2][q] = c * 0.5 * (1.0 - nu) * Bm[2][q];
+    }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            const long slot = ms_find(mrow, mcol, v[a], int(v[b]));
+            for (int ca = 0; ca < 3; ++ca)
+                for (int cb = 0; cb < 3; ++cb) {
+                    const int pa = 3 * a + ca, pb = 3 * b + cb;
+                    const double k = A * (Bm[0][pa] * DB[0][pb] + Bm[1][pa] * DB[1][pb] + Bm[2][pa] * DB[2][pb]);
+                    atomicAdd(mval + 9 * slot + 3 * ca + cb, k);
+                }
+        }
+}
+
+__global__ void ms_dinv(const double* __restrict__ kdiag, const double* __restrict__ mval,
+                        const int64_t* __restrict__ mdiag, const double* __restrict__ mass,
+                        const uint8_t* __restrict__ pinned, long nv, double dt2, double* __restrict__ dinv) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    const double* b = mval + 9 * mdiag[i];
+    const double d = mass[i] + dt2 * (kdiag[i] + (b[0] + b[4] + b[8]) / 3.0);
+    dinv[i] = (pinned[i] || d == 0.0) ? 0.0 : 1.0 / d;
+}
+
+// r = -g, y = 0, z = D^-1 r, p = z; partials r.z, r.r
+__global__ __launch_bounds__(kMsBlk) void ms_pcg_init(const double* __restrict__ g, const double* __restrict__ dinv,
+                                                      double* __restrict__ r, double* __restrict__ z,
+                                                      double* __restrict__ p, double* __restrict__ y, long nv,
+                                                      double* __restrict__ part, long ngroups) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < nv)
+        for (int c = 0; c < 3; ++c) {
+            const double ri = -g[3 * i + c], zi = dinv[i] * ri;
+            r[3 * i + c] = ri;
+            z[3 * i + c] = zi;
+            p[3 * i + c] = zi;
+            y[3 * i + c] = 0.0;
+            v[0] += ri * zi;
+            v[1] += ri * ri;
+        }
+    ms_partials<2>(v, part, ngroups);
+}
+
+__global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__ part, long ngroups,
+                                                      double* __restrict__ scal, double rtol2, int target,
+                                                      int replay) {
+    double t[2];
+    ms_totals<2>(part, ngroups, t);
+    if (threadIdx.x == 0) {
+        scal[S_RZ] = t[0];
+        scal[S_RR0] = t[1];
+        scal[S_RR] = t[1];
+        scal[S_TOL2] = rtol2 * t[1];
+        scal[S_IT] = 0.0;
+        scal[S_TARGET] = double(target);
+        scal[S_REPLAY] = double(replay);
+        scal[S_BUDGET] = 0.0;
+        scal[S_ACTIVE] = (0 < target && (replay || t[1] > rtol2 * t[1])) ? 1.0 : 0.0;
+    }
+}
+
+// q = M p + dt^2 (K_s (x) I3 + K_GN) p, fixed rows zero; partial p.q
+__global__ __launch_bounds__(kMsBlk) void ms_apply(const double* __restrict__ scal, const int64_t* __restrict__ srow,
+                                                   const int32_t* __restrict__ scol, const double* __restrict__ sval,
+                                                   const int64_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
+                                                   const double* __restrict__ mval, const double* __restrict__ mass,
+                                                   const uint8_t* __restrict__ pinned, const double* __restrict__ p,
+                                                   double* __restrict__ q, long nv, double dt2,
+                                                   double* __restrict__ part, long ngroups) {
+    if (scal[S_ACTIVE] == 0.0) return;
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    double v[1] = {0.0};
+    if (i < nv) {
+        double a[3] = {0.0, 0.0, 0.0};
+        for (long e = srow[i]; e < srow[i + 1]; ++e) {
+            const long j = scol[e];
+            const double k = sval[e];
+            for (int c = 0; c < 3; ++c) a[c] += k * p[3 * j + c];
+        }
+        for (long e = mrow[i]; e < mrow[i + 1]; ++e) {
+            const long j = mcol[e];
+            const double* b = mval + 9 * e;
+            for (int c = 0; c < 3; ++c) a[c] += b[3 * c] * p[3 * j] + b[3 * c + 1] * p[3 * j + 1] + b[3 * c + 2] * p[3 * j + 2];
+        }
+        for (int c = 0; c < 3; ++c) {
+            const double qi = pinned[i] ? 0.0 : mass[i] * p[3 * i + c] + dt2 * a[c];
+            q[3 * i + c] = qi;
+            v[0] += p[3 * i + c] * qi;
+        }
+    }
+    ms_partials<1>(v, part, ngroups);
+}
+
+__global__ __launch_bounds__(kMsBlk) void ms_fin_apply(const double* __restrict__ part, long ngroups,
+                                                       double* __restrict__ scal) {
+    if (scal[S_ACTIVE] == 0.0) return;
+    double t[1];
+    ms_totals<1>(part, ngroups, t);
+    if (threadIdx.x == 0) {
+        scal[S_PQ] = t[0];
+        scal[S_ALPHA] = t[0] != 0.0 ? scal[S_RZ] / t[0] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kMsBlk) void ms_update(const double* __restrict__ scal, const double* __restrict__ p,
+                                                    const double* __restrict__ q, const double* __restrict__ dinv,
+                                                    double* __restrict__ y, double* __restrict__ r,
+                                                    double* __restrict__ z, long nv, double* __restrict__ part,
+                                                    long ngroups) {
+    if (scal[S_ACTIVE] == 0.0) return;
+    const double al = scal[S_ALPHA];
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    double v[2] = {0.0, 0.0};
+    if (i < nv)
+        for (int c = 0; c < 3; ++c) {
+            y[3 * i + c] += al * p[3 * i + c];
+            const double ri = r[3 * i + c] - al * q[3 * i + c], zi = dinv[i] * ri;
+            r[3 * i + c] = ri;
+            z[3 * i + c] = zi;
+            v[0] += ri * zi;
+            v[1] += ri * ri;
+        }
+    ms_partials<2>(v, part, ngroups);
+}
+
+__global__ __launch_bounds__(kMsBlk) void ms_fin_update(const double* __restrict__ part, long ngroups,
+                                                        double* __restrict__ scal) {
+    if (scal[S_ACTIVE] == 0.0) return;
+    double t[2];
+    ms_totals<2>(part, ngroups, t);
+    if (threadIdx.x == 0) {
+        const double rz = scal[S_RZ];
+        scal[S_BETA] = rz != 0.0 ? t[0] / rz : 0.0;
+        scal[S_RZ] = t[0];
+        scal[S_RR] = t[1];
+        const double it = scal[S_IT] + 1.0, target = scal[S_TARGET];
+        const bool replay = scal[S_REPLAY] != 0.0;
+        const bool more = replay || t[1] > scal[S_TOL2];
+        if (!replay && it >= target && more) scal[S_BUDGET] = 1.0;
+        scal[S_IT] = it;
+        scal[S_ACTIVE] = (it < target && more && isfinite(t[1])) ? 1.0 : 0.0;
+        if (!isfinite(t[1])) scal[S_BUDGET] = 2.0;
+    }
+}
+
+// p = z + beta p (for the next iteration; skipped once the recurrence has stopped)
+__global__ void ms_dir(const double* __restrict__ scal, const double* __restrict__ z, double* __restrict__ p, long n) {
+    if (scal[S_ACTIVE] == 0.0) return;
+    const double be = scal[S_BETA];
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = z[i] + be * p[i];
+}
+
 }  // namespace
 
 void launch_membrane_rest(shell_stencils_s& st, hipStream_t s) {
@@ -157,6 +473,222 @@ void launch_membrane_forces(shell_stencils_s& st, const double* pos, const doubl
                                                                st.nv, st.T, c, st.poisson, static_cast<double*>(f),
                                                                st.mepart.p);
     SHELL_HIP(hipGetLastError());
+}
+
+namespace {
+
+__global__ void ms_gather_csr(const double* __restrict__ val, const int64_t* __restrict__ csr2sell, long nnz,
+                              double* __restrict__ out) {
+    long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (e < nnz) out[e] = val[csr2sell[e]];
+}
+
+__global__ void ms_zero(double* __restrict__ p, long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+inline unsigned ms_grid(long n) { return unsigned(std::max(1L, (n + kMsBlk - 1) / kMsBlk)); }
+
+}  // namespace
+
+void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
+    shell_stencils_s& st = *sim.st;
+    shell_hessian_s& h = *sim.h;
+    auto ms = std::make_unique<MembraneSolve>();
+    const long nv = st.nv, nt = st.nt, n3 = 3 * nv;
+    // K_s as CSR from the assembled SELL slots
+    const SellPattern& pat = h.pat;
+    ms->srow.alloc(pat.rowptr.size());
+    ms->srow.upload(pat.rowptr.data(), pat.rowptr.size(), s);
+    ms->scol.alloc(std::max<size_t>(pat.col.size(), 1));
+    ms->scol.upload(pat.col.data(), pat.col.size(), s);
+    ms->sval.alloc(std::max<size_t>(pat.col.size(), 1));
+    DevArray<int64_t> c2s(std::max<size_t>(pat.csr2sell.size(), 1));
+    c2s.upload(pat.csr2sell.data(), pat.csr2sell.size(), s);
+    if (!pat.col.empty())
+        ms_gather_csr<<<ms_grid(long(pat.col.size())), kMsBlk, 0, s>>>(h.val.p, c2s.p, long(pat.col.size()),
+                                                                        ms->sval.p);
+    // membrane block pattern: each vertex, its triangle neighbours and itself, sorted
+    std::vector<std::vector<int32_t>> nb(static_cast<size_t>(nv));
+    for (long i = 0; i < nv; ++i) nb[size_t(i)].push_back(int32_t(i));
+    for (long t = 0; t < nt; ++t)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (a != b) nb[size_t(st.h_tris[size_t(3 * t + a)])].push_back(st.h_tris[size_t(3 * t + b)]);
+    std::vector<int64_t> mrow(size_t(nv + 1), 0), mdiag(size_t(nv), 0);
+    std::vector<int32_t> mcol;
+    for (long i = 0; i < nv; ++i) {
+        auto& v = nb[size_t(i)];
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        for (int32_t j : v) {
+            if (j == i) mdiag[size_t(i)] = int64_t(mcol.size());
+            mcol.push_back(j);
+        }
+        mrow[size_t(i + 1)] = int64_t(mcol.size());
+    }
+    ms->mrow.alloc(mrow.size());
+    ms->mrow.upload(mrow.data(), mrow.size(), s);
+    ms->mcol.alloc(std::max<size_t>(mcol.size(), 1));
+    ms->mcol.upload(mcol.data(), mcol.size(), s);
+    ms->mdiag.alloc(std::max<size_t>(mdiag.size(), 1));
+    ms->mdiag.upload(mdiag.data(), mdiag.size(), s);
+    ms->mval.alloc(std::max<size_t>(9 * mcol.size(), 1));
+    // per-triangle rest data
+    ms->rest.alloc(size_t(std::max(5 * nt, 1L)));
+    DevArray<int32_t> bad(1);
+    SHELL_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
+    if (nt > 0) membrane_rest<<<int((nt + 255) / 256), 256, 0, s>>>(st.X.p, st.tris.p, nt, ms->rest.p, bad.p);
+    for (auto* a : {&ms->xtry, &ms->ftry, &ms->z, &ms->p, &ms->q, &ms->y, &ms->r})
+        a->alloc(size_t(std::max(n3, 1L)));
+    ms->dinv.alloc(size_t(std::max(nv, 1L)));
+    ms->ngroups = long(ms_grid(nv));
+    ms->part.alloc(size_t(2 * ms->ngroups + std::max<int64_t>(st.nblocks, 1)));
+    ms->scal.alloc(S_COUNT);
+    // bending force at xtry into ftry, with its energy partials after the reduction partials
+    ForceDesc d{};
+    d.x = ms->xtry.p;
+    d.f = ms->ftry.p;
+    d.epart = ms->part.p + 2 * ms->ngroups;
+    d.bias = st.bias.p;
+    d.boff = st.boff.p;
+    d.tidx = st.tidx.p;
+    d.trec = st.trec64.p;
+    d.nst = st.nst_pad;
+    d.nv = st.nv;
+    d.T = st.T;
+    d.model = st.model;
+    d.kb = st.kb;
+    d.nu = st.poisson;
+    std::vector<WorkItem> items(size_t(st.nblocks));
+    for (int64_t t = 0; t < st.nblocks; ++t) items[size_t(t)] = {0, int32_t(t)};
+    ms->fdesc.alloc(1);
+    ms->fdesc.upload(&d, 1, s);
+    ms->items.alloc(std::max<size_t>(items.size(), 1));
+    ms->items.upload(items.data(), items.size(), s);
+    int32_t hb = 0;
+    bad.download(&hb, 1, s);
+    SHELL_HIP(hipStreamSynchronize(s));  // the staging above is released on return
+    SHELL_CHECK(hb == 0, SHELL_E_DEGENERATE, "degenerate triangle (zero area) for the membrane");
+    sim.ms = std::move(ms);
+}
+
+shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, shell_step_stats_t& out,
+                             hipStream_t s) {
+    shell_stencils_s& st = *sim.st;
+    MembraneSolve& m = *sim.ms;
+    const long nv = sim.nv, n3 = 3 * nv, nt = st.nt, ng = m.ngroups;
+    const double dt = p.dt, dt2 = dt * dt;
+    const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
+    double* part = m.part.p;
+    double* eb = m.part.p + 2 * ng;
+    out = shell_step_stats_t{};
+    double hs[S_COUNT];
+    auto read_scal = [&]() {
+        SHELL_HIP(hipMemcpyAsync(hs, m.scal.p, sizeof(hs), hipMemcpyDeviceToHost, s));
+        SHELL_HIP(hipStreamSynchronize(s));
+    };
+    // energy and force at xtry (force into ftry)
+    auto evaluate = [&]() {
+        launch_force_items(st.model, SHELL_PREC_FP64, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
+        launch_membrane_forces(st, m.xtry.p, nullptr, m.ftry.p, s);
+        ms_inertia<<<ms_grid(nv), kMsBlk, 0, s>>>(m.xtry.p, sim.xhat.p, sim.mass.p, nv, part, ng);
+        ms_energy<<<1, kMsBlk, 0, s>>>(eb, st.nblocks, st.mepart.p, st.nblocks, st.bias_e0, part, ng, dt2,
+                                       m.scal.p);
+        SHELL_HIP(hipGetLastError());
+        read_scal();
+        return hs[S_E];
+    };
+    ms_predictor<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.x.p, sim.v.p, sim.xt.p, sim.xhat.p, sim.pinned.p, nv, dt,
+                                                 p.gravity[0], p.gravity[1], p.gravity[2]);
+    SHELL_HIP(hipMemcpyAsync(m.xtry.p, sim.x.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    double E = evaluate();
+    SHELL_HIP(hipMemcpyAsync(sim.f.p, m.ftry.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const bool replay = p.mode == SHELL_PCG_REPLAY;
+    double gn0 = 0.0, gn = 0.0;
+    bool budget = false, nonfinite = false;
+    for (int k = 0;; ++k) {
+        ms_grad<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.x.p, sim.xhat.p, sim.mass.p, sim.f.p, sim.pinned.p, nv, dt2,
+                                               sim.g.p, part, ng);
+        ms_fin1<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, S_GSQ);
+        read_scal();
+        if (!std::isfinite(hs[S_GSQ])) {
+            nonfinite = true;
+            break;
+        }
+        gn = std::sqrt(hs[S_GSQ]);
+        if (k == 0) gn0 = gn;
+        if (gn0 == 0.0 || (k > 0 && gn <= p.newton_rtol * gn0) || k == p.max_newton) break;
+        // Gauss-Newton matrix and its Jacobi preconditioner
+        const long nb9 = long(m.mval.n);
+        ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
+        if (nt > 0)
+            ms_gn<<<ms_grid(nt), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, nt, sim.x.p, c, st.poisson, m.mrow.p,
+                                                 m.mcol.p, m.mval.p);
+        ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.mass.p, sim.pinned.p, nv,
+                                               dt2, m.dinv.p);
+        // one PCG over all coordinates
+        const int target = replay ? p.replay_counts[3 * k] : p.max_pcg;
+        ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.g.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, part, ng);
+        ms_fin_init<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, p.pcg_rtol * p.pcg_rtol, target, replay ? 1 : 0);
+        SHELL_HIP(hipGetLastError());
+        read_scal();
+        int chunk = 16;
+        while (hs[S_ACTIVE] != 0.0) {
+            for (int it = 0; it < chunk; ++it) {
+                ms_apply<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p,
+                                                        m.mval.p, sim.mass.p, sim.pinned.p, m.p.p, m.q.p, nv, dt2,
+                                                        part, ng);
+                ms_fin_apply<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
+                ms_update<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.p.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
+                                                         part, ng);
+                ms_fin_update<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
+                ms_dir<<<ms_grid(n3), kMsBlk, 0, s>>>(m.scal.p, m.z.p, m.p.p, n3);
+            }
+            SHELL_HIP(hipGetLastError());
+            read_scal();
+            chunk = std::min(2 * chunk, 256);
+        }
+        if (hs[S_BUDGET] == 2.0) {
+            nonfinite = true;
+            break;
+        }
+        budget |= hs[S_BUDGET] != 0.0;
+        const int its = int(hs[S_IT]);
+        // Armijo backtracking on the incremental potential
+        ms_dot<<<unsigned(ng), kMsBlk, 0, s>>>(sim.g.p, m.y.p, n3, part, ng);  // grid-stride: one partial per group
+        ms_fin1<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, S_SLOPE);
+        read_scal();
+        const double slope = hs[S_SLOPE];
+        int halv = 0;
+        double a = 1.0, Etry = 0.0;
+        for (;;) {
+            ms_axpy<<<ms_grid(n3), kMsBlk, 0, s>>>(sim.x.p, m.y.p, a, m.xtry.p, n3);
+            Etry = evaluate();
+            const bool done = replay ? halv >= p.replay_counts[3 * k + 1] : (Etry <= E + 1e-4 * a * slope || halv == 6);
+            if (done) break;
+            a *= 0.5;
+            ++halv;
+        }
+        SHELL_HIP(hipMemcpyAsync(sim.x.p, m.xtry.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
+        SHELL_HIP(hipMemcpyAsync(sim.f.p, m.ftry.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
+        E = Etry;
+        out.counts[k][0] = its;
+        out.counts[k][1] = halv;
+        out.pcg_total += its;
+        out.newton_iters++;
+    }
+    ms_velocity<<<ms_grid(n3), kMsBlk, 0, s>>>(sim.x.p, sim.xt.p, sim.v.p, n3, dt);
+    SHELL_HIP(hipGetLastError());
+    SHELL_HIP(hipStreamSynchronize(s));
+    out.grad_norm0 = gn0;
+    out.grad_norm = gn;
+    out.status = nonfinite ? SHELL_E_NONFINITE : (budget ? SHELL_E_BUDGET : SHELL_OK);
+    sim.stats = out;
+    sim.step++;
+    sim.last_stream = s;
+    return shell_status_t(out.status);
 }
 
 }  // namespace shell

@@ -637,6 +637,7 @@ void batch_init(shell_batch_s& b) {
     b.precision = b.sims[0]->st->precision;
     b.max_T = 64;
     for (size_t m = 0; m < n; ++m) {
+        SHELL_CHECK(!b.sims[m]->ms, SHELL_E_UNSUPPORTED, "a simulation with the membrane steps alone");
         SHELL_CHECK(b.sims[m]->st->precision == b.precision, SHELL_E_INVALID_ARG,
                     "all simulations of a batch need the same precision");
         for (size_t q = 0; q < m; ++q)
