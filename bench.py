@@ -204,6 +204,46 @@ def membrane_timing(S, I, torch, reps=20):
     return out
 
 
+def membrane_step_timing(S, I, torch, sizes=(64, 256), steps=2):
+    """The implicit step of the smoothed-hinge shell with its membrane (FP64; Gauss-Newton membrane tangent,
+    coupled Jacobi-PCG, Armijo backtracking) on a cylinder patch of radius 0.5 m held at its ends, dt = 1/30,
+    Newton budget 4, PCG rtol 1e-2 (the headline step's settings): time per step and its iteration counts."""
+    out = {}
+    for n in sizes:
+        mesh = I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+        pb = S.Problem(mesh, I.MATERIAL, model="SS", flags=S.SHELL_FLAG_MEMBRANE)
+        params, _ = S.step_params(1 / 30, max_newton=4, newton_rtol=1e-8, pcg_rtol=1e-2)
+        S.shell_step_implicit(pb.sim, params)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stats = [S.shell_step_implicit(pb.sim, params)[1] for _ in range(steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        pcg = sum(st["pcg_total"] for st in stats)
+        out[f"SS_membrane_cylinder_{n}"] = dict(
+            nv=mesh.nv, ms_per_step=ms, newton_per_step=sum(st["newton_iters"] for st in stats) / steps,
+            pcg_per_step=pcg / steps, us_per_pcg_iteration=ms * 1e3 * steps / max(pcg, 1),
+            halvings=[int(c[1]) for st in stats for c in st["counts"]],
+            grad_ratio=[st["grad_norm"] / max(st["grad_norm0"], 1e-300) for st in stats])
+        pb.close()
+    print("[bench] membrane step timing done", file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_membrane_step(I, n=64):
+    """The oracle's step with the membrane on the same 64 x 64 cylinder, one step."""
+    import oracle as O
+
+    mesh = I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+    m = I.MATERIAL
+    st = O.Stencils("SS", mesh.X, mesh.tris, m["young"], m["poisson"], m["thickness"])
+    sim = O.MembraneSim(st, m, mesh.pinned)
+    t0 = time.perf_counter()
+    _, _, stats = sim.step(1 / 30, max_newton=4, newton_rtol=1e-8, pcg_rtol=1e-2)
+    return dict(workload=f"SS_membrane_cylinder_{n}", seconds_per_step=time.perf_counter() - t0,
+                pcg_per_step=stats["pcg_total"], cores=1)
+
+
 def navier_rectangle(a, b, nterm=199):
     """Navier's series for the centre deflection of a simply supported a x b plate, w = alpha q / D."""
     s = 0.0
@@ -507,8 +547,9 @@ def main(argv=None):
     ap.add_argument("--sample-every", type=int, default=16,
                     help="in the timed steps, time every n-th PCG iteration's kernels with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-quasi-static", action="store_true",
-                    help="skip the quasi-static linear plate solves (about 1e5 PCG launches; kept out of profiles)")
+    ap.add_argument("--hot-path-only", action="store_true",
+                    help="skip the quasi-static solves and the membrane (their launches are kept out of the "
+                         "counter and trace profiles of the hot path)")
     ap.add_argument("--max-pcg", type=int, default=400000, help="PCG iteration cap per coordinate solve")
     ap.add_argument("--workload", choices=("sphere-cap", "batch64", "linear-plate"), default="sphere-cap")
     ap.add_argument("--no-force-models", action="store_true",
@@ -645,15 +686,17 @@ def main(argv=None):
         pb_other.close()
     if not args.no_force_models and args.size == 1024:
         out["force_models_isolated"] = force_models(S, I, torch, (S.SHELL_PREC_MIXED, S.SHELL_PREC_FP64))
-        out["membrane_forces"] = membrane_timing(S, I, torch)
-        if not args.no_quasi_static:
+        if not args.hot_path_only:
+            out["membrane_forces"] = membrane_timing(S, I, torch)
+            out["membrane_step"] = membrane_step_timing(S, I, torch)
             out["quasi_static"] = quasi_static(S, I, torch)
             out["quasi_static"]["linear_plate_sweep"] = linear_plate_sweep(S, I, torch)
     if not args.no_cpu_baseline and args.size == 1024:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)
-        if not args.no_quasi_static:
+        if not args.hot_path_only:
             out["cpu_baseline"]["quasi_static"] = cpu_static(I)
+            out["cpu_baseline"]["membrane_step"] = cpu_membrane_step(I)
     print(json.dumps(out), flush=True)
 
 
