@@ -62,6 +62,8 @@ def lib():
         L.orc_membrane.argtypes = [i64, P, i64, P, P, d, d, d, P, P]
         L.orc_membrane_rest_hessian.argtypes = [i64, P, P, d, d, d, P]
         L.orc_membrane_gn_hessian.argtypes = [i64, P, P, P, d, d, d, P]
+        L.orc_static_membrane.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, i64, P, P, d, d, d, P, P, P, d, d, i,
+                                          d, i, P, P, P]
         L.orc_step_membrane.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, i64, P, P, d, d, d, P, P, P, P, d, P,
                                         i, d, d, i, P, P, P, P, P]
         L.orc_edge_normal_literal.argtypes = [P, P, P, P, P]
@@ -283,6 +285,26 @@ def solve_static(st: Stencils, pinned, load=None, x0=None, eps_f=1e-3, eps_u=0.0
                           max_pcg, _p(rep), _p(counts), _p(stats))
     if rc not in (0, -5):
         _check(rc, "static")
+    return x, counts, dict(newton_iters=int(stats[0]), pcg_total=int(stats[1]), resid0=stats[2], resid=stats[3],
+                           budget_hit=(rc == -5))
+
+
+def solve_static_membrane(st: Stencils, pinned, load=None, x0=None, eps_f=1e-3, eps_u=0.1, max_newton=200,
+                          pcg_rtol=1e-10, max_pcg=200000, replay=None):
+    """Quasi-static equilibrium of the shell with its membrane (eq 64); returns (x, counts, stats)."""
+    rowptr, col, val = st.hessian()
+    x = np.array(st.X if x0 is None else x0, dtype=np.float64, copy=True)
+    pin = np.ascontiguousarray(pinned, dtype=np.uint8)
+    F = None if load is None else np.ascontiguousarray(load, dtype=np.float64)
+    counts = np.zeros(max(max_newton, 1), dtype=np.int32)
+    stats = np.zeros(4)
+    rep = None if replay is None else np.ascontiguousarray(replay, dtype=np.int32)
+    rc = lib().orc_static_membrane(st.model, st.nv, st.ns, _p(st.idx), _p(st.B), _p(st.kappa0), _p(st.Crest),
+                                   _p(st.D), _p(rowptr), _p(col), _p(val), st.nt, _p(st.tris), _p(st.X), st.young,
+                                   st.poisson, st.thickness, _p(pin), _p(F), _p(x), eps_f, eps_u, max_newton,
+                                   pcg_rtol, max_pcg, _p(rep), _p(counts), _p(stats))
+    if rc not in (0, -5):
+        _check(rc, "static membrane")
     return x, counts, dict(newton_iters=int(stats[0]), pcg_total=int(stats[1]), resid0=stats[2], resid=stats[3],
                            budget_hit=(rc == -5))
 

@@ -1021,6 +1021,93 @@ int orc_membrane_gn_hessian(int64_t nt, const int32_t* tris, const double* X, co
     return ORC_OK;
 }
 
+/* One Jacobi-PCG over all 3 nv coordinates for (M + dt^2 (K_s (x) I3 + K9)) y = -g, y0 = 0 (mass NULL: no
+   mass term); the per-triangle blocks K9 are applied triangle by triangle.  Stops when ||r|| <= rtol ||b||
+   (or after exactly replay_count iterations when that is >= 0); sets *budget_hit when max_pcg ran out.
+   r, z, p, q: work vectors [3 nv].  Returns the iteration count. */
+static int coupled_pcg(int64_t nv, const int64_t* rowptr, const int32_t* col, const double* val, int64_t nt,
+                       const int32_t* tris, const double* K9, const double* mass, const uint8_t* pinned, double dt2,
+                       const double* dinv, const double* g, double* y, double rtol, int max_pcg, int replay_count,
+                       int* budget_hit, double* r, double* z, double* p, double* q) {
+    size_t n3 = (size_t)(3 * nv);
+    double bn = 0, rz = 0;
+    for (size_t i = 0; i < n3; ++i) {
+        y[i] = 0.0;
+        r[i] = -g[i];
+        bn += r[i] * r[i];
+        z[i] = dinv[i / 3] * r[i];
+        p[i] = z[i];
+        rz += r[i] * z[i];
+    }
+    bn = sqrt(bn);
+    int target = replay_count >= 0 ? replay_count : max_pcg, it = 0;
+    while (it < target) {
+        if (replay_count < 0) {
+            double rn = 0;
+            for (size_t i = 0; i < n3; ++i) rn += r[i] * r[i];
+            if (sqrt(rn) <= rtol * bn) break;
+        }
+        for (int64_t i = 0; i < nv; ++i) {
+            double acc[3] = {0, 0, 0};
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) axpy3(val[e], p + 3 * col[e], acc);
+            for (int d = 0; d < 3; ++d) q[3 * i + d] = (mass ? mass[i] * p[3 * i + d] : 0.0) + dt2 * acc[d];
+        }
+        for (int64_t t = 0; t < nt; ++t) {
+            const int32_t* tv = tris + 3 * t;
+            const double* K = K9 + 81 * t;
+            for (int a = 0; a < 9; ++a) {
+                double acc = 0;
+                for (int b = 0; b < 9; ++b) acc += K[9 * a + b] * p[3 * tv[b / 3] + b % 3];
+                q[3 * tv[a / 3] + a % 3] += dt2 * acc;
+            }
+        }
+        double pq = 0;
+        for (int64_t i = 0; i < nv; ++i)
+            for (int d = 0; d < 3; ++d) {
+                if (pinned[i]) q[3 * i + d] = 0.0;
+                pq += p[3 * i + d] * q[3 * i + d];
+            }
+        double alpha = pq != 0.0 ? rz / pq : 0.0;
+        double rz_new = 0;
+        for (size_t i = 0; i < n3; ++i) {
+            y[i] += alpha * p[i];
+            r[i] -= alpha * q[i];
+            z[i] = dinv[i / 3] * r[i];
+            rz_new += r[i] * z[i];
+        }
+        double beta = rz != 0.0 ? rz_new / rz : 0.0;
+        rz = rz_new;
+        for (size_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
+        ++it;
+    }
+    if (replay_count < 0 && it >= max_pcg) {
+        double rn = 0;
+        for (size_t i = 0; i < n3; ++i) rn += r[i] * r[i];
+        if (sqrt(rn) > rtol * bn) *budget_hit = 1;
+    }
+    return it;
+}
+
+/* Jacobi diagonal of M + dt^2 (K_s (x) I3 + K9): 1/(m + dt^2 (K_s,ii + tr(K9_ii)/3)) per vertex, 0 on fixed
+   rows and rows without stiffness (mass NULL: no mass term) */
+static void coupled_dinv(int64_t nv, const int64_t* rowptr, const int32_t* col, const double* val, int64_t nt,
+                         const int32_t* tris, const double* K9, const double* mass, const uint8_t* pinned, double dt2,
+                         double* dinv) {
+    for (int64_t i = 0; i < nv; ++i) {
+        double kii = 0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+            if (col[e] == i) kii = val[e];
+        dinv[i] = kii;
+    }
+    for (int64_t t = 0; t < nt; ++t)
+        for (int j = 0; j < 3; ++j)
+            for (int d = 0; d < 3; ++d) dinv[tris[3 * t + j]] += K9[81 * t + (3 * j + d) * 9 + 3 * j + d] / 3.0;
+    for (int64_t i = 0; i < nv; ++i) {
+        double den = (mass ? mass[i] : 0.0) + dt2 * dinv[i];
+        dinv[i] = (pinned[i] || den == 0.0) ? 0.0 : 1.0 / den;
+    }
+}
+
 /* incremental potential of the step with the membrane: 1/2 (x - x_hat)^T M (x - x_hat) + dt^2 (Psi_b + Psi_m);
    also returns the total force (bending plus membrane) in f */
 static double membrane_step_energy(int model, int64_t nv, const double* x, int64_t ns, const int32_t* idx,
@@ -1090,73 +1177,9 @@ int orc_step_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, con
         if (gn0 == 0.0 || (k > 0 && gn <= newton_rtol * gn0) || k == max_newton) break;
         rc = orc_membrane_gn_hessian(nt, tris, X, x, young, poisson, thickness, K9);
         if (rc) break;
-        for (int64_t i = 0; i < nv; ++i) {
-            double kii = 0;
-            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
-                if (col[e] == i) kii = val[e];
-            dinv[i] = kii;
-        }
-        for (int64_t t = 0; t < nt; ++t)
-            for (int j = 0; j < 3; ++j)
-                for (int d = 0; d < 3; ++d)
-                    dinv[tris[3 * t + j]] += K9[81 * t + (3 * j + d) * 9 + 3 * j + d] / 3.0;
-        for (int64_t i = 0; i < nv; ++i) dinv[i] = pinned[i] ? 0.0 : 1.0 / (mass[i] + dt2 * dinv[i]);
-        /* Jacobi-PCG, y0 = 0 */
-        double bn = 0, rz = 0;
-        for (size_t i = 0; i < n3; ++i) {
-            y[i] = 0.0;
-            r[i] = -g[i];
-            bn += r[i] * r[i];
-            z[i] = dinv[i / 3] * r[i];
-            p[i] = z[i];
-            rz += r[i] * z[i];
-        }
-        bn = sqrt(bn);
-        int target = replay_pcg ? replay_pcg[k] : max_pcg, it = 0;
-        while (it < target) {
-            if (!replay_pcg) {
-                double rn = 0;
-                for (size_t i = 0; i < n3; ++i) rn += r[i] * r[i];
-                if (sqrt(rn) <= pcg_rtol * bn) break;
-            }
-            for (int64_t i = 0; i < nv; ++i) {
-                double acc[3] = {0, 0, 0};
-                for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) axpy3(val[e], p + 3 * col[e], acc);
-                for (int d = 0; d < 3; ++d) q[3 * i + d] = mass[i] * p[3 * i + d] + dt2 * acc[d];
-            }
-            for (int64_t t = 0; t < nt; ++t) {
-                const int32_t* tv = tris + 3 * t;
-                const double* K = K9 + 81 * t;
-                for (int a = 0; a < 9; ++a) {
-                    double acc = 0;
-                    for (int b = 0; b < 9; ++b) acc += K[9 * a + b] * p[3 * tv[b / 3] + b % 3];
-                    q[3 * tv[a / 3] + a % 3] += dt2 * acc;
-                }
-            }
-            double pq = 0;
-            for (int64_t i = 0; i < nv; ++i)
-                for (int d = 0; d < 3; ++d) {
-                    if (pinned[i]) q[3 * i + d] = 0.0;
-                    pq += p[3 * i + d] * q[3 * i + d];
-                }
-            double alpha = pq != 0.0 ? rz / pq : 0.0;
-            double rz_new = 0;
-            for (size_t i = 0; i < n3; ++i) {
-                y[i] += alpha * p[i];
-                r[i] -= alpha * q[i];
-                z[i] = dinv[i / 3] * r[i];
-                rz_new += r[i] * z[i];
-            }
-            double beta = rz != 0.0 ? rz_new / rz : 0.0;
-            rz = rz_new;
-            for (size_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
-            ++it;
-        }
-        if (!replay_pcg && it >= max_pcg) {
-            double rn = 0;
-            for (size_t i = 0; i < n3; ++i) rn += r[i] * r[i];
-            if (sqrt(rn) > pcg_rtol * bn) budget_hit = 1;
-        }
+        coupled_dinv(nv, rowptr, col, val, nt, tris, K9, mass, pinned, dt2, dinv);
+        int it = coupled_pcg(nv, rowptr, col, val, nt, tris, K9, mass, pinned, dt2, dinv, g, y, pcg_rtol, max_pcg,
+                             replay_pcg ? replay_pcg[k] : -1, &budget_hit, r, z, p, q);
         if (counts) counts[k] = it;
         pcg_total += it;
         /* backtracking line search on the incremental potential */
@@ -1195,6 +1218,74 @@ int orc_step_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, con
     free(p);
     free(q);
     free(y);
+    free(dinv);
+    free(K9);
+    if (rc) return rc;
+    return budget_hit ? ORC_E_BUDGET : ORC_OK;
+}
+
+/* Quasi-static equilibrium of the shell with its membrane (eq 64 with Psi_shell = Psi_b + Psi_m):
+   Newton-Raphson on r = dPsi_shell/dx - F (fixed rows zero) with the matrix K_s (x) I3 + K_GN(x), one
+   coupled Jacobi-PCG per iteration, the increment scaled by eps_u/||dx||_inf when that exceeds eps_u > 0;
+   stop when ||r|| < eps_f or after max_newton solves.  replay/counts [max_newton] (one PCG per solve). */
+int orc_static_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B,
+                        const double* kappa0, const double* Crest, const double* D, const int64_t* rowptr,
+                        const int32_t* col, const double* val, int64_t nt, const int32_t* tris, const double* X,
+                        double young, double poisson, double thickness, const uint8_t* pinned, const double* load,
+                        double* x, double eps_f, double eps_u, int max_newton, double pcg_rtol, int max_pcg,
+                        const int32_t* replay, int32_t* counts, double* stats) {
+    if (!x || !pinned || max_newton < 0) return ORC_E_ARG;
+    size_t n3 = (size_t)(3 * nv);
+    double* f = (double*)malloc(sizeof(double) * n3);
+    double* g = (double*)malloc(sizeof(double) * n3);
+    double* y = (double*)malloc(sizeof(double) * n3);
+    double* r = (double*)malloc(sizeof(double) * n3);
+    double* z = (double*)malloc(sizeof(double) * n3);
+    double* p = (double*)malloc(sizeof(double) * n3);
+    double* q = (double*)malloc(sizeof(double) * n3);
+    double* dinv = (double*)malloc(sizeof(double) * (size_t)nv);
+    double* K9 = (double*)malloc(sizeof(double) * (size_t)(81 * nt + 1));
+    int newton = 0, pcg_total = 0, budget_hit = 0, rc = ORC_OK;
+    double rn0 = 0, rn = 0;
+    for (int k = 0;; ++k) {
+        orc_forces(model, nv, x, ns, idx, B, kappa0, Crest, D, f, NULL);
+        orc_membrane(nv, x, nt, tris, X, young, poisson, thickness, f, NULL);
+        double s2 = 0;
+        for (int64_t i = 0; i < nv; ++i)
+            for (int d = 0; d < 3; ++d) {
+                double gi = pinned[i] ? 0.0 : -f[3 * i + d] - (load ? load[3 * i + d] : 0.0);
+                g[3 * i + d] = gi;
+                s2 += gi * gi;
+            }
+        rn = sqrt(s2);
+        if (k == 0) rn0 = rn;
+        if (rn == 0.0 || rn < eps_f || k == max_newton) break;
+        rc = orc_membrane_gn_hessian(nt, tris, X, x, young, poisson, thickness, K9);
+        if (rc) break;
+        coupled_dinv(nv, rowptr, col, val, nt, tris, K9, NULL, pinned, 1.0, dinv);
+        int it = coupled_pcg(nv, rowptr, col, val, nt, tris, K9, NULL, pinned, 1.0, dinv, g, y, pcg_rtol, max_pcg,
+                             replay ? replay[k] : -1, &budget_hit, r, z, p, q);
+        if (counts) counts[k] = it;
+        pcg_total += it;
+        double dmax = 0;
+        for (size_t i = 0; i < n3; ++i) dmax = fmax(dmax, fabs(y[i]));
+        double scale = (eps_u > 0.0 && dmax > eps_u) ? eps_u / dmax : 1.0;
+        for (size_t i = 0; i < n3; ++i) x[i] += scale * y[i];
+        ++newton;
+    }
+    if (stats) {
+        stats[0] = newton;
+        stats[1] = pcg_total;
+        stats[2] = rn0;
+        stats[3] = rn;
+    }
+    free(f);
+    free(g);
+    free(y);
+    free(r);
+    free(z);
+    free(p);
+    free(q);
     free(dinv);
     free(K9);
     if (rc) return rc;

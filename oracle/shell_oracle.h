@@ -119,6 +119,16 @@ int orc_step_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, con
                       double pcg_rtol, int max_pcg, const int32_t* replay_pcg, const int32_t* replay_halvings,
                       int32_t* counts, int32_t* halvings, double* stats);
 
+/* Quasi-static equilibrium with the membrane (eq 64, Psi_shell = Psi_b + Psi_m): Newton-Raphson against
+ * K_s (x) I3 + K_GN(x), one coupled PCG per solve, eps_f / eps_u as in orc_static; replay/counts
+ * [max_newton]. */
+int orc_static_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B,
+                        const double* kappa0, const double* Crest, const double* D, const int64_t* rowptr,
+                        const int32_t* col, const double* val, int64_t nt, const int32_t* tris, const double* X,
+                        double young, double poisson, double thickness, const uint8_t* pinned, const double* load,
+                        double* x, double eps_f, double eps_u, int max_newton, double pcg_rtol, int max_pcg,
+                        const int32_t* replay, int32_t* counts, double* stats);
+
 int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3, const double* x4, double* n);
 
 #endif

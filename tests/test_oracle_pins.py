@@ -950,6 +950,53 @@ def test_membrane_step_descends_and_solves_the_step_equation():
     assert np.abs(res).max() <= 1e-8 * np.abs(dt * dt * fm).max()
 
 
+def _cantilever(nx, ny, model, scale):
+    """A 10 x 1 strip (Sec. 6 cantilever: E = 1.2e6, nu = 0.1, h = 0.1), its two left vertex columns held,
+    an end shear of total 4 * scale shared by the right-end vertices along Z."""
+    X = np.zeros((nx * ny, 3))
+    for j in range(ny):
+        for i in range(nx):
+            X[j * nx + i] = (10.0 * i / (nx - 1), 1.0 * j / (ny - 1), 0.0)
+    tris = I.grid_tris(nx, ny)
+    col = np.arange(nx * ny) % nx
+    load = np.zeros((nx * ny, 3))
+    load[col == nx - 1, 2] = 4.0 * scale / ny
+    st = O.Stencils(model, X, tris, 1.2e6, 0.1, 0.1)
+    return st, (col <= 1).astype(np.uint8), load, col
+
+
+def test_static_membrane_cantilever_converges_to_beam_theory():
+    """Quasi-static Newton-Raphson with the membrane (eq 64, Psi_b + Psi_m), small end load: the tip
+    deflection over the Euler-Bernoulli value P L^3/(3 E I) (I = b h^3/12, the clamp at the second held
+    column) tends to one at first order for the FVM and smoothed plates, and the residual meets eps_f."""
+    for model in ("FP", "SP"):
+        r = []
+        for nx, ny in ((17, 3), (33, 5), (65, 9)):
+            st, pinned, load, col = _cantilever(nx, ny, model, 1e-4)
+            # the residual's floor is the rounding of the Green strain, F^T F - I, times E h (about 1e-9 here)
+            x, _, stats = O.solve_static_membrane(st, pinned, load, eps_f=5e-9, eps_u=0.0, max_newton=20,
+                                                  pcg_rtol=1e-13)
+            assert stats["resid"] < 5e-9 and stats["resid"] < 1e-4 * stats["resid0"]
+            L = 10.0 - 10.0 / (nx - 1)
+            w = x[col == nx - 1][:, 2].mean()
+            r.append(w / (4e-4 * L**3 / (3 * 1.2e6 * 0.1**3 / 12)))
+        assert 1.0 < r[2] < r[1] < r[0] < 1.12
+        assert 1.6 < (r[0] - 1) / (r[1] - 1) < 2.4 and 1.6 < (r[1] - 1) / (r[2] - 1) < 2.4
+
+
+def test_static_membrane_large_deflection_is_an_equilibrium():
+    """The paper's full end load (P = 4): the smoothed shell converges under the eps_u = 0.1 limit to a
+    state whose residual, recomputed from fresh bending and membrane forces, is below eps_f = 1e-3."""
+    st, pinned, load, col = _cantilever(17, 3, "SS", 1.0)
+    x, _, stats = O.solve_static_membrane(st, pinned, load, eps_f=1e-3, eps_u=0.1, max_newton=200, pcg_rtol=1e-10)
+    assert stats["newton_iters"] > 60 and stats["resid"] < 1e-3  # at least tip / eps_u solves
+    fb, _ = st.forces(x)
+    fm, _ = O.membrane_forces(st, x)
+    res = (-(fb + fm) - load)[pinned == 0]
+    assert np.linalg.norm(res) < 1e-3
+    assert 6.0 < x[col == 16][:, 2].mean() < 6.7
+
+
 # ------------------------------------------------------------------ P9/P10: dynamics
 
 
