@@ -93,9 +93,10 @@ typedef struct {
  * membrane couples them; 1/(m + dt^2 (K_s,ii + tr(K_GN,ii)/3)) per vertex), then backtracks x += 2^-h y,
  * h the fewest halvings (at most 6) that satisfy Armijo's condition E(x + a y) <= E(x) + 1e-4 a g.y on
  * the incremental potential.  In its step statistics counts[k][0] is the PCG count and counts[k][1] the
- * halvings of Newton iteration k; REPLAY takes both from replay_counts the same way.  Batches, the
- * quasi-static solve and mixed precision refuse such simulations (SHELL_E_UNSUPPORTED).  A degenerate
- * triangle is SHELL_E_DEGENERATE. */
+ * halvings of Newton iteration k; REPLAY takes both from replay_counts the same way.  The quasi-static
+ * solve takes it the same way (no mass term, no line search: eq 64's eps_u scaling; counts[k][0]).
+ * Batches and mixed precision refuse such simulations (SHELL_E_UNSUPPORTED).  A degenerate triangle is
+ * SHELL_E_DEGENERATE. */
 #define SHELL_FLAG_MEMBRANE 4
 
 typedef struct shell_stencils_s* shell_stencils_t;
@@ -217,7 +218,7 @@ shell_status_t shell_hessian_apply(shell_hessian_t h, const double* mass, double
 shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const double* x0, const double* v0,
                                 const uint8_t* pinned, shell_sim_t* out);
 
-#define SHELL_MAX_NEWTON 64
+#define SHELL_MAX_NEWTON 256
 
 typedef enum { SHELL_PCG_TOLERANCE = 0, SHELL_PCG_REPLAY = 1 } shell_pcg_mode_t;
 
@@ -270,6 +271,8 @@ shell_status_t shell_step_implicit(shell_sim_t sim, const shell_step_params_t* p
  * solves.  s = eps_u / ||dx||_inf when that is below one (the incremental displacement limit), else 1.
  * Plates are linear (f = -K (x - X)), so one solve is exact; the bending-only shells' in-plane modes
  * have no stiffness of their own, so their iteration stalls at a residual of second order in the load.
+ * With SHELL_FLAG_MEMBRANE the residual includes the membrane and the matrix its Gauss-Newton tangent,
+ * K_s (x) I3 + K_GN(x), solved by one coupled Jacobi-PCG (PCG count in counts[k][0]).
  * The velocity and the step counter are not touched.  stats (host, may be NULL) as for the step:
  * grad_norm0 = ||r|| at the start, grad_norm = at the returned state.  Synchronises `stream`.
  * Errors: SHELL_E_INVALID_ARG, SHELL_E_BUDGET (a PCG column hit max_pcg; the state is still updated),

@@ -493,7 +493,6 @@ shell_status_t shell_solve_static(shell_sim_t sim, const shell_static_params_t* 
         const shell_static_params_t& q = *params;
         SHELL_CHECK(q.eps_f >= 0.0 && std::isfinite(q.eps_f), SHELL_E_INVALID_ARG, "eps_f must be >= 0");
         SHELL_CHECK(q.eps_u >= 0.0 && std::isfinite(q.eps_u), SHELL_E_INVALID_ARG, "eps_u must be >= 0");
-        SHELL_CHECK(!sim->ms, SHELL_E_UNSUPPORTED, "the quasi-static solve does not take the membrane");
         shell_step_params_t p{};
         p.dt = 1.0;  // unused by the quasi-static path
         p.max_newton = q.max_newton;
@@ -530,7 +529,16 @@ shell_status_t shell_solve_static(shell_sim_t sim, const shell_static_params_t* 
                 sim->fext.upload(h.data(), h.size(), s);
                 SHELL_HIP(hipStreamSynchronize(s));  // h is released on return
             }
-            rc = batch_step(*sim->solo, &p, 1, nullptr, s, &qs);
+            if (sim->ms) {
+                MembraneStatic mq;
+                mq.load = qs.has_load ? sim->fext.p : nullptr;
+                mq.eps_f = q.eps_f;
+                mq.eps_u = q.eps_u;
+                shell_step_stats_t st{};
+                rc = membrane_static(*sim, p, mq, st, s);
+            } else {
+                rc = batch_step(*sim->solo, &p, 1, nullptr, s, &qs);
+            }
         } else {
             sim->stats = shell_step_stats_t{};
         }

@@ -401,6 +401,13 @@ void launch_membrane_forces(shell_stencils_s& st, const double* pos, const doubl
 void membrane_sim_init(shell_sim_s& sim, hipStream_t s);
 shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, shell_step_stats_t& out,
                              hipStream_t s);
+// quasi-static Newton-Raphson with the membrane (eq 64): load = device [nv][3] internal order, or null
+struct MembraneStatic {
+    const double* load = nullptr;
+    double eps_f = 0.0, eps_u = 0.0;
+};
+shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, const MembraneStatic& qs,
+                               shell_step_stats_t& out, hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
 // dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order padded displacements
 void launch_gather_displacements(const double* src, const int32_t* perm, const double* X, double* dst, int64_t nv,

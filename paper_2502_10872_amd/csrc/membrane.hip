@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __r
 constexpr int kMsBlk = 256;
 // device scalars
 enum : int { S_RZ, S_RZN, S_PQ, S_RR, S_RR0, S_TOL2, S_ALPHA, S_BETA, S_GSQ, S_SLOPE, S_E, S_IT, S_TARGET,
-             S_ACTIVE, S_REPLAY, S_BUDGET, S_COUNT };
+             S_ACTIVE, S_REPLAY, S_BUDGET, S_YMAX, S_COUNT };
 
 template <int NQ>
 __device__ __forceinline__ void ms_partials(double (&v)[NQ], double* part, long ngroups) {
@@ -422,6 +422,36 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_update(const double* __restrict
     }
 }
 
+// largest |y| entry: per-block maxima, then their maximum
+__global__ __launch_bounds__(kMsBlk) void ms_absmax(const double* __restrict__ y, long n, double* __restrict__ part,
+                                                    long ngroups) {
+    double m = 0.0;
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < n; i += long(gridDim.x) * blockDim.x)
+        m = fmax(m, fabs(y[i]));
+    __shared__ double sh[kMsBlk];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kMsBlk / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kMsBlk) void ms_fin_max(const double* __restrict__ part, long ngroups,
+                                                     double* __restrict__ scal) {
+    double m = 0.0;
+    for (long b = threadIdx.x; b < ngroups; b += blockDim.x) m = fmax(m, part[b]);
+    __shared__ double sh[kMsBlk];
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kMsBlk / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scal[S_YMAX] = sh[0];
+}
+
 // p = z + beta p (for the next iteration; skipped once the recurrence has stopped)
 __global__ void ms_dir(const double* __restrict__ scal, const double* __restrict__ z, double* __restrict__ p, long n) {
     if (scal[S_ACTIVE] == 0.0) return;
@@ -687,6 +717,106 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
     out.status = nonfinite ? SHELL_E_NONFINITE : (budget ? SHELL_E_BUDGET : SHELL_OK);
     sim.stats = out;
     sim.step++;
+    sim.last_stream = s;
+    return shell_status_t(out.status);
+}
+
+shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, const MembraneStatic& qs,
+                               shell_step_stats_t& out, hipStream_t s) {
+    shell_stencils_s& st = *sim.st;
+    MembraneSolve& m = *sim.ms;
+    const long nv = sim.nv, n3 = 3 * nv, nt = st.nt, ng = m.ngroups;
+    const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
+    double* part = m.part.p;
+    out = shell_step_stats_t{};
+    if (!sim.zmass.p) {
+        sim.zmass.alloc(size_t(nv));
+        ms_zero<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.zmass.p, nv);
+    }
+    double hs[S_COUNT];
+    auto read_scal = [&]() {
+        SHELL_HIP(hipMemcpyAsync(hs, m.scal.p, sizeof(hs), hipMemcpyDeviceToHost, s));
+        SHELL_HIP(hipStreamSynchronize(s));
+    };
+    // bending plus membrane force at xtry into ftry, then the load added: ftry = f + F
+    auto forces_at_try = [&]() {
+        launch_force_items(st.model, SHELL_PREC_FP64, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
+        launch_membrane_forces(st, m.xtry.p, nullptr, m.ftry.p, s);
+        if (qs.load) ms_axpy<<<ms_grid(n3), kMsBlk, 0, s>>>(m.ftry.p, qs.load, 1.0, m.ftry.p, n3);
+        SHELL_HIP(hipGetLastError());
+    };
+    SHELL_HIP(hipMemcpyAsync(m.xtry.p, sim.x.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    forces_at_try();
+    const bool replay = p.mode == SHELL_PCG_REPLAY;
+    double gn0 = 0.0, gn = 0.0;
+    bool budget = false, nonfinite = false;
+    for (int k = 0;; ++k) {
+        // r = -(f + F) on the free rows: the step's gradient with no mass (x_hat unused)
+        ms_grad<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.x.p, sim.x.p, sim.zmass.p, m.ftry.p, sim.pinned.p, nv, 1.0,
+                                               sim.g.p, part, ng);
+        ms_fin1<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, S_GSQ);
+        read_scal();
+        if (!std::isfinite(hs[S_GSQ])) {
+            nonfinite = true;
+            break;
+        }
+        gn = std::sqrt(hs[S_GSQ]);
+        if (k == 0) gn0 = gn;
+        if (gn == 0.0 || gn < qs.eps_f || k == p.max_newton) break;
+        const long nb9 = long(m.mval.n);
+        ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
+        if (nt > 0)
+            ms_gn<<<ms_grid(nt), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, nt, sim.x.p, c, st.poisson, m.mrow.p,
+                                                 m.mcol.p, m.mval.p);
+        ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.zmass.p, sim.pinned.p, nv,
+                                               1.0, m.dinv.p);
+        const int target = replay ? p.replay_counts[3 * k] : p.max_pcg;
+        ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.g.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, part, ng);
+        ms_fin_init<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, p.pcg_rtol * p.pcg_rtol, target, replay ? 1 : 0);
+        SHELL_HIP(hipGetLastError());
+        read_scal();
+        int chunk = 16;
+        while (hs[S_ACTIVE] != 0.0) {
+            for (int it = 0; it < chunk; ++it) {
+                ms_apply<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p,
+                                                        m.mval.p, sim.zmass.p, sim.pinned.p, m.p.p, m.q.p, nv, 1.0,
+                                                        part, ng);
+                ms_fin_apply<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
+                ms_update<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.p.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
+                                                         part, ng);
+                ms_fin_update<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
+                ms_dir<<<ms_grid(n3), kMsBlk, 0, s>>>(m.scal.p, m.z.p, m.p.p, n3);
+            }
+            SHELL_HIP(hipGetLastError());
+            read_scal();
+            chunk = std::min(2 * chunk, 256);
+        }
+        if (hs[S_BUDGET] == 2.0) {
+            nonfinite = true;
+            break;
+        }
+        budget |= hs[S_BUDGET] != 0.0;
+        const int its = int(hs[S_IT]);
+        // incremental displacement limit
+        double scale = 1.0;
+        if (qs.eps_u > 0.0) {
+            ms_absmax<<<unsigned(ng), kMsBlk, 0, s>>>(m.y.p, n3, part, ng);
+            ms_fin_max<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
+            read_scal();
+            if (hs[S_YMAX] > qs.eps_u) scale = qs.eps_u / hs[S_YMAX];
+        }
+        ms_axpy<<<ms_grid(n3), kMsBlk, 0, s>>>(sim.x.p, m.y.p, scale, m.xtry.p, n3);
+        forces_at_try();
+        SHELL_HIP(hipMemcpyAsync(sim.x.p, m.xtry.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
+        out.counts[k][0] = its;
+        out.pcg_total += its;
+        out.newton_iters++;
+    }
+    SHELL_HIP(hipStreamSynchronize(s));
+    out.grad_norm0 = gn0;
+    out.grad_norm = gn;
+    out.status = nonfinite ? SHELL_E_NONFINITE : (budget ? SHELL_E_BUDGET : SHELL_OK);
+    sim.stats = out;
     sim.last_stream = s;
     return shell_status_t(out.status);
 }

@@ -19,7 +19,7 @@ SHELL_OK, SHELL_E_BUDGET, SHELL_E_NONFINITE = 0, 6, 5
 SHELL_E_INVALID_ARG, SHELL_E_UNSUPPORTED = 1, 9
 SHELL_PREC_FP64, SHELL_PREC_MIXED = 0, 1
 SHELL_PCG_TOLERANCE, SHELL_PCG_REPLAY = 0, 1
-SHELL_MAX_NEWTON = 64
+SHELL_MAX_NEWTON = 256
 MODELS = ("EP", "ES", "FP", "FS", "SP", "SS")
 STATUS = {0: "SHELL_OK", 1: "SHELL_E_INVALID_ARG", 2: "SHELL_E_NONMANIFOLD", 3: "SHELL_E_ORIENTATION",
           4: "SHELL_E_DEGENERATE", 5: "SHELL_E_NONFINITE", 6: "SHELL_E_BUDGET", 7: "SHELL_E_OOM", 8: "SHELL_E_HIP",

@@ -48,7 +48,7 @@ def test_status_strings_need_no_device(library):
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(S.shell_material_t) == 32
     assert ctypes.sizeof(S.shell_config_t) == 16 and S.shell_config_t.flags.offset == 12
-    assert ctypes.sizeof(S.shell_step_stats_t) == 4 * 4 + 2 * 8 + 64 * 3 * 4
+    assert ctypes.sizeof(S.shell_step_stats_t) == 4 * 4 + 2 * 8 + 256 * 3 * 4
     assert ctypes.sizeof(S.shell_step_params_t) == 8 + 24 + 8 + 16 + 8 + 8 + 8
     assert ctypes.sizeof(S.shell_static_params_t) == 8 + 8 + 8 + 8 + 8 + 16 + 8
     assert S.shell_static_params_t.pcg_rtol.offset == 32 and S.shell_static_params_t.replay_counts.offset == 56
