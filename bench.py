@@ -291,6 +291,55 @@ def linear_plate_sweep(S, I, torch, n=65):
     return out
 
 
+def cantilever_problem(I, model):
+    """Sec. 6 cantilever under end shear: a 10 x 1 strip of 17 x 3 vertices (51), E = 1.2e6, nu = 0.1,
+    h = 0.1, the two left vertex columns held, F = 4/3 along Z on each of the three right-end vertices."""
+    nx, ny = 17, 3
+    X = np.zeros((nx * ny, 3))
+    for j in range(ny):
+        for i in range(nx):
+            X[j * nx + i] = (10.0 * i / (nx - 1), 1.0 * j / (ny - 1), 0.0)
+    col = np.arange(nx * ny) % nx
+    load = np.zeros((nx * ny, 3))
+    load[col == nx - 1, 2] = 4.0 / 3.0
+    mesh = I.Mesh("cantilever", X, I.grid_tris(nx, ny), (col <= 1).astype(np.uint8), model, 10.0 / (nx - 1), {})
+    return mesh, load, col, dict(young=1.2e6, poisson=0.1, thickness=0.1, density=1.0)
+
+
+def cantilever(S, I, torch):
+    """The cantilever with the membrane, quasi-static Newton-Raphson with the paper's eps_f = 1e-3 and
+    eps_u = 0.1 (PCG rtol 1e-10) on the GPU: tip deflection along Z, Newton solves, time.  The paper's
+    table gives 6.056 (FP), 6.072 (FS), 6.055 (SP), 6.072 (SS) in 67-68 solves; ABAQUS S4R 6.012."""
+    out = {}
+    for model in ("FP", "FS", "SP", "SS"):
+        mesh, load, col, mat = cantilever_problem(I, model)
+        pb = S.Problem(mesh, mat, model=model, flags=S.SHELL_FLAG_MEMBRANE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = S.shell_solve_static(pb.sim, load, eps_f=1e-3, eps_u=0.1, max_newton=200, pcg_rtol=1e-10)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        x, _, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+        pb.close()
+        out[model] = dict(w_tip=float((x - mesh.X)[col == 16][:, 2].mean()), newton_iters=st["newton_iters"],
+                          pcg_total=st["pcg_total"], ms=ms, residual=st["grad_norm"], status=rc)
+    print("[bench] cantilever done", file=sys.stderr, flush=True)
+    return out
+
+
+def cpu_cantilever(I, model="SS"):
+    """The oracle's cantilever solve (the smoothed shell)."""
+    import oracle as O
+
+    mesh, load, col, mat = cantilever_problem(I, model)
+    st = O.Stencils(model, mesh.X, mesh.tris, mat["young"], mat["poisson"], mat["thickness"])
+    t0 = time.perf_counter()
+    x, _, stats = O.solve_static_membrane(st, mesh.pinned, load, eps_f=1e-3, eps_u=0.1, max_newton=200,
+                                          pcg_rtol=1e-10)
+    return dict(workload=f"cantilever_{model}", seconds=time.perf_counter() - t0,
+                newton_iters=stats["newton_iters"], w_tip=float((x - mesh.X)[col == 16][:, 2].mean()), cores=1)
+
+
 def cpu_static(I, n=65):
     """The oracle's quasi-static solve of the same clamped plate (one Newton-Raphson solve, PCG rtol 1e-10)."""
     import oracle as O
@@ -316,6 +365,7 @@ def run_linear_plate(args):
     S.lib()
     qs = quasi_static(S, I, torch)
     sweep = linear_plate_sweep(S, I, torch)
+    qs["cantilever"] = cantilever(S, I, torch)
     big = qs["SP_clamped_257"]
     print(json.dumps(dict(metric="linear plate solve time (SP, clamped, 257x257, FP64, PCG rtol 1e-10)",
                           value=big["ms"] / 1e3, unit="s", higher_is_better=False, n_gpus=1, data="synthetic",
@@ -691,12 +741,14 @@ def main(argv=None):
             out["membrane_step"] = membrane_step_timing(S, I, torch)
             out["quasi_static"] = quasi_static(S, I, torch)
             out["quasi_static"]["linear_plate_sweep"] = linear_plate_sweep(S, I, torch)
+            out["quasi_static"]["cantilever"] = cantilever(S, I, torch)
     if not args.no_cpu_baseline and args.size == 1024:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)
         if not args.hot_path_only:
             out["cpu_baseline"]["quasi_static"] = cpu_static(I)
             out["cpu_baseline"]["membrane_step"] = cpu_membrane_step(I)
+            out["cpu_baseline"]["cantilever"] = cpu_cantilever(I)
     print(json.dumps(out), flush=True)
 
 
