@@ -372,6 +372,23 @@ def run_linear_plate(args):
                           quasi_static=qs, linear_plate_sweep=sweep)), flush=True)
 
 
+def run_membrane(args):
+    """The membrane alone (its force pass on the 1M-vertex cap, and the step with it on cylinders), one JSON
+    line; a kernel trace of this workload shows the membrane kernels by themselves."""
+    import torch
+
+    from paper_2502_10872_amd import inputs as I
+    from paper_2502_10872_amd import shell as S
+
+    S.lib()
+    forces = membrane_timing(S, I, torch)
+    steps = membrane_step_timing(S, I, torch)
+    print(json.dumps(dict(metric="implicit steps/s with the membrane (SS, 256x256 cylinder, FP64)",
+                          value=1e3 / steps["SS_membrane_cylinder_256"]["ms_per_step"], unit="steps/s",
+                          higher_is_better=True, n_gpus=1, data="synthetic", membrane_forces=forces,
+                          membrane_step=steps)), flush=True)
+
+
 def run_batch64(args):
     """64 meshes (16^2..512^2 vertices, log-uniform, all six models, 1 cm spacing, mixed precision, Newton
     budget 4, PCG rtol 1e-2, dt = 1/60) stepped as one batch, against the same meshes stepped one at a
@@ -601,7 +618,7 @@ def main(argv=None):
                     help="skip the quasi-static solves and the membrane (their launches are kept out of the "
                          "counter and trace profiles of the hot path)")
     ap.add_argument("--max-pcg", type=int, default=400000, help="PCG iteration cap per coordinate solve")
-    ap.add_argument("--workload", choices=("sphere-cap", "batch64", "linear-plate"), default="sphere-cap")
+    ap.add_argument("--workload", choices=("sphere-cap", "batch64", "linear-plate", "membrane"), default="sphere-cap")
     ap.add_argument("--no-force-models", action="store_true",
                     help="skip the per-model force kernel timing (six 1M-vertex meshes, both precisions)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -623,6 +640,8 @@ def main(argv=None):
         return run_batch64(args)
     if args.workload == "linear-plate":
         return run_linear_plate(args)
+    if args.workload == "membrane":
+        return run_membrane(args)
     head = S.SHELL_PREC_MIXED if args.precision == "mixed" else S.SHELL_PREC_FP64
     other = S.SHELL_PREC_FP64 if head == S.SHELL_PREC_MIXED else S.SHELL_PREC_MIXED
     mat = I.MATERIAL
