@@ -279,11 +279,27 @@ struct MembraneSolve {
     DevArray<int64_t> mdiag; // [nv] slot of the diagonal block
     DevArray<double> mval;   // [nnz][9] row-major 3x3 blocks
     DevArray<double> rest;   // [nt][5] G = Dm^-1 and the rest area
-    DevArray<double> xtry, ftry, z, p, q, y, r, dinv, part;
+    DevArray<double> xtry, ftry, z, p, p2, q, y, r, dinv, part;
+    DevArray<double> ppart;      // per-block partials of the PCG product's p.q
     DevArray<double> scal;   // device scalars of the PCG and the energies
     DevArray<ForceDesc> fdesc;   // bending force at xtry with energy partials
     DevArray<WorkItem> items;
     int64_t ngroups = 0;
+    bool pswap = false;          // which of p, p2 holds the current PCG direction
+    // instantiated graphs of PCG chunks, keyed by what their kernel arguments bake in
+    struct PcgGraph {
+        const double* mass;
+        double dt2;
+        int count;
+        bool parity;
+        hipGraphExec_t ex;
+    };
+    std::vector<PcgGraph> graphs;  // oldest first
+    hipStream_t capture = nullptr; // private stream the chunks are captured on
+    MembraneSolve() = default;
+    MembraneSolve(const MembraneSolve&) = delete;
+    MembraneSolve& operator=(const MembraneSolve&) = delete;
+    ~MembraneSolve();
 };
 }  // namespace shell
 

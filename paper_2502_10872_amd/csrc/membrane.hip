@@ -334,60 +334,87 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__
         scal[S_TARGET] = double(target);
         scal[S_REPLAY] = double(replay);
         scal[S_BUDGET] = 0.0;
+        scal[S_BETA] = 0.0;
         scal[S_ACTIVE] = (0 < target && (replay || t[1] > rtol2 * t[1])) ? 1.0 : 0.0;
     }
 }
 
-// q = M p + dt^2 (K_s (x) I3 + K_GN) p, fixed rows zero; partial p.q
-__global__ __launch_bounds__(kMsBlk) void ms_apply(const double* __restrict__ scal, const int64_t* __restrict__ srow,
-                                                   const int32_t* __restrict__ scol, const double* __restrict__ sval,
-                                                   const int64_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
-                                                   const double* __restrict__ mval, const double* __restrict__ mass,
-                                                   const uint8_t* __restrict__ pinned, const double* __restrict__ p,
-                                                   double* __restrict__ q, long nv, double dt2,
-                                                   double* __restrict__ part, long ngroups) {
+// The coupled PCG iteration in three kernels, none with cross-block synchronisation inside it: the
+// product writes per-block partials of p.q, every block of the update sums them itself in the same fixed
+// order (so all blocks agree on alpha), and one block finishes the update's partials and the stop test.
+
+// p_new = z + beta p_old (row i, stored) and q = M p_new + dt^2 (K_s (x) I3 + K_GN) p_new, the neighbours'
+// p_new formed on the fly from their z and p_old; fixed rows zero; partial p.q.  kMsRowLanes lanes share a
+// row: they take its K_s entries and its 3x3 blocks in turn (consecutive lanes read consecutive entries)
+// and combine their sums by shuffles; the row's first lane stores.
+constexpr int kMsRowLanes = 16;
+constexpr int kMsRowsPerBlk = kMsBlk / kMsRowLanes;
+inline unsigned ms_product_grid(long nv) {
+    return unsigned(std::max(1L, (nv + kMsRowsPerBlk - 1) / kMsRowsPerBlk));
+}
+
+__global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restrict__ scal,
+                                                          const int64_t* __restrict__ srow,
+                                                          const int32_t* __restrict__ scol, const double* __restrict__ sval,
+                                                          const int64_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
+                                                          const double* __restrict__ mval, const double* __restrict__ mass,
+                                                          const uint8_t* __restrict__ pinned, const double* __restrict__ z,
+                                                          const double* __restrict__ pold, double* __restrict__ pnew,
+                                                          double* __restrict__ q, long nv, double dt2,
+                                                          double* __restrict__ ppart, long npart) {
     if (scal[S_ACTIVE] == 0.0) return;
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    double v[1] = {0.0};
+    const double be = scal[S_BETA];
+    const long i = blockIdx.x * long(kMsRowsPerBlk) + threadIdx.x / kMsRowLanes;
+    const int lane = threadIdx.x % kMsRowLanes;
+    double a[3] = {0.0, 0.0, 0.0};
     if (i < nv) {
-        double a[3] = {0.0, 0.0, 0.0};
-        for (long e = srow[i]; e < srow[i + 1]; ++e) {
+        for (long e = srow[i] + lane; e < srow[i + 1]; e += kMsRowLanes) {
             const long j = scol[e];
             const double k = sval[e];
-            for (int c = 0; c < 3; ++c) a[c] += k * p[3 * j + c];
+            for (int c = 0; c < 3; ++c) a[c] += k * (z[3 * j + c] + be * pold[3 * j + c]);
         }
-        for (long e = mrow[i]; e < mrow[i + 1]; ++e) {
+        for (long e = mrow[i] + lane; e < mrow[i + 1]; e += kMsRowLanes) {
             const long j = mcol[e];
             const double* b = mval + 9 * e;
-            for (int c = 0; c < 3; ++c) a[c] += b[3 * c] * p[3 * j] + b[3 * c + 1] * p[3 * j + 1] + b[3 * c + 2] * p[3 * j + 2];
+            const double pj[3] = {z[3 * j] + be * pold[3 * j], z[3 * j + 1] + be * pold[3 * j + 1],
+                                  z[3 * j + 2] + be * pold[3 * j + 2]};
+            for (int c = 0; c < 3; ++c) a[c] += b[3 * c] * pj[0] + b[3 * c + 1] * pj[1] + b[3 * c + 2] * pj[2];
         }
+    }
+    for (int off = kMsRowLanes / 2; off > 0; off >>= 1)
+        for (int c = 0; c < 3; ++c) a[c] += __shfl_xor(a[c], off, kMsRowLanes);
+    double v[1] = {0.0};
+    if (i < nv && lane == 0)
         for (int c = 0; c < 3; ++c) {
-            const double qi = pinned[i] ? 0.0 : mass[i] * p[3 * i + c] + dt2 * a[c];
+            const double pi = z[3 * i + c] + be * pold[3 * i + c];
+            pnew[3 * i + c] = pi;
+            const double qi = pinned[i] ? 0.0 : mass[i] * pi + dt2 * a[c];
             q[3 * i + c] = qi;
-            v[0] += p[3 * i + c] * qi;
+            v[0] += pi * qi;
+        }
+    ms_partials<1>(v, ppart, npart);
+}
+
+// alpha = r.z / p.q from the product's partials (summed by every block alike); y += alpha p,
+// r -= alpha q, z = D^-1 r; partials r.z and r.r
+__global__ __launch_bounds__(kMsBlk) void ms_iter_update(double* __restrict__ scal, const double* __restrict__ ppart,
+                                                         long npart, const double* __restrict__ p, const double* __restrict__ q,
+                                                         const double* __restrict__ dinv, double* __restrict__ y,
+                                                         double* __restrict__ r, double* __restrict__ z, long nv,
+                                                         double* __restrict__ part, long ngroups) {
+    if (scal[S_ACTIVE] == 0.0) return;
+    __shared__ double alpha;
+    double pq[1];
+    ms_totals<1>(ppart, npart, pq);
+    if (threadIdx.x == 0) {
+        alpha = pq[0] != 0.0 ? scal[S_RZ] / pq[0] : 0.0;
+        if (blockIdx.x == 0) {
+            scal[S_PQ] = pq[0];
+            scal[S_ALPHA] = alpha;
         }
     }
-    ms_partials<1>(v, part, ngroups);
-}
-
-__global__ __launch_bounds__(kMsBlk) void ms_fin_apply(const double* __restrict__ part, long ngroups,
-                                                       double* __restrict__ scal) {
-    if (scal[S_ACTIVE] == 0.0) return;
-    double t[1];
-    ms_totals<1>(part, ngroups, t);
-    if (threadIdx.x == 0) {
-        scal[S_PQ] = t[0];
-        scal[S_ALPHA] = t[0] != 0.0 ? scal[S_RZ] / t[0] : 0.0;
-    }
-}
-
-__global__ __launch_bounds__(kMsBlk) void ms_update(const double* __restrict__ scal, const double* __restrict__ p,
-                                                    const double* __restrict__ q, const double* __restrict__ dinv,
-                                                    double* __restrict__ y, double* __restrict__ r,
-                                                    double* __restrict__ z, long nv, double* __restrict__ part,
-                                                    long ngroups) {
-    if (scal[S_ACTIVE] == 0.0) return;
-    const double al = scal[S_ALPHA];
+    __syncthreads();
+    const double al = alpha;
     long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
     double v[2] = {0.0, 0.0};
     if (i < nv)
@@ -402,8 +429,9 @@ __global__ __launch_bounds__(kMsBlk) void ms_update(const double* __restrict__ s
     ms_partials<2>(v, part, ngroups);
 }
 
-__global__ __launch_bounds__(kMsBlk) void ms_fin_update(const double* __restrict__ part, long ngroups,
-                                                        double* __restrict__ scal) {
+// r.z and r.r, then beta, the iteration count and the stop test (one block)
+__global__ __launch_bounds__(kMsBlk) void ms_iter_finish(const double* __restrict__ part, long ngroups,
+                                                         double* __restrict__ scal) {
     if (scal[S_ACTIVE] == 0.0) return;
     double t[2];
     ms_totals<2>(part, ngroups, t);
@@ -452,15 +480,12 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_max(const double* __restrict__ 
     if (threadIdx.x == 0) scal[S_YMAX] = sh[0];
 }
 
-// p = z + beta p (for the next iteration; skipped once the recurrence has stopped)
-__global__ void ms_dir(const double* __restrict__ scal, const double* __restrict__ z, double* __restrict__ p, long n) {
-    if (scal[S_ACTIVE] == 0.0) return;
-    const double be = scal[S_BETA];
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i < n) p[i] = z[i] + be * p[i];
-}
-
 }  // namespace
+
+MembraneSolve::~MembraneSolve() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.ex);
+    if (capture) (void)hipStreamDestroy(capture);
+}
 
 void launch_membrane_rest(shell_stencils_s& st, hipStream_t s) {
     const long nt = st.nt;
@@ -570,11 +595,12 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     DevArray<int32_t> bad(1);
     SHELL_HIP(hipMemsetAsync(bad.p, 0, sizeof(int32_t), s));
     if (nt > 0) membrane_rest<<<int((nt + 255) / 256), 256, 0, s>>>(st.X.p, st.tris.p, nt, ms->rest.p, bad.p);
-    for (auto* a : {&ms->xtry, &ms->ftry, &ms->z, &ms->p, &ms->q, &ms->y, &ms->r})
+    for (auto* a : {&ms->xtry, &ms->ftry, &ms->z, &ms->p, &ms->p2, &ms->q, &ms->y, &ms->r})
         a->alloc(size_t(std::max(n3, 1L)));
     ms->dinv.alloc(size_t(std::max(nv, 1L)));
     ms->ngroups = long(ms_grid(nv));
     ms->part.alloc(size_t(2 * ms->ngroups + std::max<int64_t>(st.nblocks, 1)));
+    ms->ppart.alloc(ms_product_grid(nv));
     ms->scal.alloc(S_COUNT);
     // bending force at xtry into ftry, with its energy partials after the reduction partials
     ForceDesc d{};
@@ -604,10 +630,67 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     sim.ms = std::move(ms);
 }
 
+// One PCG iteration: the product kernel forms the new direction into one of the two p buffers from z and
+// the other, the update kernel reads it; the buffers alternate.  Once the stop test has cleared the active
+// flag all three kernels return at once, so the alternation may run on past the last iteration.
+static void pcg_iteration(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2,
+                          hipStream_t s) {
+    double* pold = m.pswap ? m.p2.p : m.p.p;
+    double* pnew = m.pswap ? m.p.p : m.p2.p;
+    const unsigned pg = ms_product_grid(nv);
+    ms_iter_product<<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p, m.mval.p, mass,
+                                          pinned, m.z.p, pold, pnew, m.q.p, nv, dt2, m.ppart.p, long(pg));
+    ms_iter_update<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.ppart.p, long(pg), pnew, m.q.p, m.dinv.p, m.y.p, m.r.p,
+                                                  m.z.p, nv, m.part.p, m.ngroups);
+    ms_iter_finish<<<1, kMsBlk, 0, s>>>(m.part.p, m.ngroups, m.scal.p);
+    m.pswap = !m.pswap;
+}
+
+constexpr size_t kMsMaxGraphs = 16;
+
+// `count` PCG iterations.  With graphs allowed a chunk is captured once on a private stream and replayed
+// (the kernels read the scalars and vectors when the graph runs, so one capture serves every solve with
+// the same mass array, dt and buffer parity); otherwise the kernels are launched one by one.
+static void pcg_iterations(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2,
+                           int count, bool graphs, hipStream_t s) {
+    if (!graphs) {
+        for (int it = 0; it < count; ++it) pcg_iteration(m, mass, pinned, nv, dt2, s);
+        return;
+    }
+    const bool parity = m.pswap;
+    hipGraphExec_t ex = nullptr;
+    for (const auto& g : m.graphs)
+        if (g.mass == mass && g.dt2 == dt2 && g.count == count && g.parity == parity) ex = g.ex;
+    if (!ex) {
+        if (!m.capture) SHELL_HIP(hipStreamCreateWithFlags(&m.capture, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        SHELL_HIP(hipStreamBeginCapture(m.capture, hipStreamCaptureModeThreadLocal));
+        for (int it = 0; it < count; ++it) pcg_iteration(m, mass, pinned, nv, dt2, m.capture);
+        const hipError_t launched = hipGetLastError();
+        const hipError_t ended = hipStreamEndCapture(m.capture, &g);
+        m.pswap = parity;
+        if (launched != hipSuccess || ended != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            SHELL_HIP(launched != hipSuccess ? launched : ended);
+        }
+        const hipError_t err = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        SHELL_HIP(err);
+        if (m.graphs.size() >= kMsMaxGraphs) {
+            (void)hipGraphExecDestroy(m.graphs.front().ex);
+            m.graphs.erase(m.graphs.begin());
+        }
+        m.graphs.push_back({mass, dt2, count, parity, ex});
+    }
+    SHELL_HIP(hipGraphLaunch(ex, s));
+    m.pswap = (count & 1) ? !parity : parity;
+}
+
 shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, shell_step_stats_t& out,
                              hipStream_t s) {
     shell_stencils_s& st = *sim.st;
     MembraneSolve& m = *sim.ms;
+    const bool graphs = (p.flags & SHELL_STEP_NO_GRAPHS) == 0;
     const long nv = sim.nv, n3 = 3 * nv, nt = st.nt, ng = m.ngroups;
     const double dt = p.dt, dt2 = dt * dt;
     const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
@@ -660,22 +743,14 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
                                                dt2, m.dinv.p);
         // one PCG over all coordinates
         const int target = replay ? p.replay_counts[3 * k] : p.max_pcg;
+        m.pswap = false;  // ms_pcg_init writes p = z into m.p, the first product's old direction
         ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.g.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, part, ng);
         ms_fin_init<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, p.pcg_rtol * p.pcg_rtol, target, replay ? 1 : 0);
         SHELL_HIP(hipGetLastError());
         read_scal();
         int chunk = 16;
         while (hs[S_ACTIVE] != 0.0) {
-            for (int it = 0; it < chunk; ++it) {
-                ms_apply<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p,
-                                                        m.mval.p, sim.mass.p, sim.pinned.p, m.p.p, m.q.p, nv, dt2,
-                                                        part, ng);
-                ms_fin_apply<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
-                ms_update<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.p.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
-                                                         part, ng);
-                ms_fin_update<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
-                ms_dir<<<ms_grid(n3), kMsBlk, 0, s>>>(m.scal.p, m.z.p, m.p.p, n3);
-            }
+            pcg_iterations(m, sim.mass.p, sim.pinned.p, nv, dt2, chunk, graphs, s);
             SHELL_HIP(hipGetLastError());
             read_scal();
             chunk = std::min(2 * chunk, 256);
@@ -725,6 +800,7 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
                                shell_step_stats_t& out, hipStream_t s) {
     shell_stencils_s& st = *sim.st;
     MembraneSolve& m = *sim.ms;
+    const bool graphs = (p.flags & SHELL_STEP_NO_GRAPHS) == 0;
     const long nv = sim.nv, n3 = 3 * nv, nt = st.nt, ng = m.ngroups;
     const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
     double* part = m.part.p;
@@ -771,22 +847,14 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
         ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.zmass.p, sim.pinned.p, nv,
                                                1.0, m.dinv.p);
         const int target = replay ? p.replay_counts[3 * k] : p.max_pcg;
+        m.pswap = false;  // ms_pcg_init writes p = z into m.p, the first product's old direction
         ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.g.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, part, ng);
         ms_fin_init<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, p.pcg_rtol * p.pcg_rtol, target, replay ? 1 : 0);
         SHELL_HIP(hipGetLastError());
         read_scal();
         int chunk = 16;
         while (hs[S_ACTIVE] != 0.0) {
-            for (int it = 0; it < chunk; ++it) {
-                ms_apply<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p,
-                                                        m.mval.p, sim.zmass.p, sim.pinned.p, m.p.p, m.q.p, nv, 1.0,
-                                                        part, ng);
-                ms_fin_apply<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
-                ms_update<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.p.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
-                                                         part, ng);
-                ms_fin_update<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p);
-                ms_dir<<<ms_grid(n3), kMsBlk, 0, s>>>(m.scal.p, m.z.p, m.p.p, n3);
-            }
+            pcg_iterations(m, sim.zmass.p, sim.pinned.p, nv, 1.0, chunk, graphs, s);
             SHELL_HIP(hipGetLastError());
             read_scal();
             chunk = std::min(2 * chunk, 256);

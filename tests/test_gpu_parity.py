@@ -417,6 +417,38 @@ def test_membrane_step_replay_matches_oracle(model):
     assert err[0] <= TOL64 and err[1] <= TOL64, err
 
 
+def test_membrane_pcg_graphs_match_direct_launches():
+    """The membrane's PCG chunks replayed from captured graphs run the same kernels as launching them one by
+    one (SHELL_STEP_NO_GRAPHS).  The Gauss-Newton blocks are assembled with floating-point atomics, so two
+    runs differ in rounding and the stiff system can turn that into different PCG counts: the direct
+    launches therefore replay the graph run's counts and halvings and must give its positions and
+    velocities to 1e-10, over several chunks per solve and two steps that reuse the captured graphs."""
+    mesh = I.cylinder_mesh(17, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+    states, reps = [], []
+    for flags in (0, S.SHELL_STEP_NO_GRAPHS):
+        with S.Problem(mesh, MAT, model="SS", block_vertices=128, flags=S.SHELL_FLAG_MEMBRANE) as pb:
+            for k in range(2):
+                if flags == 0:
+                    params, _keep = S.step_params(1 / 120, max_newton=3, newton_rtol=1e-6, pcg_rtol=1e-13)
+                    rc, gs = S.shell_step_implicit(pb.sim, params)
+                    n = gs["newton_iters"]
+                    rep = np.zeros((max(n, 1), 3), np.int32)
+                    rep[:n, :2] = np.asarray(gs["counts"][:n])[:, :2]
+                    reps.append((n, rep))
+                else:
+                    n, rep = reps[k]
+                    params, _keep = S.step_params(1 / 120, max_newton=n, newton_rtol=1e-6, pcg_rtol=1e-13,
+                                                  replay=rep, flags=flags)
+                    rc, gs = S.shell_step_implicit(pb.sim, params)
+                    assert gs["newton_iters"] == n
+                    assert np.array_equal(np.asarray(gs["counts"][:n])[:, :2], rep[:n, :2])
+            x, v, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+            states.append((x, v))
+    assert max(int(c) for _, rep in reps for c in rep[:, 0]) > 48  # several chunks per solve
+    err = (rel(states[1][0] - mesh.X, states[0][0] - mesh.X), rel(states[1][1], states[0][1]))
+    assert err[0] <= TOL64 and err[1] <= TOL64, err
+
+
 def test_membrane_step_tolerance_mode_descends_and_refusals():
     """Tolerance mode: the residual falls within the Newton budget; batches and mixed precision refuse a
     simulation with the membrane."""
