@@ -278,6 +278,8 @@ struct MembraneSolve {
     DevArray<int32_t> mcol;
     DevArray<int64_t> mdiag; // [nv] slot of the diagonal block
     DevArray<double> mval;   // [nnz][9] row-major 3x3 blocks
+    DevArray<int64_t> vtrow; // [nv+1] each vertex's triangles, ascending
+    DevArray<int32_t> vttri;
     DevArray<double> rest;   // [nt][5] G = Dm^-1 and the rest area
     DevArray<double> xtry, ftry, z, p, p2, q, y, r, dinv, part;
     DevArray<double> ppart;      // per-block partials of the PCG product's p.q

@@ -249,45 +249,50 @@ __device__ __forceinline__ long ms_find(const int64_t* __restrict__ row, const i
     return lo;
 }
 
-// Gauss-Newton tangent of the membrane per triangle, added into the 3x3 blocks
-__global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict__ tris, long nt,
+// Gauss-Newton tangent of the membrane into the 3x3 blocks, one thread per vertex row: the thread walks
+// the row's triangles in ascending order and adds its corner's three blocks of each, so every block is
+// written by one thread in a fixed order (no atomics; the same state gives the same matrix bit for bit).
+__global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict__ tris,
+                      const int64_t* __restrict__ vtrow, const int32_t* __restrict__ vttri, long nv,
                       const double* __restrict__ x, double c, double nu, const int64_t* __restrict__ mrow,
                       const int32_t* __restrict__ mcol, double* __restrict__ mval) {
-    long t = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (t >= nt) return;
-    const long v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
-    const double G[2][2] = {{rest[5 * t], rest[5 * t + 1]}, {rest[5 * t + 2], rest[5 * t + 3]}};
-    const double A = rest[5 * t + 4];
-    double F[3][2];
-    for (int i = 0; i < 3; ++i) {
-        const double d1 = x[3 * v[1] + i] - x[3 * v[0] + i], d2 = x[3 * v[2] + i] - x[3 * v[0] + i];
-        for (int b = 0; b < 2; ++b) F[i][b] = d1 * G[0][b] + d2 * G[1][b];
-    }
-    const double g[3][2] = {{-G[0][0] - G[1][0], -G[0][1] - G[1][1]}, {G[0][0], G[0][1]}, {G[1][0], G[1][1]}};
-    double Bm[3][9];
-    for (int j = 0; j < 3; ++j)
+    const long r = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (r >= nv) return;
+    for (long e = vtrow[r]; e < vtrow[r + 1]; ++e) {
+        const long t = vttri[e];
+        const long v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+        const int a = v[0] == r ? 0 : (v[1] == r ? 1 : 2);
+        const double G[2][2] = {{rest[5 * t], rest[5 * t + 1]}, {rest[5 * t + 2], rest[5 * t + 3]}};
+        const double A = rest[5 * t + 4];
+        double F[3][2];
         for (int i = 0; i < 3; ++i) {
-            Bm[0][3 * j + i] = g[j][0] * F[i][0];
-            Bm[1][3 * j + i] = g[j][1] * F[i][1];
-            Bm[2][3 * j + i] = g[j][1] * F[i][0] + g[j][0] * F[i][1];
+            const double d1 = x[3 * v[1] + i] - x[3 * v[0] + i], d2 = x[3 * v[2] + i] - x[3 * v[0] + i];
+            for (int k = 0; k < 2; ++k) F[i][k] = d1 * G[0][k] + d2 * G[1][k];
         }
-    // D_m B (D_m = c [[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu)/2]])
-    double DB[3][9];
-    for (int q = 0; q < 9; ++q) {
-        DB[0][q] = c * (Bm[0][q] + nu * Bm[1][q]);
-        DB[1][q] = c * (nu * Bm[0][q] + Bm[1][q]);
-        DB[2][q] = c * 0.5 * (1.0 - nu) * Bm[2][q];
-    }
-    for (int a = 0; a < 3; ++a)
+        const double g[3][2] = {{-G[0][0] - G[1][0], -G[0][1] - G[1][1]}, {G[0][0], G[0][1]}, {G[1][0], G[1][1]}};
+        double Bm[3][9];
+        for (int j = 0; j < 3; ++j)
+            for (int i = 0; i < 3; ++i) {
+                Bm[0][3 * j + i] = g[j][0] * F[i][0];
+                Bm[1][3 * j + i] = g[j][1] * F[i][1];
+                Bm[2][3 * j + i] = g[j][1] * F[i][0] + g[j][0] * F[i][1];
+            }
+        // D_m B (D_m = c [[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu)/2]])
+        double DB[3][9];
+        for (int q = 0; q < 9; ++q) {
+            DB[0][q] = c * (Bm[0][q] + nu * Bm[1][q]);
+            DB[1][q] = c * (nu * Bm[0][q] + Bm[1][q]);
+            DB[2][q] = c * 0.5 * (1.0 - nu) * Bm[2][q];
+        }
         for (int b = 0; b < 3; ++b) {
-            const long slot = ms_find(mrow, mcol, v[a], int(v[b]));
+            double* blk = mval + 9 * ms_find(mrow, mcol, r, int(v[b]));
             for (int ca = 0; ca < 3; ++ca)
                 for (int cb = 0; cb < 3; ++cb) {
                     const int pa = 3 * a + ca, pb = 3 * b + cb;
-                    const double k = A * (Bm[0][pa] * DB[0][pb] + Bm[1][pa] * DB[1][pb] + Bm[2][pa] * DB[2][pb]);
-                    atomicAdd(mval + 9 * slot + 3 * ca + cb, k);
+                    blk[3 * ca + cb] += A * (Bm[0][pa] * DB[0][pb] + Bm[1][pa] * DB[1][pb] + Bm[2][pa] * DB[2][pb]);
                 }
         }
+    }
 }
 
 __global__ void ms_dinv(const double* __restrict__ kdiag, const double* __restrict__ mval,
@@ -590,6 +595,20 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->mdiag.alloc(std::max<size_t>(mdiag.size(), 1));
     ms->mdiag.upload(mdiag.data(), mdiag.size(), s);
     ms->mval.alloc(std::max<size_t>(9 * mcol.size(), 1));
+    // each vertex's triangles, ascending (the Gauss-Newton assembly's fixed order)
+    std::vector<int64_t> vtrow(size_t(nv + 1), 0);
+    for (long t = 0; t < 3 * nt; ++t) ++vtrow[size_t(st.h_tris[size_t(t)]) + 1];
+    for (long i = 0; i < nv; ++i) vtrow[size_t(i + 1)] += vtrow[size_t(i)];
+    std::vector<int32_t> vttri(size_t(std::max(3 * nt, 1L)));
+    {
+        std::vector<int64_t> fill(vtrow.begin(), vtrow.end() - 1);
+        for (long t = 0; t < nt; ++t)
+            for (int a = 0; a < 3; ++a) vttri[size_t(fill[size_t(st.h_tris[size_t(3 * t + a)])]++)] = int32_t(t);
+    }
+    ms->vtrow.alloc(vtrow.size());
+    ms->vtrow.upload(vtrow.data(), vtrow.size(), s);
+    ms->vttri.alloc(vttri.size());
+    ms->vttri.upload(vttri.data(), size_t(3 * nt), s);
     // per-triangle rest data
     ms->rest.alloc(size_t(std::max(5 * nt, 1L)));
     DevArray<int32_t> bad(1);
@@ -737,8 +756,8 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
         const long nb9 = long(m.mval.n);
         ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
         if (nt > 0)
-            ms_gn<<<ms_grid(nt), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, nt, sim.x.p, c, st.poisson, m.mrow.p,
-                                                 m.mcol.p, m.mval.p);
+            ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, sim.x.p, c,
+                                                 st.poisson, m.mrow.p, m.mcol.p, m.mval.p);
         ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.mass.p, sim.pinned.p, nv,
                                                dt2, m.dinv.p);
         // one PCG over all coordinates
@@ -842,8 +861,8 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
         const long nb9 = long(m.mval.n);
         ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
         if (nt > 0)
-            ms_gn<<<ms_grid(nt), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, nt, sim.x.p, c, st.poisson, m.mrow.p,
-                                                 m.mcol.p, m.mval.p);
+            ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, sim.x.p, c,
+                                                 st.poisson, m.mrow.p, m.mcol.p, m.mval.p);
         ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.zmass.p, sim.pinned.p, nv,
                                                1.0, m.dinv.p);
         const int target = replay ? p.replay_counts[3 * k] : p.max_pcg;
