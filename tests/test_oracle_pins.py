@@ -325,6 +325,29 @@ def test_plate_force_is_minus_K_x(model):
         assert abs(e - 0.5 * (x * Kx).sum()) <= 1e-12 * np.abs(x * Kx).sum()  # cancellation-aware
 
 
+@pytest.mark.parametrize("model", ["EP", "FP", "SP"])
+def test_apply_is_the_step_operator(model):
+    """q = M p + dt^2 (K_s (x) I3) p, the operator of the step (eqs 62-63), pinned three ways: with no
+    mass and dt^2 = 1 it is minus the plate force (itself pinned by finite differences above), since a
+    plate's force is -(K_s (x) I3) x; constants are in the null space of K_s (eq 12), so it maps the
+    all-ones field to the mass; with dt^2 = 0 it is the mass alone."""
+    m = I.plate_mesh(9, 1.0, 0.2, 5, model, "none")
+    st = stencils(model, m.X, m.tris)
+    csr = st.hessian()
+    mass = O.mass(m.X, m.tris, 200.0, 1e-3)
+    g = I.rng(15)
+    x = m.X + 0.05 * g.standard_normal(m.X.shape)
+    f, _ = st.forces(x)
+    q = O.apply(csr, None, 1.0, x)
+    assert np.abs(q + f).max() <= 1e-12 * np.abs(f).max()
+    ones = np.ones_like(m.X)
+    q1 = O.apply(csr, mass, 0.7, ones)
+    scale = mass.max() + 0.7 * np.abs(csr[2]).max()  # the row sums cancel entries of this size
+    assert np.abs(q1 - mass[:, None]).max() <= 1e-13 * scale
+    p = g.standard_normal(m.X.shape)
+    assert np.array_equal(O.apply(csr, mass, 0.0, p), mass[:, None] * p)
+
+
 @pytest.mark.parametrize("model", ["ES", "FS", "SS"])
 def test_shell_on_flat_rest_normal_block_is_K(model):
     """Shells on a flat rest: the out-of-plane block of the force Jacobian at rest is -K_s, the
