@@ -29,10 +29,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 def algorithmic_bytes(info: dict, hinfo: dict, precision: int, clamp_bias: bool = False) -> dict:
     """Bytes each kernel must move once (no re-reads, no SELL padding), per launch.
 
-    force:  per stencil its k vertex ids, r x k operator, (shells) r rest curvatures and, in mixed
-            precision, the r x 3 rest curvature vectors and (shells) the rest differences of the normal;
-            per vertex the position (mixed: displacement from rest) read and the force written; FP64
-            plates with clamped edges also read the constant clamp force per vertex.
+    force:  per stencil its k vertex ids, the operator (FP64: r x k entries; mixed: r x (k - 1), the
+            origin's column being implied by the zero row sums), (shells) r float64 rest curvatures and
+            (mixed edge plate) the tip's two float64 rest-plane coordinates; per vertex the float64 position
+            read (mixed triangle plates also the rest position) and the force written; FP64 plates with
+            clamped edges also read the constant clamp force per vertex.
     spmv:   (the product kernel, which also forms the new direction p = z + beta p_old) every nonzero's
             value and 16-bit local column id, each row group's distinct-column list, slice widths and
             offsets, and per vertex the direction's inputs (FP64: r and D^-1; mixed: the stored float z)
@@ -43,9 +44,10 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int, clamp_bias: bool 
     shell = info["model"] in (1, 3, 5)
     mixed = precision == 1
     real = 4 if mixed else 8  # stencil operators, matrix values, p, q, z, D^-1, forces
-    rest_diffs = (9 if k == 4 else 6) if shell else 0
-    per_stencil = 4 * k + real * r * k + (real * r if shell else 0) + (4 * (3 * r + rest_diffs) if mixed else 0)
-    force = ns * per_stencil + nv * (24 + 3 * real) + (nv * 24 if clamp_bias and not mixed else 0)
+    per_stencil = (4 * k + real * r * (k - 1 if mixed else k) + (8 * r if shell else 0)
+                   + (16 if mixed and k == 4 and not shell else 0))
+    force = (ns * per_stencil + nv * (24 + 3 * real) + (nv * 24 if clamp_bias and not mixed else 0)
+             + (nv * 24 if mixed and k == 6 and not shell else 0))
     ngroups = (nv + 511) // 512  # 512-row groups
     idx = 2 if hinfo["staged"] else 4
     direction_in = 3 * real if mixed else 24 + real

@@ -18,8 +18,9 @@
  *    and must stay valid until the stream reaches the work.
  *  - `stream` is a hipStream_t; NULL selects the null stream.
  *  - Vertex arrays are [nv][3] row-major float64 in the caller's vertex order.
- *    The library keeps its own (Morton block) order internally and converts
- *    at the boundary.
+ *    The library keeps its own order internally (by default recursive
+ *    coordinate bisection into compact tiles, Morton order inside a tile; see
+ *    shell_config_t.reorder) and converts at the boundary.
  *  - Handles are owned by the library and released by shell_destroy_*; one
  *    handle must not be used by two threads at once.
  *  - Models are identified by shell_model_t; a model's curvature size r is 1
@@ -228,11 +229,14 @@ typedef struct {
     int32_t max_newton;    /* Newton solves per step, 0..SHELL_MAX_NEWTON */
     int32_t max_pcg;       /* PCG iteration cap per column (tolerance mode) */
     double newton_rtol;    /* stop when ||g_k|| <= newton_rtol ||g_0|| */
-    double pcg_rtol;       /* per column: stop when ||r|| <= pcg_rtol ||b|| */
+    double pcg_rtol;       /* per column: stop when ||r|| <= pcg_rtol ||b||.  Mixed precision uses it for
+                              its float32 inner solve as well (there is no separate inner tolerance): the
+                              recurrence residual r is float64, the Newton loop re-forms the residual in
+                              float64 each iteration */
     int32_t mode;          /* shell_pcg_mode_t */
     int32_t chunk;         /* PCG iterations launched between host convergence checks; 0 = default */
-    int32_t pcg_workgroups; /* work-groups of each PCG kernel (each takes consecutive 512-row groups);
-                               0 = default (512: two per CU).  Batches use the first entry's value */
+    int32_t pcg_workgroups; /* work-groups of each PCG kernel (each takes consecutive 512-row groups),
+                               0..1024; 0 = default (512: two per CU).  Batches use the first entry's value */
     int32_t flags;         /* 0 or SHELL_STEP_NO_GRAPHS; batches use the first entry's value */
     const int32_t* replay_counts; /* host [max_newton][3], REPLAY only: exact PCG iterations */
 } shell_step_params_t;
@@ -246,7 +250,9 @@ typedef struct {
     int32_t newton_iters;  /* Newton solves performed */
     int32_t pcg_total;     /* PCG iterations summed over solves and columns */
     int32_t status;        /* shell_status_t of the step (SHELL_E_BUDGET is a warning) */
-    int32_t reserved;
+    int32_t newton_capped; /* 1: the Newton loop stopped at max_newton solves before its residual test held
+                              (||g|| > newton_rtol ||g_0||, or for the quasi-static solve ||r|| >= eps_f);
+                              the state is that of the last solve.  0: the residual test stopped it */
     double grad_norm0;     /* ||g|| at the predictor */
     double grad_norm;      /* ||g|| at the returned state */
     int32_t counts[SHELL_MAX_NEWTON][3]; /* PCG iterations per Newton solve and coordinate */

@@ -40,7 +40,8 @@ void check_params(const shell_step_params_t& p) {
     SHELL_CHECK(p.mode != SHELL_PCG_REPLAY || p.replay_counts, SHELL_E_INVALID_ARG, "replay needs counts");
     SHELL_CHECK(p.mode == SHELL_PCG_REPLAY || p.max_pcg > 0, SHELL_E_INVALID_ARG, "max_pcg must be positive");
     SHELL_CHECK(p.chunk >= 0, SHELL_E_INVALID_ARG, "chunk must be >= 0");
-    SHELL_CHECK(p.pcg_workgroups >= 0, SHELL_E_INVALID_ARG, "pcg_workgroups must be >= 0");
+    SHELL_CHECK(p.pcg_workgroups >= 0 && p.pcg_workgroups <= 1024, SHELL_E_INVALID_ARG,
+                "pcg_workgroups must be in 0..1024");
     SHELL_CHECK((p.flags & ~SHELL_STEP_NO_GRAPHS) == 0, SHELL_E_INVALID_ARG, "unknown step flag");
     for (int c = 0; c < 3; ++c) SHELL_CHECK(std::isfinite(p.gravity[c]), SHELL_E_INVALID_ARG, "gravity not finite");
     if (p.mode == SHELL_PCG_REPLAY)
@@ -83,7 +84,7 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         SHELL_CHECK(out && mat && (X || nv == 0) && (tris || nt == 0), SHELL_E_INVALID_ARG, "null argument");
         *out = nullptr;
         SHELL_CHECK(model >= SHELL_EP && model <= SHELL_SS, SHELL_E_INVALID_ARG, "unknown model");
-        SHELL_CHECK(nv >= 0 && nt >= 0 && nv < (int64_t(1) << 31) && 3 * nt < (int64_t(1) << 31), SHELL_E_INVALID_ARG,
+        SHELL_CHECK(nv >= 0 && nt >= 0 && nv < (int64_t(1) << 30) && 3 * nt < (int64_t(1) << 31), SHELL_E_INVALID_ARG,
                     "mesh size out of range");
         SHELL_CHECK(n_clamped >= 0 && (clamped_edges || n_clamped == 0), SHELL_E_INVALID_ARG, "bad clamped edge list");
         for (int64_t e = 0; e < 2 * n_clamped; ++e)
@@ -122,8 +123,26 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
         st->thickness = mat->thickness;
         st->density = mat->density;
         st->kb = mat->young * std::pow(mat->thickness, 3) / (12.0 * (1.0 - mat->poisson * mat->poisson));
-
         HostTopology topo = build_topology(model, nv, nt, tris, n_clamped, clamped_edges);
+        {
+            // force scales of the order-independent tile accumulation (powers of two); the topology
+            // check above has validated the triangle ids
+            double lsum = 0.0;
+            for (int64_t t = 0; t < nt; ++t)
+                for (int e = 0; e < 3; ++e) {
+                    const double* a = X + 3 * size_t(tris[3 * t + e]);
+                    const double* b = X + 3 * size_t(tris[3 * t + (e + 1) % 3]);
+                    lsum += std::sqrt((a[0] - b[0]) * (a[0] - b[0]) + (a[1] - b[1]) * (a[1] - b[1]) +
+                                      (a[2] - b[2]) * (a[2] - b[2]));
+                }
+            const double ell = nt ? lsum / double(3 * nt) : 1.0;
+            auto pow2 = [](double v) {
+                return (std::isfinite(v) && v > 0.0) ? std::ldexp(1.0, int(std::lround(std::log2(v)))) : 1.0;
+            };
+            st->fscale = pow2(st->kb / ell) * 0x1p-10;
+            st->mscale = pow2(mat->young * mat->thickness * ell * 0x1p-16);
+        }
+
         const int k = st->k, r = st->r;
         st->ns = topo.ns;
         st->perm = vertex_order(X, nv, reorder, T);
@@ -260,10 +279,11 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
         const bool f32 = st->precision == SHELL_PREC_MIXED;
         if (st->nv > 0 && !st->fdesc.p) {
             // caller-order staging, descriptor and tile items, made on first use
-            st->xin.alloc(size_t((f32 ? 4 : 3) * st->nv));  // mixed: padded displacements
+            st->xin.alloc(size_t(3 * st->nv));
             st->fout.alloc(size_t(3 * st->nv));
             ForceDesc d{};
             d.x = st->xin.p;
+            d.X = st->X.p;
             d.f = st->fout.p;
             d.epart = st->epart.p;
             d.bias = st->bias.p;
@@ -275,6 +295,7 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
             d.T = st->T;
             d.model = st->model;
             d.kb = st->kb;
+            d.fscale = st->fscale;
             d.nu = st->poisson;
             std::vector<WorkItem> items(size_t(st->nblocks));
             for (int64_t t = 0; t < st->nblocks; ++t) items[size_t(t)] = {0, int32_t(t)};
@@ -285,13 +306,9 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
                                 hipMemcpyHostToDevice));
         }
         if (st->nv > 0) {
-            if (f32)
-                launch_gather_displacements(x, st->perm_d.p, st->X.p, st->xin.p, st->nv, s);
-            else
-                launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
+            launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
             launch_force_items(st->model, st->precision, st->fdesc.p, st->tile_items.p, st->nblocks, st->T, s);
-            if (st->cfg_flags & SHELL_FLAG_MEMBRANE)
-                launch_membrane_forces(*st, f32 ? nullptr : st->xin.p, f32 ? st->xin.p : nullptr, st->fout.p, s);
+            if (st->cfg_flags & SHELL_FLAG_MEMBRANE) launch_membrane_forces(*st, st->xin.p, st->fout.p, s);
             launch_scatter_rows(st->fout.p, st->perm_d.p, f, st->nv, f32, s);
         }
         if (energy) {
@@ -741,7 +758,7 @@ shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, i
             b += int64_t(v);
         for (size_t v : {sim->x.bytes(), sim->v.bytes(), sim->xt.bytes(), sim->xhat.bytes(), sim->g.bytes(),
                          sim->mass.bytes(), sim->y.bytes(), sim->r.bytes(), sim->f.bytes(), sim->dinv.bytes(), sim->mq.bytes(),
-                         sim->pinned.bytes(), sim->p.bytes(), sim->p2.bytes(), sim->z.bytes(), sim->q.bytes(), sim->u4.bytes(),
+                         sim->pinned.bytes(), sim->p.bytes(), sim->p2.bytes(), sim->z.bytes(), sim->q.bytes(),
                          sim->bins.bytes(), sim->partials.bytes()})
             c += int64_t(v);
         if (stencil_bytes) *stencil_bytes = a;

@@ -5,11 +5,11 @@
 // tile boundary appear in each tile they touch).  Each stencil's force on the tile's own vertices is
 // added into a float64 LDS accumulator; contributions to other tiles' vertices are left to those
 // tiles.  The tile is then written to HBM once: no global atomics, no zero-fill, one coalesced store
-// per vertex.  Stencil data is streamed in blocks of 64 stencils, in 16-byte chunks of fields (a
+// per vertex.  The accumulation is exact in fixed-point parts (TileAcc), so its result does not depend
+// on the order in which the waves add.  Stencil data is streamed in blocks of 64 stencils, in 16-byte chunks of fields (a
 // wave's 64 loads of one chunk are one contiguous 1 KB run, so every load is coalesced and a wave
 // touches one region of memory); a tile's list stays in spatial order so the gathers of one wave touch
-// few cache lines.  (float32 LDS atomics contended badly on shared vertices; the float64 accumulator
-// does not.)
+// few cache lines.
 //
 // Per stencil (operator B already scaled by the square root of its stiffness):
 //   C_i = sum_j B_ij (x_j - x_o)            curvature vectors, x_o the stencil origin (rows of B
@@ -20,15 +20,26 @@
 // with D = 1 (edge) or D_b / k_b-form [[1,nu,0],[nu,1,0],[0,0,(1-nu)/2]] * k_b (triangle), n the
 // unit normal of the central triangle (eq 15) or the bisector of the two hinge triangle normals
 // (edge; the line of eq 8), its gradient by the chain rule of App. B (eqs 67, 73).
-// Mixed precision: the kernels gather the float64 displacements u = x - X from the rest shape and
-// difference them in float64; everything after the difference is float32.  The curvature is formed
-// relative to the rest shape, C = C0 + B (u^e), with C0 = B X^e precomputed in float64, so float32
-// rounds the displacement differences (of the size of the deformation) instead of the position
-// differences (of the size of an edge): the net force of a smooth deformation is a cancelling sum over
-// stencils, and with position differences its relative error grew with the mesh resolution and with
-// the inverse of the deformation (2e-3 at 1024x1024 for an amplitude of side/100).  The shell normals
-// use the position differences of their vertices, rebuilt as the streamed rest differences plus the
-// displacement differences.
+//
+// Mixed precision.  The positions are gathered in float64 and differenced in float64; what float32
+// rounds is chosen so that it never cancels against the size of an edge:
+//  - shells take the bending strain from the heights h_j = (x_j - x_o) . n over the current normal
+//    (float64 dot products with the float32 normal): delta = B~ h - kappa0~, summed in float64, with B~
+//    the float32 operator and kappa0~ = B~ h0 the rest curvature of that same rounded operator (float64,
+//    computed at build time).  The normal is renormalised in float64; its remaining direction error adds a
+//    linear function of the positions to h, which B annihilates up to the tangential part of the
+//    curvature vectors (eq 12's argument), so delta stays accurate whatever the rigid motion or the size of
+//    the stencil, also near the rest shape where it is small.  The curvature vectors C = B~ (x_j - x_o) and the normal gradient (which
+//    meet only g = D delta, and the tangent plane) are float32.
+//  - plates remove the stencil's affine part before rounding: the map A that carries the rest edges of
+//    the central triangle (edge stencils: of the first hinge triangle, in the rest tangent plane) onto
+//    the current ones is applied in float64, and C = sum_j B~_j (x_j - x_o - A (X_j - X_o)) over the
+//    flaps, the only vertices where that difference is not zero.  B annihilates affine fields of the
+//    rest stencil (eqs 12, 49), so this is B x^e, and float32 now rounds the deformation of the stencil
+//    instead of its position, also under rotations.  Triangle plates gather the rest positions and
+//    solve for A's coefficients in float64; the edge plate reads its tip's two coefficients from its
+//    record.  Plate stencils with a clamped edge are rest-relative, C = B~ (u_j - u_o), u = x - X.
+// After that everything is float32, with float64 tile accumulation.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -40,44 +51,60 @@ namespace shell {
 
 namespace {
 
-// Edge stencil (vertices 0-3, hinge 1-2) from the differences a = x0 - x1, c = x2 - x1, b = x3 - x1 and the
-// curvature vector C = sum_j L_j x_j formed by the caller.
+// Normal of an edge stencil (vertices 0-3, hinge 1-2) from a = x0 - x1, c = x2 - x1, b = x3 - x1: the two
+// hinge triangles' unit normals and their normalised bisector.
+template <typename R>
+struct EdgeFrame {
+    V3<R> na, nb, n;
+    R ila, ilb, ilm;
+};
+template <typename R>
+__device__ __forceinline__ EdgeFrame<R> edge_frame(V3<R> a, V3<R> c, V3<R> b) {
+    EdgeFrame<R> e;
+    const V3<R> ua = cross(c, a), ub = cross(b, c);
+    e.ila = R(1) / norm(ua);
+    e.ilb = R(1) / norm(ub);
+    e.na = e.ila * ua;
+    e.nb = e.ilb * ub;
+    const V3<R> m = e.na + e.nb;
+    e.ilm = R(1) / norm(m);
+    e.n = e.ilm * m;
+    return e;
+}
+
+// Edge stencil force from the curvature vector C = sum_j L_j x_j and, for shells, the bending strain
+// delta and the frame.
 template <typename R, bool SHELL>
-__device__ __forceinline__ void edge_stencil(V3<R> a, V3<R> c, V3<R> b, V3<R> C, const R (&L)[4], R kappa0,
-                                             V3<R> (&f)[4], R& energy) {
+__device__ __forceinline__ void edge_force(V3<R> a, V3<R> c, V3<R> b, V3<R> C, const R (&L)[4],
+                                           const EdgeFrame<R>& e, R delta, V3<R> (&f)[4], R& energy) {
     if constexpr (!SHELL) {
         energy = R(0.5) * dot(C, C);
 #pragma unroll
         for (int j = 0; j < 4; ++j) f[j] = (-L[j]) * C;
     } else {
-        V3<R> ua = cross(c, a), ub = cross(b, c);
-        R ila = R(1) / norm(ua), ilb = R(1) / norm(ub);
-        V3<R> na = ila * ua, nb = ilb * ub;
-        V3<R> m = na + nb;
-        R ilm = R(1) / norm(m);
-        V3<R> n = ilm * m;
-        R delta = dot(n, C) - kappa0;
         energy = R(0.5) * delta * delta;
         // w = (I - n n^T) C / |m|, then through each unit triangle normal
-        V3<R> w = ilm * (C - dot(C, n) * n);
-        V3<R> wa = ila * (w - dot(w, na) * na);
-        V3<R> wb = ilb * (w - dot(w, nb) * nb);
-        V3<R> g1 = cross(wa, c);
-        V3<R> g2 = cross(wa, a - c) + cross(wb, c - b);
-        V3<R> g3 = cross(wb, b) - cross(wa, a);
-        V3<R> g4 = cross(c, wb);
-        f[0] = (-delta) * (L[0] * n + g1);
-        f[1] = (-delta) * (L[1] * n + g2);
-        f[2] = (-delta) * (L[2] * n + g3);
-        f[3] = (-delta) * (L[3] * n + g4);
+        const V3<R> w = e.ilm * (C - dot(C, e.n) * e.n);
+        const V3<R> wa = e.ila * (w - dot(w, e.na) * e.na);
+        const V3<R> wb = e.ilb * (w - dot(w, e.nb) * e.nb);
+        const V3<R> g1 = cross(wa, c);
+        const V3<R> g2 = cross(wa, a - c) + cross(wb, c - b);
+        const V3<R> g3 = cross(wb, b) - cross(wa, a);
+        const V3<R> g4 = cross(c, wb);
+        f[0] = (-delta) * (L[0] * e.n + g1);
+        f[1] = (-delta) * (L[1] * e.n + g2);
+        f[2] = (-delta) * (L[2] * e.n + g3);
+        f[3] = (-delta) * (L[3] * e.n + g4);
     }
 }
 
-// Triangle stencil from the differences d_j = x_j - x_0 (d_0 = 0) and the curvature vectors
-// C_i = sum_j B_ij x_j formed by the caller.
+// Triangle stencil force from the differences d_j = x_j - x_0 (d_0 = 0), the curvature vectors
+// C_i = sum_j B_ij x_j and, for shells, the bending strain de_i and the central triangle's unit normal n
+// with 1/|d_1 x d_2|.
 template <typename R, bool SHELL>
-__device__ __forceinline__ void tri_stencil(const V3<R> (&d)[6], const V3<R> (&C)[3], const R (&B)[3][6],
-                                            const R (&k0)[3], R kb, R nu, V3<R> (&f)[6], R& energy) {
+__device__ __forceinline__ void tri_force(const V3<R> (&d)[6], const V3<R> (&C)[3], const R (&B)[3][6],
+                                          const R (&de)[3], V3<R> n, R ilu, R kb, R nu, V3<R> (&f)[6],
+                                          R& energy) {
     const R t = R(0.5) * (R(1) - nu);
     if constexpr (!SHELL) {
         V3<R> DC[3];
@@ -93,19 +120,15 @@ __device__ __forceinline__ void tri_stencil(const V3<R> (&d)[6], const V3<R> (&C
             f[j] = fj;
         }
     } else {
-        V3<R> u = cross(d[1], d[2]);
-        R ilu = R(1) / norm(u);
-        V3<R> n = ilu * u;
-        R de0 = dot(n, C[0]) - k0[0], de1 = dot(n, C[1]) - k0[1], de2 = dot(n, C[2]) - k0[2];
-        R g0 = kb * (de0 + nu * de1), g1 = kb * (nu * de0 + de1), g2 = kb * t * de2;
-        energy = R(0.5) * (de0 * g0 + de1 * g1 + de2 * g2);
+        const R g0 = kb * (de[0] + nu * de[1]), g1 = kb * (nu * de[0] + de[1]), g2 = kb * t * de[2];
+        energy = R(0.5) * (de[0] * g0 + de[1] * g1 + de[2] * g2);
         V3<R> Cg = g0 * C[0];
         fma3(Cg, g1, C[1]);
         fma3(Cg, g2, C[2]);
-        V3<R> w = ilu * (Cg - dot(Cg, n) * n);
+        const V3<R> w = ilu * (Cg - dot(Cg, n) * n);
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
-            R bj = g0 * B[0][j] + g1 * B[1][j] + g2 * B[2][j];
+            const R bj = g0 * B[0][j] + g1 * B[1][j] + g2 * B[2][j];
             f[j] = (-bj) * n;
         }
         // (du/dx1)^T w = w x (x3 - x2), (du/dx2)^T w = w x (x1 - x3), (du/dx3)^T w = w x (x2 - x1)
@@ -115,20 +138,36 @@ __device__ __forceinline__ void tri_stencil(const V3<R> (&d)[6], const V3<R> (&C
     }
 }
 
+// Coefficients (a, b) of the projection of v on the plane of e1, e2: v ~ a e1 + b e2 (float64 normal
+// equations of the 2 x 2 Gram system).
+struct Plane2 {
+    double g11, g12, g22, idet;
+    __device__ __forceinline__ Plane2(V3<double> e1, V3<double> e2) {
+        g11 = dot(e1, e1);
+        g12 = dot(e1, e2);
+        g22 = dot(e2, e2);
+        idet = 1.0 / (g11 * g22 - g12 * g12);
+    }
+    __device__ __forceinline__ void coords(V3<double> e1, V3<double> e2, V3<double> v, double& a, double& b) const {
+        const double r1 = dot(e1, v), r2 = dot(e2, v);
+        a = (g22 * r1 - g12 * r2) * idet;
+        b = (g11 * r2 - g12 * r1) * idet;
+    }
+};
+
 // 16-byte stream chunks (clang vector types, which load through address-space pointers in one
 // instruction).  The streams are read with non-temporal loads, which keep them from displacing the
-// gathered positions or displacements from L2 (measured 2-5% faster than plain loads for the float
-// record).
+// gathered positions from L2 (measured 2-5% faster than plain loads for the float record).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-// tile accumulator in float64 for both precisions (ds_add_f64)
+// a stencil's force on an owned vertex into the tile's order-independent accumulator (both precisions)
 template <typename R>
-__device__ __forceinline__ void lds_add(double* acc, int slot, V3<R> v) {
-    atomicAdd(acc + 3 * slot + 0, double(v.x));
-    atomicAdd(acc + 3 * slot + 1, double(v.y));
-    atomicAdd(acc + 3 * slot + 2, double(v.z));
+__device__ __forceinline__ void lds_add(TileAcc& acc, int slot, V3<R> v, double inv_scale) {
+    acc.add(3 * slot + 0, double(v.x) * inv_scale);
+    acc.add(3 * slot + 1, double(v.y) * inv_scale);
+    acc.add(3 * slot + 2, double(v.z) * inv_scale);
 }
 
 // Largest force work-group; the kernels are compiled for it, so any size up to it can be launched.
@@ -141,44 +180,50 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
     constexpr bool EDGE = (MODEL == SHELL_EP || MODEL == SHELL_ES);
     constexpr bool SHELL = (MODEL == SHELL_ES || MODEL == SHELL_FS || MODEL == SHELL_SS);
     constexpr int K = EDGE ? 4 : 6;
+    constexpr int O = EDGE ? 1 : 0;                 // origin of the differences
+    constexpr bool MIX = sizeof(R) == 4;
+    constexpr bool REST = MIX && !SHELL && !EDGE;   // mixed triangle plates also gather the rest positions
     extern __shared__ unsigned char smem_raw[];
-    double* acc = reinterpret_cast<double*>(smem_raw);
     long it = xcd_logical(blockIdx.x, gridDim.x);
     if (it >= nitems) return;
     const WorkItem wi = items[it];
     const ForceDesc& d = descs[wi.mesh];
     // global-address views of the descriptor's pointers: global loads wait on the vector-memory counter
     // only, so the LDS accumulation does not stall behind loads in flight
-    const gbl<const double>* x = G(static_cast<const double*>(d.x));
+    const gbl<const double>* x = G(d.x);
+    const gbl<const double>* X = G(d.X);
     const R kb = R(d.kb), nu = R(d.nu);
     const long blk = wi.unit;
     const long base = blk * long(d.T);
     const int nown = int(min(long(d.T), d.nv - base));
-    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) acc[i] = 0.0;
+    TileAcc acc(smem_raw, d.T);
+    acc.clear(3 * nown);
+    const double inv_scale = 1.0 / d.fscale;  // a power of two: exact
     __syncthreads();
     double e_own = 0.0;
     // a tile's list starts on a 64-stencil block and the work-group's stride is a whole number of
     // blocks, so each wave reads whole blocks: every field of its 64 stencils is one contiguous run
-    constexpr int NB = EDGE ? 4 : 18;               // operator entries per stencil
-    constexpr int NK = EDGE ? 1 : 3;                // rest-curvature slots per stencil (zero for plates)
-    constexpr bool REL = sizeof(R) == 4;            // float: curvature relative to the rest shape
-    constexpr int NC = REL ? 3 * NK : 1;            // rest curvature vector components (float only)
-    constexpr int ND = REL ? (rec32_rest_diffs(K, SHELL) ? rec32_rest_diffs(K, SHELL) : 1) : 1;
-    // 16-byte chunks per stencil: mixed, one record of ids, operator, rest curvatures, C0 and rest
-    // differences; FP64, the ids and the float64 values in two streams
-    constexpr int NCH32 = stream_chunks(rec32_fields(K, NK, SHELL), 4);
+    constexpr int R_ = EDGE ? 1 : 3;                // curvature components
+    constexpr int NB = R_ * K;                      // FP64: operator entries per stencil
+    constexpr int NK = R_;                          // FP64: rest-curvature slots (zero for plates)
+    constexpr int NBM = R_ * (K - 1);               // mixed: operator entries without the origin column
+    constexpr int NV = MIX ? NBM : NB + NK;         // float values per stencil (mixed shells: then the
+                                                    // rest curvatures as float64)
+    constexpr int NCH32 = stream_chunks(rec32_fields(K, R_, SHELL), 4);
     constexpr int NCHI = stream_chunks(K, 4);
-    constexpr int NCHV = stream_chunks(rec64_fields(K, NK), 2);
+    constexpr int NCHV = stream_chunks(rec64_fields(K, R_), 2);
     struct In {
         int vid[K];
-        V3<double> pg[K];  // FP64: positions; mixed: displacements from the rest shape
-        R ob[NB + NK];
-        R c0[NC];
-        R rd[ND];          // mixed shells: rest differences
+        bool clamp;           // mixed plates: a stencil with a clamped edge (rest-relative curvature)
+        double ab[2];         // mixed edge plates: the tip's rest-plane coordinates (alpha, beta)
+        double k0[SHELL ? R_ : 1];  // mixed shells: the rest curvatures of the rounded operator
+        V3<double> pg[K];     // positions
+        V3<double> pr[REST ? K : 1];  // mixed plates: rest positions
+        R ob[NV];
     };
     auto load = [&](long e, In& in) {
         const long first = (e / kStreamBlock) * kStreamBlock, lane = e % kStreamBlock;
-        if constexpr (REL) {
+        if constexpr (MIX) {
             const gbl<const f32x4>* rec = G(static_cast<const f32x4*>(d.trec)) + first * NCH32 + lane;
             float f[4 * NCH32];
 #pragma unroll
@@ -189,22 +234,24 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
                 f[4 * c + 2] = v.z;
                 f[4 * c + 3] = v.w;
             }
+            const uint32_t id0 = __float_as_uint(f[0]);
+            in.clamp = (id0 & kRecClampBit) != 0;
+            in.vid[0] = int(id0 & kRecIdMask);
 #pragma unroll
-            for (int j = 0; j < K; ++j) in.vid[j] = __float_as_int(f[j]);
+            for (int j = 1; j < K; ++j) in.vid[j] = __float_as_int(f[j]);
 #pragma unroll
-            for (int q = 0; q < NB + NK; ++q) in.ob[q] = f[K + q];
+            for (int q = 0; q < NV; ++q) in.ob[q] = f[K + q];
+            auto f64 = [&](int at) {
+                return __longlong_as_double((long long)((unsigned long long)__float_as_uint(f[at]) |
+                                                        ((unsigned long long)__float_as_uint(f[at + 1]) << 32)));
+            };
+            if constexpr (EDGE && !SHELL) {
 #pragma unroll
-            for (int q = 0; q < NC; ++q) in.c0[q] = f[K + NB + NK + q];
+                for (int q = 0; q < 2; ++q) in.ab[q] = f64(kRecEdgeAffine + 2 * q);
+            }
             if constexpr (SHELL) {
 #pragma unroll
-                for (int q = 0; q < ND; ++q) in.rd[q] = f[K + NB + NK + NC + q];
-            }
-            // padded displacements: (x, y) and (z, 0) are two aligned 16-byte loads per vertex
-            const gbl<const f64x2>* u2 = G(reinterpret_cast<const f64x2*>(d.x));
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const f64x2 a = u2[2L * in.vid[j]], b = u2[2L * in.vid[j] + 1];
-                in.pg[j] = {a.x, a.y, b.x};
+                for (int q = 0; q < R_; ++q) in.k0[q] = f64(K + NBM + 2 * q);
             }
         } else {
             const gbl<const i32x4>* ti = G(reinterpret_cast<const i32x4*>(d.tidx)) + first * NCHI + lane;
@@ -227,76 +274,174 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
             }
 #pragma unroll
             for (int j = 0; j < K; ++j) in.vid[j] = fi[j];
+            in.clamp = false;
 #pragma unroll
-            for (int q = 0; q < NB + NK; ++q) in.ob[q] = R(fv[q]);
+            for (int q = 0; q < NV; ++q) in.ob[q] = R(fv[q]);
+        }
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            in.pg[j] = {x[3L * in.vid[j]], x[3L * in.vid[j] + 1], x[3L * in.vid[j] + 2]};
+        if constexpr (REST) {
 #pragma unroll
             for (int j = 0; j < K; ++j)
-                in.pg[j] = {x[3L * in.vid[j]], x[3L * in.vid[j] + 1], x[3L * in.vid[j] + 2]};
+                in.pr[j] = {X[3L * in.vid[j]], X[3L * in.vid[j] + 1], X[3L * in.vid[j] + 2]};
         }
     };
-    // float64 difference of the gathered vectors of vertices j and o, rounded to R (FP64: of positions;
-    // mixed: of displacements)
-    auto diff = [&](const In& in, int j, int o) { return cvt<R>(in.pg[j] - in.pg[o]); };
-    auto rest = [&](const In& in, int q) { return mk(in.rd[3 * q], in.rd[3 * q + 1], in.rd[3 * q + 2]); };
     auto compute = [&](const In& in) {
         V3<R> fs[K];
         R en;
+        // float64 differences from the origin
+        V3<double> dv[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) dv[j] = in.pg[j] - in.pg[O];
         if constexpr (EDGE) {
-            const R L[4] = {in.ob[0], in.ob[1], in.ob[2], in.ob[3]};
-            V3<R> a = diff(in, 0, 1), c = diff(in, 2, 1), b = diff(in, 3, 1);
+            R L[4];
+            if constexpr (MIX) {
+                L[0] = in.ob[0];
+                L[2] = in.ob[1];
+                L[3] = in.ob[2];
+                L[1] = -(L[0] + L[2] + L[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) L[j] = in.ob[j];
+            }
+            const V3<R> a = cvt<R>(dv[0]), c = cvt<R>(dv[2]), b = cvt<R>(dv[3]);
             V3<R> C;
-            if constexpr (REL) {
-                // a, c, b are displacement differences here: C = C0 + B u^e, then the position
-                // differences of the normal are the rest ones plus these
-                C = mk(in.c0[0], in.c0[1], in.c0[2]);
-                fma3(C, L[0], a);
+            R delta = R(0);
+            EdgeFrame<R> fr{};
+            if constexpr (SHELL) {
+                fr = edge_frame<R>(a, c, b);
+                C = L[0] * a;
                 fma3(C, L[2], c);
                 fma3(C, L[3], b);
-                if constexpr (SHELL) {
-                    a = rest(in, 0) + a;
-                    c = rest(in, 1) + c;
-                    b = rest(in, 2) + b;
+                if constexpr (MIX) {
+                    // the float32 normal renormalised in float64: its length error would otherwise
+                    // enter the heights along n, as kappa0 times eps_32
+                    V3<double> nd = cvt<double>(fr.n);
+                    nd = (1.0 / norm(nd)) * nd;
+                    double dl = -in.k0[0];
+                    dl = fma(double(L[0]), dot(dv[0], nd), dl);
+                    dl = fma(double(L[2]), dot(dv[2], nd), dl);
+                    dl = fma(double(L[3]), dot(dv[3], nd), dl);
+                    delta = R(dl);
+                } else {
+                    delta = dot(fr.n, C) - in.ob[4];
+                }
+            } else if constexpr (MIX) {
+                if (in.clamp) {
+                    // rest-relative (a boundary stencil): the rest positions are gathered here only
+                    C = mk(R(0), R(0), R(0));
+                    const V3<double> Xo = {X[3L * in.vid[O]], X[3L * in.vid[O] + 1], X[3L * in.vid[O] + 2]};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (j != O) {
+                            const V3<double> Xj = {X[3L * in.vid[j]], X[3L * in.vid[j] + 1], X[3L * in.vid[j] + 2]};
+                            fma3(C, L[j], cvt<R>(dv[j] - (Xj - Xo)));
+                        }
+                } else {
+                    // the tip's deviation from the affine map of the first hinge triangle
+                    V3<double> w = dv[3];
+                    fma3(w, -in.ab[0], dv[0]);
+                    fma3(w, -in.ab[1], dv[2]);
+                    C = L[3] * cvt<R>(w);
                 }
             } else {
                 C = L[0] * a;
                 fma3(C, L[2], c);
                 fma3(C, L[3], b);
             }
-            edge_stencil<R, SHELL>(a, c, b, C, L, in.ob[4], fs, en);
+            edge_force<R, SHELL>(a, c, b, C, L, fr, delta, fs, en);
         } else {
-            R Bm[3][6], k0[3];
+            R Bm[3][6];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
+                if constexpr (MIX) {
+                    R s0 = R(0);
 #pragma unroll
-                for (int j = 0; j < 6; ++j) Bm[i][j] = in.ob[i * 6 + j];
-                k0[i] = in.ob[NB + i];
+                    for (int j = 1; j < 6; ++j) {
+                        Bm[i][j] = in.ob[5 * i + j - 1];
+                        s0 += Bm[i][j];
+                    }
+                    Bm[i][0] = -s0;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 6; ++j) Bm[i][j] = in.ob[6 * i + j];
+                }
             }
             V3<R> dd[6], C[3];
-            dd[0] = mk(R(0), R(0), R(0));
 #pragma unroll
-            for (int j = 1; j < 6; ++j) dd[j] = diff(in, j, 0);
+            for (int j = 0; j < 6; ++j) dd[j] = cvt<R>(dv[j]);
+            R de[3] = {R(0), R(0), R(0)};
+            V3<R> n = mk(R(0), R(0), R(0));
+            R ilu = R(0);
+            if constexpr (SHELL) {
+                const V3<R> u = cross(dd[1], dd[2]);
+                ilu = R(1) / norm(u);
+                n = ilu * u;
+            }
+            if constexpr (MIX && !SHELL) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                if constexpr (REL)
-                    C[i] = mk(in.c0[3 * i], in.c0[3 * i + 1], in.c0[3 * i + 2]);
-                else
+                for (int i = 0; i < 3; ++i) C[i] = mk(R(0), R(0), R(0));
+                if (in.clamp) {
+#pragma unroll
+                    for (int j = 1; j < 6; ++j) {
+                        const V3<R> du = cvt<R>(dv[j] - (in.pr[j] - in.pr[0]));
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) fma3(C[i], Bm[i][j], du);
+                    }
+                } else {
+                    // the flaps' deviation from the affine map of the central triangle
+                    const V3<double> e1 = in.pr[1] - in.pr[0], e2 = in.pr[2] - in.pr[0];
+                    const Plane2 pl(e1, e2);
+#pragma unroll
+                    for (int j = 3; j < 6; ++j) {
+                        double a, b;
+                        pl.coords(e1, e2, in.pr[j] - in.pr[0], a, b);
+                        V3<double> w = dv[j];
+                        fma3(w, -a, dv[1]);
+                        fma3(w, -b, dv[2]);
+                        const V3<R> wr = cvt<R>(w);
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) fma3(C[i], Bm[i][j], wr);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
                     C[i] = mk(R(0), R(0), R(0));
 #pragma unroll
-                for (int j = 1; j < 6; ++j) fma3(C[i], Bm[i][j], dd[j]);
+                    for (int j = 1; j < 6; ++j) fma3(C[i], Bm[i][j], dd[j]);
+                }
+                if constexpr (SHELL) {
+                    if constexpr (MIX) {
+                        // the float32 normal renormalised in float64 (its length error would otherwise
+                        // enter the heights along n, as kappa0 times eps_32)
+                        V3<double> nd = cvt<double>(n);
+                        nd = (1.0 / norm(nd)) * nd;
+                        double h[6];
+#pragma unroll
+                        for (int j = 1; j < 6; ++j) h[j] = dot(dv[j], nd);
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            double s0 = -in.k0[i];
+#pragma unroll
+                            for (int j = 1; j < 6; ++j) s0 = fma(double(Bm[i][j]), h[j], s0);
+                            de[i] = R(s0);
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) de[i] = dot(n, C[i]) - in.ob[NB + i];
+                    }
+                }
             }
-            if constexpr (REL && SHELL) {
-                // the normal and its gradient use the position differences of the central triangle
-                dd[1] = rest(in, 0) + dd[1];
-                dd[2] = rest(in, 1) + dd[2];
-            }
-            tri_stencil<R, SHELL>(dd, C, Bm, k0, kb, nu, fs, en);
+            tri_force<R, SHELL>(dd, C, Bm, de, n, ilu, kb, nu, fs, en);
         }
         // the tile that owns vertex 1 of the stencil counts its energy
         if (unsigned(in.vid[0] - base) < unsigned(nown)) e_own += double(en);
 #pragma unroll
         for (int j = 0; j < K; ++j) {
             unsigned slot = unsigned(in.vid[j] - base);
-            if (slot < unsigned(nown)) lds_add(acc, int(slot), fs[j]);
+            if (slot < unsigned(nown)) lds_add(acc, int(slot), fs[j], inv_scale);
         }
     };
     const long e0 = d.boff[2 * blk], e1 = d.boff[2 * blk + 1];
@@ -307,21 +452,22 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
     }
     __syncthreads();
     gbl<R>* out = G(static_cast<R*>(d.f)) + 3 * base;
-    if constexpr (!REL) {
+    const double sc = d.fscale;
+    if constexpr (!MIX) {
         if (d.bias) {
             // plates with clamped edges: the constant force and energy terms that make the clamped
             // stencils rest-relative, f + F0 and E - F0 . x (+ E0 once, when the partials are summed)
             const gbl<const double>* b = G(d.bias) + 3 * base;
             for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) {
                 const double bi = b[i];
-                out[i] = acc[i] + bi;
+                out[i] = acc.get(i) * sc + bi;
                 e_own -= bi * x[3 * base + i];
             }
         } else {
-            for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
+            for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc.get(i) * sc);
         }
     } else {
-        for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc[i]);
+        for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(acc.get(i) * sc);
     }
     if (d.epart) {
         __shared__ double sh[kMaxForceThreads / 64];
@@ -354,7 +500,7 @@ void launch_model(int precision, const ForceDesc* descs, const WorkItem* items, 
     static const int threads_d = force_threads(force_tiles<MODEL, double>);
     static const int threads_f = force_threads(force_tiles<MODEL, float>);
     const dim3 grid(unsigned(xcd_grid(nitems)));
-    const uint32_t lds = uint32_t(size_t(3 * lds_T) * sizeof(double));
+    const uint32_t lds = uint32_t(TileAcc::bytes(lds_T));
     // start/stop (may be null) receive the dispatch's own begin and end times
     if (precision == SHELL_PREC_FP64)
         hipExtLaunchKernelGGL(force_tiles<MODEL, double>, grid, dim3(threads_d), lds, s, start, stop, 0, descs,
@@ -374,17 +520,6 @@ __global__ void energy_finalize(const double* __restrict__ part, long n, double 
     double v[1] = {acc};
     block_sum<1>(v, sh);
     if (threadIdx.x == 0) *out = v[0] + add;
-}
-
-// dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order displacements from the rest
-// shape, padded to four doubles (the mixed-precision force kernels' input)
-__global__ void gather_displacements(const double* __restrict__ src, const int32_t* __restrict__ perm,
-                                     const double* __restrict__ X, double* __restrict__ dst, long nv) {
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i >= nv) return;
-    long u = perm[i];
-    for (int c = 0; c < 3; ++c) dst[4 * i + c] = src[3 * u + c] - X[3 * i + c];
-    dst[4 * i + 3] = 0.0;
 }
 
 __global__ void gather_rows(const double* __restrict__ src, const int32_t* __restrict__ perm,
@@ -427,13 +562,6 @@ void launch_force_items(int model, int precision, const ForceDesc* descs, const 
 void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s,
                             const double* extra, int64_t m) {
     energy_finalize<<<1, 256, 0, s>>>(epart, n, add, extra, m, energy);
-    SHELL_HIP(hipGetLastError());
-}
-
-void launch_gather_displacements(const double* src, const int32_t* perm, const double* X, double* dst, int64_t nv,
-                                 hipStream_t s) {
-    if (!nv) return;
-    gather_displacements<<<(nv + 255) / 256, 256, 0, s>>>(src, perm, X, dst, nv);
     SHELL_HIP(hipGetLastError());
 }
 

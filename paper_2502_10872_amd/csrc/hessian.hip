@@ -28,38 +28,43 @@ __device__ __forceinline__ long find_slot(const int32_t* __restrict__ scol, cons
     return s0 + 64L * lo;
 }
 
+// Row i of K_s: over the stencils that contain vertex i (as local vertex j), in ascending order, row j of
+// the stencil's block B^T D B.  One thread per row writes only its own slots, so the sums take the same
+// order in every run.
 template <int K, int R>
-__global__ void assemble_stencils(const int32_t* __restrict__ idx, const double* __restrict__ B, long ns,
-                                  const int32_t* __restrict__ missing, double kb, double nu,
-                                  const int32_t* __restrict__ scol, const int64_t* __restrict__ sptr,
-                                  const int32_t* __restrict__ rowlen, double* __restrict__ val) {
-    long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (s >= ns) return;
-    int v[K];
-    double Bm[R][K];
-    for (int j = 0; j < K; ++j) v[j] = idx[j * ns + s];
-    for (int i = 0; i < R; ++i)
-        for (int j = 0; j < K; ++j) Bm[i][j] = B[(i * K + j) * ns + s];
-    int miss = missing ? missing[s] : 0;
-    // D B (the stiffness is already folded into B for edges; triangles carry D_b)
-    double DB[R][K];
-    if constexpr (R == 1) {
-        for (int j = 0; j < K; ++j) DB[0][j] = Bm[0][j];
-    } else {
-        double t = 0.5 * (1.0 - nu);
-        for (int j = 0; j < K; ++j) {
-            DB[0][j] = kb * (Bm[0][j] + nu * Bm[1][j]);
-            DB[1][j] = kb * (nu * Bm[0][j] + Bm[1][j]);
-            DB[2][j] = kb * t * Bm[2][j];
+__global__ void assemble_rows(const int64_t* __restrict__ inc_ptr, const int64_t* __restrict__ inc,
+                              const int32_t* __restrict__ idx, const double* __restrict__ B, long ns,
+                              const int32_t* __restrict__ missing, double kb, double nu,
+                              const int32_t* __restrict__ scol, const int64_t* __restrict__ sptr,
+                              const int32_t* __restrict__ rowlen, long nv, double* __restrict__ val) {
+    const long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i >= nv) return;
+    for (int64_t e = inc_ptr[i]; e < inc_ptr[i + 1]; ++e) {
+        const long s = long(inc[e] >> 3);
+        const int j = int(inc[e] & 7);
+        int v[K];
+        double Bm[R][K];
+        for (int l = 0; l < K; ++l) v[l] = idx[l * ns + s];
+        for (int r = 0; r < R; ++r)
+            for (int l = 0; l < K; ++l) Bm[r][l] = B[(r * K + l) * ns + s];
+        const int miss = missing ? missing[s] : 0;
+        // D B (the stiffness is already folded into B for edges; triangles carry D_b)
+        double DB[R][K];
+        if constexpr (R == 1) {
+            for (int l = 0; l < K; ++l) DB[0][l] = Bm[0][l];
+        } else {
+            const double t = 0.5 * (1.0 - nu);
+            for (int l = 0; l < K; ++l) {
+                DB[0][l] = kb * (Bm[0][l] + nu * Bm[1][l]);
+                DB[1][l] = kb * (nu * Bm[0][l] + Bm[1][l]);
+                DB[2][l] = kb * t * Bm[2][l];
+            }
         }
-    }
-    for (int j = 0; j < K; ++j) {
-        if (j >= 3 && (miss & (1 << (j - 3)))) continue;
         for (int l = 0; l < K; ++l) {
             if (l >= 3 && (miss & (1 << (l - 3)))) continue;
             double g = 0.0;
-            for (int i = 0; i < R; ++i) g += Bm[i][j] * DB[i][l];
-            atomicAdd(val + find_slot(scol, sptr, rowlen, v[j], v[l]), g);
+            for (int r = 0; r < R; ++r) g += Bm[r][j] * DB[r][l];
+            val[find_slot(scol, sptr, rowlen, i, v[l])] += g;
         }
     }
 }
@@ -123,14 +128,19 @@ void launch_assemble(shell_hessian_s& h, hipStream_t s) {
         md.upload(mask.data(), size_t(ns), s);
     }
     if (ns) {
-        long grid = (ns + 255) / 256;
+        const Incidence inc = build_incidence(st.h_idx, st.k, ns, st.nv);
+        DevArray<int64_t> iptr(inc.ptr.size()), icode(std::max<size_t>(inc.code.size(), 1));
+        iptr.upload(inc.ptr.data(), inc.ptr.size(), s);
+        icode.upload(inc.code.data(), inc.code.size(), s);
+        const long grid = (st.nv + 255) / 256;
         if (model_is_edge(st.model))
-            assemble_stencils<4, 1><<<grid, 256, 0, s>>>(st.idx.p, st.B.p, ns, nullptr, st.kb, st.poisson, h.scol.p,
-                                                         h.sptr.p, h.rowlen.p, h.val.p);
+            assemble_rows<4, 1><<<grid, 256, 0, s>>>(iptr.p, icode.p, st.idx.p, st.B.p, ns, nullptr, st.kb,
+                                                     st.poisson, h.scol.p, h.sptr.p, h.rowlen.p, st.nv, h.val.p);
         else
-            assemble_stencils<6, 3><<<grid, 256, 0, s>>>(st.idx.p, st.B.p, ns, md.p, st.kb, st.poisson, h.scol.p,
-                                                         h.sptr.p, h.rowlen.p, h.val.p);
+            assemble_rows<6, 3><<<grid, 256, 0, s>>>(iptr.p, icode.p, st.idx.p, st.B.p, ns, md.p, st.kb,
+                                                     st.poisson, h.scol.p, h.sptr.p, h.rowlen.p, st.nv, h.val.p);
         SHELL_HIP(hipGetLastError());
+        SHELL_HIP(hipStreamSynchronize(s));  // the incidence lists are released on return
     }
     DevArray<int64_t> dslot(static_cast<size_t>(st.nv));
     dslot.upload(h.pat.dslot.data(), size_t(st.nv), s);

@@ -351,4 +351,23 @@ SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t n
     return P;
 }
 
+Incidence build_incidence(const std::vector<int32_t>& idx, int k, int64_t n, int64_t nv) {
+    Incidence inc;
+    inc.ptr.assign(size_t(nv + 1), 0);
+    for (int64_t t = 0; t < n; ++t)
+        for (int j = 0; j < k; ++j) {
+            const int32_t v = idx[size_t(k * t + j)];
+            if (v >= 0) ++inc.ptr[size_t(v) + 1];
+        }
+    for (int64_t v = 0; v < nv; ++v) inc.ptr[size_t(v + 1)] += inc.ptr[size_t(v)];
+    inc.code.resize(size_t(inc.ptr[size_t(nv)]));
+    std::vector<int64_t> fill(inc.ptr.begin(), inc.ptr.end() - 1);
+    for (int64_t t = 0; t < n; ++t)
+        for (int j = 0; j < k; ++j) {
+            const int32_t v = idx[size_t(k * t + j)];
+            if (v >= 0) inc.code[size_t(fill[size_t(v)]++)] = t * 8 + j;
+        }
+    return inc;
+}
+
 }  // namespace shell

@@ -104,14 +104,22 @@ constexpr int kStreamBlock = 64;
 __host__ __device__ constexpr int stream_chunks(int nfields, int per_chunk) {
     return (nfields + per_chunk - 1) / per_chunk;
 }
-// Fields per stencil.  Mixed precision: one 32-bit record of k vertex ids, r*k operator entries, r rest
-// curvatures, the 3r components of the rest curvature vectors C0 = B X^e and, for shells, the rest
-// differences that the normal needs (edge: X0 - X1, X2 - X1, X3 - X1; triangle: X1 - X0, X2 - X0).
+// Fields per stencil.  Mixed precision: one 32-bit record of the k vertex ids, the operator's r*(k-1)
+// entries other than the origin's column (edge: vertex 1, the hinge's first end; triangle: vertex 0),
+// which the kernel takes as minus the sum of the row's other entries (every row of B sums to zero), and
+// for shells the r rest curvatures kappa0 = B~ h0 of the float32-rounded operator B~ on the rest heights
+// h0, in float64 (as the bit patterns of r doubles), so that the bending strain B~ h - kappa0, summed in
+// float64, vanishes at the rest shape to float64 rounding.  The edge plate adds, from field 8 on, the
+// float64 coordinates (alpha, beta) of its tip 3 in the basis of the rest edges 0 - 1 and 2 - 1, all three
+// projected onto the rest tangent plane, as two doubles.  Plate stencils with a clamped edge set bit 31 of
+// the first id.
 // FP64: the k ids in one stream and the r*k + r operator entries and rest curvatures in another.
-__host__ __device__ constexpr int rec32_rest_diffs(int k, bool shell) { return shell ? (k == 4 ? 9 : 6) : 0; }
 __host__ __device__ constexpr int rec32_fields(int k, int r, bool shell) {
-    return k + r * k + r + 3 * r + rec32_rest_diffs(k, shell);
+    return (k == 4 && !shell) ? 12 : k + r * (k - 1) + (shell ? 2 * r : 0);
 }
+constexpr int kRecEdgeAffine = 8;  // first field of the edge plate's (alpha, beta)
+constexpr uint32_t kRecClampBit = 0x80000000u;
+constexpr uint32_t kRecIdMask = 0x7fffffffu;
 __host__ __device__ constexpr int rec64_fields(int k, int r) { return r * k + r; }
 
 struct Tiling {
@@ -123,6 +131,15 @@ struct Tiling {
 };
 // Groups stencils (internal vertex ids) by the vertex tiles they touch; halo stencils repeat.
 Tiling build_tiling(const std::vector<int32_t>& idx, int k, int64_t ns, int64_t nv, int T);
+
+// For every vertex, the tuples of a k-tuple list (stencils, triangles) that contain it, in ascending
+// tuple order: code = tuple * 8 + position.  Lets the one-time sums over a vertex's stencils (the rows of
+// K_s, the lumped mass, the clamp force) be taken per vertex in a fixed order, without atomics.
+struct Incidence {
+    std::vector<int64_t> ptr;   // [nv + 1]
+    std::vector<int64_t> code;  // [ptr[nv]]
+};
+Incidence build_incidence(const std::vector<int32_t>& idx, int k, int64_t n, int64_t nv);
 
 struct SellPattern {
     int64_t nv = 0, nslices = 0, nnz = 0, nslots = 0;
@@ -151,7 +168,8 @@ SellPattern build_sell_pattern(const std::vector<int32_t>& idx, int k, int64_t n
 // Per-mesh arguments of the force kernel.  Kernels take an array of descriptors and a list of work
 // items (mesh, unit): one launch covers any set of meshes, a single mesh being a set of one.
 struct ForceDesc {
-    const double* x;       // FP64: positions [nv][3]; mixed: displacements from the rest shape [nv][4]
+    const double* x;       // positions [nv][3] (both precisions)
+    const double* X;       // rest positions [nv][3] (read by the mixed plate kernels)
     void* f;               // double or float [nv][3]
     double* epart;         // per-tile energy, or null
     const double* bias;    // FP64 plates with clamped edges: constant force [nv][3] added to f, or null
@@ -161,6 +179,7 @@ struct ForceDesc {
     int64_t nst, nv;
     int32_t T, model;
     double kb, nu;
+    double fscale;         // power-of-two force scale of the tile accumulation (TileAcc)
 };
 
 // Per-mesh arguments of the implicit-step kernels.
@@ -176,8 +195,9 @@ struct SolveDesc {
     const double* fext;             // quasi-static: the applied load F [nv][3] (internal order), or null
     double* ustep;                  // quasi-static with an increment limit: the Newton step's scale, or null
     double eps_u;                   // quasi-static increment limit (max |dx| per Newton iteration)
-    void* y;                        // the Newton increment the PCG builds (float in mixed precision)
-    double* u4;                     // mixed precision only: x - X padded to [nv][4], the force kernel's input
+    void* y;                        // the Newton increment the PCG builds (float in mixed precision: the part
+                                    // not yet folded into y64)
+    double* y64;                    // mixed precision only: the float64 part of the increment (y = y64 + y)
     const double* X;                // rest positions
     void *f, *p0, *p1, *q, *dinv;   // float in mixed precision; p0/p1 alternate as the search direction
     float* z;                       // mixed precision only: z = D^-1 r as float (null in FP64: recomputed)
@@ -193,7 +213,9 @@ struct SolveDesc {
     const uint16_t* lcol;
     PcgState* st;                   // two states: st[t & 1] enters PCG iteration t
     double* part;                   // reduction partials, quantity-major [q][group]
-    double* bins;                   // PCG dot-product bins [parity][set][quantity][bin]
+    double* bins;                   // PCG dot-product partials [parity][set][quantity][work-group slot]
+    int32_t pq_lo, pq_hi;           // logical work-groups of the product launch that can touch this mesh
+    int32_t rz_lo, rz_hi;           // the same for the update launch (and the solve's first kernel)
     int64_t nv, ngroups;
     double dt, dt2, grav[3], rtol2;
     int32_t replay, target[3];
@@ -215,6 +237,10 @@ struct shell_stencils_s {
     int cfg_flags = 0;  // SHELL_FLAG_*
     bool reordered = false;
     double young = 0, poisson = 0, thickness = 0, density = 0, kb = 0;
+    // power-of-two force scales of the tile accumulation (l the mean rest edge): bending k_b / l 2^-10, the
+    // force of a kink at the element scale divided by 1024, so that contributions up to 128 times that
+    // force and down to 1e-18 of it are summed exactly; membrane E h l 2^-16, strains up to 2
+    double fscale = 1.0, mscale = 1.0;
     std::vector<int32_t> perm, iperm;    // internal -> caller, caller -> internal
     std::vector<int32_t> h_idx;          // [ns][k] internal ids, -1 = missing
     std::vector<int32_t> h_tris;         // [nt][3] internal ids
@@ -241,7 +267,7 @@ struct shell_stencils_s {
     // tiled streams, only those of the configured precision: [nst_pad / 64][chunks][64][fields per chunk]
     shell::DevArray<int32_t> tidx;       // FP64: vertex ids
     shell::DevArray<double> trec64;      // FP64: operator entries and rest curvatures
-    shell::DevArray<float> trec32;       // mixed: ids (bit patterns), operator, rest curvatures, C0
+    shell::DevArray<float> trec32;       // mixed: ids (bit patterns), operator, rest curvatures
     // scratch for the caller-order entry point
     shell::DevArray<double> xin;         // [nv][3]
     shell::DevArray<double> fout;        // [nv][3] (float for mixed, sized in doubles)
@@ -313,13 +339,13 @@ struct shell_sim_s {
     double dinv_dt = -1.0;               // dt the preconditioner was built for (0: the quasi-static K alone)
     hipStream_t last_stream = nullptr;
     shell::DevArray<double> x, v, xt, xhat, g, mass, y, r;
+    shell::DevArray<double> y64;         // mixed only: float64 part of the PCG increment
     shell::DevArray<double> f;           // float64 forces (or float32 in mixed, sized in doubles)
     shell::DevArray<double> dinv;        // [nv] (float in mixed)
     shell::DevArray<double> mq;          // [nv] mass for the product, -1 on fixed rows (float in mixed)
     shell::DevArray<uint8_t> pinned;
     shell::DevArray<double> p, p2, q;    // PCG work vectors (float in mixed; sized in doubles)
     shell::DevArray<float> z;            // mixed only: the preconditioned residual, read by the product
-    shell::DevArray<double> u4;          // mixed only: displacements from the rest shape, [nv][4]
     shell::DevArray<double> bins;        // PCG dot-product bins
     shell::DevArray<double> partials;    // reduction partials
     // quasi-static solves only: zero mass, the applied load (internal order), the Newton step's scale
@@ -411,10 +437,10 @@ void launch_force_items(int model, int precision, const ForceDesc* descs, const 
 // energy = add + sum of the n partials (+ the m partials of `extra`, when given)
 void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s,
                             const double* extra = nullptr, int64_t m = 0);
-// membrane.hip: rest data of the membrane (SHELL_FLAG_MEMBRANE); its force added into f (internal order),
-// from positions (FP64) or from displacements u4 [nv][4] and the rest positions (mixed)
+// membrane.hip: rest data of the membrane (SHELL_FLAG_MEMBRANE); its force added into f (internal order,
+// double or float per the stencils' precision) from the float64 positions pos
 void launch_membrane_rest(shell_stencils_s& st, hipStream_t s);
-void launch_membrane_forces(shell_stencils_s& st, const double* pos, const double* u4, void* f, hipStream_t s);
+void launch_membrane_forces(shell_stencils_s& st, const double* pos, void* f, hipStream_t s);
 // the implicit step with the membrane: set-up once per simulation, then one step (float64)
 void membrane_sim_init(shell_sim_s& sim, hipStream_t s);
 shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, shell_step_stats_t& out,
@@ -427,9 +453,6 @@ struct MembraneStatic {
 shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, const MembraneStatic& qs,
                                shell_step_stats_t& out, hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
-// dst[i] = (src[perm[i]] - X[i], 0): caller-order positions to internal-order padded displacements
-void launch_gather_displacements(const double* src, const int32_t* perm, const double* X, double* dst, int64_t nv,
-                                 hipStream_t s);
 void launch_scatter_rows(const void* src, const int32_t* perm, void* dst, int64_t nv, bool f32, hipStream_t s);
 // hessian.hip
 void launch_assemble(shell_hessian_s& h, hipStream_t s);

@@ -7,8 +7,10 @@
 // dPsi/dDs = A F S G^T (S the stress as a 2x2 tensor), so f1 and f2 are minus its columns and f0 their
 // sum.  The triangles are grouped by the same vertex tiles as the bending stencils (halo triangles
 // repeat): each work-group accumulates the forces of its own vertices in LDS and adds them to the force
-// the bending kernel stored, one read and one write per vertex and no global atomics.  In mixed precision
-// the edge vectors are the rest edges plus the displacement differences, in float64.
+// the bending kernel stored, one read and one write per vertex and no global atomics (the LDS sums are
+// exact fixed-point parts, so they do not depend on the order of the additions).  Both precisions
+// compute in float64 from float64 positions (the Green strain F^T F - I cancels to the strain's size);
+// mixed precision stores the sum as float32.
 #include <algorithm>
 #include <cmath>
 
@@ -61,19 +63,18 @@ constexpr int kMembThreads = 512;
 
 template <typename R>
 __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __restrict__ pos,
-                                                               const double* __restrict__ u4,
-                                                               const double* __restrict__ X,
                                                                const int32_t* __restrict__ tid,
                                                                const double* __restrict__ trest,
                                                                const int64_t* __restrict__ boff, long nv, int T,
-                                                               double c, double nu, R* __restrict__ f,
-                                                               double* __restrict__ epart) {
+                                                               double c, double nu, double scale,
+                                                               R* __restrict__ f, double* __restrict__ epart) {
     extern __shared__ unsigned char smem_raw[];
-    double* acc = reinterpret_cast<double*>(smem_raw);
     const long blk = blockIdx.x;
     const long base = blk * long(T);
     const int nown = int(min(long(T), nv - base));
-    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) acc[i] = 0.0;
+    TileAcc acc(smem_raw, T);
+    acc.clear(3 * nown);
+    const double inv_scale = 1.0 / scale;  // a power of two: exact
     __syncthreads();
     double en[1] = {0.0};
     const long e0 = boff[2 * blk], e1 = boff[2 * blk + 1];
@@ -81,13 +82,8 @@ __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __r
         const long v[3] = {tid[4 * e], tid[4 * e + 1], tid[4 * e + 2]};
         double d1[3], d2[3];
         for (int i = 0; i < 3; ++i) {
-            if (pos) {
-                d1[i] = pos[3 * v[1] + i] - pos[3 * v[0] + i];
-                d2[i] = pos[3 * v[2] + i] - pos[3 * v[0] + i];
-            } else {
-                d1[i] = (X[3 * v[1] + i] - X[3 * v[0] + i]) + (u4[4 * v[1] + i] - u4[4 * v[0] + i]);
-                d2[i] = (X[3 * v[2] + i] - X[3 * v[0] + i]) + (u4[4 * v[2] + i] - u4[4 * v[0] + i]);
-            }
+            d1[i] = pos[3 * v[1] + i] - pos[3 * v[0] + i];
+            d2[i] = pos[3 * v[2] + i] - pos[3 * v[0] + i];
         }
         const double G[2][2] = {{trest[6 * e], trest[6 * e + 1]}, {trest[6 * e + 2], trest[6 * e + 3]}};
         const double A = trest[6 * e + 4];
@@ -104,14 +100,15 @@ __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __r
         for (int i = 0; i < 3; ++i) {
             const double P0 = A * (F[i][0] * s0 + F[i][1] * s2), P1 = A * (F[i][0] * s2 + F[i][1] * s1);
             const double h0 = P0 * G[0][0] + P1 * G[0][1], h1 = P0 * G[1][0] + P1 * G[1][1];
-            if (o1 < unsigned(nown)) atomicAdd(acc + 3 * o1 + i, -h0);
-            if (o2 < unsigned(nown)) atomicAdd(acc + 3 * o2 + i, -h1);
-            if (o0 < unsigned(nown)) atomicAdd(acc + 3 * o0 + i, h0 + h1);
+            if (o1 < unsigned(nown)) acc.add(3 * o1 + i, -h0 * inv_scale);
+            if (o2 < unsigned(nown)) acc.add(3 * o2 + i, -h1 * inv_scale);
+            if (o0 < unsigned(nown)) acc.add(3 * o0 + i, (h0 + h1) * inv_scale);
         }
     }
     __syncthreads();
     R* out = f + 3 * base;
-    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(double(out[i]) + acc[i]);
+    const double sc = scale;
+    for (int i = threadIdx.x; i < 3 * nown; i += blockDim.x) out[i] = R(double(out[i]) + acc.get(i) * sc);
     __shared__ double sh[kMembThreads / 64];
     block_sum<1>(en, sh);
     if (threadIdx.x == 0) epart[blk] = en[0];
@@ -519,18 +516,18 @@ void launch_membrane_rest(shell_stencils_s& st, hipStream_t s) {
     SHELL_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
 }
 
-void launch_membrane_forces(shell_stencils_s& st, const double* pos, const double* u4, void* f, hipStream_t s) {
+void launch_membrane_forces(shell_stencils_s& st, const double* pos, void* f, hipStream_t s) {
     if (st.nv == 0 || st.nblocks == 0) return;
     const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
-    const size_t lds = size_t(3 * st.T) * sizeof(double);
+    const size_t lds = TileAcc::bytes(st.T);
     const unsigned grid = unsigned(st.nblocks);
     if (st.precision == SHELL_PREC_MIXED)
-        membrane_tiles<float><<<grid, kMembThreads, lds, s>>>(pos, u4, st.X.p, st.mtid.p, st.mtrest.p, st.mboff.p,
-                                                              st.nv, st.T, c, st.poisson, static_cast<float*>(f),
+        membrane_tiles<float><<<grid, kMembThreads, lds, s>>>(pos, st.mtid.p, st.mtrest.p, st.mboff.p,
+                                                              st.nv, st.T, c, st.poisson, st.mscale, static_cast<float*>(f),
                                                               st.mepart.p);
     else
-        membrane_tiles<double><<<grid, kMembThreads, lds, s>>>(pos, u4, st.X.p, st.mtid.p, st.mtrest.p, st.mboff.p,
-                                                               st.nv, st.T, c, st.poisson, static_cast<double*>(f),
+        membrane_tiles<double><<<grid, kMembThreads, lds, s>>>(pos, st.mtid.p, st.mtrest.p, st.mboff.p,
+                                                               st.nv, st.T, c, st.poisson, st.mscale, static_cast<double*>(f),
                                                                st.mepart.p);
     SHELL_HIP(hipGetLastError());
 }
@@ -624,6 +621,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     // bending force at xtry into ftry, with its energy partials after the reduction partials
     ForceDesc d{};
     d.x = ms->xtry.p;
+    d.X = st.X.p;
     d.f = ms->ftry.p;
     d.epart = ms->part.p + 2 * ms->ngroups;
     d.bias = st.bias.p;
@@ -635,6 +633,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     d.T = st.T;
     d.model = st.model;
     d.kb = st.kb;
+    d.fscale = st.fscale;
     d.nu = st.poisson;
     std::vector<WorkItem> items(size_t(st.nblocks));
     for (int64_t t = 0; t < st.nblocks; ++t) items[size_t(t)] = {0, int32_t(t)};
@@ -724,7 +723,7 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
     // energy and force at xtry (force into ftry)
     auto evaluate = [&]() {
         launch_force_items(st.model, SHELL_PREC_FP64, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
-        launch_membrane_forces(st, m.xtry.p, nullptr, m.ftry.p, s);
+        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s);
         ms_inertia<<<ms_grid(nv), kMsBlk, 0, s>>>(m.xtry.p, sim.xhat.p, sim.mass.p, nv, part, ng);
         ms_energy<<<1, kMsBlk, 0, s>>>(eb, st.nblocks, st.mepart.p, st.nblocks, st.bias_e0, part, ng, dt2,
                                        m.scal.p);
@@ -751,7 +750,11 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
         }
         gn = std::sqrt(hs[S_GSQ]);
         if (k == 0) gn0 = gn;
-        if (gn0 == 0.0 || (k > 0 && gn <= p.newton_rtol * gn0) || k == p.max_newton) break;
+        if (gn0 == 0.0 || (k > 0 && gn <= p.newton_rtol * gn0)) break;
+        if (k == p.max_newton) {
+            out.newton_capped = 1;
+            break;
+        }
         // Gauss-Newton matrix and its Jacobi preconditioner
         const long nb9 = long(m.mval.n);
         ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
@@ -836,7 +839,7 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
     // bending plus membrane force at xtry into ftry, then the load added: ftry = f + F
     auto forces_at_try = [&]() {
         launch_force_items(st.model, SHELL_PREC_FP64, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
-        launch_membrane_forces(st, m.xtry.p, nullptr, m.ftry.p, s);
+        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s);
         if (qs.load) ms_axpy<<<ms_grid(n3), kMsBlk, 0, s>>>(m.ftry.p, qs.load, 1.0, m.ftry.p, n3);
         SHELL_HIP(hipGetLastError());
     };
@@ -857,7 +860,11 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
         }
         gn = std::sqrt(hs[S_GSQ]);
         if (k == 0) gn0 = gn;
-        if (gn == 0.0 || gn < qs.eps_f || k == p.max_newton) break;
+        if (gn == 0.0 || gn < qs.eps_f) break;
+        if (k == p.max_newton) {
+            out.newton_capped = 1;
+            break;
+        }
         const long nb9 = long(m.mval.n);
         ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
         if (nt > 0)

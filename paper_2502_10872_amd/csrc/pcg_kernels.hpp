@@ -25,6 +25,25 @@ inline long blocks(long n) { return (n + kBlk - 1) / kBlk; }
 template <typename VR>
 constexpr bool kStoredZ = sizeof(VR) == 4;
 
+// Mixed precision keeps the PCG increment y in float32 and folds it into a float64 accumulator y64 every
+// kFoldIters iterations of its column (when that column's count is kFoldIters - 1 mod kFoldIters): one
+// float32 rounding per iteration would otherwise leave y about sqrt(iterations) * eps_32 off after a long
+// solve (4e-6 after 19,000 iterations on the 256 x 256 sphere cap), while a float64 y would add 24 B per
+// row to every update.  The fold reads and writes y64 once per kFoldIters iterations.  The condition
+// uses the device-side iteration count, so where the folds fall does not depend on how the iterations
+// were launched.
+constexpr int kFoldIters = 16;
+
+// Whether the product applies K_s in difference form, (K_s p)_i = sum_j K_ij (p_j - p_i) (float32
+// matrix).  Every row of K_s sums to zero (constants are in its null space, eq 12), but float32 entries
+// rounded one at a time do not: a row then sums to about eps_32 |K_ii|, which on a fine mesh outweighs
+// the mass term m_i / dt^2 in the step matrix and spoils its smoothest modes (on the 512 x 512 sphere cap
+// the solution of one step system moves by 1e-3).  In difference form the diagonal entry meets p_i - p_i
+// = 0 and the implied diagonal is minus the sum of the rounded off-diagonals, so each row sums to zero
+// exactly (solution error 2e-7 on the same system).  The float64 matrix keeps the plain form.
+template <typename MR>
+constexpr bool kDiffForm = sizeof(MR) == 4;
+
 // fixed-order sum of NQ partials over ngroups work-groups; result in thread 0's out[]
 template <int NQ>
 __device__ void reduce_partials(const double* __restrict__ part, long ngroups, double (&out)[NQ]) {
@@ -47,38 +66,45 @@ __device__ __forceinline__ bool work_item(const WorkItem* __restrict__ items, lo
 }
 
 // ---------------------------------------------------------------- PCG dot products
-// Each work-group adds its partial sums with device-scope atomics into one of kBins bins per quantity
-// (bin = row group mod kBins), so no bin sees more than ngroups / kBins additions.  The kernel that
-// needs a total sums the kBins bins in a fixed butterfly; every wave of every work-group obtains the
-// same bits.  Bins are double-buffered by iteration parity: a kernel clears the set that the next
-// kernel adds into, never one that a running kernel reads.
-constexpr int kBins = 64;
-constexpr int kBinQ = 8;  // quantity slots per set
+// Each work-group sums its rows' partial dot products of a mesh (in its fixed walk order and a fixed
+// block tree) and stores them, without atomics, in its own slot of that mesh's partials: slot = its
+// logical work-group id.  The kernel that needs a total sums the slots of the work-groups that can touch
+// the mesh ([pq_lo, pq_hi) for the product launch, [rz_lo, rz_hi) for the update launch, set by the host
+// for each launch shape): lane k adds slots lo + k, lo + k + 64, ... in order, then a butterfly across
+// the wave, so every wave of every work-group obtains the same bits, and so does every run.  Slots of
+// work-groups in the range that never meet the mesh stay at the zero written when the solve starts.
+// Partials are double-buffered by iteration parity, so a kernel never writes a set a running kernel
+// reads.
+constexpr int kSlots = 1024;  // largest logical work-group count of a PCG launch
+constexpr int kBinQ = 8;      // quantity slots per set
 constexpr int kSetPq = 0, kSetRz = 1;  // p.q (3 quantities); r.z and r.r (6)
 
 __device__ __forceinline__ double* bin_set(const SolveDesc& d, long par, int set) {
-    return d.bins + (size_t(par & 1) * 2 + size_t(set)) * kBinQ * kBins;
+    return d.bins + (size_t(par & 1) * 2 + size_t(set)) * kBinQ * kSlots;
 }
 
-// totals of NQ quantities, in every lane of the calling wave
+// totals of NQ quantities over the slots [lo, hi), in every lane of the calling wave
 template <int NQ>
-__device__ __forceinline__ void bin_totals(const double* set, double (&tot)[NQ]) {
-    const gbl<const double>* b = G(set) + (threadIdx.x & 63);
+__device__ __forceinline__ void bin_totals(const double* set, int lo, int hi, double (&tot)[NQ]) {
+    const gbl<const double>* b = G(set);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) tot[q] = b[q * kBins];
+    for (int q = 0; q < NQ; ++q) tot[q] = 0.0;
+    for (int k = lo + int(threadIdx.x & 63); k < hi; k += 64)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) tot[q] += b[q * kSlots + k];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) tot[q] = wave_sum(tot[q]);
 }
 
 template <int NQ>
-__device__ __forceinline__ void bin_add(double* set, int unit, const double (&v)[NQ]) {
+__device__ __forceinline__ void bin_store(double* set, int slot, const double (&v)[NQ]) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) atomicAdd(set + q * kBins + (unit % kBins), v[q]);
+    for (int q = 0; q < NQ; ++q) G(set)[q * kSlots + slot] = v[q];
 }
 
-// clears one set; every thread of the work-group takes part
-__device__ __forceinline__ void bin_clear(double* set) {
-    for (int k = threadIdx.x; k < kBinQ * kBins; k += blockDim.x) G(set)[k] = 0.0;
+// zeroes every set of a mesh's partials; every thread of the work-group takes part
+__device__ __forceinline__ void bin_clear_all(const SolveDesc& d) {
+    for (int k = threadIdx.x; k < 2 * 2 * kBinQ * kSlots; k += blockDim.x) G(d.bins)[k] = 0.0;
 }
 
 __global__ __launch_bounds__(kBlk) void k_predictor(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
@@ -140,51 +166,16 @@ __global__ __launch_bounds__(kBlk) void k_residual(const SolveDesc* __restrict__
     if (threadIdx.x == 0) d.part[wi.unit] = acc[0];
 }
 
-// |g|^2 of each mesh; also clears the bins that the coming solve's first kernels add into (the initial
-// r.z, r.r and the first product's p.q)
+// |g|^2 of each mesh; also zeroes the dot-product partials of the coming solve
 __global__ __launch_bounds__(kRedBlk) void k_fin_residual(const SolveDesc* __restrict__ descs, const int32_t* __restrict__ meshes) {
     const SolveDesc& d = descs[meshes[blockIdx.x]];
     double tot[1];
     reduce_partials<1>(d.part, d.ngroups, tot);
-    bin_clear(bin_set(d, 1, kSetRz));
-    bin_clear(bin_set(d, 0, kSetPq));
+    bin_clear_all(d);
     if (threadIdx.x == 0) {
         d.st[0].gsq = tot[0];
         d.st[0].nonfinite = !isfinite(tot[0]);
     }
-}
-
-// r = -g, y = 0; r.z (z = D^-1 r) and r.r into the bins read by the first product (parity 1).  The
-// first product forms p = z itself.
-template <typename VR>
-__global__ __launch_bounds__(kBlk) void k_pcg_init(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items, long nitems) {
-    WorkItem wi;
-    if (!work_item(items, nitems, wi)) return;
-    const SolveDesc& d = descs[wi.mesh];
-    long i = long(wi.unit) * kBlk + threadIdx.x;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    if (i < d.nv) {
-        const VR di = G(static_cast<const VR*>(d.dinv))[i];
-        const gbl<const double>* g = G(static_cast<const double*>(d.g));
-        double gi[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) gi[c] = g[3 * i + c];
-        gbl<double>* r = G(d.r);
-        gbl<VR>* y = G(static_cast<VR*>(d.y));
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double ri = -gi[c];
-            const VR zi = di * VR(ri);
-            r[3 * i + c] = ri;
-            y[3 * i + c] = VR(0);
-            if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zi;
-            acc[c] = ri * double(zi);
-            acc[3 + c] = ri * ri;
-        }
-    }
-    __shared__ double sh[6 * (kBlk / 64)];
-    block_sum<6>(acc, sh);
-    if (threadIdx.x == 0) bin_add<6>(bin_set(d, 1, kSetRz), wi.unit, acc);
 }
 
 // What the rest of a product needs of the recurrence state.
@@ -195,15 +186,14 @@ struct ProductState {
 
 // The recurrence state entering product t: at t == 0 from the initial residual, else the previous state
 // (parity t) advanced by the update of iteration t - 1 (beta, activity, counts, budget).  Every lane of
-// every work-group computes beta and done identically from the bins; thread 0 of row group 0's
-// work-group stores the new state (parity t + 1) field by field, and that work-group clears the bins
-// of this iteration's update.
+// every work-group computes beta and done identically from the partials; thread 0 of row group 0's
+// work-group stores the new state (parity t + 1) field by field.
 __device__ __forceinline__ ProductState product_state(const SolveDesc& d, const WorkItem& wi, long t) {
     const PcgState* so = d.st + (t & 1);
     PcgState* sn = d.st + ((t + 1) & 1);
     const bool writer = wi.unit == 0 && threadIdx.x == 0;
     double tot[6];
-    bin_totals<6>(bin_set(d, t + 1, kSetRz), tot);
+    bin_totals<6>(bin_set(d, t + 1, kSetRz), d.rz_lo, d.rz_hi, tot);
     ProductState r;
     int any = 0;
     if (t == 0) {
@@ -276,7 +266,6 @@ __device__ __forceinline__ ProductState product_state(const SolveDesc& d, const 
             sn->gsq = so->gsq;
         }
     }
-    if (wi.unit == 0) bin_clear(bin_set(d, t, kSetRz));
     return r;
 }
 
@@ -333,8 +322,8 @@ __device__ __forceinline__ void direction(const DirIn<VR>& in, long j, VR (&pj)[
 // Row product for row groups too wide to stage: each neighbour's new direction is formed from its own
 // gathers (four entries in flight per lane).
 template <typename MR, typename VR>
-__device__ __forceinline__ void row_product_direction(const SolveDesc& d, long row, const DirIn<VR>& in, MR& ax,
-                                                      MR& ay, MR& az) {
+__device__ __forceinline__ void row_product_direction(const SolveDesc& d, long row, const DirIn<VR>& in,
+                                                      const VR (&pi)[3], MR& ax, MR& ay, MR& az) {
     const gbl<const int32_t>* scol = G(d.scol);
     const gbl<const MR>* val = G(static_cast<const MR*>(d.val));
     const long slice = row >> 6;
@@ -358,9 +347,15 @@ __device__ __forceinline__ void row_product_direction(const SolveDesc& d, long r
         for (int u = 0; u < U; ++u) direction<VR>(in, c[u], pc[u]);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            ax = fma(a[u], MR(pc[u][0]), ax);
-            ay = fma(a[u], MR(pc[u][1]), ay);
-            az = fma(a[u], MR(pc[u][2]), az);
+            if constexpr (kDiffForm<MR>) {
+                ax = fma(a[u], MR(pc[u][0]) - MR(pi[0]), ax);
+                ay = fma(a[u], MR(pc[u][1]) - MR(pi[1]), ay);
+                az = fma(a[u], MR(pc[u][2]) - MR(pi[2]), az);
+            } else {
+                ax = fma(a[u], MR(pc[u][0]), ax);
+                ay = fma(a[u], MR(pc[u][1]), ay);
+                az = fma(a[u], MR(pc[u][2]), az);
+            }
         }
     }
 }
@@ -382,7 +377,7 @@ __device__ __forceinline__ void product_direct(const SolveDesc& d, const WorkIte
     VR pi[3];
     direction<VR>(in, i, pi);
     MR ax, ay, az;
-    row_product_direction<MR, VR>(d, i, in, ax, ay, az);
+    row_product_direction<MR, VR>(d, i, in, pi, ax, ay, az);
     VR qv[3] = {0, 0, 0};
     if (!pin) {
         const MR dt2 = MR(d.dt2);
@@ -454,6 +449,9 @@ __device__ __forceinline__ void product_staged(const SolveDesc& d, const WorkIte
     }
     __syncthreads();
     if (!wave_live) return;
+    // the row's own direction (the same bits as its staged copy)
+    VR pi[3] = {0, 0, 0};
+    if (own) own_op.finish(in.beta, pi);
     MR ax = 0, ay = 0, az = 0;
     for (int kk = 0; kk < row.w; kk += U) {
         int cn[U];
@@ -464,9 +462,15 @@ __device__ __forceinline__ void product_staged(const SolveDesc& d, const WorkIte
         for (int u = 0; u < U; ++u) {
             const VR* pc = ps + 3 * c[u];
             const MR au = kk + u < row.w ? a[u] : MR(0);
-            ax = fma(au, MR(pc[0]), ax);
-            ay = fma(au, MR(pc[1]), ay);
-            az = fma(au, MR(pc[2]), az);
+            if constexpr (kDiffForm<MR>) {
+                ax = fma(au, MR(pc[0]) - MR(pi[0]), ax);
+                ay = fma(au, MR(pc[1]) - MR(pi[1]), ay);
+                az = fma(au, MR(pc[2]) - MR(pi[2]), az);
+            } else {
+                ax = fma(au, MR(pc[0]), ax);
+                ay = fma(au, MR(pc[1]), ay);
+                az = fma(au, MR(pc[2]), az);
+            }
         }
         if (more)
 #pragma unroll
@@ -476,8 +480,6 @@ __device__ __forceinline__ void product_staged(const SolveDesc& d, const WorkIte
             }
     }
     if (!own) return;
-    VR pi[3];
-    own_op.finish(in.beta, pi);
     VR qv[3] = {0, 0, 0};
     if (!pin) {
         const MR dt2 = MR(d.dt2);
@@ -518,11 +520,11 @@ __device__ __forceinline__ bool item_stride(long nitems, int per, long& first, l
     return first < last;
 }
 
-// Sums a work-group's per-thread partials and adds them into the bins of one mesh
+// Sums a work-group's per-thread partials and stores them in its slot of one mesh's partials
 template <int NQ>
-__device__ __forceinline__ void flush_partials(double* set, int unit, double (&acc)[NQ], double* sh) {
+__device__ __forceinline__ void flush_partials(double* set, double (&acc)[NQ], double* sh) {
     block_sum<NQ>(acc, sh);
-    if (threadIdx.x == 0) bin_add<NQ>(set, unit, acc);
+    if (threadIdx.x == 0) bin_store<NQ>(set, int(xcd_logical(blockIdx.x, gridDim.x)), acc);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
 }
@@ -541,7 +543,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
     VR* ps = reinterpret_cast<VR*>(smem_raw);
     __shared__ double sh[3 * (kBlk / 64)];
     double acc[3] = {0, 0, 0};
-    int cur = -1, cur_unit = 0;
+    int cur = -1;
     ProductState S{};
     DirIn<VR> in{};
     gbl<VR>* pnew = nullptr;
@@ -549,9 +551,8 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
         const WorkItem wi = items[it];
         const SolveDesc& d = descs[wi.mesh];
         if (wi.mesh != cur) {
-            if (cur >= 0 && !S.done) flush_partials<3>(bin_set(descs[cur], t, kSetPq), cur_unit, acc, sh);
+            if (cur >= 0 && !S.done) flush_partials<3>(bin_set(descs[cur], t, kSetPq), acc, sh);
             cur = wi.mesh;
-            cur_unit = wi.unit;
             S = product_state(d, wi, t);
             const bool odd = t & 1;
             in.r = G(static_cast<const double*>(d.r));
@@ -567,7 +568,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
         else
             product_direct<VR, MR>(d, wi, in, pnew, acc);
     }
-    if (cur >= 0 && !S.done) flush_partials<3>(bin_set(descs[cur], t, kSetPq), cur_unit, acc, sh);
+    if (cur >= 0 && !S.done) flush_partials<3>(bin_set(descs[cur], t, kSetPq), acc, sh);
 }
 
 // PCG iteration t, second kernel.  Each work-group takes `per` consecutive row groups; per mesh it meets
@@ -579,7 +580,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
 // which corrects its rounding at the next iteration; r stays float64.
 template <typename VR>
 __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem& wi, long t, const double (&al)[3],
-                                             double (&acc)[6]) {
+                                             int fold, double (&acc)[6]) {
     const long i = long(wi.unit) * kBlk + threadIdx.x;
     if (i >= d.nv) return;
     const gbl<const VR>* p = G(static_cast<const VR*>((t & 1) ? d.p1 : d.p0));
@@ -607,6 +608,12 @@ __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem&
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+        if constexpr (sizeof(VR) == 4) {
+            if (fold & (1 << c)) {  // wave-uniform: the same for every row of the mesh
+                G(d.y64)[3 * i + c] += yv[c];
+                yv[c] = 0.0;
+            }
+        }
         y[3 * i + c] = VR(yv[c]);
         r[3 * i + c] = rv[c];
         if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zv[c];
@@ -621,39 +628,70 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(const SolveDesc* __restrict
     if (!item_range(nitems, per, first, last)) return;
     __shared__ double sh[6 * (kBlk / 64)];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    int cur = -1, cur_unit = 0, done = 1;
+    int cur = -1, done = 1, fold = 0;
     double al[3] = {0, 0, 0};
     for (long it = first; it < last; ++it) {
         const WorkItem wi = items[it];
         const SolveDesc& d = descs[wi.mesh];
         if (wi.mesh != cur) {
-            if (cur >= 0 && !done) flush_partials<6>(bin_set(descs[cur], t, kSetRz), cur_unit, acc, sh);
+            if (cur >= 0 && !done) flush_partials<6>(bin_set(descs[cur], t, kSetRz), acc, sh);
             cur = wi.mesh;
-            cur_unit = wi.unit;
             const PcgState* st = d.st + ((t + 1) & 1);
             double pq[3];
-            bin_totals<3>(bin_set(d, t, kSetPq), pq);
+            bin_totals<3>(bin_set(d, t, kSetPq), d.pq_lo, d.pq_hi, pq);
             done = st->done;
-            for (int c = 0; c < 3; ++c) al[c] = (st->active[c] && pq[c] != 0.0) ? st->rz[c] / pq[c] : 0.0;
-            if (!done && wi.unit == 0) bin_clear(bin_set(d, t + 1, kSetPq));
+            fold = 0;
+            for (int c = 0; c < 3; ++c) {
+                al[c] = (st->active[c] && pq[c] != 0.0) ? st->rz[c] / pq[c] : 0.0;
+                if (st->active[c] && st->iters[c] % kFoldIters == kFoldIters - 1) fold |= 1 << c;
+            }
         }
         if (done) continue;
-        update_group<VR>(d, wi, t, al, acc);
+        update_group<VR>(d, wi, t, al, fold, acc);
     }
-    if (cur >= 0 && !done) flush_partials<6>(bin_set(descs[cur], t, kSetRz), cur_unit, acc, sh);
+    if (cur >= 0 && !done) flush_partials<6>(bin_set(descs[cur], t, kSetRz), acc, sh);
 }
 
-// u = x - X, padded to four doubles per vertex (mixed precision: the force kernels' input, gathered with
-// two aligned 16-byte loads per vertex)
-__global__ __launch_bounds__(kBlk) void k_displacements(const SolveDesc* __restrict__ descs,
-                                                        const WorkItem* __restrict__ items, long nitems) {
-    WorkItem wi;
-    if (!work_item(items, nitems, wi)) return;
-    const SolveDesc& d = descs[wi.mesh];
-    long i = long(wi.unit) * kBlk + threadIdx.x;
-    if (i >= d.nv) return;
-    for (int c = 0; c < 3; ++c) d.u4[4 * i + c] = d.x[3 * i + c] - d.X[3 * i + c];
-    d.u4[4 * i + 3] = 0.0;
+// r = -g, y = 0; r.z (z = D^-1 r) and r.r into the partials read by the first product (parity 1).  The
+// first product forms p = z itself.  Launched with the update kernel's grid and walk, so that its
+// partials sit in the slots the update's would.
+template <typename VR>
+__global__ __launch_bounds__(kBlk) void k_pcg_init(const SolveDesc* __restrict__ descs,
+                                                   const WorkItem* __restrict__ items, long nitems, int per) {
+    long first, last;
+    if (!item_range(nitems, per, first, last)) return;
+    __shared__ double sh[6 * (kBlk / 64)];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    int cur = -1;
+    for (long it = first; it < last; ++it) {
+        const WorkItem wi = items[it];
+        const SolveDesc& d = descs[wi.mesh];
+        if (wi.mesh != cur) {
+            if (cur >= 0) flush_partials<6>(bin_set(descs[cur], 1, kSetRz), acc, sh);
+            cur = wi.mesh;
+        }
+        const long i = long(wi.unit) * kBlk + threadIdx.x;
+        if (i >= d.nv) continue;
+        const VR di = G(static_cast<const VR*>(d.dinv))[i];
+        const gbl<const double>* g = G(static_cast<const double*>(d.g));
+        double gi[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gi[c] = g[3 * i + c];
+        gbl<double>* r = G(d.r);
+        gbl<VR>* y = G(static_cast<VR*>(d.y));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double ri = -gi[c];
+            const VR zi = di * VR(ri);
+            r[3 * i + c] = ri;
+            y[3 * i + c] = VR(0);
+            if constexpr (kStoredZ<VR>) G(d.y64)[3 * i + c] = 0.0;
+            if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zi;
+            acc[c] += ri * double(zi);
+            acc[3 + c] += ri * ri;
+        }
+    }
+    if (cur >= 0) flush_partials<6>(bin_set(descs[cur], 1, kSetRz), acc, sh);
 }
 
 // x += s y (Newton update); s = 1 unless a quasi-static increment limit set it
@@ -667,7 +705,11 @@ __global__ __launch_bounds__(kBlk) void k_newton_update(const SolveDesc* __restr
     if (i >= d.nv) return;
     const VR* y = static_cast<const VR*>(d.y);
     const double sc = d.ustep ? *d.ustep : 1.0;
-    for (int c = 0; c < 3; ++c) d.x[3 * i + c] += sc * double(y[3 * i + c]);
+    for (int c = 0; c < 3; ++c) {
+        double yi = double(y[3 * i + c]);
+        if constexpr (sizeof(VR) == 4) yi += d.y64[3 * i + c];
+        d.x[3 * i + c] += sc * yi;
+    }
 }
 
 // largest |y| entry of each row group, into the partials
@@ -681,7 +723,11 @@ __global__ __launch_bounds__(kBlk) void k_absmax(const SolveDesc* __restrict__ d
     double m = 0.0;
     if (i < d.nv) {
         const VR* y = static_cast<const VR*>(d.y);
-        for (int c = 0; c < 3; ++c) m = fmax(m, fabs(double(y[3 * i + c])));
+        for (int c = 0; c < 3; ++c) {
+            double yi = double(y[3 * i + c]);
+            if constexpr (sizeof(VR) == 4) yi += d.y64[3 * i + c];
+            m = fmax(m, fabs(yi));
+        }
     }
     __shared__ double sh[kBlk];
     sh[threadIdx.x] = m;
@@ -718,23 +764,21 @@ __global__ __launch_bounds__(kBlk) void k_velocity(const SolveDesc* __restrict__
     for (int c = 0; c < 3; ++c) d.v[3 * i + c] = (d.x[3 * i + c] - d.xt[3 * i + c]) / d.dt;
 }
 
-// lumped mass rho h sum(A_T)/3 from the rest triangles
-__global__ void k_mass(const double* __restrict__ X, const int32_t* __restrict__ tris, long nt, double rho_h,
-                       double* __restrict__ mass) {
-    long t = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (t >= nt) return;
-    int a = tris[3 * t], b = tris[3 * t + 1], c = tris[3 * t + 2];
-    V3<double> xa = load3(X, a);
-    double third = rho_h * 0.5 * norm(cross(load3(X, b) - xa, load3(X, c) - xa)) / 3.0;
-    atomicAdd(mass + a, third);
-    atomicAdd(mass + b, third);
-    atomicAdd(mass + c, third);
+// lumped mass rho h sum(A_T)/3 from the rest triangles around each vertex, in ascending triangle order
+__global__ void k_mass_rows(const double* __restrict__ X, const int32_t* __restrict__ tris,
+                            const int64_t* __restrict__ vt_ptr, const int64_t* __restrict__ vt, long nv,
+                            double rho_h, double* __restrict__ mass) {
+    const long v = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (v >= nv) return;
+    double m = 0.0;
+    for (int64_t e = vt_ptr[v]; e < vt_ptr[v + 1]; ++e) {
+        const long t = long(vt[e] >> 3);
+        const V3<double> xa = load3(X, tris[3 * t]);
+        m += rho_h * 0.5 * norm(cross(load3(X, tris[3 * t + 1]) - xa, load3(X, tris[3 * t + 2]) - xa)) / 3.0;
+    }
+    mass[v] = m;
 }
 
-__global__ void k_zero(double* __restrict__ p, long n) {
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i < n) p[i] = 0.0;
-}
 
 }  // namespace
 

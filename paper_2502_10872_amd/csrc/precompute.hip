@@ -16,8 +16,8 @@
 // kappa0 = B N0^T X (eqs 43, 51).  Scaled by sqrt(A).
 //
 // Plate stencils with a clamped edge measure their curvature vectors from the rest shape, the clamped
-// fold not annihilating the flat rest coordinates: the mixed record stores C0 = 0 for them, and FP64
-// adds the constant force F0 = -f(X) of those stencils (clamp_bias).
+// fold not annihilating the flat rest coordinates: the mixed record marks them (the kernel then forms
+// C = B (x - X)), and FP64 adds the constant force F0 = -f(X) of those stencils (clamp_bias).
 #include "devmath.hpp"
 #include "internal.hpp"
 
@@ -234,41 +234,75 @@ __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_
     const long s = src[e];  // -1: alignment padding, filled with vertex 0 and zeros (never read)
     const long blk = e / kStreamBlock, lane = e % kStreamBlock;
     if (trec32) {
-        // mixed: ids, operator, rest curvatures, the rest curvature vectors C0_i = sum_j B_ij (X_j - X_1)
-        // (float64 sums; the rows of B sum to zero) and (shells) rest differences in one 32-bit record
+        // mixed: ids, the operator's entries other than the origin column, rounded to float32, and (shells)
+        // the rest curvatures of the rounded operator, kappa0_i = sum_j B~_ij (X_j - X_o) . n0 with the
+        // rest normal n0 of the force kernel's construction (float64 sums, stored as float64)
         const int nf = rec32_fields(k, r, shell), nch = stream_chunks(nf, 4);
         float* base = trec32 + (blk * nch * kStreamBlock + lane) * 4;
         auto put = [&](int f, float v) { base[(f / 4) * kStreamBlock * 4 + f % 4] = v; };
-        for (int j = 0; j < k; ++j) put(j, __int_as_float(s < 0 ? 0 : idx[j * ns + s]));
-        for (int q = 0; q < r * k; ++q) put(k + q, s < 0 ? 0.0f : float(B[q * ns + s]));
-        for (int q = 0; q < r; ++q) put(k + r * k + q, s < 0 ? 0.0f : float(k0[q * ns + s]));
-        // a clamped plate stencil keeps C0 = 0: its curvature is measured from the rest shape
-        const bool rest_relative = s >= 0 && !shell && (bc[s] & kBcClampedAny) != 0;
-        for (int i = 0; i < r; ++i) {
-            double c[3] = {0.0, 0.0, 0.0};
-            if (s >= 0 && !rest_relative) {
-                const long o = idx[s];
-                for (int j = 1; j < k; ++j) {
-                    const long v = idx[j * ns + s];
-                    const double b = B[(i * k + j) * ns + s];
-                    for (int a = 0; a < 3; ++a) c[a] += b * (X[3 * v + a] - X[3 * o + a]);
-                }
-            }
-            for (int a = 0; a < 3; ++a) put(k + r * k + r + 3 * i + a, float(c[a]));
+        const int o = k == 4 ? 1 : 0;  // origin: the hinge's first end (edge) or the central vertex 0
+        const bool clamped_plate = s >= 0 && !shell && (bc[s] & kBcClampedAny) != 0;
+        for (int j = 0; j < k; ++j) {
+            uint32_t id = s < 0 ? 0u : uint32_t(idx[j * ns + s]);
+            if (j == 0 && clamped_plate) id |= kRecClampBit;
+            put(j, __uint_as_float(id));
         }
+        int f = k;
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j < k; ++j)
+                if (j != o) put(f++, s < 0 ? 0.0f : float(B[(i * k + j) * ns + s]));
         if (shell) {
-            // edge: X0 - X1, X2 - X1, X3 - X1; triangle: X1 - X0, X2 - X0 (the differences the normal uses)
-            const int f0 = k + r * k + r + 3 * r;
-            const int o = k == 4 ? 1 : 0;
-            const int js[3] = {k == 4 ? 0 : 1, 2, 3};
-            const int nd = k == 4 ? 3 : 2;
-            for (int q = 0; q < nd; ++q)
-                for (int a = 0; a < 3; ++a) {
-                    const double v = s < 0 ? 0.0 : X[3L * idx[js[q] * ns + s] + a] - X[3L * idx[o * ns + s] + a];
-                    put(f0 + 3 * q + a, float(v));
+            double h0[6] = {0, 0, 0, 0, 0, 0};
+            if (s >= 0) {
+                V3<double> P[6];
+                for (int j = 0; j < k; ++j) P[j] = load3(X, idx[j * ns + s]) - load3(X, idx[o * ns + s]);
+                V3<double> n0;
+                if (k == 4) {
+                    // bisector of the two hinge triangles' unit normals (hinge 1 -> 2, tips 0 and 3)
+                    const V3<double> ua = cross(P[2], P[0]), ub = cross(P[3], P[2]);
+                    const V3<double> m = (1.0 / norm(ua)) * ua + (1.0 / norm(ub)) * ub;
+                    n0 = (1.0 / norm(m)) * m;
+                } else {
+                    const V3<double> u = cross(P[1], P[2]);
+                    n0 = (1.0 / norm(u)) * u;
                 }
+                for (int j = 0; j < k; ++j) h0[j] = dot(P[j], n0);
+            }
+            for (int i = 0; i < r; ++i) {
+                double kr = 0.0;
+                for (int j = 0; j < k; ++j)
+                    if (j != o && s >= 0) kr += double(float(B[(i * k + j) * ns + s])) * h0[j];
+                const unsigned long long bits = __double_as_longlong(kr);
+                put(f++, __uint_as_float(uint32_t(bits & 0xffffffffull)));
+                put(f++, __uint_as_float(uint32_t(bits >> 32)));
+            }
         }
-        for (int f = nf; f < 4 * nch; ++f) put(f, 0.0f);
+        if (k == 4 && !shell) {
+            // edge plate: the tip's coordinates in the rest tangent plane (the plane of the bisector
+            // normal, in which the operator annihilates affine fields), x3 - x1 ~ alpha (x0 - x1) +
+            // beta (x2 - x1) for every affine motion of the rest stencil
+            double ab[2] = {0.0, 0.0};
+            if (s >= 0) {
+                const V3<double> x1 = load3(X, idx[ns + s]);
+                const V3<double> A = load3(X, idx[s]) - x1, Cc = load3(X, idx[2 * ns + s]) - x1;
+                const V3<double> Bb = load3(X, idx[3 * ns + s]) - x1;
+                const V3<double> ua = cross(Cc, A), ub = cross(Bb, Cc);
+                V3<double> n0 = (1.0 / norm(ua)) * ua + (1.0 / norm(ub)) * ub;
+                n0 = (1.0 / norm(n0)) * n0;
+                const V3<double> Ap = A - dot(A, n0) * n0, Cp = Cc - dot(Cc, n0) * n0, Bp = Bb - dot(Bb, n0) * n0;
+                const double g11 = dot(Ap, Ap), g12 = dot(Ap, Cp), g22 = dot(Cp, Cp);
+                const double r1 = dot(Ap, Bp), r2 = dot(Cp, Bp), idet = 1.0 / (g11 * g22 - g12 * g12);
+                ab[0] = (g22 * r1 - g12 * r2) * idet;
+                ab[1] = (g11 * r2 - g12 * r1) * idet;
+            }
+            for (; f < kRecEdgeAffine; ++f) put(f, 0.0f);
+            for (int q = 0; q < 2; ++q) {
+                const unsigned long long bits = __double_as_longlong(ab[q]);
+                put(f++, __uint_as_float(uint32_t(bits & 0xffffffffull)));
+                put(f++, __uint_as_float(uint32_t(bits >> 32)));
+            }
+        }
+        for (; f < 4 * nch; ++f) put(f, 0.0f);
     } else {
         const int nchi = stream_chunks(k, 4), nchv = stream_chunks(rec64_fields(k, r), 2);
         int32_t* bi = tidx + (blk * nchi * kStreamBlock + lane) * 4;
@@ -282,20 +316,16 @@ __global__ void tile_copy(const int32_t* __restrict__ src, long nt, const int32_
     }
 }
 
-__global__ void fill_zero(double* __restrict__ p, long n) {
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (i < n) p[i] = 0.0;
-}
 
 // FP64 plates: the clamped stencils' rest curvature vectors C0_i = sum_j B_ij X_j (on differences from
 // vertex 1; B's rows sum to zero), their force at the rest shape, f_j = -sum_i B_ij (D C0)_i, and energy
-// 1/2 C0 . D C0.  bias accumulates -f (so that f(x) + bias is the force of C = B (x - X)), e0 the energy.
-// D is 1 for the edge operator (k_b A_E is folded into B) and D_b for triangles (A is folded into B).
-__global__ void clamp_bias(const double* __restrict__ X, const int32_t* __restrict__ idx,
-                           const double* __restrict__ B, const int32_t* __restrict__ bc, long ns, int k, int r,
-                           double kb, double nu, double* __restrict__ bias, double* __restrict__ e0) {
-    long s = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (s >= ns || !(bc[s] & kBcClampedAny)) return;
+// 1/2 C0 . D C0.  bias = -f summed per vertex (so that f(x) + bias is the force of C = B (x - X)), e0 the
+// energy.  D is 1 for the edge operator (k_b A_E is folded into B) and D_b for triangles (A is folded into
+// B).  One thread per vertex walks its stencils in ascending order (and per-stencil energies are summed
+// in a fixed order), so the result is the same in every run.
+__device__ void clamp_stencil(const double* __restrict__ X, const int32_t* __restrict__ idx,
+                              const double* __restrict__ B, long ns, long s, int k, int r, double kb, double nu,
+                              double (&g)[3][3], double& en) {
     const long o = idx[s];
     double C[3][3];
     for (int i = 0; i < r; ++i) {
@@ -306,7 +336,6 @@ __global__ void clamp_bias(const double* __restrict__ X, const int32_t* __restri
             for (int a = 0; a < 3; ++a) C[i][a] += b * (X[3 * v + a] - X[3 * o + a]);
         }
     }
-    double g[3][3];
     if (r == 1) {
         for (int a = 0; a < 3; ++a) g[0][a] = C[0][a];
     } else {
@@ -316,18 +345,48 @@ __global__ void clamp_bias(const double* __restrict__ X, const int32_t* __restri
             g[2][a] = kb * 0.5 * (1.0 - nu) * C[2][a];
         }
     }
-    double en = 0.0;
+    en = 0.0;
     for (int i = 0; i < r; ++i)
         for (int a = 0; a < 3; ++a) en += 0.5 * C[i][a] * g[i][a];
-    atomicAdd(e0, en);
-    for (int j = 0; j < k; ++j) {
-        const long v = idx[j * ns + s];
+}
+
+__global__ void clamp_bias_rows(const double* __restrict__ X, const int32_t* __restrict__ idx,
+                                const double* __restrict__ B, const int32_t* __restrict__ bc,
+                                const int64_t* __restrict__ inc_ptr, const int64_t* __restrict__ inc, long ns,
+                                long nv, int k, int r, double kb, double nu, double* __restrict__ bias) {
+    const long v = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (v >= nv) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t e = inc_ptr[v]; e < inc_ptr[v + 1]; ++e) {
+        const long s = long(inc[e] >> 3);
+        const int j = int(inc[e] & 7);
+        if (!(bc[s] & kBcClampedAny)) continue;
+        double g[3][3], en;
+        clamp_stencil(X, idx, B, ns, s, k, r, kb, nu, g, en);
         for (int a = 0; a < 3; ++a) {
             double fb = 0.0;
             for (int i = 0; i < r; ++i) fb += B[(i * k + j) * ns + s] * g[i][a];
-            if (fb != 0.0) atomicAdd(bias + 3 * v + a, fb);
+            acc[a] += fb;
         }
     }
+    for (int a = 0; a < 3; ++a) bias[3 * v + a] = acc[a];
+}
+
+// e0 = the clamped stencils' rest energy, one work-group, each thread a fixed strided subset, then a
+// fixed tree
+__global__ void clamp_energy(const double* __restrict__ X, const int32_t* __restrict__ idx,
+                             const double* __restrict__ B, const int32_t* __restrict__ bc, long ns, int k, int r,
+                             double kb, double nu, double* __restrict__ e0) {
+    double acc[1] = {0.0};
+    for (long s = threadIdx.x; s < ns; s += blockDim.x) {
+        if (!(bc[s] & kBcClampedAny)) continue;
+        double g[3][3], en;
+        clamp_stencil(X, idx, B, ns, s, k, r, kb, nu, g, en);
+        acc[0] += en;
+    }
+    __shared__ double sh[16];
+    block_sum<1>(acc, sh);
+    if (threadIdx.x == 0) *e0 = acc[0];
 }
 
 }  // namespace
@@ -362,11 +421,14 @@ void launch_clamp_bias(shell_stencils_s& st, const int32_t* bc, hipStream_t s) {
     const long ns = st.ns;
     st.bias.alloc(size_t(3 * st.nv));
     DevArray<double> e0(1);
-    fill_zero<<<int((3 * st.nv + 255) / 256), 256, 0, s>>>(st.bias.p, 3 * st.nv);
-    fill_zero<<<1, 64, 0, s>>>(e0.p, 1);
-    if (ns > 0)
-        clamp_bias<<<int((ns + 255) / 256), 256, 0, s>>>(st.X.p, st.idx.p, st.B.p, bc, ns, st.k, st.r, st.kb,
-                                                         st.poisson, st.bias.p, e0.p);
+    const Incidence inc = build_incidence(st.h_idx, st.k, ns, st.nv);
+    DevArray<int64_t> iptr(inc.ptr.size()), icode(std::max<size_t>(inc.code.size(), 1));
+    iptr.upload(inc.ptr.data(), inc.ptr.size(), s);
+    icode.upload(inc.code.data(), inc.code.size(), s);
+    if (st.nv > 0)
+        clamp_bias_rows<<<int((st.nv + 255) / 256), 256, 0, s>>>(st.X.p, st.idx.p, st.B.p, bc, iptr.p, icode.p, ns,
+                                                                 st.nv, st.k, st.r, st.kb, st.poisson, st.bias.p);
+    clamp_energy<<<1, 1024, 0, s>>>(st.X.p, st.idx.p, st.B.p, bc, ns, st.k, st.r, st.kb, st.poisson, e0.p);
     SHELL_HIP(hipGetLastError());
     e0.download(&st.bias_e0, 1, s);
     SHELL_HIP(hipStreamSynchronize(s));

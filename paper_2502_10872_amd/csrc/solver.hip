@@ -8,16 +8,18 @@
 //
 // Every scalar of the recurrences lives on the device.  A PCG iteration is two streaming kernels: the
 // product kernel advances the recurrence state by the previous update (beta, activity flags, counts),
-// forms the new search direction p = z + beta p_old (z = D^-1 r recomputed, never stored) for its row
-// group's distinct columns while staging them in LDS, writes p for its own rows and q = A p; the update
-// kernel computes alpha and advances y and r.  The dot products reach the next kernel through binned
-// device-scope atomics (see the bins below), so no reduction kernel sits between them.  p alternates
+// forms the new search direction p = z + beta p_old for its row group's distinct columns while staging
+// them in LDS, writes p for its own rows and q = A p; the update kernel computes alpha and advances y
+// and r.  The dot products reach the next kernel as per-work-group partials in fixed slots, summed in
+// a fixed order by every work-group that needs them (see the partials in pcg_kernels.hpp), so no
+// reduction kernel sits between them and the result does not depend on scheduling.  p alternates
 // between two buffers because other row groups still read the previous direction while it is
 // rewritten.  Kernels of converged meshes return at once, so the host launches iterations in chunks and
 // reads the flags once per chunk.
 //
-// Precision: FP64 throughout, or mixed: float32 matrix values, Jacobi diagonal and the vectors p, q and
-// f; float64 solution y, residual r, all dot products and the Newton residual.
+// Precision: FP64 throughout, or mixed: float32 matrix values (applied in difference form), Jacobi
+// diagonal and the vectors p, q, z and f; the increment y in float32 folded into float64 every 16
+// iterations; float64 residual r, all dot products and the Newton residual.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -199,12 +201,7 @@ long pcg_iterations(shell_batch_s& b, const Launch& L, long t, int count, hipStr
     return t;
 }
 
-void forces(const Launch& L, hipStream_t s, StepProfiler* prof = nullptr, bool displacements = true) {
-    // mixed precision: the force kernels read the displacements from the rest shape
-    if (displacements && L.precision == SHELL_PREC_MIXED && L.nrows) {
-        k_displacements<<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
-        SHELL_HIP(hipGetLastError());
-    }
+void forces(const Launch& L, hipStream_t s, StepProfiler* prof = nullptr) {
     timed_launch(prof, prof && prof->every > 0, SHELL_PHASE_FORCES, s, [&](hipEvent_t e0, hipEvent_t e1) {
         // the first model's kernel starts the interval, the last one's ends it
         int first = -1, last = -1;
@@ -284,6 +281,27 @@ Launch upload(shell_batch_s& b, const ItemBuilder& ib, hipStream_t s, int pcg_wo
     return L;
 }
 
+// The logical work-groups of L's PCG launches that can touch each mesh of the item list (the slots its
+// dot-product partials are summed over), into the staged descriptors.  The product kernel's XCD x takes
+// the run of items [x run, (x + 1) run), run = per W with W work-groups per XCD, so a mesh's items meet
+// at most the work-groups of the XCDs whose runs overlap them; the update kernel's work-group takes
+// per_u consecutive items.
+void set_slot_ranges(shell_batch_s& b, const Launch& L, const ItemBuilder& ib) {
+    const long W = L.pcg_grid / kXcds, run = long(L.per) * W;
+    size_t a = 0;
+    while (a < ib.rows.size()) {
+        const int m = ib.rows[a].mesh;
+        size_t e = a;
+        while (e < ib.rows.size() && ib.rows[e].mesh == m) ++e;
+        SolveDesc& d = b.sdesc_host[m];
+        d.pq_lo = int32_t((long(a) / run) * W);
+        d.pq_hi = int32_t(std::min(L.pcg_grid, ((long(e) - 1) / run + 1) * W));
+        d.rz_lo = int32_t(long(a) / L.per_u);
+        d.rz_hi = int32_t((long(e) - 1) / L.per_u + 1);
+        a = e;
+    }
+}
+
 void upload_descs(shell_batch_s& b, hipStream_t s) {
     SHELL_HIP(hipMemcpyAsync(b.sdesc.p, b.sdesc_host, b.sims.size() * sizeof(SolveDesc), hipMemcpyHostToDevice, s));
 }
@@ -298,13 +316,13 @@ void read_states(shell_batch_s& b, hipStream_t s) {
 SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
     SolveDesc d{};
     d.x = sim.x.p;
-    d.u4 = sim.u4.p;  // null in FP64
     d.X = sim.st->X.p;
     d.xhat = sim.xhat.p;
     d.xt = sim.xt.p;
     d.v = sim.v.p;
     d.g = sim.g.p;
     d.y = sim.y.p;
+    d.y64 = sim.y64.p;  // null in FP64
     d.r = sim.r.p;
     d.f = sim.f.p;
     d.p0 = sim.p.p;
@@ -336,7 +354,8 @@ ForceDesc force_desc(shell_sim_s& sim) {
     const shell_stencils_s& st = *sim.st;
     const bool f32 = st.precision == SHELL_PREC_MIXED;
     ForceDesc d{};
-    d.x = f32 ? sim.u4.p : sim.x.p;
+    d.x = sim.x.p;
+    d.X = st.X.p;
     d.f = sim.f.p;
     d.epart = nullptr;
     d.bias = st.bias.p;
@@ -348,6 +367,7 @@ ForceDesc force_desc(shell_sim_s& sim) {
     d.T = st.T;
     d.model = st.model;
     d.kb = st.kb;
+    d.fscale = st.fscale;
     d.nu = st.poisson;
     return d;
 }
@@ -439,25 +459,28 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
             st.gn = std::sqrt(ps.gsq);
             if (k == 0) st.gn0 = st.gn;
             const shell_step_params_t& p = *st.prm;
-            if (qs) {
-                if (st.gn0 == 0.0 || st.gn < qs->eps_f || k == p.max_newton) continue;
-            } else if (st.gn0 == 0.0 || (k > 0 && st.gn <= p.newton_rtol * st.gn0) || k == p.max_newton) {
+            const bool met = st.gn0 == 0.0 || (qs ? st.gn < qs->eps_f : (k > 0 && st.gn <= p.newton_rtol * st.gn0));
+            if (met) continue;
+            if (k == p.max_newton) {
+                st.stats.newton_capped = 1;
                 continue;
             }
             solve.push_back(m);
         }
         if (solve.empty()) break;
-        // per-mesh PCG targets of this Newton iteration (the staging is idle: read_states drained)
+        // per-mesh PCG targets of this Newton iteration and the slot ranges of its launch shape (upload()
+        // drains the stream first, so the staging is idle)
+        ib.build(b.sims, solve);
+        L = upload(b, ib, s, wg);
         for (int m : solve) {
             const shell_step_params_t& p = *ms[size_t(m)].prm;
             SolveDesc& d = b.sdesc_host[m];
             d.replay = p.mode == SHELL_PCG_REPLAY;
             for (int c = 0; c < 3; ++c) d.target[c] = d.replay ? p.replay_counts[3 * k + c] : p.max_pcg;
         }
+        set_slot_ranges(b, L, ib);
         upload_descs(b, s);
-        ib.build(b.sims, solve);
-        L = upload(b, ib, s, wg);
-        k_pcg_init<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_pcg_init<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, L.per_u);
         timed_launch(b.prof.get(), b.prof && b.prof->every > 0, SHELL_PHASE_PRODUCT, s,
                      [&](hipEvent_t e0, hipEvent_t e1) {
                          hipExtLaunchKernelGGL(k_pcg_spmv<VR, MR>, dim3(unsigned(L.pcg_grid)), dim3(kBlk),
@@ -556,6 +579,8 @@ void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out,
     ItemBuilder ib;
     ib.build(b.sims, std::vector<int>{0});
     Launch L = upload(b, ib, s);
+    set_slot_ranges(b, L, ib);
+    upload_descs(b, s);
     const long grid = xcd_grid(L.nrows);
     k_dinv<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
     sim.dinv_dt = dt;
@@ -567,7 +592,7 @@ void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out,
         forces(L, s);
         k_residual<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 0);
         k_fin_residual<<<1, kRedBlk, 0, s>>>(L.sdesc, L.meshes);
-        k_pcg_init<VR><<<grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+        k_pcg_init<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, L.per_u);
         k_pcg_spmv<VR, MR><<<L.pcg_grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows, 0, L.per);
         k_pcg_update<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, 0, L.per_u);
         SHELL_HIP(hipGetLastError());
@@ -583,11 +608,9 @@ void time_impl(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out,
         return double(ms) / reps;
     };
     out.reps = reps;
-    // the force kernels alone (mixed precision: the displacements are written once before)
-    forces(L, s);
-    out.force_ms = timed([&] { forces(L, s, nullptr, false); });
-    // repeated launches of one iteration's kernel: each re-reads the same state and bins (the bins it
-    // adds into only grow, which changes no control flow of an always-active replay)
+    // the force kernels alone
+    out.force_ms = timed([&] { forces(L, s); });
+    // repeated launches of one iteration's kernel: each re-reads the same state and partials
     init();
     out.spmv_ms = timed([&] {
         k_pcg_spmv<VR, MR><<<L.pcg_grid, kBlk, L.lds_spmv, s>>>(L.sdesc, L.rows, L.nrows, 1, L.per);
@@ -608,10 +631,10 @@ void sim_alloc(shell_sim_s& sim) {
     const long nv = sim.nv, n3 = 3 * nv;
     for (auto* a : {&sim.x, &sim.v, &sim.xt, &sim.xhat, &sim.g, &sim.y, &sim.r, &sim.f, &sim.p, &sim.p2, &sim.q})
         a->alloc(size_t(std::max(n3, 1L)));
-    sim.bins.alloc(size_t(2 * 2 * kBinQ * kBins));
+    sim.bins.alloc(size_t(2 * 2 * kBinQ * kSlots));
     if (sim.st->precision == SHELL_PREC_MIXED) {
         sim.z.alloc(size_t(std::max(n3, 1L)));
-        sim.u4.alloc(size_t(std::max(4 * nv, 1L)));
+        sim.y64.alloc(size_t(std::max(n3, 1L)));
     }
     sim.mass.alloc(size_t(std::max(nv, 1L)));
     sim.dinv.alloc(size_t(std::max(nv, 1L)));
@@ -623,9 +646,14 @@ void sim_alloc(shell_sim_s& sim) {
 void sim_mass(shell_sim_s& sim, hipStream_t s) {
     shell_stencils_s& st = *sim.st;
     if (!sim.nv) return;
-    k_zero<<<blocks(sim.nv), kBlk, 0, s>>>(sim.mass.p, sim.nv);
-    if (st.nt) k_mass<<<blocks(st.nt), kBlk, 0, s>>>(st.X.p, st.tris.p, st.nt, st.density * st.thickness, sim.mass.p);
+    const Incidence vt = build_incidence(st.h_tris, 3, st.nt, st.nv);
+    DevArray<int64_t> ptr(vt.ptr.size()), code(std::max<size_t>(vt.code.size(), 1));
+    ptr.upload(vt.ptr.data(), vt.ptr.size(), s);
+    code.upload(vt.code.data(), vt.code.size(), s);
+    k_mass_rows<<<blocks(sim.nv), kBlk, 0, s>>>(st.X.p, st.tris.p, ptr.p, code.p, sim.nv, st.density * st.thickness,
+                                                sim.mass.p);
     SHELL_HIP(hipGetLastError());
+    SHELL_HIP(hipStreamSynchronize(s));  // the incidence lists are released on return
 }
 
 // (Re)binds a batch to its member simulations.  Buffers only grow; the force descriptors are staged on

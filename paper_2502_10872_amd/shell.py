@@ -44,7 +44,7 @@ class shell_config_t(ctypes.Structure):
 
 SHELL_FLAG_DIRECT_PRODUCT = 1
 SHELL_FLAG_WORLD_FRAME = 2  # edge models: the quadratic thin plate/shell operator (App. D, eq 79)
-SHELL_FLAG_MEMBRANE = 4  # shell_eval_forces adds the membrane of Sec. 3 (eq 1); not taken by the step
+SHELL_FLAG_MEMBRANE = 4  # adds the membrane of Sec. 3 (eq 1): forces (both precisions), step and static solve (FP64)
 
 
 class shell_stencils_info_t(ctypes.Structure):
@@ -73,7 +73,7 @@ class shell_static_params_t(ctypes.Structure):
 
 class shell_step_stats_t(ctypes.Structure):
     _fields_ = [("newton_iters", ctypes.c_int32), ("pcg_total", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("grad_norm0", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("newton_capped", ctypes.c_int32), ("grad_norm0", ctypes.c_double), ("grad_norm", ctypes.c_double),
                 ("counts", (ctypes.c_int32 * 3) * SHELL_MAX_NEWTON)]
 
 
@@ -285,7 +285,7 @@ def stats_dict(s: shell_step_stats_t) -> dict:
     n = max(s.newton_iters, 0)
     counts = np.array([[s.counts[k][d] for d in range(3)] for k in range(n)], np.int32).reshape(n, 3)
     return dict(newton_iters=s.newton_iters, pcg_total=s.pcg_total, status=s.status, grad_norm0=s.grad_norm0,
-                grad_norm=s.grad_norm, counts=counts)
+                grad_norm=s.grad_norm, counts=counts, newton_capped=bool(s.newton_capped))
 
 
 def shell_step_implicit(sim, params: shell_step_params_t, with_stats=True, stream=None):
