@@ -140,7 +140,7 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
                 return (std::isfinite(v) && v > 0.0) ? std::ldexp(1.0, int(std::lround(std::log2(v)))) : 1.0;
             };
             st->fscale = pow2(st->kb / ell) * 0x1p-10;
-            st->mscale = pow2(mat->young * mat->thickness * ell * 0x1p-16);
+            st->mscale = pow2(mat->young * mat->thickness * ell) * 0x1p-10;
         }
 
         const int k = st->k, r = st->r;
@@ -313,7 +313,7 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
         }
         if (energy) {
             if (st->nv == 0)
-                SHELL_HIP(hipMemsetAsync(energy, 0, sizeof(double), s));
+                launch_energy_finalize(nullptr, 0, 0.0, energy, s);  // a kernel, not a memset node
             else
                 launch_energy_finalize(st->epart.p, st->nblocks, st->bias_e0, energy, s, st->mepart.p,
                                        int64_t(st->mepart.n));
