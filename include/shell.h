@@ -172,6 +172,20 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
                                  shell_stream_t stream);
 
 /*
+ * shell_eval_forces_noalloc - shell_eval_forces for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same kernels and
+ * results, with the scratch (the positions in internal order, the force before it is scattered back to
+ * caller order, the per-tile energy partials, the descriptor and the tile list) in a file-scope device
+ * array of 64 MiB, which each device the library runs on holds until the process ends.  Allocates
+ * nothing (its first call on a device looks up that device's address of the array).  Meshes beyond about
+ * 1.39 million vertices (those whose scratch would exceed 64 MiB) are SHELL_E_INVALID_ARG.  Every call on
+ * a device shares that device's array: calls that overlap on one device (concurrent streams or threads)
+ * race and must be serialised by the caller.  Arguments, precision and errors as shell_eval_forces.
+ */
+shell_status_t shell_eval_forces_noalloc(shell_stencils_t st, const double* x, void* f, double* energy,
+                                         shell_stream_t stream);
+
+/*
  * shell_assemble_constant_hessian - the constant bending Hessian K = K_s (x) I3 assembled once
  * from the rest operators (eqs 21, 41, 53; the shells reuse the plate Hessian as the paper states
  * for each model).  Only the scalar K_s is stored.  Synchronises `stream`.

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 
 #include "internal.hpp"
@@ -318,6 +319,92 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
                 launch_energy_finalize(st->epart.p, st->nblocks, st->bias_e0, energy, s, st->mepart.p,
                                        int64_t(st->mepart.n));
         }
+        return SHELL_OK;
+    });
+}
+
+// ------------------------------------------------------------------ force evaluation without allocation
+
+namespace {
+
+// The scratch of shell_eval_forces_noalloc on every device the library runs on: the caller-order
+// positions in internal order, the internal-order force (float64 or float32), the per-tile energy
+// partials, the force descriptor and the tile work items.  The array's name is a host-side stand-in:
+// host code uses only the device address hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_for_current_device() {
+    int dev = 0;
+    SHELL_HIP(hipGetDevice(&dev));
+    SHELL_CHECK(dev >= 0 && dev < kMaxDevices, SHELL_E_UNSUPPORTED, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        SHELL_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        SHELL_CHECK(ptr != nullptr, SHELL_E_HIP, "hipGetSymbolAddress returned no address for the scratch");
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
+
+shell_status_t shell_eval_forces_noalloc(shell_stencils_t st, const double* x, void* f, double* energy,
+                                         shell_stream_t stream) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(st && (x || st->nv == 0) && (f || st->nv == 0), SHELL_E_INVALID_ARG, "null argument");
+        hipStream_t s = as_stream(stream);
+        const bool f32 = st->precision == SHELL_PREC_MIXED;
+        // layout of the scratch: positions, force, energy partials, descriptor, tile items
+        const size_t o_x = 0, o_f = align256(o_x + size_t(3 * st->nv) * sizeof(double));
+        const size_t o_e = align256(o_f + size_t(3 * st->nv) * sizeof(double));
+        const size_t o_d = align256(o_e + size_t(st->nblocks) * sizeof(double));
+        const size_t o_i = align256(o_d + sizeof(ForceDesc));
+        const size_t need = o_i + size_t(st->nblocks) * sizeof(WorkItem);
+        SHELL_CHECK(need <= kScratchBytes, SHELL_E_INVALID_ARG,
+                    "mesh too large for the no-allocation force entry point (its 64 MiB scratch holds about "
+                    "1.39 million vertices)");
+        if (st->nv == 0) {
+            if (energy) launch_energy_finalize(nullptr, 0, 0.0, energy, s);
+            return SHELL_OK;
+        }
+        unsigned char* base = static_cast<unsigned char*>(scratch_for_current_device());
+        double* xin = reinterpret_cast<double*>(base + o_x);
+        void* fout = base + o_f;
+        double* epart = reinterpret_cast<double*>(base + o_e);
+        ForceDesc* desc = reinterpret_cast<ForceDesc*>(base + o_d);
+        WorkItem* items = reinterpret_cast<WorkItem*>(base + o_i);
+        ForceDesc d{};
+        d.x = xin;
+        d.X = st->X.p;
+        d.f = fout;
+        d.epart = epart;
+        d.bias = st->bias.p;
+        d.boff = st->boff.p;
+        d.tidx = st->tidx.p;
+        d.trec = f32 ? static_cast<const void*>(st->trec32.p) : static_cast<const void*>(st->trec64.p);
+        d.nst = st->nst_pad;
+        d.nv = st->nv;
+        d.T = st->T;
+        d.model = st->model;
+        d.kb = st->kb;
+        d.fscale = st->fscale;
+        d.nu = st->poisson;
+        // descriptor and items written by kernels on the stream (no host-to-device copy to order)
+        launch_write_force_desc(d, desc, items, st->nblocks, s);
+        launch_gather_rows(x, st->perm_d.p, xin, st->nv, s);
+        launch_force_items(st->model, st->precision, desc, items, st->nblocks, st->T, s);
+        if (st->cfg_flags & SHELL_FLAG_MEMBRANE) launch_membrane_forces(*st, xin, fout, s);
+        launch_scatter_rows(fout, st->perm_d.p, f, st->nv, f32, s);
+        if (energy)
+            launch_energy_finalize(epart, st->nblocks, st->bias_e0, energy, s, st->mepart.p, int64_t(st->mepart.n));
         return SHELL_OK;
     });
 }

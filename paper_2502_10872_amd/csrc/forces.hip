@@ -522,6 +522,12 @@ __global__ void energy_finalize(const double* __restrict__ part, long n, double 
     if (threadIdx.x == 0) *out = v[0] + add;
 }
 
+__global__ void write_force_desc(ForceDesc d, ForceDesc* __restrict__ dst, WorkItem* __restrict__ items, long n) {
+    const long t = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (t == 0) *dst = d;
+    if (t < n) items[t] = WorkItem{0, int32_t(t)};
+}
+
 __global__ void gather_rows(const double* __restrict__ src, const int32_t* __restrict__ perm,
                             double* __restrict__ dst, long nv) {
     long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
@@ -557,6 +563,11 @@ void launch_force_items(int model, int precision, const ForceDesc* descs, const 
         case SHELL_SS: launch_model<SHELL_SS>(precision, descs, items, nitems, lds_T, s, start, stop); break;
         default: throw Error(SHELL_E_INVALID_ARG, "unknown model");
     }
+}
+
+void launch_write_force_desc(const ForceDesc& d, ForceDesc* dst, WorkItem* items, int64_t ntiles, hipStream_t s) {
+    write_force_desc<<<unsigned((std::max<int64_t>(ntiles, 1) + 255) / 256), 256, 0, s>>>(d, dst, items, ntiles);
+    SHELL_HIP(hipGetLastError());
 }
 
 void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s,

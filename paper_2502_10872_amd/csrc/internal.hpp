@@ -434,6 +434,8 @@ void launch_clamp_bias(shell_stencils_s& st, const int32_t* bc, hipStream_t s);
 // start/stop: events that receive the kernel's own begin and end times (null: none)
 void launch_force_items(int model, int precision, const ForceDesc* descs, const WorkItem* items, long nitems,
                         int lds_T, hipStream_t s, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
+// writes the descriptor *dst = d and the tile items (0, t), t < ntiles, from a kernel
+void launch_write_force_desc(const ForceDesc& d, ForceDesc* dst, WorkItem* items, int64_t ntiles, hipStream_t s);
 // energy = add + sum of the n partials (+ the m partials of `extra`, when given)
 void launch_energy_finalize(const double* epart, int64_t n, double add, double* energy, hipStream_t s,
                             const double* extra = nullptr, int64_t m = 0);

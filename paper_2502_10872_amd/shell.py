@@ -104,7 +104,7 @@ EXPORTS = ("shell_build_stencils", "shell_stencils_info", "shell_stencils_export
            "shell_batch_reset", "shell_sim_device_bytes", "shell_batch_profile", "shell_batch_profile_read",
            "shell_sim_profile", "shell_sim_profile_read",
            "shell_destroy_stencils", "shell_destroy_hessian", "shell_destroy_sim", "shell_destroy_batch",
-           "shell_status_string", "shell_last_error")
+           "shell_status_string", "shell_last_error", "shell_eval_forces_noalloc")
 
 _lib = None
 
@@ -121,6 +121,7 @@ def lib() -> ctypes.CDLL:
         L.shell_stencils_info.argtypes = [P, P]
         L.shell_stencils_export.argtypes = [P, P, P, P]
         L.shell_eval_forces.argtypes = [P, P, P, P, P]
+        L.shell_eval_forces_noalloc.argtypes = [P, P, P, P, P]
         L.shell_assemble_constant_hessian.argtypes = [P, P, P]
         L.shell_hessian_export_csr.argtypes = [P, P, P, P, P]
         L.shell_hessian_info.argtypes = [P, P]
@@ -222,6 +223,12 @@ def shell_stencils_export(st):
 def shell_eval_forces(st, x, f, energy=None, stream=None):
     _check(lib().shell_eval_forces(st, _dev_ptr(x), _dev_ptr(f), _dev_ptr(energy), _stream(stream)),
            "shell_eval_forces")
+
+
+def shell_eval_forces_noalloc(st, x, f, energy=None, stream=None):
+    """shell_eval_forces with its scratch in the library's fixed device array (allocates nothing)."""
+    _check(lib().shell_eval_forces_noalloc(st, _dev_ptr(x), _dev_ptr(f), _dev_ptr(energy), _stream(stream)),
+           "shell_eval_forces_noalloc")
 
 
 def shell_assemble_constant_hessian(st, stream=None):
