@@ -140,8 +140,8 @@ shell_status_t shell_build_stencils(const double* X, int64_t nv, const int32_t* 
             auto pow2 = [](double v) {
                 return (std::isfinite(v) && v > 0.0) ? std::ldexp(1.0, int(std::lround(std::log2(v)))) : 1.0;
             };
-            st->fscale = pow2(st->kb / ell) * 0x1p-10;
-            st->mscale = pow2(mat->young * mat->thickness * ell) * 0x1p-10;
+            st->fscale = pow2(st->kb / ell) * 0x1p-12;
+            st->mscale = pow2(mat->young * mat->thickness * ell) * 0x1p-12;
         }
 
         const int k = st->k, r = st->r;

@@ -111,44 +111,49 @@ __device__ __forceinline__ void block_sum(double (&v)[NQ], double* sh) {
 
 namespace shell {
 
-// Order-independent float64 accumulation of the owner-computes tiles in LDS.  Floating-point atomics
-// add in whatever order the waves arrive, so their last bits would change from run to run.  Instead each
-// contribution v (in units of a per-mesh power-of-two force scale, so exactly rescaled) is split into a
-// float64 part h, v rounded to a multiple of 2^-30 (by adding and subtracting 1.5 * 2^22, whose ulp that
-// is), and an integer count q of 2^-49 in the rest (the low bits of the rest plus 12, whose ulp is 2^-49),
-// each added with its own LDS atomic (ds_add_f64, ds_add_u32; float32 LDS atomics are slow here).  While
-// |v| < 2^17, every partial sum of up to 64 h parts is a multiple of 2^-30 below 2^23, so exactly
-// representable, and the counts (|q| <= 2^18) are integers: neither total depends on the order of the
-// additions.  What is dropped is below 2^-50 of the scale per contribution.  A contribution outside that
-// range (2^17 times the scale is about a hundred times the force of a kink at the element scale) is added
-// whole to the float64 part, which keeps the sum finite but makes its last bits order-dependent; a
-// non-finite one propagates.  LDS: 12 bytes per component.
+// Order-independent accumulation of the owner-computes tiles in LDS.  Floating-point atomics add in
+// whatever order the waves arrive, so their last bits would change from run to run.  Instead each
+// contribution v (in units of a per-mesh power-of-two force scale, so exactly rescaled) is held as two
+// integers: h, the count of 2^-20 nearest to v (int64), and q, the count of 2^-39 nearest to the rest
+// (int32, |q| <= 2^18), each added with its own integer LDS atomic (ds_add_u64, ds_add_u32; float32 LDS
+// atomics are slow here).  Integer sums do not depend on the order of the additions.  The total is
+// h 2^-20 + q 2^-39: what is dropped is below 2^-40 of the scale per contribution.  A contribution of
+// 2^36 or more (with 64 contributions per component the int64 sum stays below 2^62), or a non-finite one,
+// sets a flag on which the tile writes NaN, so that the state is reported as non-finite; with the scales
+// chosen per mesh that is some ten million times the force of a kink at the element scale.  LDS: 12
+// bytes per component and a flag.
 struct TileAcc {
-    double* hi;
+    long long* hi;
     int* lo;
-    static constexpr double kMax = 0x1p17;
-    __host__ __device__ static constexpr size_t bytes(long n) { return size_t(36 * n); }
+    int* bad;
+    static constexpr double kMax = 0x1p36;
+    __host__ __device__ static constexpr size_t bytes(long n) { return size_t(36 * n + 16); }
     __device__ __forceinline__ TileAcc(void* smem, long n)
-        : hi(static_cast<double*>(smem)), lo(reinterpret_cast<int*>(hi + 3 * n)) {}
+        : hi(static_cast<long long*>(smem)), lo(reinterpret_cast<int*>(hi + 3 * n)),
+          bad(reinterpret_cast<int*>(lo + 3 * n)) {}
     // every thread of the work-group calls it
     __device__ __forceinline__ void clear(int n3) {
         for (int i = threadIdx.x; i < n3; i += blockDim.x) {
-            hi[i] = 0.0;
+            hi[i] = 0;
             lo[i] = 0;
         }
+        if (threadIdx.x == 0) *bad = 0;
     }
     __device__ __forceinline__ void add(int k, double v) {
         if (!(fabs(v) < kMax)) {
-            atomicAdd(hi + k, v);
+            *bad = 1;
             return;
         }
-        const double h = (v + 0x1.8p22) - 0x1.8p22;
-        // 12 + (v - h) lies in [8, 16), where the ulp is 2^-49 and 12's low 32 mantissa bits are zero
-        const int q = __double2loint((v - h) + 0x1.8p3);
-        atomicAdd(hi + k, h);
+        const double t = v * 0x1p20;  // exact (a power of two)
+        const double h = rint(t);
+        const int q = int(rint((t - h) * 0x1p19));  // t - h is exact, |t - h| <= 1/2
+        atomicAdd(reinterpret_cast<unsigned long long*>(hi + k), static_cast<unsigned long long>(static_cast<long long>(h)));
         atomicAdd(lo + k, q);
     }
-    __device__ __forceinline__ double get(int k) const { return hi[k] + double(lo[k]) * 0x1p-49; }
+    // the total in units of the scale, or NaN when a contribution was out of range (after a barrier)
+    __device__ __forceinline__ double get(int k) const {
+        return *bad ? __builtin_nan("") : (double(hi[k]) + double(lo[k]) * 0x1p-19) * 0x1p-20;
+    }
 };
 
 }  // namespace shell

@@ -237,9 +237,10 @@ struct shell_stencils_s {
     int cfg_flags = 0;  // SHELL_FLAG_*
     bool reordered = false;
     double young = 0, poisson = 0, thickness = 0, density = 0, kb = 0;
-    // power-of-two force scales of the tile accumulation (l the mean rest edge): bending k_b / l 2^-10, the
-    // force of a kink at the element scale divided by 1024, so that contributions up to 128 times that
-    // force and down to 1e-18 of it are summed exactly; membrane E h l 2^-10, strains up to 128
+    // power-of-two force scales of the tile accumulation (l the mean rest edge): bending k_b / l 2^-12, the
+    // force of a kink at the element scale divided by 4096, so that contributions up to 2^24 times that
+    // force are summed exactly, to 2^-51 of it (a few float64 ulps); membrane E h l 2^-12, strains up to
+    // 2^24
     double fscale = 1.0, mscale = 1.0;
     std::vector<int32_t> perm, iperm;    // internal -> caller, caller -> internal
     std::vector<int32_t> h_idx;          // [ns][k] internal ids, -1 = missing
