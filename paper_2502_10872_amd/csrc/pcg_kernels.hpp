@@ -70,8 +70,8 @@ __device__ __forceinline__ bool work_item(const WorkItem* __restrict__ items, lo
 // block tree) and stores them, without atomics, in its own slot of that mesh's partials: slot = its
 // logical work-group id.  The kernel that needs a total sums the slots of the work-groups that can touch
 // the mesh ([pq_lo, pq_hi) for the product launch, [rz_lo, rz_hi) for the update launch, set by the host
-// for each launch shape): lane k adds slots lo + k, lo + k + 64, ... in order, then a butterfly across
-// the wave, so every wave of every work-group obtains the same bits, and so does every run.  Slots of
+// for each launch shape) in a fixed order (bin_totals), so every work-group obtains the same bits, and so
+// does every run.  Slots of
 // work-groups in the range that never meet the mesh stay at the zero written when the solve starts.
 // Partials are double-buffered by iteration parity, so a kernel never writes a set a running kernel
 // reads.
@@ -83,9 +83,39 @@ __device__ __forceinline__ double* bin_set(const SolveDesc& d, long par, int set
     return d.bins + (size_t(par & 1) * 2 + size_t(set)) * kBinQ * kSlots;
 }
 
-// totals of NQ quantities over the slots [lo, hi), in every lane of the calling wave
+// totals of NQ quantities over the slots [lo, hi), in every thread of the work-group (every thread calls
+// it; it holds barriers): wave w adds slots lo + 64 w + lane, lo + 64 (w + W) + lane, ... (W waves) and
+// sums them across the wave with a butterfly, then every thread adds the W wave sums in order.  One slot
+// per lane and quantity on a 512-slot set, so the update kernel starts after one round of loads.
 template <int NQ>
-__device__ __forceinline__ void bin_totals(const double* set, int lo, int hi, double (&tot)[NQ]) {
+__device__ __forceinline__ void bin_totals(const double* set, int lo, int hi, double (&tot)[NQ], double* sh) {
+    const gbl<const double>* b = G(set);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    double v[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = 0.0;
+    for (int k = lo + 64 * w + lane; k < hi; k += 64 * nw)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) v[q] += b[q * kSlots + k];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
+    __syncthreads();  // a previous use of sh is over
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) sh[q * nw + w] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double t = 0.0;
+        for (int k = 0; k < nw; ++k) t += sh[q * nw + k];
+        tot[q] = t;
+    }
+}
+
+// the same totals computed by each wave on its own (no barrier), lane k adding slots lo + k, lo + k + 64,
+// ... in order: the product kernel uses it, whose waves then go on to issue their own loads at once
+template <int NQ>
+__device__ __forceinline__ void bin_totals_wave(const double* set, int lo, int hi, double (&tot)[NQ]) {
     const gbl<const double>* b = G(set);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) tot[q] = 0.0;
@@ -193,7 +223,7 @@ __device__ __forceinline__ ProductState product_state(const SolveDesc& d, const 
     PcgState* sn = d.st + ((t + 1) & 1);
     const bool writer = wi.unit == 0 && threadIdx.x == 0;
     double tot[6];
-    bin_totals<6>(bin_set(d, t + 1, kSetRz), d.rz_lo, d.rz_hi, tot);
+    bin_totals_wave<6>(bin_set(d, t + 1, kSetRz), d.rz_lo, d.rz_hi, tot);
     ProductState r;
     int any = 0;
     if (t == 0) {
@@ -578,7 +608,7 @@ __global__ __launch_bounds__(kBlk) __attribute__((amdgpu_waves_per_eu(4))) void 
 // the bins.  In mixed precision the increment y is stored in float (the update is formed in float64):
 // it feeds nothing inside the solve, and the Newton loop recomputes the residual of x + y in float64,
 // which corrects its rounding at the next iteration; r stays float64.
-template <typename VR>
+template <typename VR, bool FOLD>
 __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem& wi, long t, const double (&al)[3],
                                              int fold, double (&acc)[6]) {
     const long i = long(wi.unit) * kBlk + threadIdx.x;
@@ -608,7 +638,7 @@ __device__ __forceinline__ void update_group(const SolveDesc& d, const WorkItem&
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        if constexpr (sizeof(VR) == 4) {
+        if constexpr (FOLD) {
             if (fold & (1 << c)) {  // wave-uniform: the same for every row of the mesh
                 G(d.y64)[3 * i + c] += yv[c];
                 yv[c] = 0.0;
@@ -627,6 +657,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(const SolveDesc* __restrict
     long first, last;
     if (!item_range(nitems, per, first, last)) return;
     __shared__ double sh[6 * (kBlk / 64)];
+    __shared__ double shb[3 * (kBlk / 64)];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     int cur = -1, done = 1, fold = 0;
     double al[3] = {0, 0, 0};
@@ -638,7 +669,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(const SolveDesc* __restrict
             cur = wi.mesh;
             const PcgState* st = d.st + ((t + 1) & 1);
             double pq[3];
-            bin_totals<3>(bin_set(d, t, kSetPq), d.pq_lo, d.pq_hi, pq);
+            bin_totals<3>(bin_set(d, t, kSetPq), d.pq_lo, d.pq_hi, pq, shb);
             done = st->done;
             fold = 0;
             for (int c = 0; c < 3; ++c) {
@@ -647,7 +678,14 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(const SolveDesc* __restrict
             }
         }
         if (done) continue;
-        update_group<VR>(d, wi, t, al, fold, acc);
+        if constexpr (sizeof(VR) == 4) {
+            if (fold)
+                update_group<VR, true>(d, wi, t, al, fold, acc);
+            else
+                update_group<VR, false>(d, wi, t, al, 0, acc);
+        } else {
+            update_group<VR, false>(d, wi, t, al, 0, acc);
+        }
     }
     if (cur >= 0 && !done) flush_partials<6>(bin_set(descs[cur], t, kSetRz), acc, sh);
 }
