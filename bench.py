@@ -95,35 +95,78 @@ def measured_traffic(key: str):
     return float(fields[key])
 
 
-def cpu_baseline(mesh, material, counts_per_step, newton_per_step, budget_s=30.0):
-    """The FP64 CPU oracle on the same mesh: one force evaluation and a short replayed PCG run are
-    timed, then scaled to the GPU step's measured Newton and PCG iteration counts."""
-    import oracle as O
+def host_cpu() -> dict:
+    """The host's processor model and the cores this process may use."""
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return dict(model=model, nproc=nproc, logical_cpus=os.cpu_count(),
+                omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
 
-    st = O.Stencils("SS", mesh.X, mesh.tris, material["young"], material["poisson"], material["thickness"])
-    sim = O.Sim(st, material, mesh.pinned)
+
+def _oracle_step_sample(O, sim, st, X):
+    """One force evaluation, then one Newton solve with 10 and with 40 replayed PCG iterations per
+    coordinate; returns the per-part times (force, Newton overhead without forces, one coordinate
+    PCG iteration)."""
     t0 = time.perf_counter()
-    st.forces(mesh.X)
+    st.forces(X)
     t_force = time.perf_counter() - t0
-    # one Newton solve with 10 and with 20 replayed PCG iterations per coordinate
     times = {}
-    for n in (10, 20):
-        sim.x[:] = mesh.X
+    for n in (10, 40):
+        sim.x[:] = X
         sim.v[:] = 0.0
         t0 = time.perf_counter()
         sim.step(1 / 30, max_newton=1, replay=np.full((1, 3), n, np.int32))
         times[n] = time.perf_counter() - t0
-    t_iter = max(times[20] - times[10], 1e-9) / 30.0  # one PCG iteration of one coordinate
+    t_iter = max(times[40] - times[10], 1e-9) / 90.0  # one PCG iteration of one coordinate
     t_newton = max(times[10] - 30 * t_iter, 0.0)  # predictor, 2 force evaluations and residuals, PCG setup
-    t_setup = max(t_newton - 2 * t_force, 0.0)
-    step_s = newton_per_step * t_setup + (newton_per_step + 1) * t_force + counts_per_step * t_iter
-    return dict(value=1.0 / step_s, unit="steps/s", cores=1, kind="oracle",
-                sample=(f"full 1024x1024 mesh: one force evaluation ({t_force:.2f} s) and one Newton solve with 10 "
-                        f"and 20 replayed PCG iterations per coordinate ({times[10]:.2f} s, {times[20]:.2f} s), "
-                        f"scaled to {newton_per_step:.1f} Newton solves and {counts_per_step:.0f} PCG "
-                        f"coordinate-iterations per step; single thread, {platform.processor() or 'host'} "
-                        f"({os.cpu_count()} logical cpus present)"),
-                seconds=dict(force=t_force, newton_overhead=t_newton, pcg_coord_iter=t_iter))
+    return dict(force=t_force, newton_overhead=t_newton, pcg_coord_iter=t_iter, newton_10=times[10],
+                newton_40=times[40])
+
+
+def cpu_baseline(mesh, material, counts_per_step, newton_per_step):
+    """The FP64 CPU oracle on the same mesh, on one thread (the plain build) and on all host cores (the
+    OpenMP timing build of the same source): one force evaluation and a short replayed PCG run are
+    timed, then scaled to the GPU step's measured Newton and PCG iteration counts."""
+    import oracle as O
+
+    host = host_cpu()
+    O.use_openmp(False)
+    st = O.Stencils("SS", mesh.X, mesh.tris, material["young"], material["poisson"], material["thickness"])
+    sim = O.Sim(st, material, mesh.pinned)
+
+    def steps_per_s(t):
+        t_setup = max(t["newton_overhead"] - 2 * t["force"], 0.0)
+        step_s = newton_per_step * t_setup + (newton_per_step + 1) * t["force"] + counts_per_step * t["pcg_coord_iter"]
+        return 1.0 / step_s
+
+    legs = {}
+    try:
+        for omp in (False, True):
+            threads = O.use_openmp(omp, host["nproc"] if omp else 0)
+            t = _oracle_step_sample(O, sim, st, mesh.X)
+            legs[omp] = dict(value=steps_per_s(t), cores=threads, seconds=t)
+    finally:
+        O.use_openmp(False)
+    one, allc = legs[False], legs[True]
+    sample = (f"full {int(round(mesh.nv ** 0.5))}^2 SS cap: one force evaluation and one Newton solve with 10 and "
+              f"40 replayed PCG iterations per coordinate, scaled to {newton_per_step:.1f} Newton solves and "
+              f"{counts_per_step:.0f} PCG coordinate-iterations per step (the GPU step's counts)")
+    print(f"[bench] oracle: 1 thread {one['value']:.2e} steps/s, {allc['cores']} threads "
+          f"{allc['value']:.2e} steps/s", file=sys.stderr, flush=True)
+    return dict(value=allc["value"], unit="steps/s", cores=allc["cores"], kind="oracle",
+                build="OpenMP timing build (stencil loop, sparse product and vector loops parallel)",
+                sample=sample, host=host, seconds=allc["seconds"],
+                single_thread=dict(value=one["value"], unit="steps/s", cores=1, build="plain serial build",
+                                   seconds=one["seconds"]),
+                parallel_speedup=allc["value"] / one["value"])
 
 
 CLAMPED_PLATE_ALPHA = 0.0012653  # clamped square plate, w_max = alpha q a^4 / D (Timoshenko & Woinowsky-Krieger)
@@ -391,57 +434,158 @@ def run_membrane(args):
                           membrane_step=steps)), flush=True)
 
 
+def batch64_timing(S, I, torch, precision, steps, warmup=1, max_pcg=400000):
+    """64 meshes (16^2..512^2 vertices, log-uniform, all six models, 1 cm spacing, Newton budget 4, PCG
+    rtol 1e-2, dt = 1/60) stepped as one batch (one launch per phase over all meshes), against the same
+    meshes stepped one at a time for the same number of steps."""
+    specs = I.batch_specs(64)
+    meshes = [I.mesh_from_spec(sp, spacing=0.01) for sp in specs]
+    t0 = time.perf_counter()
+    probs = [S.Problem(m, I.MATERIAL, precision=precision) for m in meshes]
+    setup_s = time.perf_counter() - t0
+    nv_total = sum(m.nv for m in meshes)
+    params, _ = S.step_params(1.0 / 60.0, gravity=I.GRAVITY, max_newton=4, max_pcg=max_pcg, pcg_rtol=1e-2)
+    batch = S.shell_batch_create([pb.sim for pb in probs])
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        S.shell_batch_step(batch, params, len(probs), stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pcg = 0
+    for k in range(steps):
+        rc, st = S.shell_batch_step(batch, params, len(probs), stream=stream)
+        pcg += sum(x["pcg_total"] for x in st)
+        print(f"[bench] batch step {k}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / steps
+    S.shell_destroy_batch(batch)
+    # one mesh at a time, same number of steps per mesh
+    t0 = time.perf_counter()
+    for pb in probs:
+        for _ in range(steps):
+            S.shell_step_implicit(pb.sim, params, stream=stream)
+    torch.cuda.synchronize()
+    seq_s = (time.perf_counter() - t0) / steps
+    for pb in probs:
+        pb.close()
+    print("[bench] batch64 done", file=sys.stderr, flush=True)
+    return dict(workload="64-mesh batch, sizes 16^2..512^2 log-uniform (seed 2502108724), all six models, "
+                         "1 cm spacing, dt=1/60 s, Newton budget 4, Jacobi-PCG rtol 0.01",
+                meshes=len(meshes), vertices=nv_total, steps=steps, warmup=warmup,
+                precision="fp64" if precision == S.SHELL_PREC_FP64 else "mixed",
+                mesh_steps_per_s=len(meshes) / batch_s, batch_ms_per_step=1e3 * batch_s,
+                vertex_steps_per_s=nv_total / batch_s,
+                one_at_a_time=dict(mesh_steps_per_s=len(meshes) / seq_s, ms_per_round=1e3 * seq_s),
+                speedup_vs_one_at_a_time=seq_s / batch_s, pcg_coord_iters_per_step=pcg / steps, setup_s=setup_s)
+
+
 def run_batch64(args):
-    """64 meshes (16^2..512^2 vertices, log-uniform, all six models, 1 cm spacing, mixed precision, Newton
-    budget 4, PCG rtol 1e-2, dt = 1/60) stepped as one batch, against the same meshes stepped one at a
-    time.  Prints one JSON line."""
+    """The multi-mesh batch as its own workload; prints one JSON line."""
     import torch
 
     from paper_2502_10872_amd import inputs as I
     from paper_2502_10872_amd import shell as S
 
-    specs = I.batch_specs(64)
-    meshes = [I.mesh_from_spec(sp, spacing=0.01) for sp in specs]
     precision = S.SHELL_PREC_MIXED if args.precision == "mixed" else S.SHELL_PREC_FP64
-    t0 = time.perf_counter()
-    probs = [S.Problem(m, I.MATERIAL, precision=precision) for m in meshes]
-    setup_s = time.perf_counter() - t0
-    nv_total = sum(m.nv for m in meshes)
-    params, _ = S.step_params(1.0 / 60.0, gravity=I.GRAVITY, max_newton=4, max_pcg=args.max_pcg, pcg_rtol=1e-2)
-    batch = S.shell_batch_create([pb.sim for pb in probs])
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        S.shell_batch_step(batch, params, len(probs), stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pcg = 0
-    for k in range(args.steps):
-        rc, st = S.shell_batch_step(batch, params, len(probs), stream=stream)
-        pcg += sum(x["pcg_total"] for x in st)
-        print(f"[bench] batch step {k}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    batch_s = (time.perf_counter() - t0) / args.steps
-    S.shell_destroy_batch(batch)
-    # one mesh at a time, same number of steps per mesh
-    t0 = time.perf_counter()
-    for pb in probs:
-        for _ in range(args.steps):
-            S.shell_step_implicit(pb.sim, params, stream=stream)
-    torch.cuda.synchronize()
-    seq_s = (time.perf_counter() - t0) / args.steps
-    for pb in probs:
-        pb.close()
-    out = dict(metric="batched implicit steps/s (64 meshes per step)", value=1.0 / batch_s, unit="batch steps/s",
-               n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * batch_s, higher_is_better=True,
-               scaling="weak", vs_baseline=None, dtype="f64" if precision == 0 else "f32+f64", data="synthetic",
-               config=dict(workload="64-mesh batch, sizes 16^2..512^2 log-uniform (seed 2502108724), all six models, "
-                                    "1 cm spacing, dt=1/60 s, Newton budget 4, Jacobi-PCG rtol 0.01",
-                           meshes=len(meshes), vertices=nv_total, precision=args.precision),
-               mesh_steps_per_s=len(meshes) / batch_s, vertex_steps_per_s=nv_total / batch_s,
-               one_at_a_time=dict(mesh_steps_per_s=len(meshes) / seq_s, ms_per_round=1e3 * seq_s),
-               speedup_vs_one_at_a_time=seq_s / batch_s, pcg_coord_iters_per_step=pcg / args.steps,
-               setup_s=setup_s)
+    b = batch64_timing(S, I, torch, precision, args.steps, args.warmup, args.max_pcg)
+    out = dict(metric="batched implicit steps/s (64 meshes per step)", value=1e3 / b["batch_ms_per_step"],
+               unit="batch steps/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+               ms_per_step=b["batch_ms_per_step"], higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64" if precision == S.SHELL_PREC_FP64 else "f32+f64", data="synthetic",
+               config=dict(workload=b["workload"], meshes=b["meshes"], vertices=b["vertices"],
+                           precision=args.precision),
+               mesh_steps_per_s=b["mesh_steps_per_s"], vertex_steps_per_s=b["vertex_steps_per_s"],
+               one_at_a_time=b["one_at_a_time"], speedup_vs_one_at_a_time=b["speedup_vs_one_at_a_time"],
+               pcg_coord_iters_per_step=b["pcg_coord_iters_per_step"], setup_s=b["setup_s"])
     print(json.dumps(out), flush=True)
+
+
+def config_steps(S, torch, mesh, precision, dt, steps, max_newton, newton_rtol, pcg_rtol, max_pcg=400000):
+    """`steps` implicit steps from rest, timed end to end (one untimed step first, then the state is reset
+    to rest, so the timed trajectory is the one a fresh run takes).  Returns the timing, the iteration
+    counts and the final positions."""
+    from paper_2502_10872_amd import inputs as I
+
+    pb = S.Problem(mesh, I.MATERIAL, precision=precision)
+    params, _ = S.step_params(dt, gravity=I.GRAVITY, max_newton=max_newton, max_pcg=max_pcg,
+                              newton_rtol=newton_rtol, pcg_rtol=pcg_rtol)
+    S.shell_step_implicit(pb.sim, params)
+    S.shell_sim_set_state(pb.sim, mesh.X, None, 0)
+    torch.cuda.synchronize()
+    stats, lat = [], []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        stats.append(S.shell_step_implicit(pb.sim, params)[1])
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    wall = time.perf_counter() - t_start
+    x, _, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+    pb.close()
+    lat.sort()
+    res = dict(steps=steps, steps_per_s=steps / wall, ms_per_step=1e3 * wall / steps,
+               p50_ms=1e3 * lat[len(lat) // 2], max_ms=1e3 * lat[-1],
+               newton_per_step=sum(st["newton_iters"] for st in stats) / steps,
+               pcg_coord_iters_per_step=sum(st["pcg_total"] for st in stats) / steps,
+               newton_capped_steps=sum(int(st.get("newton_capped", 0)) for st in stats),
+               last_grad_ratio=stats[-1]["grad_norm"] / max(stats[-1]["grad_norm0"], 1e-300))
+    return res, x
+
+
+def small_configs(S, I, torch):
+    """The two smaller workloads as full runs of 10 steps: the clamped 32 x 32 edge-hinge plate (FP64, dt =
+    1/60, PCG rtol 1e-10) and the 256 x 256 FVM-hinge cylinder patch (FP64 and mixed, dt = 1/30, Newton
+    budget 4, PCG rtol 1e-2, the headline step's settings), with the mixed result's distance from the FP64
+    one after the 10 steps."""
+    out = {}
+    plate = I.workload_plate32()
+    r, _ = config_steps(S, torch, plate, S.SHELL_PREC_FP64, 1 / 60, 10, 4, 1e-8, 1e-10)
+    r["workload"] = "rest-flat 32x32 square plate, EP, FP64, one side clamped, dt=1/60 s, PCG rtol 1e-10"
+    r["nv"] = plate.nv
+    out["plate32_ep"] = r
+    cyl = I.workload_cylinder(256, "FS")
+    xs = {}
+    for prec, key in ((S.SHELL_PREC_FP64, "fp64"), (S.SHELL_PREC_MIXED, "mixed")):
+        r, xs[key] = config_steps(S, torch, cyl, prec, 1 / 30, 10, 4, 1e-8, 1e-2)
+        r["workload"] = (f"cylinder patch R=0.5 m, 256x256, jitter 0.2, FVM shell (FS), {key}, pinned ends, "
+                         f"dt=1/30 s, Newton budget 4, PCG rtol 1e-2")
+        r["nv"] = cyl.nv
+        out[f"cylinder256_fs_{key}"] = r
+    # The Newton budget ends each step short of convergence (|g|/|g0| stays near 1 against the constant
+    # Hessian on this curved patch), so where a run stops depends on its PCG stopping points: the FP64 path
+    # run with a 10x tighter inner tolerance gives the spread of the method itself, beside the mixed path's
+    # distance from FP64.
+    _, x_tight = config_steps(S, torch, cyl, S.SHELL_PREC_FP64, 1 / 30, 10, 4, 1e-8, 1e-3)
+    u64 = np.linalg.norm(xs["fp64"] - cyl.X)
+    out["cylinder256_fs_mixed"]["displacement_rel_to_fp64"] = float(
+        np.linalg.norm(xs["mixed"] - xs["fp64"]) / max(u64, 1e-300))
+    out["cylinder256_fs_fp64"]["displacement_rel_fp64_rtol_1e-3_vs_1e-2"] = float(
+        np.linalg.norm(x_tight - xs["fp64"]) / max(u64, 1e-300))
+    print("[bench] plate32 and cylinder256 done", file=sys.stderr, flush=True)
+    return out
+
+
+def serving_run(torch, rates=(20.0, 200.0), durations=(3.0, 1.0), max_wait_s=5.0):
+    """The serving loop on short Poisson traces (10 steps per request, 2k..1M vertices log-normal, the six
+    models, mixed precision, 16 GB HBM budget): continuous batching against one mesh at a time on the
+    same trace.  A request that has waited longer than max_wait_s for admission is shed (rejected)."""
+    from paper_2502_10872_amd import serve
+
+    out = {}
+    for rate, dur in zip(rates, durations):
+        for mode in ("continuous", "one_at_a_time"):
+            cfg = serve.ServeConfig(max_wait_s=max_wait_s)
+            reqs = serve.make_requests(rate, dur)
+            if mode == "continuous":
+                res = serve.Server(serve.GpuExecutor(cfg), cfg).run(reqs)
+            else:
+                res = serve.run_sequential(serve.GpuExecutor(cfg), cfg, reqs)
+            torch.cuda.synchronize()
+            res.update(rate=rate, trace_s=dur, max_wait_s=max_wait_s)
+            out[f"rate{int(rate)}_{mode}"] = res
+            print(f"[bench] serving rate {rate:g} {mode}: {res['completed']}/{res['requests']} done, "
+                  f"p99 {res['p99_s']:.2f} s", file=sys.stderr, flush=True)
+    return out
 
 
 def timed_steps(S, torch, pb, params, steps, sample_every, label):
@@ -623,6 +767,8 @@ def main(argv=None):
     ap.add_argument("--workload", choices=("sphere-cap", "batch64", "linear-plate", "membrane"), default="sphere-cap")
     ap.add_argument("--no-force-models", action="store_true",
                     help="skip the per-model force kernel timing (six 1M-vertex meshes, both precisions)")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the 10-step plate and cylinder runs, the 64-mesh batch and the serving traces")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (counter calibration)")
     args = ap.parse_args(argv)
@@ -763,6 +909,10 @@ def main(argv=None):
             out["quasi_static"] = quasi_static(S, I, torch)
             out["quasi_static"]["linear_plate_sweep"] = linear_plate_sweep(S, I, torch)
             out["quasi_static"]["cantilever"] = cantilever(S, I, torch)
+    if not args.no_other_workloads and not args.hot_path_only and args.size == 1024:
+        out["other_workloads"] = small_configs(S, I, torch)
+        out["other_workloads"]["batch64"] = batch64_timing(S, I, torch, S.SHELL_PREC_MIXED, steps=3, warmup=1)
+        out["other_workloads"]["serving"] = serving_run(torch)
     if not args.no_cpu_baseline and args.size == 1024:
         print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(mesh, mat, pcg_per_step, newton_per_step)

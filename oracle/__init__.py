@@ -31,22 +31,40 @@ class OracleError(RuntimeError):
         self.code = code
 
 
-def build() -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"]
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+
+
+def build(openmp: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction).  openmp: the timing
+    build of the same source, whose stencil loop, sparse product and vector loops run on all cores."""
+    out = _LIB_OMP if openmp else _LIB
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared"] + (["-fopenmp"] if openmp else []) + \
+        ["-o", out, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
-    return _LIB
+    return out
 
 
 _lib = None
+_variant = False  # True: the OpenMP timing build is the one loaded
+
+
+def use_openmp(enable: bool, threads: int = 0) -> int:
+    """Switch later oracle calls to the OpenMP timing build (or back to the plain build) and return the
+    thread count in use.  Only the benchmark's CPU-baseline leg uses the timing build; every check uses
+    the plain build, whose summation order is fixed."""
+    global _lib, _variant
+    if enable != _variant:
+        _lib, _variant = None, enable
+    return int(lib().orc_threads(int(threads)))
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        L = ctypes.CDLL(_LIB)
+        path = _LIB_OMP if _variant else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build(_variant)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         d = ctypes.c_double
@@ -67,6 +85,7 @@ def lib():
         L.orc_step_membrane.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, i64, P, P, d, d, d, P, P, P, P, d, P,
                                         i, d, d, i, P, P, P, P, P]
         L.orc_edge_normal_literal.argtypes = [P, P, P, P, P]
+        L.orc_threads.argtypes = [i]
         _lib = L
     return _lib
 

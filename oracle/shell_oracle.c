@@ -24,6 +24,12 @@
  *             Gauss-Newton tangent, and the implicit step of the shell with
  *             its membrane (Gauss-Newton matrix, Armijo backtracking).
  *
+ * Built plain (serial, fixed summation order) for every check.  The same
+ * source built with -fopenmp is a timing build only, for the all-cores CPU
+ * baseline: the stencil loop, the sparse product and the vector loops of the
+ * implicit step then run in parallel, and the force scatter uses atomic adds,
+ * so its sums have no fixed order.
+ *
  * Readings where the paper is silent or ambiguous (each is also listed in the
  * design notes of the repository):
  *  - foot ratios are signed, s_p = (X1-X2).e/|e|^2 (the App. B definition),
@@ -58,6 +64,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* ---------------------------------------------------------------- vectors */
 
@@ -568,6 +577,7 @@ int orc_forces(int model, int64_t nv, const double* x, int64_t ns, const int32_t
     int k = orc_stencil_size(model), r = orc_curv_size(model);
     memset(f, 0, sizeof(double) * (size_t)(3 * nv));
     double E = 0.0;
+#pragma omp parallel for reduction(+ : E) schedule(static)
     for (int64_t s = 0; s < ns; ++s) {
         const int32_t* id = idx + k * s;
         const double* Bs = B + (size_t)(r * k) * s;
@@ -643,7 +653,11 @@ int orc_forces(int model, int64_t nv, const double* x, int64_t ns, const int32_t
             for (int j = 0; j < k; ++j) axpy3(-1.0, gn[j], fs[j]);
         }
         for (int j = 0; j < k; ++j)
-            if (id[j] >= 0) axpy3(1.0, fs[j], f + 3 * id[j]);
+            if (id[j] >= 0)
+                for (int c = 0; c < 3; ++c) {
+#pragma omp atomic
+                    f[3 * id[j] + c] += fs[j][c];
+                }
     }
     if (energy) *energy = E;
     return ORC_OK;
@@ -737,6 +751,7 @@ int orc_mass(int64_t nv, const double* X, int64_t nt, const int32_t* tris, doubl
 
 int orc_apply(int64_t nv, const int64_t* rowptr, const int32_t* col, const double* val, const double* mass,
               double dt2, const double* p, double* q) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nv; ++i) {
         double acc[3] = {0, 0, 0};
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) axpy3(val[e], p + 3 * col[e], acc);
@@ -754,6 +769,7 @@ static int pcg_column(int64_t nv, const int64_t* rowptr, const int32_t* col, con
     double *r = (double*)malloc(sizeof(double) * (size_t)nv), *z = (double*)malloc(sizeof(double) * (size_t)nv);
     double *p = (double*)malloc(sizeof(double) * (size_t)nv), *q = (double*)malloc(sizeof(double) * (size_t)nv);
     double bn = 0;
+#pragma omp parallel for reduction(+ : bn) schedule(static)
     for (int64_t i = 0; i < nv; ++i) {
         y[i] = 0.0;
         r[i] = pinned[i] ? 0.0 : b[i];
@@ -763,6 +779,7 @@ static int pcg_column(int64_t nv, const int64_t* rowptr, const int32_t* col, con
     int target = replay_count >= 0 ? replay_count : max_pcg;
     int it = 0;
     double rz = 0;
+#pragma omp parallel for reduction(+ : rz) schedule(static)
     for (int64_t i = 0; i < nv; ++i) {
         z[i] = dinv[i] * r[i];
         p[i] = z[i];
@@ -771,10 +788,12 @@ static int pcg_column(int64_t nv, const int64_t* rowptr, const int32_t* col, con
     while (it < target) {
         if (replay_count < 0) {
             double rn = 0;
+#pragma omp parallel for reduction(+ : rn) schedule(static)
             for (int64_t i = 0; i < nv; ++i) rn += r[i] * r[i];
             if (sqrt(rn) <= rtol * bn) break;
         }
         double pq = 0;
+#pragma omp parallel for reduction(+ : pq) schedule(static)
         for (int64_t i = 0; i < nv; ++i) {
             double acc = 0;
             for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) acc += val[e] * p[col[e]];
@@ -782,18 +801,21 @@ static int pcg_column(int64_t nv, const int64_t* rowptr, const int32_t* col, con
             pq += p[i] * q[i];
         }
         double alpha = pq != 0.0 ? rz / pq : 0.0;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < nv; ++i) {
             y[i] += alpha * p[i];
             r[i] -= alpha * q[i];
         }
         ++it;
         double rz_new = 0;
+#pragma omp parallel for reduction(+ : rz_new) schedule(static)
         for (int64_t i = 0; i < nv; ++i) {
             z[i] = dinv[i] * r[i];
             rz_new += r[i] * z[i];
         }
         double beta = rz != 0.0 ? rz_new / rz : 0.0;
         rz = rz_new;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < nv; ++i) p[i] = z[i] + beta * p[i];
     }
     if (replay_count < 0 && it >= max_pcg) {
@@ -824,11 +846,13 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
     double dt2 = dt * dt;
     memcpy(xt, x, sizeof(double) * n3);
     /* predictor x_hat = x^t + dt v^t + dt^2 M^-1 f_ext with f_ext = m g (eq 62) */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nv; ++i)
         for (int d = 0; d < 3; ++d)
             xhat[3 * i + d] = pinned[i] ? xt[3 * i + d] : xt[3 * i + d] + dt * v[3 * i + d] + dt2 * gravity[d];
     memcpy(x, xhat, sizeof(double) * n3);
     /* Jacobi preconditioner: inverse diagonal of M_s + dt^2 K_s */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nv; ++i) {
         double kii = 0;
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
@@ -841,6 +865,7 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
         /* gradient of the incremental potential, g = M(x - x_hat) - dt^2 f(x), pinned rows zero */
         orc_forces(model, nv, x, ns, idx, B, kappa0, Crest, D, f, NULL);
         double s = 0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
         for (int64_t i = 0; i < nv; ++i)
             for (int d = 0; d < 3; ++d) {
                 double gi = pinned[i] ? 0.0 : mass[i] * (x[3 * i + d] - xhat[3 * i + d]) - dt2 * f[3 * i + d];
@@ -852,12 +877,14 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
         if (gn0 == 0.0 || (k > 0 && gn <= newton_rtol * gn0) || k == max_newton) break;
         /* Newton direction against the constant matrix, one PCG per coordinate */
         for (int d = 0; d < 3; ++d) {
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < nv; ++i) bcol[i] = -g[3 * i + d];
             int rc_count = replay ? replay[3 * k + d] : -1;
             int it = pcg_column(nv, rowptr, col, val, mass, pinned, dt2, dinv, bcol, ycol, pcg_rtol, max_pcg,
                                 rc_count, &budget_hit);
             if (counts) counts[3 * k + d] = it;
             pcg_total += it;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < nv; ++i) x[3 * i + d] += ycol[i];
         }
         ++newton;
@@ -1379,4 +1406,14 @@ int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3
     if (!(ml > 0)) return ORC_E_DEGENERATE;
     scale3(m, 1.0 / ml, n);
     return ORC_OK;
+}
+
+int orc_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }

@@ -131,4 +131,8 @@ int orc_static_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, c
 
 int orc_edge_normal_literal(const double* x1, const double* x2, const double* x3, const double* x4, double* n);
 
+/* Threads of the parallel loops: sets the count when n > 0 and returns the count in use
+   (always 1 in the serial build, which ignores n). */
+int orc_threads(int n);
+
 #endif

@@ -6,6 +6,7 @@ all of them together: each tick is one batched implicit step (one launch per pha
 mesh, per-mesh Newton and PCG control), and requests join and leave between ticks:
 
 * arrival      -> FIFO queue (bounded; a request whose estimated footprint can never fit is rejected)
+* shedding     -> a request still queued max_wait_s after its arrival is dropped (status "shed")
 * admission    -> while the HBM budget and the slot limit allow, the queue head is handed to a builder
                   thread (topology, rest precompute and Hessian assembly on the builder's own stream)
 * ready        -> joins the active batch at the next tick
@@ -57,6 +58,7 @@ class ServeConfig:
     hbm_budget: int = 16 << 30
     max_active: int = 256
     max_queue: int = 100000
+    max_wait_s: float = math.inf  # queue-wait deadline: longer-waiting requests are shed
     builders: int = 4
     dt: float = 1.0 / 60.0
     max_newton: int = 4
@@ -212,6 +214,17 @@ class Server:
                         done.append(r)
                     else:
                         queue.append(r)
+                # shedding: requests that waited past the deadline leave the queue unserved
+                if queue and now - queue[0].t_arrival > cfg.max_wait_s:
+                    kept = collections.deque()
+                    for r in queue:
+                        if now - r.t_arrival > cfg.max_wait_s:
+                            r.status = "shed"
+                            r.t_done = now
+                            done.append(r)
+                        else:
+                            kept.append(r)
+                    queue = kept
                 # admission: FIFO under the HBM budget and the slot limit
                 while queue and len(building) + len(active) < cfg.max_active and \
                         self.in_use + int(self.bpv * queue[0].nv) <= cfg.hbm_budget:
@@ -288,6 +301,9 @@ def run_sequential(executor, cfg: ServeConfig, requests, realtime=True):
                     time.sleep(wait)
             else:
                 r.t_arrival = 0.0
+            if clock() - r.t_arrival > cfg.max_wait_s:
+                r.status, r.t_done = "shed", clock()
+                continue
             r.t_admit = clock()
             try:
                 r.handle = executor.build(r)
@@ -315,6 +331,7 @@ def summarize(requests, wall, server):
     steps = sum(r.steps_done for r in ok)
     out = dict(requests=len(requests), completed=len(ok),
                rejected=sum(r.status == "rejected" for r in requests),
+               shed=sum(r.status == "shed" for r in requests),
                failed=sum(r.status == "failed" for r in requests),
                wall_s=wall, req_per_s=len(ok) / wall if wall > 0 else math.nan,
                steps_per_s=steps / wall if wall > 0 else math.nan,

@@ -61,3 +61,17 @@ def test_realtime_latency_accounting_and_sequential_baseline():
     assert seq["completed"] == 4
     # batching amortises the per-step overhead: fewer ticks than the sequential path's steps
     assert out["ticks"] < 12
+
+
+def test_requests_past_the_wait_deadline_are_shed():
+    # one slot, 30 ms per step, 4 steps per request: the queue outgrows a 50 ms wait deadline
+    cfg = V.ServeConfig(hbm_budget=1 << 40, builders=1, max_active=1, max_wait_s=0.05)
+    rs = reqs([100] * 6, steps=4, gap=0.002)
+    out = V.Server(V.FakeExecutor(cfg, step_s_per_vertex=3e-6), cfg).run(rs)
+    assert out["shed"] >= 1 and out["completed"] >= 1
+    assert out["completed"] + out["shed"] == 6 and out["rejected"] == 0
+    assert all(r.steps_done == 0 for r in rs if r.status == "shed")
+    # the one-at-a-time path sheds by the same deadline
+    rs2 = reqs([100] * 6, steps=4, gap=0.002)
+    seq = V.run_sequential(V.FakeExecutor(cfg, step_s_per_vertex=3e-6), cfg, rs2)
+    assert seq["shed"] >= 1 and seq["completed"] + seq["shed"] == 6
