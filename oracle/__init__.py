@@ -80,6 +80,7 @@ def lib():
         L.orc_membrane.argtypes = [i64, P, i64, P, P, d, d, d, P, P]
         L.orc_membrane_rest_hessian.argtypes = [i64, P, P, d, d, d, P]
         L.orc_membrane_gn_hessian.argtypes = [i64, P, P, P, d, d, d, P]
+        L.orc_membrane_tangent.argtypes = [i64, P, P, P, d, d, d, P]
         L.orc_static_membrane.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, i64, P, P, d, d, d, P, P, P, d, d, i,
                                           d, i, P, P, P]
         L.orc_step_membrane.argtypes = [i, i64, i64, P, P, P, P, P, P, P, P, i64, P, P, d, d, d, P, P, P, P, d, P,
@@ -92,6 +93,15 @@ def lib():
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def held_mask(pinned, held=None):
+    """The solvers' per-vertex mask of held coordinates: every coordinate of a vertex whose `pinned`
+    entry is nonzero, plus the coordinates that `held` names (bit d holds coordinate d of the vertex)."""
+    m = np.where(np.asarray(pinned) != 0, 7, 0).astype(np.uint8)
+    if held is not None:
+        m |= np.asarray(held, dtype=np.uint8) & 7
+    return np.ascontiguousarray(m)
 
 
 def _check(rc, what):
@@ -220,15 +230,25 @@ def membrane_gn_hessian(st: Stencils, x):
     return K9
 
 
+def membrane_tangent(st: Stencils, x):
+    """Per-triangle membrane tangent of the solvers at x (Gauss-Newton plus the stress part with the
+    stress's positive semi-definite part), [nt][9][9]."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    K9 = np.zeros((st.nt, 9, 9))
+    _check(lib().orc_membrane_tangent(st.nt, _p(st.tris), _p(st.X), _p(x), st.young, st.poisson, st.thickness,
+                                      _p(K9)), "membrane tangent")
+    return K9
+
+
 class MembraneSim:
-    """Implicit-Euler state of the shell with its membrane (Sec. 3 and Sec. 5): Gauss-Newton matrix, one
+    """Implicit-Euler state of the shell with its membrane (Sec. 3 and Sec. 5): the membrane tangent, one
     coupled Jacobi-PCG per Newton solve, Armijo backtracking on the incremental potential."""
 
-    def __init__(self, st: Stencils, material: dict, pinned, x0=None, v0=None):
+    def __init__(self, st: Stencils, material: dict, pinned, x0=None, v0=None, held=None):
         self.st = st
         self.csr = st.hessian()
         self.mass = mass(st.X, st.tris, material["density"], material["thickness"])
-        self.pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
+        self.pinned = held_mask(pinned, held)
         self.x = np.array(st.X if x0 is None else x0, dtype=np.float64, copy=True)
         self.v = np.zeros_like(self.x) if v0 is None else np.array(v0, dtype=np.float64, copy=True)
 
@@ -258,11 +278,11 @@ class MembraneSim:
 class Sim:
     """Implicit-Euler state advanced by the oracle (Sec. 5, eqs 62-63 without contact)."""
 
-    def __init__(self, st: Stencils, material: dict, pinned, x0=None, v0=None):
+    def __init__(self, st: Stencils, material: dict, pinned, x0=None, v0=None, held=None):
         self.st = st
         self.csr = st.hessian()
         self.mass = mass(st.X, st.tris, material["density"], material["thickness"])
-        self.pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
+        self.pinned = held_mask(pinned, held)
         self.x = np.array(st.X if x0 is None else x0, dtype=np.float64, copy=True)
         self.v = np.zeros_like(self.x) if v0 is None else np.array(v0, dtype=np.float64, copy=True)
 
@@ -288,11 +308,11 @@ class Sim:
 
 
 def solve_static(st: Stencils, pinned, load=None, x0=None, eps_f=1e-3, eps_u=0.0, max_newton=20, pcg_rtol=1e-10,
-                 max_pcg=200000, replay=None):
+                 max_pcg=200000, replay=None, held=None):
     """Quasi-static equilibrium under the applied load (Sec. 5, eq 64); returns (x, counts, stats)."""
     rowptr, col, val = st.hessian()
     x = np.array(st.X if x0 is None else x0, dtype=np.float64, copy=True)
-    pin = np.ascontiguousarray(pinned, dtype=np.uint8)
+    pin = held_mask(pinned, held)
     F = None if load is None else np.ascontiguousarray(load, dtype=np.float64)
     counts = np.zeros((max(max_newton, 1), 3), dtype=np.int32)
     stats = np.zeros(4)
@@ -309,11 +329,11 @@ def solve_static(st: Stencils, pinned, load=None, x0=None, eps_f=1e-3, eps_u=0.0
 
 
 def solve_static_membrane(st: Stencils, pinned, load=None, x0=None, eps_f=1e-3, eps_u=0.1, max_newton=200,
-                          pcg_rtol=1e-10, max_pcg=200000, replay=None):
+                          pcg_rtol=1e-10, max_pcg=200000, replay=None, held=None):
     """Quasi-static equilibrium of the shell with its membrane (eq 64); returns (x, counts, stats)."""
     rowptr, col, val = st.hessian()
     x = np.array(st.X if x0 is None else x0, dtype=np.float64, copy=True)
-    pin = np.ascontiguousarray(pinned, dtype=np.uint8)
+    pin = held_mask(pinned, held)
     F = None if load is None else np.ascontiguousarray(load, dtype=np.float64)
     counts = np.zeros(max(max_newton, 1), dtype=np.int32)
     stats = np.zeros(4)

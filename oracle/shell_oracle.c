@@ -55,7 +55,9 @@
  *    clamped edges; the edge shell emits no clamped stencil (its energy would
  *    vanish identically in its own triangle's frame);
  *  - mass is lumped, m_v = rho h sum(A_T)/3; x_hat = x + dt v + dt^2 g;
- *    v^{t+1} = (x^{t+1} - x^t)/dt; pinned vertices keep their position;
+ *    v^{t+1} = (x^{t+1} - x^t)/dt; held coordinates keep their value (the
+ *    fixed set is a per-vertex mask of coordinates, bit d holding coordinate d,
+ *    so a symmetry plane holds one coordinate of its vertices);
  *  - linear solver: Jacobi-preconditioned CG per coordinate, x0 = 0, stop when
  *    ||r|| <= rtol ||b||; alpha = 0 when p.q = 0, beta = 0 when r.z was 0.
  */
@@ -64,6 +66,10 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* held coordinates: pinned[i] bit d holds coordinate d of vertex i; 7 holds the whole vertex */
+static int held(const uint8_t* pinned, int64_t i, int d) { return (pinned[i] >> d) & 1; }
+static int held_all(const uint8_t* pinned, int64_t i) { return (pinned[i] & 7) == 7; }
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -764,15 +770,15 @@ int orc_apply(int64_t nv, const int64_t* rowptr, const int32_t* col, const doubl
 
 /* one column of (M + dt^2 K_s)_ff y = b by Jacobi-PCG; returns the iteration count */
 static int pcg_column(int64_t nv, const int64_t* rowptr, const int32_t* col, const double* val, const double* mass,
-                      const uint8_t* pinned, double dt2, const double* dinv, const double* b, double* y, double rtol,
-                      int max_pcg, int replay_count, int* budget_hit) {
+                      const uint8_t* pinned, int dcol, double dt2, const double* dinv, const double* b, double* y,
+                      double rtol, int max_pcg, int replay_count, int* budget_hit) {
     double *r = (double*)malloc(sizeof(double) * (size_t)nv), *z = (double*)malloc(sizeof(double) * (size_t)nv);
     double *p = (double*)malloc(sizeof(double) * (size_t)nv), *q = (double*)malloc(sizeof(double) * (size_t)nv);
     double bn = 0;
 #pragma omp parallel for reduction(+ : bn) schedule(static)
     for (int64_t i = 0; i < nv; ++i) {
         y[i] = 0.0;
-        r[i] = pinned[i] ? 0.0 : b[i];
+        r[i] = held(pinned, i, dcol) ? 0.0 : b[i];
         bn += r[i] * r[i];
     }
     bn = sqrt(bn);
@@ -797,7 +803,7 @@ static int pcg_column(int64_t nv, const int64_t* rowptr, const int32_t* col, con
         for (int64_t i = 0; i < nv; ++i) {
             double acc = 0;
             for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) acc += val[e] * p[col[e]];
-            q[i] = pinned[i] ? 0.0 : mass[i] * p[i] + dt2 * acc;
+            q[i] = held(pinned, i, dcol) ? 0.0 : mass[i] * p[i] + dt2 * acc;
             pq += p[i] * q[i];
         }
         double alpha = pq != 0.0 ? rz / pq : 0.0;
@@ -849,7 +855,7 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < nv; ++i)
         for (int d = 0; d < 3; ++d)
-            xhat[3 * i + d] = pinned[i] ? xt[3 * i + d] : xt[3 * i + d] + dt * v[3 * i + d] + dt2 * gravity[d];
+            xhat[3 * i + d] = held(pinned, i, d) ? xt[3 * i + d] : xt[3 * i + d] + dt * v[3 * i + d] + dt2 * gravity[d];
     memcpy(x, xhat, sizeof(double) * n3);
     /* Jacobi preconditioner: inverse diagonal of M_s + dt^2 K_s */
 #pragma omp parallel for schedule(static)
@@ -857,7 +863,7 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
         double kii = 0;
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
             if (col[e] == i) kii = val[e];
-        dinv[i] = pinned[i] ? 0.0 : 1.0 / (mass[i] + dt2 * kii);
+        dinv[i] = held_all(pinned, i) ? 0.0 : 1.0 / (mass[i] + dt2 * kii);
     }
     int newton = 0, pcg_total = 0, budget_hit = 0;
     double gn0 = 0, gn = 0;
@@ -868,7 +874,7 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
 #pragma omp parallel for reduction(+ : s) schedule(static)
         for (int64_t i = 0; i < nv; ++i)
             for (int d = 0; d < 3; ++d) {
-                double gi = pinned[i] ? 0.0 : mass[i] * (x[3 * i + d] - xhat[3 * i + d]) - dt2 * f[3 * i + d];
+                double gi = held(pinned, i, d) ? 0.0 : mass[i] * (x[3 * i + d] - xhat[3 * i + d]) - dt2 * f[3 * i + d];
                 g[3 * i + d] = gi;
                 s += gi * gi;
             }
@@ -880,7 +886,7 @@ int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double
 #pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < nv; ++i) bcol[i] = -g[3 * i + d];
             int rc_count = replay ? replay[3 * k + d] : -1;
-            int it = pcg_column(nv, rowptr, col, val, mass, pinned, dt2, dinv, bcol, ycol, pcg_rtol, max_pcg,
+            int it = pcg_column(nv, rowptr, col, val, mass, pinned, d, dt2, dinv, bcol, ycol, pcg_rtol, max_pcg,
                                 rc_count, &budget_hit);
             if (counts) counts[3 * k + d] = it;
             pcg_total += it;
@@ -1091,7 +1097,7 @@ static int coupled_pcg(int64_t nv, const int64_t* rowptr, const int32_t* col, co
         double pq = 0;
         for (int64_t i = 0; i < nv; ++i)
             for (int d = 0; d < 3; ++d) {
-                if (pinned[i]) q[3 * i + d] = 0.0;
+                if (held(pinned, i, d)) q[3 * i + d] = 0.0;
                 pq += p[3 * i + d] * q[3 * i + d];
             }
         double alpha = pq != 0.0 ? rz / pq : 0.0;
@@ -1131,8 +1137,64 @@ static void coupled_dinv(int64_t nv, const int64_t* rowptr, const int32_t* col, 
             for (int d = 0; d < 3; ++d) dinv[tris[3 * t + j]] += K9[81 * t + (3 * j + d) * 9 + 3 * j + d] / 3.0;
     for (int64_t i = 0; i < nv; ++i) {
         double den = (mass ? mass[i] : 0.0) + dt2 * dinv[i];
-        dinv[i] = (pinned[i] || den == 0.0) ? 0.0 : 1.0 / den;
+        dinv[i] = (held_all(pinned, i) || den == 0.0) ? 0.0 : 1.0 / den;
     }
+}
+
+/* Membrane tangent used by the solvers: the Gauss-Newton part plus the stress (geometric) part of the
+   exact Hessian, A (g_a^T S g_b) I3 for the vertex pair (a, b) with g the shape-function gradients and S
+   the second Piola-Kirchhoff stress, with S replaced by its positive semi-definite part (negative
+   principal stresses dropped).  Under tension this is the exact Hessian of the membrane energy; under
+   compression it is the Gauss-Newton tangent; it is PSD throughout.  K9 [nt][9][9] as above. */
+int orc_membrane_tangent(int64_t nt, const int32_t* tris, const double* X, const double* x, double young,
+                         double poisson, double thickness, double* K9) {
+    int rc = orc_membrane_gn_hessian(nt, tris, X, x, young, poisson, thickness, K9);
+    if (rc) return rc;
+    double c = young * thickness / (1.0 - poisson * poisson);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t* v = tris + 3 * t;
+        double e1[3], e2[3], G[2][2];
+        double A = cst_frame(X + 3 * v[0], X + 3 * v[1], X + 3 * v[2], e1, e2, G);
+        double d1[3], d2[3], F[3][2];
+        sub3(x + 3 * v[1], x + 3 * v[0], d1);
+        sub3(x + 3 * v[2], x + 3 * v[0], d2);
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 2; ++b) F[i][b] = d1[i] * G[0][b] + d2[i] * G[1][b];
+        double C[2][2];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) C[a][b] = F[0][a] * F[0][b] + F[1][a] * F[1][b] + F[2][a] * F[2][b];
+        double eps[3] = {0.5 * (C[0][0] - 1.0), 0.5 * (C[1][1] - 1.0), C[0][1]};
+        double s11 = c * (eps[0] + poisson * eps[1]), s22 = c * (poisson * eps[0] + eps[1]);
+        double s12 = c * 0.5 * (1.0 - poisson) * eps[2];
+        /* positive part of the 2x2 stress from its principal values l1 >= l2 */
+        double mean = 0.5 * (s11 + s22), half = 0.5 * (s11 - s22);
+        double rad = sqrt(half * half + s12 * s12);
+        double l1 = mean + rad, l2 = mean - rad;
+        double P[2][2];
+        if (l2 >= 0.0) {
+            P[0][0] = s11;
+            P[0][1] = P[1][0] = s12;
+            P[1][1] = s22;
+        } else if (l1 <= 0.0) {
+            P[0][0] = P[0][1] = P[1][0] = P[1][1] = 0.0;
+        } else {
+            /* l1 v v^T with v v^T = (S - l2 I) / (l1 - l2) */
+            double w = l1 / (l1 - l2);
+            P[0][0] = w * (s11 - l2);
+            P[0][1] = P[1][0] = w * s12;
+            P[1][1] = w * (s22 - l2);
+        }
+        double g[3][2] = {{-G[0][0] - G[1][0], -G[0][1] - G[1][1]}, {G[0][0], G[0][1]}, {G[1][0], G[1][1]}};
+        double* K = K9 + 81 * t;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double gsg = 0;
+                for (int p = 0; p < 2; ++p)
+                    for (int q = 0; q < 2; ++q) gsg += g[a][p] * P[p][q] * g[b][q];
+                for (int i = 0; i < 3; ++i) K[9 * (3 * a + i) + 3 * b + i] += A * gsg;
+            }
+    }
+    return ORC_OK;
 }
 
 /* incremental potential of the step with the membrane: 1/2 (x - x_hat)^T M (x - x_hat) + dt^2 (Psi_b + Psi_m);
@@ -1185,7 +1247,7 @@ int orc_step_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, con
     memcpy(xt, x, sizeof(double) * n3);
     for (int64_t i = 0; i < nv; ++i)
         for (int d = 0; d < 3; ++d)
-            xhat[3 * i + d] = pinned[i] ? xt[3 * i + d] : xt[3 * i + d] + dt * v[3 * i + d] + dt2 * gravity[d];
+            xhat[3 * i + d] = held(pinned, i, d) ? xt[3 * i + d] : xt[3 * i + d] + dt * v[3 * i + d] + dt2 * gravity[d];
     memcpy(x, xhat, sizeof(double) * n3);
     int newton = 0, pcg_total = 0, budget_hit = 0, rc = ORC_OK;
     double gn0 = 0, gn = 0;
@@ -1195,14 +1257,14 @@ int orc_step_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, con
         double s2 = 0;
         for (int64_t i = 0; i < nv; ++i)
             for (int d = 0; d < 3; ++d) {
-                double gi = pinned[i] ? 0.0 : mass[i] * (x[3 * i + d] - xhat[3 * i + d]) - dt2 * f[3 * i + d];
+                double gi = held(pinned, i, d) ? 0.0 : mass[i] * (x[3 * i + d] - xhat[3 * i + d]) - dt2 * f[3 * i + d];
                 g[3 * i + d] = gi;
                 s2 += gi * gi;
             }
         gn = sqrt(s2);
         if (k == 0) gn0 = gn;
         if (gn0 == 0.0 || (k > 0 && gn <= newton_rtol * gn0) || k == max_newton) break;
-        rc = orc_membrane_gn_hessian(nt, tris, X, x, young, poisson, thickness, K9);
+        rc = orc_membrane_tangent(nt, tris, X, x, young, poisson, thickness, K9);
         if (rc) break;
         coupled_dinv(nv, rowptr, col, val, nt, tris, K9, mass, pinned, dt2, dinv);
         int it = coupled_pcg(nv, rowptr, col, val, nt, tris, K9, mass, pinned, dt2, dinv, g, y, pcg_rtol, max_pcg,
@@ -1280,14 +1342,14 @@ int orc_static_membrane(int model, int64_t nv, int64_t ns, const int32_t* idx, c
         double s2 = 0;
         for (int64_t i = 0; i < nv; ++i)
             for (int d = 0; d < 3; ++d) {
-                double gi = pinned[i] ? 0.0 : -f[3 * i + d] - (load ? load[3 * i + d] : 0.0);
+                double gi = held(pinned, i, d) ? 0.0 : -f[3 * i + d] - (load ? load[3 * i + d] : 0.0);
                 g[3 * i + d] = gi;
                 s2 += gi * gi;
             }
         rn = sqrt(s2);
         if (k == 0) rn0 = rn;
         if (rn == 0.0 || rn < eps_f || k == max_newton) break;
-        rc = orc_membrane_gn_hessian(nt, tris, X, x, young, poisson, thickness, K9);
+        rc = orc_membrane_tangent(nt, tris, X, x, young, poisson, thickness, K9);
         if (rc) break;
         coupled_dinv(nv, rowptr, col, val, nt, tris, K9, NULL, pinned, 1.0, dinv);
         int it = coupled_pcg(nv, rowptr, col, val, nt, tris, K9, NULL, pinned, 1.0, dinv, g, y, pcg_rtol, max_pcg,
@@ -1341,7 +1403,7 @@ int orc_static(int model, int64_t nv, int64_t ns, const int32_t* idx, const doub
         double kii = 0;
         for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
             if (col[e] == i) kii = val[e];
-        dinv[i] = (pinned[i] || kii == 0.0) ? 0.0 : 1.0 / kii;
+        dinv[i] = (held_all(pinned, i) || kii == 0.0) ? 0.0 : 1.0 / kii;
     }
     int newton = 0, pcg_total = 0, budget_hit = 0;
     double rn0 = 0, rn = 0;
@@ -1350,7 +1412,7 @@ int orc_static(int model, int64_t nv, int64_t ns, const int32_t* idx, const doub
         double s2 = 0;
         for (int64_t i = 0; i < nv; ++i)
             for (int d = 0; d < 3; ++d) {
-                double ri = pinned[i] ? 0.0 : -f[3 * i + d] - (load ? load[3 * i + d] : 0.0);
+                double ri = held(pinned, i, d) ? 0.0 : -f[3 * i + d] - (load ? load[3 * i + d] : 0.0);
                 r[3 * i + d] = ri;
                 s2 += ri * ri;
             }
@@ -1359,7 +1421,7 @@ int orc_static(int model, int64_t nv, int64_t ns, const int32_t* idx, const doub
         if (rn == 0.0 || rn < eps_f || k == max_newton) break;
         for (int d = 0; d < 3; ++d) {
             for (int64_t i = 0; i < nv; ++i) bcol[i] = -r[3 * i + d];
-            int it = pcg_column(nv, rowptr, col, val, zero, pinned, 1.0, dinv, bcol, ycol, pcg_rtol, max_pcg,
+            int it = pcg_column(nv, rowptr, col, val, zero, pinned, d, 1.0, dinv, bcol, ycol, pcg_rtol, max_pcg,
                                 replay ? replay[3 * k + d] : -1, &budget_hit);
             if (counts) counts[3 * k + d] = it;
             pcg_total += it;

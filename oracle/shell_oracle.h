@@ -80,7 +80,9 @@ int orc_apply(int64_t nv, const int64_t* rowptr, const int32_t* col, const doubl
  * x, v: in x^t, v^t; out x^{t+1}, v^{t+1}.  replay [max_newton][3] or NULL:
  * when given, every solve runs exactly that many PCG iterations per column.
  * counts [max_newton][3] receives the iterations taken; stats[4] =
- * {newton_iters, pcg_total, grad_norm0, grad_norm_final}. */
+ * {newton_iters, pcg_total, grad_norm0, grad_norm_final}.  pinned [nv] (here and in every solver below):
+ * the held coordinates of each vertex, bit d holding coordinate d (x, y, z), 7 the whole vertex; a held
+ * coordinate keeps its value and its residual row is zero. */
 int orc_step(int model, int64_t nv, int64_t ns, const int32_t* idx, const double* B, const double* kappa0,
              const double* Crest, const double* D, const int64_t* rowptr, const int32_t* col, const double* val,
              const double* mass, const uint8_t* pinned, double* x, double* v,
@@ -108,6 +110,11 @@ int orc_membrane_rest_hessian(int64_t nt, const int32_t* tris, const double* X, 
 /* Gauss-Newton membrane tangent at x per triangle, K9 [nt][9][9] (PSD; the rest Hessian at x = X). */
 int orc_membrane_gn_hessian(int64_t nt, const int32_t* tris, const double* X, const double* x, double young,
                             double poisson, double thickness, double* K9);
+/* Membrane tangent of the solvers: the Gauss-Newton part plus the stress part of the exact Hessian with
+ * the stress replaced by its positive semi-definite part (exact under tension, Gauss-Newton under
+ * compression, PSD throughout), K9 [nt][9][9]. */
+int orc_membrane_tangent(int64_t nt, const int32_t* tris, const double* X, const double* x, double young,
+                         double poisson, double thickness, double* K9);
 /* Implicit-Euler step with bending and membrane: Newton matrix M + dt^2 (K_s (x) I3 + K_GN(x)), one
  * Jacobi-PCG over all coordinates, Armijo backtracking (at most 6 halvings) on the incremental potential.
  * replay_pcg, replay_halvings [max_newton] (may be NULL); counts, halvings [max_newton] out. */

@@ -253,6 +253,57 @@ def sphere_cap_mesh(n: int, radius: float, side: float = None, jitter: float = 0
                 dict(n=n, radius=radius, side=side, jitter=jitter, seed=seed))
 
 
+def hemisphere_mesh(rings: int = 17, around: int = 64, radius: float = 10.0, cut_deg: float = 18.0,
+                    model: str = "SS") -> Mesh:
+    """Hemisphere of radius R (pole on +z, equator in z = 0) with a circular hole of half-angle cut_deg
+    at the pole: `rings` latitude rings from the hole's rim (ring 0) to the equator, `around` vertices
+    per ring starting on +x (vertex id = ring * around + j, azimuth 2 pi j / around), each quad split
+    into two triangles.  Nothing pinned."""
+    theta = np.radians(np.linspace(cut_deg, 90.0, rings))
+    phi = 2.0 * math.pi * np.arange(around) / around
+    t, p = np.meshgrid(theta, phi, indexing="ij")
+    X = radius * np.stack([np.sin(t) * np.cos(p), np.sin(t) * np.sin(p), np.cos(t)], axis=-1).reshape(-1, 3)
+    # the azimuth grid is closed: column `around` is column 0
+    X[np.abs(X) < 1e-12 * radius] = 0.0
+    tris = []
+    for k in range(rings - 1):
+        for j in range(around):
+            a, b = k * around + j, k * around + (j + 1) % around
+            c, d = a + around, b + around
+            tris += [(a, c, d), (a, d, b)]
+    return Mesh(f"hemisphere{rings}x{around}", X, np.array(tris, dtype=np.int32),
+                np.zeros(rings * around, dtype=np.uint8), model, radius * math.radians(90.0 - cut_deg) / (rings - 1),
+                dict(rings=rings, around=around, radius=radius, cut_deg=cut_deg))
+
+
+HEMISPHERE_MATERIAL = dict(young=6.825e7, poisson=0.3, thickness=0.04, density=1.0)
+
+
+def hemisphere_problem(rings: int = 17, around: int = 64, load: float = 200.0, model: str = "SS"):
+    """The pinched hemisphere with an 18 degree hole: four radial point loads of size `load` on the
+    equator, inward on the x axis and outward on the y axis.  Held coordinates: x of the vertices in the
+    plane x = 0, y of those in the plane y = 0, and z of the hole-rim vertices in the plane x = 0.
+    Returns (mesh, held mask [nv] with bit d holding coordinate d, load [nv, 3], the load vertices on +x
+    and +y)."""
+    if around % 4:
+        raise ValueError("the load points and symmetry planes need around % 4 == 0")
+    m = hemisphere_mesh(rings, around, 10.0, 18.0, model)
+    j = np.tile(np.arange(around), rings)
+    k = np.repeat(np.arange(rings), around)
+    q = around // 4
+    held = np.zeros(m.nv, dtype=np.uint8)
+    held[(j == q) | (j == 3 * q)] |= 1
+    held[(j == 0) | (j == 2 * q)] |= 2
+    held[(k == 0) & ((j == q) | (j == 3 * q))] |= 4
+    F = np.zeros((m.nv, 3))
+    eq = (rings - 1) * around
+    F[eq + 0, 0] = -load
+    F[eq + 2 * q, 0] = load
+    F[eq + q, 1] = load
+    F[eq + 3 * q, 1] = -load
+    return m, held, F, (eq, eq + q)
+
+
 # --------------------------------------------------------------------------------------------
 # The five workloads (shapes, sizes and seeds) that the tests and the benchmark use.
 # --------------------------------------------------------------------------------------------

@@ -939,6 +939,39 @@ def test_membrane_gauss_newton_tangent():
     assert ev.min() >= -1e-10 * ev.max()
 
 
+def test_membrane_tangent_is_the_exact_hessian_under_tension_and_gauss_newton_under_compression():
+    """The solvers' membrane tangent (Gauss-Newton plus the stress term with the stress's PSD part): under
+    a uniform in-plane stretch every triangle's stress is positive definite, so it equals minus the
+    force's central-difference Jacobian (the exact Hessian); under a uniform shrink every stress is
+    negative definite, so it equals the Gauss-Newton tangent; in a mixed state (stretch along x, shrink
+    along y) it lies between them and stays PSD."""
+    m = I.plate_mesh(6, 1.0, 0.2, 9, "SP", "none")
+    st = O.Stencils("SP", m.X, m.tris, 1.0e6, 0.3, 1e-2)
+    g = I.rng(64)
+    Q = I.random_rotation(g)
+    for sx, sy, kind in ((1.04, 1.03, "tension"), (0.97, 0.96, "compression"), (1.05, 0.95, "mixed")):
+        x = (m.X * np.array([sx, sy, 1.0])) @ Q.T + g.standard_normal(3)
+        KT = _assemble9(st, O.membrane_tangent(st, x))
+        KG = _assemble9(st, O.membrane_gn_hessian(st, x))
+        if kind == "tension":
+            for _ in range(2):
+                d = g.standard_normal(3 * st.nv)
+                hh = 1e-7
+                fp, _ = O.membrane_forces(st, x + hh * d.reshape(-1, 3))
+                fm, _ = O.membrane_forces(st, x - hh * d.reshape(-1, 3))
+                J = -(fp - fm).ravel() / (2 * hh)
+                assert np.abs(J - KT @ d).max() <= 1e-6 * np.abs(KT @ d).max()
+                assert np.abs(J - KG @ d).max() > 1e-3 * np.abs(KT @ d).max()  # the stress term matters
+        elif kind == "compression":
+            assert np.abs(KT - KG).max() <= 1e-12 * np.abs(KG).max()
+        else:
+            diff = KT - KG
+            ev = np.linalg.eigvalsh(0.5 * (diff + diff.T))
+            assert ev.min() >= -1e-10 * ev.max() and ev.max() > 0
+        ev = np.linalg.eigvalsh(0.5 * (KT + KT.T))
+        assert ev.min() >= -1e-10 * ev.max()
+
+
 def _membrane_energy(st, mass, xhat, x, dt):
     eb = st.energy(x)
     _, em = O.membrane_forces(st, x)
@@ -1116,3 +1149,116 @@ def test_pcg_budget_is_reported():
     sim = O.Sim(st, I.MATERIAL, m.pinned)
     counts, stats = sim.step(1 / 60, max_newton=1, pcg_rtol=1e-12, max_pcg=3)
     assert stats["budget_hit"] and counts[0, 2] == 3
+
+
+# ------------------------------------------------------------------ held coordinates (per-vertex masks)
+
+
+def _held_plate_mask(n):
+    """Held coordinates of an n x n plate: x on the two outer columns, y on the two outer rows, z on the
+    two left columns; each coordinate's held set removes that coordinate's affine null space of K."""
+    i = np.tile(np.arange(n), n)
+    j = np.repeat(np.arange(n), n)
+    mask = np.zeros(n * n, dtype=np.uint8)
+    mask[(i == 0) | (i == n - 1)] |= 1
+    mask[(j == 0) | (j == n - 1)] |= 2
+    mask[i <= 1] |= 4
+    return mask
+
+
+@pytest.mark.parametrize("model", ["EP", "SP"])
+def test_static_plate_with_held_coordinates_is_one_sparse_solve_per_coordinate(model):
+    """Plates are linear per coordinate (f = -K (x - X)): with a different held set for each coordinate,
+    the first Newton-Raphson iterate is, for each coordinate d, the sparse direct solution of
+    K_ff u_d = F_d on that coordinate's free vertices, and held coordinates keep their rest value."""
+    n = 9
+    m = I.plate_mesh(n, 1.0, 0.2, 5, model, "none")
+    st = O.Stencils(model, m.X, m.tris, 1.0, 0.3, 1.0)
+    mask = _held_plate_mask(n)
+    load = I.rng(11).standard_normal((m.nv, 3))
+    x, _, stats = O.solve_static(st, np.zeros(m.nv), load, eps_f=1e-9 * np.abs(load).sum(), max_newton=5,
+                                 pcg_rtol=1e-14, held=mask)
+    rowptr, col, val = st.hessian()
+    K = sp.csr_matrix((val, col, rowptr), shape=(m.nv, m.nv))
+    u = np.zeros((m.nv, 3))
+    for d in range(3):
+        free = np.where((mask >> d) & 1 == 0)[0]
+        u[free, d] = spl.spsolve(K[free][:, free].tocsc(), load[free, d])
+    assert stats["newton_iters"] == 1
+    np.testing.assert_allclose(x - m.X, u, atol=1e-9 * np.abs(u).max())
+    for d in range(3):
+        h = (mask >> d) & 1 == 1
+        assert np.array_equal(x[h, d], m.X[h, d])
+
+
+def test_plate_step_with_held_coordinates_matches_dense_solve():
+    """A plate step with per-coordinate held sets: for each coordinate, (M + dt^2 K) x = M x_hat on its
+    free vertices, its held vertices keeping their value (x_hat from a random initial velocity)."""
+    n = 9
+    m = I.plate_mesh(n, 1.0, 0.2, 5, "EP", "none")
+    st = O.Stencils("EP", m.X, m.tris, I.MATERIAL["young"], I.MATERIAL["poisson"], I.MATERIAL["thickness"])
+    mask = _held_plate_mask(n)
+    v0 = 0.1 * I.rng(12).standard_normal((m.nv, 3))
+    sim = O.Sim(st, I.MATERIAL, np.zeros(m.nv), v0=v0, held=mask)
+    dt = 1 / 60
+    K = O.hessian_dense(st)
+    M = sim.mass
+    A = np.diag(M) + dt * dt * K
+    x = m.X.copy()
+    for d in range(3):
+        free = (mask >> d) & 1 == 0
+        xhat = m.X[:, d] + dt * v0[:, d] + dt * dt * I.GRAVITY[d]
+        rhs = M[free] * xhat[free] - A[np.ix_(free, ~free)] @ m.X[~free, d]
+        x[free, d] = np.linalg.solve(A[np.ix_(free, free)], rhs)
+    sim.step(dt, gravity=I.GRAVITY, max_newton=1, pcg_rtol=1e-14)
+    assert np.abs(sim.x - x).max() <= 1e-10 * np.abs(x - m.X).max()
+    for d in range(3):
+        h = (mask >> d) & 1 == 1
+        assert np.array_equal(sim.x[h, d], m.X[h, d]) and not sim.v[h, d].any()
+
+
+def _mirror_plate(n, side):
+    """Flat n x n square whose cell diagonals flip at the mid column, so that the mesh is its own mirror
+    image in the plane X = side / 2."""
+    X = I.flat_from_uv(I.grid_uv(n, n, side, side))
+    tris = []
+    for j in range(n - 1):
+        for i in range(n - 1):
+            a, b, c, d = j * n + i, j * n + i + 1, (j + 1) * n + i, (j + 1) * n + i + 1
+            if i < (n - 1) // 2:
+                tris += [(a, b, d), (a, d, c)]
+            else:
+                tris += [(a, b, c), (b, d, c)]
+    return X, np.array(tris, dtype=np.int32)
+
+
+def test_symmetry_plane_held_coordinate_leaves_the_symmetric_solution_unchanged():
+    """A mirror-symmetric plate (mesh, supports and load) with bending and membrane under a large
+    transverse load: its equilibrium is symmetric, so holding the normal coordinate x of the mid-column
+    vertices (a symmetry plane) changes nothing; the held coordinate stays exactly at rest and every free
+    coordinate's residual, recomputed from fresh forces, meets eps_f."""
+    n, side = 9, 1.0
+    X, tris = _mirror_plate(n, side)
+    st = O.Stencils("SS", X, tris, 1.0e6, 0.3, 1e-2)
+    i = np.tile(np.arange(n), n)
+    pinned = ((i <= 1) | (i >= n - 2)).astype(np.uint8)
+    load = np.zeros((n * n, 3))
+    load[:, 2] = -200.0 * O.mass(X, tris, 1.0, 1.0)
+    mid = i == (n - 1) // 2
+    held = np.where(mid, 1, 0).astype(np.uint8)
+    eps_f = 1e-9 * np.abs(load).sum()
+    xa, _, sa = O.solve_static_membrane(st, pinned, load, eps_f=eps_f, eps_u=0.1 * side, max_newton=200,
+                                        pcg_rtol=1e-12)
+    xb, _, sb = O.solve_static_membrane(st, pinned, load, eps_f=eps_f, eps_u=0.1 * side, max_newton=200,
+                                        pcg_rtol=1e-12, held=held)
+    w = np.abs(xa[:, 2] - X[:, 2]).max()
+    assert w > 0.05 * side  # large deflection: the membrane carries load
+    assert sa["resid"] < eps_f and sb["resid"] < eps_f
+    assert np.abs(xa[mid, 0] - X[mid, 0]).max() <= 1e-9 * w  # the free solution is symmetric
+    assert np.array_equal(xb[mid, 0], X[mid, 0])
+    np.testing.assert_allclose(xb, xa, atol=1e-8 * w)
+    fb, _ = st.forces(xb)
+    fm, _ = O.membrane_forces(st, xb)
+    res = -(fb + fm) - load
+    free = (O.held_mask(pinned, held)[:, None] >> np.arange(3)) & 1 == 0
+    assert np.linalg.norm(res[free]) < eps_f
