@@ -250,7 +250,7 @@ def membrane_timing(S, I, torch, reps=20):
 
 
 def membrane_step_timing(S, I, torch, sizes=(64, 256), steps=2):
-    """The implicit step of the smoothed-hinge shell with its membrane (FP64; Gauss-Newton membrane tangent,
+    """The implicit step of the smoothed-hinge shell with its membrane (FP64; the membrane tangent,
     coupled Jacobi-PCG, Armijo backtracking) on a cylinder patch of radius 0.5 m held at its ends, dt = 1/30,
     Newton budget 4, PCG rtol 1e-2 (the headline step's settings): time per step and its iteration counts."""
     out = {}
@@ -562,6 +562,40 @@ def small_configs(S, I, torch):
     out["cylinder256_fs_fp64"]["displacement_rel_fp64_rtol_1e-3_vs_1e-2"] = float(
         np.linalg.norm(x_tight - xs["fp64"]) / max(u64, 1e-300))
     print("[bench] plate32 and cylinder256 done", file=sys.stderr, flush=True)
+    return out
+
+
+# The combined table of Sec. 6 (hemisphere columns): u_min, v_max, Newton iterations and the authors' CPU
+# time for the three shell models and the reference shell element; quoted as context, not as a target.
+PAPER_HEMISPHERE = {"ES": (-4.072, 2.799, 56, 27.334), "FS": (-5.752, 3.403, 84, 44.153),
+                    "SS": (-5.923, 3.534, 87, 45.035), "reference_S4R": (-5.902, 3.406, 112, None)}
+
+
+def hemisphere_benchmark(S, I, torch):
+    """The pinched hemisphere (R = 10, 18 degree hole, four radial point loads of 200 on the equator,
+    E = 6.825e7, nu = 0.3, h = 0.04, 17 x 64 = 1088 vertices; x held on the plane x = 0, y on y = 0, z of
+    the hole-rim vertices on x = 0): quasi-static Newton-Raphson with the membrane, eps_f = 1e-3,
+    eps_u = 0.1, PCG rtol 1e-10, FP64, timed end to end per shell model."""
+    out = {}
+    for model in ("ES", "FS", "SS"):
+        mesh, held, F, _ = I.hemisphere_problem(17, 64, model=model)
+        with S.Problem(mesh, I.HEMISPHERE_MATERIAL, model=model, flags=S.SHELL_FLAG_MEMBRANE, held=held) as pb:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = S.shell_solve_static(pb.sim, F, eps_f=1e-3, eps_u=0.1, max_newton=250, pcg_rtol=1e-10)
+            torch.cuda.synchronize()
+            sec = time.perf_counter() - t0
+            x, _, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+        u = x - mesh.X
+        pu, pv, pn, pt = PAPER_HEMISPHERE[model]
+        pcg = int(np.asarray(st["counts"])[: st["newton_iters"], 0].sum())
+        out[model] = dict(nv=mesh.nv, newton_iters=st["newton_iters"], pcg_iters=pcg, seconds=sec,
+                          us_per_pcg_iteration=1e6 * sec / max(pcg, 1), residual=st["grad_norm"], status=rc,
+                          u_min=float(u[:, 0].min()), v_max=float(u[:, 1].max()),
+                          paper=dict(u_min=pu, v_max=pv, newton_iters=pn, seconds_on_the_authors_cpu=pt))
+        print(f"[bench] hemisphere {model}: newton {st['newton_iters']} u_min {u[:, 0].min():.3f} "
+              f"v_max {u[:, 1].max():.3f} {sec:.2f} s", file=sys.stderr, flush=True)
+    out["reference_S4R"] = dict(zip(("u_min", "v_max", "newton_iters"), PAPER_HEMISPHERE["reference_S4R"][:3]))
     return out
 
 
@@ -909,6 +943,7 @@ def main(argv=None):
             out["quasi_static"] = quasi_static(S, I, torch)
             out["quasi_static"]["linear_plate_sweep"] = linear_plate_sweep(S, I, torch)
             out["quasi_static"]["cantilever"] = cantilever(S, I, torch)
+            out["quasi_static"]["hemisphere"] = hemisphere_benchmark(S, I, torch)
     if not args.no_other_workloads and not args.hot_path_only and args.size == 1024:
         out["other_workloads"] = small_configs(S, I, torch)
         out["other_workloads"]["batch64"] = batch64_timing(S, I, torch, S.SHELL_PREC_MIXED, steps=3, warmup=1)

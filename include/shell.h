@@ -89,9 +89,12 @@ typedef struct {
  * D_m = h E_el (plane stress), energy A/2 eps^T D_m eps of the Green strain per triangle, on every
  * triangle of the mesh and for any model.  shell_eval_forces adds its force and energy (both precisions).
  * The implicit step takes it in float64, one simulation at a time: each Newton iteration assembles the
- * membrane's Gauss-Newton tangent A B(F)^T D_m B(F) (positive semi-definite; its Hessian at rest) into
- * 3x3 blocks, solves (M + dt^2 (K_s (x) I3 + K_GN)) y = -g by one Jacobi-PCG over all coordinates (the
- * membrane couples them; 1/(m + dt^2 (K_s,ii + tr(K_GN,ii)/3)) per vertex), then backtracks x += 2^-h y,
+ * membrane tangent K_m into 3x3 blocks (per triangle the Gauss-Newton part A B(F)^T D_m B(F) plus the
+ * stress part A (g_a^T S+ g_b) I3, S+ the positive semi-definite part of the 2x2 second Piola-Kirchhoff
+ * stress and g the shape-function gradients: the exact Hessian under tension, the Gauss-Newton tangent
+ * under compression, positive semi-definite always), solves (M + dt^2 (K_s (x) I3 + K_m)) y = -g by one
+ * Jacobi-PCG over all coordinates (the membrane couples them; 1/(m + dt^2 (K_s,ii + tr(K_m,ii)/3)) per
+ * vertex), then backtracks x += 2^-h y,
  * h the fewest halvings (at most 6) that satisfy Armijo's condition E(x + a y) <= E(x) + 1e-4 a g.y on
  * the incremental potential.  In its step statistics counts[k][0] is the PCG count and counts[k][1] the
  * halvings of Newton iteration k; REPLAY takes both from replay_counts the same way.  The quasi-static
@@ -291,8 +294,8 @@ shell_status_t shell_step_implicit(shell_sim_t sim, const shell_step_params_t* p
  * solves.  s = eps_u / ||dx||_inf when that is below one (the incremental displacement limit), else 1.
  * Plates are linear (f = -K (x - X)), so one solve is exact; the bending-only shells' in-plane modes
  * have no stiffness of their own, so their iteration stalls at a residual of second order in the load.
- * With SHELL_FLAG_MEMBRANE the residual includes the membrane and the matrix its Gauss-Newton tangent,
- * K_s (x) I3 + K_GN(x), solved by one coupled Jacobi-PCG (PCG count in counts[k][0]).
+ * With SHELL_FLAG_MEMBRANE the residual includes the membrane and the matrix its tangent,
+ * K_s (x) I3 + K_m(x), solved by one coupled Jacobi-PCG (PCG count in counts[k][0]).
  * The velocity and the step counter are not touched.  stats (host, may be NULL) as for the step:
  * grad_norm0 = ||r|| at the start, grad_norm = at the returned state.  Synchronises `stream`.
  * Errors: SHELL_E_INVALID_ARG, SHELL_E_BUDGET (a PCG column hit max_pcg; the state is still updated),
@@ -319,6 +322,17 @@ shell_status_t shell_sim_get_stats(shell_sim_t sim, shell_step_stats_t* out);
 /* host copies in caller order; x, v may be NULL; synchronises the simulation's last stream */
 shell_status_t shell_sim_get_state(shell_sim_t sim, double* x, double* v, int64_t* step);
 shell_status_t shell_sim_set_state(shell_sim_t sim, const double* x, const double* v, int64_t step);
+/*
+ * shell_sim_set_held - which coordinates of each vertex are held (kept at their current value by the
+ * step and the quasi-static solve): held host [nv] in caller order, bit c (1, 2, 4) holding coordinate
+ * c (x, y, z) of the vertex, 7 the whole vertex, as a symmetry plane holds the coordinate normal to it
+ * (the hemisphere benchmark of Sec. 6 holds x on the plane x = 0, y on y = 0 and z of two hole-rim
+ * vertices).  It replaces the set given to shell_sim_create (whose nonzero entries hold all three);
+ * NULL holds nothing.  A held coordinate's residual row is zero and its increment stays zero.  Takes
+ * effect at the next step or solve; synchronises the simulation's last stream.
+ * Errors: SHELL_E_INVALID_ARG (an entry above 7).
+ */
+shell_status_t shell_sim_set_held(shell_sim_t sim, const uint8_t* held);
 /* device views of the state in the library's internal order (for timing harnesses), may be NULL */
 shell_status_t shell_sim_device_state(shell_sim_t sim, double** x, double** v);
 

@@ -542,7 +542,7 @@ shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const do
                 xi[size_t(3 * i + c)] = x0[3 * u + c];
                 if (v0) vi[size_t(3 * i + c)] = v0[3 * u + c];
             }
-            if (pinned) pi[size_t(i)] = pinned[u] ? 1 : 0;
+            if (pinned) pi[size_t(i)] = pinned[u] ? 7 : 0;  // every coordinate held
         }
         hipStream_t s = nullptr;
         sim->x.upload(xi.data(), xi.size(), s);
@@ -700,6 +700,30 @@ shell_status_t shell_sim_set_state(shell_sim_t sim, const double* x, const doubl
             SHELL_HIP(hipDeviceSynchronize());
         }
         sim->step = step;
+        return SHELL_OK;
+    });
+}
+
+shell_status_t shell_sim_set_held(shell_sim_t sim, const uint8_t* held) {
+    return guarded([&]() -> shell_status_t {
+        SHELL_CHECK(sim, SHELL_E_INVALID_ARG, "null handle");
+        const int64_t nv = sim->nv;
+        const auto& perm = sim->st->perm;
+        std::vector<uint8_t> m(size_t(std::max<int64_t>(nv, 1)), 0);
+        bool partial = false;
+        for (int64_t i = 0; i < nv; ++i) {
+            const uint8_t b = held ? held[perm[size_t(i)]] : uint8_t(0);
+            SHELL_CHECK(b <= 7, SHELL_E_INVALID_ARG, "a held mask takes bits 0..2 only");
+            m[size_t(i)] = b;
+            partial = partial || (b != 0 && b != 7);
+        }
+        SHELL_HIP(hipStreamSynchronize(sim->last_stream));
+        if (nv > 0) {
+            sim->pinned.upload(m.data(), size_t(nv), nullptr);
+            SHELL_HIP(hipDeviceSynchronize());
+        }
+        sim->partial_held = partial;
+        sim->dinv_dt = -1.0;  // the preconditioner's fixed rows changed
         return SHELL_OK;
     });
 }

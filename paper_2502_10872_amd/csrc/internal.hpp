@@ -202,7 +202,7 @@ struct SolveDesc {
     void *f, *p0, *p1, *q, *dinv;   // float in mixed precision; p0/p1 alternate as the search direction
     float* z;                       // mixed precision only: z = D^-1 r as float (null in FP64: recomputed)
     const double *mass, *kdiag;
-    const uint8_t* pinned;
+    const uint8_t* pinned;          // held coordinates per vertex: bit c holds coordinate c, 7 the vertex
     void* mq;                       // the product's mass, in the vector precision; -1 on fixed rows
     const int32_t* scol;
     const void* val;                // SELL values, float in mixed precision
@@ -219,6 +219,7 @@ struct SolveDesc {
     int64_t nv, ngroups;
     double dt, dt2, grav[3], rtol2;
     int32_t replay, target[3];
+    int32_t partial_held;           // some vertex has only part of its coordinates held
 };
 
 struct WorkItem {
@@ -295,8 +296,8 @@ struct shell_hessian_s {
 
 
 namespace shell {
-// The implicit step of a shell with its membrane (SHELL_FLAG_MEMBRANE), float64: K_s as CSR, the membrane's
-// Gauss-Newton tangent as 3x3 blocks on the triangle adjacency, one PCG over all coordinates, line search.
+// The implicit step of a shell with its membrane (SHELL_FLAG_MEMBRANE), float64: K_s as CSR, the membrane
+// tangent as 3x3 blocks on the triangle adjacency, one PCG over all coordinates, line search.
 struct MembraneSolve {
     DevArray<int64_t> srow;  // K_s CSR (internal order)
     DevArray<int32_t> scol;
@@ -344,7 +345,8 @@ struct shell_sim_s {
     shell::DevArray<double> f;           // float64 forces (or float32 in mixed, sized in doubles)
     shell::DevArray<double> dinv;        // [nv] (float in mixed)
     shell::DevArray<double> mq;          // [nv] mass for the product, -1 on fixed rows (float in mixed)
-    shell::DevArray<uint8_t> pinned;
+    shell::DevArray<uint8_t> pinned;     // [nv] held coordinates: bit c holds coordinate c, 7 the vertex
+    bool partial_held = false;           // some vertex holds only part of its coordinates
     shell::DevArray<double> p, p2, q;    // PCG work vectors (float in mixed; sized in doubles)
     shell::DevArray<float> z;            // mixed only: the preconditioned residual, read by the product
     shell::DevArray<double> bins;        // PCG dot-product bins

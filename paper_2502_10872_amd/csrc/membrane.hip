@@ -117,10 +117,12 @@ __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __r
 // ---------------------------------------------------------------- implicit step with the membrane
 //
 // Sec. 5's step (eq 62) with the membrane of Sec. 3 added to the bending energy.  Each Newton iteration:
-// g = M (x - x_hat) - dt^2 f (fixed rows zero); the matrix M + dt^2 (K_s (x) I3 + K_GN(x)) with K_GN the
-// membrane's Gauss-Newton tangent A B(F)^T D_m B(F) per triangle (B(F) the linearised Green strain, rows
-// g_j0 F0^T, g_j1 F1^T, g_j1 F0^T + g_j0 F1^T), assembled into 3x3 blocks on the triangle adjacency; one
-// Jacobi-PCG over all coordinates (1/(m + dt^2 (K_s,ii + tr(K_GN,ii)/3)) per vertex); then x += 2^-h y
+// g = M (x - x_hat) - dt^2 f (held coordinates' rows zero); the matrix M + dt^2 (K_s (x) I3 + K_m(x)) with
+// K_m the membrane tangent per triangle: the Gauss-Newton part A B(F)^T D_m B(F) (B(F) the linearised
+// Green strain, rows g_j0 F0^T, g_j1 F1^T, g_j1 F0^T + g_j0 F1^T) plus the stress part A (g_a^T S+ g_b) I3
+// with S+ the positive semi-definite part of the 2x2 stress (the exact Hessian under tension, Gauss-Newton
+// under compression, PSD always), assembled into 3x3 blocks on the triangle adjacency; one
+// Jacobi-PCG over all coordinates (1/(m + dt^2 (K_s,ii + tr(K_m,ii)/3)) per vertex); then x += 2^-h y
 // with h the fewest halvings (at most 6) meeting Armijo's condition E(x + a y) <= E(x) + 1e-4 a g.y on the
 // incremental potential E = 1/2 (x - x_hat)^T M (x - x_hat) + dt^2 (Psi_b + Psi_m).  Sums are per
 // 256-thread block, then in a fixed order by one block, so they do not depend on scheduling.
@@ -156,7 +158,7 @@ __global__ void ms_predictor(double* __restrict__ x, const double* __restrict__ 
     const double gr[3] = {gx, gy, gz};
     for (int c = 0; c < 3; ++c) {
         const double xi = x[3 * i + c];
-        const double xh = pinned[i] ? xi : xi + dt * v[3 * i + c] + dt * dt * gr[c];
+        const double xh = (pinned[i] >> c & 1u) ? xi : xi + dt * v[3 * i + c] + dt * dt * gr[c];
         xt[3 * i + c] = xi;
         xhat[3 * i + c] = xh;
         x[3 * i + c] = xh;
@@ -214,7 +216,7 @@ __global__ __launch_bounds__(kMsBlk) void ms_grad(const double* __restrict__ x, 
     double v[1] = {0.0};
     if (i < nv)
         for (int c = 0; c < 3; ++c) {
-            const double gi = pinned[i] ? 0.0 : mass[i] * (x[3 * i + c] - xhat[3 * i + c]) - dt2 * f[3 * i + c];
+            const double gi = (pinned[i] >> c & 1u) ? 0.0 : mass[i] * (x[3 * i + c] - xhat[3 * i + c]) - dt2 * f[3 * i + c];
             g[3 * i + c] = gi;
             v[0] += gi * gi;
         }
@@ -246,9 +248,9 @@ __device__ __forceinline__ long ms_find(const int64_t* __restrict__ row, const i
     return lo;
 }
 
-// Gauss-Newton tangent of the membrane into the 3x3 blocks, one thread per vertex row: the thread walks
-// the row's triangles in ascending order and adds its corner's three blocks of each, so every block is
-// written by one thread in a fixed order (no atomics; the same state gives the same matrix bit for bit).
+// The membrane tangent into the 3x3 blocks, one thread per vertex row: the thread walks the row's
+// triangles in ascending order and adds its corner's three blocks of each, so every block is written by
+// one thread in a fixed order (no atomics; the same state gives the same matrix bit for bit).
 __global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict__ tris,
                       const int64_t* __restrict__ vtrow, const int32_t* __restrict__ vttri, long nv,
                       const double* __restrict__ x, double c, double nu, const int64_t* __restrict__ mrow,
@@ -281,6 +283,24 @@ __global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict
             DB[1][q] = c * (nu * Bm[0][q] + Bm[1][q]);
             DB[2][q] = c * 0.5 * (1.0 - nu) * Bm[2][q];
         }
+        // the stress and its positive semi-definite part from the principal values l1 >= l2
+        const double C00 = F[0][0] * F[0][0] + F[1][0] * F[1][0] + F[2][0] * F[2][0];
+        const double C11 = F[0][1] * F[0][1] + F[1][1] * F[1][1] + F[2][1] * F[2][1];
+        const double C01 = F[0][0] * F[0][1] + F[1][0] * F[1][1] + F[2][0] * F[2][1];
+        const double e0 = 0.5 * (C00 - 1.0), e1 = 0.5 * (C11 - 1.0);
+        const double s11 = c * (e0 + nu * e1), s22 = c * (nu * e0 + e1), s12 = c * 0.5 * (1.0 - nu) * C01;
+        const double mean = 0.5 * (s11 + s22), half = 0.5 * (s11 - s22);
+        const double rad = sqrt(half * half + s12 * s12);
+        const double l1 = mean + rad, l2 = mean - rad;
+        double P00 = s11, P01 = s12, P11 = s22;
+        if (l1 <= 0.0) {
+            P00 = P01 = P11 = 0.0;
+        } else if (l2 < 0.0) {
+            const double w = l1 / (l1 - l2);  // l1 v v^T with v v^T = (S - l2 I) / (l1 - l2)
+            P00 = w * (s11 - l2);
+            P01 = w * s12;
+            P11 = w * (s22 - l2);
+        }
         for (int b = 0; b < 3; ++b) {
             double* blk = mval + 9 * ms_find(mrow, mcol, r, int(v[b]));
             for (int ca = 0; ca < 3; ++ca)
@@ -288,6 +308,8 @@ __global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict
                     const int pa = 3 * a + ca, pb = 3 * b + cb;
                     blk[3 * ca + cb] += A * (Bm[0][pa] * DB[0][pb] + Bm[1][pa] * DB[1][pb] + Bm[2][pa] * DB[2][pb]);
                 }
+            const double gsg = g[a][0] * (P00 * g[b][0] + P01 * g[b][1]) + g[a][1] * (P01 * g[b][0] + P11 * g[b][1]);
+            for (int cc = 0; cc < 3; ++cc) blk[4 * cc] += A * gsg;
         }
     }
 }
@@ -299,7 +321,7 @@ __global__ void ms_dinv(const double* __restrict__ kdiag, const double* __restri
     if (i >= nv) return;
     const double* b = mval + 9 * mdiag[i];
     const double d = mass[i] + dt2 * (kdiag[i] + (b[0] + b[4] + b[8]) / 3.0);
-    dinv[i] = (pinned[i] || d == 0.0) ? 0.0 : 1.0 / d;
+    dinv[i] = ((pinned[i] & 7u) == 7u || d == 0.0) ? 0.0 : 1.0 / d;
 }
 
 // r = -g, y = 0, z = D^-1 r, p = z; partials r.z, r.r
@@ -345,7 +367,7 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__
 // product writes per-block partials of p.q, every block of the update sums them itself in the same fixed
 // order (so all blocks agree on alpha), and one block finishes the update's partials and the stop test.
 
-// p_new = z + beta p_old (row i, stored) and q = M p_new + dt^2 (K_s (x) I3 + K_GN) p_new, the neighbours'
+// p_new = z + beta p_old (row i, stored) and q = M p_new + dt^2 (K_s (x) I3 + K_m) p_new, the neighbours'
 // p_new formed on the fly from their z and p_old; fixed rows zero; partial p.q.  kMsRowLanes lanes share a
 // row: they take its K_s entries and its 3x3 blocks in turn (consecutive lanes read consecutive entries)
 // and combine their sums by shuffles; the row's first lane stores.
@@ -390,7 +412,7 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restri
         for (int c = 0; c < 3; ++c) {
             const double pi = z[3 * i + c] + be * pold[3 * i + c];
             pnew[3 * i + c] = pi;
-            const double qi = pinned[i] ? 0.0 : mass[i] * pi + dt2 * a[c];
+            const double qi = (pinned[i] >> c & 1u) ? 0.0 : mass[i] * pi + dt2 * a[c];
             q[3 * i + c] = qi;
             v[0] += pi * qi;
         }
@@ -592,7 +614,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->mdiag.alloc(std::max<size_t>(mdiag.size(), 1));
     ms->mdiag.upload(mdiag.data(), mdiag.size(), s);
     ms->mval.alloc(std::max<size_t>(9 * mcol.size(), 1));
-    // each vertex's triangles, ascending (the Gauss-Newton assembly's fixed order)
+    // each vertex's triangles, ascending (the tangent assembly's fixed order)
     std::vector<int64_t> vtrow(size_t(nv + 1), 0);
     for (long t = 0; t < 3 * nt; ++t) ++vtrow[size_t(st.h_tris[size_t(t)]) + 1];
     for (long i = 0; i < nv; ++i) vtrow[size_t(i + 1)] += vtrow[size_t(i)];
@@ -755,7 +777,7 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
             out.newton_capped = 1;
             break;
         }
-        // Gauss-Newton matrix and its Jacobi preconditioner
+        // the membrane tangent and the Jacobi preconditioner
         const long nb9 = long(m.mval.n);
         ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
         if (nt > 0)

@@ -143,12 +143,12 @@ __global__ __launch_bounds__(kBlk) void k_predictor(const SolveDesc* __restrict_
     const SolveDesc& d = descs[wi.mesh];
     long i = long(wi.unit) * kBlk + threadIdx.x;
     if (i >= d.nv) return;
-    bool pin = d.pinned[i];
+    const unsigned held = d.pinned[i];
     for (int c = 0; c < 3; ++c) {
         double xi = d.x[3 * i + c];
         d.xt[3 * i + c] = xi;
         // dt = 0 (the quasi-static solve): x_hat = x without reading the velocity
-        double xh = (pin || d.dt == 0.0) ? xi : xi + d.dt * d.v[3 * i + c] + d.dt * d.dt * d.grav[c];
+        double xh = ((held >> c & 1u) || d.dt == 0.0) ? xi : xi + d.dt * d.v[3 * i + c] + d.dt * d.dt * d.grav[c];
         d.xhat[3 * i + c] = xh;
         d.x[3 * i + c] = xh;
     }
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlk) void k_dinv(const SolveDesc* __restrict__ des
     const SolveDesc& d = descs[wi.mesh];
     long i = long(wi.unit) * kBlk + threadIdx.x;
     if (i >= d.nv) return;
-    const bool pin = d.pinned[i];
+    const bool pin = (d.pinned[i] & 7u) == 7u;  // every coordinate held
     const double den = d.mass[i] + d.dt2 * d.kdiag[i];  // zero only for a quasi-static row without stiffness
     static_cast<VR*>(d.dinv)[i] = (pin || den == 0.0) ? VR(0) : VR(1.0 / den);
     // the product reads one value per row for both the mass and the fixed flag
@@ -181,12 +181,12 @@ __global__ __launch_bounds__(kBlk) void k_residual(const SolveDesc* __restrict__
     long i = long(wi.unit) * kBlk + threadIdx.x;
     double acc[1] = {0.0};
     if (i < d.nv) {
-        bool pin = d.pinned[i];
+        const unsigned held = d.pinned[i];
         double m = d.mass[i];
         for (int c = 0; c < 3; ++c) {
             double fi = double(f[3 * i + c]);
             if (d.fext) fi += d.fext[3 * i + c];
-            double gi = pin ? 0.0 : m * (d.x[3 * i + c] - xh[3 * i + c]) - d.dt2 * fi;
+            double gi = (held >> c & 1u) ? 0.0 : m * (d.x[3 * i + c] - xh[3 * i + c]) - d.dt2 * fi;
             d.g[3 * i + c] = gi;
             acc[0] += gi * gi;
         }
@@ -394,6 +394,17 @@ __device__ __forceinline__ void row_product_direction(const SolveDesc& d, long r
 #define SHELL_PRODUCT_BATCH 8  // matrix entries per batch of the product's stream
 #endif
 
+// A vertex with some of its coordinates held: those coordinates' rows of q are zero (with the residual
+// zero there from the start, r, z, p and the increment then stay zero on them).  Vertices with every
+// coordinate held are the fixed rows of mq.
+template <typename VR>
+__device__ __forceinline__ void zero_held_rows(const SolveDesc& d, long i, VR (&qv)[3]) {
+    const unsigned held = G(d.pinned)[i];
+    if (held & 1u) qv[0] = VR(0);
+    if (held & 2u) qv[1] = VR(0);
+    if (held & 4u) qv[2] = VR(0);
+}
+
 // Unstaged product (row groups too wide for LDS): the same quantities with every neighbour's direction
 // formed from its own gathers.
 template <typename VR, typename MR>
@@ -415,6 +426,7 @@ __device__ __forceinline__ void product_direct(const SolveDesc& d, const WorkIte
         qv[1] = VR(fma(m, MR(pi[1]), dt2 * ay));
         qv[2] = VR(fma(m, MR(pi[2]), dt2 * az));
     }
+    if (d.partial_held) zero_held_rows(d, i, qv);
     gbl<VR>* q = G(static_cast<VR*>(d.q));
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
@@ -517,6 +529,7 @@ __device__ __forceinline__ void product_staged(const SolveDesc& d, const WorkIte
         qv[1] = VR(fma(m, MR(pi[1]), dt2 * ay));
         qv[2] = VR(fma(m, MR(pi[2]), dt2 * az));
     }
+    if (d.partial_held) zero_held_rows(d, i, qv);
     gbl<VR>* q = G(static_cast<VR*>(d.q));
 #pragma unroll
     for (int e = 0; e < 3; ++e) {

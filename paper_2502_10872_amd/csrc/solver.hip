@@ -334,6 +334,7 @@ SolveDesc solve_desc(shell_sim_s& sim, PcgState* st) {
     d.mass = sim.mass.p;
     d.kdiag = sim.h->kdiag.p;
     d.pinned = sim.pinned.p;
+    d.partial_held = sim.partial_held ? 1 : 0;
     d.scol = sim.h->scol.p;
     d.val = sim.st->precision == SHELL_PREC_MIXED ? static_cast<const void*>(sim.h->valf.p)
                                                    : static_cast<const void*>(sim.h->val.p);

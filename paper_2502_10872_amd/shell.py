@@ -100,6 +100,7 @@ EXPORTS = ("shell_build_stencils", "shell_stencils_info", "shell_stencils_export
            "shell_assemble_constant_hessian", "shell_hessian_export_csr", "shell_hessian_info",
            "shell_hessian_apply", "shell_sim_create",
            "shell_step_implicit", "shell_solve_static", "shell_sim_get_stats", "shell_sim_get_state", "shell_sim_set_state",
+           "shell_sim_set_held",
            "shell_sim_device_state", "shell_sim_time_kernels", "shell_batch_create", "shell_batch_step",
            "shell_batch_reset", "shell_sim_device_bytes", "shell_batch_profile", "shell_batch_profile_read",
            "shell_sim_profile", "shell_sim_profile_read",
@@ -132,6 +133,7 @@ def lib() -> ctypes.CDLL:
         L.shell_sim_get_stats.argtypes = [P, P]
         L.shell_sim_get_state.argtypes = [P, P, P, P]
         L.shell_sim_set_state.argtypes = [P, P, P, i64]
+        L.shell_sim_set_held.argtypes = [P, P]
         L.shell_sim_device_state.argtypes = [P, P, P]
         L.shell_sim_time_kernels.argtypes = [P, d, i32, P, P]
         L.shell_batch_create.argtypes = [P, i32, P]
@@ -355,6 +357,12 @@ def shell_sim_set_state(sim, x, v, step: int):
     _check(lib().shell_sim_set_state(sim, _np_ptr(x), _np_ptr(v), int(step)), "shell_sim_set_state")
 
 
+def shell_sim_set_held(sim, held):
+    """held: host [nv] in caller order, bit c holding coordinate c (7 the vertex), or None (nothing held)."""
+    held = None if held is None else np.ascontiguousarray(held, dtype=np.uint8)
+    _check(lib().shell_sim_set_held(sim, _np_ptr(held)), "shell_sim_set_held")
+
+
 def shell_sim_device_state(sim):
     x = ctypes.c_void_p()
     v = ctypes.c_void_p()
@@ -458,7 +466,7 @@ class Problem:
     """One mesh with its stencils, constant Hessian and (optionally) a simulation, freed together."""
 
     def __init__(self, mesh, material: dict, model=None, precision=SHELL_PREC_FP64, block_vertices=0, reorder=1,
-                 sim=True, flags=0, clamped_edges=None):
+                 sim=True, flags=0, clamped_edges=None, held=None):
         self.mesh = mesh
         self.nv = mesh.nv
         self.model = mesh.model if model is None else model
@@ -467,6 +475,10 @@ class Problem:
         self.info = shell_stencils_info(self.st)
         self.h = shell_assemble_constant_hessian(self.st)
         self.sim = shell_sim_create(self.st, self.h, mesh.X, None, mesh.pinned) if sim else None
+        if self.sim and held is not None:
+            # the mesh's pinned vertices hold every coordinate, `held` adds single coordinates
+            shell_sim_set_held(self.sim, np.where(np.asarray(mesh.pinned) != 0, 7, 0).astype(np.uint8)
+                               | (np.asarray(held, dtype=np.uint8) & 7))
 
     def close(self):
         if self.sim:

@@ -391,7 +391,7 @@ def test_membrane_forces_match_oracle(model):
 
 @pytest.mark.parametrize("model", ["SS", "FS", "ES"])
 def test_membrane_step_replay_matches_oracle(model):
-    """The implicit step with the membrane (Gauss-Newton tangent, coupled PCG, Armijo backtracking) on a
+    """The implicit step with the membrane (membrane tangent, coupled PCG, Armijo backtracking) on a
     cylinder patch held at its ends: two steps with the oracle's PCG counts and halvings replayed give the
     oracle's positions and velocities to 1e-10.  The membrane makes the system stiff, so two solvers
     stopped at the same count agree only to about the condition number times the residual they reached
@@ -489,7 +489,7 @@ def _cantilever(model, scale=1.0, nx=17, ny=3):
 @pytest.mark.parametrize("model", ["FS", "SP"])
 def test_static_membrane_cantilever_matches_oracle(model):
     """Quasi-static Newton-Raphson with the membrane on the Sec. 6 cantilever.  With no mass the matrix
-    K_s (x) I3 + K_GN spans the membrane's in-plane stiffness down to the softest bending mode, and
+    K_s (x) I3 + K_m spans the membrane's in-plane stiffness down to the softest bending mode, and
     finite-precision CG iterates part after a few iterations (against the exact recurrence: 7e-12 after
     one, 9e-5 after five, 0.8 after twenty), so replayed counts prove nothing here: every solve runs to
     rtol 1e-13.  The first solve equals a dense solve of the oracle's system; 12 solves under eps_u = 0.1

@@ -246,7 +246,7 @@ def test_checkpoint_resume_is_bitwise():
 
 def test_membrane_step_is_bitwise_reproducible():
     """The step with the membrane (float64) repeats to the bit: its force tiles accumulate exactly, the
-    Gauss-Newton blocks are summed per row and its dot products in fixed-order blocks."""
+    tangent blocks are summed per row and its dot products in fixed-order blocks."""
     mesh = I.workload_cylinder(48, "SS")
     params, _ = S.step_params(1 / 30, max_newton=3, pcg_rtol=1e-6)
     res = []
