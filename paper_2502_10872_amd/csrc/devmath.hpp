@@ -113,47 +113,67 @@ namespace shell {
 
 // Order-independent accumulation of the owner-computes tiles in LDS.  Floating-point atomics add in
 // whatever order the waves arrive, so their last bits would change from run to run.  Instead each
-// contribution v (in units of a per-mesh power-of-two force scale, so exactly rescaled) is held as two
-// integers: h, the count of 2^-20 nearest to v (int64), and q, the count of 2^-39 nearest to the rest
-// (int32, |q| <= 2^18), each added with its own integer LDS atomic (ds_add_u64, ds_add_u32; float32 LDS
-// atomics are slow here).  Integer sums do not depend on the order of the additions.  The total is
-// h 2^-20 + q 2^-39: what is dropped is below 2^-40 of the scale per contribution.  A contribution of
-// 2^36 or more (with 64 contributions per component the int64 sum stays below 2^62), or a non-finite one,
-// sets a flag on which the tile writes NaN, so that the state is reported as non-finite; with the scales
-// chosen per mesh that is some ten million times the force of a kink at the element scale.  LDS: 12
-// bytes per component and a flag.
-struct TileAcc {
+// contribution v (in units of a per-mesh power-of-two force scale, so exactly rescaled) is held in
+// integers whose sums do not depend on the order of the additions (integer LDS atomics; float32 LDS
+// atomics are slow here).  Float64 results (PARTS = 2): h, the count of 2^-20 nearest to v (int64, one
+// ds_add_u64), and q, the count of 2^-39 nearest to the rest (int32, |q| <= 2^18, one ds_add_u32); the
+// total h 2^-20 + q 2^-39 drops less than 2^-40 of the scale per contribution.  Float32 results
+// (PARTS = 1): h alone, counting 2^-26, which drops less than 2^-27 of the scale, that is 2^-39 of the
+// element's force unit (the scale is 2^-12 of k_b / l for bending, of E h l for the membrane), far below
+// the float32 rounding of such forces.  A count below 2^51 in magnitude (a contribution below 2^31 resp.
+// 2^25 times the scale, some 2^13 force units or more: nearly all of them) is rounded by one float64
+// addition of 1.5 2^52, which leaves the integer in the low mantissa bits; larger ones take the general
+// conversion.  A contribution of 2^56 counts or more (2^36 resp. 2^30 times the scale; with 64
+// contributions per component the int64 sum stays below 2^62), or a non-finite one, sets a flag on which
+// the tile writes NaN, so that the state is reported as non-finite.  LDS: 12 (PARTS = 2) or 8 bytes per
+// component, and a flag.
+template <int PARTS>
+struct TileAccT {
     long long* hi;
     int* lo;
     int* bad;
-    static constexpr double kMax = 0x1p36;
-    __host__ __device__ static constexpr size_t bytes(long n) { return size_t(36 * n + 16); }
-    __device__ __forceinline__ TileAcc(void* smem, long n)
+    static constexpr double kUnit = PARTS == 2 ? 0x1p20 : 0x1p26;  // counts of h per unit of the scale
+    __host__ __device__ static constexpr size_t bytes(long n) { return size_t((PARTS == 2 ? 36 : 24) * n + 16); }
+    __device__ __forceinline__ TileAccT(void* smem, long n)
         : hi(static_cast<long long*>(smem)), lo(reinterpret_cast<int*>(hi + 3 * n)),
-          bad(reinterpret_cast<int*>(lo + 3 * n)) {}
+          bad(PARTS == 2 ? reinterpret_cast<int*>(lo + 3 * n) : reinterpret_cast<int*>(hi + 3 * n)) {}
     // every thread of the work-group calls it
     __device__ __forceinline__ void clear(int n3) {
         for (int i = threadIdx.x; i < n3; i += blockDim.x) {
             hi[i] = 0;
-            lo[i] = 0;
+            if constexpr (PARTS == 2) lo[i] = 0;
         }
         if (threadIdx.x == 0) *bad = 0;
     }
-    __device__ __forceinline__ void add(int k, double v) {
-        if (!(fabs(v) < kMax)) {
+    // t: the contribution in counts of h, that is v * kUnit (an exact power-of-two rescaling)
+    __device__ __forceinline__ void add_counts(int k, double t) {
+        constexpr double kMagic = 0x1.8p52;
+        long long h;
+        double hd;  // h as a float64
+        if (fabs(t) < 0x1p51) {
+            const double tm = t + kMagic;  // t rounded to an integer (ties to even), held in the low bits
+            h = __double_as_longlong(tm) - __double_as_longlong(kMagic);
+            hd = tm - kMagic;
+        } else if (fabs(t) < 0x1p56) {
+            hd = rint(t);
+            h = static_cast<long long>(hd);
+        } else {
             *bad = 1;
             return;
         }
-        const double t = v * 0x1p20;  // exact (a power of two)
-        const double h = rint(t);
-        const int q = int(rint((t - h) * 0x1p19));  // t - h is exact, |t - h| <= 1/2
-        atomicAdd(reinterpret_cast<unsigned long long*>(hi + k), static_cast<unsigned long long>(static_cast<long long>(h)));
-        atomicAdd(lo + k, q);
+        atomicAdd(reinterpret_cast<unsigned long long*>(hi + k), static_cast<unsigned long long>(h));
+        if constexpr (PARTS == 2) {
+            const double rest = t - hd;  // exact, |rest| <= 1/2
+            atomicAdd(lo + k, int(static_cast<unsigned>(__double_as_longlong(fma(rest, 0x1p19, kMagic)))));
+        }
     }
     // the total in units of the scale, or NaN when a contribution was out of range (after a barrier)
     __device__ __forceinline__ double get(int k) const {
-        return *bad ? __builtin_nan("") : (double(hi[k]) + double(lo[k]) * 0x1p-19) * 0x1p-20;
+        if (*bad) return __builtin_nan("");
+        if constexpr (PARTS == 2) return (double(hi[k]) + double(lo[k]) * 0x1p-19) * 0x1p-20;
+        return double(hi[k]) * (1.0 / kUnit);
     }
 };
+using TileAcc = TileAccT<2>;
 
 }  // namespace shell

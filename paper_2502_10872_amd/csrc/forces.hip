@@ -163,11 +163,11 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // a stencil's force on an owned vertex into the tile's order-independent accumulator (both precisions)
-template <typename R>
-__device__ __forceinline__ void lds_add(TileAcc& acc, int slot, V3<R> v, double inv_scale) {
-    acc.add(3 * slot + 0, double(v.x) * inv_scale);
-    acc.add(3 * slot + 1, double(v.y) * inv_scale);
-    acc.add(3 * slot + 2, double(v.z) * inv_scale);
+template <typename R, typename Acc>
+__device__ __forceinline__ void lds_add(Acc& acc, int slot, V3<R> v, double counts_per_unit) {
+    acc.add_counts(3 * slot + 0, double(v.x) * counts_per_unit);
+    acc.add_counts(3 * slot + 1, double(v.y) * counts_per_unit);
+    acc.add_counts(3 * slot + 2, double(v.z) * counts_per_unit);
 }
 
 // Largest force work-group; the kernels are compiled for it, so any size up to it can be launched.
@@ -196,9 +196,10 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
     const long blk = wi.unit;
     const long base = blk * long(d.T);
     const int nown = int(min(long(d.T), d.nv - base));
-    TileAcc acc(smem_raw, d.T);
+    // float32 results take the one-part accumulator
+    TileAccT<MIX ? 1 : 2> acc(smem_raw, d.T);
     acc.clear(3 * nown);
-    const double inv_scale = 1.0 / d.fscale;  // a power of two: exact
+    const double inv_scale = acc.kUnit / d.fscale;  // counts per force unit, a power of two: exact
     __syncthreads();
     double e_own = 0.0;
     // a tile's list starts on a 64-stencil block and the work-group's stride is a whole number of
@@ -500,14 +501,13 @@ void launch_model(int precision, const ForceDesc* descs, const WorkItem* items, 
     static const int threads_d = force_threads(force_tiles<MODEL, double>);
     static const int threads_f = force_threads(force_tiles<MODEL, float>);
     const dim3 grid(unsigned(xcd_grid(nitems)));
-    const uint32_t lds = uint32_t(TileAcc::bytes(lds_T));
     // start/stop (may be null) receive the dispatch's own begin and end times
     if (precision == SHELL_PREC_FP64)
-        hipExtLaunchKernelGGL(force_tiles<MODEL, double>, grid, dim3(threads_d), lds, s, start, stop, 0, descs,
-                              items, nitems);
+        hipExtLaunchKernelGGL(force_tiles<MODEL, double>, grid, dim3(threads_d), uint32_t(TileAccT<2>::bytes(lds_T)),
+                              s, start, stop, 0, descs, items, nitems);
     else
-        hipExtLaunchKernelGGL(force_tiles<MODEL, float>, grid, dim3(threads_f), lds, s, start, stop, 0, descs,
-                              items, nitems);
+        hipExtLaunchKernelGGL(force_tiles<MODEL, float>, grid, dim3(threads_f), uint32_t(TileAccT<1>::bytes(lds_T)),
+                              s, start, stop, 0, descs, items, nitems);
     SHELL_HIP(hipGetLastError());
 }
 

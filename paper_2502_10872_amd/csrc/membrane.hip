@@ -72,9 +72,9 @@ __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __r
     const long blk = blockIdx.x;
     const long base = blk * long(T);
     const int nown = int(min(long(T), nv - base));
-    TileAcc acc(smem_raw, T);
+    TileAccT<sizeof(R) == 4 ? 1 : 2> acc(smem_raw, T);  // float32 results take the one-part accumulator
     acc.clear(3 * nown);
-    const double inv_scale = 1.0 / scale;  // a power of two: exact
+    const double inv_scale = acc.kUnit / scale;  // counts per force unit, a power of two: exact
     __syncthreads();
     double en[1] = {0.0};
     const long e0 = boff[2 * blk], e1 = boff[2 * blk + 1];
@@ -100,9 +100,9 @@ __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __r
         for (int i = 0; i < 3; ++i) {
             const double P0 = A * (F[i][0] * s0 + F[i][1] * s2), P1 = A * (F[i][0] * s2 + F[i][1] * s1);
             const double h0 = P0 * G[0][0] + P1 * G[0][1], h1 = P0 * G[1][0] + P1 * G[1][1];
-            if (o1 < unsigned(nown)) acc.add(3 * o1 + i, -h0 * inv_scale);
-            if (o2 < unsigned(nown)) acc.add(3 * o2 + i, -h1 * inv_scale);
-            if (o0 < unsigned(nown)) acc.add(3 * o0 + i, (h0 + h1) * inv_scale);
+            if (o1 < unsigned(nown)) acc.add_counts(3 * o1 + i, -h0 * inv_scale);
+            if (o2 < unsigned(nown)) acc.add_counts(3 * o2 + i, -h1 * inv_scale);
+            if (o0 < unsigned(nown)) acc.add_counts(3 * o0 + i, (h0 + h1) * inv_scale);
         }
     }
     __syncthreads();
@@ -541,14 +541,13 @@ void launch_membrane_rest(shell_stencils_s& st, hipStream_t s) {
 void launch_membrane_forces(shell_stencils_s& st, const double* pos, void* f, hipStream_t s) {
     if (st.nv == 0 || st.nblocks == 0) return;
     const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
-    const size_t lds = TileAcc::bytes(st.T);
     const unsigned grid = unsigned(st.nblocks);
     if (st.precision == SHELL_PREC_MIXED)
-        membrane_tiles<float><<<grid, kMembThreads, lds, s>>>(pos, st.mtid.p, st.mtrest.p, st.mboff.p,
+        membrane_tiles<float><<<grid, kMembThreads, TileAccT<1>::bytes(st.T), s>>>(pos, st.mtid.p, st.mtrest.p, st.mboff.p,
                                                               st.nv, st.T, c, st.poisson, st.mscale, static_cast<float*>(f),
                                                               st.mepart.p);
     else
-        membrane_tiles<double><<<grid, kMembThreads, lds, s>>>(pos, st.mtid.p, st.mtrest.p, st.mboff.p,
+        membrane_tiles<double><<<grid, kMembThreads, TileAccT<2>::bytes(st.T), s>>>(pos, st.mtid.p, st.mtrest.p, st.mboff.p,
                                                                st.nv, st.T, c, st.poisson, st.mscale, static_cast<double*>(f),
                                                                st.mepart.p);
     SHELL_HIP(hipGetLastError());
