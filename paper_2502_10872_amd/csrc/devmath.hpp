@@ -54,6 +54,28 @@ __device__ __forceinline__ V3<R> cvt(V3<S> a) {
     return {R(a.x), R(a.y), R(a.z)};
 }
 
+// 1/|a| for a nonzero vector: the hardware reciprocal square root estimate of |a|^2 (v_rsq), within
+// about one ulp in float32; in float64 (an estimate good to some 2^-23) refined by Newton-Raphson steps
+// y <- y + y (1 - s y^2) / 2, each of which squares the relative error: two reach float64 rounding, one
+// (STEPS = 1) some 2^-46.  A few instructions instead of a correctly rounded square root and division.
+__device__ __forceinline__ float inv_norm(V3<float> a) { return __builtin_amdgcn_rsqf(dot(a, a)); }
+template <int STEPS = 2>
+__device__ __forceinline__ double inv_norm(V3<double> a) {
+    const double s = dot(a, a);
+    double y = __builtin_amdgcn_rsq(s);
+#pragma unroll
+    for (int k = 0; k < STEPS; ++k) y = fma(0.5 * y, fma(-s * y, y, 1.0), y);
+    return y;
+}
+
+// 1/d for d != 0 in float64: the hardware reciprocal estimate (v_rcp, good to some 2^-23) refined by two
+// Newton-Raphson steps y <- y + y (1 - d y), each squaring the relative error, to float64 rounding.
+__device__ __forceinline__ double inv_fast(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+    y = fma(y, fma(-d, y, 1.0), y);
+    return fma(y, fma(-d, y, 1.0), y);
+}
+
 __device__ __forceinline__ V3<double> load3(const double* p, long i) {
     return {p[3 * i], p[3 * i + 1], p[3 * i + 2]};
 }
@@ -164,6 +186,17 @@ struct TileAccT {
         atomicAdd(reinterpret_cast<unsigned long long*>(hi + k), static_cast<unsigned long long>(h));
         if constexpr (PARTS == 2) {
             const double rest = t - hd;  // exact, |rest| <= 1/2
+            atomicAdd(lo + k, int(static_cast<unsigned>(__double_as_longlong(fma(rest, 0x1p19, kMagic)))));
+        }
+    }
+    // t with |t| < 2^51 known (a whole stencil's contributions tested at once): the rounding alone
+    __device__ __forceinline__ void add_counts_small(int k, double t) {
+        constexpr double kMagic = 0x1.8p52;
+        const double tm = t + kMagic;
+        atomicAdd(reinterpret_cast<unsigned long long*>(hi + k),
+                  static_cast<unsigned long long>(__double_as_longlong(tm) - __double_as_longlong(kMagic)));
+        if constexpr (PARTS == 2) {
+            const double rest = t - (tm - kMagic);
             atomicAdd(lo + k, int(static_cast<unsigned>(__double_as_longlong(fma(rest, 0x1p19, kMagic)))));
         }
     }

@@ -62,12 +62,12 @@ template <typename R>
 __device__ __forceinline__ EdgeFrame<R> edge_frame(V3<R> a, V3<R> c, V3<R> b) {
     EdgeFrame<R> e;
     const V3<R> ua = cross(c, a), ub = cross(b, c);
-    e.ila = R(1) / norm(ua);
-    e.ilb = R(1) / norm(ub);
+    e.ila = inv_norm(ua);
+    e.ilb = inv_norm(ub);
     e.na = e.ila * ua;
     e.nb = e.ilb * ub;
     const V3<R> m = e.na + e.nb;
-    e.ilm = R(1) / norm(m);
+    e.ilm = inv_norm(m);
     e.n = e.ilm * m;
     return e;
 }
@@ -146,7 +146,7 @@ struct Plane2 {
         g11 = dot(e1, e1);
         g12 = dot(e1, e2);
         g22 = dot(e2, e2);
-        idet = 1.0 / (g11 * g22 - g12 * g12);
+        idet = inv_fast(g11 * g22 - g12 * g12);
     }
     __device__ __forceinline__ void coords(V3<double> e1, V3<double> e2, V3<double> v, double& a, double& b) const {
         const double r1 = dot(e1, v), r2 = dot(e2, v);
@@ -163,11 +163,50 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // a stencil's force on an owned vertex into the tile's order-independent accumulator (both precisions)
-template <typename R, typename Acc>
-__device__ __forceinline__ void lds_add(Acc& acc, int slot, V3<R> v, double counts_per_unit) {
-    acc.add_counts(3 * slot + 0, double(v.x) * counts_per_unit);
-    acc.add_counts(3 * slot + 1, double(v.y) * counts_per_unit);
-    acc.add_counts(3 * slot + 2, double(v.z) * counts_per_unit);
+// A stencil's forces on the tile's own vertices into its order-independent accumulator (both
+// precisions).  HOIST: one range test for the whole stencil; when its largest component is below 2^51
+// counts (nearly always), each component is rounded by the accumulator's one-addition path, else by the
+// general one, which also flags values out of range.  Otherwise each component is tested on its own
+// (the triangle shells: the second copy of the loop costs them registers and is slower there).
+template <bool HOIST, int K, typename R, typename Acc>
+__device__ __forceinline__ void lds_add_stencil(Acc& acc, const int (&vid)[K], long base, int nown,
+                                                const V3<R> (&f)[K], double counts_per_unit) {
+    if constexpr (!HOIST) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const unsigned slot = unsigned(vid[j] - base);
+            if (slot < unsigned(nown)) {
+                acc.add_counts(3 * int(slot) + 0, double(f[j].x) * counts_per_unit);
+                acc.add_counts(3 * int(slot) + 1, double(f[j].y) * counts_per_unit);
+                acc.add_counts(3 * int(slot) + 2, double(f[j].z) * counts_per_unit);
+            }
+        }
+        return;
+    }
+    R m = R(0);
+#pragma unroll
+    for (int j = 0; j < K; ++j) m = fmax(m, fmax(fabs(f[j].x), fmax(fabs(f[j].y), fabs(f[j].z))));
+    if (double(m) * counts_per_unit < 0x1p51) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const unsigned slot = unsigned(vid[j] - base);
+            if (slot < unsigned(nown)) {
+                acc.add_counts_small(3 * int(slot) + 0, double(f[j].x) * counts_per_unit);
+                acc.add_counts_small(3 * int(slot) + 1, double(f[j].y) * counts_per_unit);
+                acc.add_counts_small(3 * int(slot) + 2, double(f[j].z) * counts_per_unit);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const unsigned slot = unsigned(vid[j] - base);
+            if (slot < unsigned(nown)) {
+                acc.add_counts(3 * int(slot) + 0, double(f[j].x) * counts_per_unit);
+                acc.add_counts(3 * int(slot) + 1, double(f[j].y) * counts_per_unit);
+                acc.add_counts(3 * int(slot) + 2, double(f[j].z) * counts_per_unit);
+            }
+        }
+    }
 }
 
 // Largest force work-group; the kernels are compiled for it, so any size up to it can be launched.
@@ -319,7 +358,7 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
                     // the float32 normal renormalised in float64: its length error would otherwise
                     // enter the heights along n, as kappa0 times eps_32
                     V3<double> nd = cvt<double>(fr.n);
-                    nd = (1.0 / norm(nd)) * nd;
+                    nd = inv_norm<1>(nd) * nd;
                     double dl = -in.k0[0];
                     dl = fma(double(L[0]), dot(dv[0], nd), dl);
                     dl = fma(double(L[2]), dot(dv[2], nd), dl);
@@ -377,7 +416,7 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
             R ilu = R(0);
             if constexpr (SHELL) {
                 const V3<R> u = cross(dd[1], dd[2]);
-                ilu = R(1) / norm(u);
+                ilu = inv_norm(u);
                 n = ilu * u;
             }
             if constexpr (MIX && !SHELL) {
@@ -418,7 +457,7 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
                         // the float32 normal renormalised in float64 (its length error would otherwise
                         // enter the heights along n, as kappa0 times eps_32)
                         V3<double> nd = cvt<double>(n);
-                        nd = (1.0 / norm(nd)) * nd;
+                        nd = inv_norm<1>(nd) * nd;
                         double h[6];
 #pragma unroll
                         for (int j = 1; j < 6; ++j) h[j] = dot(dv[j], nd);
@@ -439,11 +478,7 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
         }
         // the tile that owns vertex 1 of the stencil counts its energy
         if (unsigned(in.vid[0] - base) < unsigned(nown)) e_own += double(en);
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            unsigned slot = unsigned(in.vid[j] - base);
-            if (slot < unsigned(nown)) lds_add(acc, int(slot), fs[j], inv_scale);
-        }
+        lds_add_stencil<!(SHELL && !EDGE), K>(acc, in.vid, base, nown, fs, inv_scale);
     };
     const long e0 = d.boff[2 * blk], e1 = d.boff[2 * blk + 1];
     for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
