@@ -137,74 +137,84 @@ namespace shell {
 // whatever order the waves arrive, so their last bits would change from run to run.  Instead each
 // contribution v (in units of a per-mesh power-of-two force scale, so exactly rescaled) is held in
 // integers whose sums do not depend on the order of the additions (integer LDS atomics; float32 LDS
-// atomics are slow here).  Float64 results (PARTS = 2): h, the count of 2^-20 nearest to v (int64, one
-// ds_add_u64), and q, the count of 2^-39 nearest to the rest (int32, |q| <= 2^18, one ds_add_u32); the
-// total h 2^-20 + q 2^-39 drops less than 2^-40 of the scale per contribution.  Float32 results
-// (PARTS = 1): h alone, counting 2^-26, which drops less than 2^-27 of the scale, that is 2^-39 of the
-// element's force unit (the scale is 2^-12 of k_b / l for bending, of E h l for the membrane), far below
-// the float32 rounding of such forces.  A count below 2^51 in magnitude (a contribution below 2^31 resp.
-// 2^25 times the scale, some 2^13 force units or more: nearly all of them) is rounded by one float64
-// addition of 1.5 2^52, which leaves the integer in the low mantissa bits; larger ones take the general
-// conversion.  A contribution of 2^56 counts or more (2^36 resp. 2^30 times the scale; with 64
-// contributions per component the int64 sum stays below 2^62), or a non-finite one, sets a flag on which
-// the tile writes NaN, so that the state is reported as non-finite.  LDS: 12 (PARTS = 2) or 8 bytes per
-// component, and a flag.
+// atomics are slow here).  Per component an int64 h and an int32 c:
+//  - float64 results (PARTS = 2): h counts 2^-20 (the nearest count to v) and c counts 2^-39 (the nearest
+//    to the rest, |c| <= 2^18), two atomics per contribution (ds_add_u64, ds_add_u32); the total
+//    h 2^-20 + c 2^-39 drops less than 2^-40 of the scale per contribution;
+//  - float32 results (PARTS = 1): h counts 2^-26, one atomic per contribution, dropping less than 2^-27
+//    of the scale, that is 2^-39 of the element's force unit (the scale is 2^-12 of k_b / l for bending,
+//    of E h l for the membrane); a contribution of 2^25 times the scale or more (2^13 force units: the
+//    far states of an unconverged step, its predictor included, reach beyond 2^30 times the scale on the
+//    1M-vertex cap) puts its nearest multiple of 2^20 into c (counting 2^20) and the rest into h.
+// A count below 2^51 in magnitude is rounded by one float64 addition of 1.5 2^52, which leaves the
+// integer in the low mantissa bits.  A contribution of 2^36 times the scale or more (with 64
+// contributions per component the sums stay below 2^62 and 2^24), or a non-finite one, sets a flag on
+// which the tile writes NaN, so that the state is reported as non-finite.  LDS: 12 bytes per component
+// and a flag.
 template <int PARTS>
 struct TileAccT {
     long long* hi;
     int* lo;
     int* bad;
     static constexpr double kUnit = PARTS == 2 ? 0x1p20 : 0x1p26;  // counts of h per unit of the scale
-    __host__ __device__ static constexpr size_t bytes(long n) { return size_t((PARTS == 2 ? 36 : 24) * n + 16); }
+    static constexpr double kMax = 0x1p36;                          // largest contribution, in the scale
+    __host__ __device__ static constexpr size_t bytes(long n) { return size_t(36 * n + 16); }
     __device__ __forceinline__ TileAccT(void* smem, long n)
         : hi(static_cast<long long*>(smem)), lo(reinterpret_cast<int*>(hi + 3 * n)),
-          bad(PARTS == 2 ? reinterpret_cast<int*>(lo + 3 * n) : reinterpret_cast<int*>(hi + 3 * n)) {}
+          bad(reinterpret_cast<int*>(lo + 3 * n)) {}
     // every thread of the work-group calls it
     __device__ __forceinline__ void clear(int n3) {
         for (int i = threadIdx.x; i < n3; i += blockDim.x) {
             hi[i] = 0;
-            if constexpr (PARTS == 2) lo[i] = 0;
+            lo[i] = 0;
         }
         if (threadIdx.x == 0) *bad = 0;
     }
-    // t: the contribution in counts of h, that is v * kUnit (an exact power-of-two rescaling)
-    __device__ __forceinline__ void add_counts(int k, double t) {
-        constexpr double kMagic = 0x1.8p52;
-        long long h;
-        double hd;  // h as a float64
-        if (fabs(t) < 0x1p51) {
-            const double tm = t + kMagic;  // t rounded to an integer (ties to even), held in the low bits
-            h = __double_as_longlong(tm) - __double_as_longlong(kMagic);
-            hd = tm - kMagic;
-        } else if (fabs(t) < 0x1p56) {
-            hd = rint(t);
-            h = static_cast<long long>(hd);
-        } else {
-            *bad = 1;
-            return;
-        }
-        atomicAdd(reinterpret_cast<unsigned long long*>(hi + k), static_cast<unsigned long long>(h));
-        if constexpr (PARTS == 2) {
-            const double rest = t - hd;  // exact, |rest| <= 1/2
-            atomicAdd(lo + k, int(static_cast<unsigned>(__double_as_longlong(fma(rest, 0x1p19, kMagic)))));
-        }
+    static constexpr double kMagic = 0x1.8p52;
+    // the nearest integer to t, |t| < 2^51, as an int64 (one float64 addition) and as a float64
+    __device__ __forceinline__ static long long round_small(double t, double& td) {
+        const double tm = t + kMagic;
+        td = tm - kMagic;
+        return __double_as_longlong(tm) - __double_as_longlong(kMagic);
     }
     // t with |t| < 2^51 known (a whole stencil's contributions tested at once): the rounding alone
     __device__ __forceinline__ void add_counts_small(int k, double t) {
-        constexpr double kMagic = 0x1.8p52;
-        const double tm = t + kMagic;
-        atomicAdd(reinterpret_cast<unsigned long long*>(hi + k),
-                  static_cast<unsigned long long>(__double_as_longlong(tm) - __double_as_longlong(kMagic)));
+        double td;
+        const long long h = round_small(t, td);
+        atomicAdd(reinterpret_cast<unsigned long long*>(hi + k), static_cast<unsigned long long>(h));
         if constexpr (PARTS == 2) {
-            const double rest = t - (tm - kMagic);
-            atomicAdd(lo + k, int(static_cast<unsigned>(__double_as_longlong(fma(rest, 0x1p19, kMagic)))));
+            double cd;
+            atomicAdd(lo + k, int(round_small((t - td) * 0x1p19, cd)));  // t - td exact, |t - td| <= 1/2
+        }
+    }
+    // t: the contribution in counts of h, that is v * kUnit (an exact power-of-two rescaling)
+    __device__ __forceinline__ void add_counts(int k, double t) {
+        if (fabs(t) < 0x1p51) {
+            add_counts_small(k, t);
+            return;
+        }
+        if (!(fabs(t) < kMax * kUnit)) {
+            *bad = 1;
+            return;
+        }
+        if constexpr (PARTS == 2) {
+            const double td = rint(t);
+            atomicAdd(reinterpret_cast<unsigned long long*>(hi + k),
+                      static_cast<unsigned long long>(static_cast<long long>(td)));
+            double cd;
+            atomicAdd(lo + k, int(round_small((t - td) * 0x1p19, cd)));
+        } else {
+            double cd;
+            const int c = int(round_small(t * (0x1p-20 / kUnit), cd));  // multiples of 2^20 of the scale
+            add_counts_small(k, fma(-cd, 0x1p20 * kUnit, t));            // the rest: exact, below 2^46
+            atomicAdd(lo + k, c);
         }
     }
     // the total in units of the scale, or NaN when a contribution was out of range (after a barrier)
     __device__ __forceinline__ double get(int k) const {
         if (*bad) return __builtin_nan("");
         if constexpr (PARTS == 2) return (double(hi[k]) + double(lo[k]) * 0x1p-19) * 0x1p-20;
-        return double(hi[k]) * (1.0 / kUnit);
+        return double(hi[k]) * (1.0 / kUnit) + double(lo[k]) * 0x1p20;
     }
 };
 using TileAcc = TileAccT<2>;

@@ -149,7 +149,9 @@ def test_forces_under_rigid_motions(model, flags, precision):
     Mixed: amplitude side/10^4 and a translation of several metres, bound 2e-6 (observed 1e-7 to 5.5e-7,
     the float32 rounding of the stencils' deformation: the plates remove the affine part of each stencil in
     float64, the shells take the bending strain from float64 heights over a float64-renormalised normal;
-    the bounds of the unrotated smooth-deformation test were 1e-4 and 5e-4).  Float64: 1e-10 at amplitude
+    the bounds of the unrotated smooth-deformation test were 1e-4 and 5e-4; rounding each contribution to
+    2^-20 of the force scale in the tile accumulation would alone give 3e-6 to 1.7e-5 at forces this
+    small, which is why float32 results count 2^-26).  Float64: 1e-10 at amplitude
     side/10 and
     a translation below a metre.  (The force of a smooth field is a fourth derivative, so small against
     the stencil-scale rounding of the positions that at side/10^4 and 3 m any two float64 evaluations
