@@ -249,10 +249,20 @@ def membrane_timing(S, I, torch, reps=20):
     return out
 
 
-def membrane_step_timing(S, I, torch, sizes=(64, 256), steps=2):
+def membrane_product_bytes(nv, nnz_s, nnz_m):
+    """Algorithmic bytes of one coupled product launch (FP64): K_s as CSR (row offsets 8 B, column 4 B and
+    value 8 B per entry), the membrane tangent's 3x3 blocks (row offsets, column 4 B and 72 B of values
+    per block), the mass and the held mask, z and the previous direction read once, the new direction and
+    q written once."""
+    return 16 * (nv + 1) + 12 * nnz_s + 76 * nnz_m + nv * (8 + 1 + 48 + 48)
+
+
+def membrane_step_timing(S, I, torch, sizes=(64, 256, 1024), steps=2):
     """The implicit step of the smoothed-hinge shell with its membrane (FP64; the membrane tangent,
     coupled Jacobi-PCG, Armijo backtracking) on a cylinder patch of radius 0.5 m held at its ends, dt = 1/30,
-    Newton budget 4, PCG rtol 1e-2 (the headline step's settings): time per step and its iteration counts."""
+    Newton budget 4, PCG rtol 1e-2 (the headline step's settings): time per step and its iteration counts,
+    then the coupled product and update launched back to back (shell_sim_time_kernels) with the
+    product's fraction of the HBM peak on its algorithmic bytes."""
     out = {}
     for n in sizes:
         mesh = I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
@@ -265,13 +275,25 @@ def membrane_step_timing(S, I, torch, sizes=(64, 256), steps=2):
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
         pcg = sum(st["pcg_total"] for st in stats)
+        kt = S.shell_sim_time_kernels(pb.sim, 1 / 30, reps=10)
+        nnz_s = S.shell_hessian_info(pb.h)["nnz"]
+        t = np.sort(mesh.tris, axis=1)
+        edges = np.unique(np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [0, 2]]]), axis=0)
+        nnz_m = mesh.nv + 2 * len(edges)
+        pbytes = membrane_product_bytes(mesh.nv, nnz_s, nnz_m)
+        gbs = pbytes / (kt["spmv_ms"] * 1e-3) / 1e9 if kt["spmv_ms"] else None
         out[f"SS_membrane_cylinder_{n}"] = dict(
-            nv=mesh.nv, ms_per_step=ms, newton_per_step=sum(st["newton_iters"] for st in stats) / steps,
+            nv=mesh.nv, steps_per_s=1e3 / ms, ms_per_step=ms,
+            newton_per_step=sum(st["newton_iters"] for st in stats) / steps,
             pcg_per_step=pcg / steps, us_per_pcg_iteration=ms * 1e3 * steps / max(pcg, 1),
             halvings=[int(c[1]) for st in stats for c in st["counts"]],
-            grad_ratio=[st["grad_norm"] / max(st["grad_norm0"], 1e-300) for st in stats])
+            grad_ratio=[st["grad_norm"] / max(st["grad_norm0"], 1e-300) for st in stats],
+            back_to_back_ms=dict(force=kt["force_ms"], product=kt["spmv_ms"], update=kt["update_ms"]),
+            product=dict(kernel="ms_iter_product", bytes_per_launch=pbytes, achieved_gbs=gbs,
+                         frac=gbs / HBM_PEAK_GBS if gbs else None, nnz_s=nnz_s, blocks=nnz_m))
         pb.close()
-    print("[bench] membrane step timing done", file=sys.stderr, flush=True)
+        print(f"[bench] membrane step {n}: {ms:.1f} ms/step, product {1e3 * kt['spmv_ms']:.1f} us", file=sys.stderr,
+              flush=True)
     return out
 
 
@@ -428,8 +450,8 @@ def run_membrane(args):
     S.lib()
     forces = membrane_timing(S, I, torch)
     steps = membrane_step_timing(S, I, torch)
-    print(json.dumps(dict(metric="implicit steps/s with the membrane (SS, 256x256 cylinder, FP64)",
-                          value=1e3 / steps["SS_membrane_cylinder_256"]["ms_per_step"], unit="steps/s",
+    print(json.dumps(dict(metric="implicit steps/s with the membrane (SS, 1024x1024 cylinder, FP64)",
+                          value=1e3 / steps["SS_membrane_cylinder_1024"]["ms_per_step"], unit="steps/s",
                           higher_is_better=True, n_gpus=1, data="synthetic", membrane_forces=forces,
                           membrane_step=steps)), flush=True)
 

@@ -364,13 +364,16 @@ void shell_destroy_batch(shell_batch_t batch);
 /*
  * shell_sim_time_kernels - timing harness: average duration of one launch of each hot kernel of the
  * step, measured with HIP events on `stream` over `reps` back-to-back launches on the simulation's
- * current state (forces at x, then the three PCG kernels on a freshly initialised recurrence).  The
- * position and velocity are not modified; the solver's work vectors are.  Synchronises `stream`.
+ * current state (forces at x, then the PCG kernels on a freshly initialised recurrence).  The position
+ * and velocity are not modified; the solver's work vectors are.  Synchronises `stream`.  For a
+ * simulation with the membrane: the bending and membrane force tiles, the coupled product (with the
+ * membrane tangent at x) and its update.
  */
 typedef struct {
-    double force_ms;      /* bending force kernel over all stencils (internal vertex order; mixed: without
-                             the pass that writes the displacements from the rest shape) */
-    double spmv_ms;       /* PCG direction update p = D^-1 r + beta p and product q = (M + dt^2 K_s) p */
+    double force_ms;      /* force kernels over all stencils (internal vertex order); with the membrane,
+                             bending and membrane tiles together */
+    double spmv_ms;       /* PCG direction update p = D^-1 r + beta p and product q = (M + dt^2 K_s) p
+                             (with the membrane: + dt^2 K_m p, coordinates coupled) */
     double update_ms;     /* PCG y/r update with its dot products */
     double direction_ms;  /* always 0: the direction update is part of the product kernel */
     int32_t reps;

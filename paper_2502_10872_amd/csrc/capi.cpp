@@ -742,7 +742,10 @@ shell_status_t shell_sim_time_kernels(shell_sim_t sim, double dt, int32_t reps, 
     return guarded([&]() -> shell_status_t {
         SHELL_CHECK(sim && out && reps > 0 && dt > 0, SHELL_E_INVALID_ARG, "bad argument");
         std::memset(out, 0, sizeof(*out));
-        if (sim->solo) batch_time_kernels(*sim->solo, dt, reps, *out, as_stream(stream));
+        if (sim->ms)
+            membrane_time_kernels(*sim, dt, reps, *out, as_stream(stream));
+        else if (sim->solo)
+            batch_time_kernels(*sim->solo, dt, reps, *out, as_stream(stream));
         return SHELL_OK;
     });
 }

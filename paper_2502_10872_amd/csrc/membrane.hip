@@ -363,9 +363,10 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__
     }
 }
 
-// The coupled PCG iteration in three kernels, none with cross-block synchronisation inside it: the
-// product writes per-block partials of p.q, every block of the update sums them itself in the same fixed
-// order (so all blocks agree on alpha), and one block finishes the update's partials and the stop test.
+// The coupled PCG iteration in four kernels, none with cross-block synchronisation inside it: the
+// product writes per-work-group partials of p.q, one work-group sums them in a fixed order into alpha,
+// the update reads alpha, and one work-group finishes the update's partials and the stop test.  The
+// product and the update stride over the rows with at most kMsPartMax work-groups.
 
 // p_new = z + beta p_old (row i, stored) and q = M p_new + dt^2 (K_s (x) I3 + K_m) p_new, the neighbours'
 // p_new formed on the fly from their z and p_old; fixed rows zero; partial p.q.  kMsRowLanes lanes share a
@@ -373,8 +374,14 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__
 // and combine their sums by shuffles; the row's first lane stores.
 constexpr int kMsRowLanes = 16;
 constexpr int kMsRowsPerBlk = kMsBlk / kMsRowLanes;
+// The product and the update stride over the rows with at most kMsPartMax work-groups, so that one
+// work-group sums their partials in a fixed order in a few microseconds at any mesh size.
+constexpr long kMsPartMax = 2048;
 inline unsigned ms_product_grid(long nv) {
-    return unsigned(std::max(1L, (nv + kMsRowsPerBlk - 1) / kMsRowsPerBlk));
+    return unsigned(std::min(kMsPartMax, std::max(1L, (nv + kMsRowsPerBlk - 1) / kMsRowsPerBlk)));
+}
+inline unsigned ms_update_grid(long nv) {
+    return unsigned(std::min(kMsPartMax, std::max(1L, (nv + kMsBlk - 1) / kMsBlk)));
 }
 
 __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restrict__ scal,
@@ -388,8 +395,10 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restri
                                                           double* __restrict__ ppart, long npart) {
     if (scal[S_ACTIVE] == 0.0) return;
     const double be = scal[S_BETA];
-    const long i = blockIdx.x * long(kMsRowsPerBlk) + threadIdx.x / kMsRowLanes;
     const int lane = threadIdx.x % kMsRowLanes;
+    double v[1] = {0.0};
+    for (long i = blockIdx.x * long(kMsRowsPerBlk) + threadIdx.x / kMsRowLanes; i - threadIdx.x / kMsRowLanes < nv;
+         i += long(gridDim.x) * kMsRowsPerBlk) {
     double a[3] = {0.0, 0.0, 0.0};
     if (i < nv) {
         for (long e = srow[i] + lane; e < srow[i + 1]; e += kMsRowLanes) {
@@ -407,7 +416,6 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restri
     }
     for (int off = kMsRowLanes / 2; off > 0; off >>= 1)
         for (int c = 0; c < 3; ++c) a[c] += __shfl_xor(a[c], off, kMsRowLanes);
-    double v[1] = {0.0};
     if (i < nv && lane == 0)
         for (int c = 0; c < 3; ++c) {
             const double pi = z[3 * i + c] + be * pold[3 * i + c];
@@ -416,32 +424,32 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restri
             q[3 * i + c] = qi;
             v[0] += pi * qi;
         }
+    }
     ms_partials<1>(v, ppart, npart);
 }
 
-// alpha = r.z / p.q from the product's partials (summed by every block alike); y += alpha p,
-// r -= alpha q, z = D^-1 r; partials r.z and r.r
-__global__ __launch_bounds__(kMsBlk) void ms_iter_update(double* __restrict__ scal, const double* __restrict__ ppart,
-                                                         long npart, const double* __restrict__ p, const double* __restrict__ q,
-                                                         const double* __restrict__ dinv, double* __restrict__ y,
-                                                         double* __restrict__ r, double* __restrict__ z, long nv,
-                                                         double* __restrict__ part, long ngroups) {
+// p.q from the product's partials (one work-group, fixed order), then alpha = r.z / p.q
+__global__ __launch_bounds__(kMsBlk) void ms_iter_alpha(const double* __restrict__ ppart, long npart,
+                                                        double* __restrict__ scal) {
     if (scal[S_ACTIVE] == 0.0) return;
-    __shared__ double alpha;
     double pq[1];
     ms_totals<1>(ppart, npart, pq);
     if (threadIdx.x == 0) {
-        alpha = pq[0] != 0.0 ? scal[S_RZ] / pq[0] : 0.0;
-        if (blockIdx.x == 0) {
-            scal[S_PQ] = pq[0];
-            scal[S_ALPHA] = alpha;
-        }
+        scal[S_PQ] = pq[0];
+        scal[S_ALPHA] = pq[0] != 0.0 ? scal[S_RZ] / pq[0] : 0.0;
     }
-    __syncthreads();
-    const double al = alpha;
-    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+}
+
+// y += alpha p, r -= alpha q, z = D^-1 r (alpha from ms_iter_alpha); partials r.z and r.r
+__global__ __launch_bounds__(kMsBlk) void ms_iter_update(const double* __restrict__ scal, const double* __restrict__ p,
+                                                         const double* __restrict__ q, const double* __restrict__ dinv,
+                                                         double* __restrict__ y, double* __restrict__ r,
+                                                         double* __restrict__ z, long nv, double* __restrict__ part,
+                                                         long ngroups) {
+    if (scal[S_ACTIVE] == 0.0) return;
+    const double al = scal[S_ALPHA];
     double v[2] = {0.0, 0.0};
-    if (i < nv)
+    for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < nv; i += long(gridDim.x) * blockDim.x)
         for (int c = 0; c < 3; ++c) {
             y[3 * i + c] += al * p[3 * i + c];
             const double ri = r[3 * i + c] - al * q[3 * i + c], zi = dinv[i] * ri;
@@ -677,11 +685,12 @@ static void pcg_iteration(MembraneSolve& m, const double* mass, const uint8_t* p
     double* pold = m.pswap ? m.p2.p : m.p.p;
     double* pnew = m.pswap ? m.p.p : m.p2.p;
     const unsigned pg = ms_product_grid(nv);
+    const unsigned ug = ms_update_grid(nv);
     ms_iter_product<<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p, m.mval.p, mass,
                                           pinned, m.z.p, pold, pnew, m.q.p, nv, dt2, m.ppart.p, long(pg));
-    ms_iter_update<<<ms_grid(nv), kMsBlk, 0, s>>>(m.scal.p, m.ppart.p, long(pg), pnew, m.q.p, m.dinv.p, m.y.p, m.r.p,
-                                                  m.z.p, nv, m.part.p, m.ngroups);
-    ms_iter_finish<<<1, kMsBlk, 0, s>>>(m.part.p, m.ngroups, m.scal.p);
+    ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, long(pg), m.scal.p);
+    ms_iter_update<<<ug, kMsBlk, 0, s>>>(m.scal.p, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p, long(ug));
+    ms_iter_finish<<<1, kMsBlk, 0, s>>>(m.part.p, long(ug), m.scal.p);
     m.pswap = !m.pswap;
 }
 
@@ -934,6 +943,64 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
     sim.stats = out;
     sim.last_stream = s;
     return shell_status_t(out.status);
+}
+
+// Timing harness of the step with the membrane: the force evaluation (bending and membrane tiles), the
+// coupled product and the update, each launched `reps` times back to back with HIP events on `s`, on the
+// tangent at the current positions and a recurrence started from the force there (every kernel active).
+// The positions and velocities are not changed; the solver's work vectors are.
+void membrane_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {
+    shell_stencils_s& st = *sim.st;
+    MembraneSolve& m = *sim.ms;
+    const long nv = sim.nv, n3 = 3 * nv, nt = st.nt, ng = m.ngroups;
+    const double dt2 = dt * dt;
+    const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
+    hipEvent_t e0, e1;
+    SHELL_HIP(hipEventCreate(&e0));
+    SHELL_HIP(hipEventCreate(&e1));
+    auto elapsed = [&]() {
+        SHELL_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        SHELL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        return double(ms) / reps;
+    };
+    SHELL_HIP(hipMemcpyAsync(m.xtry.p, sim.x.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    SHELL_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k) {
+        launch_force_items(st.model, SHELL_PREC_FP64, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
+        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s);
+    }
+    SHELL_HIP(hipEventRecord(e1, s));
+    out.force_ms = elapsed();
+    const long nb9 = long(m.mval.n);
+    ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
+    if (nt > 0)
+        ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, sim.x.p, c, st.poisson,
+                                             m.mrow.p, m.mcol.p, m.mval.p);
+    ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.mass.p, sim.pinned.p, nv, dt2,
+                                           m.dinv.p);
+    ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(m.ftry.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, m.part.p, ng);
+    ms_fin_init<<<1, kMsBlk, 0, s>>>(m.part.p, ng, m.scal.p, 0.0, 1 << 30, 1);
+    const unsigned pg = ms_product_grid(nv), ug = ms_update_grid(nv);
+    SHELL_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k)
+        ms_iter_product<<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p, m.mval.p,
+                                              sim.mass.p, sim.pinned.p, m.z.p, m.p.p, m.p2.p, m.q.p, nv, dt2,
+                                              m.ppart.p, long(pg));
+    SHELL_HIP(hipEventRecord(e1, s));
+    out.spmv_ms = elapsed();
+    ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, long(pg), m.scal.p);
+    SHELL_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < reps; ++k)
+        ms_iter_update<<<ug, kMsBlk, 0, s>>>(m.scal.p, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p,
+                                             long(ug));
+    SHELL_HIP(hipEventRecord(e1, s));
+    out.update_ms = elapsed();
+    SHELL_HIP(hipGetLastError());
+    out.reps = reps;
+    SHELL_HIP(hipEventDestroy(e0));
+    SHELL_HIP(hipEventDestroy(e1));
+    m.pswap = false;
 }
 
 }  // namespace shell
