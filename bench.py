@@ -249,24 +249,26 @@ def membrane_timing(S, I, torch, reps=20):
     return out
 
 
-def membrane_product_bytes(nv, nnz_s, nnz_m):
-    """Algorithmic bytes of one coupled product launch (FP64): K_s as CSR (row offsets 8 B, column 4 B and
-    value 8 B per entry), the membrane tangent's 3x3 blocks (row offsets, column 4 B and 72 B of values
-    per block), the mass and the held mask, z and the previous direction read once, the new direction and
-    q written once."""
-    return 16 * (nv + 1) + 12 * nnz_s + 76 * nnz_m + nv * (8 + 1 + 48 + 48)
+def membrane_product_bytes(nv, nnz_s, nnz_m, mixed=False):
+    """Algorithmic bytes of one coupled product launch: K_s as CSR (row offsets 8 B, column 4 B and a value
+    per entry), the membrane tangent's 3x3 blocks (row offsets, column 4 B and nine values per block), the
+    values float64 (float32 in mixed precision), the mass and the held mask, z and the previous direction
+    read once, the new direction and q written once (float64 vectors in both precisions)."""
+    real = 4 if mixed else 8
+    return 16 * (nv + 1) + (4 + real) * nnz_s + (4 + 9 * real) * nnz_m + nv * (8 + 1 + 48 + 48)
 
 
 def membrane_step_timing(S, I, torch, sizes=(64, 256, 1024), steps=2):
-    """The implicit step of the smoothed-hinge shell with its membrane (FP64; the membrane tangent,
-    coupled Jacobi-PCG, Armijo backtracking) on a cylinder patch of radius 0.5 m held at its ends, dt = 1/30,
-    Newton budget 4, PCG rtol 1e-2 (the headline step's settings): time per step and its iteration counts,
-    then the coupled product and update launched back to back (shell_sim_time_kernels) with the
-    product's fraction of the HBM peak on its algorithmic bytes."""
+    """The implicit step of the smoothed-hinge shell with its membrane (the membrane tangent, coupled
+    Jacobi-PCG, Armijo backtracking) on a cylinder patch of radius 0.5 m held at its ends, dt = 1/30,
+    Newton budget 4, PCG rtol 1e-2 (the headline step's settings), FP64 and mixed: time per step and its
+    iteration counts, then the coupled product and update launched back to back (shell_sim_time_kernels)
+    with the product's fraction of the HBM peak on its algorithmic bytes."""
     out = {}
-    for n in sizes:
+    for n, prec in [(n, p) for n in sizes for p in (S.SHELL_PREC_FP64, S.SHELL_PREC_MIXED)]:
+        mixed = prec == S.SHELL_PREC_MIXED
         mesh = I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
-        pb = S.Problem(mesh, I.MATERIAL, model="SS", flags=S.SHELL_FLAG_MEMBRANE)
+        pb = S.Problem(mesh, I.MATERIAL, model="SS", precision=prec, flags=S.SHELL_FLAG_MEMBRANE)
         params, _ = S.step_params(1 / 30, max_newton=4, newton_rtol=1e-8, pcg_rtol=1e-2)
         S.shell_step_implicit(pb.sim, params)  # warm-up
         torch.cuda.synchronize()
@@ -280,9 +282,9 @@ def membrane_step_timing(S, I, torch, sizes=(64, 256, 1024), steps=2):
         t = np.sort(mesh.tris, axis=1)
         edges = np.unique(np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [0, 2]]]), axis=0)
         nnz_m = mesh.nv + 2 * len(edges)
-        pbytes = membrane_product_bytes(mesh.nv, nnz_s, nnz_m)
+        pbytes = membrane_product_bytes(mesh.nv, nnz_s, nnz_m, mixed)
         gbs = pbytes / (kt["spmv_ms"] * 1e-3) / 1e9 if kt["spmv_ms"] else None
-        out[f"SS_membrane_cylinder_{n}"] = dict(
+        out[f"SS_membrane_cylinder_{n}" + ("_mixed" if mixed else "")] = dict(
             nv=mesh.nv, steps_per_s=1e3 / ms, ms_per_step=ms,
             newton_per_step=sum(st["newton_iters"] for st in stats) / steps,
             pcg_per_step=pcg / steps, us_per_pcg_iteration=ms * 1e3 * steps / max(pcg, 1),
@@ -292,8 +294,8 @@ def membrane_step_timing(S, I, torch, sizes=(64, 256, 1024), steps=2):
             product=dict(kernel="ms_iter_product", bytes_per_launch=pbytes, achieved_gbs=gbs,
                          frac=gbs / HBM_PEAK_GBS if gbs else None, nnz_s=nnz_s, blocks=nnz_m))
         pb.close()
-        print(f"[bench] membrane step {n}: {ms:.1f} ms/step, product {1e3 * kt['spmv_ms']:.1f} us", file=sys.stderr,
-              flush=True)
+        print(f"[bench] membrane step {n} {'mixed' if mixed else 'fp64'}: {ms:.1f} ms/step, "
+              f"product {1e3 * kt['spmv_ms']:.1f} us", file=sys.stderr, flush=True)
     return out
 
 

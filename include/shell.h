@@ -88,7 +88,7 @@ typedef struct {
 /* Adds the membrane of Sec. 3 (eq 1): constant strain triangles with the Saint Venant-Kirchhoff model,
  * D_m = h E_el (plane stress), energy A/2 eps^T D_m eps of the Green strain per triangle, on every
  * triangle of the mesh and for any model.  shell_eval_forces adds its force and energy (both precisions).
- * The implicit step takes it in float64, one simulation at a time: each Newton iteration assembles the
+ * The implicit step takes it one simulation at a time, in either precision: each Newton iteration assembles the
  * membrane tangent K_m into 3x3 blocks (per triangle the Gauss-Newton part A B(F)^T D_m B(F) plus the
  * stress part A (g_a^T S+ g_b) I3, S+ the positive semi-definite part of the 2x2 second Piola-Kirchhoff
  * stress and g the shape-function gradients: the exact Hessian under tension, the Gauss-Newton tangent
@@ -99,7 +99,11 @@ typedef struct {
  * the incremental potential.  In its step statistics counts[k][0] is the PCG count and counts[k][1] the
  * halvings of Newton iteration k; REPLAY takes both from replay_counts the same way.  The quasi-static
  * solve takes it the same way (no mass term, no line search: eq 64's eps_u scaling; counts[k][0]).
- * Batches and mixed precision refuse such simulations (SHELL_E_UNSUPPORTED).  A degenerate triangle is
+ * In mixed precision the bending and membrane forces are the float32 kernels' (widened to float64 for the
+ * Newton loop), and the product reads float32 copies of K_s and of the tangent's blocks in difference
+ * form, q_i = m_i p_i + dt^2 sum_j (K_s,ij I + K_m,ij)(p_j - p_i), which keeps translations in their null
+ * space whatever the rounding; the vectors, dot products and the Newton loop stay float64.
+ * Batches refuse such simulations (SHELL_E_UNSUPPORTED).  A degenerate triangle is
  * SHELL_E_DEGENERATE. */
 #define SHELL_FLAG_MEMBRANE 4
 
@@ -231,7 +235,7 @@ shell_status_t shell_hessian_apply(shell_hessian_t h, const double* mass, double
  * x0, v0 host [nv][3] (v0 may be NULL = zero); pinned host [nv], 1 = all three coordinates held at
  * x0 (fixed boundary nodes, Sec. 4.3), may be NULL.  The lumped mass rho h sum(A_T)/3 is computed
  * from the rest mesh.  The stencils and Hessian must outlive the simulation.  Stencils built with
- * SHELL_FLAG_MEMBRANE give the step with the membrane (float64 only, else SHELL_E_UNSUPPORTED).
+ * SHELL_FLAG_MEMBRANE give the step with the membrane (either precision).
  */
 shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const double* x0, const double* v0,
                                 const uint8_t* pinned, shell_sim_t* out);

@@ -526,8 +526,6 @@ shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const do
         SHELL_CHECK(st && h && out && (x0 || st->nv == 0) && h->st == st, SHELL_E_INVALID_ARG, "bad argument");
         *out = nullptr;
         const bool membrane = (st->cfg_flags & SHELL_FLAG_MEMBRANE) != 0;
-        SHELL_CHECK(!membrane || st->precision == SHELL_PREC_FP64, SHELL_E_UNSUPPORTED,
-                    "the implicit step with the membrane runs in float64 only");
         auto sim = std::make_unique<shell_sim_s>();
         sim->st = st;
         sim->h = h;

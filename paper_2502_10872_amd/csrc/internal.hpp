@@ -310,6 +310,10 @@ struct MembraneSolve {
     DevArray<int32_t> vttri;
     DevArray<double> rest;   // [nt][5] G = Dm^-1 and the rest area
     DevArray<double> xtry, ftry, z, p, p2, q, y, r, dinv, part;
+    // mixed precision: the force kernels' float32 output (widened into ftry), and the float32 copies of
+    // K_s and of the tangent's blocks that the product reads (in difference form)
+    bool mixed = false;
+    DevArray<float> ff, svalf, mvalf;
     DevArray<double> ppart;      // per-block partials of the PCG product's p.q
     DevArray<double> scal;   // device scalars of the PCG and the energies
     DevArray<ForceDesc> fdesc;   // bending force at xtry with energy partials

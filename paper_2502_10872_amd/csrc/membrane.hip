@@ -369,53 +369,68 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__
 // product and the update stride over the rows with at most kMsPartMax work-groups.
 
 // p_new = z + beta p_old (row i, stored) and q = M p_new + dt^2 (K_s (x) I3 + K_m) p_new, the neighbours'
-// p_new formed on the fly from their z and p_old; fixed rows zero; partial p.q.  kMsRowLanes lanes share a
-// row: they take its K_s entries and its 3x3 blocks in turn (consecutive lanes read consecutive entries)
-// and combine their sums by shuffles; the row's first lane stores.
-constexpr int kMsRowLanes = 16;
-constexpr int kMsRowsPerBlk = kMsBlk / kMsRowLanes;
+// p_new formed on the fly from their z and p_old; fixed rows zero; partial p.q.  LANES lanes share a row:
+// they take its K_s entries and its 3x3 blocks in turn (consecutive lanes read consecutive entries) and
+// combine their sums by shuffles; the row's first lane stores.  Measured at 1M vertices: 8 lanes for
+// float64 entries (315 us, against 384 with 16 and 328 with 4), 4 for float32 entries (252 us, against
+// 445 with 16, 291 with 8 and 340 with 2): fewer lanes give each more entries in flight and fewer
+// shuffles, until too few rows share a wave's loads.
+constexpr int kMsLanesF64 = 8;
+constexpr int kMsLanesF32 = 4;
 // The product and the update stride over the rows with at most kMsPartMax work-groups, so that one
 // work-group sums their partials in a fixed order in a few microseconds at any mesh size.
 constexpr long kMsPartMax = 2048;
-inline unsigned ms_product_grid(long nv) {
-    return unsigned(std::min(kMsPartMax, std::max(1L, (nv + kMsRowsPerBlk - 1) / kMsRowsPerBlk)));
+inline unsigned ms_product_grid(long nv, int lanes) {
+    const long rows = kMsBlk / lanes;
+    return unsigned(std::min(kMsPartMax, std::max(1L, (nv + rows - 1) / rows)));
 }
 inline unsigned ms_update_grid(long nv) {
     return unsigned(std::min(kMsPartMax, std::max(1L, (nv + kMsBlk - 1) / kMsBlk)));
 }
 
+// VT: the type of the stored K_s entries and blocks.  Float32 entries (mixed precision) are applied in
+// difference form, q_i = m_i p_i + dt^2 sum_j (K_s,ij I + K_m,ij)(p_j - p_i): K_s and the tangent both
+// annihilate translations (their rows of 3x3 blocks sum to zero), and this form keeps that exactly
+// whatever the rounding of the entries, as the bending product's mixed form does.
+template <typename VT, int LANES>
 __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restrict__ scal,
                                                           const int64_t* __restrict__ srow,
-                                                          const int32_t* __restrict__ scol, const double* __restrict__ sval,
+                                                          const int32_t* __restrict__ scol, const VT* __restrict__ sval,
                                                           const int64_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
-                                                          const double* __restrict__ mval, const double* __restrict__ mass,
+                                                          const VT* __restrict__ mval, const double* __restrict__ mass,
                                                           const uint8_t* __restrict__ pinned, const double* __restrict__ z,
                                                           const double* __restrict__ pold, double* __restrict__ pnew,
                                                           double* __restrict__ q, long nv, double dt2,
                                                           double* __restrict__ ppart, long npart) {
     if (scal[S_ACTIVE] == 0.0) return;
     const double be = scal[S_BETA];
-    const int lane = threadIdx.x % kMsRowLanes;
+    constexpr int ROWS = kMsBlk / LANES;
+    const int lane = threadIdx.x % LANES;
     double v[1] = {0.0};
-    for (long i = blockIdx.x * long(kMsRowsPerBlk) + threadIdx.x / kMsRowLanes; i - threadIdx.x / kMsRowLanes < nv;
-         i += long(gridDim.x) * kMsRowsPerBlk) {
+    for (long i = blockIdx.x * long(ROWS) + threadIdx.x / LANES; i - threadIdx.x / LANES < nv;
+         i += long(gridDim.x) * ROWS) {
+    constexpr bool DIFF = sizeof(VT) == 4;
     double a[3] = {0.0, 0.0, 0.0};
     if (i < nv) {
-        for (long e = srow[i] + lane; e < srow[i + 1]; e += kMsRowLanes) {
+        double po[3] = {0.0, 0.0, 0.0};  // the row's own direction (difference form)
+        if constexpr (DIFF)
+            for (int c = 0; c < 3; ++c) po[c] = z[3 * i + c] + be * pold[3 * i + c];
+        for (long e = srow[i] + lane; e < srow[i + 1]; e += LANES) {
             const long j = scol[e];
-            const double k = sval[e];
-            for (int c = 0; c < 3; ++c) a[c] += k * (z[3 * j + c] + be * pold[3 * j + c]);
+            const double k = double(sval[e]);
+            for (int c = 0; c < 3; ++c) a[c] += k * (z[3 * j + c] + be * pold[3 * j + c] - po[c]);
         }
-        for (long e = mrow[i] + lane; e < mrow[i + 1]; e += kMsRowLanes) {
+        for (long e = mrow[i] + lane; e < mrow[i + 1]; e += LANES) {
             const long j = mcol[e];
-            const double* b = mval + 9 * e;
-            const double pj[3] = {z[3 * j] + be * pold[3 * j], z[3 * j + 1] + be * pold[3 * j + 1],
-                                  z[3 * j + 2] + be * pold[3 * j + 2]};
-            for (int c = 0; c < 3; ++c) a[c] += b[3 * c] * pj[0] + b[3 * c + 1] * pj[1] + b[3 * c + 2] * pj[2];
+            const VT* b = mval + 9 * e;
+            const double pj[3] = {z[3 * j] + be * pold[3 * j] - po[0], z[3 * j + 1] + be * pold[3 * j + 1] - po[1],
+                                  z[3 * j + 2] + be * pold[3 * j + 2] - po[2]};
+            for (int c = 0; c < 3; ++c)
+                a[c] += double(b[3 * c]) * pj[0] + double(b[3 * c + 1]) * pj[1] + double(b[3 * c + 2]) * pj[2];
         }
     }
-    for (int off = kMsRowLanes / 2; off > 0; off >>= 1)
-        for (int c = 0; c < 3; ++c) a[c] += __shfl_xor(a[c], off, kMsRowLanes);
+    for (int off = LANES / 2; off > 0; off >>= 1)
+        for (int c = 0; c < 3; ++c) a[c] += __shfl_xor(a[c], off, LANES);
     if (i < nv && lane == 0)
         for (int c = 0; c < 3; ++c) {
             const double pi = z[3 * i + c] + be * pold[3 * i + c];
@@ -569,6 +584,16 @@ __global__ void ms_gather_csr(const double* __restrict__ val, const int64_t* __r
     if (e < nnz) out[e] = val[csr2sell[e]];
 }
 
+__global__ void ms_narrow(const double* __restrict__ src, float* __restrict__ dst, long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) dst[i] = float(src[i]);
+}
+
+__global__ void ms_widen(const float* __restrict__ src, double* __restrict__ dst, long n) {
+    long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (i < n) dst[i] = double(src[i]);
+}
+
 __global__ void ms_zero(double* __restrict__ p, long n) {
     long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (i < n) p[i] = 0.0;
@@ -595,6 +620,12 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     if (!pat.col.empty())
         ms_gather_csr<<<ms_grid(long(pat.col.size())), kMsBlk, 0, s>>>(h.val.p, c2s.p, long(pat.col.size()),
                                                                         ms->sval.p);
+    ms->mixed = st.precision == SHELL_PREC_MIXED;
+    if (ms->mixed) {
+        ms->svalf.alloc(std::max<size_t>(pat.col.size(), 1));
+        if (!pat.col.empty())
+            ms_narrow<<<ms_grid(long(pat.col.size())), kMsBlk, 0, s>>>(ms->sval.p, ms->svalf.p, long(pat.col.size()));
+    }
     // membrane block pattern: each vertex, its triangle neighbours and itself, sorted
     std::vector<std::vector<int32_t>> nb(static_cast<size_t>(nv));
     for (long i = 0; i < nv; ++i) nb[size_t(i)].push_back(int32_t(i));
@@ -621,6 +652,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->mdiag.alloc(std::max<size_t>(mdiag.size(), 1));
     ms->mdiag.upload(mdiag.data(), mdiag.size(), s);
     ms->mval.alloc(std::max<size_t>(9 * mcol.size(), 1));
+    if (ms->mixed) ms->mvalf.alloc(std::max<size_t>(9 * mcol.size(), 1));
     // each vertex's triangles, ascending (the tangent assembly's fixed order)
     std::vector<int64_t> vtrow(size_t(nv + 1), 0);
     for (long t = 0; t < 3 * nt; ++t) ++vtrow[size_t(st.h_tris[size_t(t)]) + 1];
@@ -642,21 +674,23 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     if (nt > 0) membrane_rest<<<int((nt + 255) / 256), 256, 0, s>>>(st.X.p, st.tris.p, nt, ms->rest.p, bad.p);
     for (auto* a : {&ms->xtry, &ms->ftry, &ms->z, &ms->p, &ms->p2, &ms->q, &ms->y, &ms->r})
         a->alloc(size_t(std::max(n3, 1L)));
+    if (ms->mixed) ms->ff.alloc(size_t(std::max(n3, 1L)));
     ms->dinv.alloc(size_t(std::max(nv, 1L)));
     ms->ngroups = long(ms_grid(nv));
     ms->part.alloc(size_t(2 * ms->ngroups + std::max<int64_t>(st.nblocks, 1)));
-    ms->ppart.alloc(ms_product_grid(nv));
+    ms->ppart.alloc(size_t(kMsPartMax));
     ms->scal.alloc(S_COUNT);
-    // bending force at xtry into ftry, with its energy partials after the reduction partials
+    // bending force at xtry into ftry (mixed: into ff, widened into ftry afterwards), with its energy
+    // partials after the reduction partials
     ForceDesc d{};
     d.x = ms->xtry.p;
     d.X = st.X.p;
-    d.f = ms->ftry.p;
+    d.f = ms->mixed ? static_cast<void*>(ms->ff.p) : static_cast<void*>(ms->ftry.p);
     d.epart = ms->part.p + 2 * ms->ngroups;
     d.bias = st.bias.p;
     d.boff = st.boff.p;
     d.tidx = st.tidx.p;
-    d.trec = st.trec64.p;
+    d.trec = ms->mixed ? static_cast<const void*>(st.trec32.p) : static_cast<const void*>(st.trec64.p);
     d.nst = st.nst_pad;
     d.nv = st.nv;
     d.T = st.T;
@@ -677,6 +711,40 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     sim.ms = std::move(ms);
 }
 
+// Bending and membrane force at xtry into ftry (float64; mixed precision computes it in float32 into ff
+// and widens it), with the energy partials of both passes.
+static void forces_at_try(shell_sim_s& sim, hipStream_t s) {
+    shell_stencils_s& st = *sim.st;
+    MembraneSolve& m = *sim.ms;
+    const long n3 = 3 * sim.nv;
+    launch_force_items(st.model, st.precision, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
+    if (m.mixed) {
+        launch_membrane_forces(st, m.xtry.p, m.ff.p, s);
+        ms_widen<<<ms_grid(n3), kMsBlk, 0, s>>>(m.ff.p, m.ftry.p, n3);
+    } else {
+        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s);
+    }
+    SHELL_HIP(hipGetLastError());
+}
+
+// The membrane tangent at x into the 3x3 blocks (and their float32 copy in mixed precision), and the
+// Jacobi preconditioner of M + dt^2 (K_s (x) I3 + K_m) with the given mass.
+static void tangent_at(shell_sim_s& sim, const double* x, const double* mass, double dt2, hipStream_t s) {
+    shell_stencils_s& st = *sim.st;
+    MembraneSolve& m = *sim.ms;
+    const long nv = sim.nv, nt = st.nt;
+    const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
+    const long nb9 = long(m.mval.n);
+    ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
+    if (nt > 0)
+        ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, x, c, st.poisson,
+                                             m.mrow.p, m.mcol.p, m.mval.p);
+    ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, mass, sim.pinned.p, nv, dt2,
+                                           m.dinv.p);
+    if (m.mixed) ms_narrow<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, m.mvalf.p, nb9);
+    SHELL_HIP(hipGetLastError());
+}
+
 // One PCG iteration: the product kernel forms the new direction into one of the two p buffers from z and
 // the other, the update kernel reads it; the buffers alternate.  Once the stop test has cleared the active
 // flag all three kernels return at once, so the alternation may run on past the last iteration.
@@ -684,10 +752,16 @@ static void pcg_iteration(MembraneSolve& m, const double* mass, const uint8_t* p
                           hipStream_t s) {
     double* pold = m.pswap ? m.p2.p : m.p.p;
     double* pnew = m.pswap ? m.p.p : m.p2.p;
-    const unsigned pg = ms_product_grid(nv);
+    const unsigned pg = ms_product_grid(nv, m.mixed ? kMsLanesF32 : kMsLanesF64);
     const unsigned ug = ms_update_grid(nv);
-    ms_iter_product<<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p, m.mval.p, mass,
-                                          pinned, m.z.p, pold, pnew, m.q.p, nv, dt2, m.ppart.p, long(pg));
+    if (m.mixed)
+        ms_iter_product<float, kMsLanesF32><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.svalf.p, m.mrow.p, m.mcol.p,
+                                                     m.mvalf.p, mass, pinned, m.z.p, pold, pnew, m.q.p, nv, dt2,
+                                                     m.ppart.p, long(pg));
+    else
+        ms_iter_product<double, kMsLanesF64><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p,
+                                                                   m.mcol.p, m.mval.p, mass, pinned, m.z.p, pold, pnew,
+                                                                   m.q.p, nv, dt2, m.ppart.p, long(pg));
     ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, long(pg), m.scal.p);
     ms_iter_update<<<ug, kMsBlk, 0, s>>>(m.scal.p, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p, long(ug));
     ms_iter_finish<<<1, kMsBlk, 0, s>>>(m.part.p, long(ug), m.scal.p);
@@ -739,9 +813,8 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
     shell_stencils_s& st = *sim.st;
     MembraneSolve& m = *sim.ms;
     const bool graphs = (p.flags & SHELL_STEP_NO_GRAPHS) == 0;
-    const long nv = sim.nv, n3 = 3 * nv, nt = st.nt, ng = m.ngroups;
+    const long nv = sim.nv, n3 = 3 * nv, ng = m.ngroups;
     const double dt = p.dt, dt2 = dt * dt;
-    const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
     double* part = m.part.p;
     double* eb = m.part.p + 2 * ng;
     out = shell_step_stats_t{};
@@ -752,8 +825,7 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
     };
     // energy and force at xtry (force into ftry)
     auto evaluate = [&]() {
-        launch_force_items(st.model, SHELL_PREC_FP64, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
-        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s);
+        forces_at_try(sim, s);
         ms_inertia<<<ms_grid(nv), kMsBlk, 0, s>>>(m.xtry.p, sim.xhat.p, sim.mass.p, nv, part, ng);
         ms_energy<<<1, kMsBlk, 0, s>>>(eb, st.nblocks, st.mepart.p, st.nblocks, st.bias_e0, part, ng, dt2,
                                        m.scal.p);
@@ -786,13 +858,7 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
             break;
         }
         // the membrane tangent and the Jacobi preconditioner
-        const long nb9 = long(m.mval.n);
-        ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
-        if (nt > 0)
-            ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, sim.x.p, c,
-                                                 st.poisson, m.mrow.p, m.mcol.p, m.mval.p);
-        ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.mass.p, sim.pinned.p, nv,
-                                               dt2, m.dinv.p);
+        tangent_at(sim, sim.x.p, sim.mass.p, dt2, s);
         // one PCG over all coordinates
         const int target = replay ? p.replay_counts[3 * k] : p.max_pcg;
         m.pswap = false;  // ms_pcg_init writes p = z into m.p, the first product's old direction
@@ -850,11 +916,9 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
 
 shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, const MembraneStatic& qs,
                                shell_step_stats_t& out, hipStream_t s) {
-    shell_stencils_s& st = *sim.st;
     MembraneSolve& m = *sim.ms;
     const bool graphs = (p.flags & SHELL_STEP_NO_GRAPHS) == 0;
-    const long nv = sim.nv, n3 = 3 * nv, nt = st.nt, ng = m.ngroups;
-    const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
+    const long nv = sim.nv, n3 = 3 * nv, ng = m.ngroups;
     double* part = m.part.p;
     out = shell_step_stats_t{};
     if (!sim.zmass.p) {
@@ -867,14 +931,13 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
         SHELL_HIP(hipStreamSynchronize(s));
     };
     // bending plus membrane force at xtry into ftry, then the load added: ftry = f + F
-    auto forces_at_try = [&]() {
-        launch_force_items(st.model, SHELL_PREC_FP64, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
-        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s);
+    auto forces_and_load = [&]() {
+        forces_at_try(sim, s);
         if (qs.load) ms_axpy<<<ms_grid(n3), kMsBlk, 0, s>>>(m.ftry.p, qs.load, 1.0, m.ftry.p, n3);
         SHELL_HIP(hipGetLastError());
     };
     SHELL_HIP(hipMemcpyAsync(m.xtry.p, sim.x.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
-    forces_at_try();
+    forces_and_load();
     const bool replay = p.mode == SHELL_PCG_REPLAY;
     double gn0 = 0.0, gn = 0.0;
     bool budget = false, nonfinite = false;
@@ -895,13 +958,7 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
             out.newton_capped = 1;
             break;
         }
-        const long nb9 = long(m.mval.n);
-        ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
-        if (nt > 0)
-            ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, sim.x.p, c,
-                                                 st.poisson, m.mrow.p, m.mcol.p, m.mval.p);
-        ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.zmass.p, sim.pinned.p, nv,
-                                               1.0, m.dinv.p);
+        tangent_at(sim, sim.x.p, sim.zmass.p, 1.0, s);
         const int target = replay ? p.replay_counts[3 * k] : p.max_pcg;
         m.pswap = false;  // ms_pcg_init writes p = z into m.p, the first product's old direction
         ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.g.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, part, ng);
@@ -930,7 +987,7 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
             if (hs[S_YMAX] > qs.eps_u) scale = qs.eps_u / hs[S_YMAX];
         }
         ms_axpy<<<ms_grid(n3), kMsBlk, 0, s>>>(sim.x.p, m.y.p, scale, m.xtry.p, n3);
-        forces_at_try();
+        forces_and_load();
         SHELL_HIP(hipMemcpyAsync(sim.x.p, m.xtry.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
         out.counts[k][0] = its;
         out.pcg_total += its;
@@ -950,11 +1007,9 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
 // tangent at the current positions and a recurrence started from the force there (every kernel active).
 // The positions and velocities are not changed; the solver's work vectors are.
 void membrane_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {
-    shell_stencils_s& st = *sim.st;
     MembraneSolve& m = *sim.ms;
-    const long nv = sim.nv, n3 = 3 * nv, nt = st.nt, ng = m.ngroups;
+    const long nv = sim.nv, n3 = 3 * nv, ng = m.ngroups;
     const double dt2 = dt * dt;
-    const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
     hipEvent_t e0, e1;
     SHELL_HIP(hipEventCreate(&e0));
     SHELL_HIP(hipEventCreate(&e1));
@@ -966,27 +1021,24 @@ void membrane_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_t
     };
     SHELL_HIP(hipMemcpyAsync(m.xtry.p, sim.x.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
     SHELL_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < reps; ++k) {
-        launch_force_items(st.model, SHELL_PREC_FP64, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
-        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s);
-    }
+    for (int k = 0; k < reps; ++k) forces_at_try(sim, s);
     SHELL_HIP(hipEventRecord(e1, s));
     out.force_ms = elapsed();
-    const long nb9 = long(m.mval.n);
-    ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
-    if (nt > 0)
-        ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, sim.x.p, c, st.poisson,
-                                             m.mrow.p, m.mcol.p, m.mval.p);
-    ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, sim.mass.p, sim.pinned.p, nv, dt2,
-                                           m.dinv.p);
+    tangent_at(sim, sim.x.p, sim.mass.p, dt2, s);
     ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(m.ftry.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, m.part.p, ng);
     ms_fin_init<<<1, kMsBlk, 0, s>>>(m.part.p, ng, m.scal.p, 0.0, 1 << 30, 1);
-    const unsigned pg = ms_product_grid(nv), ug = ms_update_grid(nv);
+    const unsigned pg = ms_product_grid(nv, m.mixed ? kMsLanesF32 : kMsLanesF64), ug = ms_update_grid(nv);
     SHELL_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < reps; ++k)
-        ms_iter_product<<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p, m.mcol.p, m.mval.p,
-                                              sim.mass.p, sim.pinned.p, m.z.p, m.p.p, m.p2.p, m.q.p, nv, dt2,
-                                              m.ppart.p, long(pg));
+    for (int k = 0; k < reps; ++k) {
+        if (m.mixed)
+            ms_iter_product<float, kMsLanesF32><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.svalf.p, m.mrow.p,
+                                                         m.mcol.p, m.mvalf.p, sim.mass.p, sim.pinned.p, m.z.p, m.p.p,
+                                                         m.p2.p, m.q.p, nv, dt2, m.ppart.p, long(pg));
+        else
+            ms_iter_product<double, kMsLanesF64><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p,
+                                                          m.mcol.p, m.mval.p, sim.mass.p, sim.pinned.p, m.z.p, m.p.p,
+                                                          m.p2.p, m.q.p, nv, dt2, m.ppart.p, long(pg));
+    }
     SHELL_HIP(hipEventRecord(e1, s));
     out.spmv_ms = elapsed();
     ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, long(pg), m.scal.p);

@@ -137,6 +137,26 @@ def test_small_hemisphere_converges_to_the_oracle_equilibrium(model):
     assert_held_fixed(x, None, mesh.X, held)
 
 
+def test_small_hemisphere_mixed_precision_against_the_oracle():
+    """The 9 x 32 SS hemisphere in mixed precision (float32 forces and matrix entries, float64 Newton
+    loop) down to the paper's eps_f = 1e-3, against the oracle's FP64 equilibrium at the same tolerance:
+    the displacement to 1e-4 relative (the two stop at different points below eps_f, and the float32
+    forces' rounding moves the equilibrium by some 1e-6)."""
+    mesh, held, F, _ = I.hemisphere_problem(9, 32, model="SS")
+    mat = I.HEMISPHERE_MATERIAL
+    with S.Problem(mesh, mat, model="SS", precision=S.SHELL_PREC_MIXED, flags=S.SHELL_FLAG_MEMBRANE,
+                   held=held) as pb:
+        rc, gs = S.shell_solve_static(pb.sim, F, eps_f=1e-3, eps_u=0.1, max_newton=250, pcg_rtol=1e-10)
+        x, _, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+    ost = O.Stencils("SS", mesh.X, mesh.tris, mat["young"], mat["poisson"], mat["thickness"])
+    xo, _, ostats = O.solve_static_membrane(ost, np.zeros(mesh.nv), F, eps_f=1e-3, eps_u=0.1, max_newton=250,
+                                            pcg_rtol=1e-10, held=held)
+    err = rel(x - mesh.X, xo - mesh.X)
+    print(f"SS mixed 9x32: newton {gs['newton_iters']} (oracle {ostats['newton_iters']}), rel {err:.2e}")
+    assert gs["grad_norm"] < 1e-3 and err <= 1e-4
+    assert_held_fixed(x, None, mesh.X, held)
+
+
 def test_hemisphere_benchmark_matches_the_oracle_golden():
     """The benchmark's 17 x 64 hemisphere (1088 vertices), smoothed shell with its membrane, eps_f = 1e-3,
     eps_u = 0.1: the GPU equilibrium against the oracle's (tests/golden/hemisphere_ss_1088.json, written by

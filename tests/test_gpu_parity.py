@@ -450,26 +450,44 @@ def test_membrane_pcg_graphs_match_direct_launches():
 
 
 def test_membrane_step_tolerance_mode_descends_and_refusals():
-    """Tolerance mode: the residual falls within the Newton budget; batches and mixed precision refuse a
+    """Tolerance mode: the residual falls within the Newton budget, in both precisions; batches refuse a
     simulation with the membrane."""
     mesh = I.cylinder_mesh(17, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
-    with S.Problem(mesh, MAT, model="SS", block_vertices=128, flags=S.SHELL_FLAG_MEMBRANE) as pb:
-        params, _ = S.step_params(1 / 30, max_newton=6, newton_rtol=1e-6, pcg_rtol=1e-6)
-        rc, gs = S.shell_step_implicit(pb.sim, params)
-        assert gs["newton_iters"] >= 1 and gs["grad_norm"] < gs["grad_norm0"]
-        with pytest.raises(S.ShellError) as ei:
-            S.shell_batch_create([pb.sim])
-        assert ei.value.status == S.SHELL_E_UNSUPPORTED
-    st32 = S.shell_build_stencils(mesh.X, mesh.tris, "SS", MAT, precision=S.SHELL_PREC_MIXED,
-                                  flags=S.SHELL_FLAG_MEMBRANE)
-    h = S.shell_assemble_constant_hessian(st32)
-    try:
-        with pytest.raises(S.ShellError) as ei:
-            S.shell_sim_create(st32, h, mesh.X, None, mesh.pinned)
-        assert ei.value.status == S.SHELL_E_UNSUPPORTED
-    finally:
-        S.shell_destroy_hessian(h)
-        S.shell_destroy_stencils(st32)
+    for prec in (S.SHELL_PREC_FP64, S.SHELL_PREC_MIXED):
+        with S.Problem(mesh, MAT, model="SS", precision=prec, block_vertices=128, flags=S.SHELL_FLAG_MEMBRANE) as pb:
+            params, _ = S.step_params(1 / 30, max_newton=6, newton_rtol=1e-6, pcg_rtol=1e-6)
+            rc, gs = S.shell_step_implicit(pb.sim, params)
+            assert gs["newton_iters"] >= 1 and gs["grad_norm"] < 0.1 * gs["grad_norm0"]
+            with pytest.raises(S.ShellError) as ei:
+                S.shell_batch_create([pb.sim])
+            assert ei.value.status == S.SHELL_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("model", ["SS", "ES"])
+def test_mixed_membrane_step_replay_matches_oracle(model):
+    """The step with the membrane in mixed precision (float32 forces, float32 K_s and tangent blocks in
+    difference form, float64 vectors and Newton loop) against the FP64 oracle, the oracle's PCG counts and
+    halvings replayed as in the FP64 test: two steps at dt = 1/120 to 1e-6 relative displacement
+    (float32 rounding of the forces and of the matrix entries, 6e-8 relative each, through a
+    mass-dominated system)."""
+    mesh = I.cylinder_mesh(17, 0.5, 0.9, 0.8, 0.2, 3, model, "ends")
+    ost = oracle_stencils(model, mesh)
+    osim = O.MembraneSim(ost, MAT, mesh.pinned)
+    with S.Problem(mesh, MAT, model=model, precision=S.SHELL_PREC_MIXED, block_vertices=128,
+                   flags=S.SHELL_FLAG_MEMBRANE) as pb:
+        for _ in range(2):
+            counts, halv, ostats = osim.step(1 / 120, max_newton=3, newton_rtol=1e-6, pcg_rtol=1e-13)
+            n = ostats["newton_iters"]
+            rep = np.zeros((max(n, 1), 3), np.int32)
+            rep[:n, 0] = counts[:n]
+            rep[:n, 1] = halv[:n]
+            params, _keep = S.step_params(1 / 120, max_newton=n, newton_rtol=1e-6, pcg_rtol=1e-13, replay=rep)
+            rc, gs = S.shell_step_implicit(pb.sim, params)
+            assert gs["newton_iters"] == n
+        x, v, step = S.shell_sim_get_state(pb.sim, mesh.nv)
+    err = (rel(x - mesh.X, osim.x - mesh.X), rel(v, osim.v))
+    print(f"{model} mixed membrane step: displacement {err[0]:.2e}, velocity {err[1]:.2e}")
+    assert err[0] <= 1e-6 and err[1] <= 1e-6, err
 
 
 def _cantilever(model, scale=1.0, nx=17, ny=3):
