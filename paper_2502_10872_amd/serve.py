@@ -360,8 +360,9 @@ def main(argv=None):
     ap.add_argument("--builders", type=int, default=4)
     ap.add_argument("--nv-max", type=float, default=1e6)
     ap.add_argument("--sequential", action="store_true", help="also serve each trace one mesh at a time")
+    ap.add_argument("--max-wait", type=float, default=math.inf, help="queue-wait deadline past which a request is shed")
     args = ap.parse_args(argv)
-    cfg = ServeConfig(hbm_budget=int(args.budget_gb * (1 << 30)), builders=args.builders)
+    cfg = ServeConfig(hbm_budget=int(args.budget_gb * (1 << 30)), builders=args.builders, max_wait_s=args.max_wait)
     results = []
     for rate in [float(r) for r in args.rates.split(",")]:
         reqs = make_requests(rate, args.duration, nv_max=args.nv_max)
