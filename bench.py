@@ -250,12 +250,13 @@ def membrane_timing(S, I, torch, reps=20):
 
 
 def membrane_product_bytes(nv, nnz_s, nnz_m, mixed=False):
-    """Algorithmic bytes of one coupled product launch: K_s as CSR (row offsets 8 B, column 4 B and a value
-    per entry), the membrane tangent's 3x3 blocks (row offsets, column 4 B and nine values per block), the
-    values float64 (float32 in mixed precision), the mass and the held mask, z and the previous direction
-    read once, the new direction and q written once (float64 vectors in both precisions)."""
+    """Algorithmic bytes of one coupled product launch in the staged SELL layout: K_s (a 2-byte group-local
+    column id and a value per entry), the membrane tangent's 3x3 blocks (a 2-byte column id and nine values
+    per block), the values float64 (float32 in mixed precision), the mass and the held mask, z and the
+    previous direction read once, the new direction and q written once (float64 vectors in both
+    precisions).  Slice offsets and the groups' column lists (a few bytes per row) are not counted."""
     real = 4 if mixed else 8
-    return 16 * (nv + 1) + (4 + real) * nnz_s + (4 + 9 * real) * nnz_m + nv * (8 + 1 + 48 + 48)
+    return (2 + real) * nnz_s + (2 + 9 * real) * nnz_m + nv * (8 + 1 + 48 + 48)
 
 
 def membrane_step_timing(S, I, torch, sizes=(64, 256, 1024), steps=2):

@@ -101,6 +101,14 @@ __device__ __forceinline__ long xcd_logical(long bid, long ngrid) {
     return (bid % kXcds) * per + bid / kXcds;
 }
 
+// A 64-bit value that is the same in every lane of the wave, read from the first lane into scalar
+// registers (the low word zero-extended).
+__device__ __forceinline__ long uniform64(int64_t v) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+    const int hi = __builtin_amdgcn_readfirstlane(int(v >> 32));
+    return long((uint64_t(uint32_t(hi)) << 32) | lo);
+}
+
 // wave64 sum of a double through lane shuffles
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -304,8 +304,26 @@ struct MembraneSolve {
     DevArray<double> sval;
     DevArray<int64_t> mrow;  // membrane block pattern: each vertex and its triangle neighbours, sorted
     DevArray<int32_t> mcol;
-    DevArray<int64_t> mdiag; // [nv] slot of the diagonal block
-    DevArray<double> mval;   // [nnz][9] row-major 3x3 blocks
+    // The tangent's 3x3 blocks, component (a, b) of block e at mval[mbase[e] + (3 a + b) mstride]: CSR
+    // blocks one after the other (mbase = 9 e, mstride = 1), or, for the staged product, SELL-64 slices of
+    // nine component arrays (mbase = the block's slot, mstride = the slot count)
+    DevArray<int64_t> mbase;  // [nnz] base index of each CSR block
+    DevArray<int64_t> mdiag;  // [nv] base index of the diagonal block
+    int64_t mstride = 1;
+    DevArray<double> mval;
+    // staged product: rows in groups of kRowGroup, the group's directions staged in LDS.  K_s is read from
+    // the bending Hessian's SELL slots and the blocks from their own SELL-64 slices (mptr, mwidth), each
+    // slot's column an index into its group's list of the distinct columns of both matrices (gptr, gcols,
+    // sorted); gself: the list index of the group's first row (its rows follow in order)
+    bool staged = false;
+    int32_t max_gcols = 0;
+    DevArray<int32_t> gptr, gcols, gself, mwidth;
+    DevArray<int64_t> mptr;
+    DevArray<uint16_t> slcol, mlcol;
+    const int64_t* hsptr = nullptr;  // the bending Hessian's SELL slices and values (owned by the Hessian)
+    const int32_t* hwidth = nullptr;
+    const double* hval = nullptr;
+    const float* hvalf = nullptr;
     DevArray<int64_t> vtrow; // [nv+1] each vertex's triangles, ascending
     DevArray<int32_t> vttri;
     DevArray<double> rest;   // [nt][5] G = Dm^-1 and the rest area

@@ -250,11 +250,13 @@ __device__ __forceinline__ long ms_find(const int64_t* __restrict__ row, const i
 
 // The membrane tangent into the 3x3 blocks, one thread per vertex row: the thread walks the row's
 // triangles in ascending order and adds its corner's three blocks of each, so every block is written by
-// one thread in a fixed order (no atomics; the same state gives the same matrix bit for bit).
+// one thread in a fixed order (no atomics; the same state gives the same matrix bit for bit).  Component
+// (a, b) of CSR block e is mval[mbase[e] + (3 a + b) mstride].
 __global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict__ tris,
                       const int64_t* __restrict__ vtrow, const int32_t* __restrict__ vttri, long nv,
                       const double* __restrict__ x, double c, double nu, const int64_t* __restrict__ mrow,
-                      const int32_t* __restrict__ mcol, double* __restrict__ mval) {
+                      const int32_t* __restrict__ mcol, const int64_t* __restrict__ mbase, long mstride,
+                      double* __restrict__ mval) {
     const long r = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (r >= nv) return;
     for (long e = vtrow[r]; e < vtrow[r + 1]; ++e) {
@@ -302,25 +304,26 @@ __global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict
             P11 = w * (s22 - l2);
         }
         for (int b = 0; b < 3; ++b) {
-            double* blk = mval + 9 * ms_find(mrow, mcol, r, int(v[b]));
+            double* blk = mval + mbase[ms_find(mrow, mcol, r, int(v[b]))];
             for (int ca = 0; ca < 3; ++ca)
                 for (int cb = 0; cb < 3; ++cb) {
                     const int pa = 3 * a + ca, pb = 3 * b + cb;
-                    blk[3 * ca + cb] += A * (Bm[0][pa] * DB[0][pb] + Bm[1][pa] * DB[1][pb] + Bm[2][pa] * DB[2][pb]);
+                    blk[(3 * ca + cb) * mstride] +=
+                        A * (Bm[0][pa] * DB[0][pb] + Bm[1][pa] * DB[1][pb] + Bm[2][pa] * DB[2][pb]);
                 }
             const double gsg = g[a][0] * (P00 * g[b][0] + P01 * g[b][1]) + g[a][1] * (P01 * g[b][0] + P11 * g[b][1]);
-            for (int cc = 0; cc < 3; ++cc) blk[4 * cc] += A * gsg;
+            for (int cc = 0; cc < 3; ++cc) blk[4 * cc * mstride] += A * gsg;
         }
     }
 }
 
 __global__ void ms_dinv(const double* __restrict__ kdiag, const double* __restrict__ mval,
-                        const int64_t* __restrict__ mdiag, const double* __restrict__ mass,
+                        const int64_t* __restrict__ mdiag, long mstride, const double* __restrict__ mass,
                         const uint8_t* __restrict__ pinned, long nv, double dt2, double* __restrict__ dinv) {
     long i = blockIdx.x * long(blockDim.x) + threadIdx.x;
     if (i >= nv) return;
-    const double* b = mval + 9 * mdiag[i];
-    const double d = mass[i] + dt2 * (kdiag[i] + (b[0] + b[4] + b[8]) / 3.0);
+    const double* b = mval + mdiag[i];
+    const double d = mass[i] + dt2 * (kdiag[i] + (b[0] + b[4 * mstride] + b[8 * mstride]) / 3.0);
     dinv[i] = ((pinned[i] & 7u) == 7u || d == 0.0) ? 0.0 : 1.0 / d;
 }
 
@@ -441,6 +444,87 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restri
         }
     }
     ms_partials<1>(v, ppart, npart);
+}
+
+// The same product over SELL-64 slices with the rows in groups of kRowGroup, one work-group per group
+// (striding over the groups with at most kMsPartMax work-groups): the group's new directions
+// p_new = z + beta p_old at its distinct columns are formed once into LDS, then each lane takes one row
+// through K_s (the bending Hessian's slots) and through the blocks' nine component arrays.  A slice's
+// width and offset are the same in every lane of its wave, and consecutive lanes read consecutive slots,
+// so every load of ids and values is coalesced; padding slots hold zero values.  Rows past nv in the last
+// slice run the loops on their padding and store nothing.
+template <typename VT>
+__global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
+    const double* __restrict__ scal, const int64_t* __restrict__ sptr, const int32_t* __restrict__ swidth,
+    const uint16_t* __restrict__ slcol, const VT* __restrict__ sval, const int64_t* __restrict__ mptr,
+    const int32_t* __restrict__ mwidth, const uint16_t* __restrict__ mlcol, const VT* __restrict__ mval, long mstride,
+    const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcols, const int32_t* __restrict__ gself,
+    const double* __restrict__ mass, const uint8_t* __restrict__ pinned, const double* __restrict__ z,
+    const double* __restrict__ pold, double* __restrict__ pnew, double* __restrict__ q, long nv, double dt2,
+    double* __restrict__ ppart) {
+    extern __shared__ double ps[];
+    __shared__ double red[kRowGroup / 64];
+    if (scal[S_ACTIVE] == 0.0) return;
+    const double be = scal[S_BETA];
+    constexpr bool DIFF = sizeof(VT) == 4;
+    const long ngroups = (nv + kRowGroup - 1) / kRowGroup, nslices = (nv + 63) / 64;
+    double v = 0.0;
+    for (long g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int a0 = gptr[g], n = gptr[g + 1] - a0;
+        __syncthreads();  // the previous group's rows have read ps
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const long j = gcols[a0 + k];
+            for (int c = 0; c < 3; ++c) ps[3 * k + c] = z[3 * j + c] + be * pold[3 * j + c];
+        }
+        __syncthreads();
+        const long i = g * kRowGroup + threadIdx.x;
+        const long slice = i >> 6;
+        if (slice >= nslices) continue;  // whole waves past the last slice
+        double po[3] = {0.0, 0.0, 0.0};
+        if (i < nv)
+            for (int c = 0; c < 3; ++c) po[c] = ps[3 * (gself[g] + threadIdx.x) + c];
+        double a[3] = {0.0, 0.0, 0.0};
+        {
+            const int w = __builtin_amdgcn_readfirstlane(swidth[slice]);
+            const long s0 = uniform64(sptr[slice]) + (i & 63);
+            for (int k = 0; k < w; ++k) {
+                const long o = s0 + 64L * k;
+                const double kv = double(sval[o]);
+                const double* pc = ps + 3 * int(slcol[o]);
+                for (int c = 0; c < 3; ++c) a[c] = fma(kv, DIFF ? pc[c] - po[c] : pc[c], a[c]);
+            }
+        }
+        {
+            const int w = __builtin_amdgcn_readfirstlane(mwidth[slice]);
+            const long m0 = uniform64(mptr[slice]) + (i & 63);
+            for (int k = 0; k < w; ++k) {
+                const long o = m0 + 64L * k;
+                const double* pc = ps + 3 * int(mlcol[o]);
+                const double d[3] = {DIFF ? pc[0] - po[0] : pc[0], DIFF ? pc[1] - po[1] : pc[1],
+                                     DIFF ? pc[2] - po[2] : pc[2]};
+                for (int r = 0; r < 3; ++r)
+                    a[r] += double(mval[o + (3 * r) * mstride]) * d[0] + double(mval[o + (3 * r + 1) * mstride]) * d[1] +
+                            double(mval[o + (3 * r + 2) * mstride]) * d[2];
+            }
+        }
+        if (i < nv)
+            for (int c = 0; c < 3; ++c) {
+                const double pi = po[c];
+                pnew[3 * i + c] = pi;
+                const double qi = (pinned[i] >> c & 1u) ? 0.0 : mass[i] * pi + dt2 * a[c];
+                q[3 * i + c] = qi;
+                v += pi * qi;
+            }
+    }
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kRowGroup / 64; ++w) t += red[w];
+        ppart[blockIdx.x] = t;
+    }
 }
 
 // p.q from the product's partials (one work-group, fixed order), then alpha = r.z / p.q
@@ -608,24 +692,8 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     shell_hessian_s& h = *sim.h;
     auto ms = std::make_unique<MembraneSolve>();
     const long nv = st.nv, nt = st.nt, n3 = 3 * nv;
-    // K_s as CSR from the assembled SELL slots
     const SellPattern& pat = h.pat;
-    ms->srow.alloc(pat.rowptr.size());
-    ms->srow.upload(pat.rowptr.data(), pat.rowptr.size(), s);
-    ms->scol.alloc(std::max<size_t>(pat.col.size(), 1));
-    ms->scol.upload(pat.col.data(), pat.col.size(), s);
-    ms->sval.alloc(std::max<size_t>(pat.col.size(), 1));
-    DevArray<int64_t> c2s(std::max<size_t>(pat.csr2sell.size(), 1));
-    c2s.upload(pat.csr2sell.data(), pat.csr2sell.size(), s);
-    if (!pat.col.empty())
-        ms_gather_csr<<<ms_grid(long(pat.col.size())), kMsBlk, 0, s>>>(h.val.p, c2s.p, long(pat.col.size()),
-                                                                        ms->sval.p);
     ms->mixed = st.precision == SHELL_PREC_MIXED;
-    if (ms->mixed) {
-        ms->svalf.alloc(std::max<size_t>(pat.col.size(), 1));
-        if (!pat.col.empty())
-            ms_narrow<<<ms_grid(long(pat.col.size())), kMsBlk, 0, s>>>(ms->sval.p, ms->svalf.p, long(pat.col.size()));
-    }
     // membrane block pattern: each vertex, its triangle neighbours and itself, sorted
     std::vector<std::vector<int32_t>> nb(static_cast<size_t>(nv));
     for (long i = 0; i < nv; ++i) nb[size_t(i)].push_back(int32_t(i));
@@ -649,10 +717,123 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->mrow.upload(mrow.data(), mrow.size(), s);
     ms->mcol.alloc(std::max<size_t>(mcol.size(), 1));
     ms->mcol.upload(mcol.data(), mcol.size(), s);
+    // where each block is stored: CSR order (the direct product), or SELL-64 slices for the staged one
+    const int64_t nnz_m = int64_t(mcol.size());
+    std::vector<int64_t> mbase(size_t(std::max<int64_t>(nnz_m, 1)), 0);
+    int64_t nblock_vals = 9 * nnz_m;
+    ms->staged = (st.cfg_flags & SHELL_FLAG_DIRECT_PRODUCT) == 0 && nv > 0;
+    if (ms->staged) {
+        // each row group's distinct columns of K_s and of the blocks, with its own rows
+        const int64_t ng = (nv + kRowGroup - 1) / kRowGroup, nsl = (nv + 63) / 64;
+        std::vector<std::vector<int32_t>> gl(static_cast<size_t>(ng));
+        for (int64_t g = 0; g < ng; ++g) {
+            auto& v = gl[size_t(g)];
+            for (int64_t i = g * kRowGroup; i < std::min<int64_t>(nv, (g + 1) * kRowGroup); ++i) {
+                v.push_back(int32_t(i));
+                v.insert(v.end(), pat.col.begin() + pat.rowptr[size_t(i)], pat.col.begin() + pat.rowptr[size_t(i + 1)]);
+                v.insert(v.end(), mcol.begin() + mrow[size_t(i)], mcol.begin() + mrow[size_t(i + 1)]);
+            }
+            std::sort(v.begin(), v.end());
+            v.erase(std::unique(v.begin(), v.end()), v.end());
+            ms->max_gcols = std::max<int32_t>(ms->max_gcols, int32_t(v.size()));
+        }
+        ms->staged = ms->max_gcols <= kMaxGroupCols && pat.nslices == nsl;
+        if (ms->staged) {
+            auto local = [&](int64_t g, int32_t c) {  // index of column c in group g's list (0 if absent)
+                const auto& v = gl[size_t(g)];
+                auto it = std::lower_bound(v.begin(), v.end(), c);
+                return (it != v.end() && *it == c) ? uint16_t(it - v.begin()) : uint16_t(0);
+            };
+            std::vector<int32_t> gptr(static_cast<size_t>(ng + 1), 0), gcols, gself(static_cast<size_t>(ng));
+            for (int64_t g = 0; g < ng; ++g) {
+                gptr[size_t(g + 1)] = gptr[size_t(g)] + int32_t(gl[size_t(g)].size());
+                gcols.insert(gcols.end(), gl[size_t(g)].begin(), gl[size_t(g)].end());
+                gself[size_t(g)] = local(g, int32_t(g * kRowGroup));
+            }
+            std::vector<uint16_t> slcol(size_t(pat.nslots));
+            for (int64_t sl = 0; sl < nsl; ++sl)
+                for (int64_t slot = pat.sptr[size_t(sl)]; slot < pat.sptr[size_t(sl + 1)]; ++slot)
+                    slcol[size_t(slot)] = local((64 * sl) / kRowGroup, pat.scol[size_t(slot)]);
+            std::vector<int32_t> mwidth(static_cast<size_t>(nsl));
+            std::vector<int64_t> mptr(size_t(nsl + 1), 0);
+            for (int64_t sl = 0; sl < nsl; ++sl) {
+                int w = 1;
+                for (int64_t i = 64 * sl; i < std::min<int64_t>(nv, 64 * sl + 64); ++i)
+                    w = std::max(w, int(mrow[size_t(i + 1)] - mrow[size_t(i)]));
+                mwidth[size_t(sl)] = w;
+                mptr[size_t(sl + 1)] = mptr[size_t(sl)] + 64 * int64_t(w);
+            }
+            const int64_t mslots = mptr[size_t(nsl)];
+            std::vector<uint16_t> mlcol(size_t(mslots), 0);
+            for (int64_t sl = 0; sl < nsl; ++sl)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int64_t i = 64 * sl + lane, g = i / kRowGroup;
+                    const int64_t len = i < nv ? mrow[size_t(i + 1)] - mrow[size_t(i)] : 0;
+                    for (int64_t k = 0; k < mwidth[size_t(sl)]; ++k) {
+                        const int64_t slot = mptr[size_t(sl)] + 64 * k + lane;
+                        if (k < len) {
+                            const int64_t e = mrow[size_t(i)] + k;
+                            mbase[size_t(e)] = slot;
+                            mlcol[size_t(slot)] = local(g, mcol[size_t(e)]);
+                        } else {
+                            mlcol[size_t(slot)] = i < nv ? local(g, int32_t(i)) : uint16_t(0);  // zero value
+                        }
+                    }
+                }
+            ms->mstride = mslots;
+            nblock_vals = 9 * mslots;
+            ms->hsptr = h.sptr.p;
+            ms->hwidth = h.width.p;
+            ms->hval = h.val.p;
+            ms->hvalf = h.valf.p;
+            SHELL_CHECK(!ms->mixed || ms->hvalf, SHELL_E_INVALID_ARG, "mixed precision needs the float32 K_s");
+            ms->gptr.alloc(gptr.size());
+            ms->gptr.upload(gptr.data(), gptr.size(), s);
+            ms->gcols.alloc(std::max<size_t>(gcols.size(), 1));
+            ms->gcols.upload(gcols.data(), gcols.size(), s);
+            ms->gself.alloc(gself.size());
+            ms->gself.upload(gself.data(), gself.size(), s);
+            ms->slcol.alloc(std::max<size_t>(slcol.size(), 1));
+            ms->slcol.upload(slcol.data(), slcol.size(), s);
+            ms->mwidth.alloc(mwidth.size());
+            ms->mwidth.upload(mwidth.data(), mwidth.size(), s);
+            ms->mptr.alloc(mptr.size());
+            ms->mptr.upload(mptr.data(), mptr.size(), s);
+            ms->mlcol.alloc(mlcol.size());
+            ms->mlcol.upload(mlcol.data(), mlcol.size(), s);
+            SHELL_HIP(hipStreamSynchronize(s));  // the host copies are released on leaving the scope
+        }
+    }
+    if (!ms->staged) {
+        ms->mstride = 1;
+        for (int64_t e = 0; e < nnz_m; ++e) mbase[size_t(e)] = 9 * e;
+    }
+    DevArray<int64_t> c2s;
+    if (!ms->staged) {  // the direct product reads K_s as CSR, gathered from the assembled SELL slots
+        ms->srow.alloc(pat.rowptr.size());
+        ms->srow.upload(pat.rowptr.data(), pat.rowptr.size(), s);
+        ms->scol.alloc(std::max<size_t>(pat.col.size(), 1));
+        ms->scol.upload(pat.col.data(), pat.col.size(), s);
+        ms->sval.alloc(std::max<size_t>(pat.col.size(), 1));
+        c2s.alloc(std::max<size_t>(pat.csr2sell.size(), 1));
+        c2s.upload(pat.csr2sell.data(), pat.csr2sell.size(), s);
+        if (!pat.col.empty())
+            ms_gather_csr<<<ms_grid(long(pat.col.size())), kMsBlk, 0, s>>>(h.val.p, c2s.p, long(pat.col.size()),
+                                                                            ms->sval.p);
+        if (ms->mixed) {
+            ms->svalf.alloc(std::max<size_t>(pat.col.size(), 1));
+            if (!pat.col.empty())
+                ms_narrow<<<ms_grid(long(pat.col.size())), kMsBlk, 0, s>>>(ms->sval.p, ms->svalf.p,
+                                                                            long(pat.col.size()));
+        }
+    }
+    for (long i = 0; i < nv; ++i) mdiag[size_t(i)] = mbase[size_t(mdiag[size_t(i)])];
+    ms->mbase.alloc(mbase.size());
+    ms->mbase.upload(mbase.data(), mbase.size(), s);
     ms->mdiag.alloc(std::max<size_t>(mdiag.size(), 1));
     ms->mdiag.upload(mdiag.data(), mdiag.size(), s);
-    ms->mval.alloc(std::max<size_t>(9 * mcol.size(), 1));
-    if (ms->mixed) ms->mvalf.alloc(std::max<size_t>(9 * mcol.size(), 1));
+    ms->mval.alloc(size_t(std::max<int64_t>(nblock_vals, 1)));
+    if (ms->mixed) ms->mvalf.alloc(size_t(std::max<int64_t>(nblock_vals, 1)));
     // each vertex's triangles, ascending (the tangent assembly's fixed order)
     std::vector<int64_t> vtrow(size_t(nv + 1), 0);
     for (long t = 0; t < 3 * nt; ++t) ++vtrow[size_t(st.h_tris[size_t(t)]) + 1];
@@ -738,8 +919,8 @@ static void tangent_at(shell_sim_s& sim, const double* x, const double* mass, do
     ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
     if (nt > 0)
         ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, x, c, st.poisson,
-                                             m.mrow.p, m.mcol.p, m.mval.p);
-    ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, mass, sim.pinned.p, nv, dt2,
+                                             m.mrow.p, m.mcol.p, m.mbase.p, long(m.mstride), m.mval.p);
+    ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, long(m.mstride), mass, sim.pinned.p, nv, dt2,
                                            m.dinv.p);
     if (m.mixed) ms_narrow<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, m.mvalf.p, nb9);
     SHELL_HIP(hipGetLastError());
@@ -748,21 +929,44 @@ static void tangent_at(shell_sim_s& sim, const double* x, const double* mass, do
 // One PCG iteration: the product kernel forms the new direction into one of the two p buffers from z and
 // the other, the update kernel reads it; the buffers alternate.  Once the stop test has cleared the active
 // flag all three kernels return at once, so the alternation may run on past the last iteration.
-static void pcg_iteration(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2,
-                          hipStream_t s) {
-    double* pold = m.pswap ? m.p2.p : m.p.p;
-    double* pnew = m.pswap ? m.p.p : m.p2.p;
+// The coupled product q = (M + dt^2 (K_s (x) I3 + K_m)) p_new with p_new = z + beta p_old written to pnew,
+// and its per-work-group partials of p.q in m.ppart; returns the number of partials.
+static long launch_product(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2,
+                           const double* pold, double* pnew, hipStream_t s) {
+    if (m.staged) {
+        const unsigned pg = unsigned(std::min(kMsPartMax, (nv + kRowGroup - 1) / kRowGroup));
+        const size_t lds = size_t(m.max_gcols) * 3 * sizeof(double);
+        if (m.mixed)
+            ms_iter_product_staged<float><<<pg, kRowGroup, lds, s>>>(
+                m.scal.p, m.hsptr, m.hwidth, m.slcol.p, m.hvalf, m.mptr.p, m.mwidth.p, m.mlcol.p, m.mvalf.p,
+                long(m.mstride), m.gptr.p, m.gcols.p, m.gself.p, mass, pinned, m.z.p, pold, pnew, m.q.p, nv, dt2,
+                m.ppart.p);
+        else
+            ms_iter_product_staged<double><<<pg, kRowGroup, lds, s>>>(
+                m.scal.p, m.hsptr, m.hwidth, m.slcol.p, m.hval, m.mptr.p, m.mwidth.p, m.mlcol.p, m.mval.p,
+                long(m.mstride), m.gptr.p, m.gcols.p, m.gself.p, mass, pinned, m.z.p, pold, pnew, m.q.p, nv, dt2,
+                m.ppart.p);
+        return long(pg);
+    }
     const unsigned pg = ms_product_grid(nv, m.mixed ? kMsLanesF32 : kMsLanesF64);
-    const unsigned ug = ms_update_grid(nv);
     if (m.mixed)
-        ms_iter_product<float, kMsLanesF32><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.svalf.p, m.mrow.p, m.mcol.p,
-                                                     m.mvalf.p, mass, pinned, m.z.p, pold, pnew, m.q.p, nv, dt2,
-                                                     m.ppart.p, long(pg));
+        ms_iter_product<float, kMsLanesF32><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.svalf.p, m.mrow.p,
+                                                                  m.mcol.p, m.mvalf.p, mass, pinned, m.z.p, pold, pnew,
+                                                                  m.q.p, nv, dt2, m.ppart.p, long(pg));
     else
         ms_iter_product<double, kMsLanesF64><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p,
                                                                    m.mcol.p, m.mval.p, mass, pinned, m.z.p, pold, pnew,
                                                                    m.q.p, nv, dt2, m.ppart.p, long(pg));
-    ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, long(pg), m.scal.p);
+    return long(pg);
+}
+
+static void pcg_iteration(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2,
+                          hipStream_t s) {
+    double* pold = m.pswap ? m.p2.p : m.p.p;
+    double* pnew = m.pswap ? m.p.p : m.p2.p;
+    const long np = launch_product(m, mass, pinned, nv, dt2, pold, pnew, s);
+    const unsigned ug = ms_update_grid(nv);
+    ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, m.scal.p);
     ms_iter_update<<<ug, kMsBlk, 0, s>>>(m.scal.p, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p, long(ug));
     ms_iter_finish<<<1, kMsBlk, 0, s>>>(m.part.p, long(ug), m.scal.p);
     m.pswap = !m.pswap;
@@ -1027,21 +1231,13 @@ void membrane_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_t
     tangent_at(sim, sim.x.p, sim.mass.p, dt2, s);
     ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(m.ftry.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, m.part.p, ng);
     ms_fin_init<<<1, kMsBlk, 0, s>>>(m.part.p, ng, m.scal.p, 0.0, 1 << 30, 1);
-    const unsigned pg = ms_product_grid(nv, m.mixed ? kMsLanesF32 : kMsLanesF64), ug = ms_update_grid(nv);
+    const unsigned ug = ms_update_grid(nv);
+    long np = 0;
     SHELL_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < reps; ++k) {
-        if (m.mixed)
-            ms_iter_product<float, kMsLanesF32><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.svalf.p, m.mrow.p,
-                                                         m.mcol.p, m.mvalf.p, sim.mass.p, sim.pinned.p, m.z.p, m.p.p,
-                                                         m.p2.p, m.q.p, nv, dt2, m.ppart.p, long(pg));
-        else
-            ms_iter_product<double, kMsLanesF64><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p,
-                                                          m.mcol.p, m.mval.p, sim.mass.p, sim.pinned.p, m.z.p, m.p.p,
-                                                          m.p2.p, m.q.p, nv, dt2, m.ppart.p, long(pg));
-    }
+    for (int k = 0; k < reps; ++k) np = launch_product(m, sim.mass.p, sim.pinned.p, nv, dt2, m.p.p, m.p2.p, s);
     SHELL_HIP(hipEventRecord(e1, s));
     out.spmv_ms = elapsed();
-    ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, long(pg), m.scal.p);
+    ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, m.scal.p);
     SHELL_HIP(hipEventRecord(e0, s));
     for (int k = 0; k < reps; ++k)
         ms_iter_update<<<ug, kMsBlk, 0, s>>>(m.scal.p, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p,

@@ -40,9 +40,7 @@ __device__ __forceinline__ void sell_row_product(const int32_t* __restrict__ sco
     // the whole wave shares the slice (work-groups are whole waves aligned to 64 rows)
     const int w = __builtin_amdgcn_readfirstlane(G(width)[slice]);
     const int64_t sp = G(sptr)[slice];
-    const long s0 = (long(__builtin_amdgcn_readfirstlane(int(sp & 0xffffffff))) |
-                     (long(__builtin_amdgcn_readfirstlane(int(sp >> 32))) << 32)) +
-                    (row & 63);
+    const long s0 = uniform64(sp) + (row & 63);
     ax = MR(0);
     ay = MR(0);
     az = MR(0);
@@ -115,9 +113,7 @@ __device__ __forceinline__ void sell_row_product_staged(const uint16_t* __restri
     const long slice = row >> 6;
     const int w = __builtin_amdgcn_readfirstlane(G(width)[slice]);
     const int64_t sp = G(sptr)[slice];
-    const long s0 = (long(__builtin_amdgcn_readfirstlane(int(sp & 0xffffffff))) |
-                     (long(__builtin_amdgcn_readfirstlane(int(sp >> 32))) << 32)) +
-                    (row & 63);
+    const long s0 = uniform64(sp) + (row & 63);
     ax = MR(0);
     ay = MR(0);
     az = MR(0);
@@ -178,9 +174,7 @@ struct SellStream {
         const long slice = row >> 6;
         w = __builtin_amdgcn_readfirstlane(G(width)[slice]);
         const int64_t sp = G(sptr)[slice];
-        s0 = (long(__builtin_amdgcn_readfirstlane(int(sp & 0xffffffff))) |
-              (long(__builtin_amdgcn_readfirstlane(int(sp >> 32))) << 32)) +
-             (row & 63);
+        s0 = uniform64(sp) + (row & 63);
     }
 
     // A float64 matrix (twice the bytes of the vectors it meets) is read with non-temporal loads, which

@@ -490,6 +490,39 @@ def test_mixed_membrane_step_replay_matches_oracle(model):
     assert err[0] <= 1e-6 and err[1] <= 1e-6, err
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("direct", [False, True], ids=["staged", "direct"])
+def test_membrane_step_multi_group_matches_oracle(prec, direct):
+    """The membrane step's coupled product over several 512-row groups with a ragged last group and a
+    partial last 64-row slice (a 37 x 37 cylinder patch, 1369 vertices): the staged SELL product (the
+    group's directions in LDS, K_s from the bending Hessian's slots, the blocks in SELL-64 component
+    arrays) and the direct CSR product (SHELL_FLAG_DIRECT_PRODUCT) both replay the oracle's two steps to
+    the FP64 bound, or to the mixed bound of the single-group test."""
+    mesh = I.cylinder_mesh(37, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+    assert mesh.nv == 1369
+    ost = oracle_stencils("SS", mesh)
+    osim = O.MembraneSim(ost, MAT, mesh.pinned)
+    flags = S.SHELL_FLAG_MEMBRANE | (S.SHELL_FLAG_DIRECT_PRODUCT if direct else 0)
+    precision = S.SHELL_PREC_MIXED if prec == "mixed" else S.SHELL_PREC_FP64
+    with S.Problem(mesh, MAT, model="SS", precision=precision, flags=flags) as pb:
+        for _ in range(2):
+            counts, halv, ostats = osim.step(1 / 120, max_newton=3, newton_rtol=1e-6, pcg_rtol=1e-13)
+            n = ostats["newton_iters"]
+            rep = np.zeros((max(n, 1), 3), np.int32)
+            rep[:n, 0] = counts[:n]
+            rep[:n, 1] = halv[:n]
+            params, _keep = S.step_params(1 / 120, max_newton=n, newton_rtol=1e-6, pcg_rtol=1e-13, replay=rep)
+            rc, gs = S.shell_step_implicit(pb.sim, params)
+            assert gs["newton_iters"] == n
+            if prec == "fp64":
+                assert [list(c[:2]) for c in gs["counts"][:n]] == [[int(a), int(b)] for a, b in zip(counts[:n], halv[:n])]
+        x, v, step = S.shell_sim_get_state(pb.sim, mesh.nv)
+    err = (rel(x - mesh.X, osim.x - mesh.X), rel(v, osim.v))
+    print(f"{prec} {'direct' if direct else 'staged'} multi-group membrane step: {err[0]:.2e} {err[1]:.2e}")
+    bound = TOL64 if prec == "fp64" else 1e-6
+    assert err[0] <= bound and err[1] <= bound, err
+
+
 def _cantilever(model, scale=1.0, nx=17, ny=3):
     """The Sec. 6 cantilever: a 10 x 1 strip of nx x ny vertices, E = 1.2e6, nu = 0.1, h = 0.1, its two
     left vertex columns held, an end shear of total 4 * scale along Z on the right-end vertices."""
