@@ -292,7 +292,7 @@ def membrane_step_timing(S, I, torch, sizes=(64, 256, 1024), steps=2):
             halvings=[int(c[1]) for st in stats for c in st["counts"]],
             grad_ratio=[st["grad_norm"] / max(st["grad_norm0"], 1e-300) for st in stats],
             back_to_back_ms=dict(force=kt["force_ms"], product=kt["spmv_ms"], update=kt["update_ms"]),
-            product=dict(kernel="ms_iter_product", bytes_per_launch=pbytes, achieved_gbs=gbs,
+            product=dict(kernel="ms_iter_product_staged", bytes_per_launch=pbytes, achieved_gbs=gbs,
                          frac=gbs / HBM_PEAK_GBS if gbs else None, nnz_s=nnz_s, blocks=nnz_m))
         pb.close()
         print(f"[bench] membrane step {n} {'mixed' if mixed else 'fp64'}: {ms:.1f} ms/step, "
