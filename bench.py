@@ -453,10 +453,53 @@ def run_membrane(args):
     S.lib()
     forces = membrane_timing(S, I, torch)
     steps = membrane_step_timing(S, I, torch)
+    mbatch = membrane_batch_timing(S, I, torch)
     print(json.dumps(dict(metric="implicit steps/s with the membrane (SS, 1024x1024 cylinder, FP64)",
                           value=1e3 / steps["SS_membrane_cylinder_1024"]["ms_per_step"], unit="steps/s",
                           higher_is_better=True, n_gpus=1, data="synthetic", membrane_forces=forces,
-                          membrane_step=steps)), flush=True)
+                          membrane_step=steps, membrane_batch=mbatch)), flush=True)
+
+
+def membrane_batch_timing(S, I, torch, count=32, steps=2, warmup=1):
+    """A batch of `count` simulations with the membrane (the 64-mesh batch's size and model mix, its
+    first `count` specs: 16^2..512^2 vertices, 1 cm spacing, mixed precision, dt = 1/60, Newton budget 4,
+    PCG rtol 1e-2), stepped as one batch (members concurrently on the library's streams) against the
+    same simulations stepped one at a time."""
+    specs = I.batch_specs(64)[:count]
+    meshes = [I.mesh_from_spec(sp, spacing=0.01) for sp in specs]
+    probs = [S.Problem(m, I.MATERIAL, precision=S.SHELL_PREC_MIXED, flags=S.SHELL_FLAG_MEMBRANE) for m in meshes]
+    nv_total = sum(m.nv for m in meshes)
+    params, _ = S.step_params(1.0 / 60.0, gravity=I.GRAVITY, max_newton=4, pcg_rtol=1e-2)
+    stream = torch.cuda.current_stream()
+    batch = S.shell_batch_create([pb.sim for pb in probs])
+    for _ in range(warmup):
+        S.shell_batch_step(batch, params, len(probs), stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pcg = 0
+    for _ in range(steps):
+        rc, st = S.shell_batch_step(batch, params, len(probs), stream=stream)
+        pcg += sum(x["pcg_total"] for x in st)
+    torch.cuda.synchronize()
+    batch_s = (time.perf_counter() - t0) / steps
+    S.shell_destroy_batch(batch)
+    t0 = time.perf_counter()
+    for pb in probs:
+        for _ in range(steps):
+            S.shell_step_implicit(pb.sim, params, stream=stream)
+    torch.cuda.synchronize()
+    seq_s = (time.perf_counter() - t0) / steps
+    for pb in probs:
+        pb.close()
+    print(f"[bench] membrane batch of {count}: {1e3 * batch_s:.1f} ms per step, one at a time {1e3 * seq_s:.1f} ms",
+          file=sys.stderr, flush=True)
+    return dict(workload=f"{count} simulations with the membrane, sizes 16^2..512^2 log-uniform (the first {count} "
+                         "specs of the 64-mesh batch, seed 2502108724), all six models, 1 cm spacing, mixed, "
+                         "dt=1/60 s, Newton budget 4, PCG rtol 0.01",
+                meshes=count, vertices=nv_total, steps=steps, mesh_steps_per_s=count / batch_s,
+                batch_ms_per_step=1e3 * batch_s, pcg_iters_per_step=pcg / steps,
+                one_at_a_time=dict(mesh_steps_per_s=count / seq_s, ms_per_round=1e3 * seq_s),
+                speedup_vs_one_at_a_time=seq_s / batch_s)
 
 
 def batch64_timing(S, I, torch, precision, steps, warmup=1, max_pcg=400000):
@@ -965,6 +1008,7 @@ def main(argv=None):
         if not args.hot_path_only:
             out["membrane_forces"] = membrane_timing(S, I, torch)
             out["membrane_step"] = membrane_step_timing(S, I, torch)
+            out["membrane_batch"] = membrane_batch_timing(S, I, torch)
             out["quasi_static"] = quasi_static(S, I, torch)
             out["quasi_static"]["linear_plate_sweep"] = linear_plate_sweep(S, I, torch)
             out["quasi_static"]["cantilever"] = cantilever(S, I, torch)

@@ -102,9 +102,11 @@ typedef struct {
  * In mixed precision the bending and membrane forces are the float32 kernels' (widened to float64 for the
  * Newton loop), and the product reads float32 copies of K_s and of the tangent's blocks in difference
  * form, q_i = m_i p_i + dt^2 sum_j (K_s,ij I + K_m,ij)(p_j - p_i), which keeps translations in their null
- * space whatever the rounding; the vectors, dot products and the Newton loop stay float64.
- * Batches refuse such simulations (SHELL_E_UNSUPPORTED).  A degenerate triangle is
- * SHELL_E_DEGENERATE. */
+ * space whatever the rounding; the vectors, dot products and the Newton loop stay float64.  Unless
+ * SHELL_FLAG_DIRECT_PRODUCT is set, the product takes the rows in groups of 512 with the group's
+ * directions staged in LDS, K_s from the bending Hessian's SELL-64 slots and the blocks in SELL-64 slices.
+ * A batch of such simulations steps each member as it would step alone (see shell_batch_create).  A
+ * degenerate triangle is SHELL_E_DEGENERATE. */
 #define SHELL_FLAG_MEMBRANE 4
 
 typedef struct shell_stencils_s* shell_stencils_t;
@@ -347,7 +349,12 @@ shell_status_t shell_sim_device_state(shell_sim_t sim, double** x, double** v);
  * stepping it alone (up to summation order of the tile accumulation).
  *
  * shell_batch_create: sims host [n] distinct handles of one precision, n >= 1; the simulations must
- * outlive the batch and must not be stepped alone while the batch is in use.
+ * outlive the batch and must not be stepped alone while the batch is in use.  Simulations with the
+ * membrane (SHELL_FLAG_MEMBRANE) form batches of their own (mixing them with simulations without it is
+ * SHELL_E_INVALID_ARG): each member takes the step it takes alone, bit for bit, on one of up to 8
+ * library-owned streams, members on different streams driven concurrently by library-owned host threads;
+ * the members start after the work queued on `stream`, and the call returns when all have finished.
+ * Sampled timing (shell_batch_profile) refuses such a batch (SHELL_E_UNSUPPORTED).
  * shell_batch_step: params host [nparams], nparams = 1 (shared) or n; stats host [n] or NULL.  Returns
  * the worst per-mesh status (SHELL_E_NONFINITE, then SHELL_E_BUDGET); per-mesh statuses are in stats.
  * Synchronises `stream` at the end of every Newton round.

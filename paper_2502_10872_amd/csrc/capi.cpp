@@ -772,6 +772,8 @@ void profile_read(const shell_batch_s* b, shell_profile_t* out) {
 shell_status_t shell_batch_profile(shell_batch_t batch, int32_t every) {
     return guarded([&]() -> shell_status_t {
         SHELL_CHECK(batch && every >= 0, SHELL_E_INVALID_ARG, "bad argument");
+        SHELL_CHECK(!batch->membrane || every == 0, SHELL_E_UNSUPPORTED,
+                    "sampled timing covers the solver without the membrane");
         profile_set(*batch, every);
         return SHELL_OK;
     });

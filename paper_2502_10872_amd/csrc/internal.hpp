@@ -445,6 +445,10 @@ struct shell_batch_s {
     size_t items_cap = 0;
     shell::DevArray<shell::WorkItem> items;   // [rows | tiles of each model]
     shell::DevArray<int32_t> mlist;
+    // simulations with the membrane: each member steps alone on one of these streams, the members
+    // shared out among host workers
+    bool membrane = false;
+    std::vector<hipStream_t> mstreams;
 };
 
 namespace shell {
@@ -480,6 +484,9 @@ struct MembraneStatic {
 shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, const MembraneStatic& qs,
                                shell_step_stats_t& out, hipStream_t s);
 void membrane_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_times_t& out, hipStream_t s);
+// one implicit step of every member of a batch of simulations with the membrane (stats: [n])
+shell_status_t membrane_batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams,
+                                   shell_step_stats_t* stats, hipStream_t s);
 void launch_gather_rows(const double* src, const int32_t* perm, double* dst, int64_t nv, hipStream_t s);
 void launch_scatter_rows(const void* src, const int32_t* perm, void* dst, int64_t nv, bool f32, hipStream_t s);
 // hessian.hip

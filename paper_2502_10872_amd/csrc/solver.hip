@@ -665,14 +665,18 @@ void batch_init(shell_batch_s& b) {
     SHELL_CHECK(n > 0, SHELL_E_INVALID_ARG, "empty batch");
     b.precision = b.sims[0]->st->precision;
     b.max_T = 64;
+    const bool membrane = b.sims[0]->ms != nullptr;
     for (size_t m = 0; m < n; ++m) {
-        SHELL_CHECK(!b.sims[m]->ms, SHELL_E_UNSUPPORTED, "a simulation with the membrane steps alone");
+        SHELL_CHECK((b.sims[m]->ms != nullptr) == membrane, SHELL_E_INVALID_ARG,
+                    "a batch holds simulations with the membrane or simulations without it, not both");
         SHELL_CHECK(b.sims[m]->st->precision == b.precision, SHELL_E_INVALID_ARG,
                     "all simulations of a batch need the same precision");
         for (size_t q = 0; q < m; ++q)
             SHELL_CHECK(b.sims[q] != b.sims[m], SHELL_E_INVALID_ARG, "a simulation appears twice in a batch");
         b.max_T = std::max(b.max_T, b.sims[m]->st->T);
     }
+    b.membrane = membrane;
+    if (membrane) return;  // the members step with their own solver state
     size_t vr = b.precision == SHELL_PREC_MIXED ? sizeof(float) : sizeof(double);
     b.lds_spmv = 0;
     for (size_t m = 0; m < n; ++m)
@@ -702,6 +706,8 @@ void batch_free_host(shell_batch_s& b) {
 }
 
 void batch_release(shell_batch_s& b) {
+    for (hipStream_t t : b.mstreams) (void)hipStreamDestroy(t);
+    b.mstreams.clear();
     b.graphs.reset();
     batch_free_host(b);
     if (b.items_host) (void)hipHostFree(b.items_host);
@@ -713,11 +719,16 @@ shell_status_t batch_step(shell_batch_s& b, const shell_step_params_t* p, int np
                           hipStream_t s, const StaticMode* qs) {
     for (shell_sim_s* sim : b.sims)
         SHELL_CHECK(sim->nv > 0, SHELL_E_INVALID_ARG, "empty simulation in a batch");
+    if (b.membrane) {
+        SHELL_CHECK(!qs, SHELL_E_UNSUPPORTED, "the quasi-static solve with the membrane runs per simulation");
+        return membrane_batch_step(b, p, nparams, stats, s);
+    }
     if (b.precision == SHELL_PREC_MIXED) return step_impl<float, float>(b, p, nparams, stats, s, qs);
     return step_impl<double, double>(b, p, nparams, stats, s, qs);
 }
 
 void batch_time_kernels(shell_batch_s& b, double dt, int reps, shell_kernel_times_t& out, hipStream_t s) {
+    SHELL_CHECK(!b.membrane, SHELL_E_UNSUPPORTED, "kernel timing of a simulation with the membrane runs per simulation");
     if (b.precision == SHELL_PREC_MIXED)
         time_impl<float, float>(b, dt, reps, out, s);
     else

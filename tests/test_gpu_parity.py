@@ -450,17 +450,88 @@ def test_membrane_pcg_graphs_match_direct_launches():
 
 
 def test_membrane_step_tolerance_mode_descends_and_refusals():
-    """Tolerance mode: the residual falls within the Newton budget, in both precisions; batches refuse a
-    simulation with the membrane."""
+    """Tolerance mode: the residual falls within the Newton budget, in both precisions.  A batch does not
+    mix simulations with and without the membrane, and sampled timing refuses a membrane batch."""
     mesh = I.cylinder_mesh(17, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
     for prec in (S.SHELL_PREC_FP64, S.SHELL_PREC_MIXED):
-        with S.Problem(mesh, MAT, model="SS", precision=prec, block_vertices=128, flags=S.SHELL_FLAG_MEMBRANE) as pb:
+        with S.Problem(mesh, MAT, model="SS", precision=prec, block_vertices=128, flags=S.SHELL_FLAG_MEMBRANE) as pb, \
+                S.Problem(mesh, MAT, model="SS", precision=prec, block_vertices=128) as plain:
             params, _ = S.step_params(1 / 30, max_newton=6, newton_rtol=1e-6, pcg_rtol=1e-6)
             rc, gs = S.shell_step_implicit(pb.sim, params)
             assert gs["newton_iters"] >= 1 and gs["grad_norm"] < 0.1 * gs["grad_norm0"]
             with pytest.raises(S.ShellError) as ei:
-                S.shell_batch_create([pb.sim])
-            assert ei.value.status == S.SHELL_E_UNSUPPORTED
+                S.shell_batch_create([pb.sim, plain.sim])
+            assert ei.value.status == S.SHELL_E_INVALID_ARG
+            batch = S.shell_batch_create([pb.sim])
+            try:
+                with pytest.raises(S.ShellError) as ei:
+                    S.shell_batch_profile(batch, 4)
+                assert ei.value.status == S.SHELL_E_UNSUPPORTED
+            finally:
+                S.shell_destroy_batch(batch)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_membrane_batch_equals_each_simulation_alone(prec):
+    """A batch of simulations with the membrane (models, sizes and per-member parameters differing; more
+    members than host workers) steps every member exactly as stepping it alone does, bit for bit; the
+    first member replays the oracle's counts through the batch and matches the oracle (FP64 bound, or
+    the mixed bound).  Resetting the batch to a subset, and to simulations without the membrane, works."""
+    precision = S.SHELL_PREC_MIXED if prec == "mixed" else S.SHELL_PREC_FP64
+    models = ["SS", "FS", "ES", "SS", "FS", "ES", "SS", "FS", "ES", "SS"]
+    meshes = [I.cylinder_mesh(17 + 3 * k, 0.5, 0.9, 0.8, 0.2, 3, mdl, "ends") for k, mdl in enumerate(models)]
+    ost = oracle_stencils(models[0], meshes[0])
+    osim = O.MembraneSim(ost, MAT, meshes[0].pinned)
+    tol_params = [S.step_params(1 / 60, max_newton=3, newton_rtol=1e-8, pcg_rtol=1e-6 * (1 + k))
+                  for k in range(len(meshes))]
+    flags = S.SHELL_FLAG_MEMBRANE
+
+    def problems():
+        return [S.Problem(m, MAT, model=mdl, precision=precision, block_vertices=128, flags=flags)
+                for m, mdl in zip(meshes, models)]
+
+    batched, alone = problems(), problems()
+    keep = []
+    try:
+        batch = S.shell_batch_create([pb.sim for pb in batched])
+        try:
+            for step in range(2):
+                counts, halv, ostats = osim.step(1 / 120, max_newton=3, newton_rtol=1e-6, pcg_rtol=1e-13)
+                n = ostats["newton_iters"]
+                rep = np.zeros((max(n, 1), 3), np.int32)
+                rep[:n, 0] = counts[:n]
+                rep[:n, 1] = halv[:n]
+                p0, k0 = S.step_params(1 / 120, max_newton=n, newton_rtol=1e-6, pcg_rtol=1e-13, replay=rep)
+                keep.append(k0)
+                plist = [p0] + [tp[0] for tp in tol_params[1:]]
+                rc, stats = S.shell_batch_step(batch, plist, len(plist))
+                assert stats[0]["newton_iters"] == n
+                for k, pb in enumerate(alone):
+                    rc1, st1 = S.shell_step_implicit(pb.sim, plist[k])
+                    assert st1["pcg_total"] == stats[k]["pcg_total"] and st1["newton_iters"] == stats[k]["newton_iters"]
+            for pa, pb in zip(batched, alone):
+                xa, va, sa = S.shell_sim_get_state(pa.sim, pa.nv)
+                xb, vb, sb = S.shell_sim_get_state(pb.sim, pb.nv)
+                assert sa == sb == 2
+                assert np.array_equal(xa, xb) and np.array_equal(va, vb)
+            x0, v0, _ = S.shell_sim_get_state(batched[0].sim, meshes[0].nv)
+            err = (rel(x0 - meshes[0].X, osim.x - meshes[0].X), rel(v0, osim.v))
+            bound = TOL64 if prec == "fp64" else 1e-6
+            assert err[0] <= bound and err[1] <= bound, err
+            # a subset, then simulations without the membrane, through the same batch
+            sub = [batched[k].sim for k in (1, 4, 7)]
+            S.shell_batch_reset(batch, sub)
+            rc, stats = S.shell_batch_step(batch, tol_params[1][0], len(sub))
+            assert all(st["newton_iters"] >= 1 for st in stats)
+            with S.Problem(meshes[1], MAT, model=models[1], precision=precision, block_vertices=128) as plain:
+                S.shell_batch_reset(batch, [plain.sim])
+                rc, stats = S.shell_batch_step(batch, tol_params[1][0], 1)
+                assert stats[0]["newton_iters"] >= 1
+        finally:
+            S.shell_destroy_batch(batch)
+    finally:
+        for pb in batched + alone:
+            pb.close()
 
 
 @pytest.mark.parametrize("model", ["SS", "ES"])
