@@ -383,6 +383,11 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__
 // shuffles, until too few rows share a wave's loads.
 constexpr int kMsLanesF64 = 8;
 constexpr int kMsLanesF32 = 4;
+// The staged product (below) from this many rows up: one work-group per 512-row group leaves most of the
+// chip idle on small meshes, where its latency floor (about 10 us) exceeds the CSR product's.  Measured
+// on SS cylinders, staged against CSR, FP64: 10.1 / 5.3 us at 4K rows, 14.4 / 10.2 at 33K, 15.0 / 14.1
+// at 48K, 15.5 / 18.1 at 65K, 20.2 / 32.9 at 131K, 144 / 317 at 1M.
+constexpr long kMsStagedMinRows = 49152;
 // The product and the update stride over the rows with at most kMsPartMax work-groups, so that one
 // work-group sums their partials in a fixed order in a few microseconds at any mesh size.
 constexpr long kMsPartMax = 2048;
@@ -727,7 +732,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     const int64_t nnz_m = int64_t(mcol.size());
     std::vector<int64_t> mbase(size_t(std::max<int64_t>(nnz_m, 1)), 0);
     int64_t nblock_vals = 9 * nnz_m;
-    ms->staged = (st.cfg_flags & SHELL_FLAG_DIRECT_PRODUCT) == 0 && nv > 0;
+    ms->staged = (st.cfg_flags & SHELL_FLAG_DIRECT_PRODUCT) == 0 && nv >= kMsStagedMinRows;
     if (ms->staged) {
         // each row group's distinct columns of K_s and of the blocks, with its own rows
         const int64_t ng = (nv + kRowGroup - 1) / kRowGroup, nsl = (nv + 63) / 64;
