@@ -445,10 +445,7 @@ struct shell_batch_s {
     size_t items_cap = 0;
     shell::DevArray<shell::WorkItem> items;   // [rows | tiles of each model]
     shell::DevArray<int32_t> mlist;
-    // simulations with the membrane: each member steps alone on one of these streams, the members
-    // shared out among host workers
-    bool membrane = false;
-    std::vector<hipStream_t> mstreams;
+    bool membrane = false;  // simulations with the membrane: the members step one after the other
 };
 
 namespace shell {

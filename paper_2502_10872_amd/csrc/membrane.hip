@@ -12,9 +12,6 @@
 // compute in float64 from float64 positions (the Green strain F^T F - I cancels to the strain's size);
 // mixed precision stores the sum as float32.
 #include <algorithm>
-#include <atomic>
-#include <exception>
-#include <thread>
 #include <cmath>
 
 #include "devmath.hpp"
@@ -1130,62 +1127,15 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
 }
 
 // A batch of simulations with the membrane: every member takes the step it would take alone (the same
-// kernels on its own state, so the same result bit for bit), the members shared out in order among up to
-// kMsBatchWorkers host workers, each driving its members one after the other on its own stream.  The
-// step's host decisions (the stop tests, the line search) wait on one member's stream at a time, so
-// members on different workers overlap their kernels and their waits.  The members start after the work
-// already queued on s; each worker's step synchronises its stream before it returns, and the members'
-// last stream becomes s.
-constexpr int kMsBatchWorkers = 8;
-
+// kernels on its own state, so the same result bit for bit), one after the other on s.
 shell_status_t membrane_batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams,
                                    shell_step_stats_t* stats, hipStream_t s) {
-    const int n = int(b.sims.size());
-    const int workers = std::min(n, kMsBatchWorkers);
-    while (int(b.mstreams.size()) < workers) {
-        hipStream_t t = nullptr;
-        SHELL_HIP(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
-        b.mstreams.push_back(t);
-    }
-    int device = 0;
-    SHELL_HIP(hipGetDevice(&device));
-    hipEvent_t ready = nullptr;
-    SHELL_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-    std::vector<shell_step_stats_t> st(static_cast<size_t>(n));
-    std::vector<shell_status_t> rc(static_cast<size_t>(n), SHELL_OK);
-    std::vector<std::exception_ptr> err(static_cast<size_t>(workers));
-    std::atomic<int> next{0};
-    auto work = [&](int w) {
-        try {
-            SHELL_HIP(hipSetDevice(device));
-            SHELL_HIP(hipStreamWaitEvent(b.mstreams[size_t(w)], ready, 0));
-            for (int m; (m = next.fetch_add(1)) < n;)
-                rc[size_t(m)] = membrane_step(*b.sims[size_t(m)], p[nparams == 1 ? 0 : m], st[size_t(m)],
-                                              b.mstreams[size_t(w)]);
-        } catch (...) {
-            err[size_t(w)] = std::current_exception();
-            next.store(n);  // the other workers take no further member
-        }
-    };
-    try {
-        SHELL_HIP(hipEventRecord(ready, s));
-        std::vector<std::thread> pool;
-        for (int w = 1; w < workers; ++w) pool.emplace_back(work, w);
-        work(0);
-        for (auto& t : pool) t.join();
-    } catch (...) {
-        (void)hipEventDestroy(ready);
-        throw;
-    }
-    (void)hipEventDestroy(ready);
-    for (auto& e : err)
-        if (e) std::rethrow_exception(e);
     shell_status_t worst = SHELL_OK;
-    for (int m = 0; m < n; ++m) {
-        b.sims[size_t(m)]->last_stream = s;
-        if (stats) stats[m] = st[size_t(m)];
-        if (rc[size_t(m)] == SHELL_E_NONFINITE || (rc[size_t(m)] == SHELL_E_BUDGET && worst == SHELL_OK))
-            worst = rc[size_t(m)];
+    for (size_t m = 0; m < b.sims.size(); ++m) {
+        shell_step_stats_t st{};
+        const shell_status_t rc = membrane_step(*b.sims[m], p[nparams == 1 ? 0 : m], st, s);
+        if (stats) stats[m] = st;
+        if (rc == SHELL_E_NONFINITE || (rc == SHELL_E_BUDGET && worst == SHELL_OK)) worst = rc;
     }
     return worst;
 }

@@ -706,8 +706,6 @@ void batch_free_host(shell_batch_s& b) {
 }
 
 void batch_release(shell_batch_s& b) {
-    for (hipStream_t t : b.mstreams) (void)hipStreamDestroy(t);
-    b.mstreams.clear();
     b.graphs.reset();
     batch_free_host(b);
     if (b.items_host) (void)hipHostFree(b.items_host);

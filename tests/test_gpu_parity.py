@@ -473,8 +473,8 @@ def test_membrane_step_tolerance_mode_descends_and_refusals():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_membrane_batch_equals_each_simulation_alone(prec):
-    """A batch of simulations with the membrane (models, sizes and per-member parameters differing; more
-    members than host workers) steps every member exactly as stepping it alone does, bit for bit; the
+    """A batch of simulations with the membrane (models, sizes and per-member parameters differing) steps
+    every member exactly as stepping it alone does, bit for bit; the
     first member replays the oracle's counts through the batch and matches the oracle (FP64 bound, or
     the mixed bound).  Resetting the batch to a subset, and to simulations without the membrane, works."""
     precision = S.SHELL_PREC_MIXED if prec == "mixed" else S.SHELL_PREC_FP64
