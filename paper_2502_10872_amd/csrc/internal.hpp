@@ -324,8 +324,9 @@ struct MembraneSolve {
     const int32_t* hwidth = nullptr;
     const double* hval = nullptr;
     const float* hvalf = nullptr;
-    DevArray<int64_t> vtrow; // [nv+1] each vertex's triangles, ascending
-    DevArray<int32_t> vttri;
+    DevArray<int32_t> brow;   // [nnz] the row of each block
+    DevArray<int64_t> btptr;  // [nnz+1] the triangles holding both vertices of each block, ascending
+    DevArray<int32_t> bttri;
     DevArray<double> rest;   // [nt][5] G = Dm^-1 and the rest area
     DevArray<double> xtry, ftry, z, p, p2, q, y, r, dinv, part;
     // mixed precision: the force kernels' float32 output (widened into ftry), and the float32 copies of

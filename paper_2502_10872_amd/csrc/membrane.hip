@@ -238,52 +238,47 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin1(const double* __restrict__ par
     if (threadIdx.x == 0) scal[slot] = t[0];
 }
 
-__device__ __forceinline__ long ms_find(const int64_t* __restrict__ row, const int32_t* __restrict__ col, long i,
-                                        int j) {
-    long lo = row[i], hi = row[i + 1] - 1;
-    while (lo < hi) {
-        const long mid = (lo + hi) >> 1;
-        if (col[mid] < j) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
-// The membrane tangent into the 3x3 blocks, one thread per vertex row: the thread walks the row's
-// triangles in ascending order and adds its corner's three blocks of each, so every block is written by
-// one thread in a fixed order (no atomics; the same state gives the same matrix bit for bit).  Component
-// (a, b) of CSR block e is mval[mbase[e] + (3 a + b) mstride].
-__global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict__ tris,
-                      const int64_t* __restrict__ vtrow, const int32_t* __restrict__ vttri, long nv,
-                      const double* __restrict__ x, double c, double nu, const int64_t* __restrict__ mrow,
-                      const int32_t* __restrict__ mcol, const int64_t* __restrict__ mbase, long mstride,
-                      double* __restrict__ mval) {
-    const long r = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (r >= nv) return;
-    for (long e = vtrow[r]; e < vtrow[r + 1]; ++e) {
-        const long t = vttri[e];
-        const long v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
+// The membrane tangent into the 3x3 blocks, one thread per stored block (i, j): the thread sums, in
+// ascending order, the contributions of the triangles holding both vertices (the one or two triangles
+// of edge ij; every triangle of i when j = i) in registers and writes the block once, so every block
+// takes the same sums in every run (no atomics, no read-modify-write).  Per triangle, with a and b the
+// corners of i and j: the Gauss-Newton part A B_a^T D_m B_b (B_c the linearised Green strain of corner
+// c: rows g_c0 F0^T, g_c1 F1^T, g_c1 F0^T + g_c0 F1^T) and the stress part A (g_a^T S+ g_b) I3.
+// Component (a, b) of block e is mval[mbase[e] + (3 a + b) mstride].
+__global__ void ms_tangent(const double* __restrict__ rest, const int32_t* __restrict__ tris,
+                           const int32_t* __restrict__ brow, const int32_t* __restrict__ mcol,
+                           const int64_t* __restrict__ btptr, const int32_t* __restrict__ bttri, long nb,
+                           const double* __restrict__ x, double c, double nu, const int64_t* __restrict__ mbase,
+                           long mstride, double* __restrict__ mval) {
+    const long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (e >= nb) return;
+    const int32_t r = brow[e], jc = mcol[e];
+    double acc[9];
+    for (int k = 0; k < 9; ++k) acc[k] = 0.0;
+    for (long q = btptr[e]; q < btptr[e + 1]; ++q) {
+        const long t = bttri[q];
+        const int32_t v[3] = {tris[3 * t], tris[3 * t + 1], tris[3 * t + 2]};
         const int a = v[0] == r ? 0 : (v[1] == r ? 1 : 2);
+        const int b = v[0] == jc ? 0 : (v[1] == jc ? 1 : 2);
         const double G[2][2] = {{rest[5 * t], rest[5 * t + 1]}, {rest[5 * t + 2], rest[5 * t + 3]}};
         const double A = rest[5 * t + 4];
         double F[3][2];
         for (int i = 0; i < 3; ++i) {
-            const double d1 = x[3 * v[1] + i] - x[3 * v[0] + i], d2 = x[3 * v[2] + i] - x[3 * v[0] + i];
+            const double d1 = x[3L * v[1] + i] - x[3L * v[0] + i], d2 = x[3L * v[2] + i] - x[3L * v[0] + i];
             for (int k = 0; k < 2; ++k) F[i][k] = d1 * G[0][k] + d2 * G[1][k];
         }
         const double g[3][2] = {{-G[0][0] - G[1][0], -G[0][1] - G[1][1]}, {G[0][0], G[0][1]}, {G[1][0], G[1][1]}};
-        double Bm[3][9];
-        for (int j = 0; j < 3; ++j)
-            for (int i = 0; i < 3; ++i) {
-                Bm[0][3 * j + i] = g[j][0] * F[i][0];
-                Bm[1][3 * j + i] = g[j][1] * F[i][1];
-                Bm[2][3 * j + i] = g[j][1] * F[i][0] + g[j][0] * F[i][1];
-            }
-        // D_m B (D_m = c [[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu)/2]])
-        double DB[3][9];
-        for (int q = 0; q < 9; ++q) {
-            DB[0][q] = c * (Bm[0][q] + nu * Bm[1][q]);
-            DB[1][q] = c * (nu * Bm[0][q] + Bm[1][q]);
-            DB[2][q] = c * 0.5 * (1.0 - nu) * Bm[2][q];
+        // B rows of corner a (coordinate ca) and D_m B of corner b (coordinate cb),
+        // D_m = c [[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu)/2]]
+        double Ba[3][3], DBb[3][3];
+        for (int k = 0; k < 3; ++k) {
+            Ba[k][0] = g[a][0] * F[k][0];
+            Ba[k][1] = g[a][1] * F[k][1];
+            Ba[k][2] = g[a][1] * F[k][0] + g[a][0] * F[k][1];
+            const double b0 = g[b][0] * F[k][0], b1 = g[b][1] * F[k][1], b2 = g[b][1] * F[k][0] + g[b][0] * F[k][1];
+            DBb[k][0] = c * (b0 + nu * b1);
+            DBb[k][1] = c * (nu * b0 + b1);
+            DBb[k][2] = c * 0.5 * (1.0 - nu) * b2;
         }
         // the stress and its positive semi-definite part from the principal values l1 >= l2
         const double C00 = F[0][0] * F[0][0] + F[1][0] * F[1][0] + F[2][0] * F[2][0];
@@ -303,18 +298,14 @@ __global__ void ms_gn(const double* __restrict__ rest, const int32_t* __restrict
             P01 = w * s12;
             P11 = w * (s22 - l2);
         }
-        for (int b = 0; b < 3; ++b) {
-            double* blk = mval + mbase[ms_find(mrow, mcol, r, int(v[b]))];
-            for (int ca = 0; ca < 3; ++ca)
-                for (int cb = 0; cb < 3; ++cb) {
-                    const int pa = 3 * a + ca, pb = 3 * b + cb;
-                    blk[(3 * ca + cb) * mstride] +=
-                        A * (Bm[0][pa] * DB[0][pb] + Bm[1][pa] * DB[1][pb] + Bm[2][pa] * DB[2][pb]);
-                }
-            const double gsg = g[a][0] * (P00 * g[b][0] + P01 * g[b][1]) + g[a][1] * (P01 * g[b][0] + P11 * g[b][1]);
-            for (int cc = 0; cc < 3; ++cc) blk[4 * cc * mstride] += A * gsg;
-        }
+        for (int ca = 0; ca < 3; ++ca)
+            for (int cb = 0; cb < 3; ++cb)
+                acc[3 * ca + cb] += A * (Ba[ca][0] * DBb[cb][0] + Ba[ca][1] * DBb[cb][1] + Ba[ca][2] * DBb[cb][2]);
+        const double gsg = g[a][0] * (P00 * g[b][0] + P01 * g[b][1]) + g[a][1] * (P01 * g[b][0] + P11 * g[b][1]);
+        for (int cc = 0; cc < 3; ++cc) acc[4 * cc] += A * gsg;
     }
+    double* blk = mval + mbase[e];
+    for (int k = 0; k < 9; ++k) blk[k * mstride] = acc[k];
 }
 
 __global__ void ms_dinv(const double* __restrict__ kdiag, const double* __restrict__ mval,
@@ -842,20 +833,38 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->mdiag.upload(mdiag.data(), mdiag.size(), s);
     ms->mval.alloc(size_t(std::max<int64_t>(nblock_vals, 1)));
     if (ms->mixed) ms->mvalf.alloc(size_t(std::max<int64_t>(nblock_vals, 1)));
-    // each vertex's triangles, ascending (the tangent assembly's fixed order)
-    std::vector<int64_t> vtrow(size_t(nv + 1), 0);
-    for (long t = 0; t < 3 * nt; ++t) ++vtrow[size_t(st.h_tris[size_t(t)]) + 1];
-    for (long i = 0; i < nv; ++i) vtrow[size_t(i + 1)] += vtrow[size_t(i)];
-    std::vector<int32_t> vttri(size_t(std::max(3 * nt, 1L)));
+    // each block's row, and the triangles holding both of its vertices, ascending (the tangent assembly's
+    // fixed order): every triangle adds to the nine blocks of its corner pairs
+    std::vector<int32_t> brow(size_t(std::max<int64_t>(nnz_m, 1)), 0);
+    for (long i = 0; i < nv; ++i)
+        for (int64_t e = mrow[size_t(i)]; e < mrow[size_t(i + 1)]; ++e) brow[size_t(e)] = int32_t(i);
+    auto entry = [&](int32_t i, int32_t j) {
+        auto lo = mcol.begin() + mrow[size_t(i)], hi = mcol.begin() + mrow[size_t(i + 1)];
+        return int64_t(std::lower_bound(lo, hi, j) - mcol.begin());
+    };
+    std::vector<int64_t> btptr(size_t(nnz_m + 1), 0);
+    for (long t = 0; t < nt; ++t)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                ++btptr[size_t(entry(st.h_tris[size_t(3 * t + a)], st.h_tris[size_t(3 * t + b)]) + 1)];
+    for (int64_t e = 0; e < nnz_m; ++e) btptr[size_t(e + 1)] += btptr[size_t(e)];
+    std::vector<int32_t> bttri(size_t(std::max(9 * nt, 1L)));
     {
-        std::vector<int64_t> fill(vtrow.begin(), vtrow.end() - 1);
+        std::vector<int64_t> fill(btptr.begin(), btptr.end() - 1);
         for (long t = 0; t < nt; ++t)
-            for (int a = 0; a < 3; ++a) vttri[size_t(fill[size_t(st.h_tris[size_t(3 * t + a)])]++)] = int32_t(t);
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    bttri[size_t(fill[size_t(entry(st.h_tris[size_t(3 * t + a)], st.h_tris[size_t(3 * t + b)]))]++)] =
+                        int32_t(t);
     }
-    ms->vtrow.alloc(vtrow.size());
-    ms->vtrow.upload(vtrow.data(), vtrow.size(), s);
-    ms->vttri.alloc(vttri.size());
-    ms->vttri.upload(vttri.data(), size_t(3 * nt), s);
+    ms->brow.alloc(brow.size());
+    ms->brow.upload(brow.data(), brow.size(), s);
+    ms->btptr.alloc(btptr.size());
+    ms->btptr.upload(btptr.data(), btptr.size(), s);
+    ms->bttri.alloc(bttri.size());
+    ms->bttri.upload(bttri.data(), size_t(9 * nt), s);
+    // the blocks' padding slots (staged layout) stay zero: the assembly writes every stored block
+    if (ms->mval.n) ms_zero<<<ms_grid(long(ms->mval.n)), kMsBlk, 0, s>>>(ms->mval.p, long(ms->mval.n));
     // per-triangle rest data
     ms->rest.alloc(size_t(std::max(5 * nt, 1L)));
     DevArray<int32_t> bad(1);
@@ -923,11 +932,10 @@ static void tangent_at(shell_sim_s& sim, const double* x, const double* mass, do
     MembraneSolve& m = *sim.ms;
     const long nv = sim.nv, nt = st.nt;
     const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
-    const long nb9 = long(m.mval.n);
-    ms_zero<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, nb9);
-    if (nt > 0)
-        ms_gn<<<ms_grid(nv), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.vtrow.p, m.vttri.p, nv, x, c, st.poisson,
-                                             m.mrow.p, m.mcol.p, m.mbase.p, long(m.mstride), m.mval.p);
+    const long nb9 = long(m.mval.n), nb = long(m.mcol.n);
+    if (nt > 0 && nb > 0)
+        ms_tangent<<<ms_grid(nb), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.brow.p, m.mcol.p, m.btptr.p, m.bttri.p, nb, x,
+                                                  c, st.poisson, m.mbase.p, long(m.mstride), m.mval.p);
     ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, long(m.mstride), mass, sim.pinned.p, nv, dt2,
                                            m.dinv.p);
     if (m.mixed) ms_narrow<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, m.mvalf.p, nb9);
