@@ -249,14 +249,21 @@ def membrane_timing(S, I, torch, reps=20):
     return out
 
 
+MEMBRANE_STAGED_MIN_ROWS = 49152  # the library's staged membrane product from this many vertices up
+
+
 def membrane_product_bytes(nv, nnz_s, nnz_m, mixed=False):
-    """Algorithmic bytes of one coupled product launch in the staged SELL layout: K_s (a 2-byte group-local
-    column id and a value per entry), the membrane tangent's 3x3 blocks (a 2-byte column id and nine values
-    per block), the values float64 (float32 in mixed precision), the mass and the held mask, z and the
-    previous direction read once, the new direction and q written once (float64 vectors in both
-    precisions).  Slice offsets and the groups' column lists (a few bytes per row) are not counted."""
+    """Algorithmic bytes of one coupled product launch: K_s (a column id and a value per entry), the
+    membrane tangent's 3x3 blocks (a column id and nine values per block), the values float64 (float32 in
+    mixed precision), the mass and the held mask, z and the previous direction read once, the new
+    direction and q written once (float64 vectors in both precisions).  The staged SELL layout (from
+    MEMBRANE_STAGED_MIN_ROWS vertices) has 2-byte group-local column ids, its slice offsets and the
+    groups' column lists (a few bytes per row) not counted; the CSR layout has 4-byte ids and two 8-byte
+    row offsets per row."""
     real = 4 if mixed else 8
-    return (2 + real) * nnz_s + (2 + 9 * real) * nnz_m + nv * (8 + 1 + 48 + 48)
+    if nv >= MEMBRANE_STAGED_MIN_ROWS:
+        return (2 + real) * nnz_s + (2 + 9 * real) * nnz_m + nv * (8 + 1 + 48 + 48)
+    return 16 * (nv + 1) + (4 + real) * nnz_s + (4 + 9 * real) * nnz_m + nv * (8 + 1 + 48 + 48)
 
 
 def membrane_step_timing(S, I, torch, sizes=(64, 256, 1024), steps=2):
@@ -292,7 +299,8 @@ def membrane_step_timing(S, I, torch, sizes=(64, 256, 1024), steps=2):
             halvings=[int(c[1]) for st in stats for c in st["counts"]],
             grad_ratio=[st["grad_norm"] / max(st["grad_norm0"], 1e-300) for st in stats],
             back_to_back_ms=dict(force=kt["force_ms"], product=kt["spmv_ms"], update=kt["update_ms"]),
-            product=dict(kernel="ms_iter_product_staged", bytes_per_launch=pbytes, achieved_gbs=gbs,
+            product=dict(kernel="ms_iter_product_staged" if mesh.nv >= MEMBRANE_STAGED_MIN_ROWS else "ms_iter_product",
+                         bytes_per_launch=pbytes, achieved_gbs=gbs,
                          frac=gbs / HBM_PEAK_GBS if gbs else None, nnz_s=nnz_s, blocks=nnz_m))
         pb.close()
         print(f"[bench] membrane step {n} {'mixed' if mixed else 'fp64'}: {ms:.1f} ms/step, "
