@@ -218,6 +218,9 @@ struct SolveDesc {
     int32_t rz_lo, rz_hi;           // the same for the update launch (and the solve's first kernel)
     int64_t nv, ngroups;
     double dt, dt2, grav[3], rtol2;
+    double tol2_abs[3];             // > 0: the stop test's bound on r.r as given (a refinement pass keeps
+                                    // the first pass's); 0: rtol2 times the initial r.r
+    const double* rq;               // mixed refinement: the float64 product (M + dt^2 K_s) y64
     int32_t replay, target[3];
     int32_t partial_held;           // some vertex has only part of its coordinates held
 };
@@ -365,6 +368,7 @@ struct shell_sim_s {
     hipStream_t last_stream = nullptr;
     shell::DevArray<double> x, v, xt, xhat, g, mass, y, r;
     shell::DevArray<double> y64;         // mixed only: float64 part of the PCG increment
+    shell::DevArray<double> rq;          // mixed only, made on first use: (M + dt^2 K_s) y64 in float64
     shell::DevArray<double> f;           // float64 forces (or float32 in mixed, sized in doubles)
     shell::DevArray<double> dinv;        // [nv] (float in mixed)
     shell::DevArray<double> mq;          // [nv] mass for the product, -1 on fixed rows (float in mixed)

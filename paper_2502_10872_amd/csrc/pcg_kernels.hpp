@@ -228,7 +228,7 @@ __device__ __forceinline__ ProductState product_state(const SolveDesc& d, const 
     int any = 0;
     if (t == 0) {
         for (int c = 0; c < 3; ++c) {
-            const double tol2 = d.rtol2 * tot[3 + c];
+            const double tol2 = d.tol2_abs[c] > 0.0 ? d.tol2_abs[c] : d.rtol2 * tot[3 + c];
             const int act = (0 < d.target[c]) && (d.replay || tot[3 + c] > tol2);
             r.beta[c] = 0.0;
             any |= act;
@@ -737,6 +737,62 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(const SolveDesc* __restrict__
             r[3 * i + c] = ri;
             y[3 * i + c] = VR(0);
             if constexpr (kStoredZ<VR>) G(d.y64)[3 * i + c] = 0.0;
+            if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zi;
+            acc[c] += ri * double(zi);
+            acc[3 + c] += ri * ri;
+        }
+    }
+    if (cur >= 0) flush_partials<6>(bin_set(descs[cur], 1, kSetRz), acc, sh);
+}
+
+// Mixed refinement, first kernel: the float part of the increment folded into its float64 part,
+// y64 += y, y = 0, so that y64 holds the whole increment for the float64 product.
+template <typename VR>
+__global__ __launch_bounds__(kBlk) void k_pcg_fold(const SolveDesc* __restrict__ descs, const WorkItem* __restrict__ items,
+                                                   long nitems) {
+    const long it = xcd_logical(blockIdx.x, gridDim.x);
+    if (it >= nitems) return;
+    const WorkItem wi = items[it];
+    const SolveDesc& d = descs[wi.mesh];
+    const long i = long(wi.unit) * kBlk + threadIdx.x;
+    if (i >= d.nv) return;
+    gbl<VR>* y = G(static_cast<VR*>(d.y));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        G(d.y64)[3 * i + c] += double(y[3 * i + c]);
+        y[3 * i + c] = VR(0);
+    }
+}
+
+// Mixed refinement, second kernel (residual replacement): the true residual of the increment,
+// r = -g - (M + dt^2 K_s) y64 with the float64 matrix (zero on held coordinates), restarts the PCG; r.z
+// and r.r into the partials read by the first product, as k_pcg_init does.  Launched with the update
+// kernel's grid and walk.
+template <typename VR>
+__global__ __launch_bounds__(kBlk) void k_pcg_refine_init(const SolveDesc* __restrict__ descs,
+                                                          const WorkItem* __restrict__ items, long nitems, int per) {
+    long first, last;
+    if (!item_range(nitems, per, first, last)) return;
+    __shared__ double sh[6 * (kBlk / 64)];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    int cur = -1;
+    for (long it = first; it < last; ++it) {
+        const WorkItem wi = items[it];
+        const SolveDesc& d = descs[wi.mesh];
+        if (wi.mesh != cur) {
+            if (cur >= 0) flush_partials<6>(bin_set(descs[cur], 1, kSetRz), acc, sh);
+            cur = wi.mesh;
+        }
+        const long i = long(wi.unit) * kBlk + threadIdx.x;
+        if (i >= d.nv) continue;
+        const VR di = G(static_cast<const VR*>(d.dinv))[i];
+        const unsigned held = d.pinned[i];
+        gbl<double>* r = G(d.r);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double ri = (held >> c & 1u) ? 0.0 : -G(static_cast<const double*>(d.g))[3 * i + c] - G(d.rq)[3 * i + c];
+            const VR zi = di * VR(ri);
+            r[3 * i + c] = ri;
             if constexpr (kStoredZ<VR>) G(reinterpret_cast<VR*>(d.z))[3 * i + c] = zi;
             acc[c] += ri * double(zi);
             acc[3 + c] += ri * ri;

@@ -21,6 +21,7 @@
 // diagonal and the vectors p, q, z and f; the increment y in float32 folded into float64 every 16
 // iterations; float64 residual r, all dot products and the Newton residual.
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 
@@ -378,7 +379,14 @@ struct MeshStep {
     shell_step_stats_t stats{};
     bool budget = false;
     double gn0 = 0, gn = 0;
+    double tol2[3] = {0, 0, 0};  // the current solve's bound on r.r (kept by its refinement passes)
 };
+
+// Mixed precision: a tolerance-mode solve asked for a relative residual below this gets residual
+// replacement passes (at most kRefinePasses), since the float32 products let the float64 recurrence
+// residual drift from the true one by about this much.
+constexpr double kRefineBelowRtol = 1e-6;
+constexpr int kRefinePasses = 2;
 
 // The step of every mesh of the batch: Newton rounds over the meshes still iterating; each round is
 // one force/residual launch set, then one PCG loop over the meshes that still need a solve.
@@ -469,65 +477,126 @@ shell_status_t step_impl(shell_batch_s& b, const shell_step_params_t* prms, int 
             solve.push_back(m);
         }
         if (solve.empty()) break;
-        // per-mesh PCG targets of this Newton iteration and the slot ranges of its launch shape (upload()
-        // drains the stream first, so the staging is idle)
-        ib.build(b.sims, solve);
-        L = upload(b, ib, s, wg);
-        for (int m : solve) {
-            const shell_step_params_t& p = *ms[size_t(m)].prm;
-            SolveDesc& d = b.sdesc_host[m];
-            d.replay = p.mode == SHELL_PCG_REPLAY;
-            for (int c = 0; c < 3; ++c) d.target[c] = d.replay ? p.replay_counts[3 * k + c] : p.max_pcg;
-        }
-        set_slot_ranges(b, L, ib);
-        upload_descs(b, s);
-        k_pcg_init<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, L.per_u);
-        timed_launch(b.prof.get(), b.prof && b.prof->every > 0, SHELL_PHASE_PRODUCT, s,
-                     [&](hipEvent_t e0, hipEvent_t e1) {
-                         hipExtLaunchKernelGGL(k_pcg_spmv<VR, MR>, dim3(unsigned(L.pcg_grid)), dim3(kBlk),
-                                               uint32_t(L.lds_spmv), s, e0, e1, 0, L.sdesc, L.rows, L.nrows, 0L,
-                                               L.per);
-                     });
-        SHELL_HIP(hipGetLastError());
-        long t = 0;  // the last product launched
-        bool all_replay = true;
-        int most = 0, first_chunk = 8, max_chunk = 128;
-        for (int m : solve) {
-            const shell_step_params_t& p = *ms[size_t(m)].prm;
-            all_replay &= p.mode == SHELL_PCG_REPLAY;
-            for (int c = 0; c < 3; ++c) most = std::max(most, b.sdesc_host[m].target[c]);
-            if (p.chunk > 0) first_chunk = max_chunk = p.chunk;
-        }
-        if (all_replay) {
-            t = pcg_iterations<VR, MR>(b, L, t, most, s, graphs);
-            read_states(b, s);
-        } else {
-            read_states(b, s);
-            int chunk = first_chunk;
-            for (;;) {
-                bool done = true;
-                for (int m : solve) done &= b.state_host[2 * m + ((t + 1) & 1)].done != 0;
-                if (done) break;
-                t = pcg_iterations<VR, MR>(b, L, t, chunk, s, graphs);
-                read_states(b, s);
-                chunk = std::min(2 * chunk, max_chunk);
+        // One PCG solve over the meshes of `set`: per-mesh targets and the slot ranges of its launch shape
+        // (upload() drains the stream first, so the staging is idle), the first kernel (from r = -g, or
+        // for a refinement pass from the true residual of the increment so far), the first product, then
+        // chunks until every mesh is done.  Returns the last product launched.
+        auto run_pcg = [&](const std::vector<int>& set, bool refine) -> long {
+            ib.build(b.sims, set);
+            L = upload(b, ib, s, wg);
+            for (int m : set) {
+                const shell_step_params_t& p = *ms[size_t(m)].prm;
+                SolveDesc& d = b.sdesc_host[m];
+                d.replay = p.mode == SHELL_PCG_REPLAY;
+                for (int c = 0; c < 3; ++c) {
+                    d.target[c] = d.replay ? p.replay_counts[3 * k + c] : p.max_pcg;
+                    d.tol2_abs[c] = refine ? ms[size_t(m)].tol2[c] : 0.0;
+                }
             }
-        }
-        std::vector<int> next;
-        for (int m : solve) {
+            set_slot_ranges(b, L, ib);
+            upload_descs(b, s);
+            if (refine) {
+                k_pcg_fold<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
+                for (int m : set) {
+                    shell_sim_s& sim = *b.sims[size_t(m)];
+                    const SolveDesc& d = b.sdesc_host[m];
+                    launch_apply(*sim.h, d.mass, d.dt2, sim.y64.p, sim.rq.p, s);
+                }
+                k_pcg_refine_init<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, L.per_u);
+            } else {
+                k_pcg_init<VR><<<L.upd_grid, kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows, L.per_u);
+            }
+            timed_launch(b.prof.get(), b.prof && b.prof->every > 0, SHELL_PHASE_PRODUCT, s,
+                         [&](hipEvent_t e0, hipEvent_t e1) {
+                             hipExtLaunchKernelGGL(k_pcg_spmv<VR, MR>, dim3(unsigned(L.pcg_grid)), dim3(kBlk),
+                                                   uint32_t(L.lds_spmv), s, e0, e1, 0, L.sdesc, L.rows, L.nrows,
+                                                   0L, L.per);
+                         });
+            SHELL_HIP(hipGetLastError());
+            long t = 0;  // the last product launched
+            bool all_replay = true;
+            int most = 0, first_chunk = 8, max_chunk = 128;
+            for (int m : set) {
+                const shell_step_params_t& p = *ms[size_t(m)].prm;
+                all_replay &= p.mode == SHELL_PCG_REPLAY;
+                for (int c = 0; c < 3; ++c) most = std::max(most, b.sdesc_host[m].target[c]);
+                if (p.chunk > 0) first_chunk = max_chunk = p.chunk;
+            }
+            if (all_replay) {
+                t = pcg_iterations<VR, MR>(b, L, t, most, s, graphs);
+                read_states(b, s);
+            } else {
+                read_states(b, s);
+                int chunk = first_chunk;
+                for (;;) {
+                    bool done = true;
+                    for (int m : set) done &= b.state_host[2 * m + ((t + 1) & 1)].done != 0;
+                    if (done) break;
+                    t = pcg_iterations<VR, MR>(b, L, t, chunk, s, graphs);
+                    read_states(b, s);
+                    chunk = std::min(2 * chunk, max_chunk);
+                }
+            }
+            return t;
+        };
+        // Counts a finished solve (or refinement pass) into the Newton iteration's statistics; false when
+        // the mesh's state went non-finite.  Returns the iterations of the pass in `its`.
+        auto account = [&](int m, long t, int& its) {
             MeshStep& st = ms[size_t(m)];
             const PcgState& ps = b.state_host[2 * m + ((t + 1) & 1)];
+            its = 0;
             if (ps.nonfinite) {
                 st.stats.status = SHELL_E_NONFINITE;
-                continue;
+                return false;
             }
             st.budget |= ps.budget != 0;
             for (int c = 0; c < 3; ++c) {
-                st.stats.counts[k][c] = ps.iters[c];
+                st.stats.counts[k][c] += ps.iters[c];
                 st.stats.pcg_total += ps.iters[c];
+                its += ps.iters[c];
+                st.tol2[c] = ps.tol2[c] > 0.0 ? ps.tol2[c] : DBL_MIN;
             }
+            return true;
+        };
+        long t = run_pcg(solve, false);
+        std::vector<int> next, refine;
+        for (int m : solve) {
+            int its = 0;
+            if (!account(m, t, its)) continue;
+            MeshStep& st = ms[size_t(m)];
             st.stats.newton_iters++;
             next.push_back(m);
+            const shell_step_params_t& p = *st.prm;
+            if (b.precision == SHELL_PREC_MIXED && p.mode == SHELL_PCG_TOLERANCE && p.pcg_rtol < kRefineBelowRtol &&
+                !st.budget)
+                refine.push_back(m);
+        }
+        // Mixed precision asked for more than the float32 products can give: residual replacement.  The
+        // float64 recurrence residual drifts from the true one as float32 products accumulate, so the
+        // true residual of the increment is formed with the float64 matrix and the PCG restarted from it,
+        // with the first pass's bound on r.r; a pass that starts within the bound takes no iteration.
+        const bool refined = !refine.empty();
+        for (int pass = 0; pass < kRefinePasses && !refine.empty(); ++pass) {
+            for (int m : refine) {
+                shell_sim_s& sim = *b.sims[size_t(m)];
+                if (!sim.rq.p) sim.rq.alloc(size_t(3 * sim.nv));
+                b.sdesc_host[m].rq = sim.rq.p;
+            }
+            t = run_pcg(refine, true);
+            std::vector<int> again;
+            for (int m : refine) {
+                int its = 0;
+                if (!account(m, t, its)) {
+                    next.erase(std::remove(next.begin(), next.end(), m), next.end());
+                    continue;
+                }
+                if (its > 0 && !ms[size_t(m)].budget) again.push_back(m);
+            }
+            refine = again;
+        }
+        if (refined) {  // the Newton update below takes the launch shape of the whole solve again
+            ib.build(b.sims, solve);
+            L = upload(b, ib, s, wg);
         }
         if (qs && qs->eps_u > 0.0) {
             k_absmax<VR><<<xcd_grid(L.nrows), kBlk, 0, s>>>(L.sdesc, L.rows, L.nrows);
