@@ -256,7 +256,9 @@ typedef struct {
     double pcg_rtol;       /* per column: stop when ||r|| <= pcg_rtol ||b||.  Mixed precision uses it for
                               its float32 inner solve as well (there is no separate inner tolerance): the
                               recurrence residual r is float64, the Newton loop re-forms the residual in
-                              float64 each iteration */
+                              float64 each iteration; below 1e-6 (tolerance mode), a converged solve is
+                              restarted from its true residual, formed with the float64 K_s, at most
+                              twice (residual replacement; the passes' iterations count in the stats) */
     int32_t mode;          /* shell_pcg_mode_t */
     int32_t chunk;         /* PCG iterations launched between host convergence checks; 0 = default */
     int32_t pcg_workgroups; /* work-groups of each PCG kernel (each takes consecutive 512-row groups),
