@@ -869,8 +869,9 @@ def main(argv=None):
     ap.add_argument("--max-newton", type=int, default=4)
     ap.add_argument("--pcg-rtol", type=float, default=1e-2)
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel of the isolated back-to-back timing")
-    ap.add_argument("--sample-every", type=int, default=16,
-                    help="in the timed steps, time every n-th PCG iteration's kernels with HIP events")
+    ap.add_argument("--sample-every", type=int, default=17,
+                    help="in the timed steps, time every n-th PCG iteration's kernels with HIP events (17: prime "
+                         "to the 16-iteration period of the mixed update's fold, so every phase of it is sampled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hot-path-only", action="store_true",
                     help="skip the quasi-static solves and the membrane (their launches are kept out of the "

@@ -218,11 +218,11 @@ struct SolveDesc {
     int32_t rz_lo, rz_hi;           // the same for the update launch (and the solve's first kernel)
     int64_t nv, ngroups;
     double dt, dt2, grav[3], rtol2;
+    int32_t replay, target[3];
+    int32_t partial_held;           // some vertex has only part of its coordinates held
     double tol2_abs[3];             // > 0: the stop test's bound on r.r as given (a refinement pass keeps
                                     // the first pass's); 0: rtol2 times the initial r.r
     const double* rq;               // mixed refinement: the float64 product (M + dt^2 K_s) y64
-    int32_t replay, target[3];
-    int32_t partial_held;           // some vertex has only part of its coordinates held
 };
 
 struct WorkItem {
