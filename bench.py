@@ -59,11 +59,11 @@ def algorithmic_bytes(info: dict, hinfo: dict, precision: int, clamp_bias: bool 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sphere_cap_1024_ss_hbm_traffic.md")
 # the device code of the measured kernels, the layouts they read (host_mesh.cpp and precompute.hip build
-# them) and their launch shapes (solver.hip)
+# them, internal.hpp declares the descriptors) and their launch shapes (solver.hip)
 TRAFFIC_SOURCES = ["paper_2502_10872_amd/csrc/spmv.hpp", "paper_2502_10872_amd/csrc/pcg_kernels.hpp",
                    "paper_2502_10872_amd/csrc/forces.hip", "paper_2502_10872_amd/csrc/host_mesh.cpp",
                    "paper_2502_10872_amd/csrc/devmath.hpp", "paper_2502_10872_amd/csrc/precompute.hip",
-                   "paper_2502_10872_amd/csrc/solver.hip"]
+                   "paper_2502_10872_amd/csrc/solver.hip", "paper_2502_10872_amd/csrc/internal.hpp"]
 
 
 def sources_digest(files=TRAFFIC_SOURCES) -> str:
