@@ -526,6 +526,9 @@ __global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
     }
 }
 
+// The update sums the product's partials itself (FUSED) up to this many partials.
+constexpr long kMsFuseAlphaMax = 256;
+
 // p.q from the product's partials (one work-group, fixed order), then alpha = r.z / p.q
 __global__ __launch_bounds__(kMsBlk) void ms_iter_alpha(const double* __restrict__ ppart, long npart,
                                                         double* __restrict__ scal) {
@@ -538,14 +541,27 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_alpha(const double* __restrict
     }
 }
 
-// y += alpha p, r -= alpha q, z = D^-1 r (alpha from ms_iter_alpha); partials r.z and r.r
+// y += alpha p, r -= alpha q, z = D^-1 r; partials r.z and r.r.  alpha from ms_iter_alpha, or, with FUSED
+// (few product partials), summed by every work-group itself from the product's partials in the same fixed
+// order as ms_iter_alpha sums them (the same bits), which saves that launch on small meshes.
+template <bool FUSED>
 __global__ __launch_bounds__(kMsBlk) void ms_iter_update(const double* __restrict__ scal, const double* __restrict__ p,
                                                          const double* __restrict__ q, const double* __restrict__ dinv,
                                                          double* __restrict__ y, double* __restrict__ r,
                                                          double* __restrict__ z, long nv, double* __restrict__ part,
-                                                         long ngroups) {
+                                                         long ngroups, const double* __restrict__ ppart, long npart) {
     if (scal[S_ACTIVE] == 0.0) return;
-    const double al = scal[S_ALPHA];
+    double al;
+    if constexpr (FUSED) {
+        __shared__ double al_sh;
+        double pq[1];
+        ms_totals<1>(ppart, npart, pq);
+        if (threadIdx.x == 0) al_sh = pq[0] != 0.0 ? scal[S_RZ] / pq[0] : 0.0;
+        __syncthreads();
+        al = al_sh;
+    } else {
+        al = scal[S_ALPHA];
+    }
     double v[2] = {0.0, 0.0};
     for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < nv; i += long(gridDim.x) * blockDim.x)
         for (int c = 0; c < 3; ++c) {
@@ -982,8 +998,14 @@ static void pcg_iteration(MembraneSolve& m, const double* mass, const uint8_t* p
     double* pnew = m.pswap ? m.p.p : m.p2.p;
     const long np = launch_product(m, mass, pinned, nv, dt2, pold, pnew, s);
     const unsigned ug = ms_update_grid(nv);
-    ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, m.scal.p);
-    ms_iter_update<<<ug, kMsBlk, 0, s>>>(m.scal.p, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p, long(ug));
+    if (np <= kMsFuseAlphaMax) {
+        ms_iter_update<true><<<ug, kMsBlk, 0, s>>>(m.scal.p, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p,
+                                                   long(ug), m.ppart.p, np);
+    } else {
+        ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, m.scal.p);
+        ms_iter_update<false><<<ug, kMsBlk, 0, s>>>(m.scal.p, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
+                                                    m.part.p, long(ug), m.ppart.p, np);
+    }
     ms_iter_finish<<<1, kMsBlk, 0, s>>>(m.part.p, long(ug), m.scal.p);
     m.pswap = !m.pswap;
 }
@@ -1269,9 +1291,14 @@ void membrane_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_t
     out.spmv_ms = elapsed();
     ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, m.scal.p);
     SHELL_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < reps; ++k)
-        ms_iter_update<<<ug, kMsBlk, 0, s>>>(m.scal.p, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p,
-                                             long(ug));
+    for (int k = 0; k < reps; ++k) {
+        if (np <= kMsFuseAlphaMax)
+            ms_iter_update<true><<<ug, kMsBlk, 0, s>>>(m.scal.p, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
+                                                       m.part.p, long(ug), m.ppart.p, np);
+        else
+            ms_iter_update<false><<<ug, kMsBlk, 0, s>>>(m.scal.p, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
+                                                        m.part.p, long(ug), m.ppart.p, np);
+    }
     SHELL_HIP(hipEventRecord(e1, s));
     out.update_ms = elapsed();
     SHELL_HIP(hipGetLastError());
