@@ -87,6 +87,80 @@ def test_converged_newton_iterations_on_the_256_cap(cap256_newton, precision, ne
     assert err <= bound and emax <= vbound
 
 
+def _exact_first_iterate(mesh, model, dt):
+    """x_hat + y with (M + dt^2 K_s)_ff y = dt^2 f(x_hat)_f solved exactly (oracle force and K_s, sparse LU):
+    the first Newton iterate of a step from rest under gravity."""
+    ost = O.Stencils(model, mesh.X, mesh.tris, MAT["young"], MAT["poisson"], MAT["thickness"])
+    rowptr, col, val = ost.hessian()
+    K = sp.csr_matrix((val, col, rowptr), shape=(mesh.nv, mesh.nv))
+    mass = O.mass(mesh.X, mesh.tris, MAT["density"], MAT["thickness"])
+    free = np.flatnonzero(mesh.pinned == 0)
+    xhat = mesh.X.copy()
+    xhat[free] += dt * dt * np.array(I.GRAVITY)
+    f, _ = ost.forces(xhat)
+    A = (sp.diags(mass) + dt * dt * K).tocsr()[free][:, free].tocsc()
+    x1 = xhat.copy()
+    x1[free] += spl.splu(A).solve(dt * dt * f[free])
+    return x1
+
+
+def test_residual_replacement_in_a_mixed_batch():
+    """A mixed batch whose members ask for different PCG tolerances: the two asking for rtol 1e-10 take
+    residual-replacement passes (a relaunch over those members only) and land on the exact first Newton
+    iterate to 1e-6; the one asking for 1e-3 takes none, and the Newton update still reaches it (within
+    the looser solve's own distance, 1e-2)."""
+    dt = 1.0 / 30.0
+    cases = [(I.sphere_cap_mesh(64, 1.5, model="SS"), "SS", 1e-10), (I.cylinder_mesh(48, model="FS"), "FS", 1e-3),
+             (I.plate_mesh(40, model="EP"), "EP", 1e-10)]
+    probs = [S.Problem(m, MAT, model=mdl, precision=S.SHELL_PREC_MIXED) for m, mdl, _ in cases]
+    keep = []
+    try:
+        plist = []
+        for _, _, rtol in cases:
+            p, k = S.step_params(dt, max_newton=1, newton_rtol=0.0, pcg_rtol=rtol)
+            plist.append(p)
+            keep.append(k)
+        batch = S.shell_batch_create([pb.sim for pb in probs])
+        try:
+            rc, stats = S.shell_batch_step(batch, plist, len(plist))
+        finally:
+            S.shell_destroy_batch(batch)
+        for (m, mdl, rtol), pb, st in zip(cases, probs, stats):
+            assert st["newton_iters"] == 1
+            x, _, _ = S.shell_sim_get_state(pb.sim, m.nv)
+            xe = _exact_first_iterate(m, mdl, dt)
+            err = rel(x - m.X, xe - m.X)
+            print(f"{mdl} rtol {rtol:g}: {err:.2e} from the exact iterate, {st['pcg_total']} PCG iterations")
+            assert err <= (1e-6 if rtol < 1e-6 else 1e-2), (mdl, err)
+    finally:
+        for pb in probs:
+            pb.close()
+
+
+def test_residual_replacement_in_the_quasi_static_solve():
+    """The mixed quasi-static solve (no mass: K_s alone, the load in the residual) of the clamped FVM plate
+    with its boundary ring held, one Newton solve at PCG rtol 1e-10 (residual replacement on), against the
+    oracle's FP64 solve.  From rest the mixed plate force is exactly zero (it is formed rest-relative), so
+    the residual is the load itself, and the replacement passes, which form the true residual with the
+    float64 K_s, carry the float32 inner solves to the float64 solution of this linear problem: 1e-9
+    (observed 5e-12; without them the first pass's float32 recurrence would stop near 1e-6)."""
+    m = I.plate_mesh(33, 8.0, 0.2, 5, "FP", "ring")
+    cl = I.boundary_edges(m.tris)
+    load = np.zeros((m.nv, 3))
+    load[:, 2] = -9.81 * O.mass(m.X, m.tris, 1.0, 1.0)
+    mat = dict(MAT, young=2e11, poisson=0.3, thickness=0.01)
+    ost = O.Stencils("FP", m.X, m.tris, mat["young"], mat["poisson"], mat["thickness"], clamped=cl)
+    xo, _, _ = O.solve_static(ost, m.pinned, load, eps_f=0.0, max_newton=1, pcg_rtol=1e-13)
+    with S.Problem(m, mat, model="FP", precision=S.SHELL_PREC_MIXED, block_vertices=128, clamped_edges=cl) as pb:
+        rc, gs = S.shell_solve_static(pb.sim, load, eps_f=0.0, max_newton=1, pcg_rtol=1e-10)
+        x, _, _ = S.shell_sim_get_state(pb.sim, m.nv)
+    err = rel(x - m.X, xo - m.X)
+    print(f"mixed static solve with residual replacement: {err:.2e}, {gs['pcg_total']} PCG iterations")
+    assert gs["newton_iters"] == 1 and np.isfinite(x).all()
+    assert err <= 1e-9, err
+    assert np.array_equal(x[m.pinned != 0], m.X[m.pinned != 0])
+
+
 def test_newton_budget_is_flagged():
     """A step that stops at max_newton before its residual test held says so; a plate, whose single
     solve is exact, does not."""
