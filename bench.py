@@ -729,12 +729,13 @@ def step_error(S, torch, mesh, pb64, pbm, params, steps, short_iters=200):
 
     full:  from the state the FP64 trajectory reached, the FP64 path steps in tolerance mode; then the
            FP64 path again and the mixed path, both from that same state, replay its Newton and PCG
-           counts.  The FP64 rerun differs from the first run only in the summation order of the
-           atomically binned dot products; thousands of Krylov iterations stopped at a 1e-2 residual
-           amplify that into a different inexact step, so `fp64_rerun` is the scale against which the
-           mixed figure is read.
+           counts.  The FP64 step is bitwise reproducible, so the rerun lands on the same bits; thousands
+           of Krylov iterations stopped at a 1e-2 residual amplify the mixed path's rounding into a
+           different inexact step of the same residual tolerance.
     short: one Newton iteration with `short_iters` replayed PCG iterations per coordinate from the same
-           state, where the difference is the precision alone."""
+           state, where the difference is the precision alone.
+    converged: one Newton iteration from rest with both solves run to PCG rtol 1e-10 (the mixed one with
+           its residual-replacement passes), the two precisions at a matched residual."""
     zero = np.zeros_like(mesh.X)
 
     def rel_disp(x, ref, x0):
@@ -774,10 +775,22 @@ def step_error(S, torch, mesh, pb64, pbm, params, steps, short_iters=200):
         short.append(rel_disp(xm, x64, x0))
         short_rerun.append(rel_disp(x64b, x64, x0))
         S.shell_sim_set_state(pb64.sim, x64, v64, s64)
+    cp, _keep = S.step_params(params.dt, gravity=tuple(params.gravity), max_newton=1, newton_rtol=0.0,
+                              pcg_rtol=1e-10)
+    conv_pcg = {}
+    for name, pb in (("fp64", pb64), ("mixed", pbm)):
+        S.shell_sim_set_state(pb.sim, mesh.X, zero, 0)
+        rc, st = S.shell_step_implicit(pb.sim, cp)
+        conv_pcg[name] = int(st["pcg_total"])
+    x64, _, _ = S.shell_sim_get_state(pb64.sim, mesh.nv)
+    xm, _, _ = S.shell_sim_get_state(pbm.sim, mesh.nv)
+    conv = rel_disp(xm, x64, mesh.X)
     print(f"[bench] mixed vs fp64 displacement error per step: full {full} (fp64 rerun {rerun}), short {short} "
-          f"(fp64 rerun {short_rerun})", file=sys.stderr, flush=True)
+          f"(fp64 rerun {short_rerun}); one converged Newton iteration {conv:.2e} (PCG {conv_pcg})",
+          file=sys.stderr, flush=True)
     return dict(full_step_replayed_counts=full, full_step_fp64_rerun=rerun, one_newton_200_pcg=short,
-                one_newton_200_pcg_fp64_rerun=short_rerun)
+                one_newton_200_pcg_fp64_rerun=short_rerun, one_newton_converged=conv,
+                one_newton_converged_pcg_coord_iters=conv_pcg)
 
 
 def stream_copy_gbs(torch):
