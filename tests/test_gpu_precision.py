@@ -161,6 +161,25 @@ def test_residual_replacement_in_the_quasi_static_solve():
     assert np.array_equal(x[m.pinned != 0], m.X[m.pinned != 0])
 
 
+def test_mixed_matches_fp64_at_a_matched_residual_on_the_1M_cap():
+    """The headline mesh (1024 x 1024 sphere cap, SS, ring held, dt = 1/30, from rest): one Newton iteration
+    with both solves run to PCG rtol 1e-10 (the mixed one with its residual-replacement passes) gives the
+    same displacement to 1e-6 (observed 2.4e-8): at a matched residual the precisions differ only by the
+    float32 force's rounding in the right-hand side."""
+    mesh = I.workload_sphere_cap(1024, "SS")
+    out = {}
+    for prec in (S.SHELL_PREC_FP64, S.SHELL_PREC_MIXED):
+        with S.Problem(mesh, MAT, precision=prec) as pb:
+            params, _keep = S.step_params(1.0 / 30.0, max_newton=1, newton_rtol=0.0, pcg_rtol=1e-10)
+            rc, st = S.shell_step_implicit(pb.sim, params)
+            assert rc == S.SHELL_OK and st["newton_iters"] == 1
+            out[prec] = S.shell_sim_get_state(pb.sim, mesh.nv)[0]
+    err = rel(out[S.SHELL_PREC_MIXED] - mesh.X, out[S.SHELL_PREC_FP64] - mesh.X)
+    emax = relmax(out[S.SHELL_PREC_MIXED] - mesh.X, out[S.SHELL_PREC_FP64] - mesh.X)
+    print(f"1M cap, one converged Newton iteration: mixed vs FP64 {err:.2e} norm-wise, {emax:.2e} per vertex")
+    assert err <= 1e-6 and emax <= 2e-6, (err, emax)
+
+
 def test_newton_budget_is_flagged():
     """A step that stops at max_newton before its residual test held says so; a plate, whose single
     solve is exact, does not."""
