@@ -239,6 +239,11 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
     TileAccT<MIX ? 1 : 2> acc(smem_raw, d.T);
     acc.clear(3 * nown);
     const double inv_scale = acc.kUnit / d.fscale;  // counts per force unit, a power of two: exact
+    // The triangle models' forces are linear in kb: scaled by inv_scale (exactly: a power of two) it gives
+    // their forces, and energies, in counts directly, the same values without a multiply per component.
+    const R kbt = EDGE ? kb : R(d.kb * inv_scale);
+    const double count_unit = EDGE ? inv_scale : 1.0;    // counts per unit of the stencil forces below
+    const double en_unit = EDGE ? 1.0 : 1.0 / inv_scale;  // energy units per unit of their energies
     __syncthreads();
     double e_own = 0.0;
     // a tile's list starts on a 64-stencil block and the work-group's stride is a whole number of
@@ -474,11 +479,11 @@ __global__ __launch_bounds__(kMaxForceThreads) void force_tiles(const ForceDesc*
                     }
                 }
             }
-            tri_force<R, SHELL>(dd, C, Bm, de, n, ilu, kb, nu, fs, en);
+            tri_force<R, SHELL>(dd, C, Bm, de, n, ilu, kbt, nu, fs, en);
         }
         // the tile that owns vertex 1 of the stencil counts its energy
-        if (unsigned(in.vid[0] - base) < unsigned(nown)) e_own += double(en);
-        lds_add_stencil<!(SHELL && !EDGE), K>(acc, in.vid, base, nown, fs, inv_scale);
+        if (unsigned(in.vid[0] - base) < unsigned(nown)) e_own += double(en) * en_unit;
+        lds_add_stencil<!(SHELL && !EDGE), K>(acc, in.vid, base, nown, fs, count_unit);
     };
     const long e0 = d.boff[2 * blk], e1 = d.boff[2 * blk + 1];
     for (long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
