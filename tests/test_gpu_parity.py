@@ -637,6 +637,42 @@ def test_membrane_step_staged_product_matches_oracle(prec):
     assert mutual[0] <= mbound and mutual[1] <= mbound, mutual
 
 
+def test_membrane_step_staged_product_with_held_coordinates_matches_oracle():
+    """The staged product's held rows: on the 49729-vertex cylinder patch, besides its pinned ends, every
+    7th vertex has z held and every 11th x held (bit c holds coordinate c), so rows mix free and held
+    coordinates across the row groups.  One step of two Newton iterations with 40 replayed PCG iterations
+    each: the staged and the CSR layouts reach the oracle to 1e-10, agree with each other to 1e-12, and
+    leave every held coordinate at its rest value bit for bit.  The count stays at 40: the held points,
+    kept at rest while their neighbours fall, stretch the membrane (the first gradient is 23 times that
+    of the unconstrained patch), and on that stiffer system unconverged CG iterates lose their agreement
+    once orthogonality is lost.  At 150 iterations (1793 are needed to converge) even the two GPU layouts,
+    which differ only in the product's summation order, are 5e-7 apart, against 1e-14 at 40."""
+    mesh = I.cylinder_mesh(_STAGED_N, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+    held = np.zeros(mesh.nv, np.uint8)
+    held[::7] |= 4
+    held[::11] |= 1
+    osim = O.MembraneSim(oracle_stencils("SS", mesh), MAT, mesh.pinned, held=held)
+    osim.step(1 / 60, max_newton=2, newton_rtol=1e-12, pcg_rtol=1e-13, replay_pcg=[40, 40], replay_halvings=[0, 0])
+    mask = O.held_mask(mesh.pinned, held)
+    res = {}
+    for direct in (False, True):
+        flags = S.SHELL_FLAG_MEMBRANE | (S.SHELL_FLAG_DIRECT_PRODUCT if direct else 0)
+        with S.Problem(mesh, MAT, model="SS", flags=flags, held=held) as pb:
+            rep = np.array([[40, 0, 0], [40, 0, 0]], np.int32)
+            params, _keep = S.step_params(1 / 60, max_newton=2, newton_rtol=1e-12, pcg_rtol=1e-13, replay=rep)
+            rc, gs = S.shell_step_implicit(pb.sim, params)
+            assert gs["newton_iters"] == 2 and gs["pcg_total"] == 80
+            res[direct] = S.shell_sim_get_state(pb.sim, mesh.nv)[:2]
+    for direct, (x, v) in res.items():
+        err = (rel(x - mesh.X, osim.x - mesh.X), rel(v, osim.v))
+        print(f"held coordinates, {'direct' if direct else 'staged'}: {err[0]:.2e} {err[1]:.2e}")
+        assert err[0] <= TOL64 and err[1] <= TOL64, (direct, err)
+        for c in range(3):
+            rows = (mask >> c) & 1 == 1
+            assert np.array_equal(x[rows, c], mesh.X[rows, c]) and not v[rows, c].any()
+    assert rel(res[False][0] - mesh.X, res[True][0] - mesh.X) <= 1e-12
+
+
 def _cantilever(model, scale=1.0, nx=17, ny=3):
     """The Sec. 6 cantilever: a 10 x 1 strip of nx x ny vertices, E = 1.2e6, nu = 0.1, h = 0.1, its two
     left vertex columns held, an end shear of total 4 * scale along Z on the right-end vertices."""
