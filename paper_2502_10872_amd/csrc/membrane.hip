@@ -575,6 +575,142 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_update(const double* __restric
     ms_partials<2>(v, part, ngroups);
 }
 
+// Small meshes (at most kMsSmallRows vertices): the whole PCG iteration in one work-group, up to `count`
+// iterations per launch, work-group barriers in place of the kernel boundaries of the chain above (whose
+// launches, some microseconds each, dominate at these sizes).  The direction p and the product q live in
+// LDS for the launch (p is read from and written back to m.p at its ends); LANES lanes share a row's
+// entries (consecutive lanes, consecutive entries) and combine their sums by shuffles.  The same
+// recurrence and stop test: p = z + beta p, q with held coordinates zero, alpha = r.z / p.q, y, r, z
+// updated, then beta, the count, the budget and the activity from r.z and r.r exactly as ms_iter_finish
+// takes them.  Sums are per wave, then over the waves in a fixed order, so a run is reproducible; VT as
+// in ms_iter_product (float32 entries in difference form).  Measured: one thread per row of a
+// 1088-vertex mesh took 38 us per iteration (each row's gathers one after another), three times the
+// kernel chain; with p in LDS and several lanes per row the one-work-group solver wins up to some
+// hundreds of vertices.
+constexpr int kMsSmallThreads = 1024;
+constexpr long kMsSmallRows = 512;
+constexpr int kMsSmallChunk = 4096;  // iterations per launch at most (the host loop launches again)
+
+template <int NQ>
+__device__ __forceinline__ void ms_small_sum(double (&v)[NQ], double* sh) {
+    constexpr int NW = kMsSmallThreads / 64;
+    for (int q = 0; q < NQ; ++q) v[q] = wave_sum(v[q]);
+    __syncthreads();  // the previous sum's readers are done with sh
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < NQ; ++q) sh[q * NW + (threadIdx.x >> 6)] = v[q];
+    __syncthreads();
+    for (int q = 0; q < NQ; ++q) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += sh[q * NW + w];
+        v[q] = t;  // every thread, the same order
+    }
+}
+
+template <typename VT, int LANES>
+__global__ __launch_bounds__(kMsSmallThreads) void ms_pcg_small(
+    double* __restrict__ scal, const int64_t* __restrict__ srow, const int32_t* __restrict__ scol,
+    const VT* __restrict__ sval, const int64_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
+    const VT* __restrict__ mval, const double* __restrict__ mass, const uint8_t* __restrict__ pinned,
+    const double* __restrict__ dinv, double* __restrict__ z, double* __restrict__ pg, double* __restrict__ y,
+    double* __restrict__ r, long nv, double dt2, int count) {
+    __shared__ double sh[2 * (kMsSmallThreads / 64)];
+    __shared__ double ps[3 * kMsSmallRows], qs[3 * kMsSmallRows];
+    constexpr bool DIFF = sizeof(VT) == 4;
+    constexpr int ROWS = kMsSmallThreads / LANES;
+    const int lane = threadIdx.x % LANES;
+    for (long i = threadIdx.x; i < 3 * nv; i += blockDim.x) ps[i] = pg[i];
+    __syncthreads();
+    for (int k = 0; k < count; ++k) {
+        if (scal[S_ACTIVE] == 0.0) break;  // every thread reads it after the same barrier
+        const double be = scal[S_BETA];
+        for (long i = threadIdx.x; i < 3 * nv; i += blockDim.x) ps[i] = z[i] + be * ps[i];
+        __syncthreads();
+        double pq[1] = {0.0};
+        for (long i0 = 0; i0 < nv; i0 += ROWS) {  // every lane of a row group takes part in the shuffles
+            const long i = i0 + threadIdx.x / LANES;
+            double a[3] = {0.0, 0.0, 0.0};
+            double po[3] = {0.0, 0.0, 0.0};
+            if (i < nv) {
+                if constexpr (DIFF)
+                    for (int c = 0; c < 3; ++c) po[c] = ps[3 * i + c];
+                for (long e = srow[i] + lane; e < srow[i + 1]; e += LANES) {
+                    const long j = scol[e];
+                    const double kv = double(sval[e]);
+                    for (int c = 0; c < 3; ++c) a[c] += kv * (ps[3 * j + c] - po[c]);
+                }
+                for (long e = mrow[i] + lane; e < mrow[i + 1]; e += LANES) {
+                    const long j = mcol[e];
+                    const VT* b = mval + 9 * e;
+                    const double pj[3] = {ps[3 * j] - po[0], ps[3 * j + 1] - po[1], ps[3 * j + 2] - po[2]};
+                    for (int c = 0; c < 3; ++c)
+                        a[c] += double(b[3 * c]) * pj[0] + double(b[3 * c + 1]) * pj[1] + double(b[3 * c + 2]) * pj[2];
+                }
+            }
+            for (int off = LANES / 2; off > 0; off >>= 1)
+                for (int c = 0; c < 3; ++c) a[c] += __shfl_xor(a[c], off, LANES);
+            if (i < nv && lane == 0)
+                for (int c = 0; c < 3; ++c) {
+                    const double pi = ps[3 * i + c];
+                    const double qi = (pinned[i] >> c & 1u) ? 0.0 : mass[i] * pi + dt2 * a[c];
+                    qs[3 * i + c] = qi;
+                    pq[0] += pi * qi;
+                }
+        }
+        ms_small_sum<1>(pq, sh);
+        const double al = pq[0] != 0.0 ? scal[S_RZ] / pq[0] : 0.0;
+        double v[2] = {0.0, 0.0};
+        for (long i = threadIdx.x; i < 3 * nv; i += blockDim.x) {
+            y[i] += al * ps[i];
+            const double ri = r[i] - al * qs[i], zi = dinv[i / 3] * ri;
+            r[i] = ri;
+            z[i] = zi;
+            v[0] += ri * zi;
+            v[1] += ri * ri;
+        }
+        ms_small_sum<2>(v, sh);
+        if (threadIdx.x == 0) {
+            scal[S_PQ] = pq[0];
+            scal[S_ALPHA] = al;
+            const double rz = scal[S_RZ];
+            scal[S_BETA] = rz != 0.0 ? v[0] / rz : 0.0;
+            scal[S_RZ] = v[0];
+            scal[S_RR] = v[1];
+            const double it = scal[S_IT] + 1.0, target = scal[S_TARGET];
+            const bool replay = scal[S_REPLAY] != 0.0;
+            const bool more = replay || v[1] > scal[S_TOL2];
+            if (!replay && it >= target && more) scal[S_BUDGET] = 1.0;
+            scal[S_IT] = it;
+            scal[S_ACTIVE] = (it < target && more && isfinite(v[1])) ? 1.0 : 0.0;
+            if (!isfinite(v[1])) scal[S_BUDGET] = 2.0;
+        }
+        __syncthreads();  // the scalars and this iteration's vectors are in place for the next
+    }
+    for (long i = threadIdx.x; i < 3 * nv; i += blockDim.x) pg[i] = ps[i];
+}
+
+template <typename VT, int L>
+void launch_pcg_small_lanes(MembraneSolve& m, const VT* sval, const VT* mval, const double* mass,
+                            const uint8_t* pinned, long nv, double dt2, hipStream_t s) {
+    ms_pcg_small<VT, L><<<1, kMsSmallThreads, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, sval, m.mrow.p, m.mcol.p, mval,
+                                                      mass, pinned, m.dinv.p, m.z.p, m.p.p, m.y.p, m.r.p, nv, dt2,
+                                                      kMsSmallChunk);
+}
+
+template <typename VT>
+void launch_pcg_small(MembraneSolve& m, const VT* sval, const VT* mval, const double* mass, const uint8_t* pinned,
+                      long nv, double dt2, hipStream_t s) {
+    // lanes per row: as many as the work-group has to spare, at most 16
+    const long spare = kMsSmallThreads / std::max(nv, 1L);
+    if (spare >= 16)
+        launch_pcg_small_lanes<VT, 16>(m, sval, mval, mass, pinned, nv, dt2, s);
+    else if (spare >= 8)
+        launch_pcg_small_lanes<VT, 8>(m, sval, mval, mass, pinned, nv, dt2, s);
+    else if (spare >= 4)
+        launch_pcg_small_lanes<VT, 4>(m, sval, mval, mass, pinned, nv, dt2, s);
+    else
+        launch_pcg_small_lanes<VT, 2>(m, sval, mval, mass, pinned, nv, dt2, s);
+}
+
 // r.z and r.r, then beta, the iteration count and the stop test (one block)
 __global__ __launch_bounds__(kMsBlk) void ms_iter_finish(const double* __restrict__ part, long ngroups,
                                                          double* __restrict__ scal) {
@@ -1017,6 +1153,16 @@ constexpr size_t kMsMaxGraphs = 16;
 // the same mass array, dt and buffer parity); otherwise the kernels are launched one by one.
 static void pcg_iterations(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2,
                            int count, bool graphs, hipStream_t s) {
+    if (nv <= kMsSmallRows && !m.staged) {  // one work-group runs the iterations (m.p holds the direction)
+        if (m.mixed)
+            launch_pcg_small<float>(m, m.svalf.p, m.mvalf.p, mass, pinned, nv, dt2, s);
+        else
+            launch_pcg_small<double>(m, m.sval.p, m.mval.p, mass, pinned, nv, dt2, s);
+        SHELL_HIP(hipGetLastError());
+        (void)count;
+        (void)graphs;
+        return;
+    }
     if (!graphs) {
         for (int it = 0; it < count; ++it) pcg_iteration(m, mass, pinned, nv, dt2, s);
         return;

@@ -417,6 +417,28 @@ def test_membrane_step_replay_matches_oracle(model):
     assert err[0] <= TOL64 and err[1] <= TOL64, err
 
 
+@pytest.mark.parametrize("n", [7, 11, 15])
+def test_membrane_step_small_meshes_match_oracle(n):
+    """Small meshes take the one-work-group PCG (up to 512 vertices): 7 x 7, 11 x 11 and 15 x 15 cylinder
+    patches (49, 121 and 225 vertices) give it 16, 8 and 4 lanes per row.  Two steps replaying the
+    oracle's counts and halvings reach the oracle's positions and velocities to 1e-10."""
+    mesh = I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+    osim = O.MembraneSim(oracle_stencils("SS", mesh), MAT, mesh.pinned)
+    with S.Problem(mesh, MAT, model="SS", block_vertices=128, flags=S.SHELL_FLAG_MEMBRANE) as pb:
+        for _ in range(2):
+            counts, halv, ostats = osim.step(1 / 120, max_newton=3, newton_rtol=1e-6, pcg_rtol=1e-13)
+            k = ostats["newton_iters"]
+            rep = np.zeros((max(k, 1), 3), np.int32)
+            rep[:k, 0] = counts[:k]
+            rep[:k, 1] = halv[:k]
+            params, _keep = S.step_params(1 / 120, max_newton=k, newton_rtol=1e-6, pcg_rtol=1e-13, replay=rep)
+            rc, gs = S.shell_step_implicit(pb.sim, params)
+            assert gs["newton_iters"] == k
+        x, v, _ = S.shell_sim_get_state(pb.sim, mesh.nv)
+    err = (rel(x - mesh.X, osim.x - mesh.X), rel(v, osim.v))
+    assert err[0] <= TOL64 and err[1] <= TOL64, err
+
+
 def test_membrane_pcg_graphs_match_direct_launches():
     """The membrane's PCG chunks replayed from captured graphs run the same kernels as launching them one by
     one (SHELL_STEP_NO_GRAPHS).  The direct launches replay the graph run's counts and halvings and must
@@ -563,11 +585,12 @@ def test_mixed_membrane_step_replay_matches_oracle(model):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_membrane_step_multi_block_matches_oracle(prec):
-    """The membrane step's CSR product (meshes below the staged layout's size) over many work-groups with a
-    partial last one (a 37 x 37 cylinder patch, 1369 vertices): two steps replaying the oracle's counts
-    reach the oracle to the FP64 bound, or to the mixed bound of the single-block test."""
-    mesh = I.cylinder_mesh(37, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
-    assert mesh.nv == 1369
+    """The membrane step's multi-kernel CSR product chain (meshes above the one-work-group solver's 2048
+    vertices and below the staged layout's size) over many work-groups with a partial last one (a 48 x 48
+    cylinder patch, 2304 vertices): two steps replaying the oracle's counts reach the oracle to the FP64
+    bound, or to the mixed bound of the small-mesh test."""
+    mesh = I.cylinder_mesh(48, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+    assert mesh.nv == 2304
     ost = oracle_stencils("SS", mesh)
     osim = O.MembraneSim(ost, MAT, mesh.pinned)
     precision = S.SHELL_PREC_MIXED if prec == "mixed" else S.SHELL_PREC_FP64
