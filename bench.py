@@ -695,8 +695,8 @@ def serving_run(torch, rates=(20.0, 200.0), durations=(3.0, 1.0), max_wait_s=5.0
             torch.cuda.synchronize()
             res.update(rate=rate, trace_s=dur, max_wait_s=max_wait_s)
             out[f"rate{int(rate)}_{mode}"] = res
-            print(f"[bench] serving rate {rate:g} {mode}: {res['completed']}/{res['requests']} done, "
-                  f"p99 {res['p99_s']:.2f} s", file=sys.stderr, flush=True)
+            print(f"[bench] serving rate {rate:g} {mode}: {res['completed']}/{res['requests']} done, {res['shed']} shed, "
+                  f"{res['failed']} failed, p99 {res['p99_s']:.2f} s", file=sys.stderr, flush=True)
     return out
 
 

@@ -110,7 +110,8 @@ class GpuExecutor:
             self.batch = S.shell_batch_create(sims)
         else:
             S.shell_batch_reset(self.batch, sims)
-        rc, stats = S.shell_batch_step(self.batch, self.params, len(sims), stream=self.stream)
+        # a mesh whose state went non-finite is reported in its own stats; the others stepped normally
+        rc, stats = S.shell_batch_step(self.batch, self.params, len(sims), stream=self.stream, allow_nonfinite=True)
         return stats
 
     def state(self, req):
@@ -137,10 +138,11 @@ class FakeExecutor:
     batch step costing a launch overhead plus the sum of the members' work.  Tests the scheduler."""
 
     def __init__(self, cfg: ServeConfig, build_s_per_vertex=2e-8, step_s_per_vertex=5e-9, step_overhead=1e-4,
-                 sleep=True, fail=None):
+                 sleep=True, fail=None, diverge=None):
         self.cfg = cfg
         self.bspv, self.sspv, self.ovh, self.sleep = build_s_per_vertex, step_s_per_vertex, step_overhead, sleep
         self.fail = fail or (lambda req: False)
+        self.diverge = diverge or (lambda req: False)  # requests whose state goes non-finite at their 2nd step
         self.batches = []
 
     def build(self, req):
@@ -155,7 +157,8 @@ class FakeExecutor:
         self.batches.append([r.rid for r in reqs])
         if self.sleep:
             time.sleep(self.ovh + self.sspv * sum(r.nv for r in reqs))
-        return [dict(newton_iters=2, pcg_total=60, status=0) for _ in reqs]
+        return [dict(newton_iters=2, pcg_total=60, status=5 if self.diverge(r) and r.steps_done == 1 else 0)
+                for r in reqs]
 
     def release(self, req):
         req.handle = None
@@ -311,13 +314,16 @@ def run_sequential(executor, cfg: ServeConfig, requests, realtime=True):
                 r.status, r.error, r.t_done = "failed", str(e), clock()
                 continue
             r.t_ready = clock()
+            r.status = "done"
             for _ in range(r.steps):
                 s = executor.step([r])[0]
                 r.steps_done += 1
                 r.newton += int(s["newton_iters"])
                 r.pcg += int(s["pcg_total"])
+                if s.get("status", 0) == 5:
+                    r.status, r.error = "failed", "non-finite state"
+                    break
             r.t_done = clock()
-            r.status = "done"
             executor.release(r)
     finally:
         executor.close()

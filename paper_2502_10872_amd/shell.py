@@ -384,13 +384,16 @@ def shell_batch_create(sims):
     return out.value
 
 
-def shell_batch_step(batch, params, n, with_stats=True, stream=None):
-    """params: one shell_step_params_t (shared) or a list of n.  Returns (status, [stats dict] or None)."""
+def shell_batch_step(batch, params, n, with_stats=True, stream=None, allow_nonfinite=False):
+    """params: one shell_step_params_t (shared) or a list of n.  Returns (status, [stats dict] or None).
+    SHELL_E_BUDGET is returned, not raised; so is SHELL_E_NONFINITE with allow_nonfinite (the per-mesh
+    statuses in the stats then say which meshes went non-finite)."""
     plist = params if isinstance(params, (list, tuple)) else [params]
     parr = (shell_step_params_t * len(plist))(*plist)
     stats = (shell_step_stats_t * n)()
     rc = lib().shell_batch_step(batch, parr, len(plist), stats if with_stats else None, _stream(stream))
-    _check(rc, "shell_batch_step", allow=(SHELL_OK, SHELL_E_BUDGET))
+    _check(rc, "shell_batch_step",
+           allow=(SHELL_OK, SHELL_E_BUDGET, SHELL_E_NONFINITE) if allow_nonfinite else (SHELL_OK, SHELL_E_BUDGET))
     return rc, ([stats_dict(stats[m]) for m in range(n)] if with_stats else None)
 
 

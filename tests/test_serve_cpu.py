@@ -50,6 +50,20 @@ def test_failed_build_retires_alone():
     assert rs[2].status == "failed" and out["failed"] == 1 and out["completed"] == 3
 
 
+def test_nonfinite_mesh_retires_alone():
+    """A mesh whose state goes non-finite (reported in its own step stats) retires as failed after that
+    step, in the continuous server and one at a time; the other requests complete."""
+    cfg = V.ServeConfig(hbm_budget=1 << 40, builders=2)
+    rs = reqs([30, 30, 30, 30], steps=3)
+    out = V.Server(V.FakeExecutor(cfg, sleep=False, diverge=lambda r: r.rid == 1), cfg).run(rs, realtime=False)
+    assert rs[1].status == "failed" and rs[1].steps_done == 2 and rs[1].error == "non-finite state"
+    assert out["failed"] == 1 and out["completed"] == 3
+    rs2 = reqs([30, 30, 30, 30], steps=3)
+    seq = V.run_sequential(V.FakeExecutor(cfg, sleep=False, diverge=lambda r: r.rid == 1), cfg, rs2, realtime=False)
+    assert rs2[1].status == "failed" and rs2[1].steps_done == 2
+    assert seq["failed"] == 1 and seq["completed"] == 3
+
+
 def test_realtime_latency_accounting_and_sequential_baseline():
     cfg = V.ServeConfig(hbm_budget=1 << 40, builders=2)
     # steps (20 ms per mesh) outlast the arrival gap (5 ms), so later arrivals join running batches
