@@ -368,7 +368,9 @@ shell_status_t shell_batch_step(shell_batch_t batch, const shell_step_params_t* 
 shell_status_t shell_batch_reset(shell_batch_t batch, const shell_sim_t* sims, int32_t n);
 
 /* shell_sim_device_bytes: device memory held by the simulation's stencils, Hessian and state (host
- * int64 outputs, each may be NULL); for admission by HBM footprint. */
+ * int64 outputs, each may be NULL); for admission by HBM footprint.  The state counts the solver's work
+ * arrays, the membrane solver's when the simulation has one, and buffers made on first use (the quasi-
+ * static load and mass, the mixed refinement's product) once they exist. */
 shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, int64_t* hessian_bytes,
                                       int64_t* sim_bytes);
 void shell_destroy_batch(shell_batch_t batch);

@@ -873,8 +873,10 @@ shell_status_t shell_sim_device_bytes(shell_sim_t sim, int64_t* stencil_bytes, i
         for (size_t v : {sim->x.bytes(), sim->v.bytes(), sim->xt.bytes(), sim->xhat.bytes(), sim->g.bytes(),
                          sim->mass.bytes(), sim->y.bytes(), sim->r.bytes(), sim->f.bytes(), sim->dinv.bytes(), sim->mq.bytes(),
                          sim->pinned.bytes(), sim->p.bytes(), sim->p2.bytes(), sim->z.bytes(), sim->q.bytes(),
-                         sim->bins.bytes(), sim->partials.bytes()})
+                         sim->bins.bytes(), sim->partials.bytes(), sim->y64.bytes(), sim->rq.bytes(),
+                         sim->zmass.bytes(), sim->fext.bytes(), sim->ustep.bytes()})
             c += int64_t(v);
+        if (sim->ms) c += int64_t(sim->ms->bytes());
         if (stencil_bytes) *stencil_bytes = a;
         if (hessian_bytes) *hessian_bytes = b;
         if (sim_bytes) *sim_bytes = c;

@@ -352,6 +352,18 @@ struct MembraneSolve {
     };
     std::vector<PcgGraph> graphs;  // oldest first
     hipStream_t capture = nullptr; // private stream the chunks are captured on
+    // device memory held by the arrays above
+    size_t bytes() const {
+        size_t n = 0;
+        for (size_t v : {srow.bytes(), scol.bytes(), sval.bytes(), mrow.bytes(), mcol.bytes(), mbase.bytes(),
+                         mdiag.bytes(), mval.bytes(), gptr.bytes(), gcols.bytes(), gself.bytes(), mwidth.bytes(),
+                         mptr.bytes(), slcol.bytes(), mlcol.bytes(), brow.bytes(), btptr.bytes(), bttri.bytes(),
+                         rest.bytes(), xtry.bytes(), ftry.bytes(), z.bytes(), p.bytes(), p2.bytes(), q.bytes(),
+                         y.bytes(), r.bytes(), dinv.bytes(), part.bytes(), ff.bytes(), svalf.bytes(), mvalf.bytes(),
+                         ppart.bytes(), scal.bytes(), fdesc.bytes(), items.bytes()})
+            n += v;
+        return n;
+    }
     MembraneSolve() = default;
     MembraneSolve(const MembraneSolve&) = delete;
     MembraneSolve& operator=(const MembraneSolve&) = delete;

@@ -180,6 +180,23 @@ def test_mixed_matches_fp64_at_a_matched_residual_on_the_1M_cap():
     assert err <= 1e-6 and emax <= 2e-6, (err, emax)
 
 
+def test_device_bytes_count_the_membrane_and_buffers_made_on_first_use():
+    """shell_sim_device_bytes, the serving admission's footprint: a simulation with the membrane counts at
+    least its tangent's blocks (nine float64 and nine float32 values per block) beyond the same mesh
+    without it, and a mixed simulation's first residual-replacement pass adds its float64 product buffer
+    (24 bytes per vertex)."""
+    mesh = I.cylinder_mesh(17, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+    t = np.sort(mesh.tris, axis=1)
+    pairs = {(int(a), int(b)) for tr in t for a in tr for b in tr}
+    with S.Problem(mesh, MAT, model="SS", precision=S.SHELL_PREC_MIXED) as plain, \
+            S.Problem(mesh, MAT, model="SS", precision=S.SHELL_PREC_MIXED, flags=S.SHELL_FLAG_MEMBRANE) as memb:
+        b0, bm = S.shell_sim_device_bytes(plain.sim), S.shell_sim_device_bytes(memb.sim)
+        assert bm - b0 >= len(pairs) * 9 * (8 + 4)
+        params, _keep = S.step_params(1 / 30, max_newton=1, newton_rtol=0.0, pcg_rtol=1e-10)
+        S.shell_step_implicit(plain.sim, params)
+        assert S.shell_sim_device_bytes(plain.sim) - b0 == 24 * mesh.nv
+
+
 def test_newton_budget_is_flagged():
     """A step that stops at max_newton before its residual test held says so; a plate, whose single
     solve is exact, does not."""
