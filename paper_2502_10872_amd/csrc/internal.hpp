@@ -323,6 +323,7 @@ struct MembraneSolve {
     DevArray<int32_t> gptr, gcols, gself, mwidth;
     DevArray<int64_t> mptr;
     DevArray<uint16_t> slcol, mlcol;
+    DevArray<int64_t> s2e;  // [slots] the CSR block of each block slot, -1 on padding
     const int64_t* hsptr = nullptr;  // the bending Hessian's SELL slices and values (owned by the Hessian)
     const int32_t* hwidth = nullptr;
     const double* hval = nullptr;
@@ -357,7 +358,7 @@ struct MembraneSolve {
         size_t n = 0;
         for (size_t v : {srow.bytes(), scol.bytes(), sval.bytes(), mrow.bytes(), mcol.bytes(), mbase.bytes(),
                          mdiag.bytes(), mval.bytes(), gptr.bytes(), gcols.bytes(), gself.bytes(), mwidth.bytes(),
-                         mptr.bytes(), slcol.bytes(), mlcol.bytes(), brow.bytes(), btptr.bytes(), bttri.bytes(),
+                         mptr.bytes(), slcol.bytes(), mlcol.bytes(), s2e.bytes(), brow.bytes(), btptr.bytes(), bttri.bytes(),
                          rest.bytes(), xtry.bytes(), ftry.bytes(), z.bytes(), p.bytes(), p2.bytes(), q.bytes(),
                          y.bytes(), r.bytes(), dinv.bytes(), part.bytes(), ff.bytes(), svalf.bytes(), mvalf.bytes(),
                          ppart.bytes(), scal.bytes(), fdesc.bytes(), items.bytes()})

@@ -244,14 +244,20 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin1(const double* __restrict__ par
 // takes the same sums in every run (no atomics, no read-modify-write).  Per triangle, with a and b the
 // corners of i and j: the Gauss-Newton part A B_a^T D_m B_b (B_c the linearised Green strain of corner
 // c: rows g_c0 F0^T, g_c1 F1^T, g_c1 F0^T + g_c0 F1^T) and the stress part A (g_a^T S+ g_b) I3.
-// Component (a, b) of block e is mval[mbase[e] + (3 a + b) mstride].
+// Component (a, b) of CSR block e is mval[mbase[e] + (3 a + b) mstride].  With s2e (the staged layout)
+// thread t takes SELL slot t, s2e[t] its CSR block (-1 on padding, which stays zero), so that the
+// lanes of a wave write consecutive slots; otherwise thread t takes CSR block t.  Mixed precision
+// (mvalf not null) also writes the float32 copy the product reads.
 __global__ void ms_tangent(const double* __restrict__ rest, const int32_t* __restrict__ tris,
                            const int32_t* __restrict__ brow, const int32_t* __restrict__ mcol,
-                           const int64_t* __restrict__ btptr, const int32_t* __restrict__ bttri, long nb,
-                           const double* __restrict__ x, double c, double nu, const int64_t* __restrict__ mbase,
-                           long mstride, double* __restrict__ mval) {
-    const long e = blockIdx.x * long(blockDim.x) + threadIdx.x;
-    if (e >= nb) return;
+                           const int64_t* __restrict__ btptr, const int32_t* __restrict__ bttri,
+                           const int64_t* __restrict__ s2e, long nthreads, const double* __restrict__ x, double c,
+                           double nu, const int64_t* __restrict__ mbase, long mstride, double* __restrict__ mval,
+                           float* __restrict__ mvalf) {
+    const long tid = blockIdx.x * long(blockDim.x) + threadIdx.x;
+    if (tid >= nthreads) return;
+    const long e = s2e ? s2e[tid] : tid;
+    if (e < 0) return;
     const int32_t r = brow[e], jc = mcol[e];
     double acc[9];
     for (int k = 0; k < 9; ++k) acc[k] = 0.0;
@@ -304,8 +310,10 @@ __global__ void ms_tangent(const double* __restrict__ rest, const int32_t* __res
         const double gsg = g[a][0] * (P00 * g[b][0] + P01 * g[b][1]) + g[a][1] * (P01 * g[b][0] + P11 * g[b][1]);
         for (int cc = 0; cc < 3; ++cc) acc[4 * cc] += A * gsg;
     }
-    double* blk = mval + mbase[e];
-    for (int k = 0; k < 9; ++k) blk[k * mstride] = acc[k];
+    const long base = s2e ? tid : mbase[e];
+    for (int k = 0; k < 9; ++k) mval[base + k * mstride] = acc[k];
+    if (mvalf)
+        for (int k = 0; k < 9; ++k) mvalf[base + k * mstride] = float(acc[k]);
 }
 
 __global__ void ms_dinv(const double* __restrict__ kdiag, const double* __restrict__ mval,
@@ -916,6 +924,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
             }
             const int64_t mslots = mptr[size_t(nsl)];
             std::vector<uint16_t> mlcol(size_t(mslots), 0);
+            std::vector<int64_t> s2e(size_t(mslots), -1);
             for (int64_t sl = 0; sl < nsl; ++sl)
                 for (int lane = 0; lane < 64; ++lane) {
                     const int64_t i = 64 * sl + lane, g = i / kRowGroup;
@@ -925,6 +934,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
                         if (k < len) {
                             const int64_t e = mrow[size_t(i)] + k;
                             mbase[size_t(e)] = slot;
+                            s2e[size_t(slot)] = e;
                             mlcol[size_t(slot)] = local(g, mcol[size_t(e)]);
                         } else {
                             mlcol[size_t(slot)] = i < nv ? local(g, int32_t(i)) : uint16_t(0);  // zero value
@@ -952,6 +962,8 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
             ms->mptr.upload(mptr.data(), mptr.size(), s);
             ms->mlcol.alloc(mlcol.size());
             ms->mlcol.upload(mlcol.data(), mlcol.size(), s);
+            ms->s2e.alloc(s2e.size());
+            ms->s2e.upload(s2e.data(), s2e.size(), s);
             SHELL_HIP(hipStreamSynchronize(s));  // the host copies are released on leaving the scope
         }
     }
@@ -1017,6 +1029,8 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->bttri.upload(bttri.data(), size_t(9 * nt), s);
     // the blocks' padding slots (staged layout) stay zero: the assembly writes every stored block
     if (ms->mval.n) ms_zero<<<ms_grid(long(ms->mval.n)), kMsBlk, 0, s>>>(ms->mval.p, long(ms->mval.n));
+    if (ms->mixed && ms->mval.n)
+        ms_narrow<<<ms_grid(long(ms->mval.n)), kMsBlk, 0, s>>>(ms->mval.p, ms->mvalf.p, long(ms->mval.n));
     // per-triangle rest data
     ms->rest.alloc(size_t(std::max(5 * nt, 1L)));
     DevArray<int32_t> bad(1);
@@ -1084,13 +1098,14 @@ static void tangent_at(shell_sim_s& sim, const double* x, const double* mass, do
     MembraneSolve& m = *sim.ms;
     const long nv = sim.nv, nt = st.nt;
     const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
-    const long nb9 = long(m.mval.n), nb = long(m.mcol.n);
+    const long nb = long(m.mcol.n), nthreads = m.staged ? long(m.mstride) : nb;
     if (nt > 0 && nb > 0)
-        ms_tangent<<<ms_grid(nb), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.brow.p, m.mcol.p, m.btptr.p, m.bttri.p, nb, x,
-                                                  c, st.poisson, m.mbase.p, long(m.mstride), m.mval.p);
+        ms_tangent<<<ms_grid(nthreads), kMsBlk, 0, s>>>(m.rest.p, st.tris.p, m.brow.p, m.mcol.p, m.btptr.p, m.bttri.p,
+                                                        m.staged ? m.s2e.p : nullptr, nthreads, x, c, st.poisson,
+                                                        m.mbase.p, long(m.mstride), m.mval.p,
+                                                        m.mixed ? m.mvalf.p : nullptr);
     ms_dinv<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.h->kdiag.p, m.mval.p, m.mdiag.p, long(m.mstride), mass, sim.pinned.p, nv, dt2,
                                            m.dinv.p);
-    if (m.mixed) ms_narrow<<<ms_grid(nb9), kMsBlk, 0, s>>>(m.mval.p, m.mvalf.p, nb9);
     SHELL_HIP(hipGetLastError());
 }
 
