@@ -22,7 +22,15 @@
  *    coordinate bisection into compact tiles, Morton order inside a tile; see
  *    shell_config_t.reorder) and converts at the boundary.
  *  - Handles are owned by the library and released by shell_destroy_*; one
- *    handle must not be used by two threads at once.
+ *    handle must not be used by two threads at once.  Distinct handles may be
+ *    driven from distinct threads.  Steps capture their PCG iterations into HIP
+ *    graphs, and the runtime refuses some calls made by another thread during a
+ *    capture (a device-wide synchronisation is one), invalidating the capture.
+ *    The library never synchronises the whole device, and its allocations,
+ *    releases, stream creation and captures take one process-wide lock.  A
+ *    caller's own such call from another thread, made during a step, can still
+ *    fail that step with SHELL_E_HIP; SHELL_STEP_NO_GRAPHS steps without
+ *    captures.
  *  - Models are identified by shell_model_t; a model's curvature size r is 1
  *    (edge) or 3 (triangle), its stencil size k is 4 (edge) or 6 (triangle).
  */

@@ -34,6 +34,23 @@ shell_status_t guarded(F&& fn) {
 
 hipStream_t as_stream(shell_stream_t s) { return static_cast<hipStream_t>(s); }
 
+// A private non-blocking stream for the copies of a call that has no stream argument (an export, the
+// initial state of a simulation): it waits only for its own work, never for another thread's streams
+// (the arrays an export reads were complete when their create call returned).
+struct HostCopyStream {
+    hipStream_t s = nullptr;
+    HostCopyStream() {
+        RuntimeLock lk(runtime_mutex());
+        SHELL_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    }
+    ~HostCopyStream() {
+        RuntimeLock lk(runtime_mutex());
+        (void)hipStreamDestroy(s);
+    }
+    HostCopyStream(const HostCopyStream&) = delete;
+    HostCopyStream& operator=(const HostCopyStream&) = delete;
+};
+
 void check_params(const shell_step_params_t& p) {
     SHELL_CHECK(p.dt > 0 && std::isfinite(p.dt), SHELL_E_INVALID_ARG, "dt must be positive");
     SHELL_CHECK(p.max_newton >= 0 && p.max_newton <= SHELL_MAX_NEWTON, SHELL_E_INVALID_ARG, "max_newton out of range");
@@ -258,9 +275,10 @@ shell_status_t shell_stencils_export(shell_stencils_t st, int32_t* idx, double* 
                 }
         if (B || kappa0) {
             std::vector<double> hb(size_t(r * k) * ns), hk(size_t(r) * ns);
-            st->B.download(hb.data(), hb.size(), nullptr);
-            st->k0.download(hk.data(), hk.size(), nullptr);
-            SHELL_HIP(hipDeviceSynchronize());
+            HostCopyStream cs;
+            st->B.download(hb.data(), hb.size(), cs.s);
+            st->k0.download(hk.data(), hk.size(), cs.s);
+            SHELL_HIP(hipStreamSynchronize(cs.s));
             for (size_t q = 0; q < ns; ++q) {
                 if (B)
                     for (int c = 0; c < r * k; ++c) B[size_t(r * k) * q + c] = hb[size_t(c) * ns + q];
@@ -302,9 +320,9 @@ shell_status_t shell_eval_forces(shell_stencils_t st, const double* x, void* f, 
             for (int64_t t = 0; t < st->nblocks; ++t) items[size_t(t)] = {0, int32_t(t)};
             st->fdesc.alloc(1);
             st->tile_items.alloc(items.size());
-            SHELL_HIP(hipMemcpy(st->fdesc.p, &d, sizeof(d), hipMemcpyHostToDevice));
-            SHELL_HIP(hipMemcpy(st->tile_items.p, items.data(), items.size() * sizeof(WorkItem),
-                                hipMemcpyHostToDevice));
+            st->fdesc.upload(&d, 1, s);
+            st->tile_items.upload(items.data(), items.size(), s);
+            SHELL_HIP(hipStreamSynchronize(s));
         }
         if (st->nv > 0) {
             launch_gather_rows(x, st->perm_d.p, st->xin.p, st->nv, s);
@@ -469,8 +487,9 @@ shell_status_t shell_hessian_export_csr(shell_hessian_t h, int64_t* nnz, int64_t
         if (!col && !val && !rowptr) return SHELL_OK;
         const shell_stencils_s& st = *h->st;
         std::vector<double> sv(size_t(P.nslots));
-        h->val.download(sv.data(), sv.size(), nullptr);
-        SHELL_HIP(hipDeviceSynchronize());
+        HostCopyStream cs;
+        h->val.download(sv.data(), sv.size(), cs.s);
+        SHELL_HIP(hipStreamSynchronize(cs.s));
         const int64_t nv = st.nv;
         // caller row u = perm[i]; its entries are internal row i's, columns mapped by perm and re-sorted
         std::vector<int64_t> ptr(size_t(nv + 1), 0);
@@ -542,7 +561,8 @@ shell_status_t shell_sim_create(shell_stencils_t st, shell_hessian_t h, const do
             }
             if (pinned) pi[size_t(i)] = pinned[u] ? 7 : 0;  // every coordinate held
         }
-        hipStream_t s = nullptr;
+        HostCopyStream cs;
+        hipStream_t s = cs.s;
         sim->x.upload(xi.data(), xi.size(), s);
         sim->v.upload(vi.data(), vi.size(), s);
         sim->pinned.upload(pi.data(), pi.size(), s);
@@ -672,8 +692,8 @@ shell_status_t shell_sim_get_state(shell_sim_t sim, double* x, double* v, int64_
         for (int which = 0; which < 2; ++which) {
             double* dst = which ? v : x;
             if (!dst) continue;
-            (which ? sim->v : sim->x).download(buf.data(), buf.size(), nullptr);
-            SHELL_HIP(hipDeviceSynchronize());
+            (which ? sim->v : sim->x).download(buf.data(), buf.size(), sim->last_stream);
+            SHELL_HIP(hipStreamSynchronize(sim->last_stream));
             for (int64_t i = 0; i < nv; ++i)
                 for (int c = 0; c < 3; ++c) dst[3 * int64_t(perm[size_t(i)]) + c] = buf[size_t(3 * i + c)];
         }
@@ -694,8 +714,8 @@ shell_status_t shell_sim_set_state(shell_sim_t sim, const double* x, const doubl
             if (!src) continue;
             for (int64_t i = 0; i < nv; ++i)
                 for (int c = 0; c < 3; ++c) buf[size_t(3 * i + c)] = src[3 * int64_t(perm[size_t(i)]) + c];
-            (which ? sim->v : sim->x).upload(buf.data(), buf.size(), nullptr);
-            SHELL_HIP(hipDeviceSynchronize());
+            (which ? sim->v : sim->x).upload(buf.data(), buf.size(), sim->last_stream);
+            SHELL_HIP(hipStreamSynchronize(sim->last_stream));
         }
         sim->step = step;
         return SHELL_OK;
@@ -717,8 +737,8 @@ shell_status_t shell_sim_set_held(shell_sim_t sim, const uint8_t* held) {
         }
         SHELL_HIP(hipStreamSynchronize(sim->last_stream));
         if (nv > 0) {
-            sim->pinned.upload(m.data(), size_t(nv), nullptr);
-            SHELL_HIP(hipDeviceSynchronize());
+            sim->pinned.upload(m.data(), size_t(nv), sim->last_stream);
+            SHELL_HIP(hipStreamSynchronize(sim->last_stream));
         }
         sim->partial_held = partial;
         sim->dinv_dt = -1.0;  // the preconditioner's fixed rows changed

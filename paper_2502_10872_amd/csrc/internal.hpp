@@ -7,6 +7,7 @@
 #include <stdexcept>
 #include <string>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "shell.h"
@@ -33,6 +34,19 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::shell::Error((status), (msg));                \
     } while (0)
 
+// ------------------------------------------------------------------ runtime calls against graph capture
+//
+// While one thread captures a stream into a graph, the HIP runtime refuses some calls from other threads
+// (a device-wide synchronisation is one) and the refusal also invalidates that capture.  The library
+// makes no device-wide synchronisation; its allocations, releases, stream creation and destruction and
+// its own capture sections all take this one process-wide lock, so that handles driven from different
+// threads never interleave such a call with a capture.
+inline std::recursive_mutex& runtime_mutex() {
+    static std::recursive_mutex m;
+    return m;
+}
+using RuntimeLock = std::lock_guard<std::recursive_mutex>;
+
 // ------------------------------------------------------------------ device buffers
 
 template <typename T>
@@ -47,10 +61,16 @@ struct DevArray {
     void alloc(size_t count) {
         release();
         n = count;
-        if (count) SHELL_HIP(hipMalloc(&p, count * sizeof(T)));
+        if (count) {
+            RuntimeLock lk(runtime_mutex());
+            SHELL_HIP(hipMalloc(&p, count * sizeof(T)));
+        }
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            RuntimeLock lk(runtime_mutex());
+            (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
     }

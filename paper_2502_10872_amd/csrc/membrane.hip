@@ -773,6 +773,7 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_max(const double* __restrict__ 
 }  // namespace
 
 MembraneSolve::~MembraneSolve() {
+    RuntimeLock lk(runtime_mutex());
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.ex);
     if (capture) (void)hipStreamDestroy(capture);
 }
@@ -1187,6 +1188,7 @@ static void pcg_iterations(MembraneSolve& m, const double* mass, const uint8_t* 
     for (const auto& g : m.graphs)
         if (g.mass == mass && g.dt2 == dt2 && g.count == count && g.parity == parity) ex = g.ex;
     if (!ex) {
+        RuntimeLock lk(runtime_mutex());
         if (!m.capture) SHELL_HIP(hipStreamCreateWithFlags(&m.capture, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
         SHELL_HIP(hipStreamBeginCapture(m.capture, hipStreamCaptureModeThreadLocal));

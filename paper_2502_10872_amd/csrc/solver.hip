@@ -65,6 +65,7 @@ void StepProfiler::reset() {
 }
 
 GraphCache::~GraphCache() {
+    RuntimeLock lk(runtime_mutex());
     for (auto& e : entries) (void)hipGraphExecDestroy(e.second);
     if (capture) (void)hipStreamDestroy(capture);
 }
@@ -165,7 +166,10 @@ long pcg_iterations(shell_batch_s& b, const Launch& L, long t, int count, hipStr
     if (!use_graphs || (prof && prof->every > 0)) return pcg_chunk<VR, MR>(L, t, count, s, prof);
     if (!b.graphs) b.graphs = std::make_unique<GraphCache>();
     GraphCache& gc = *b.graphs;
-    if (!gc.capture) SHELL_HIP(hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking));
+    if (!gc.capture) {
+        RuntimeLock lk(runtime_mutex());
+        SHELL_HIP(hipStreamCreateWithFlags(&gc.capture, hipStreamNonBlocking));
+    }
     while (count > 0) {
         int c = kMinGraphChunk;
         while (2 * c <= count && 2 * c <= kMaxGraphChunk) c *= 2;
@@ -176,6 +180,7 @@ long pcg_iterations(shell_batch_s& b, const Launch& L, long t, int count, hipStr
         for (auto& e : gc.entries)
             if (e.first == key) ex = e.second;
         if (!ex) {
+            RuntimeLock lk(runtime_mutex());
             hipGraph_t g = nullptr;
             SHELL_HIP(hipStreamBeginCapture(gc.capture, hipStreamCaptureModeThreadLocal));
             try {
@@ -246,10 +251,13 @@ Launch upload(shell_batch_s& b, const ItemBuilder& ib, hipStream_t s, int pcg_wo
     size_t total = ib.rows.size();
     for (const auto& t : ib.tiles) total += t.size();
     if (total > b.items_cap || !b.items_host) {
-        if (b.items_host) (void)hipHostFree(b.items_host);
-        b.items_host = nullptr;
-        b.items_cap = std::max<size_t>(total, 64) * 2;
-        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.items_host), b.items_cap * sizeof(WorkItem)));
+        {
+            RuntimeLock lk(runtime_mutex());
+            if (b.items_host) (void)hipHostFree(b.items_host);
+            b.items_host = nullptr;
+            b.items_cap = std::max<size_t>(total, 64) * 2;
+            SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.items_host), b.items_cap * sizeof(WorkItem)));
+        }
         b.items.alloc(b.items_cap);
     }
     Launch L{};
@@ -757,16 +765,20 @@ void batch_init(shell_batch_s& b) {
         b.fdesc.alloc(b.capacity);
         b.sdesc.alloc(b.capacity);
         b.state.alloc(2 * b.capacity);
-        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.state_host), 2 * b.capacity * sizeof(PcgState)));
-        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.sdesc_host), b.capacity * sizeof(SolveDesc)));
-        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.fdesc_host), b.capacity * sizeof(ForceDesc)));
-        SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.mlist_host), (b.capacity + 1) * sizeof(int32_t)));
+        {
+            RuntimeLock lk(runtime_mutex());
+            SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.state_host), 2 * b.capacity * sizeof(PcgState)));
+            SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.sdesc_host), b.capacity * sizeof(SolveDesc)));
+            SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.fdesc_host), b.capacity * sizeof(ForceDesc)));
+            SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&b.mlist_host), (b.capacity + 1) * sizeof(int32_t)));
+        }
         b.mlist.alloc(b.capacity + 1);
     }
     b.fdesc_dirty = true;
 }
 
 void batch_free_host(shell_batch_s& b) {
+    RuntimeLock lk(runtime_mutex());
     for (void** p : {reinterpret_cast<void**>(&b.state_host), reinterpret_cast<void**>(&b.sdesc_host),
                      reinterpret_cast<void**>(&b.fdesc_host), reinterpret_cast<void**>(&b.mlist_host)}) {
         if (*p) (void)hipHostFree(*p);
@@ -777,6 +789,7 @@ void batch_free_host(shell_batch_s& b) {
 void batch_release(shell_batch_s& b) {
     b.graphs.reset();
     batch_free_host(b);
+    RuntimeLock lk(runtime_mutex());
     if (b.items_host) (void)hipHostFree(b.items_host);
     b.items_host = nullptr;
     b.items_cap = 0;

@@ -76,3 +76,49 @@ def test_two_threads_stepping_their_own_batches_match_one_thread():
         for (xs, vs), (xp, vp) in zip(seq[lane], par[lane]):
             assert np.isfinite(xp).all()
             assert np.array_equal(xs, xp) and np.array_equal(vs, vp)
+
+
+def _reader(torch, done, counts, errors):
+    """Builds, exports, reads and frees small problems (allocations, releases, host copies) until the
+    stepping thread is done."""
+    try:
+        k = 0
+        while not done.is_set() and k < 400:
+            with S.Problem(I.plate_mesh(12 + k % 5, model="SS" if k % 2 else "EP"), I.MATERIAL) as pb:
+                S.shell_stencils_export(pb.st)
+                S.shell_hessian_export_csr(pb.h, pb.nv)
+                x, v = S.shell_sim_get_state(pb.sim, pb.nv)[:2]
+                S.shell_sim_set_state(pb.sim, x, v, 0)
+                S.shell_sim_set_held(pb.sim, np.asarray(pb.mesh.pinned, dtype=np.uint8) * 7)
+            k += 1
+        counts.append(k)
+    except BaseException as e:
+        errors.append(("reader", e))
+
+
+def test_host_calls_of_one_thread_leave_another_threads_graph_captures_intact():
+    """One thread steps a batch whose member list changes every step (a graph is captured at each step)
+    while another creates, exports, reads, writes and frees problems of its own: neither call fails, and
+    the stepping thread reaches bit for bit the states it reaches alone."""
+    import torch
+
+    steps = 6
+    alone = [None, None]
+    errors = []
+    _run_lane(1, torch, steps, alone, errors)
+    assert not errors, errors
+    together = [None, None]
+    done = threading.Event()
+    counts = []
+    reader = threading.Thread(target=_reader, args=(torch, done, counts, errors))
+    reader.start()
+    try:
+        _run_lane(1, torch, steps, together, errors)
+    finally:
+        done.set()
+        reader.join(timeout=240)
+    assert not reader.is_alive()
+    assert not errors, errors
+    assert counts and counts[0] >= 1
+    for (xs, vs), (xp, vp) in zip(alone[1], together[1]):
+        assert np.array_equal(xs, xp) and np.array_equal(vs, vp)
