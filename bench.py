@@ -473,8 +473,8 @@ def run_membrane(args):
 def membrane_batch_timing(S, I, torch, count=32, steps=2, warmup=1):
     """A batch of `count` simulations with the membrane (the 64-mesh batch's size and model mix, its
     first `count` specs: 16^2..512^2 vertices, 1 cm spacing, mixed precision, dt = 1/60, Newton budget 4,
-    PCG rtol 1e-2), stepped as one batch (the members one after the other inside one call) against the
-    same simulations stepped one at a time."""
+    PCG rtol 1e-2), stepped as one batch (one call; the members' steps in flight together on their own
+    streams) against the same simulations stepped one at a time."""
     specs = I.batch_specs(64)[:count]
     meshes = [I.mesh_from_spec(sp, spacing=0.01) for sp in specs]
     probs = [S.Problem(m, I.MATERIAL, precision=S.SHELL_PREC_MIXED, flags=S.SHELL_FLAG_MEMBRANE) for m in meshes]

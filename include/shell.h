@@ -362,8 +362,10 @@ shell_status_t shell_sim_device_state(shell_sim_t sim, double** x, double** v);
  * shell_batch_create: sims host [n] distinct handles of one precision, n >= 1; the simulations must
  * outlive the batch and must not be stepped alone while the batch is in use.  Simulations with the
  * membrane (SHELL_FLAG_MEMBRANE) form batches of their own (mixing them with simulations without it is
- * SHELL_E_INVALID_ARG): the members take, one after the other on `stream`, the step each takes alone
- * (bit for bit).  Sampled timing (shell_batch_profile) refuses such a batch (SHELL_E_UNSUPPORTED).
+ * SHELL_E_INVALID_ARG): each member takes the step it takes alone (bit for bit), on a stream of its own
+ * that starts after the work already on `stream`; the calling thread keeps the members' steps in flight
+ * together and returns when every one has finished.  Members may share stencils and Hessian handles.
+ * Sampled timing (shell_batch_profile) refuses such a batch (SHELL_E_UNSUPPORTED).
  * shell_batch_step: params host [nparams], nparams = 1 (shared) or n; stats host [n] or NULL.  Returns
  * the worst per-mesh status (SHELL_E_NONFINITE, then SHELL_E_BUDGET); per-mesh statuses are in stats.
  * Synchronises `stream` at the end of every Newton round.

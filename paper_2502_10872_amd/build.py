@@ -19,13 +19,17 @@ SOURCES = ["host_mesh.cpp", "precompute.hip", "forces.hip", "membrane.hip", "hes
 ARCH = os.environ.get("SHELL_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [
-    "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC",
     "-munsafe-fp-atomics",
     # packed FP32 instructions stay off: plain scalar FP32 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wall", "-Wno-unused-function",
 ]
+
+
+# the membrane step's host side is a C++20 coroutine (resumed as its device values land)
+STD = {"membrane.hip": "-std=c++20"}
 
 
 def hipcc() -> str:
@@ -40,7 +44,8 @@ def build(verbose: bool = False, defines=(), lib: str = LIB, obj: str = OBJ) -> 
     for src in SOURCES:
         o = os.path.join(obj, os.path.splitext(src)[0] + ".o")
         objs.append(o)
-        cmd = [hipcc(), *CFLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", o]
+        cmd = [hipcc(), *CFLAGS, STD.get(src, "-std=c++17"), *[f"-D{d}" for d in defines], "-c",
+               os.path.join(CSRC, src), "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -359,6 +359,7 @@ struct MembraneSolve {
     DevArray<float> ff, svalf, mvalf;
     DevArray<double> ppart;      // per-block partials of the PCG product's p.q
     DevArray<double> scal;   // device scalars of the PCG and the energies
+    DevArray<double> mepart;     // the membrane tiles' energy partials (this simulation's own)
     DevArray<ForceDesc> fdesc;   // bending force at xtry with energy partials
     DevArray<WorkItem> items;
     int64_t ngroups = 0;
@@ -373,6 +374,11 @@ struct MembraneSolve {
     };
     std::vector<PcgGraph> graphs;  // oldest first
     hipStream_t capture = nullptr; // private stream the chunks are captured on
+    // the step's host side, made on first use: a pinned copy of scal, the event marking it filled, and
+    // the stream the simulation steps on inside a batch
+    double* hscal = nullptr;
+    hipEvent_t ready = nullptr;
+    hipStream_t lane = nullptr;
     // device memory held by the arrays above
     size_t bytes() const {
         size_t n = 0;
@@ -381,7 +387,7 @@ struct MembraneSolve {
                          mptr.bytes(), slcol.bytes(), mlcol.bytes(), s2e.bytes(), brow.bytes(), btptr.bytes(), bttri.bytes(),
                          rest.bytes(), xtry.bytes(), ftry.bytes(), z.bytes(), p.bytes(), p2.bytes(), q.bytes(),
                          y.bytes(), r.bytes(), dinv.bytes(), part.bytes(), ff.bytes(), svalf.bytes(), mvalf.bytes(),
-                         ppart.bytes(), scal.bytes(), fdesc.bytes(), items.bytes()})
+                         ppart.bytes(), scal.bytes(), mepart.bytes(), fdesc.bytes(), items.bytes()})
             n += v;
         return n;
     }
@@ -483,7 +489,7 @@ struct shell_batch_s {
     size_t items_cap = 0;
     shell::DevArray<shell::WorkItem> items;   // [rows | tiles of each model]
     shell::DevArray<int32_t> mlist;
-    bool membrane = false;  // simulations with the membrane: the members step one after the other
+    bool membrane = false;  // simulations with the membrane: the members' steps interleave on their own streams
 };
 
 namespace shell {
@@ -506,7 +512,8 @@ void launch_energy_finalize(const double* epart, int64_t n, double add, double* 
 // membrane.hip: rest data of the membrane (SHELL_FLAG_MEMBRANE); its force added into f (internal order,
 // double or float per the stencils' precision) from the float64 positions pos
 void launch_membrane_rest(shell_stencils_s& st, hipStream_t s);
-void launch_membrane_forces(shell_stencils_s& st, const double* pos, void* f, hipStream_t s);
+// epart: where the tiles' energy partials go (the stencils' own array when null)
+void launch_membrane_forces(shell_stencils_s& st, const double* pos, void* f, hipStream_t s, double* epart = nullptr);
 // the implicit step with the membrane: set-up once per simulation, then one step (float64)
 void membrane_sim_init(shell_sim_s& sim, hipStream_t s);
 shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, shell_step_stats_t& out,

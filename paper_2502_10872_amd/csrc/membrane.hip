@@ -13,6 +13,9 @@
 // mixed precision stores the sum as float32.
 #include <algorithm>
 #include <cmath>
+#include <coroutine>
+#include <exception>
+#include <utility>
 
 #include "devmath.hpp"
 #include "internal.hpp"
@@ -776,6 +779,9 @@ MembraneSolve::~MembraneSolve() {
     RuntimeLock lk(runtime_mutex());
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.ex);
     if (capture) (void)hipStreamDestroy(capture);
+    if (lane) (void)hipStreamDestroy(lane);
+    if (ready) (void)hipEventDestroy(ready);
+    if (hscal) (void)hipHostFree(hscal);
 }
 
 void launch_membrane_rest(shell_stencils_s& st, hipStream_t s) {
@@ -805,18 +811,19 @@ void launch_membrane_rest(shell_stencils_s& st, hipStream_t s) {
     SHELL_HIP(hipStreamSynchronize(s));  // the temporaries are released on return
 }
 
-void launch_membrane_forces(shell_stencils_s& st, const double* pos, void* f, hipStream_t s) {
+void launch_membrane_forces(shell_stencils_s& st, const double* pos, void* f, hipStream_t s, double* epart) {
     if (st.nv == 0 || st.nblocks == 0) return;
+    double* ep = epart ? epart : st.mepart.p;
     const double c = st.young * st.thickness / (1.0 - st.poisson * st.poisson);
     const unsigned grid = unsigned(st.nblocks);
     if (st.precision == SHELL_PREC_MIXED)
         membrane_tiles<float><<<grid, kMembThreads, TileAccT<1>::bytes(st.T), s>>>(pos, st.mtid.p, st.mtrest.p, st.mboff.p,
                                                               st.nv, st.T, c, st.poisson, st.mscale, static_cast<float*>(f),
-                                                              st.mepart.p);
+                                                              ep);
     else
         membrane_tiles<double><<<grid, kMembThreads, TileAccT<2>::bytes(st.T), s>>>(pos, st.mtid.p, st.mtrest.p, st.mboff.p,
                                                                st.nv, st.T, c, st.poisson, st.mscale, static_cast<double*>(f),
-                                                               st.mepart.p);
+                                                               ep);
     SHELL_HIP(hipGetLastError());
 }
 
@@ -1045,6 +1052,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->part.alloc(size_t(2 * ms->ngroups + std::max<int64_t>(st.nblocks, 1)));
     ms->ppart.alloc(size_t(kMsPartMax));
     ms->scal.alloc(S_COUNT);
+    ms->mepart.alloc(size_t(std::max<int64_t>(st.nblocks, 1)));
     // bending force at xtry into ftry (mixed: into ff, widened into ftry afterwards), with its energy
     // partials after the reduction partials
     ForceDesc d{};
@@ -1084,10 +1092,10 @@ static void forces_at_try(shell_sim_s& sim, hipStream_t s) {
     const long n3 = 3 * sim.nv;
     launch_force_items(st.model, st.precision, m.fdesc.p, m.items.p, st.nblocks, st.T, s);
     if (m.mixed) {
-        launch_membrane_forces(st, m.xtry.p, m.ff.p, s);
+        launch_membrane_forces(st, m.xtry.p, m.ff.p, s, m.mepart.p);
         ms_widen<<<ms_grid(n3), kMsBlk, 0, s>>>(m.ff.p, m.ftry.p, n3);
     } else {
-        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s);
+        launch_membrane_forces(st, m.xtry.p, m.ftry.p, s, m.mepart.p);
     }
     SHELL_HIP(hipGetLastError());
 }
@@ -1213,8 +1221,61 @@ static void pcg_iterations(MembraneSolve& m, const double* mass, const uint8_t* 
     m.pswap = (count & 1) ? !parity : parity;
 }
 
-shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, shell_step_stats_t& out,
-                             hipStream_t s) {
+namespace {
+
+// The host side of one simulation's step as a resumable task.  It suspends wherever it needs a value its
+// stream has yet to produce, leaving the event that marks the value ready, so that one host thread can
+// keep the steps of several simulations in flight on their own streams.
+struct StepTask {
+    struct promise_type;
+    using Handle = std::coroutine_handle<promise_type>;
+    struct promise_type {
+        shell_status_t rc = SHELL_OK;
+        hipEvent_t wait = nullptr;
+        std::exception_ptr err;
+        StepTask get_return_object() { return StepTask(Handle::from_promise(*this)); }
+        std::suspend_always initial_suspend() noexcept { return {}; }
+        std::suspend_always final_suspend() noexcept { return {}; }
+        void return_value(shell_status_t r) { rc = r; }
+        void unhandled_exception() { err = std::current_exception(); }
+    };
+    Handle h;
+    explicit StepTask(Handle x) : h(x) {}
+    StepTask(StepTask&& o) noexcept : h(std::exchange(o.h, {})) {}
+    StepTask(const StepTask&) = delete;
+    StepTask& operator=(const StepTask&) = delete;
+    ~StepTask() {
+        if (h) h.destroy();
+    }
+    // runs to the next suspension (rethrowing what the step threw); true once the step has returned
+    bool advance() {
+        h.resume();
+        if (h.promise().err) std::rethrow_exception(h.promise().err);
+        return h.done();
+    }
+    hipEvent_t waiting_on() const { return h.promise().wait; }
+    shell_status_t result() const { return h.promise().rc; }
+};
+
+// co_await DeviceReady{e}: suspend until the stream has reached event e
+struct DeviceReady {
+    hipEvent_t ev;
+    bool await_ready() const noexcept { return false; }
+    void await_suspend(StepTask::Handle h) const noexcept { h.promise().wait = ev; }
+    void await_resume() const noexcept {}
+};
+
+void ensure_host_side(MembraneSolve& m) {
+    if (m.hscal && m.ready) return;
+    RuntimeLock lk(runtime_mutex());
+    if (!m.hscal) SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&m.hscal), S_COUNT * sizeof(double)));
+    if (!m.ready) SHELL_HIP(hipEventCreateWithFlags(&m.ready, hipEventDisableTiming));
+}
+
+// One implicit step with the membrane (Sec. 5, eq 62 with the membrane energy of Sec. 3): Newton on the
+// incremental potential, each Newton iteration one PCG over all coordinates against the tangent, then
+// Armijo backtracking; the same kernels in the same order whichever way the task is driven.
+StepTask membrane_step_task(shell_sim_s& sim, shell_step_params_t p, shell_step_stats_t& out, hipStream_t s) {
     shell_stencils_s& st = *sim.st;
     MembraneSolve& m = *sim.ms;
     const bool graphs = (p.flags & SHELL_STEP_NO_GRAPHS) == 0;
@@ -1223,25 +1284,28 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
     double* part = m.part.p;
     double* eb = m.part.p + 2 * ng;
     out = shell_step_stats_t{};
-    double hs[S_COUNT];
-    auto read_scal = [&]() {
-        SHELL_HIP(hipMemcpyAsync(hs, m.scal.p, sizeof(hs), hipMemcpyDeviceToHost, s));
-        SHELL_HIP(hipStreamSynchronize(s));
+    ensure_host_side(m);
+    const double* hs = m.hscal;
+    // the device scalars into the pinned copy; awaiting the result suspends the step until it has landed
+    auto fetch = [&]() {
+        SHELL_HIP(hipMemcpyAsync(m.hscal, m.scal.p, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+        SHELL_HIP(hipEventRecord(m.ready, s));
+        return DeviceReady{m.ready};
     };
-    // energy and force at xtry (force into ftry)
+    // energy and force at xtry (force into ftry); the energy lands in hs[S_E] with the next fetch
     auto evaluate = [&]() {
         forces_at_try(sim, s);
         ms_inertia<<<ms_grid(nv), kMsBlk, 0, s>>>(m.xtry.p, sim.xhat.p, sim.mass.p, nv, part, ng);
-        ms_energy<<<1, kMsBlk, 0, s>>>(eb, st.nblocks, st.mepart.p, st.nblocks, st.bias_e0, part, ng, dt2,
+        ms_energy<<<1, kMsBlk, 0, s>>>(eb, st.nblocks, m.mepart.p, st.nblocks, st.bias_e0, part, ng, dt2,
                                        m.scal.p);
         SHELL_HIP(hipGetLastError());
-        read_scal();
-        return hs[S_E];
     };
     ms_predictor<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.x.p, sim.v.p, sim.xt.p, sim.xhat.p, sim.pinned.p, nv, dt,
                                                  p.gravity[0], p.gravity[1], p.gravity[2]);
     SHELL_HIP(hipMemcpyAsync(m.xtry.p, sim.x.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
-    double E = evaluate();
+    evaluate();
+    co_await fetch();
+    double E = hs[S_E];
     SHELL_HIP(hipMemcpyAsync(sim.f.p, m.ftry.p, size_t(n3) * sizeof(double), hipMemcpyDeviceToDevice, s));
     const bool replay = p.mode == SHELL_PCG_REPLAY;
     double gn0 = 0.0, gn = 0.0;
@@ -1250,7 +1314,7 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
         ms_grad<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.x.p, sim.xhat.p, sim.mass.p, sim.f.p, sim.pinned.p, nv, dt2,
                                                sim.g.p, part, ng);
         ms_fin1<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, S_GSQ);
-        read_scal();
+        co_await fetch();
         if (!std::isfinite(hs[S_GSQ])) {
             nonfinite = true;
             break;
@@ -1270,12 +1334,12 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
         ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.g.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, part, ng);
         ms_fin_init<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, p.pcg_rtol * p.pcg_rtol, target, replay ? 1 : 0);
         SHELL_HIP(hipGetLastError());
-        read_scal();
+        co_await fetch();
         int chunk = 16;
         while (hs[S_ACTIVE] != 0.0) {
             pcg_iterations(m, sim.mass.p, sim.pinned.p, nv, dt2, chunk, graphs, s);
             SHELL_HIP(hipGetLastError());
-            read_scal();
+            co_await fetch();
             chunk = std::min(2 * chunk, 256);
         }
         if (hs[S_BUDGET] == 2.0) {
@@ -1287,13 +1351,15 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
         // Armijo backtracking on the incremental potential
         ms_dot<<<unsigned(ng), kMsBlk, 0, s>>>(sim.g.p, m.y.p, n3, part, ng);  // grid-stride: one partial per group
         ms_fin1<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, S_SLOPE);
-        read_scal();
+        co_await fetch();
         const double slope = hs[S_SLOPE];
         int halv = 0;
         double a = 1.0, Etry = 0.0;
         for (;;) {
             ms_axpy<<<ms_grid(n3), kMsBlk, 0, s>>>(sim.x.p, m.y.p, a, m.xtry.p, n3);
-            Etry = evaluate();
+            evaluate();
+            co_await fetch();
+            Etry = hs[S_E];
             const bool done = replay ? halv >= p.replay_counts[3 * k + 1] : (Etry <= E + 1e-4 * a * slope || halv == 6);
             if (done) break;
             a *= 0.5;
@@ -1309,27 +1375,107 @@ shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, she
     }
     ms_velocity<<<ms_grid(n3), kMsBlk, 0, s>>>(sim.x.p, sim.xt.p, sim.v.p, n3, dt);
     SHELL_HIP(hipGetLastError());
-    SHELL_HIP(hipStreamSynchronize(s));
+    SHELL_HIP(hipEventRecord(m.ready, s));
+    co_await DeviceReady{m.ready};
     out.grad_norm0 = gn0;
     out.grad_norm = gn;
     out.status = nonfinite ? SHELL_E_NONFINITE : (budget ? SHELL_E_BUDGET : SHELL_OK);
     sim.stats = out;
     sim.step++;
     sim.last_stream = s;
-    return shell_status_t(out.status);
+    co_return shell_status_t(out.status);
 }
 
-// A batch of simulations with the membrane: every member takes the step it would take alone (the same
-// kernels on its own state, so the same result bit for bit), one after the other on s.
+// Lanes of a membrane batch that are left with work when a member's step throws are drained before the
+// error propagates, so that no step is still running when the caller reads or frees the members.
+struct LaneDrain {
+    const std::vector<hipStream_t>& lanes;
+    bool armed = true;
+    ~LaneDrain() {
+        if (armed)
+            for (hipStream_t l : lanes) (void)hipStreamSynchronize(l);
+    }
+};
+
+}  // namespace
+
+shell_status_t membrane_step(shell_sim_s& sim, const shell_step_params_t& p, shell_step_stats_t& out,
+                             hipStream_t s) {
+    StepTask t = membrane_step_task(sim, p, out, s);
+    while (!t.advance()) SHELL_HIP(hipStreamSynchronize(s));
+    return t.result();
+}
+
+// A batch of simulations with the membrane.  Every member takes the step it would take alone: the same
+// kernels, in the same order, on its own state, so the same result bit for bit.  The members run on
+// streams of their own, after the work already on s; one host thread keeps their steps in flight
+// together, resuming each whenever the value it waits for has landed (the GPU overlaps one member's
+// kernels with another's and with the host's waits and launches).  Every member's work has finished
+// when the call returns.
 shell_status_t membrane_batch_step(shell_batch_s& b, const shell_step_params_t* p, int nparams,
                                    shell_step_stats_t* stats, hipStream_t s) {
+    const size_t n = b.sims.size();
+    std::vector<shell_step_stats_t> out(n);
     shell_status_t worst = SHELL_OK;
-    for (size_t m = 0; m < b.sims.size(); ++m) {
-        shell_step_stats_t st{};
-        const shell_status_t rc = membrane_step(*b.sims[m], p[nparams == 1 ? 0 : m], st, s);
-        if (stats) stats[m] = st;
+    auto merge = [&](shell_status_t rc) {
         if (rc == SHELL_E_NONFINITE || (rc == SHELL_E_BUDGET && worst == SHELL_OK)) worst = rc;
+    };
+    if (n == 1) {
+        merge(membrane_step(*b.sims[0], p[0], out[0], s));
+    } else if (n > 1) {
+        std::vector<hipStream_t> lanes(n);
+        hipEvent_t start = nullptr;
+        {
+            RuntimeLock lk(runtime_mutex());
+            for (size_t i = 0; i < n; ++i) {
+                MembraneSolve& m = *b.sims[i]->ms;
+                if (!m.lane) SHELL_HIP(hipStreamCreateWithFlags(&m.lane, hipStreamNonBlocking));
+                lanes[i] = m.lane;
+            }
+            SHELL_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+        }
+        struct EventGuard {
+            hipEvent_t e;
+            ~EventGuard() { (void)hipEventDestroy(e); }
+        } start_guard{start};
+        SHELL_HIP(hipEventRecord(start, s));
+        for (hipStream_t l : lanes) SHELL_HIP(hipStreamWaitEvent(l, start, 0));
+        LaneDrain drain{lanes};
+        std::vector<StepTask> tasks;
+        tasks.reserve(n);
+        for (size_t i = 0; i < n; ++i)
+            tasks.push_back(membrane_step_task(*b.sims[i], p[nparams == 1 ? 0 : i], out[i], lanes[i]));
+        std::vector<char> done(n, 0);
+        size_t left = n;
+        while (left > 0) {
+            bool moved = false;
+            for (size_t i = 0; i < n; ++i) {
+                if (done[i]) continue;
+                if (hipEvent_t e = tasks[i].waiting_on()) {
+                    const hipError_t q = hipEventQuery(e);
+                    if (q == hipErrorNotReady) continue;
+                    SHELL_HIP(q);
+                }
+                if (tasks[i].advance()) {
+                    done[i] = 1;
+                    --left;
+                    merge(tasks[i].result());
+                }
+                moved = true;
+            }
+            if (!moved) {
+                // nothing has landed: block on the first member still waiting
+                for (size_t i = 0; i < n; ++i)
+                    if (!done[i]) {
+                        SHELL_HIP(hipEventSynchronize(tasks[i].waiting_on()));
+                        break;
+                    }
+            }
+        }
+        drain.armed = false;
     }
+    if (stats)
+        for (size_t i = 0; i < n; ++i) stats[i] = out[i];
     return worst;
 }
 

@@ -377,10 +377,15 @@ def shell_sim_time_kernels(sim, dt, reps=20, stream=None) -> dict:
     return {name: getattr(out, name) for name, _ in shell_kernel_times_t._fields_ if name != "reserved"}
 
 
+# member count of each live batch handle: the stats buffer of a step must hold one record per member
+_batch_members = {}
+
+
 def shell_batch_create(sims):
     arr = (ctypes.c_void_p * len(sims))(*sims)
     out = ctypes.c_void_p()
     _check(lib().shell_batch_create(arr, len(sims), ctypes.byref(out)), "shell_batch_create")
+    _batch_members[out.value] = len(sims)
     return out.value
 
 
@@ -388,6 +393,8 @@ def shell_batch_step(batch, params, n, with_stats=True, stream=None, allow_nonfi
     """params: one shell_step_params_t (shared) or a list of n.  Returns (status, [stats dict] or None).
     SHELL_E_BUDGET is returned, not raised; so is SHELL_E_NONFINITE with allow_nonfinite (the per-mesh
     statuses in the stats then say which meshes went non-finite)."""
+    if batch in _batch_members and n != _batch_members[batch]:
+        raise ValueError(f"shell_batch_step: n = {n}, but the batch has {_batch_members[batch]} members")
     plist = params if isinstance(params, (list, tuple)) else [params]
     parr = (shell_step_params_t * len(plist))(*plist)
     stats = (shell_step_stats_t * n)()
@@ -400,6 +407,7 @@ def shell_batch_step(batch, params, n, with_stats=True, stream=None, allow_nonfi
 def shell_batch_reset(batch, sims):
     arr = (ctypes.c_void_p * len(sims))(*sims)
     _check(lib().shell_batch_reset(batch, arr, len(sims)), "shell_batch_reset")
+    _batch_members[batch] = len(sims)
 
 
 def shell_sim_device_bytes(sim) -> int:
@@ -443,6 +451,7 @@ def shell_sim_profile_read(sim) -> dict:
 
 
 def shell_destroy_batch(batch):
+    _batch_members.pop(batch, None)
     lib().shell_destroy_batch(batch)
 
 

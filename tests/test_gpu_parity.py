@@ -556,6 +556,50 @@ def test_membrane_batch_equals_each_simulation_alone(prec):
             pb.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_membrane_batch_members_sharing_stencils_step_as_alone(prec):
+    """Simulations made from one stencils handle and its Hessian, with different initial velocities,
+    stepped together in a batch (their steps in flight at once on their own streams) reach bit for bit
+    the states that stepping each alone reaches: nothing a step writes lives in the shared handles.
+    Sizes below and above the one-work-group solver's limit."""
+    precision = S.SHELL_PREC_MIXED if prec == "mixed" else S.SHELL_PREC_FP64
+    params, _keep = S.step_params(1 / 60, max_newton=3, newton_rtol=1e-8, pcg_rtol=1e-6)
+    rng = np.random.default_rng(7)
+    handles = []  # (destroy, handle), destroyed in reverse
+    members, twins, nvs = [], [], []
+    try:
+        for n, model, count in ((26, "SS", 3), (17, "FS", 2)):
+            m = I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 3, model, "ends")
+            st = S.shell_build_stencils(m.X, m.tris, model, MAT, precision, 128, flags=S.SHELL_FLAG_MEMBRANE)
+            handles.append((S.shell_destroy_stencils, st))
+            h = S.shell_assemble_constant_hessian(st)
+            handles.append((S.shell_destroy_hessian, h))
+            for k in range(count):
+                v0 = 0.05 * (k + 1) * rng.standard_normal((m.nv, 3))
+                for out in (members, twins):
+                    sim = S.shell_sim_create(st, h, m.X, v0, m.pinned)
+                    handles.append((S.shell_destroy_sim, sim))
+                    out.append(sim)
+                nvs.append(m.nv)
+        batch = S.shell_batch_create(members)
+        try:
+            for _ in range(2):
+                rc, stats = S.shell_batch_step(batch, params, len(members))
+                for k, t in enumerate(twins):
+                    rc1, st1 = S.shell_step_implicit(t, params)
+                    assert st1["pcg_total"] == stats[k]["pcg_total"] and st1["newton_iters"] == stats[k]["newton_iters"]
+        finally:
+            S.shell_destroy_batch(batch)
+        for sim, t, nv in zip(members, twins, nvs):
+            xa, va, sa = S.shell_sim_get_state(sim, nv)
+            xb, vb, sb = S.shell_sim_get_state(t, nv)
+            assert sa == sb == 2
+            assert np.isfinite(xa).all() and np.array_equal(xa, xb) and np.array_equal(va, vb)
+    finally:
+        for destroy, hnd in reversed(handles):
+            destroy(hnd)
+
+
 @pytest.mark.parametrize("model", ["SS", "ES"])
 def test_mixed_membrane_step_replay_matches_oracle(model):
     """The step with the membrane in mixed precision (float32 forces, float32 K_s and tangent blocks in

@@ -56,6 +56,18 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(S.shell_hessian_info_t) == 5 * 8 + 2 * 4
 
 
+def test_batch_step_refuses_a_stats_count_other_than_the_member_count():
+    # the stats buffer holds one record per member: a wrong count is refused before the library is called
+    params, _keep = S.step_params(1 / 60)
+    fake = 0x7E57
+    S._batch_members[fake] = 3
+    try:
+        with pytest.raises(ValueError, match="3 members"):
+            S.shell_batch_step(fake, params, 1)
+    finally:
+        S._batch_members.pop(fake, None)
+
+
 def test_workload_shapes():
     m = I.workload_plate32()
     assert m.nv == 1024 and m.nt == 1922 and m.pinned.sum() == 64
