@@ -134,7 +134,11 @@ __global__ __launch_bounds__(kMembThreads) void membrane_tiles(const double* __r
 constexpr int kMsBlk = 256;
 // device scalars
 enum : int { S_RZ, S_RZN, S_PQ, S_RR, S_RR0, S_TOL2, S_ALPHA, S_BETA, S_GSQ, S_SLOPE, S_E, S_IT, S_TARGET,
-             S_ACTIVE, S_REPLAY, S_BUDGET, S_YMAX, S_COUNT };
+             S_ACTIVE, S_REPLAY, S_BUDGET, S_YMAX, S_FRESH, S_COUNT };
+// The coupled PCG's state lives in two sets of these scalars (set k at scal + k S_COUNT) that alternate
+// with the direction buffers: a product reads its iteration's state from one set and stores the next into
+// the other, which no work-group of the same launch reads.  The solve's constants (S_TOL2, S_TARGET,
+// S_REPLAY, S_RR0) and the step's other scalars stay in set 0; the one-work-group solver uses set 0 only.
 
 template <int NQ>
 __device__ __forceinline__ void ms_partials(double (&v)[NQ], double* part, long ngroups) {
@@ -366,13 +370,88 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__
         scal[S_BUDGET] = 0.0;
         scal[S_BETA] = 0.0;
         scal[S_ACTIVE] = (0 < target && (replay || t[1] > rtol2 * t[1])) ? 1.0 : 0.0;
+        scal[S_FRESH] = 1.0;
     }
 }
 
-// The coupled PCG iteration in four kernels, none with cross-block synchronisation inside it: the
-// product writes per-work-group partials of p.q, one work-group sums them in a fixed order into alpha,
-// the update reads alpha, and one work-group finishes the update's partials and the stop test.  The
-// product and the update stride over the rows with at most kMsPartMax work-groups.
+// The coupled PCG iteration in two kernels, none with cross-block synchronisation inside it: the product
+// first finishes the previous update (r.z, r.r, beta, the count and the stop test from the update's
+// partials, summed by every work-group alike in one fixed order) and writes per-work-group partials of
+// p.q; the update sums those (or, with many, one work-group does, into alpha) and writes its own partials.
+// A chunk of iterations ends with a one-work-group kernel that finishes the last update, so that the host
+// reads the exact state; on large meshes (many update partials) that kernel runs after every iteration
+// and the product finds the state settled.  The product and the update stride over the rows with at most
+// kMsPartMax work-groups.
+
+// Totals of the update's two partial arrays (ung entries each) in one fixed order whatever the work-group
+// size: the first kMsBlk threads stride over them, then the wave sums in order; valid in thread 0.  sh
+// holds 2 * (blockDim.x / 64) doubles.
+__device__ __forceinline__ void ms_update_totals(const double* __restrict__ upart, long ung, double (&t)[2],
+                                                 double* sh) {
+    t[0] = t[1] = 0.0;
+    if (threadIdx.x < kMsBlk)
+        for (long b = threadIdx.x; b < ung; b += kMsBlk) {
+            t[0] += upart[b];
+            t[1] += upart[ung + b];
+        }
+    block_sum<2>(t, sh);
+}
+
+// One thread: the state that follows `sin` once the update with partial totals t has run (beta, r.z, r.r,
+// the count, the budget and the activity), into `out` (which may be sin); the constants from `cst`.
+__device__ __forceinline__ void ms_finish_to(const double* cst, const double* sin, const double (&t)[2], double* out) {
+    const double rz = sin[S_RZ], it = sin[S_IT] + 1.0, target = cst[S_TARGET];
+    double budget = sin[S_BUDGET];
+    const bool replay = cst[S_REPLAY] != 0.0;
+    const bool more = replay || t[1] > cst[S_TOL2];
+    if (!replay && it >= target && more) budget = 1.0;
+    if (!isfinite(t[1])) budget = 2.0;
+    out[S_BETA] = rz != 0.0 ? t[0] / rz : 0.0;
+    out[S_RZ] = t[0];
+    out[S_RR] = t[1];
+    out[S_IT] = it;
+    out[S_BUDGET] = budget;
+    out[S_ACTIVE] = (it < target && more && isfinite(t[1])) ? 1.0 : 0.0;
+}
+
+// The state a product's iteration starts from, alike in every work-group: set `sin` as the previous product
+// left it, finished here from the previous update's partials unless it is settled (S_FRESH: the solve's
+// first iteration, or the first of a chunk after ms_iter_settle) or stopped.  Work-group 0 stores it,
+// unsettled, into `sout` for the update and the next product.  Returns false when the solve has stopped;
+// beta otherwise.
+__device__ __forceinline__ bool ms_iteration_state(const double* cst, const double* __restrict__ sin,
+                                                   double* __restrict__ sout, const double* __restrict__ upart,
+                                                   long ung, double& beta) {
+    __shared__ double sh[2 * (kRowGroup / 64)];
+    __shared__ double res[2];
+    const bool settled = sin[S_FRESH] != 0.0, running = sin[S_ACTIVE] != 0.0;  // the same in every thread
+    double t[2] = {0.0, 0.0};
+    if (!settled && running) ms_update_totals(upart, ung, t, sh);
+    if (threadIdx.x == 0) {
+        double o[S_COUNT];
+        o[S_RZ] = sin[S_RZ];
+        o[S_RR] = sin[S_RR];
+        o[S_IT] = sin[S_IT];
+        o[S_BUDGET] = sin[S_BUDGET];
+        o[S_ACTIVE] = sin[S_ACTIVE];
+        o[S_BETA] = sin[S_BETA];
+        if (!settled && running) ms_finish_to(cst, sin, t, o);
+        if (blockIdx.x == 0) {
+            sout[S_RZ] = o[S_RZ];
+            sout[S_RR] = o[S_RR];
+            sout[S_IT] = o[S_IT];
+            sout[S_BUDGET] = o[S_BUDGET];
+            sout[S_ACTIVE] = o[S_ACTIVE];
+            sout[S_BETA] = o[S_BETA];
+            sout[S_FRESH] = 0.0;
+        }
+        res[0] = o[S_BETA];
+        res[1] = o[S_ACTIVE];
+    }
+    __syncthreads();
+    beta = res[0];
+    return res[1] != 0.0;
+}
 
 // p_new = z + beta p_old (row i, stored) and q = M p_new + dt^2 (K_s (x) I3 + K_m) p_new, the neighbours'
 // p_new formed on the fly from their z and p_old; fixed rows zero; partial p.q.  LANES lanes share a row:
@@ -404,8 +483,9 @@ inline unsigned ms_update_grid(long nv) {
 // annihilate translations (their rows of 3x3 blocks sum to zero), and this form keeps that exactly
 // whatever the rounding of the entries, as the bending product's mixed form does.
 template <typename VT, int LANES>
-__global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restrict__ scal,
-                                                          const int64_t* __restrict__ srow,
+__global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* cst, const double* __restrict__ sin,
+                                                          double* __restrict__ sout, const double* __restrict__ upart,
+                                                          long ung, const int64_t* __restrict__ srow,
                                                           const int32_t* __restrict__ scol, const VT* __restrict__ sval,
                                                           const int64_t* __restrict__ mrow, const int32_t* __restrict__ mcol,
                                                           const VT* __restrict__ mval, const double* __restrict__ mass,
@@ -413,8 +493,8 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restri
                                                           const double* __restrict__ pold, double* __restrict__ pnew,
                                                           double* __restrict__ q, long nv, double dt2,
                                                           double* __restrict__ ppart, long npart) {
-    if (scal[S_ACTIVE] == 0.0) return;
-    const double be = scal[S_BETA];
+    double be;
+    if (!ms_iteration_state(cst, sin, sout, upart, ung, be)) return;
     constexpr int ROWS = kMsBlk / LANES;
     const int lane = threadIdx.x % LANES;
     double v[1] = {0.0};
@@ -465,7 +545,8 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* __restri
 // update reads next from the caches (measured at 1M vertices: 173 -> 144 us FP64, 112 -> 92 us mixed).
 template <typename VT>
 __global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
-    const double* __restrict__ scal, const int64_t* __restrict__ sptr, const int32_t* __restrict__ swidth,
+    const double* cst, const double* __restrict__ sin, double* __restrict__ sout, const double* __restrict__ upart,
+    long ung, const int64_t* __restrict__ sptr, const int32_t* __restrict__ swidth,
     const uint16_t* __restrict__ slcol, const VT* __restrict__ sval, const int64_t* __restrict__ mptr,
     const int32_t* __restrict__ mwidth, const uint16_t* __restrict__ mlcol, const VT* __restrict__ mval, long mstride,
     const int32_t* __restrict__ gptr, const int32_t* __restrict__ gcols, const int32_t* __restrict__ gself,
@@ -474,8 +555,8 @@ __global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
     double* __restrict__ ppart) {
     extern __shared__ double ps[];
     __shared__ double red[kRowGroup / 64];
-    if (scal[S_ACTIVE] == 0.0) return;
-    const double be = scal[S_BETA];
+    double be;
+    if (!ms_iteration_state(cst, sin, sout, upart, ung, be)) return;
     constexpr bool DIFF = sizeof(VT) == 4;
     const long ngroups = (nv + kRowGroup - 1) / kRowGroup, nslices = (nv + 63) / 64;
     double v = 0.0;
@@ -538,41 +619,45 @@ __global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
     }
 }
 
-// The update sums the product's partials itself (FUSED) up to this many partials.
+// The update sums the product's partials itself (FUSED) up to this many partials, and the product the
+// update's (finishing the previous iteration) up to this many.
 constexpr long kMsFuseAlphaMax = 256;
+constexpr long kMsFuseFinishMax = 256;
 
-// p.q from the product's partials (one work-group, fixed order), then alpha = r.z / p.q
+// p.q from the product's partials (one work-group, fixed order), then alpha = r.z / p.q, in the state set
+// `st` that the product wrote
 __global__ __launch_bounds__(kMsBlk) void ms_iter_alpha(const double* __restrict__ ppart, long npart,
-                                                        double* __restrict__ scal) {
-    if (scal[S_ACTIVE] == 0.0) return;
+                                                        double* __restrict__ st) {
+    if (st[S_ACTIVE] == 0.0) return;
     double pq[1];
     ms_totals<1>(ppart, npart, pq);
     if (threadIdx.x == 0) {
-        scal[S_PQ] = pq[0];
-        scal[S_ALPHA] = pq[0] != 0.0 ? scal[S_RZ] / pq[0] : 0.0;
+        st[S_PQ] = pq[0];
+        st[S_ALPHA] = pq[0] != 0.0 ? st[S_RZ] / pq[0] : 0.0;
     }
 }
 
 // y += alpha p, r -= alpha q, z = D^-1 r; partials r.z and r.r.  alpha from ms_iter_alpha, or, with FUSED
 // (few product partials), summed by every work-group itself from the product's partials in the same fixed
-// order as ms_iter_alpha sums them (the same bits), which saves that launch on small meshes.
+// order as ms_iter_alpha sums them (the same bits), which saves that launch on small meshes.  `st`: the
+// state set the product wrote.
 template <bool FUSED>
-__global__ __launch_bounds__(kMsBlk) void ms_iter_update(const double* __restrict__ scal, const double* __restrict__ p,
+__global__ __launch_bounds__(kMsBlk) void ms_iter_update(const double* __restrict__ st, const double* __restrict__ p,
                                                          const double* __restrict__ q, const double* __restrict__ dinv,
                                                          double* __restrict__ y, double* __restrict__ r,
                                                          double* __restrict__ z, long nv, double* __restrict__ part,
                                                          long ngroups, const double* __restrict__ ppart, long npart) {
-    if (scal[S_ACTIVE] == 0.0) return;
+    if (st[S_ACTIVE] == 0.0) return;
     double al;
     if constexpr (FUSED) {
         __shared__ double al_sh;
         double pq[1];
         ms_totals<1>(ppart, npart, pq);
-        if (threadIdx.x == 0) al_sh = pq[0] != 0.0 ? scal[S_RZ] / pq[0] : 0.0;
+        if (threadIdx.x == 0) al_sh = pq[0] != 0.0 ? st[S_RZ] / pq[0] : 0.0;
         __syncthreads();
         al = al_sh;
     } else {
-        al = scal[S_ALPHA];
+        al = st[S_ALPHA];
     }
     double v[2] = {0.0, 0.0};
     for (long i = blockIdx.x * long(blockDim.x) + threadIdx.x; i < nv; i += long(gridDim.x) * blockDim.x)
@@ -593,8 +678,8 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_update(const double* __restric
 // LDS for the launch (p is read from and written back to m.p at its ends); LANES lanes share a row's
 // entries (consecutive lanes, consecutive entries) and combine their sums by shuffles.  The same
 // recurrence and stop test: p = z + beta p, q with held coordinates zero, alpha = r.z / p.q, y, r, z
-// updated, then beta, the count, the budget and the activity from r.z and r.r exactly as ms_iter_finish
-// takes them.  Sums are per wave, then over the waves in a fixed order, so a run is reproducible; VT as
+// updated, then beta, the count, the budget and the activity from r.z and r.r exactly as ms_finish_to
+// takes them (in state set 0).  Sums are per wave, then over the waves in a fixed order, so a run is reproducible; VT as
 // in ms_iter_product (float32 entries in difference form).  Measured: one thread per row of a
 // 1088-vertex mesh took 38 us per iteration (each row's gathers one after another), three times the
 // kernel chain; with p in LDS and several lanes per row the one-work-group solver wins up to some
@@ -723,24 +808,19 @@ void launch_pcg_small(MembraneSolve& m, const VT* sval, const VT* mval, const do
         launch_pcg_small_lanes<VT, 2>(m, sval, mval, mass, pinned, nv, dt2, s);
 }
 
-// r.z and r.r, then beta, the iteration count and the stop test (one block)
-__global__ __launch_bounds__(kMsBlk) void ms_iter_finish(const double* __restrict__ part, long ngroups,
-                                                         double* __restrict__ scal) {
-    if (scal[S_ACTIVE] == 0.0) return;
+// The end of a chunk of iterations (one block): the last update's state finished in place in set `cur`
+// and marked settled, so that the host reads the exact state and the next chunk's first product takes it
+// as it is.
+__global__ __launch_bounds__(kMsBlk) void ms_iter_settle(const double* __restrict__ upart, long ung, double* scal,
+                                                         int cur) {
+    double* st = scal + S_COUNT * cur;
+    if (st[S_FRESH] != 0.0 || st[S_ACTIVE] == 0.0) return;
+    __shared__ double sh[2 * (kMsBlk / 64)];
     double t[2];
-    ms_totals<2>(part, ngroups, t);
+    ms_update_totals(upart, ung, t, sh);
     if (threadIdx.x == 0) {
-        const double rz = scal[S_RZ];
-        scal[S_BETA] = rz != 0.0 ? t[0] / rz : 0.0;
-        scal[S_RZ] = t[0];
-        scal[S_RR] = t[1];
-        const double it = scal[S_IT] + 1.0, target = scal[S_TARGET];
-        const bool replay = scal[S_REPLAY] != 0.0;
-        const bool more = replay || t[1] > scal[S_TOL2];
-        if (!replay && it >= target && more) scal[S_BUDGET] = 1.0;
-        scal[S_IT] = it;
-        scal[S_ACTIVE] = (it < target && more && isfinite(t[1])) ? 1.0 : 0.0;
-        if (!isfinite(t[1])) scal[S_BUDGET] = 2.0;
+        ms_finish_to(scal, st, t, st);
+        st[S_FRESH] = 1.0;
     }
 }
 
@@ -1052,7 +1132,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->ngroups = long(ms_grid(nv));
     ms->part.alloc(size_t(2 * ms->ngroups + std::max<int64_t>(st.nblocks, 1)));
     ms->ppart.alloc(size_t(kMsPartMax));
-    ms->scal.alloc(S_COUNT);
+    ms->scal.alloc(2 * S_COUNT);  // two sets of the PCG state
     ms->mepart.alloc(size_t(std::max<int64_t>(st.nblocks, 1)));
     // bending force at xtry into ftry (mixed: into ff, widened into ftry afterwards), with its energy
     // partials after the reduction partials
@@ -1123,31 +1203,34 @@ static void tangent_at(shell_sim_s& sim, const double* x, const double* mass, do
 // the other, the update kernel reads it; the buffers alternate.  Once the stop test has cleared the active
 // flag all three kernels return at once, so the alternation may run on past the last iteration.
 // The coupled product q = (M + dt^2 (K_s (x) I3 + K_m)) p_new with p_new = z + beta p_old written to pnew,
-// and its per-work-group partials of p.q in m.ppart; returns the number of partials.
+// and its per-work-group partials of p.q in m.ppart, after it has taken the iteration's state from set
+// `sin` (finishing the previous update from its partials) and stored it into set `sout`; returns the
+// number of partials.
 static long launch_product(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2,
-                           const double* pold, double* pnew, hipStream_t s) {
+                           const double* pold, double* pnew, const double* sin, double* sout, hipStream_t s) {
+    const long ung = long(ms_update_grid(nv));
     if (m.staged) {
         const unsigned pg = unsigned(std::min(kMsPartMax, (nv + kRowGroup - 1) / kRowGroup));
         const size_t lds = size_t(m.max_gcols) * 3 * sizeof(double);
         if (m.mixed)
             ms_iter_product_staged<float><<<pg, kRowGroup, lds, s>>>(
-                m.scal.p, m.hsptr, m.hwidth, m.slcol.p, m.hvalf, m.mptr.p, m.mwidth.p, m.mlcol.p, m.mvalf.p,
+                m.scal.p, sin, sout, m.part.p, ung, m.hsptr, m.hwidth, m.slcol.p, m.hvalf, m.mptr.p, m.mwidth.p, m.mlcol.p, m.mvalf.p,
                 long(m.mstride), m.gptr.p, m.gcols.p, m.gself.p, mass, pinned, m.z.p, pold, pnew, m.q.p, nv, dt2,
                 m.ppart.p);
         else
             ms_iter_product_staged<double><<<pg, kRowGroup, lds, s>>>(
-                m.scal.p, m.hsptr, m.hwidth, m.slcol.p, m.hval, m.mptr.p, m.mwidth.p, m.mlcol.p, m.mval.p,
+                m.scal.p, sin, sout, m.part.p, ung, m.hsptr, m.hwidth, m.slcol.p, m.hval, m.mptr.p, m.mwidth.p, m.mlcol.p, m.mval.p,
                 long(m.mstride), m.gptr.p, m.gcols.p, m.gself.p, mass, pinned, m.z.p, pold, pnew, m.q.p, nv, dt2,
                 m.ppart.p);
         return long(pg);
     }
     const unsigned pg = ms_product_grid(nv, m.mixed ? kMsLanesF32 : kMsLanesF64);
     if (m.mixed)
-        ms_iter_product<float, kMsLanesF32><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.svalf.p, m.mrow.p,
+        ms_iter_product<float, kMsLanesF32><<<pg, kMsBlk, 0, s>>>(m.scal.p, sin, sout, m.part.p, ung, m.srow.p, m.scol.p, m.svalf.p, m.mrow.p,
                                                                   m.mcol.p, m.mvalf.p, mass, pinned, m.z.p, pold, pnew,
                                                                   m.q.p, nv, dt2, m.ppart.p, long(pg));
     else
-        ms_iter_product<double, kMsLanesF64><<<pg, kMsBlk, 0, s>>>(m.scal.p, m.srow.p, m.scol.p, m.sval.p, m.mrow.p,
+        ms_iter_product<double, kMsLanesF64><<<pg, kMsBlk, 0, s>>>(m.scal.p, sin, sout, m.part.p, ung, m.srow.p, m.scol.p, m.sval.p, m.mrow.p,
                                                                    m.mcol.p, m.mval.p, mass, pinned, m.z.p, pold, pnew,
                                                                    m.q.p, nv, dt2, m.ppart.p, long(pg));
     return long(pg);
@@ -1157,25 +1240,36 @@ static void pcg_iteration(MembraneSolve& m, const double* mass, const uint8_t* p
                           hipStream_t s) {
     double* pold = m.pswap ? m.p2.p : m.p.p;
     double* pnew = m.pswap ? m.p.p : m.p2.p;
-    const long np = launch_product(m, mass, pinned, nv, dt2, pold, pnew, s);
+    const double* sin = m.scal.p + (m.pswap ? S_COUNT : 0);
+    double* sout = m.scal.p + (m.pswap ? 0 : S_COUNT);
+    const long np = launch_product(m, mass, pinned, nv, dt2, pold, pnew, sin, sout, s);
     const unsigned ug = ms_update_grid(nv);
     if (np <= kMsFuseAlphaMax) {
-        ms_iter_update<true><<<ug, kMsBlk, 0, s>>>(m.scal.p, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p,
+        ms_iter_update<true><<<ug, kMsBlk, 0, s>>>(sout, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p,
                                                    long(ug), m.ppart.p, np);
     } else {
-        ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, m.scal.p);
-        ms_iter_update<false><<<ug, kMsBlk, 0, s>>>(m.scal.p, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
+        ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, sout);
+        ms_iter_update<false><<<ug, kMsBlk, 0, s>>>(sout, pnew, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
                                                     m.part.p, long(ug), m.ppart.p, np);
     }
-    ms_iter_finish<<<1, kMsBlk, 0, s>>>(m.part.p, long(ug), m.scal.p);
     m.pswap = !m.pswap;
+    // with many update partials one work-group settles the state after every iteration instead (every
+    // product work-group summing them delays the start of its stream: at 1M vertices 151 against 144 us)
+    if (ug > kMsFuseFinishMax) ms_iter_settle<<<1, kMsBlk, 0, s>>>(m.part.p, long(ug), m.scal.p, m.pswap ? 1 : 0);
 }
 
 constexpr size_t kMsMaxGraphs = 16;
 
-// `count` PCG iterations.  With graphs allowed a chunk is captured once on a private stream and replayed
-// (the kernels read the scalars and vectors when the graph runs, so one capture serves every solve with
-// the same mass array, dt and buffer parity); otherwise the kernels are launched one by one.
+// `count` PCG iterations and the settling of their last update's state (which the host then reads from set
+// m.pswap).  With graphs allowed a chunk is captured once on a private stream and replayed (the kernels
+// read the scalars and vectors when the graph runs, so one capture serves every solve with the same mass
+// array, dt and buffer parity); otherwise the kernels are launched one by one.
+static void pcg_chunk(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2, int count,
+                      hipStream_t s) {
+    for (int it = 0; it < count; ++it) pcg_iteration(m, mass, pinned, nv, dt2, s);
+    ms_iter_settle<<<1, kMsBlk, 0, s>>>(m.part.p, long(ms_update_grid(nv)), m.scal.p, m.pswap ? 1 : 0);
+}
+
 static void pcg_iterations(MembraneSolve& m, const double* mass, const uint8_t* pinned, long nv, double dt2,
                            int count, bool graphs, hipStream_t s) {
     if (nv <= kMsSmallRows && !m.staged) {  // one work-group runs the iterations (m.p holds the direction)
@@ -1189,7 +1283,7 @@ static void pcg_iterations(MembraneSolve& m, const double* mass, const uint8_t* 
         return;
     }
     if (!graphs) {
-        for (int it = 0; it < count; ++it) pcg_iteration(m, mass, pinned, nv, dt2, s);
+        pcg_chunk(m, mass, pinned, nv, dt2, count, s);
         return;
     }
     const bool parity = m.pswap;
@@ -1201,7 +1295,7 @@ static void pcg_iterations(MembraneSolve& m, const double* mass, const uint8_t* 
         if (!m.capture) SHELL_HIP(hipStreamCreateWithFlags(&m.capture, hipStreamNonBlocking));
         hipGraph_t g = nullptr;
         SHELL_HIP(hipStreamBeginCapture(m.capture, hipStreamCaptureModeThreadLocal));
-        for (int it = 0; it < count; ++it) pcg_iteration(m, mass, pinned, nv, dt2, m.capture);
+        pcg_chunk(m, mass, pinned, nv, dt2, count, m.capture);
         const hipError_t launched = hipGetLastError();
         const hipError_t ended = hipStreamEndCapture(m.capture, &g);
         m.pswap = parity;
@@ -1269,7 +1363,7 @@ struct DeviceReady {
 void ensure_host_side(MembraneSolve& m) {
     if (m.hscal && m.ready) return;
     RuntimeLock lk(runtime_mutex());
-    if (!m.hscal) SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&m.hscal), S_COUNT * sizeof(double)));
+    if (!m.hscal) SHELL_HIP(hipHostMalloc(reinterpret_cast<void**>(&m.hscal), 2 * S_COUNT * sizeof(double)));
     if (!m.ready) SHELL_HIP(hipEventCreateWithFlags(&m.ready, hipEventDisableTiming));
 }
 
@@ -1287,9 +1381,11 @@ StepTask membrane_step_task(shell_sim_s& sim, shell_step_params_t p, shell_step_
     out = shell_step_stats_t{};
     ensure_host_side(m);
     const double* hs = m.hscal;
+    // the PCG state set the last iterations left (set 0 right after ms_fin_init)
+    auto pcg = [&]() { return hs + (m.pswap ? S_COUNT : 0); };
     // the device scalars into the pinned copy; awaiting the result suspends the step until it has landed
     auto fetch = [&]() {
-        SHELL_HIP(hipMemcpyAsync(m.hscal, m.scal.p, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+        SHELL_HIP(hipMemcpyAsync(m.hscal, m.scal.p, 2 * S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
         SHELL_HIP(hipEventRecord(m.ready, s));
         return DeviceReady{m.ready};
     };
@@ -1337,18 +1433,18 @@ StepTask membrane_step_task(shell_sim_s& sim, shell_step_params_t p, shell_step_
         SHELL_HIP(hipGetLastError());
         co_await fetch();
         int chunk = 16;
-        while (hs[S_ACTIVE] != 0.0) {
+        while (pcg()[S_ACTIVE] != 0.0) {
             pcg_iterations(m, sim.mass.p, sim.pinned.p, nv, dt2, chunk, graphs, s);
             SHELL_HIP(hipGetLastError());
             co_await fetch();
             chunk = std::min(2 * chunk, 256);
         }
-        if (hs[S_BUDGET] == 2.0) {
+        if (pcg()[S_BUDGET] == 2.0) {
             nonfinite = true;
             break;
         }
-        budget |= hs[S_BUDGET] != 0.0;
-        const int its = int(hs[S_IT]);
+        budget |= pcg()[S_BUDGET] != 0.0;
+        const int its = int(pcg()[S_IT]);
         // Armijo backtracking on the incremental potential
         ms_dot<<<unsigned(ng), kMsBlk, 0, s>>>(sim.g.p, m.y.p, n3, part, ng);  // grid-stride: one partial per group
         ms_fin1<<<1, kMsBlk, 0, s>>>(part, ng, m.scal.p, S_SLOPE);
@@ -1486,11 +1582,13 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
         sim.zmass.alloc(size_t(nv));
         ms_zero<<<ms_grid(nv), kMsBlk, 0, s>>>(sim.zmass.p, nv);
     }
-    double hs[S_COUNT];
+    double hs[2 * S_COUNT];
     auto read_scal = [&]() {
         SHELL_HIP(hipMemcpyAsync(hs, m.scal.p, sizeof(hs), hipMemcpyDeviceToHost, s));
         SHELL_HIP(hipStreamSynchronize(s));
     };
+    // the PCG state set the last iterations left (set 0 right after ms_fin_init)
+    auto pcg = [&]() { return hs + (m.pswap ? S_COUNT : 0); };
     // bending plus membrane force at xtry into ftry, then the load added: ftry = f + F
     auto forces_and_load = [&]() {
         forces_at_try(sim, s);
@@ -1527,18 +1625,18 @@ shell_status_t membrane_static(shell_sim_s& sim, const shell_step_params_t& p, c
         SHELL_HIP(hipGetLastError());
         read_scal();
         int chunk = 16;
-        while (hs[S_ACTIVE] != 0.0) {
+        while (pcg()[S_ACTIVE] != 0.0) {
             pcg_iterations(m, sim.zmass.p, sim.pinned.p, nv, 1.0, chunk, graphs, s);
             SHELL_HIP(hipGetLastError());
             read_scal();
             chunk = std::min(2 * chunk, 256);
         }
-        if (hs[S_BUDGET] == 2.0) {
+        if (pcg()[S_BUDGET] == 2.0) {
             nonfinite = true;
             break;
         }
-        budget |= hs[S_BUDGET] != 0.0;
-        const int its = int(hs[S_IT]);
+        budget |= pcg()[S_BUDGET] != 0.0;
+        const int its = int(pcg()[S_IT]);
         // incremental displacement limit
         double scale = 1.0;
         if (qs.eps_u > 0.0) {
@@ -1589,21 +1687,32 @@ void membrane_time_kernels(shell_sim_s& sim, double dt, int reps, shell_kernel_t
     ms_pcg_init<<<ms_grid(nv), kMsBlk, 0, s>>>(m.ftry.p, m.dinv.p, m.r.p, m.z.p, m.p.p, m.y.p, nv, m.part.p, ng);
     ms_fin_init<<<1, kMsBlk, 0, s>>>(m.part.p, ng, m.scal.p, 0.0, 1 << 30, 1);
     const unsigned ug = ms_update_grid(nv);
-    long np = 0;
+    double* set0 = m.scal.p;
+    double* set1 = m.scal.p + S_COUNT;
+    // one iteration first (state set 0 -> 1, then the update's partials), so that the timed products read
+    // an unsettled running state (set 1) and finish it from those partials, as inside a solve
+    long np = launch_product(m, sim.mass.p, sim.pinned.p, nv, dt2, m.p.p, m.p2.p, set0, set1, s);
+    auto update = [&]() {
+        if (np <= kMsFuseAlphaMax) {
+            ms_iter_update<true><<<ug, kMsBlk, 0, s>>>(set0, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
+                                                       m.part.p, long(ug), m.ppart.p, np);
+        } else {
+            ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, set0);
+            ms_iter_update<false><<<ug, kMsBlk, 0, s>>>(set0, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
+                                                        m.part.p, long(ug), m.ppart.p, np);
+        }
+    };
+    ms_iter_update<true><<<ug, kMsBlk, 0, s>>>(set1, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv, m.part.p,
+                                               long(ug), m.ppart.p, np);
+    // as in a solve: with many update partials the state is settled before each product
+    if (ug > kMsFuseFinishMax) ms_iter_settle<<<1, kMsBlk, 0, s>>>(m.part.p, long(ug), m.scal.p, 1);
     SHELL_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < reps; ++k) np = launch_product(m, sim.mass.p, sim.pinned.p, nv, dt2, m.p.p, m.p2.p, s);
+    for (int k = 0; k < reps; ++k) np = launch_product(m, sim.mass.p, sim.pinned.p, nv, dt2, m.p.p, m.p2.p, set1, set0, s);
     SHELL_HIP(hipEventRecord(e1, s));
     out.spmv_ms = elapsed();
-    ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, m.scal.p);
+    if (np > kMsFuseAlphaMax) ms_iter_alpha<<<1, kMsBlk, 0, s>>>(m.ppart.p, np, set0);
     SHELL_HIP(hipEventRecord(e0, s));
-    for (int k = 0; k < reps; ++k) {
-        if (np <= kMsFuseAlphaMax)
-            ms_iter_update<true><<<ug, kMsBlk, 0, s>>>(m.scal.p, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
-                                                       m.part.p, long(ug), m.ppart.p, np);
-        else
-            ms_iter_update<false><<<ug, kMsBlk, 0, s>>>(m.scal.p, m.p2.p, m.q.p, m.dinv.p, m.y.p, m.r.p, m.z.p, nv,
-                                                        m.part.p, long(ug), m.ppart.p, np);
-    }
+    for (int k = 0; k < reps; ++k) update();
     SHELL_HIP(hipEventRecord(e1, s));
     out.update_ms = elapsed();
     SHELL_HIP(hipGetLastError());
