@@ -15,7 +15,13 @@ pytestmark = pytest.mark.gpu
 
 MAT = I.MATERIAL
 TOL64 = 1e-10
-TOL_MIXED_FORCE = 5e-5
+# Mixed-precision forces against the FP64 oracle.  Float32 operators and curvatures (relative rounding
+# 6e-8) in sums that cancel by about an order of magnitude leave some 1e-7 to 1e-6 norm-wise (observed
+# 2e-8 to 1.3e-6 over the six models, the membrane, clamped and world-frame forms); per vertex (the
+# largest entry error over the largest reference entry) a vertex's own rounding shows up to a few times
+# that (observed up to 6.5e-6, ES).
+TOL_MIXED_FORCE = 5e-6
+TOL_MIXED_FORCE_VERTEX = 2e-5
 
 
 def dev():
@@ -25,6 +31,13 @@ def dev():
 def rel(a, b):
     nb = np.linalg.norm(b)
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def relmax(a, b):
+    """Largest per-entry error over the largest entry of the reference: an error confined to a few
+    vertices (the boundary stencils, one tile's halo) that a norm-wise comparison would dilute."""
+    nb = np.abs(b).max()
+    return np.abs(a - b).max() / (nb if nb > 0 else 1.0)
 
 
 def mesh_for(model, n=37, seed=3):
@@ -84,7 +97,7 @@ def test_forces_and_energy_match_oracle(model, block, reorder):
         info = S.shell_stencils_info(st)
         assert info["ns"] == ost.ns and info["nblocks"] == -(-mesh.nv // block)
         f, e = gpu_forces(st, x)
-        assert rel(f, f_ref) <= TOL64
+        assert rel(f, f_ref) <= TOL64 and relmax(f, f_ref) <= TOL64
         assert abs(e - e_ref) <= TOL64 * abs(e_ref)
         # rest state: zero force up to rounding of the operator's scale
         f0, e0 = gpu_forces(st, mesh.X)
@@ -102,9 +115,9 @@ def test_mixed_precision_forces_within_bound(model):
     st = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, precision=S.SHELL_PREC_MIXED, block_vertices=256)
     try:
         f, e = gpu_forces(st, x, f32=True)
-        err = rel(f, f_ref)
-        print(f"{model} mixed force rel err {err:.2e}")
-        assert err <= TOL_MIXED_FORCE
+        err, emax = rel(f, f_ref), relmax(f, f_ref)
+        print(f"{model} mixed force rel err {err:.2e} norm-wise, {emax:.2e} per vertex")
+        assert err <= TOL_MIXED_FORCE and emax <= TOL_MIXED_FORCE_VERTEX
         assert abs(e - e_ref) <= 1e-4 * abs(e_ref)
     finally:
         S.shell_destroy_stencils(st)
@@ -113,10 +126,9 @@ def test_mixed_precision_forces_within_bound(model):
 @pytest.mark.parametrize("model", I.MODELS)
 def test_mixed_forces_of_a_small_smooth_deformation(model):
     """Mixed precision on a 128 x 128 mesh deformed from rest by a smooth field of amplitude side/10^4.
-    The net force is a cancelling sum over stencils; the float kernels form the curvature from the
-    displacement differences, C = C0 + B (x^e - X^e), which keeps the error near 1e-5 (plates) and 2e-4
-    (shells, whose bending strain n.C - kappa0 keeps a float cancellation).  Float position differences
-    gave 2e-2 here."""
+    The net force is a cancelling sum over stencils of forces far larger than it; the float kernels form
+    the curvature relative to the rest shape (from the float64 positions), which keeps the error near
+    1e-7 to 6e-7 norm-wise and per vertex (observed).  Float position differences gave 2e-2 here."""
     if model.endswith("S"):
         mesh = I.workload_sphere_cap(128, model)
     else:
@@ -131,9 +143,10 @@ def test_mixed_forces_of_a_small_smooth_deformation(model):
     st = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, precision=S.SHELL_PREC_MIXED)
     try:
         f, _ = gpu_forces(st, x, f32=True)
-        err = rel(f, f_ref)
-        print(f"{model} mixed force rel err at a smooth deformation of amplitude side/1e4: {err:.2e}")
-        assert err <= (5e-4 if model.endswith("S") else 1e-4)
+        err, emax = rel(f, f_ref), relmax(f, f_ref)
+        print(f"{model} mixed force rel err at a smooth deformation of amplitude side/1e4: {err:.2e} norm-wise, "
+              f"{emax:.2e} per vertex")
+        assert err <= 2e-6 and emax <= 2e-6
     finally:
         S.shell_destroy_stencils(st)
 
@@ -258,7 +271,9 @@ def test_world_frame_variant_matches_oracle(model):
                                   flags=S.SHELL_FLAG_WORLD_FRAME)
     try:
         f32, _ = gpu_forces(st32, x, f32=True)
-        assert rel(f32, f_ref) <= TOL_MIXED_FORCE
+        err, emax = rel(f32, f_ref), relmax(f32, f_ref)
+        print(f"{model} mixed force (world frame or clamped) rel err {err:.2e} norm-wise, {emax:.2e} per vertex")
+        assert err <= TOL_MIXED_FORCE and emax <= TOL_MIXED_FORCE_VERTEX
     finally:
         S.shell_destroy_stencils(st32)
 
@@ -333,7 +348,9 @@ def test_clamped_operators_forces_and_hessian_match_oracle(model):
     st32 = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, precision=S.SHELL_PREC_MIXED, clamped_edges=cl)
     try:
         f32, _ = gpu_forces(st32, x, f32=True)
-        assert rel(f32, f_ref) <= TOL_MIXED_FORCE
+        err, emax = rel(f32, f_ref), relmax(f32, f_ref)
+        print(f"{model} mixed force (world frame or clamped) rel err {err:.2e} norm-wise, {emax:.2e} per vertex")
+        assert err <= TOL_MIXED_FORCE and emax <= TOL_MIXED_FORCE_VERTEX
     finally:
         S.shell_destroy_stencils(st32)
 
@@ -373,7 +390,7 @@ def test_membrane_forces_match_oracle(model):
     st = S.shell_build_stencils(mesh.X, mesh.tris, model, MAT, block_vertices=128, flags=S.SHELL_FLAG_MEMBRANE)
     try:
         f, e = gpu_forces(st, x)
-        assert rel(f, f_ref) <= TOL64
+        assert rel(f, f_ref) <= TOL64 and relmax(f, f_ref) <= TOL64
         assert abs(e - e_ref) <= TOL64 * abs(e_ref)
         f0, e0 = gpu_forces(st, mesh.X)
         assert np.abs(f0).max() <= 1e-11 * np.abs(f_ref).max() and abs(e0) <= 1e-12 * abs(e_ref)
@@ -383,7 +400,9 @@ def test_membrane_forces_match_oracle(model):
                                   flags=S.SHELL_FLAG_MEMBRANE)
     try:
         f32, e32 = gpu_forces(st32, x, f32=True)
-        assert rel(f32, f_ref) <= TOL_MIXED_FORCE
+        err, emax = rel(f32, f_ref), relmax(f32, f_ref)
+        print(f"{model} membrane mixed force rel err {err:.2e} norm-wise, {emax:.2e} per vertex")
+        assert err <= TOL_MIXED_FORCE and emax <= TOL_MIXED_FORCE_VERTEX
         assert abs(e32 - e_ref) <= 1e-4 * abs(e_ref)
     finally:
         S.shell_destroy_stencils(st32)
@@ -1132,7 +1151,7 @@ def test_full_size_sphere_cap_forces_match_oracle(cap_problem, cap_oracle):
     x = mesh.X + 1e-4 * I.rng(21).standard_normal(mesh.X.shape)
     f_ref, e_ref = ost.forces(x)
     f, e = gpu_forces(pb.st, x)
-    assert rel(f, f_ref) <= TOL64
+    assert rel(f, f_ref) <= TOL64 and relmax(f, f_ref) <= TOL64
     assert abs(e - e_ref) <= TOL64 * abs(e_ref)
 
 
