@@ -1227,8 +1227,10 @@ def _batch_meshes():
 @pytest.mark.parametrize("precision", [S.SHELL_PREC_FP64, S.SHELL_PREC_MIXED])
 def test_batch_equals_each_mesh_alone(precision):
     """Each mesh stepped inside a mixed batch equals the same mesh stepped alone.  The alone run is in
-    tolerance mode; the batch replays its per-mesh counts (tolerance-mode counts may move by one or two
-    when rounding of the tile accumulation moves a residual across the threshold)."""
+    tolerance mode; the batch replays its per-mesh counts (a batch splits a mesh's rows over other
+    work-groups than a lone launch, so its dot products sum their partials in another order, and a
+    tolerance-mode count may move by one or two when that rounding moves a residual across the
+    threshold)."""
     meshes = _batch_meshes()
     params, _ = S.step_params(1 / 60, max_newton=3, pcg_rtol=1e-6)
     alone, inbatch = [], []
