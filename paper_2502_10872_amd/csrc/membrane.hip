@@ -384,17 +384,30 @@ __global__ __launch_bounds__(kMsBlk) void ms_fin_init(const double* __restrict__
 // kMsPartMax work-groups.
 
 // Totals of the update's two partial arrays (ung entries each) in one fixed order whatever the work-group
-// size: the first kMsBlk threads stride over them, then the wave sums in order; valid in thread 0.  sh
-// holds 2 * (blockDim.x / 64) doubles.
-__device__ __forceinline__ void ms_update_totals(const double* __restrict__ upart, long ung, double (&t)[2],
-                                                 double* sh) {
+// size: lane l of the first wave adds entries l, l + 64, ... in turn, then the wave sum; valid in thread 0.
+// No barrier.  U entries per lane are loaded before they are added, so that their loads are in flight
+// together (the order of the additions is that of the plain loop).
+template <int U>
+__device__ __forceinline__ void ms_update_totals(const double* __restrict__ upart, long ung, double (&t)[2]) {
     t[0] = t[1] = 0.0;
-    if (threadIdx.x < kMsBlk)
-        for (long b = threadIdx.x; b < ung; b += kMsBlk) {
-            t[0] += upart[b];
-            t[1] += upart[ung + b];
+    if (threadIdx.x < 64) {
+        for (long b0 = threadIdx.x; b0 < ung; b0 += 64L * U) {
+            double a[U], c[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const long b = b0 + 64L * k;
+                a[k] = b < ung ? upart[b] : 0.0;
+                c[k] = b < ung ? upart[ung + b] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                t[0] += a[k];
+                t[1] += c[k];
+            }
         }
-    block_sum<2>(t, sh);
+        t[0] = wave_sum(t[0]);
+        t[1] = wave_sum(t[1]);
+    }
 }
 
 // One thread: the state that follows `sin` once the update with partial totals t has run (beta, r.z, r.r,
@@ -422,11 +435,10 @@ __device__ __forceinline__ void ms_finish_to(const double* cst, const double* si
 __device__ __forceinline__ bool ms_iteration_state(const double* cst, const double* __restrict__ sin,
                                                    double* __restrict__ sout, const double* __restrict__ upart,
                                                    long ung, double& beta) {
-    __shared__ double sh[2 * (kRowGroup / 64)];
     __shared__ double res[2];
     const bool settled = sin[S_FRESH] != 0.0, running = sin[S_ACTIVE] != 0.0;  // the same in every thread
     double t[2] = {0.0, 0.0};
-    if (!settled && running) ms_update_totals(upart, ung, t, sh);
+    if (!settled && running) ms_update_totals<4>(upart, ung, t);  // fused only up to 256 partials
     if (threadIdx.x == 0) {
         double o[S_COUNT];
         o[S_RZ] = sin[S_RZ];
@@ -534,7 +546,7 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* cst, con
     ms_partials<1>(v, ppart, npart);
 }
 
-// The same product over SELL-64 slices with the rows in groups of kRowGroup, one work-group per group
+// The same product over SELL-64 slices with the rows in groups of G (ms_group_rows), one work-group per group
 // (striding over the groups with at most kMsPartMax work-groups): the group's new directions
 // p_new = z + beta p_old at its distinct columns are formed once into LDS, then each lane takes one row
 // through K_s (the bending Hessian's slots) and through the blocks' nine component arrays.  A slice's
@@ -543,8 +555,8 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_product(const double* cst, con
 // slice run the loops on their padding and store nothing.  The matrix values, read once per product, are
 // loaded non-temporally so that they do not displace the staged directions' sources and the vectors the
 // update reads next from the caches (measured at 1M vertices: 173 -> 144 us FP64, 112 -> 92 us mixed).
-template <typename VT>
-__global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
+template <typename VT, int G>
+__global__ __launch_bounds__(G) void ms_iter_product_staged(
     const double* cst, const double* __restrict__ sin, double* __restrict__ sout, const double* __restrict__ upart,
     long ung, const int64_t* __restrict__ sptr, const int32_t* __restrict__ swidth,
     const uint16_t* __restrict__ slcol, const VT* __restrict__ sval, const int64_t* __restrict__ mptr,
@@ -554,11 +566,11 @@ __global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
     const double* __restrict__ pold, double* __restrict__ pnew, double* __restrict__ q, long nv, double dt2,
     double* __restrict__ ppart) {
     extern __shared__ double ps[];
-    __shared__ double red[kRowGroup / 64];
+    __shared__ double red[G / 64];
     double be;
     if (!ms_iteration_state(cst, sin, sout, upart, ung, be)) return;
     constexpr bool DIFF = sizeof(VT) == 4;
-    const long ngroups = (nv + kRowGroup - 1) / kRowGroup, nslices = (nv + 63) / 64;
+    const long ngroups = (nv + G - 1) / G, nslices = (nv + 63) / 64;
     double v = 0.0;
     for (long g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int a0 = gptr[g], n = gptr[g + 1] - a0;
@@ -568,7 +580,7 @@ __global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
             for (int c = 0; c < 3; ++c) ps[3 * k + c] = z[3 * j + c] + be * pold[3 * j + c];
         }
         __syncthreads();
-        const long i = g * kRowGroup + threadIdx.x;
+        const long i = g * G + threadIdx.x;
         const long slice = i >> 6;
         if (slice >= nslices) continue;  // whole waves past the last slice
         double po[3] = {0.0, 0.0, 0.0};
@@ -614,14 +626,14 @@ __global__ __launch_bounds__(kRowGroup) void ms_iter_product_staged(
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < kRowGroup / 64; ++w) t += red[w];
+        for (int w = 0; w < G / 64; ++w) t += red[w];
         ppart[blockIdx.x] = t;
     }
 }
 
 // The update sums the product's partials itself (FUSED) up to this many partials, and the product the
 // update's (finishing the previous iteration) up to this many.
-constexpr long kMsFuseAlphaMax = 256;
+constexpr long kMsFuseAlphaMax = 512;
 constexpr long kMsFuseFinishMax = 256;
 
 // p.q from the product's partials (one work-group, fixed order), then alpha = r.z / p.q, in the state set
@@ -815,9 +827,8 @@ __global__ __launch_bounds__(kMsBlk) void ms_iter_settle(const double* __restric
                                                          int cur) {
     double* st = scal + S_COUNT * cur;
     if (st[S_FRESH] != 0.0 || st[S_ACTIVE] == 0.0) return;
-    __shared__ double sh[2 * (kMsBlk / 64)];
     double t[2];
-    ms_update_totals(upart, ung, t, sh);
+    ms_update_totals<32>(upart, ung, t);
     if (threadIdx.x == 0) {
         ms_finish_to(scal, st, t, st);
         st[S_FRESH] = 1.0;
@@ -933,6 +944,15 @@ __global__ void ms_zero(double* __restrict__ p, long n) {
 
 inline unsigned ms_grid(long n) { return unsigned(std::max(1L, (n + kMsBlk - 1) / kMsBlk)); }
 
+// Rows per group of the staged product: the largest of 512 and 256 that still makes at least 512 groups
+// (two work-groups per CU), else 128, so that mid-size meshes fill the chip; smaller groups stage more
+// neighbouring columns per row.
+inline int ms_group_rows(long nv) {
+    for (int g : {512, 256})
+        if ((nv + g - 1) / g >= 512) return g;
+    return 128;
+}
+
 }  // namespace
 
 void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
@@ -972,11 +992,12 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
     ms->staged = (st.cfg_flags & SHELL_FLAG_DIRECT_PRODUCT) == 0 && nv >= kMsStagedMinRows;
     if (ms->staged) {
         // each row group's distinct columns of K_s and of the blocks, with its own rows
-        const int64_t ng = (nv + kRowGroup - 1) / kRowGroup, nsl = (nv + 63) / 64;
+        const int64_t G = ms_group_rows(nv);
+        const int64_t ng = (nv + G - 1) / G, nsl = (nv + 63) / 64;
         std::vector<std::vector<int32_t>> gl(static_cast<size_t>(ng));
         for (int64_t g = 0; g < ng; ++g) {
             auto& v = gl[size_t(g)];
-            for (int64_t i = g * kRowGroup; i < std::min<int64_t>(nv, (g + 1) * kRowGroup); ++i) {
+            for (int64_t i = g * G; i < std::min<int64_t>(nv, (g + 1) * G); ++i) {
                 v.push_back(int32_t(i));
                 v.insert(v.end(), pat.col.begin() + pat.rowptr[size_t(i)], pat.col.begin() + pat.rowptr[size_t(i + 1)]);
                 v.insert(v.end(), mcol.begin() + mrow[size_t(i)], mcol.begin() + mrow[size_t(i + 1)]);
@@ -996,12 +1017,12 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
             for (int64_t g = 0; g < ng; ++g) {
                 gptr[size_t(g + 1)] = gptr[size_t(g)] + int32_t(gl[size_t(g)].size());
                 gcols.insert(gcols.end(), gl[size_t(g)].begin(), gl[size_t(g)].end());
-                gself[size_t(g)] = local(g, int32_t(g * kRowGroup));
+                gself[size_t(g)] = local(g, int32_t(g * G));
             }
             std::vector<uint16_t> slcol(size_t(pat.nslots));
             for (int64_t sl = 0; sl < nsl; ++sl)
                 for (int64_t slot = pat.sptr[size_t(sl)]; slot < pat.sptr[size_t(sl + 1)]; ++slot)
-                    slcol[size_t(slot)] = local((64 * sl) / kRowGroup, pat.scol[size_t(slot)]);
+                    slcol[size_t(slot)] = local((64 * sl) / G, pat.scol[size_t(slot)]);
             std::vector<int32_t> mwidth(static_cast<size_t>(nsl));
             std::vector<int64_t> mptr(size_t(nsl + 1), 0);
             for (int64_t sl = 0; sl < nsl; ++sl) {
@@ -1016,7 +1037,7 @@ void membrane_sim_init(shell_sim_s& sim, hipStream_t s) {
             std::vector<int64_t> s2e(size_t(mslots), -1);
             for (int64_t sl = 0; sl < nsl; ++sl)
                 for (int lane = 0; lane < 64; ++lane) {
-                    const int64_t i = 64 * sl + lane, g = i / kRowGroup;
+                    const int64_t i = 64 * sl + lane, g = i / G;
                     const int64_t len = i < nv ? mrow[size_t(i + 1)] - mrow[size_t(i)] : 0;
                     for (int64_t k = 0; k < mwidth[size_t(sl)]; ++k) {
                         const int64_t slot = mptr[size_t(sl)] + 64 * k + lane;
@@ -1210,18 +1231,23 @@ static long launch_product(MembraneSolve& m, const double* mass, const uint8_t* 
                            const double* pold, double* pnew, const double* sin, double* sout, hipStream_t s) {
     const long ung = long(ms_update_grid(nv));
     if (m.staged) {
-        const unsigned pg = unsigned(std::min(kMsPartMax, (nv + kRowGroup - 1) / kRowGroup));
+        const int G = ms_group_rows(nv);
+        const unsigned pg = unsigned(std::min(kMsPartMax, (nv + G - 1) / G));
         const size_t lds = size_t(m.max_gcols) * 3 * sizeof(double);
-        if (m.mixed)
-            ms_iter_product_staged<float><<<pg, kRowGroup, lds, s>>>(
-                m.scal.p, sin, sout, m.part.p, ung, m.hsptr, m.hwidth, m.slcol.p, m.hvalf, m.mptr.p, m.mwidth.p, m.mlcol.p, m.mvalf.p,
-                long(m.mstride), m.gptr.p, m.gcols.p, m.gself.p, mass, pinned, m.z.p, pold, pnew, m.q.p, nv, dt2,
-                m.ppart.p);
-        else
-            ms_iter_product_staged<double><<<pg, kRowGroup, lds, s>>>(
-                m.scal.p, sin, sout, m.part.p, ung, m.hsptr, m.hwidth, m.slcol.p, m.hval, m.mptr.p, m.mwidth.p, m.mlcol.p, m.mval.p,
-                long(m.mstride), m.gptr.p, m.gcols.p, m.gself.p, mass, pinned, m.z.p, pold, pnew, m.q.p, nv, dt2,
-                m.ppart.p);
+        auto go = [&](auto kernel, const auto* sv, const auto* mv) {
+            kernel<<<pg, G, lds, s>>>(m.scal.p, sin, sout, m.part.p, ung, m.hsptr, m.hwidth, m.slcol.p, sv, m.mptr.p,
+                                      m.mwidth.p, m.mlcol.p, mv, long(m.mstride), m.gptr.p, m.gcols.p, m.gself.p, mass,
+                                      pinned, m.z.p, pold, pnew, m.q.p, nv, dt2, m.ppart.p);
+        };
+        if (m.mixed) {
+            if (G == 512) go(ms_iter_product_staged<float, 512>, m.hvalf, m.mvalf.p);
+            else if (G == 256) go(ms_iter_product_staged<float, 256>, m.hvalf, m.mvalf.p);
+            else go(ms_iter_product_staged<float, 128>, m.hvalf, m.mvalf.p);
+        } else {
+            if (G == 512) go(ms_iter_product_staged<double, 512>, m.hval, m.mval.p);
+            else if (G == 256) go(ms_iter_product_staged<double, 256>, m.hval, m.mval.p);
+            else go(ms_iter_product_staged<double, 128>, m.hval, m.mval.p);
+        }
         return long(pg);
     }
     const unsigned pg = ms_product_grid(nv, m.mixed ? kMsLanesF32 : kMsLanesF64);
