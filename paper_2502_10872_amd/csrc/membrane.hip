@@ -944,12 +944,17 @@ __global__ void ms_zero(double* __restrict__ p, long n) {
 
 inline unsigned ms_grid(long n) { return unsigned(std::max(1L, (n + kMsBlk - 1) / kMsBlk)); }
 
-// Rows per group of the staged product: the largest of 512 and 256 that still makes at least 512 groups
-// (two work-groups per CU), else 128, so that mid-size meshes fill the chip; smaller groups stage more
-// neighbouring columns per row.
+// Rows per group of the staged product: the largest of 512 and 256 that still makes at least 256 groups
+// (one work-group per CU), else 128, so that mid-size meshes fill the chip; smaller groups stage more
+// neighbouring columns per row.  Measured on SS cylinders against at least 512 and 1024 groups: 65K
+// vertices (256-row groups) 12.4 ms per FP64 step against 13.6 (128-row) and 13.6; 131K and 262K equal
+// within 2%, or 8-13% slower with 1024.
+#ifndef SHELL_MS_MIN_GROUPS
+#define SHELL_MS_MIN_GROUPS 256
+#endif
 inline int ms_group_rows(long nv) {
     for (int g : {512, 256})
-        if ((nv + g - 1) / g >= 512) return g;
+        if ((nv + g - 1) / g >= SHELL_MS_MIN_GROUPS) return g;
     return 128;
 }
 

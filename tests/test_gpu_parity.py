@@ -691,8 +691,8 @@ def _staged_oracle():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_membrane_step_staged_product_matches_oracle(prec):
-    """The staged SELL product (rows in 512-row groups, the group's directions in LDS, K_s from the bending
-    Hessian's slots, the blocks in SELL-64 component arrays), taken from 49152 vertices up, against the
+    """The staged SELL product (rows in groups, 128 rows at this size, the group's directions in LDS, K_s
+    from the bending Hessian's slots, the blocks in SELL-64 component arrays), taken from 49152 vertices up, against the
     CSR product forced by SHELL_FLAG_DIRECT_PRODUCT and against the oracle, on a 49729-vertex cylinder
     patch whose last row group and last slice are partial: one step of two Newton iterations with 150 PCG
     iterations each, replayed on every side.  At a fixed count this far from convergence (the residual
@@ -722,6 +722,31 @@ def test_membrane_step_staged_product_matches_oracle(prec):
         assert errs[d][0] <= bound and errs[d][1] <= bound, (d, errs[d])
     mbound = 1e-12 if prec == "fp64" else 1e-9
     assert mutual[0] <= mbound and mutual[1] <= mbound, mutual
+
+
+@pytest.mark.parametrize("n", [257, 363])
+def test_membrane_staged_product_group_sizes_agree_with_the_direct_product(n):
+    """The staged product's larger row groups: 256 rows at 66,049 vertices and 512 rows at 131,769 (the
+    group size follows the mesh size; the last group holds 1 and 185 rows).  One step of two Newton
+    iterations with 150 PCG iterations each, replayed, against the CSR product forced by
+    SHELL_FLAG_DIRECT_PRODUCT on the same mesh: the two differ only in the product's summation order
+    (bounds as in the 49,729-vertex test: 1e-12 FP64, 1e-9 mixed)."""
+    mesh = I.cylinder_mesh(n, 0.5, 0.9, 0.8, 0.2, 3, "SS", "ends")
+    for precision, mbound in ((S.SHELL_PREC_FP64, 1e-12), (S.SHELL_PREC_MIXED, 1e-9)):
+        res = {}
+        for direct in (False, True):
+            flags = S.SHELL_FLAG_MEMBRANE | (S.SHELL_FLAG_DIRECT_PRODUCT if direct else 0)
+            with S.Problem(mesh, MAT, model="SS", precision=precision, flags=flags) as pb:
+                rep = np.array([[150, 0, 0], [150, 0, 0]], np.int32)
+                params, _keep = S.step_params(1 / 60, max_newton=2, newton_rtol=1e-12, pcg_rtol=1e-13, replay=rep)
+                rc, gs = S.shell_step_implicit(pb.sim, params)
+                assert gs["newton_iters"] == 2 and gs["pcg_total"] == 300
+                res[direct] = S.shell_sim_get_state(pb.sim, mesh.nv)[:2]
+        x, v = res[False]
+        assert np.isfinite(x).all() and np.abs(x - mesh.X).max() > 0  # the step moved the mesh
+        mutual = (rel(x - mesh.X, res[True][0] - mesh.X), rel(v, res[True][1]))
+        print(f"{mesh.nv} vertices, precision {precision}: staged vs direct {mutual[0]:.2e} {mutual[1]:.2e}")
+        assert mutual[0] <= mbound and mutual[1] <= mbound, mutual
 
 
 def test_membrane_step_staged_product_with_held_coordinates_matches_oracle():
