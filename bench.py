@@ -249,7 +249,7 @@ def membrane_timing(S, I, torch, reps=20):
     return out
 
 
-MEMBRANE_STAGED_MIN_ROWS = 49152  # the library's staged membrane product from this many vertices up
+MEMBRANE_STAGED_MIN_ROWS = 32768  # the library's staged membrane product from this many vertices up
 
 
 def membrane_product_bytes(nv, nnz_s, nnz_m, mixed=False):

@@ -111,9 +111,10 @@ typedef struct {
  * Newton loop), and the product reads float32 copies of K_s and of the tangent's blocks in difference
  * form, q_i = m_i p_i + dt^2 sum_j (K_s,ij I + K_m,ij)(p_j - p_i), which keeps translations in their null
  * space whatever the rounding; the vectors, dot products and the Newton loop stay float64.  On meshes of
- * 49152 vertices or more, unless SHELL_FLAG_DIRECT_PRODUCT is set, the product takes the rows in groups
- * of 512 with the group's directions staged in LDS, K_s from the bending Hessian's SELL-64 slots and the
- * blocks in SELL-64 slices; smaller meshes (too few groups to fill the chip) read both as CSR.
+ * 32768 vertices or more, unless SHELL_FLAG_DIRECT_PRODUCT is set, the product takes the rows in groups
+ * of 128, 256 or 512 (at least 256 groups where possible) with the group's directions staged in LDS, K_s
+ * from the bending Hessian's SELL-64 slots and the blocks in SELL-64 slices; smaller meshes read both as
+ * CSR.
  * A batch of such simulations steps each member as it would step alone (see shell_batch_create).  A
  * degenerate triangle is SHELL_E_DEGENERATE. */
 #define SHELL_FLAG_MEMBRANE 4

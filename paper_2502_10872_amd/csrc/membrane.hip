@@ -474,11 +474,16 @@ __device__ __forceinline__ bool ms_iteration_state(const double* cst, const doub
 // shuffles, until too few rows share a wave's loads.
 constexpr int kMsLanesF64 = 8;
 constexpr int kMsLanesF32 = 4;
-// The staged product (below) from this many rows up: one work-group per 512-row group leaves most of the
-// chip idle on small meshes, where its latency floor (about 10 us) exceeds the CSR product's.  Measured
-// on SS cylinders, staged against CSR, FP64: 10.1 / 5.3 us at 4K rows, 14.4 / 10.2 at 33K, 15.0 / 14.1
-// at 48K, 15.5 / 18.1 at 65K, 20.2 / 32.9 at 131K, 144 / 317 at 1M.
-constexpr long kMsStagedMinRows = 49152;
+// The staged product (below) from this many rows up; on smaller meshes its latency floor exceeds the CSR
+// product's.  Measured with 512-row groups on SS cylinders, staged against CSR product, FP64: 10.1 / 5.3 us
+// at 4K rows, 14.4 / 10.2 at 33K, 15.0 / 14.1 at 48K, 15.5 / 18.1 at 65K, 20.2 / 32.9 at 131K, 144 / 317 at
+// 1M.  With the smaller groups of mid-size meshes (ms_group_rows), whole steps, staged against CSR, FP64 and
+// mixed: 12.0 / 10.3 and 11.3 / 10.4 ms at 16K rows, 9.9 / 10.9 and 10.0 / 9.4 at 33K, 12.5 / 14.4 and
+// 12.1 / 12.5 at 48K.
+#ifndef SHELL_MS_STAGED_MIN_ROWS
+#define SHELL_MS_STAGED_MIN_ROWS 32768
+#endif
+constexpr long kMsStagedMinRows = SHELL_MS_STAGED_MIN_ROWS;
 // The product and the update stride over the rows with at most kMsPartMax work-groups, so that one
 // work-group sums their partials in a fixed order in a few microseconds at any mesh size.
 constexpr long kMsPartMax = 2048;

@@ -692,7 +692,7 @@ def _staged_oracle():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_membrane_step_staged_product_matches_oracle(prec):
     """The staged SELL product (rows in groups, 128 rows at this size, the group's directions in LDS, K_s
-    from the bending Hessian's slots, the blocks in SELL-64 component arrays), taken from 49152 vertices up, against the
+    from the bending Hessian's slots, the blocks in SELL-64 component arrays), taken from 32768 vertices up, against the
     CSR product forced by SHELL_FLAG_DIRECT_PRODUCT and against the oracle, on a 49729-vertex cylinder
     patch whose last row group and last slice are partial: one step of two Newton iterations with 150 PCG
     iterations each, replayed on every side.  At a fixed count this far from convergence (the residual
