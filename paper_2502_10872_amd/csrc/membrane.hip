@@ -438,7 +438,7 @@ __device__ __forceinline__ bool ms_iteration_state(const double* cst, const doub
     __shared__ double res[2];
     const bool settled = sin[S_FRESH] != 0.0, running = sin[S_ACTIVE] != 0.0;  // the same in every thread
     double t[2] = {0.0, 0.0};
-    if (!settled && running) ms_update_totals<4>(upart, ung, t);  // fused only up to 256 partials
+    if (!settled && running) ms_update_totals<4>(upart, ung, t);  // fused only up to 1024 partials
     if (threadIdx.x == 0) {
         double o[S_COUNT];
         o[S_RZ] = sin[S_RZ];
@@ -639,7 +639,14 @@ __global__ __launch_bounds__(G) void ms_iter_product_staged(
 // The update sums the product's partials itself (FUSED) up to this many partials, and the product the
 // update's (finishing the previous iteration) up to this many.
 constexpr long kMsFuseAlphaMax = 512;
-constexpr long kMsFuseFinishMax = 256;
+// (finishing the previous update in every product work-group, against a settle kernel after every
+// iteration, measured on SS cylinders: 131K vertices, 512 update partials, 9.7 against 10.4 ms per FP64
+// step and 8.5 against 9.2 mixed; 262K, 1024 partials, 14.2 against 14.8 and 11.5 against 11.9; at 1M
+// vertices, 2048 partials, 151 against 144 us per product and slower steps)
+#ifndef SHELL_MS_FUSE_FINISH_MAX
+#define SHELL_MS_FUSE_FINISH_MAX 1024
+#endif
+constexpr long kMsFuseFinishMax = SHELL_MS_FUSE_FINISH_MAX;
 
 // p.q from the product's partials (one work-group, fixed order), then alpha = r.z / p.q, in the state set
 // `st` that the product wrote
@@ -1290,7 +1297,7 @@ static void pcg_iteration(MembraneSolve& m, const double* mass, const uint8_t* p
     }
     m.pswap = !m.pswap;
     // with many update partials one work-group settles the state after every iteration instead (every
-    // product work-group summing them delays the start of its stream: at 1M vertices 151 against 144 us)
+    // product work-group summing them delays the start of its stream)
     if (ug > kMsFuseFinishMax) ms_iter_settle<<<1, kMsBlk, 0, s>>>(m.part.p, long(ug), m.scal.p, m.pswap ? 1 : 0);
 }
 
