@@ -638,7 +638,13 @@ __global__ __launch_bounds__(G) void ms_iter_product_staged(
 
 // The update sums the product's partials itself (FUSED) up to this many partials, and the product the
 // update's (finishing the previous iteration) up to this many.
-constexpr long kMsFuseAlphaMax = 512;
+// (every update work-group summing the product's 2048 partials at 1M vertices, against ms_iter_alpha:
+// 31.2 against 31.6 ms per FP64 step, 23.2 against 23.4 mixed; so every product partial count, at most
+// kMsPartMax, is summed in the update, and ms_iter_alpha serves a lower setting of this limit)
+#ifndef SHELL_MS_FUSE_ALPHA_MAX
+#define SHELL_MS_FUSE_ALPHA_MAX 2048
+#endif
+constexpr long kMsFuseAlphaMax = SHELL_MS_FUSE_ALPHA_MAX;
 // (finishing the previous update in every product work-group, against a settle kernel after every
 // iteration, measured on SS cylinders: 131K vertices, 512 update partials, 9.7 against 10.4 ms per FP64
 // step and 8.5 against 9.2 mixed; 262K, 1024 partials, 14.2 against 14.8 and 11.5 against 11.9; at 1M
